@@ -1,0 +1,380 @@
+"""Block preconditioners for the enriched Taylor-Hood systems, written plainly
+from the paper's definitions with sparse matrices.
+
+Test infrastructure (see the package docstring).
+
+Stokes, eq:stokes_pre with viscosity nu:  P = diag(nu*A~, M~_Q / nu), where the
+pressure block is applied through the bordered (Lagrange-multiplier) system
+[[M_S, k], [k^T, 0]] of Sec. 2.2 so that every output is orthogonal to the
+frame null vector k.
+  * exact   : M_S = M_Q  -> z = M_Q^+ r (bordered SuperLU)        (P_1, Sec. 2.4)
+  * diag    : M_S = diag(M_Q) -> bordered diagonal solve           (Sec. 2.3)
+  * cheb_sgs: m steps of Chebyshev semi-iteration based on symmetric
+              Gauss-Seidel for M_Q (Sec. 2.3, P_2 of Sec. 2.4), on k-orthogonal
+              input, output projected onto k^perp.
+Velocity block: exact (SuperLU) or one geometric-multigrid V-cycle.
+
+Oseen, eq:nse-precon-diag (block upper triangular, right preconditioning):
+  * M_1 = [[F, B^T], [0, -M_Q/nu]]   (eq:nse-precon-ref)
+  * stage-I PCD on the reduced Taylor-Hood system (eq:reduced-system) with
+    the Schur approximation of eq:discrete-commutator1x:
+        B_1 F^{-1} B_1^T ~ Q_1 F_1^{-1} A_p,  A_p = B_1 M^{-1} B_1^T,
+    M = diag of the velocity mass matrix, so M_S^{-1} = A_p^+ F_1 Q_1^{-1}.
+  * two_stage(): Step I / Step II of Sec. 3.1.
+
+Multicolour ordering (the GPU-friendly reading of "symmetric Gauss-Seidel"):
+Q1 node (c, d) has colour (c mod 2) + 2 (d mod 2), every element pressure has
+colour 4; a symmetric sweep visits colours 0,1,2,3,4 then 3,2,1,0.
+"""
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .assemble import Mesh, laplacian, frame_null_vector, q1_mass, \
+    q1_convection_diffusion, velocity_mass
+from .krylov import fgmres
+
+
+# -- pressure-mass solves ------------------------------------------------------
+
+class MQExact:
+    """z = M_Q^+ r via the bordered system [[M_Q, k], [k^T, 0]] (Sec. 2.2)."""
+
+    def __init__(self, mesh, MQ):
+        k = frame_null_vector(mesh)[:, None]
+        Kb = sp.bmat([[MQ, sp.csr_matrix(k)], [sp.csr_matrix(k.T), None]]).tocsc()
+        self.lu = spla.splu(Kb)
+        self.n = MQ.shape[0]
+
+    def __call__(self, r):
+        return self.lu.solve(np.concatenate([r, [0.0]]))[: self.n]
+
+
+class MQDiag:
+    """Bordered solve with M_S = diag(M_Q):  z = D^{-1}(r - lam k), k^T z = 0,
+    i.e. lam = k^T D^{-1} r / k^T D^{-1} k (Sec. 2.2 with the diagonal
+    approximation of Sec. 2.3)."""
+
+    def __init__(self, mesh, MQ):
+        self.dinv = 1.0 / MQ.diagonal()
+        self.k = frame_null_vector(mesh)
+        self.kDk = float(self.k @ (self.dinv * self.k))
+
+    def __call__(self, r):
+        y = self.dinv * r
+        lam = float(self.k @ y) / self.kDk
+        return y - lam * (self.dinv * self.k)
+
+
+def mq_colours(mesh):
+    """Colour (0..4) of every pressure frame coefficient."""
+    n = mesh.n
+    c = np.arange(mesh.nk) % (n + 1)
+    d = np.arange(mesh.nk) // (n + 1)
+    return np.concatenate([(c % 2) + 2 * (d % 2), np.full(mesh.n0, 4)])
+
+
+def multicolour_sgs(M, colours, r, x):
+    """One symmetric multicolour Gauss-Seidel sweep for M x = r from x:
+    forward over colours 0..4, backward over 3..0 (colour 4 is diagonal within
+    itself, so a repeated update of it would change nothing)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    dinv = 1.0 / M.diagonal()
+    ncol = int(colours.max()) + 1
+    order = list(range(ncol)) + list(range(ncol - 2, -1, -1))
+    for col in order:
+        idx = np.flatnonzero(colours == col)
+        res = r[idx] - M[idx] @ x
+        x[idx] += dinv[idx] * res
+    return x
+
+
+def chebyshev(apply_A, apply_Minv, r, x0, lo, hi, steps):
+    """Chebyshev semi-iteration for A x = r preconditioned by M (eigenvalues
+    of M^{-1}A assumed in [lo, hi]), `steps` applications of M^{-1}, standard
+    three-term recurrence:
+        theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta
+        d_0 = M^{-1} r_0 / theta,  rho_0 = 1/sigma
+        rho_k = 1 / (2 sigma - rho_{k-1}),
+        d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) M^{-1} r_k
+        x_{k+1} = x_k + d_k
+    """
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    sigma = theta / delta
+    x = np.array(x0, dtype=np.float64, copy=True)
+    res = r - apply_A(x)
+    d = apply_Minv(res) / theta
+    rho = 1.0 / sigma
+    x = x + d
+    for _ in range(1, steps):
+        res = r - apply_A(x)
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * apply_Minv(res)
+        rho = rho_new
+        x = x + d
+    return x
+
+
+class MQChebSGS:
+    """`steps` Chebyshev steps based on multicolour SGS for M_Q, eigenvalue
+    interval [lo, hi] of M_SGS^{-1} M_Q (hi = 1 for SGS on a symmetric positive
+    semi-definite matrix), applied as  z = P q(M_SGS^{-1} M_Q) M_SGS^{-1} P r with
+    P the Euclidean projector onto k^perp (symmetric positive semi-definite,
+    null space span{k})."""
+
+    def __init__(self, mesh, MQ, lo, hi=1.0, steps=20):
+        self.M = MQ.tocsr()
+        self.col = mq_colours(mesh)
+        self.k = frame_null_vector(mesh)
+        self.kk = float(self.k @ self.k)
+        self.lo, self.hi, self.steps = lo, hi, steps
+
+    def project(self, v):
+        return v - (float(self.k @ v) / self.kk) * self.k
+
+    def sgs_inv(self, r):
+        return multicolour_sgs(self.M, self.col, r, np.zeros_like(r))
+
+    def __call__(self, r):
+        r = self.project(r)
+        z = chebyshev(lambda v: self.M @ v, self.sgs_inv, r, np.zeros_like(r),
+                      self.lo, self.hi, self.steps)
+        return self.project(z)
+
+
+def sgs_spectrum(mesh, MQ):
+    """Dense eigenvalues of M_SGS^{-1} M_Q (small meshes only)."""
+    M = MQ.toarray()
+    col = mq_colours(mesh)
+    n = M.shape[0]
+    Minv = np.zeros_like(M)
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        Minv[:, i] = multicolour_sgs(MQ.tocsr(), col, e, np.zeros(n))
+    ev = np.linalg.eigvals(Minv @ M)
+    return np.sort(ev.real)
+
+
+# -- geometric multigrid for the scalar Q2 Laplacian / conv-diff --------------
+
+def gmg_levels(n, coarse_n=4):
+    """Mesh sizes of the hierarchy: halve while n is even and n > coarse_n."""
+    ns = [n]
+    while ns[-1] % 2 == 0 and ns[-1] > coarse_n:
+        ns.append(ns[-1] // 2)
+    return ns
+
+
+def q2_prolongation(fine, coarse):
+    """Interpolation of Q2 functions of the coarse mesh at the fine Q2 nodes
+    (the natural embedding of nested Q2 spaces), all nodes x all nodes."""
+    Xf, Yf = fine.q2_coords()
+    H = coarse.h
+    ex = np.minimum(np.floor((Xf - coarse.x0) / H + 1e-12).astype(int), coarse.n - 1)
+    ey = np.minimum(np.floor((Yf - coarse.y0) / H + 1e-12).astype(int), coarse.n - 1)
+    xi = (Xf - coarse.x0) / H - ex
+    et = (Yf - coarse.y0) / H - ey
+    from .fem import q2_1d
+    vx, _ = q2_1d(xi)
+    vy, _ = q2_1d(et)
+    rows, cols, vals = [], [], []
+    for j in range(3):
+        for i in range(3):
+            w = vx[i] * vy[j]
+            cidx = (2 * ey + j) * coarse.nq + (2 * ex + i)
+            nz = np.abs(w) > 1e-15
+            rows.append(np.flatnonzero(nz))
+            cols.append(cidx[nz])
+            vals.append(w[nz])
+    P = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(fine.nv, coarse.nv)).tocsr()
+    P.sum_duplicates()
+    return P
+
+
+def lambda_max_dinv(A):
+    """Largest eigenvalue of D^{-1} A for symmetric positive definite A."""
+    d = 1.0 / np.sqrt(A.diagonal())
+    S = sp.diags(d) @ A @ sp.diags(d)
+    if S.shape[0] <= 400:
+        return float(np.linalg.eigvalsh(S.toarray())[-1])
+    return float(spla.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-10)[0])
+
+
+class GMG:
+    """One V-cycle for the interior scalar operator of `make_op(mesh)` applied
+    to both velocity components (the velocity block of eq:stokes_pre).
+
+    Levels by gmg_levels(); level operators re-discretised on each mesh (equal
+    to the Galerkin products for nested Q2 spaces with exact integration);
+    exact solve on the coarsest level; pre/post smoothing by a Chebyshev
+    polynomial of the given degree in D^{-1}A with interval
+    [lo_frac*lam, hi_frac*lam] where lam = lambda_max(D^{-1}A) on that level
+    (given, or computed exactly).  Parity unpinned as a whole (the method is a
+    preconditioner design of this implementation, the paper uses AMG); pinned
+    by the Galerkin identity, symmetry and convergence-rate tests.
+    """
+
+    def __init__(self, mesh, make_op, degree=2, lo_frac=0.3, hi_frac=1.1,
+                 coarse_n=4, lambdas=None):
+        self.ns = gmg_levels(mesh.n, coarse_n)
+        self.meshes = [Mesh(k, mesh.x0, mesh.x1, mesh.y0, mesh.y1) for k in self.ns]
+        self.A, self.I, self.P = [], [], []
+        for lvl, m in enumerate(self.meshes):
+            bnd = m.boundary_q2()
+            I = np.flatnonzero(~bnd)
+            Af = make_op(m)
+            self.A.append(Af[I][:, I].tocsr())
+            self.I.append(I)
+        for lvl in range(len(self.meshes) - 1):
+            Pf = q2_prolongation(self.meshes[lvl], self.meshes[lvl + 1])
+            self.P.append(Pf[self.I[lvl]][:, self.I[lvl + 1]].tocsr())
+        self.dinv = [1.0 / A.diagonal() for A in self.A]
+        if lambdas is None:
+            lambdas = [lambda_max_dinv(A) for A in self.A[:-1]]
+        self.lam = list(lambdas)
+        self.degree, self.lo_frac, self.hi_frac = degree, lo_frac, hi_frac
+        self.coarse_lu = spla.splu(self.A[-1].tocsc())
+
+    def smooth(self, lvl, r, x):
+        A, dinv, lam = self.A[lvl], self.dinv[lvl], self.lam[lvl]
+        return chebyshev(lambda v: A @ v, lambda v: dinv * v, r, x,
+                         self.lo_frac * lam, self.hi_frac * lam, self.degree)
+
+    def vcycle(self, lvl, r):
+        if lvl == len(self.A) - 1:
+            return self.coarse_lu.solve(r)
+        x = self.smooth(lvl, r, np.zeros_like(r))
+        rc = self.P[lvl].T @ (r - self.A[lvl] @ x)
+        x = x + self.P[lvl] @ self.vcycle(lvl + 1, rc)
+        return self.smooth(lvl, r, x)
+
+    def __call__(self, r_int):
+        """r_int: interior velocity vector [u_x interior; u_y interior]."""
+        m = self.A[0].shape[0]
+        return np.concatenate([self.vcycle(0, r_int[:m]), self.vcycle(0, r_int[m:])])
+
+
+def stokes_gmg(system, **kw):
+    """GMG for nu*A (the Stokes velocity block)."""
+    nu = system.nu
+    g = GMG(system.mesh, laplacian, **kw)
+    return lambda r: g(r) / nu, g
+
+
+# -- block preconditioners -------------------------------------------------------
+
+class StokesBlockDiag:
+    """eq:stokes_pre with viscosity nu on the interior layout [u_I; p]:
+    z_u = (nu A~)^{-1} r_u,  z_p = nu * M~_S^{+} r_p."""
+
+    def __init__(self, system, velocity="exact", mq="exact", mq_lo=None,
+                 mq_steps=20, gmg_kw=None):
+        s = system
+        self.s = s
+        self.nI = s.nI
+        if velocity == "exact":
+            lu = spla.splu((s.nu * s.AI).tocsc())
+            self.vel = lu.solve
+        elif velocity == "gmg":
+            self.vel, self.gmg = stokes_gmg(s, **(gmg_kw or {}))
+        else:
+            raise ValueError(velocity)
+        if mq == "exact":
+            self.mq = MQExact(s.mesh, s.MQ)
+        elif mq == "diag":
+            self.mq = MQDiag(s.mesh, s.MQ)
+        elif mq == "cheb_sgs":
+            self.mq = MQChebSGS(s.mesh, s.MQ, lo=mq_lo, steps=mq_steps)
+        else:
+            raise ValueError(mq)
+
+    def __call__(self, r):
+        return np.concatenate([self.vel(r[: self.nI]), self.s.nu * self.mq(r[self.nI:])])
+
+
+class OseenM1:
+    """M_1 = [[F~, B^T], [0, -M_Q/nu]] (eq:nse-precon-ref), right
+    preconditioner:  z_p = -nu M_Q^+ r_p,  z_u = F~^{-1}(r_u - B^T z_p)."""
+
+    def __init__(self, system, velocity_solve=None, mq=None):
+        s = self.s = system
+        self.nI = s.nI
+        self.vel = velocity_solve or spla.splu(s.FI.tocsc()).solve
+        self.mq = mq or MQExact(s.mesh, s.MQ)
+
+    def __call__(self, r):
+        zp = -self.s.nu * self.mq(r[self.nI:])
+        zu = self.vel(r[: self.nI] - self.s.BI.T @ zp)
+        return np.concatenate([zu, zp])
+
+
+class PCDStage1:
+    """Stage-I preconditioner on the reduced system [F B_1^T; B_1 0]
+    (eq:reduced-system) with M_S = Q_1 F_1^{-1} A_p (eq:discrete-commutator1x):
+        z_p = -A_p^+ F_1 Q_1^{-1} r_p,  z_u = F~^{-1}(r_u - B_1^T z_p).
+    A_p = B_1 diag(M_v)^{-1} B_1^T over interior velocity nodes (singular,
+    null space = constants; A_p^+ by a bordered solve).  F_1 and Q_1 carry no
+    boundary conditions."""
+
+    def __init__(self, system, velocity_solve=None):
+        s = self.s = system
+        m = s.mesh
+        self.nI = s.nI
+        self.B1 = s.BI[: m.nk].tocsr()
+        self.vel = velocity_solve or spla.splu(s.FI.tocsc()).solve
+        self.Q1 = q1_mass(m)
+        self.F1 = q1_convection_diffusion(m, s.wind, s.nu)
+        mv = s.Mv.diagonal()[s.vI]
+        self.Ap = (self.B1 @ sp.diags(1.0 / mv) @ self.B1.T).tocsr()
+        one = np.ones((m.nk, 1))
+        Kb = sp.bmat([[self.Ap, sp.csr_matrix(one)], [sp.csr_matrix(one.T), None]]).tocsc()
+        self.ap_lu = spla.splu(Kb)
+        self.q1_lu = spla.splu(self.Q1.tocsc())
+
+    def ap_pinv(self, r):
+        return self.ap_lu.solve(np.concatenate([r, [0.0]]))[:-1]
+
+    def schur_inv(self, rp):
+        return self.ap_pinv(self.F1 @ self.q1_lu.solve(rp))
+
+    def __call__(self, r):
+        zp = -self.schur_inv(r[self.nI:])
+        zu = self.vel(r[: self.nI] - self.B1.T @ zp)
+        return np.concatenate([zu, zp])
+
+
+def two_stage(system, b_full, eta=1e-6, c=10.0, restart=50, maxit=2000,
+              stage1_prec=None, stage2_prec=None):
+    """The two-stage PCD algorithm of Sec. 3.1.
+
+    Step I:  FGMRES on the reduced system [F B_1^T; B_1 0][u; q_1] = [f; g_1]
+             preconditioned by PCD, stopped when the reduced residual is
+             <= c*eta*||b|| (||b|| = norm of the full lifted interior RHS, the
+             initial residual for a zero initial vector).
+    Step II: FGMRES on the full system with M_1 from [u_1*; q_1*; 0],
+             stopped at eta*||b||.
+    Returns (x_full (not canonicalised), info).
+    """
+    s = system
+    m = s.mesh
+    nI = s.nI
+    b = s.to_interior(b_full)
+    bnorm = float(np.linalg.norm(b))
+    Kred = s.K[: nI + m.nk][:, : nI + m.nk].tocsr()
+    bred = b[: nI + m.nk]
+    P1 = stage1_prec or PCDStage1(s)
+    x1, info1 = fgmres(lambda v: Kred @ v, bred, P1, restart=restart, maxit=maxit,
+                       atol=c * eta * bnorm)
+    x0 = np.concatenate([x1, np.zeros(m.n0)])
+    z_star = b - s.K @ x0
+    P2 = stage2_prec or OseenM1(s)
+    x, info2 = fgmres(lambda v: s.K @ v, b, P2, restart=restart, maxit=maxit,
+                      atol=eta * bnorm, x0=x0)
+    info = dict(stage1=info1, stage2=info2, bnorm=bnorm, z_star=z_star, x_stage1=x0,
+                iterations=info1["iterations"] + info2["iterations"])
+    return s.to_full(x, u_boundary=b_full[: 2 * m.nv]), info
