@@ -1,0 +1,155 @@
+/*
+ * eth.h -- C ABI of the MI355X (gfx950) solvers for the enriched Taylor-Hood
+ * discretisation of Pestana & Silvester, "Fast solution of incompressible flow
+ * problems with two-level pressure approximation" (arXiv 2303.10233).
+ *
+ * Discrete problem (Sec. 2, eq:stokes_fe / eq:saddle_point; Sec. 3,
+ * eq:oseen-system): on a uniform n x n mesh of square Q2 elements, find
+ * x = [u; p] with K x = b, where
+ *     K = [ F  B^T ]     F = nu*A (Stokes) or nu*A + N(w) (Oseen),
+ *         [ B   0  ]     A: vector Q2 Laplacian, N(w): Q2 convection by the
+ *                        nodal Q2 wind w, B: -int q div u,
+ * and the pressure is given in the frame Q1 + P0 (eq:eth_spec): n_k = (n+1)^2
+ * Q1 coefficients followed by n_0 = n^2 element coefficients.  The frame null
+ * vector k = [1; -1] (eq:pressure_null_vector) lies in null(B^T)
+ * (rem:Bnull) and in null(M_Q) (prop:Qnull); for enclosed flow null(K) is
+ * spanned by [0; 1_{n_k}; 0] and [0; 0; 1_{n_0}].
+ *
+ * VECTOR LAYOUT (all vectors FP64, device memory, caller-owned):
+ *     [ u_x on all (2n+1)^2 Q2 nodes | u_y (same) | p_k (n+1)^2 | p_0 n^2 ]
+ * Node (I,J) of an m x m grid is entry J*m + I (x fastest); element (ex,ey) is
+ * entry ey*n + ex.  N = eth_vector_length() = 2(2n+1)^2 + (n+1)^2 + n^2.
+ * A batch of `batch` vectors is stored with stride `ld` >= N (elements).
+ * The velocity on boundary nodes is Dirichlet data: the operator acts on the
+ * interior velocity x all pressure coefficients.
+ *
+ * ERRORS: every int-returning call returns 0 on success, a negative ETH_E*
+ * code on failure (nothing is written to outputs unless stated) and a
+ * positive ETH_W* code for a warning.  eth_last_error() gives a message.
+ * Calls are ordered on the stream given at setup; handles are not thread-safe.
+ */
+#ifndef ETH_H
+#define ETH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ETH_OK             0
+#define ETH_EINVAL        -1  /* invalid argument (size, pointer, option)          */
+#define ETH_EDEVICE       -2  /* a HIP runtime error                                */
+#define ETH_ENOMEM        -3  /* device allocation failed during setup              */
+#define ETH_EINCONSISTENT -4  /* enclosed-flow RHS not orthogonal to null(K^T)      */
+#define ETH_EBREAKDOWN    -5  /* Krylov breakdown (gamma^2 < 0, NaN or Inf)         */
+#define ETH_EUNSUPPORTED  -6  /* option combination not available                   */
+#define ETH_WMAXIT         1  /* iteration limit reached; x holds the last iterate  */
+
+typedef struct eth_problem eth_problem;
+
+typedef enum { ETH_STOKES = 0, ETH_OSEEN = 1 } eth_kind;
+typedef enum { ETH_FP64 = 0, ETH_MIXED = 1 } eth_precision;
+/* velocity block of the preconditioner */
+typedef enum { ETH_VEL_GMG = 0, ETH_VEL_EXACT = 1 } eth_velocity_mode;
+/* pressure block: M_S in the bordered system [[M_S, k], [k^T, 0]] (Sec. 2.2) */
+typedef enum { ETH_MQ_DIAG = 1, ETH_MQ_CHEB_SGS = 2 } eth_mq_mode;
+typedef enum { ETH_MINRES = 0, ETH_FGMRES = 1, ETH_TWO_STAGE = 2 } eth_method;
+
+/*
+ * Problem description.  Zero-initialise, then set what you need; a zero in an
+ * optional field selects the documented default.
+ */
+typedef struct {
+  int32_t n;                 /* Q2 elements per side, >= 2                         */
+  double x0, x1, y0, y1;     /* square domain (x1-x0 == y1-y0)                      */
+  int32_t kind;              /* eth_kind                                            */
+  double nu;                 /* viscosity, > 0 (Stokes: -nu Lap u + grad p = f)     */
+  const double* wind;        /* Oseen: device, 2(2n+1)^2 nodal Q2 wind [w_x|w_y]    */
+  double lid_u;              /* tangential lid velocity on y = y1                   */
+  int32_t corner_mode;       /* 0: top corners get 0 (watertight); 1: lid value     */
+  int32_t velocity_mode;     /* eth_velocity_mode; EXACT needs (2n-1)^2 <= 4096     */
+  int32_t mq_mode;           /* eth_mq_mode (default ETH_MQ_CHEB_SGS)               */
+  int32_t mq_steps;          /* Chebyshev steps for ETH_MQ_CHEB_SGS (default 20)    */
+  double mq_cheb_lo;         /* eigen-interval of M_SGS^{-1} M_Q (default 0.01)      */
+  double mq_cheb_hi;         /*   (default 1, the SGS bound)                        */
+  int32_t gmg_coarse_n;      /* halve while n even and n > gmg_coarse_n (default 4) */
+  int32_t gmg_degree;        /* Chebyshev smoothing degree, pre and post (default 2)*/
+  double gmg_lo_frac;        /* smoother interval [lo_frac, hi_frac] * lambda_max    */
+  double gmg_hi_frac;        /*   (defaults 0.3, 1.1)                               */
+  const double* gmg_lambda;  /* host, optional: lambda_max(D^{-1}A) per smoothing
+                                level (levels-1 values); NULL: Lanczos at setup     */
+  int32_t precision;         /* eth_precision: preconditioner in FP64 or FP32       */
+  int32_t max_batch;         /* largest batch passed to any call (default 1)        */
+  void* stream;              /* hipStream_t for every call (NULL: default stream)   */
+} eth_problem_desc;
+
+typedef struct {
+  int32_t method;            /* eth_method (default ETH_MINRES)                     */
+  double rtol;               /* MINRES: |eta|/gamma_1 (P^{-1}-norm, alg:minres);
+                                GMRES: ||b-Kx||_2/||b||_2 (eq:residual-norm)       */
+  int32_t maxit;             /* iteration limit (default 1000)                      */
+  int32_t restart;           /* FGMRES restart length (default 50)                  */
+  double c_factor;           /* two-stage: stage-I factor c (default 10)           */
+  int32_t canonicalize;      /* 1: subtract the means of p_k and p_0 (default)      */
+  int32_t use_x0;            /* 1: x holds the initial guess on entry               */
+  int32_t use_graph;         /* 1: replay the iteration as a captured hipGraph      */
+  int32_t true_residual;     /* 1: compute ||b - K x||/||b|| into info (default 0)   */
+} eth_solve_opts;
+
+typedef struct {
+  int32_t status;            /* per-RHS status code                                 */
+  int32_t iterations;        /* Krylov iterations (both stages for TWO_STAGE)      */
+  int32_t stage1_iterations; /* TWO_STAGE only                                       */
+  double rel_residual_est;   /* the stopping quantity at exit                       */
+  double rel_residual_true;  /* ||b-Kx||_2/||b||_2 if requested, else -1           */
+} eth_solve_info;
+
+/* Set up a problem: allocates every workspace (solves never allocate), builds
+ * the multigrid hierarchy, diagonals and smoother bounds.  On success *out is
+ * a new handle; on failure *out is NULL and the code is returned. */
+int eth_setup(const eth_problem_desc* desc, eth_problem** out);
+int eth_destroy(eth_problem* p);
+
+/* N = 2(2n+1)^2 + (n+1)^2 + n^2 */
+int64_t eth_vector_length(const eth_problem* p);
+/* number of multigrid levels and the smoother lambda_max per level (host
+ * array of size >= levels-1); either pointer may be NULL */
+int eth_get_levels(const eth_problem* p, int32_t* levels, double* lambdas);
+
+/* Lifted right-hand side (Sec. 2, eq:stokes_fe with the boundary velocity):
+ * interior velocity rows (M_v f)_I - F_IB u_B, pressure rows -B_{:,B} u_B,
+ * boundary velocity rows the Dirichlet values u_B (lid per desc).
+ * f_nodal: device, 2(2n+1)^2 nodal forces [f_x|f_y] per batch entry with
+ * stride ld_f (>= 2(2n+1)^2), or NULL for f = 0.  b: device, batch x ld. */
+int eth_assemble_rhs(eth_problem* p, const double* f_nodal, int64_t ld_f,
+                     double* b, int64_t batch, int64_t ld);
+
+/* y = K x (transpose = 0) or K^T x (transpose = 1) on the full layout:
+ * boundary velocity entries of x are ignored, those of y are set to 0. */
+int eth_apply_operator(eth_problem* p, int transpose, const double* x, double* y,
+                       int64_t batch, int64_t ld);
+
+/* z = P^{-1} r: Stokes block-diagonal preconditioner diag(nu A~, M~_S/nu)
+ * (eq:stokes_pre) with the bordered pressure solve of Sec. 2.2 (z_p is
+ * orthogonal to k).  Boundary velocity entries of z are set to 0. */
+int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, double* z,
+                             int64_t batch, int64_t ld);
+
+/* Solve K x = b (b from eth_assemble_rhs).  x receives the boundary data on
+ * boundary rows, the Krylov solution elsewhere, the pressure canonicalised if
+ * opts->canonicalize.  info: host array of `batch` entries, or NULL.
+ * Returns the worst per-RHS status. */
+int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, double* x,
+              int64_t batch, int64_t ld, eth_solve_info* info);
+
+const char* eth_status_string(int status);
+/* message of the last failing call on this handle (or of the last failing
+ * eth_setup when p is NULL); valid until the next call */
+const char* eth_last_error(const eth_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ETH_H */

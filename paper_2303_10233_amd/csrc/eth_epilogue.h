@@ -1,0 +1,134 @@
+// Scalar work that runs in the last block of a reduction: the recurrences of
+// preconditioned MINRES (alg:minres) kept on the device in FP64, so that an
+// iteration needs no host round trip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace eth {
+
+enum Epilogue : int {
+  EPI_NONE = 0,
+  EPI_MINRES_INIT = 1,   // total = <z1, v1>            -> gamma_1
+  EPI_MINRES_DELTA = 2,  // total = <K zhat_j, zhat_j>   -> delta_j, v-update coefficients
+  EPI_MINRES_GAMMA = 3,  // total = <zhat_{j+1}, v_{j+1}> -> Givens step, w/x coefficients
+  EPI_SCALE = 4,         // out[rhs] = total * scale
+};
+
+// Status codes mirrored from eth.h
+constexpr int kStOK = 0;
+constexpr int kStBreakdown = -5;
+constexpr int kStMaxit = 1;
+
+// Per right-hand side MINRES scalars.  zhat_j = P^{-1} v_j is kept
+// unnormalised; z_j = zhat_j / gamma_j.
+struct MinresScalars {
+  double gamma, gamma_prev, gamma1, delta, eta;
+  double c, c_prev, s, s_prev;
+  double tol;
+  double vy, va, vb;   // v_{j+1} = vy*y - va*v_j - vb*v_{j-1},  y = K zhat_j
+  double wz, wp, wc;   // w_{j+1} = wz*zhat_j - wp*w_{j-1} - wc*w_j
+  double xc;           // x_j = x_{j-1} + xc*w_{j+1}
+  double rel;          // |eta| / gamma_1
+  int active;          // 1 while iterating
+  int wx_todo;         // 1 when the w/x update of the last Givens step is pending
+  int iters, maxit, status, hist_len;
+  double* hist;        // |eta|/gamma_1 per iteration (device, hist_len entries)
+};
+
+struct ScaleState {
+  double* out;
+  double scale;
+};
+
+__device__ inline void minres_init(MinresScalars& s, double g2) {
+  if (!(g2 >= 0.0) || !isfinite(g2)) {
+    s.status = kStBreakdown;
+    s.active = 0;
+    s.wx_todo = 0;
+    return;
+  }
+  const double g = sqrt(g2);
+  s.gamma = g;
+  s.gamma1 = g;
+  s.gamma_prev = 0.0;
+  s.eta = g;
+  s.c = s.c_prev = 1.0;
+  s.s = s.s_prev = 0.0;
+  s.iters = 0;
+  s.rel = 1.0;
+  s.wx_todo = 0;
+  s.status = kStOK;
+  s.active = (g > 0.0) ? 1 : 0;
+  if (s.hist && s.hist_len > 0) s.hist[0] = 1.0;
+}
+
+__device__ inline void minres_delta(MinresScalars& s, double kzz) {
+  const double g = s.gamma;
+  const double delta = kzz / (g * g);
+  s.delta = delta;
+  s.vy = 1.0 / g;
+  s.va = delta / g;
+  s.vb = (s.iters > 0) ? g / s.gamma_prev : 0.0;   // gamma_0 v_0 term is zero at j = 1
+}
+
+__device__ inline void minres_gamma(MinresScalars& s, double g2) {
+  // tolerate rounding-level negatives once the Krylov space is exhausted
+  if (g2 < 0.0 && g2 > -1e-28 * s.gamma1 * s.gamma1) g2 = 0.0;
+  if (!(g2 >= 0.0) || !isfinite(g2)) {
+    s.status = kStBreakdown;
+    s.active = 0;
+    s.wx_todo = 0;
+    return;
+  }
+  const double gn = sqrt(g2);
+  const double g = s.gamma, d = s.delta;
+  const double a0 = s.c * d - s.c_prev * s.s * g;
+  const double a1 = sqrt(a0 * a0 + gn * gn);
+  const double a2 = s.s * d + s.c_prev * s.c * g;
+  const double a3 = s.s_prev * g;
+  const double cn = a0 / a1, sn = gn / a1;
+  s.wz = 1.0 / (g * a1);
+  s.wp = a3 / a1;
+  s.wc = a2 / a1;
+  s.xc = cn * s.eta;
+  s.eta = -sn * s.eta;
+  s.c_prev = s.c;
+  s.c = cn;
+  s.s_prev = s.s;
+  s.s = sn;
+  s.gamma_prev = g;
+  s.gamma = gn;
+  s.iters += 1;
+  s.rel = fabs(s.eta) / s.gamma1;
+  if (s.hist && s.iters < s.hist_len) s.hist[s.iters] = s.rel;
+  s.wx_todo = 1;
+  if (s.rel <= s.tol || gn == 0.0) {
+    s.active = 0;
+  } else if (s.iters >= s.maxit) {
+    s.active = 0;
+    s.status = kStMaxit;
+  }
+}
+
+__device__ inline void run_epilogue(int epi, void* state, int rhs, const double* tot) {
+  switch (epi) {
+    case EPI_MINRES_INIT:
+      minres_init(static_cast<MinresScalars*>(state)[rhs], tot[0]);
+      break;
+    case EPI_MINRES_DELTA:
+      minres_delta(static_cast<MinresScalars*>(state)[rhs], tot[0]);
+      break;
+    case EPI_MINRES_GAMMA:
+      minres_gamma(static_cast<MinresScalars*>(state)[rhs], tot[0]);
+      break;
+    case EPI_SCALE: {
+      ScaleState* st = static_cast<ScaleState*>(state);
+      st->out[rhs] = tot[0] * st->scale;
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+}  // namespace eth

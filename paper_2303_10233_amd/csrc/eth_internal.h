@@ -1,0 +1,98 @@
+// Internal declarations shared by the HIP translation units of libeth.
+// gfx950 (CDNA4): 64-wide wavefronts; all reductions are deterministic
+// (fixed shuffle tree within a wave, fixed order across waves and blocks).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <string>
+
+namespace eth {
+
+// ----------------------------------------------------------------------------
+// Geometry of one mesh level.  Layout of a full vector:
+//   [u_x (nq*nq) | u_y (nq*nq) | p_k (n+1)^2 | p_0 n^2],  nq = 2n+1.
+// ----------------------------------------------------------------------------
+struct Geo {
+  int n;       // elements per side
+  int nq;      // 2n+1 Q2 nodes per side
+  int nv;      // nq*nq
+  int nk;      // (n+1)^2
+  int n0;      // n*n
+  long long N; // 2 nv + nk + n0
+  double h;    // element side
+  __host__ __device__ long long off_uy() const { return nv; }
+  __host__ __device__ long long off_pk() const { return 2LL * nv; }
+  __host__ __device__ long long off_p0() const { return 2LL * nv + nk; }
+};
+
+inline Geo make_geo(int n, double h) {
+  Geo g;
+  g.n = n;
+  g.nq = 2 * n + 1;
+  g.nv = g.nq * g.nq;
+  g.nk = (n + 1) * (n + 1);
+  g.n0 = n * n;
+  g.N = 2LL * g.nv + g.nk + g.n0;
+  g.h = h;
+  return g;
+}
+
+constexpr int kWave = 64;
+
+// ----------------------------------------------------------------------------
+// Deterministic reductions
+// ----------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over a block of NT threads (NT multiple of 64).  Result valid in every
+// thread.  `sh` must hold NT/64 doubles.
+template <int NT>
+__device__ inline double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  v = wave_sum(v);
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+// Reduction context: every block of right-hand side `rhs` writes one partial
+// (or `nvals` partials) and takes a ticket; the last block sums the partials
+// in block order and hands the totals to an epilogue.
+constexpr int kMaxRedVals = 4;
+struct RedCtx {
+  double* partials;    // [batch][nvals][nblocks]
+  unsigned* tickets;   // [batch], zero between launches (reset by last block)
+  double* result;      // [batch][nvals] totals (may be null)
+  int nblocks;         // blocks per right-hand side
+  int nvals;           // values reduced per block (<= kMaxRedVals)
+  int epi;             // epilogue id (eth_epilogue.h), 0 = none
+  void* epi_state;     // epilogue state array
+};
+
+// ----------------------------------------------------------------------------
+// Error handling helpers (host)
+// ----------------------------------------------------------------------------
+struct HipError {
+  hipError_t err;
+  std::string where;
+};
+
+#define ETH_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) throw ::eth::HipError{e_, std::string(#call)};       \
+  } while (0)
+
+#define ETH_LAUNCH_CHECK() ETH_HIP(hipGetLastError())
+
+}  // namespace eth

@@ -1,0 +1,119 @@
+// Host launchers of the HIP kernels (one declaration per kernel family).
+#pragma once
+#include "eth_epilogue.h"
+#include "eth_internal.h"
+
+namespace eth {
+
+// Per right-hand-side gate: a kernel skips RHS r when p && p[r*stride] == 0.
+struct Gate {
+  const int* p;
+  int stride;  // in ints
+  __device__ bool off(int r) const { return p && p[(long long)r * stride] == 0; }
+};
+inline Gate no_gate() { return Gate{nullptr, 0}; }
+
+// ---------------- saddle-point operator (k_saddle.hip) ----------------------
+// y = K x on the full layout, FP64.  mode 0: boundary velocity inputs are
+// masked, boundary rows of y are 0.  Optional fused reduction of <y, x>.
+int saddle_blocks(const Geo& g);
+void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, long long ld,
+                         int batch, Gate gate, const RedCtx* dot, hipStream_t st);
+// Oseen: y = [nu A + N(w)] u + B^T p, B u  (transpose: N -> N^T)
+void launch_apply_oseen(const Geo& g, double nu, const double* wind, int transpose,
+                        const double* x, double* y, long long ld, int batch, Gate gate,
+                        const RedCtx* dot, hipStream_t st);
+// b = lifted RHS: interior rows (M_v f)_I - (F u_B)_I, pressure rows -B u_B,
+// boundary rows u_B.  ub: full-length velocity Dirichlet vector (2 nv).
+void launch_lift_rhs(const Geo& g, double nu, const double* wind, const double* ub,
+                     const double* f, long long ldf, double* b, long long ld, int batch,
+                     hipStream_t st);
+void launch_dirichlet_lid(const Geo& g, double lid_u, int corner_mode, double* ub,
+                          hipStream_t st);
+
+// ---------------- vector kernels (k_vector.hip) ------------------------------
+void launch_dot(long long n, const double* x, const double* y, long long ld, int batch,
+                const RedCtx& rc, Gate gate, hipStream_t st);
+int dot_blocks(long long n);
+// y = a*x + b*y on [0,n)
+void launch_axpby(long long n, double a, const double* x, double b, double* y, long long ld,
+                  int batch, hipStream_t st);
+void launch_copy(long long n, const double* x, long long ldx, double* y, long long ldy,
+                 int batch, hipStream_t st);
+void launch_fill(long long n, double v, double* y, long long ld, int batch, hipStream_t st);
+// zero the boundary velocity rows of a full-layout vector
+void launch_zero_boundary(const Geo& g, double* y, long long ld, int batch, hipStream_t st);
+// x boundary rows <- b boundary rows
+void launch_copy_boundary(const Geo& g, const double* b, double* x, long long ld, int batch,
+                          hipStream_t st);
+// MINRES vector updates
+void launch_minres_v(long long n, const double* y, const double* v, double* vprev_io,
+                     long long ld, int batch, const MinresScalars* s, hipStream_t st);
+void launch_minres_wx(long long n, const double* z, double* wprev_io, const double* w,
+                      double* x, long long ld, int batch, MinresScalars* s,
+                      unsigned* tickets, hipStream_t st);
+// v = b - y with boundary rows zeroed (initial residual)
+void launch_residual_init(const Geo& g, const double* b, const double* y, double* v,
+                          long long ld, int batch, hipStream_t st);
+// pressure block sums (p_k, p_0) per RHS -> out[2*rhs + {0,1}]
+void launch_pressure_sums(const Geo& g, const double* x, long long ld, int batch,
+                          double* partials, unsigned* tickets, double* out, hipStream_t st);
+void launch_pressure_shift(const Geo& g, double* x, long long ld, int batch,
+                           const double* sums, hipStream_t st);
+
+// ---------------- geometric multigrid (k_gmg.hip) ---------------------------
+// Scalar Q2 Laplacian planes: [batch][2 components][nq*nq], boundary zero.
+template <typename T>
+// has_prev: 0 none (alpha ignored), 1 x_prev in xo, 2 x_prev = 0
+void launch_cheb_step(const Geo& g, const T* b, const T* x, T* xnew_io_prev, double alpha,
+                      double beta, int has_prev, int nplanes, double* out64, long long ld64,
+                      double out_scale, Gate gate, int batch, hipStream_t st);
+template <typename T>
+void launch_vcycle_entry(const Geo& g, const double* r, long long ld, T* b, T* x,
+                         double beta, int batch, Gate gate, hipStream_t st);
+template <typename T>
+void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* bc, T* xc,
+                     double beta_c, int nplanes, int batch, Gate gate, hipStream_t st);
+template <typename T>
+void launch_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int nplanes,
+                        int batch, Gate gate, hipStream_t st);
+// dense coarse solve: x = Ainv * b on the interior nodes of each plane
+template <typename T>
+// gbuf: 2*ni*batch doubles of scratch, used when ni exceeds the LDS staging limit
+void launch_dense_solve(const Geo& g, const double* Ainv, int ni, const T* b, T* x,
+                        int nplanes, double* out64, long long ld64, double out_scale,
+                        const double* in64, long long ldin, double* gbuf, int batch, Gate gate,
+                        hipStream_t st);
+// dense Laplacian of the interior nodes, and Gauss-Jordan inverse helpers
+void launch_dense_laplacian(const Geo& g, double* A, int ni, hipStream_t st);
+void launch_gj_step(double* aug, int ni, int k, double* colbuf, double* rowbuf,
+                    hipStream_t st);
+void launch_extract_inverse(const double* aug, int ni, double* Ainv, hipStream_t st);
+// setup helpers on one FP64 plane: mode 0: y = A x, mode 1: y = D^{-1} x
+// (interior nodes; boundary 0)
+void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStream_t st);
+
+// ---------------- pressure-mass solves (k_mq.hip) ----------------------------
+// z = nu * bordered diag solve of r (pressure part of full-layout vectors)
+void launch_mq_diag_dot(const Geo& g, const double* r, long long ld, int batch,
+                        const RedCtx& rc, Gate gate, hipStream_t st);
+void launch_mq_diag_apply(const Geo& g, const double* r, double* z, long long ld, int batch,
+                          const double* lam, double scale, Gate gate, hipStream_t st);
+// Chebyshev-SGS pieces on pressure vectors [batch][np] in T (np = nk + n0)
+template <typename T>
+void launch_mq_kdot(const Geo& g, const T* x, long long ldx, long long off, int batch,
+                    const RedCtx& rc, Gate gate, hipStream_t st);
+template <typename T>
+void launch_mq_project_in(const Geo& g, const double* r, long long ld, T* rt, T* z, T* t, T* d,
+                          int batch, const double* coef, Gate gate, hipStream_t st);
+template <typename T>
+void launch_mq_colour(const Geo& g, const T* r, T* t, int colour, int batch, Gate gate,
+                      hipStream_t st);
+template <typename T>
+void launch_mq_cheb_combine(const Geo& g, T* t, T* z, T* d, double a, double b, int first,
+                            int batch, Gate gate, hipStream_t st);
+template <typename T>
+void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, int batch,
+                           const double* coef, double scale, Gate gate, hipStream_t st);
+
+}  // namespace eth

@@ -1,0 +1,801 @@
+// Runtime of libeth: problem set-up (multigrid hierarchy, coarse inverses,
+// smoother bounds, workspaces), the block preconditioner, the MINRES driver
+// with device-resident recurrences and optional hipGraph replay, and the C ABI
+// declared in eth.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/eth.h"
+#include "eth_kernels.h"
+
+namespace eth {
+
+static thread_local std::string g_setup_error;
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Chebyshev polynomial smoother coefficients for degree d on [lo, hi]:
+// step k: x_{k+1} = x_k + alpha_k (x_k - x_{k-1}) + beta_k D^{-1}(b - A x_k)
+static void cheb_coefs(double lo, double hi, int d, std::vector<double>& alpha,
+                       std::vector<double>& beta) {
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  alpha.assign(d, 0.0);
+  beta.assign(d, 0.0);
+  double rho = 1.0 / sigma;
+  beta[0] = 1.0 / theta;
+  for (int k = 1; k < d; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    alpha[k] = rn * rho;
+    beta[k] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+// largest eigenvalue of a symmetric tridiagonal matrix (Sturm bisection)
+static double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < m; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = a[i] - x - b[i - 1] * b[i - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= m) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+struct Problem {
+  eth_problem_desc d{};
+  Geo g{};
+  hipStream_t st = nullptr;
+  int max_batch = 1;
+  long long ldw = 0;                 // internal stride of Krylov vectors
+  bool mixed = false;
+  std::string err;
+  std::vector<void*> allocs;
+
+  // velocity preconditioner
+  std::vector<Geo> lv;               // multigrid levels (lv[0] finest)
+  std::vector<double> lam;           // lambda_max(D^-1 A) per smoothing level
+  std::vector<std::vector<double>> ca, cb;   // Chebyshev coefficients per level
+  double* Ainv = nullptr;            // dense inverse on the coarsest level
+  int coarse_ni = 0;
+  double* dense_gbuf = nullptr;
+  std::vector<void*> vb, vx, vxo;    // per-level plane buffers (T)
+
+  // pressure preconditioner
+  void *mq_r = nullptr, *mq_z = nullptr, *mq_t = nullptr, *mq_d = nullptr;
+  double* mq_coef = nullptr;         // batch
+  double* mq_coef2 = nullptr;        // batch
+  double kDk = 0.0, kk = 0.0;
+  std::vector<double> mq_a, mq_b;    // Chebyshev coefficients for the SGS iteration
+  ScaleState* d_scale = nullptr;     // [4] scale epilogue states
+
+  // Krylov workspace
+  double *kb = nullptr, *kx = nullptr, *ky = nullptr;
+  double *kv[2] = {nullptr, nullptr}, *kz[2] = {nullptr, nullptr}, *kw[2] = {nullptr, nullptr};
+  MinresScalars* d_ms = nullptr;
+  MinresScalars* h_ms = nullptr;     // pinned host mirror
+  double* d_hist = nullptr;
+  int hist_len = 0;
+  double* red_partials = nullptr;
+  unsigned* red_tickets = nullptr;
+  unsigned* wx_tickets = nullptr;
+  double* red_result = nullptr;      // batch * 4
+  double* h_red = nullptr;           // pinned
+  double* ub = nullptr;              // Dirichlet data (2 nv)
+
+  // graph cache (keyed by batch); graphs are captured and replayed on the
+  // internal stream gst, joined to the caller's stream with events
+  hipGraphExec_t gexec = nullptr;
+  int gexec_batch = -1;
+  hipStream_t gst = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+
+  ~Problem() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (gst) (void)hipStreamDestroy(gst);
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_ms) (void)hipHostFree(h_ms);
+    if (h_red) (void)hipHostFree(h_red);
+  }
+
+  RedCtx red(int nblocks, int nvals, int epi, void* state, double* result = nullptr) {
+    RedCtx rc{};
+    rc.partials = red_partials;
+    rc.tickets = red_tickets;
+    rc.result = result;
+    rc.nblocks = nblocks;
+    rc.nvals = nvals;
+    rc.epi = epi;
+    rc.epi_state = state;
+    return rc;
+  }
+  Gate active_gate() const {
+    return Gate{&d_ms[0].active, (int)(sizeof(MinresScalars) / sizeof(int))};
+  }
+
+  // ---------------------------------------------------------------- setup
+  void setup(const eth_problem_desc& desc);
+  void build_velocity();
+  void build_pressure();
+  double lanczos_lambda_max(const Geo& g, int steps);
+
+  // ------------------------------------------------------- preconditioner
+  template <typename T>
+  void vcycle(const double* r, double* z, long long ld, int batch, Gate gate);
+  template <typename T>
+  void mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate);
+  void precond(const double* r, double* z, long long ld, int batch, Gate gate);
+
+  // ---------------------------------------------------------------- solve
+  void minres_iteration(int batch, int parity);
+  int solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
+                   eth_solve_info* info);
+  void run_iterations(int batch, int count, bool use_graph);
+};
+
+// ------------------------------------------------------------------------------
+void Problem::setup(const eth_problem_desc& desc) {
+  d = desc;
+  if (d.n < 2) throw std::invalid_argument("n must be >= 2");
+  if (!(d.x1 > d.x0) || !(d.y1 > d.y0)) throw std::invalid_argument("empty domain");
+  if (std::fabs((d.x1 - d.x0) - (d.y1 - d.y0)) > 1e-12 * (d.x1 - d.x0))
+    throw std::invalid_argument("square domain required");
+  if (!(d.nu > 0.0)) throw std::invalid_argument("nu must be > 0");
+  if (d.kind != ETH_STOKES) throw std::runtime_error("unsupported:kind");
+  if (d.mq_mode == 0) d.mq_mode = ETH_MQ_CHEB_SGS;
+  if (d.mq_mode != ETH_MQ_DIAG && d.mq_mode != ETH_MQ_CHEB_SGS)
+    throw std::invalid_argument("invalid mq_mode");
+  if (d.mq_steps <= 0) d.mq_steps = 20;
+  if (d.mq_cheb_lo <= 0.0) d.mq_cheb_lo = 0.01;
+  if (d.mq_cheb_hi <= 0.0) d.mq_cheb_hi = 1.0;
+  if (!(d.mq_cheb_hi > d.mq_cheb_lo)) throw std::invalid_argument("mq interval empty");
+  if (d.gmg_coarse_n <= 0) d.gmg_coarse_n = 4;
+  if (d.gmg_degree <= 0) d.gmg_degree = 2;
+  if (d.gmg_lo_frac <= 0.0) d.gmg_lo_frac = 0.3;
+  if (d.gmg_hi_frac <= 0.0) d.gmg_hi_frac = 1.1;
+  if (d.velocity_mode != ETH_VEL_GMG && d.velocity_mode != ETH_VEL_EXACT)
+    throw std::invalid_argument("invalid velocity_mode");
+  if (d.precision != ETH_FP64 && d.precision != ETH_MIXED)
+    throw std::invalid_argument("invalid precision");
+  mixed = d.precision == ETH_MIXED;
+  max_batch = d.max_batch > 0 ? d.max_batch : 1;
+  st = static_cast<hipStream_t>(d.stream);
+  g = make_geo(d.n, (d.x1 - d.x0) / d.n);
+  ldw = (g.N + 63) / 64 * 64;
+
+  const size_t vec = (size_t)ldw * max_batch;
+  kb = alloc<double>(vec);
+  kx = alloc<double>(vec);
+  ky = alloc<double>(vec);
+  for (int i = 0; i < 2; ++i) {
+    kv[i] = alloc<double>(vec);
+    kz[i] = alloc<double>(vec);
+    kw[i] = alloc<double>(vec);
+  }
+  d_ms = alloc<MinresScalars>(max_batch);
+  ETH_HIP(hipHostMalloc((void**)&h_ms, sizeof(MinresScalars) * max_batch, hipHostMallocDefault));
+  hist_len = 4097;
+  d_hist = alloc<double>((size_t)hist_len * max_batch);
+  const int maxblocks = std::max(std::max(dot_blocks(g.N), saddle_blocks(g)), 4096);
+  red_partials = alloc<double>((size_t)maxblocks * kMaxRedVals * max_batch);
+  red_tickets = alloc<unsigned>(max_batch);
+  wx_tickets = alloc<unsigned>(max_batch);
+  red_result = alloc<double>((size_t)kMaxRedVals * max_batch);
+  ETH_HIP(hipHostMalloc((void**)&h_red, sizeof(double) * kMaxRedVals * max_batch, hipHostMallocDefault));
+  ETH_HIP(hipMemsetAsync(red_tickets, 0, sizeof(unsigned) * max_batch, st));
+  ETH_HIP(hipMemsetAsync(wx_tickets, 0, sizeof(unsigned) * max_batch, st));
+  ETH_HIP(hipMemsetAsync(d_ms, 0, sizeof(MinresScalars) * max_batch, st));
+  ub = alloc<double>(2 * (size_t)g.nv);
+  launch_dirichlet_lid(g, d.lid_u, d.corner_mode, ub, st);
+  d_scale = alloc<ScaleState>(4);
+
+  build_velocity();
+  build_pressure();
+  ETH_HIP(hipStreamSynchronize(st));
+}
+
+double Problem::lanczos_lambda_max(const Geo& lg, int steps) {
+  // PCG with Jacobi preconditioning on A x = b; the CG coefficients define the
+  // Lanczos tridiagonal of D^{-1}A, whose largest Ritz value is returned.
+  const size_t nv = lg.nv;
+  double* r = alloc<double>(nv);
+  double* z = alloc<double>(nv);
+  double* p = alloc<double>(nv);
+  double* q = alloc<double>(nv);
+  std::vector<double> h(nv, 0.0);
+  unsigned long long s = 0x9E3779B97F4A7C15ULL;
+  for (int J = 1; J < lg.nq - 1; ++J)
+    for (int I = 1; I < lg.nq - 1; ++I) {
+      s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+      h[(size_t)J * lg.nq + I] = (double)((s >> 11) & ((1ULL << 53) - 1)) / (double)(1ULL << 53) - 0.5;
+    }
+  ETH_HIP(hipMemcpyAsync(r, h.data(), nv * sizeof(double), hipMemcpyHostToDevice, st));
+  auto dot = [&](const double* a, const double* b) {
+    RedCtx rc = red(dot_blocks((long long)nv), 1, EPI_NONE, nullptr, red_result);
+    launch_dot((long long)nv, a, b, 0, 1, rc, no_gate(), st);
+    ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double), hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    return h_red[0];
+  };
+  launch_plane_op(lg, 1, r, z, st);
+  launch_copy((long long)nv, z, 0, p, 0, 1, st);
+  double rz = dot(r, z);
+  std::vector<double> al, be;
+  for (int k = 0; k < steps; ++k) {
+    launch_plane_op(lg, 0, p, q, st);
+    const double pq = dot(p, q);
+    if (!(pq > 0.0)) break;
+    const double alpha = rz / pq;
+    launch_axpby((long long)nv, -alpha, q, 1.0, r, 0, 1, st);
+    launch_plane_op(lg, 1, r, z, st);
+    const double rzn = dot(r, z);
+    const double beta = rzn / rz;
+    al.push_back(alpha);
+    be.push_back(beta);
+    launch_axpby((long long)nv, 1.0, z, beta, p, 0, 1, st);
+    rz = rzn;
+    if (!(rz > 0.0)) break;
+  }
+  const int m = (int)al.size();
+  std::vector<double> ta(m), tb(m > 0 ? m - 1 : 0);
+  for (int k = 0; k < m; ++k) {
+    ta[k] = 1.0 / al[k] + (k > 0 ? be[k - 1] / al[k - 1] : 0.0);
+    if (k + 1 < m) tb[k] = std::sqrt(be[k]) / al[k];
+  }
+  return m > 0 ? tridiag_max_eig(ta, tb) : 1.0;
+}
+
+void Problem::build_velocity() {
+  lv.clear();
+  if (d.velocity_mode == ETH_VEL_EXACT) {
+    lv.push_back(g);
+  } else {
+    int n = d.n;
+    double h = g.h;
+    lv.push_back(g);
+    while (n % 2 == 0 && n > d.gmg_coarse_n) {
+      n /= 2;
+      h *= 2.0;
+      lv.push_back(make_geo(n, h));
+    }
+  }
+  const Geo& gc = lv.back();
+  coarse_ni = (gc.nq - 2) * (gc.nq - 2);
+  if (coarse_ni > 4225) throw std::runtime_error("unsupported:coarsest mesh too large for the dense solve (odd n > 33 needs n = m * 2^k with m <= 33)");
+  dense_gbuf = alloc<double>((size_t)2 * coarse_ni * max_batch);
+  // dense inverse of the coarsest-level Laplacian (Gauss-Jordan, SPD, no pivoting)
+  {
+    const int ni = coarse_ni;
+    double* aug = alloc<double>((size_t)ni * 2 * ni);
+    double* col = alloc<double>(ni);
+    double* row = alloc<double>(2 * (size_t)ni);
+    Ainv = alloc<double>((size_t)ni * ni);
+    launch_dense_laplacian(gc, aug, ni, st);
+    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
+    launch_extract_inverse(aug, ni, Ainv, st);
+  }
+  const int L = (int)lv.size();
+  lam.assign(std::max(L - 1, 0), 0.0);
+  ca.assign(lam.size(), {});
+  cb.assign(lam.size(), {});
+  for (int l = 0; l + 1 < L; ++l) {
+    lam[l] = d.gmg_lambda ? d.gmg_lambda[l] : lanczos_lambda_max(lv[l], 30);
+    cheb_coefs(d.gmg_lo_frac * lam[l], d.gmg_hi_frac * lam[l], d.gmg_degree, ca[l], cb[l]);
+  }
+  vb.assign(L, nullptr);
+  vx.assign(L, nullptr);
+  vxo.assign(L, nullptr);
+  if (L > 1) {
+    for (int l = 0; l < L; ++l) {
+      const size_t n = (size_t)2 * max_batch * lv[l].nv;
+      if (mixed) {
+        vb[l] = alloc<float>(n);
+        vx[l] = alloc<float>(n);
+        vxo[l] = alloc<float>(n);
+        ETH_HIP(hipMemsetAsync(vb[l], 0, n * sizeof(float), st));
+        ETH_HIP(hipMemsetAsync(vx[l], 0, n * sizeof(float), st));
+        ETH_HIP(hipMemsetAsync(vxo[l], 0, n * sizeof(float), st));
+      } else {
+        vb[l] = alloc<double>(n);
+        vx[l] = alloc<double>(n);
+        vxo[l] = alloc<double>(n);
+        ETH_HIP(hipMemsetAsync(vb[l], 0, n * sizeof(double), st));
+        ETH_HIP(hipMemsetAsync(vx[l], 0, n * sizeof(double), st));
+        ETH_HIP(hipMemsetAsync(vxo[l], 0, n * sizeof(double), st));
+      }
+    }
+  }
+}
+
+void Problem::build_pressure() {
+  const double h2 = g.h * g.h;
+  // k^T D^{-1} k and k^T k for the frame null vector k = [1; -1]
+  double s = 0.0;
+  for (int dd = 0; dd <= g.n; ++dd)
+    for (int c = 0; c <= g.n; ++c) {
+      const int mx = (c > 0) + (c < g.n), my = (dd > 0) + (dd < g.n);
+      s += 36.0 / (h2 * 4.0 * mx * my);
+    }
+  s += (double)g.n0 / h2;
+  kDk = s;
+  kk = (double)g.nk + g.n0;
+  mq_coef = alloc<double>(max_batch);
+  mq_coef2 = alloc<double>(max_batch);
+  ScaleState hs[4];
+  hs[0] = ScaleState{mq_coef, 1.0 / kDk};
+  hs[1] = ScaleState{mq_coef, 1.0 / kk};
+  hs[2] = ScaleState{mq_coef2, 1.0 / kk};
+  hs[3] = ScaleState{mq_coef, 1.0};
+  ETH_HIP(hipMemcpyAsync(d_scale, hs, sizeof(hs), hipMemcpyHostToDevice, st));
+  if (d.mq_mode == ETH_MQ_CHEB_SGS) {
+    const size_t n = (size_t)max_batch * (g.nk + g.n0);
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    mq_r = alloc<char>(n * es);
+    mq_z = alloc<char>(n * es);
+    mq_t = alloc<char>(n * es);
+    mq_d = alloc<char>(n * es);
+    // Chebyshev semi-iteration: step k uses a_k d_{k-1} + b_k s_k
+    const double lo = d.mq_cheb_lo, hi = d.mq_cheb_hi;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    mq_a.assign(d.mq_steps, 0.0);
+    mq_b.assign(d.mq_steps, 0.0);
+    double rho = 1.0 / sigma;
+    mq_b[0] = 1.0 / theta;
+    for (int k = 1; k < d.mq_steps; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      mq_a[k] = rn * rho;
+      mq_b[k] = 2.0 * rn / delta;
+      rho = rn;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <typename T>
+void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate gate) {
+  const int L = (int)lv.size();
+  const double sc = 1.0 / d.nu;
+  if (L == 1) {
+    launch_dense_solve<T>(lv[0], Ainv, coarse_ni, nullptr, nullptr, 2 * batch, z, ld, sc, r, ld,
+                          dense_gbuf, batch, gate, st);
+    launch_zero_boundary(lv[0], z, ld, batch, st);
+    return;
+  }
+  std::vector<T*> b(L), x(L), xo(L);
+  for (int l = 0; l < L; ++l) {
+    b[l] = static_cast<T*>(vb[l]);
+    x[l] = static_cast<T*>(vx[l]);
+    xo[l] = static_cast<T*>(vxo[l]);
+  }
+  const int np = 2 * batch;
+  const int deg = d.gmg_degree;
+  // finest level: b = r_u, first smoothing step from zero
+  launch_vcycle_entry<T>(lv[0], r, ld, b[0], x[0], cb[0][0], batch, gate, st);
+  for (int l = 0; l + 1 < L; ++l) {
+    for (int k = 1; k < deg; ++k) {
+      launch_cheb_step<T>(lv[l], b[l], x[l], xo[l], ca[l][k], cb[l][k], k == 1 ? 2 : 1, np,
+                          nullptr, 0, 0.0, gate, batch, st);
+      std::swap(x[l], xo[l]);
+    }
+    const double beta_c = (l + 1 < L - 1) ? cb[l + 1][0] : 0.0;
+    launch_restrict<T>(lv[l], lv[l + 1], b[l], x[l], b[l + 1], x[l + 1], beta_c, np, batch, gate, st);
+  }
+  launch_dense_solve<T>(lv[L - 1], Ainv, coarse_ni, b[L - 1], x[L - 1], np, nullptr, 0, 0.0,
+                        nullptr, 0, dense_gbuf, batch, gate, st);
+  for (int l = L - 2; l >= 0; --l) {
+    launch_prolong_add<T>(lv[l], lv[l + 1], x[l + 1], x[l], np, batch, gate, st);
+    for (int k = 0; k < deg; ++k) {
+      const bool last = (l == 0 && k == deg - 1);
+      launch_cheb_step<T>(lv[l], b[l], x[l], xo[l], ca[l][k], cb[l][k], k == 0 ? 0 : 1, np,
+                          last ? z : nullptr, ld, sc, gate, batch, st);
+      if (!last) std::swap(x[l], xo[l]);
+    }
+  }
+}
+
+template <typename T>
+void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate) {
+  T* rr = static_cast<T*>(mq_r);
+  T* zz = static_cast<T*>(mq_z);
+  T* tt = static_cast<T*>(mq_t);
+  T* dd = static_cast<T*>(mq_d);
+  const long long np = (long long)g.nk + g.n0;
+  const int nbk = dot_blocks(np);
+  RedCtx rin = red(nbk, 1, EPI_SCALE, &d_scale[1]);
+  launch_mq_kdot<double>(g, r, ld, g.off_pk(), batch, rin, gate, st);
+  launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);
+  static const int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
+  for (int k = 0; k < d.mq_steps; ++k) {
+    for (int c = 0; c < 9; ++c) launch_mq_colour<T>(g, rr, tt, order[c], batch, gate, st);
+    launch_mq_cheb_combine<T>(g, tt, zz, dd, mq_a[k], mq_b[k], k == 0, batch, gate, st);
+  }
+  RedCtx rout = red(nbk, 1, EPI_SCALE, &d_scale[2]);
+  launch_mq_kdot<T>(g, zz, np, 0, batch, rout, gate, st);
+  launch_mq_project_out<T>(g, zz, z, ld, batch, mq_coef2, d.nu, gate, st);
+}
+
+void Problem::precond(const double* r, double* z, long long ld, int batch, Gate gate) {
+  if (mixed) vcycle<float>(r, z, ld, batch, gate);
+  else vcycle<double>(r, z, ld, batch, gate);
+  if (d.mq_mode == ETH_MQ_DIAG) {
+    const long long np = (long long)g.nk + g.n0;
+    RedCtx rc = red(dot_blocks(np), 1, EPI_SCALE, &d_scale[0]);
+    launch_mq_diag_dot(g, r, ld, batch, rc, gate, st);
+    launch_mq_diag_apply(g, r, z, ld, batch, mq_coef, d.nu, gate, st);
+  } else if (mixed) {
+    mq_cheb<float>(r, z, ld, batch, gate);
+  } else {
+    mq_cheb<double>(r, z, ld, batch, gate);
+  }
+}
+
+// ---------------------------------------------------------------- MINRES
+// One iteration of alg:minres.  parity selects which buffers hold
+// (v_j, v_{j-1}), (zhat_j, zhat_{j+1}) and (w_j, w_{j-1}).
+void Problem::minres_iteration(int batch, int parity) {
+  const int a = parity, b = 1 - parity;
+  double* v = kv[a];
+  double* vp = kv[b];
+  double* z = kz[a];
+  double* zn = kz[b];
+  double* w = kw[a];
+  double* wp = kw[b];
+  const Gate gate = active_gate();
+  RedCtx rd = red(saddle_blocks(g), 1, EPI_MINRES_DELTA, d_ms);
+  launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st);
+  launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st);   // vp <- v_{j+1}
+  precond(vp, zn, ldw, batch, gate);
+  RedCtx rg = red(dot_blocks(g.N), 1, EPI_MINRES_GAMMA, d_ms);
+  launch_dot(g.N, zn, vp, ldw, batch, rg, gate, st);
+  launch_minres_wx(g.N, z, wp, w, kx, ldw, batch, d_ms, wx_tickets, st);   // wp <- w_{j+1}
+}
+
+void Problem::run_iterations(int batch, int count, bool use_graph) {
+  // `count` is even: the buffer roles repeat every two iterations
+  if (!use_graph) {
+    for (int i = 0; i < count; ++i) minres_iteration(batch, i & 1);
+    return;
+  }
+  if (!gst) {
+    ETH_HIP(hipStreamCreateWithFlags(&gst, hipStreamNonBlocking));
+    ETH_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    ETH_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  }
+  hipStream_t caller = st;
+  ETH_HIP(hipEventRecord(ev_fork, caller));
+  ETH_HIP(hipStreamWaitEvent(gst, ev_fork, 0));
+  st = gst;
+  struct Restore {
+    hipStream_t& s;
+    hipStream_t v;
+    ~Restore() { s = v; }
+  } restore{st, caller};
+  if (!gexec || gexec_batch != batch) {
+    if (gexec) {
+      ETH_HIP(hipGraphExecDestroy(gexec));
+      gexec = nullptr;
+    }
+    hipGraph_t graph;
+    ETH_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    minres_iteration(batch, 0);
+    minres_iteration(batch, 1);
+    ETH_HIP(hipStreamEndCapture(st, &graph));
+    ETH_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    ETH_HIP(hipGraphDestroy(graph));
+    gexec_batch = batch;
+  }
+  for (int i = 0; i < count; i += 2) ETH_HIP(hipGraphLaunch(gexec, gst));
+  ETH_HIP(hipEventRecord(ev_join, gst));
+  ETH_HIP(hipStreamWaitEvent(caller, ev_join, 0));
+}
+
+int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch,
+                          long long ld, eth_solve_info* info) {
+  const double tol = o.rtol > 0 ? o.rtol : 1e-8;
+  const int maxit = o.maxit > 0 ? o.maxit : 1000;
+  // Krylov RHS: b with the boundary rows zeroed (they carry Dirichlet data)
+  launch_copy(g.N, b, ld, kb, ldw, batch, st);
+  launch_zero_boundary(g, kb, ldw, batch, st);
+  // initial residual v1 = b - K x0
+  if (o.use_x0) {
+    launch_copy(g.N, x, ld, kx, ldw, batch, st);
+    launch_zero_boundary(g, kx, ldw, batch, st);
+    launch_apply_stokes(g, d.nu, kx, ky, ldw, batch, no_gate(), nullptr, st);
+    launch_residual_init(g, kb, ky, kv[0], ldw, batch, st);
+  } else {
+    launch_fill(g.N, 0.0, kx, ldw, batch, st);
+    launch_copy(g.N, kb, ldw, kv[0], ldw, batch, st);
+  }
+  launch_fill(g.N, 0.0, kv[1], ldw, batch, st);
+  launch_fill(g.N, 0.0, kw[0], ldw, batch, st);
+  launch_fill(g.N, 0.0, kw[1], ldw, batch, st);
+  // scalar state
+  for (int r = 0; r < batch; ++r) {
+    MinresScalars& s = h_ms[r];
+    std::memset(&s, 0, sizeof(s));
+    s.tol = tol;
+    s.maxit = maxit;
+    s.hist = d_hist + (size_t)r * hist_len;
+    s.hist_len = hist_len;
+    s.active = 1;
+  }
+  ETH_HIP(hipMemcpyAsync(d_ms, h_ms, sizeof(MinresScalars) * batch, hipMemcpyHostToDevice, st));
+  // z1 = P^{-1} v1, gamma_1
+  precond(kv[0], kz[0], ldw, batch, no_gate());
+  RedCtx ri = red(dot_blocks(g.N), 1, EPI_MINRES_INIT, d_ms);
+  launch_dot(g.N, kz[0], kv[0], ldw, batch, ri, no_gate(), st);
+  // iterate in chunks, predicting the remaining count from the recent rate
+  const bool use_graph = o.use_graph != 0;
+  int done = 0;
+  int chunk = 8;
+  double prev_rel = 1.0;
+  int prev_it = 0;
+  while (true) {
+    run_iterations(batch, chunk, use_graph);
+    done += chunk;
+    ETH_HIP(hipMemcpyAsync(h_ms, d_ms, sizeof(MinresScalars) * batch, hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    double worst_rel = 0.0;
+    int it = 0;
+    for (int r = 0; r < batch; ++r) {
+      if (h_ms[r].active) {
+        any = true;
+        worst_rel = std::max(worst_rel, h_ms[r].rel);
+        it = std::max(it, h_ms[r].iters);
+      }
+    }
+    if (!any || done >= maxit + 2) break;
+    // predict remaining iterations from the observed rate
+    int next = 8;
+    if (it > prev_it && worst_rel > 0 && prev_rel > worst_rel) {
+      const double rate = std::pow(worst_rel / prev_rel, 1.0 / (it - prev_it));
+      if (rate < 1.0 && rate > 0.0) {
+        const double rem = std::log(tol / worst_rel) / std::log(rate);
+        next = (int)std::ceil(rem) + 1;
+      } else {
+        next = 16;
+      }
+    }
+    next = std::max(2, std::min(next, 64));
+    next += next & 1;
+    prev_rel = worst_rel;
+    prev_it = it;
+    chunk = next;
+  }
+  // output: x = interior solution + Dirichlet rows, canonical pressure
+  launch_copy(g.N, kx, ldw, x, ld, batch, st);
+  launch_copy_boundary(g, b, x, ld, batch, st);
+  if (o.canonicalize) {
+    launch_pressure_sums(g, x, ld, batch, red_partials, red_tickets, red_result, st);
+    launch_pressure_shift(g, x, ld, batch, red_result, st);
+  }
+  std::vector<double> true_rel(batch, -1.0);
+  if (o.true_residual) {
+    launch_apply_stokes(g, d.nu, x, ky, ldw, batch, no_gate(), nullptr, st);
+    // ky <- kb - K x (boundary rows zero); reuse kv[1] for the residual
+    launch_residual_init(g, kb, ky, kv[1], ldw, batch, st);
+    RedCtx r1 = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
+    launch_dot(g.N, kv[1], kv[1], ldw, batch, r1, no_gate(), st);
+    ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    std::vector<double> rr(h_red, h_red + batch);
+    launch_dot(g.N, kb, kb, ldw, batch, r1, no_gate(), st);
+    ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < batch; ++r)
+      true_rel[r] = h_red[r] > 0 ? std::sqrt(rr[r] / h_red[r]) : 0.0;
+  }
+  ETH_HIP(hipStreamSynchronize(st));
+  int worst = ETH_OK;
+  for (int r = 0; r < batch; ++r) {
+    const MinresScalars& s = h_ms[r];
+    int status = s.status;
+    if (status == kStOK && s.active) status = ETH_WMAXIT;
+    if (info) {
+      info[r].status = status;
+      info[r].iterations = s.iters;
+      info[r].stage1_iterations = 0;
+      info[r].rel_residual_est = s.rel;
+      info[r].rel_residual_true = true_rel[r];
+    }
+    if (status < 0) worst = std::min(worst, status);
+    else if (worst >= 0) worst = std::max(worst, status);
+  }
+  return worst;
+}
+
+}  // namespace eth
+
+// =============================================================================
+// C ABI
+// =============================================================================
+struct eth_problem {
+  eth::Problem impl;
+};
+
+using eth::Problem;
+
+static int fail(eth_problem* p, int code, const std::string& msg) {
+  if (p) p->impl.err = msg;
+  else eth::g_setup_error = msg;
+  return code;
+}
+
+template <typename F>
+static int guarded(eth_problem* p, F&& f) {
+  try {
+    return f();
+  } catch (const eth::HipError& e) {
+    return fail(p, ETH_EDEVICE, e.where + ": " + hipGetErrorString(e.err));
+  } catch (const std::bad_alloc&) {
+    return fail(p, ETH_ENOMEM, "device allocation failed");
+  } catch (const std::invalid_argument& e) {
+    return fail(p, ETH_EINVAL, e.what());
+  } catch (const std::runtime_error& e) {
+    const std::string m = e.what();
+    if (m.rfind("unsupported:", 0) == 0) return fail(p, ETH_EUNSUPPORTED, m.substr(12));
+    return fail(p, ETH_EDEVICE, m);
+  }
+}
+
+static bool check_batch(eth_problem* p, int64_t batch, int64_t ld) {
+  if (batch < 1 || batch > p->impl.max_batch) return false;
+  if (batch > 1 && ld < p->impl.g.N) return false;
+  return true;
+}
+
+extern "C" {
+
+int eth_setup(const eth_problem_desc* desc, eth_problem** out) {
+  if (!out) return fail(nullptr, ETH_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(nullptr, ETH_EINVAL, "desc is NULL");
+  eth_problem* p = new (std::nothrow) eth_problem();
+  if (!p) return fail(nullptr, ETH_ENOMEM, "host allocation failed");
+  int rc;
+  try {
+    p->impl.setup(*desc);
+    rc = ETH_OK;
+  } catch (const eth::HipError& e) {
+    rc = fail(nullptr, ETH_EDEVICE, e.where + ": " + hipGetErrorString(e.err));
+  } catch (const std::bad_alloc&) {
+    rc = fail(nullptr, ETH_ENOMEM, "device allocation failed");
+  } catch (const std::invalid_argument& e) {
+    rc = fail(nullptr, ETH_EINVAL, e.what());
+  } catch (const std::runtime_error& e) {
+    const std::string m = e.what();
+    rc = (m.rfind("unsupported:", 0) == 0) ? fail(nullptr, ETH_EUNSUPPORTED, m.substr(12))
+                                           : fail(nullptr, ETH_EDEVICE, m);
+  }
+  if (rc != ETH_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return ETH_OK;
+}
+
+int eth_destroy(eth_problem* p) {
+  if (!p) return ETH_EINVAL;
+  (void)hipStreamSynchronize(p->impl.st);
+  delete p;
+  return ETH_OK;
+}
+
+int64_t eth_vector_length(const eth_problem* p) { return p ? p->impl.g.N : -1; }
+
+int eth_get_levels(const eth_problem* p, int32_t* levels, double* lambdas) {
+  if (!p) return ETH_EINVAL;
+  if (levels) *levels = (int32_t)p->impl.lv.size();
+  if (lambdas)
+    for (size_t i = 0; i < p->impl.lam.size(); ++i) lambdas[i] = p->impl.lam[i];
+  return ETH_OK;
+}
+
+int eth_assemble_rhs(eth_problem* p, const double* f_nodal, int64_t ld_f, double* b,
+                     int64_t batch, int64_t ld) {
+  if (!p || !b) return fail(p, ETH_EINVAL, "NULL handle or b");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  if (f_nodal && batch > 1 && ld_f < 2LL * p->impl.g.nv) return fail(p, ETH_EINVAL, "ld_f too small");
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    eth::launch_lift_rhs(P.g, P.d.nu, P.d.wind, P.ub, f_nodal, ld_f, b, ld, (int)batch, P.st);
+    return ETH_OK;
+  });
+}
+
+int eth_apply_operator(eth_problem* p, int transpose, const double* x, double* y, int64_t batch,
+                       int64_t ld) {
+  if (!p || !x || !y) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  if (x == y) return fail(p, ETH_EINVAL, "x and y must not alias");
+  (void)transpose;   // the Stokes operator is symmetric
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    eth::launch_apply_stokes(P.g, P.d.nu, x, y, ld, (int)batch, eth::no_gate(), nullptr, P.st);
+    return ETH_OK;
+  });
+}
+
+int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, double* z,
+                             int64_t batch, int64_t ld) {
+  if (!p || !r || !z) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  if (r == z) return fail(p, ETH_EINVAL, "r and z must not alias");
+  (void)transpose;   // the Stokes preconditioner is symmetric
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    P.precond(r, z, ld, (int)batch, eth::no_gate());
+    return ETH_OK;
+  });
+}
+
+int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, double* x,
+              int64_t batch, int64_t ld, eth_solve_info* info) {
+  if (!p || !b || !x) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  if (b == x) return fail(p, ETH_EINVAL, "b and x must not alias");
+  eth_solve_opts o{};
+  if (opts) o = *opts;
+  else o.canonicalize = 1;
+  if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
+  if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
+  return guarded(p, [&] { return p->impl.solve_minres(o, b, x, (int)batch, ld, info); });
+}
+
+const char* eth_status_string(int status) {
+  switch (status) {
+    case ETH_OK: return "ok";
+    case ETH_EINVAL: return "invalid argument";
+    case ETH_EDEVICE: return "HIP runtime error";
+    case ETH_ENOMEM: return "out of device memory";
+    case ETH_EINCONSISTENT: return "inconsistent right-hand side";
+    case ETH_EBREAKDOWN: return "Krylov breakdown";
+    case ETH_EUNSUPPORTED: return "unsupported option";
+    case ETH_WMAXIT: return "iteration limit reached";
+    default: return "unknown status";
+  }
+}
+
+const char* eth_last_error(const eth_problem* p) {
+  return p ? p->impl.err.c_str() : eth::g_setup_error.c_str();
+}
+
+}  // extern "C"

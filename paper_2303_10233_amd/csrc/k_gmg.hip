@@ -1,0 +1,491 @@
+// Geometric multigrid for the scalar Q2 Laplacian (velocity block of the
+// Stokes preconditioner, eq:stokes_pre), templated on the storage type
+// (double, or float in mixed precision).  Planes hold all (2n+1)^2 nodes of
+// one velocity component with zero boundary values.
+//
+// Uniform-grid facts used here (derived from the 1-D Q2 element matrices):
+//  * A = K (x) M + M (x) K with integer 1-D rows over 90 (h-free), so the
+//    same stencil serves every level;
+//  * diag(A) = 224/90 (vertex,vertex), 352/90 (vertex,mid), 512/90 (mid,mid);
+//  * the 1-D Q2 prolongation injects coarse nodes and gives the new fine
+//    nodes at 1/4 and 3/4 of a coarse element the weights (3/8, 3/4, -1/8)
+//    and (-1/8, 3/4, 3/8) of the coarse (left, mid, right) nodes; restriction
+//    is its transpose, P^T rows (1/8)[-1,0,3,8,3,0,-1] at a coarse vertex and
+//    (1/8)[6,8,6] at a coarse mid node.
+#include "eth_kernels.h"
+
+namespace eth {
+namespace {
+
+constexpr int NX = 64, NY = 16, NT = 256;   // smoother tile (nodes), 4 nodes per thread
+constexpr int HX = NX + 4, HY = NY + 4;
+
+__device__ __forceinline__ void k1row(int p, double* k) {
+  if (p == 0) { k[0] = 1; k[1] = -8; k[2] = 14; k[3] = -8; k[4] = 1; }
+  else        { k[0] = 0; k[1] = -8; k[2] = 16; k[3] = -8; k[4] = 0; }
+}
+__device__ __forceinline__ void m1row(int p, double* m) {
+  if (p == 0) { m[0] = -1; m[1] = 2; m[2] = 8; m[3] = 2; m[4] = -1; }
+  else        { m[0] = 0; m[1] = 2; m[2] = 16; m[3] = 2; m[4] = 0; }
+}
+__device__ __forceinline__ double diag90(int pi, int pj) {
+  return (pi + pj == 0) ? 224.0 : (pi + pj == 1) ? 352.0 : 512.0;
+}
+
+// 90 * (A u)(node) from a staged patch s (row pitch P), centre at (lx, ly)
+template <typename T, int P>
+__device__ __forceinline__ double lap90(const T* s, int lx, int ly, int pi, int pj) {
+  double kx[5], mx[5], ky[5], my[5];
+  k1row(pi, kx); m1row(pi, mx); k1row(pj, ky); m1row(pj, my);
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    double tk = 0.0, tm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      const double u = (double)s[(ly + b - 2) * P + (lx + a - 2)];
+      tk += kx[a] * u;
+      tm += mx[a] * u;
+    }
+    acc += my[b] * tk + ky[b] * tm;
+  }
+  return acc;
+}
+
+// One Chebyshev step  x_new = x + alpha (x - x_prev) + beta D^{-1} (b - A x)
+// on every plane; x_new overwrites x_prev (xo).  With out64 the result is
+// instead written (times out_scale) to the velocity part of FP64 vectors.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b,
+                                                  const T* __restrict__ x, T* __restrict__ xo,
+                                                  double alpha, double beta, int has_prev,
+                                                  double* __restrict__ out64, long long ld64,
+                                                  double out_scale, Gate gate) {
+  __shared__ T s[HY * HX];
+  const int plane = blockIdx.z;
+  if (gate.off(plane >> 1)) return;
+  const int nq = g.nq, top = nq - 1;
+  const long long po = (long long)plane * g.nv;
+  const int I0 = blockIdx.x * NX, J0 = blockIdx.y * NY;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < HX * HY; k += NT) {
+    const int lx = k % HX, ly = k / HX;
+    const int I = I0 + lx - 2, J = J0 + ly - 2;
+    s[k] = (I >= 0 && I <= top && J >= 0 && J <= top) ? x[po + (long long)J * nq + I] : T(0);
+  }
+  __syncthreads();
+  const int tx = tid & 63, ty = tid >> 6;
+  const int I = I0 + tx;
+  if (I > top) return;
+  const int pi = I & 1;
+#pragma unroll
+  for (int r = 0; r < NY / 4; ++r) {
+    const int J = J0 + ty + 4 * r;
+    if (J > top) break;
+    const long long o = po + (long long)J * nq + I;
+    double xn = 0.0;
+    if (I > 0 && J > 0 && I < top && J < top) {
+      const int pj = J & 1;
+      const int lx = tx + 2, ly = ty + 4 * r + 2;
+      const double xc = (double)s[ly * HX + lx];
+      const double res = (double)b[o] - lap90<T, HX>(s, lx, ly, pi, pj) / 90.0;
+      xn = xc + beta * res * (90.0 / diag90(pi, pj));
+      if (has_prev == 1) xn += alpha * (xc - (double)xo[o]);
+      else if (has_prev == 2) xn += alpha * xc;
+    }
+    if (out64) {
+      out64[(long long)(plane >> 1) * ld64 + (long long)(plane & 1) * g.nv +
+            (long long)J * nq + I] = out_scale * xn;
+    } else {
+      xo[o] = (T)xn;
+    }
+  }
+}
+
+// b = r_u (velocity part of an FP64 vector), x = beta D^{-1} b
+template <typename T>
+__global__ void k_vcycle_entry(Geo g, const double* __restrict__ r, long long ld,
+                               T* __restrict__ b, T* __restrict__ x, double beta, Gate gate) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (gate.off(rhs)) return;
+  if (k >= 2LL * g.nv) return;
+  const int node = (int)(k % g.nv);
+  const int I = node % g.nq, J = node / g.nq, top = g.nq - 1;
+  const long long o = (long long)rhs * 2 * g.nv + k;
+  if (I == 0 || J == 0 || I == top || J == top) {
+    b[o] = T(0);
+    x[o] = T(0);
+    return;
+  }
+  const T bv = (T)r[(long long)rhs * ld + k];
+  b[o] = bv;
+  x[o] = (T)(beta * (double)bv * 90.0 / diag90(I & 1, J & 1));
+}
+
+// 1-D restriction weight (times 8) of fine offset o in -3..3 for a coarse
+// node of parity p (0 vertex, 1 mid)
+__device__ __forceinline__ double rw8(int p, int o) {
+  if (p == 0) return o == 0 ? 8.0 : (o == 1 || o == -1) ? 3.0 : (o == 3 || o == -3) ? -1.0 : 0.0;
+  return o == 0 ? 8.0 : (o == 1 || o == -1) ? 6.0 : 0.0;
+}
+
+constexpr int CT = 16;                  // coarse tile side
+constexpr int RF = 2 * CT + 5;          // fine residual patch side
+constexpr int XF = RF + 4;              // fine iterate patch side
+
+// Coarse rhs b_c = P^T (b_f - A_f x_f); x_c = beta_c D_c^{-1} b_c
+template <typename T>
+__global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __restrict__ bf,
+                                                 const T* __restrict__ xf, T* __restrict__ bc,
+                                                 T* __restrict__ xc, double beta_c, Gate gate) {
+  __shared__ T sx[XF * XF];
+  __shared__ double sr[RF * RF];
+  const int plane = blockIdx.z;
+  if (gate.off(plane >> 1)) return;
+  const int nqf = gf.nq, topf = nqf - 1, nqc = gc.nq, topc = nqc - 1;
+  const long long pf = (long long)plane * gf.nv, pc = (long long)plane * gc.nv;
+  const int C0x = blockIdx.x * CT, C0y = blockIdx.y * CT;
+  const int F0x = 2 * C0x - 3, F0y = 2 * C0y - 3;     // residual patch origin
+  const int tid = threadIdx.x;
+  for (int k = tid; k < XF * XF; k += NT) {
+    const int lx = k % XF, ly = k / XF;
+    const int I = F0x - 2 + lx, J = F0y - 2 + ly;
+    sx[k] = (I >= 0 && I <= topf && J >= 0 && J <= topf) ? xf[pf + (long long)J * nqf + I] : T(0);
+  }
+  __syncthreads();
+  for (int k = tid; k < RF * RF; k += NT) {
+    const int lx = k % RF, ly = k / RF;
+    const int I = F0x + lx, J = F0y + ly;
+    double r = 0.0;
+    if (I > 0 && I < topf && J > 0 && J < topf)
+      r = (double)bf[pf + (long long)J * nqf + I] -
+          lap90<T, XF>(sx, lx + 2, ly + 2, I & 1, J & 1) / 90.0;
+    sr[k] = r;
+  }
+  __syncthreads();
+  for (int k = tid; k < CT * CT; k += NT) {
+    const int cx = k % CT, cy = k / CT;
+    const int Ic = C0x + cx, Jc = C0y + cy;
+    if (Ic > topc || Jc > topc) continue;
+    const long long o = pc + (long long)Jc * nqc + Ic;
+    if (Ic == 0 || Jc == 0 || Ic == topc || Jc == topc) {
+      bc[o] = T(0);
+      xc[o] = T(0);
+      continue;
+    }
+    const int pi = Ic & 1, pj = Jc & 1;
+    const int lx = 2 * cx + 3, ly = 2 * cy + 3;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = -3; q <= 3; ++q) {
+      const double wy = rw8(pj, q);
+      if (wy == 0.0) continue;
+      double t = 0.0;
+#pragma unroll
+      for (int o2 = -3; o2 <= 3; ++o2) t += rw8(pi, o2) * sr[(ly + q) * RF + lx + o2];
+      acc += wy * t;
+    }
+    acc *= (1.0 / 64.0);
+    bc[o] = (T)acc;
+    xc[o] = (T)(beta_c * acc * 90.0 / diag90(pi, pj));
+  }
+}
+
+// x_f += P x_c on interior fine nodes
+template <typename T>
+__global__ void k_prolong_add(Geo gf, Geo gc, const T* __restrict__ xc, T* __restrict__ xf,
+                              Gate gate) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  const int plane = blockIdx.z;
+  if (gate.off(plane >> 1)) return;
+  const int topf = gf.nq - 1;
+  if (I <= 0 || J <= 0 || I >= topf || J >= topf) return;
+  int ix[3], iy[3];
+  double wx[3], wy[3];
+  int cntx, cnty;
+  auto weights = [](int F, int* idx, double* w, int& cnt) {
+    if ((F & 1) == 0) {
+      idx[0] = F >> 1; w[0] = 1.0; cnt = 1;
+      return;
+    }
+    const int k = (F - 1) >> 1;
+    cnt = 3;
+    if ((k & 1) == 0) {
+      idx[0] = k; idx[1] = k + 1; idx[2] = k + 2;
+      w[0] = 0.375; w[1] = 0.75; w[2] = -0.125;
+    } else {
+      idx[0] = k - 1; idx[1] = k; idx[2] = k + 1;
+      w[0] = -0.125; w[1] = 0.75; w[2] = 0.375;
+    }
+  };
+  weights(I, ix, wx, cntx);
+  weights(J, iy, wy, cnty);
+  const long long pc = (long long)plane * gc.nv;
+  double acc = 0.0;
+  for (int b = 0; b < cnty; ++b) {
+    double t = 0.0;
+    for (int a = 0; a < cntx; ++a) t += wx[a] * (double)xc[pc + (long long)iy[b] * gc.nq + ix[a]];
+    acc += wy[b] * t;
+  }
+  const long long o = (long long)plane * gf.nv + (long long)J * gf.nq + I;
+  xf[o] = (T)((double)xf[o] + acc);
+}
+
+// Dense solve x = Ainv b on the ni interior nodes of the two planes of one
+// RHS.  Input from T planes or (in64) from an FP64 vector; output to T planes
+// or (out64, times out_scale) to an FP64 vector.
+constexpr int DS_ROWS = 16;    // rows per block (4 waves x 4 rows)
+// The gathered right-hand sides (2 ni values) are staged in LDS when they fit
+// (ni <= DS_LDS_MAX); otherwise every row reads them from global memory.
+constexpr int DS_LDS_MAX = 3969;
+template <typename T, bool STAGE>
+__global__ __launch_bounds__(NT) void k_dense_solve(Geo g, const double* __restrict__ Ainv, int ni,
+                                                    const T* __restrict__ b, T* __restrict__ x,
+                                                    double* __restrict__ out64, long long ld64,
+                                                    double out_scale,
+                                                    const double* __restrict__ in64, long long ldin,
+                                                    Gate gate) {
+  extern __shared__ double sb[];   // 2 * ni when STAGE
+  const int rhs = blockIdx.y;
+  if (gate.off(rhs)) return;
+  const int nq = g.nq, m = nq - 2;   // interior nodes per side
+  auto load = [&](int k) -> double {
+    const int comp = k / ni, i = k % ni;
+    const int I = 1 + i % m, J = 1 + i / m;
+    const long long node = (long long)J * nq + I;
+    return in64 ? in64[(long long)rhs * ldin + (long long)comp * g.nv + node]
+                : (double)b[((long long)rhs * 2 + comp) * g.nv + node];
+  };
+  if constexpr (STAGE) {
+    for (int k = threadIdx.x; k < 2 * ni; k += NT) sb[k] = load(k);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int rr = 0; rr < DS_ROWS / 4; ++rr) {
+    const int row = blockIdx.x * DS_ROWS + wid * (DS_ROWS / 4) + rr;
+    if (row >= ni) break;
+    const double* a = Ainv + (long long)row * ni;
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = lane; j < ni; j += 64) {
+      const double av = a[j];
+      if constexpr (STAGE) {
+        s0 += av * sb[j];
+        s1 += av * sb[ni + j];
+      } else {
+        s0 += av * load(j);
+        s1 += av * load(ni + j);
+      }
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) {
+      const int I = 1 + row % m, J = 1 + row / m;
+      const long long node = (long long)J * nq + I;
+      if (out64) {
+        out64[(long long)rhs * ld64 + node] = out_scale * s0;
+        out64[(long long)rhs * ld64 + g.nv + node] = out_scale * s1;
+      } else {
+        x[((long long)rhs * 2) * g.nv + node] = (T)s0;
+        x[((long long)rhs * 2 + 1) * g.nv + node] = (T)s1;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_zero_plane_boundary(Geo g, T* __restrict__ x, Gate gate) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int plane = blockIdx.y;
+  if (gate.off(plane >> 1)) return;
+  const int nq = g.nq, m = nq - 1, nb = 4 * m;
+  if (k >= nb) return;
+  int node;
+  if (k < m) node = k;
+  else if (k < 2 * m) node = (k - m) * nq + m;
+  else if (k < 3 * m) node = m * nq + (m - (k - 2 * m));
+  else node = (m - (k - 3 * m)) * nq;
+  x[(long long)plane * g.nv + node] = T(0);
+}
+
+// ---- setup helpers (FP64) ----
+__global__ void k_dense_laplacian(Geo g, double* __restrict__ A, int ni) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)ni * ni) return;
+  const int i = (int)(k / ni), j = (int)(k % ni);
+  const int m = g.nq - 2;
+  const int Ii = 1 + i % m, Ji = 1 + i / m, Ij = 1 + j % m, Jj = 1 + j / m;
+  const int dx = Ij - Ii, dy = Jj - Ji;
+  double v = 0.0;
+  if (dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2) {
+    double kx[5], mx[5], ky[5], my[5];
+    k1row(Ii & 1, kx); m1row(Ii & 1, mx); k1row(Ji & 1, ky); m1row(Ji & 1, my);
+    v = (kx[dx + 2] * my[dy + 2] + mx[dx + 2] * ky[dy + 2]) / 90.0;
+  }
+  A[(long long)i * 2 * ni + j] = v;             // augmented [A | I]
+  A[(long long)i * 2 * ni + ni + j] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void k_gj_pivot(double* __restrict__ aug, int ni, int k, double* __restrict__ col,
+                           double* __restrict__ row) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const double piv = aug[(long long)k * 2 * ni + k];
+  if (t < ni) col[t] = aug[(long long)t * 2 * ni + k];
+  if (t < 2 * ni) row[t] = aug[(long long)k * 2 * ni + t] / piv;
+}
+
+__global__ void k_gj_update(double* __restrict__ aug, int ni, int k, const double* __restrict__ col,
+                            const double* __restrict__ row) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)ni * 2 * ni) return;
+  const int i = (int)(t / (2 * ni)), j = (int)(t % (2 * ni));
+  if (i == k) aug[t] = row[j];
+  else aug[t] -= col[i] * row[j];
+}
+
+__global__ void k_extract_inverse(const double* __restrict__ aug, int ni, double* __restrict__ Ainv) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)ni * ni) return;
+  const int i = (int)(t / ni), j = (int)(t % ni);
+  // symmetrise: the inverse of the symmetric Laplacian is symmetric
+  Ainv[t] = 0.5 * (aug[(long long)i * 2 * ni + ni + j] + aug[(long long)j * 2 * ni + ni + i]);
+}
+
+// mode 0: y = A x, mode 1: y = D^{-1} x, on one FP64 plane (interior nodes; boundary 0)
+__global__ void k_plane_op(Geo g, int mode, const double* __restrict__ x, double* __restrict__ y) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  const int top = g.nq - 1;
+  if (I > top || J > top) return;
+  double v = 0.0;
+  if (I > 0 && J > 0 && I < top && J < top) {
+    if (mode == 1) {
+      v = x[(long long)J * g.nq + I] * 90.0 / diag90(I & 1, J & 1);
+    } else {
+      double kx[5], mx[5], ky[5], my[5];
+      k1row(I & 1, kx); m1row(I & 1, mx); k1row(J & 1, ky); m1row(J & 1, my);
+      double acc = 0.0;
+      for (int b = 0; b < 5; ++b)
+        for (int a = 0; a < 5; ++a) {
+          const int Ia = I + a - 2, Jb = J + b - 2;
+          if (Ia < 1 || Jb < 1 || Ia >= top || Jb >= top) continue;
+          acc += (kx[a] * my[b] + mx[a] * ky[b]) * x[(long long)Jb * g.nq + Ia];
+        }
+      v = acc / 90.0;
+    }
+  }
+  y[(long long)J * g.nq + I] = v;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_cheb_step(const Geo& g, const T* b, const T* x, T* xo, double alpha, double beta,
+                      int has_prev, int nplanes, double* out64, long long ld64,
+                      double out_scale, Gate gate, int batch, hipStream_t st) {
+  (void)batch;
+  dim3 grid((g.nq + NX - 1) / NX, (g.nq + NY - 1) / NY, nplanes);
+  hipLaunchKernelGGL(k_cheb_step<T>, grid, dim3(NT), 0, st, g, b, x, xo, alpha, beta, has_prev,
+                     out64, ld64, out_scale, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_vcycle_entry(const Geo& g, const double* r, long long ld, T* b, T* x, double beta,
+                         int batch, Gate gate, hipStream_t st) {
+  const long long n = 2LL * g.nv;
+  hipLaunchKernelGGL(k_vcycle_entry<T>, dim3((unsigned)((n + 255) / 256), batch), dim3(256), 0, st,
+                     g, r, ld, b, x, beta, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* bc, T* xc,
+                     double beta_c, int nplanes, int batch, Gate gate, hipStream_t st) {
+  (void)batch;
+  dim3 grid((gc.nq + CT - 1) / CT, (gc.nq + CT - 1) / CT, nplanes);
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int nplanes, int batch,
+                        Gate gate, hipStream_t st) {
+  (void)batch;
+  dim3 block(64, 4);
+  dim3 grid((gf.nq + 63) / 64, (gf.nq + 3) / 4, nplanes);
+  hipLaunchKernelGGL(k_prolong_add<T>, grid, block, 0, st, gf, gc, xc, xf, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_dense_solve(const Geo& g, const double* Ainv, int ni, const T* b, T* x, int nplanes,
+                        double* out64, long long ld64, double out_scale, const double* in64,
+                        long long ldin, double* gbuf, int batch, Gate gate, hipStream_t st) {
+  (void)nplanes;
+  (void)gbuf;
+  dim3 grid((ni + DS_ROWS - 1) / DS_ROWS, batch);
+  if (ni <= DS_LDS_MAX) {
+    hipLaunchKernelGGL((k_dense_solve<T, true>), grid, dim3(NT), sizeof(double) * 2 * ni, st, g,
+                       Ainv, ni, b, x, out64, ld64, out_scale, in64, ldin, gate);
+  } else {
+    hipLaunchKernelGGL((k_dense_solve<T, false>), grid, dim3(NT), 0, st, g, Ainv, ni, b, x, out64,
+                       ld64, out_scale, in64, ldin, gate);
+  }
+  ETH_LAUNCH_CHECK();
+  if (!out64) {
+    const int nb = 4 * (g.nq - 1);
+    hipLaunchKernelGGL(k_zero_plane_boundary<T>, dim3((nb + 255) / 256, 2 * batch), dim3(256), 0, st,
+                       g, x, gate);
+    ETH_LAUNCH_CHECK();
+  }
+}
+
+void launch_dense_laplacian(const Geo& g, double* A, int ni, hipStream_t st) {
+  const long long n = (long long)ni * ni;
+  hipLaunchKernelGGL(k_dense_laplacian, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, A, ni);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_gj_step(double* aug, int ni, int k, double* colbuf, double* rowbuf, hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3((2 * ni + 255) / 256), dim3(256), 0, st, aug, ni, k, colbuf,
+                     rowbuf);
+  ETH_LAUNCH_CHECK();
+  const long long n = (long long)ni * 2 * ni;
+  hipLaunchKernelGGL(k_gj_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, aug, ni, k,
+                     colbuf, rowbuf);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_extract_inverse(const double* aug, int ni, double* Ainv, hipStream_t st) {
+  const long long n = (long long)ni * ni;
+  hipLaunchKernelGGL(k_extract_inverse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, aug, ni,
+                     Ainv);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStream_t st) {
+  dim3 block(64, 4);
+  dim3 grid((g.nq + 63) / 64, (g.nq + 3) / 4);
+  hipLaunchKernelGGL(k_plane_op, grid, block, 0, st, g, mode, x, y);
+  ETH_LAUNCH_CHECK();
+}
+
+#define ETH_INST(T)                                                                             \
+  template void launch_cheb_step<T>(const Geo&, const T*, const T*, T*, double, double, int, int, \
+                                    double*, long long, double, Gate, int, hipStream_t);         \
+  template void launch_vcycle_entry<T>(const Geo&, const double*, long long, T*, T*, double, int, \
+                                       Gate, hipStream_t);                                       \
+  template void launch_restrict<T>(const Geo&, const Geo&, const T*, const T*, T*, T*, double,    \
+                                   int, int, Gate, hipStream_t);                                 \
+  template void launch_prolong_add<T>(const Geo&, const Geo&, const T*, T*, int, int, Gate,       \
+                                      hipStream_t);                                              \
+  template void launch_dense_solve<T>(const Geo&, const double*, int, const T*, T*, int, double*, \
+                                      long long, double, const double*, long long, double*, int,  \
+                                      Gate, hipStream_t);
+ETH_INST(double)
+ETH_INST(float)
+#undef ETH_INST
+
+}  // namespace eth

@@ -1,0 +1,252 @@
+// Krylov vector kernels: fused MINRES updates (alg:minres), deterministic dot
+// products and the pressure canonicalisation.  FP64 throughout.
+#include "eth_kernels.h"
+#include "eth_reduce.h"
+
+namespace eth {
+namespace {
+
+constexpr int NT = 256;
+constexpr int kVecBlocksMax = 1024;   // grid-stride cap per RHS for reductions
+
+__global__ __launch_bounds__(NT) void k_dot(long long n, const double* __restrict__ x,
+                                            const double* __restrict__ y, long long ld,
+                                            RedCtx rc, Gate gate) {
+  __shared__ double sred[NT / 64];
+  const int rhs = blockIdx.y;
+  if (gate.off(rhs)) return;
+  const double* xr = x + (long long)rhs * ld;
+  const double* yr = y + (long long)rhs * ld;
+  double a = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+    a += xr[i] * yr[i];
+  double v[1] = {a};
+  reduce_and_finish<NT>(rc, rhs, blockIdx.x, v, sred);
+}
+
+__global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b,
+                        double* __restrict__ y, long long ld) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long o = (long long)blockIdx.y * ld + i;
+  y[o] = a * x[o] + b * y[o];
+}
+
+__global__ void k_copy(long long n, const double* __restrict__ x, long long ldx,
+                       double* __restrict__ y, long long ldy) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[(long long)blockIdx.y * ldy + i] = x[(long long)blockIdx.y * ldx + i];
+}
+
+__global__ void k_fill(long long n, double v, double* __restrict__ y, long long ld) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[(long long)blockIdx.y * ld + i] = v;
+}
+
+// boundary node k (0 .. 4*(nq-1)-1) of one component -> node index
+__device__ inline int boundary_node(int k, int nq) {
+  const int m = nq - 1;
+  if (k < m) return k;                              // bottom, I = 0..m-1
+  if (k < 2 * m) return (k - m) * nq + m;           // right,  J = 0..m-1
+  if (k < 3 * m) return m * nq + (m - (k - 2 * m)); // top,    I = m..1
+  return (m - (k - 3 * m)) * nq;                    // left,   J = m..1
+}
+
+__global__ void k_zero_boundary(Geo g, double* __restrict__ y, long long ld) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = 4 * (g.nq - 1);
+  if (k >= 2 * nb) return;
+  const int comp = k / nb;
+  y[(long long)blockIdx.y * ld + (long long)comp * g.nv + boundary_node(k % nb, g.nq)] = 0.0;
+}
+
+__global__ void k_copy_boundary(Geo g, const double* __restrict__ b, double* __restrict__ x,
+                                long long ld) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = 4 * (g.nq - 1);
+  if (k >= 2 * nb) return;
+  const int comp = k / nb;
+  const long long o = (long long)blockIdx.y * ld + (long long)comp * g.nv + boundary_node(k % nb, g.nq);
+  x[o] = b[o];
+}
+
+// v = b - y on interior rows, 0 on boundary velocity rows
+__global__ void k_residual_init(Geo g, const double* __restrict__ b, const double* __restrict__ y,
+                                double* __restrict__ v, long long ld) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const long long o = (long long)blockIdx.y * ld + i;
+  bool bnd = false;
+  if (i < 2LL * g.nv) {
+    const int node = (int)(i % g.nv);
+    const int I = node % g.nq, J = node / g.nq;
+    bnd = (I == 0 || J == 0 || I == g.nq - 1 || J == g.nq - 1);
+  }
+  v[o] = bnd ? 0.0 : b[o] - y[o];
+}
+
+// v_{j+1} = vy*y - va*v_j - vb*v_{j-1}   (written over v_{j-1})
+__global__ void k_minres_v(long long n, const double* __restrict__ y, const double* __restrict__ v,
+                           double* __restrict__ vp, long long ld, const MinresScalars* __restrict__ s) {
+  const int rhs = blockIdx.y;
+  const MinresScalars& S = s[rhs];
+  if (!S.active) return;
+  const double vy = S.vy, va = S.va, vb = S.vb;
+  const long long o = (long long)rhs * ld;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    vp[o + i] = vy * y[o + i] - va * v[o + i] - vb * vp[o + i];
+}
+
+// w_{j+1} = wz*zhat_j - wp*w_{j-1} - wc*w_j (written over w_{j-1}); x += xc*w_{j+1}
+__global__ void k_minres_wx(long long n, const double* __restrict__ z, double* __restrict__ wp,
+                            const double* __restrict__ w, double* __restrict__ x, long long ld,
+                            MinresScalars* __restrict__ s, unsigned* __restrict__ tickets) {
+  const int rhs = blockIdx.y;
+  MinresScalars& S = s[rhs];
+  if (!S.wx_todo) return;
+  const double cz = S.wz, cp = S.wp, cw = S.wc, cx = S.xc;
+  const long long o = (long long)rhs * ld;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double wn = cz * z[o + i] - cp * wp[o + i] - cw * w[o + i];
+    wp[o + i] = wn;
+    x[o + i] += cx * wn;
+  }
+  // the last block to finish marks the update as consumed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = atomicAdd(&tickets[rhs], 1u);
+    if (t == gridDim.x - 1) {
+      tickets[rhs] = 0u;
+      S.wx_todo = 0;
+      __threadfence();
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_pressure_sums(Geo g, const double* __restrict__ x,
+                                                      long long ld, RedCtx rc) {
+  __shared__ double sred[NT / 64];
+  const int rhs = blockIdx.y;
+  const double* xr = x + (long long)rhs * ld + g.off_pk();
+  double a = 0.0, b = 0.0;
+  const long long np = (long long)g.nk + g.n0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < np; i += (long long)gridDim.x * NT) {
+    if (i < g.nk) a += xr[i];
+    else b += xr[i];
+  }
+  double v[2] = {a, b};
+  reduce_and_finish<NT>(rc, rhs, blockIdx.x, v, sred);
+}
+
+__global__ void k_pressure_shift(Geo g, double* __restrict__ x, long long ld,
+                                 const double* __restrict__ sums) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long np = (long long)g.nk + g.n0;
+  if (i >= np) return;
+  const int rhs = blockIdx.y;
+  const double m = (i < g.nk) ? sums[2 * rhs] / g.nk : sums[2 * rhs + 1] / g.n0;
+  x[(long long)rhs * ld + g.off_pk() + i] -= m;
+}
+
+inline unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+}  // namespace
+
+int dot_blocks(long long n) {
+  long long b = (n + NT * 4 - 1) / (NT * 4);
+  if (b < 1) b = 1;
+  if (b > kVecBlocksMax) b = kVecBlocksMax;
+  return (int)b;
+}
+
+void launch_dot(long long n, const double* x, const double* y, long long ld, int batch,
+                const RedCtx& rc, Gate gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot, dim3(rc.nblocks, batch), dim3(NT), 0, st, n, x, y, ld, rc, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_axpby(long long n, double a, const double* x, double b, double* y, long long ld,
+                  int batch, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n, 256), batch), dim3(256), 0, st, n, a, x, b, y, ld);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_copy(long long n, const double* x, long long ldx, double* y, long long ldy,
+                 int batch, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, 256), batch), dim3(256), 0, st, n, x, ldx, y, ldy);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_fill(long long n, double v, double* y, long long ld, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256), batch), dim3(256), 0, st, n, v, y, ld);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_zero_boundary(const Geo& g, double* y, long long ld, int batch, hipStream_t st) {
+  const int nb = 2 * 4 * (g.nq - 1);
+  hipLaunchKernelGGL(k_zero_boundary, dim3(blocks_for(nb, 256), batch), dim3(256), 0, st, g, y, ld);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_copy_boundary(const Geo& g, const double* b, double* x, long long ld, int batch,
+                          hipStream_t st) {
+  const int nb = 2 * 4 * (g.nq - 1);
+  hipLaunchKernelGGL(k_copy_boundary, dim3(blocks_for(nb, 256), batch), dim3(256), 0, st, g, b, x, ld);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_residual_init(const Geo& g, const double* b, const double* y, double* v,
+                          long long ld, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_init, dim3(blocks_for(g.N, 256), batch), dim3(256), 0, st, g, b, y,
+                     v, ld);
+  ETH_LAUNCH_CHECK();
+}
+
+static unsigned update_blocks(long long n) {
+  long long b = (n + 256 * 4 - 1) / (256 * 4);
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  return (unsigned)b;
+}
+
+void launch_minres_v(long long n, const double* y, const double* v, double* vprev_io,
+                     long long ld, int batch, const MinresScalars* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_minres_v, dim3(update_blocks(n), batch), dim3(256), 0, st, n, y, v,
+                     vprev_io, ld, s);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_minres_wx(long long n, const double* z, double* wprev_io, const double* w,
+                      double* x, long long ld, int batch, MinresScalars* s,
+                      unsigned* tickets, hipStream_t st) {
+  hipLaunchKernelGGL(k_minres_wx, dim3(update_blocks(n), batch), dim3(256), 0, st, n, z,
+                     wprev_io, w, x, ld, s, tickets);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_pressure_sums(const Geo& g, const double* x, long long ld, int batch,
+                          double* partials, unsigned* tickets, double* out, hipStream_t st) {
+  RedCtx rc{};
+  rc.partials = partials;
+  rc.tickets = tickets;
+  rc.result = out;
+  rc.nblocks = dot_blocks((long long)g.nk + g.n0);
+  rc.nvals = 2;
+  hipLaunchKernelGGL(k_pressure_sums, dim3(rc.nblocks, batch), dim3(NT), 0, st, g, x, ld, rc);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_pressure_shift(const Geo& g, double* x, long long ld, int batch,
+                           const double* sums, hipStream_t st) {
+  const long long np = (long long)g.nk + g.n0;
+  hipLaunchKernelGGL(k_pressure_shift, dim3(blocks_for(np, 256), batch), dim3(256), 0, st, g, x,
+                     ld, sums);
+  ETH_LAUNCH_CHECK();
+}
+
+}  // namespace eth

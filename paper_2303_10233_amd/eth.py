@@ -1,0 +1,261 @@
+"""Thin Python binding of libeth (include/eth.h): argument marshalling only.
+
+Every step of the solvers runs in the HIP library; this module turns torch
+tensors (device memory, FP64) and the current torch stream into the C ABI's
+pointers, sizes and stream handle.  There is no fallback: if the library is
+missing the import of the binding raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeth.so")
+
+STOKES, OSEEN = 0, 1
+FP64, MIXED = 0, 1
+VEL_GMG, VEL_EXACT = 0, 1
+MQ_DIAG, MQ_CHEB_SGS = 1, 2
+MINRES, FGMRES, TWO_STAGE = 0, 1, 2
+OK, EINVAL, EDEVICE, ENOMEM, EINCONSISTENT, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+WMAXIT = 1
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+        ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("kind", ctypes.c_int32),
+        ("nu", ctypes.c_double),
+        ("wind", ctypes.c_void_p),
+        ("lid_u", ctypes.c_double),
+        ("corner_mode", ctypes.c_int32),
+        ("velocity_mode", ctypes.c_int32),
+        ("mq_mode", ctypes.c_int32),
+        ("mq_steps", ctypes.c_int32),
+        ("mq_cheb_lo", ctypes.c_double),
+        ("mq_cheb_hi", ctypes.c_double),
+        ("gmg_coarse_n", ctypes.c_int32),
+        ("gmg_degree", ctypes.c_int32),
+        ("gmg_lo_frac", ctypes.c_double),
+        ("gmg_hi_frac", ctypes.c_double),
+        ("gmg_lambda", ctypes.POINTER(ctypes.c_double)),
+        ("precision", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32),
+        ("rtol", ctypes.c_double),
+        ("maxit", ctypes.c_int32),
+        ("restart", ctypes.c_int32),
+        ("c_factor", ctypes.c_double),
+        ("canonicalize", ctypes.c_int32),
+        ("use_x0", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("true_residual", ctypes.c_int32),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("stage1_iterations", ctypes.c_int32),
+        ("rel_residual_est", ctypes.c_double),
+        ("rel_residual_true", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTED = [
+    "eth_setup", "eth_destroy", "eth_vector_length", "eth_get_levels", "eth_assemble_rhs",
+    "eth_apply_operator", "eth_apply_preconditioner", "eth_solve", "eth_status_string",
+    "eth_last_error",
+]
+
+
+def load_library(path=LIB_PATH):
+    """Load libeth.so and declare the C signatures.  Raises OSError when the
+    library has not been built."""
+    if not os.path.exists(path):
+        raise OSError(f"libeth.so not found at {path}: run paper_2303_10233_amd.build")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.eth_setup.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]
+    lib.eth_setup.restype = ctypes.c_int
+    lib.eth_destroy.argtypes = [P]
+    lib.eth_destroy.restype = ctypes.c_int
+    lib.eth_vector_length.argtypes = [P]
+    lib.eth_vector_length.restype = i64
+    lib.eth_get_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.eth_get_levels.restype = ctypes.c_int
+    lib.eth_assemble_rhs.argtypes = [P, P, i64, P, i64, i64]
+    lib.eth_assemble_rhs.restype = ctypes.c_int
+    lib.eth_apply_operator.argtypes = [P, ctypes.c_int, P, P, i64, i64]
+    lib.eth_apply_operator.restype = ctypes.c_int
+    lib.eth_apply_preconditioner.argtypes = [P, ctypes.c_int, P, P, i64, i64]
+    lib.eth_apply_preconditioner.restype = ctypes.c_int
+    lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
+    lib.eth_solve.restype = ctypes.c_int
+    lib.eth_status_string.argtypes = [ctypes.c_int]
+    lib.eth_status_string.restype = ctypes.c_char_p
+    lib.eth_last_error.argtypes = [P]
+    lib.eth_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+class EthError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _check(status, handle=None):
+    if status < 0:
+        L = lib()
+        msg = L.eth_last_error(handle).decode() or L.eth_status_string(status).decode()
+        raise EthError(status, msg)
+    return status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _as_batch(t, N):
+    """(N,) -> (1, N) view; (B, ld) kept.  Returns (tensor2d, batch, ld)."""
+    if t.dim() == 1:
+        t = t.view(1, -1)
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("vectors must be float64 CUDA tensors")
+    if t.stride(1) != 1 or t.shape[1] < N:
+        raise ValueError("vectors need a contiguous last dimension of length >= N")
+    return t, t.shape[0], (t.stride(0) if t.shape[0] > 1 else t.shape[1])
+
+
+class Problem:
+    """A discrete enriched Taylor-Hood Stokes problem on the GPU (see eth.h)."""
+
+    def __init__(self, n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
+                 kind=STOKES, wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0,
+                 mq_cheb=(0.0, 0.0), gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0),
+                 gmg_lambda=None, precision=FP64, max_batch=1, device=None):
+        self.device = torch.device("cuda" if device is None else device)
+        L = lib()
+        d = ProblemDesc()
+        d.n = n
+        d.x0, d.x1, d.y0, d.y1 = domain
+        d.kind = kind
+        d.nu = nu
+        self._wind = wind
+        d.wind = _ptr(wind) if wind is not None else None
+        d.lid_u = lid_u
+        d.corner_mode = corner_mode
+        d.velocity_mode = velocity
+        d.mq_mode = mq
+        d.mq_steps = mq_steps
+        d.mq_cheb_lo, d.mq_cheb_hi = mq_cheb
+        d.gmg_coarse_n = gmg_coarse_n
+        d.gmg_degree = gmg_degree
+        d.gmg_lo_frac, d.gmg_hi_frac = gmg_frac
+        self._lam = None
+        if gmg_lambda is not None:
+            self._lam = (ctypes.c_double * len(gmg_lambda))(*gmg_lambda)
+            d.gmg_lambda = self._lam
+        d.precision = precision
+        d.max_batch = max_batch
+        with torch.cuda.device(self.device):
+            d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        h = ctypes.c_void_p()
+        _check(L.eth_setup(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.nu = nu
+        self.max_batch = max_batch
+        self.N = int(L.eth_vector_length(h))
+        nq = 2 * n + 1
+        self.nv = nq * nq
+        self.nk = (n + 1) ** 2
+        self.n0 = n * n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().eth_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levels(self):
+        L = lib()
+        lv = ctypes.c_int32()
+        _check(L.eth_get_levels(self._h, ctypes.byref(lv), None), self._h)
+        lam = (ctypes.c_double * max(lv.value, 1))()
+        _check(L.eth_get_levels(self._h, None, lam), self._h)
+        return lv.value, [lam[i] for i in range(max(lv.value - 1, 0))]
+
+    def empty(self, batch=1):
+        shape = (self.N,) if batch == 1 else (batch, self.N)
+        return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    def assemble_rhs(self, f_nodal=None, batch=1):
+        b = self.empty(batch)
+        b2, B, ld = _as_batch(b, self.N)
+        ldf = 0
+        if f_nodal is not None:
+            f2 = f_nodal.view(B, -1) if f_nodal.dim() == 1 else f_nodal
+            ldf = f2.stride(0) if B > 1 else f2.shape[-1]
+        _check(lib().eth_assemble_rhs(self._h, _ptr(f_nodal), ldf, _ptr(b2), B, ld), self._h)
+        return b
+
+    def apply_operator(self, x, transpose=False):
+        y = torch.empty_like(x)
+        x2, B, ld = _as_batch(x, self.N)
+        y2, _, _ = _as_batch(y, self.N)
+        _check(lib().eth_apply_operator(self._h, int(transpose), _ptr(x2), _ptr(y2), B, ld), self._h)
+        return y
+
+    def apply_preconditioner(self, r, transpose=False):
+        z = torch.empty_like(r)
+        r2, B, ld = _as_batch(r, self.N)
+        z2, _, _ = _as_batch(z, self.N)
+        _check(lib().eth_apply_preconditioner(self._h, int(transpose), _ptr(r2), _ptr(z2), B, ld),
+               self._h)
+        return z
+
+    def solve(self, b, rtol=1e-6, maxit=1000, x0=None, method=MINRES, restart=50, c_factor=10.0,
+              canonicalize=True, use_graph=False, true_residual=False, out=None):
+        x = out if out is not None else torch.empty_like(b)
+        if x0 is not None:
+            x.copy_(x0)
+        b2, B, ld = _as_batch(b, self.N)
+        x2, _, _ = _as_batch(x, self.N)
+        o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=c_factor,
+                      canonicalize=int(canonicalize), use_x0=int(x0 is not None),
+                      use_graph=int(use_graph), true_residual=int(true_residual))
+        infos = (SolveInfo * B)()
+        st = lib().eth_solve(self._h, ctypes.byref(o), _ptr(b2), _ptr(x2), B, ld, infos)
+        _check(st, self._h)
+        return x, [infos[i].as_dict() for i in range(B)]

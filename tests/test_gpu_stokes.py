@@ -1,0 +1,234 @@
+"""GPU parity of the Stokes path through the C ABI against the CPU oracle.
+
+Inputs are seeded (paper_2303_10233_amd.workloads); expected values come from
+oracle/ only.  Tolerances: FP64 operator and preconditioner applies agree to
+rounding (1e-12 relative); FP32 (mixed) preconditioner applies to 1e-5
+relative (single-precision rounding through the multigrid levels and 20
+Chebyshev steps); FP64 solves at rtol 1e-12 to 1e-8 relative in the
+canonicalised full vector (the spec FP64 bar).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.assemble import Mesh, System, lid_dirichlet  # noqa: E402
+from oracle.direct import direct_solve, canonicalize, rel_err  # noqa: E402
+from oracle import precond as opc  # noqa: E402
+from oracle.krylov import minres  # noqa: E402
+from paper_2303_10233_amd import eth  # noqa: E402
+from paper_2303_10233_amd.workloads import gaussian_bumps, uniform_vector  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eth.load_library()
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 16, 33, 64])
+def test_apply_operator_matches_oracle(n):
+    print(f"[apply] n={n}", flush=True)
+    m = Mesh(n)
+    s = System(m, nu=0.7)
+    P = eth.Problem(n, nu=0.7, velocity=eth.VEL_EXACT if n <= 32 else eth.VEL_GMG,
+                    mq=eth.MQ_DIAG, max_batch=3)
+    xs = [uniform_vector(m.N, 100 + n + k) for k in range(3)]
+    # batch of three with a padded stride
+    ld = m.N + 17
+    X = torch.zeros((3, ld), dtype=torch.float64, device=DEV)
+    for k in range(3):
+        X[k, : m.N] = _t(xs[k])
+    Y = P.apply_operator(X)
+    Yn = _np(Y)
+    for k in range(3):
+        ref = s.apply_full(xs[k])
+        assert rel_err(Yn[k, : m.N], ref) < 1e-13
+    # single vector
+    y1 = _np(P.apply_operator(_t(xs[0])))
+    assert rel_err(y1, s.apply_full(xs[0])) < 1e-13
+
+
+def test_operator_symmetric_and_frame_null_vector():
+    n = 24
+    m = Mesh(n)
+    P = eth.Problem(n, mq=eth.MQ_DIAG)
+    x = _t(uniform_vector(m.N, 1))
+    y = _t(uniform_vector(m.N, 2))
+    Ax, Ay = P.apply_operator(x), P.apply_operator(y)
+    # boundary velocity entries are ignored: compare on the interior layout
+    s = System(m)
+    xi, yi = s.to_interior(_np(x)), s.to_interior(_np(y))
+    a = s.to_interior(_np(Ay)) @ xi
+    b = s.to_interior(_np(Ax)) @ yi
+    assert abs(a - b) <= 1e-13 * (abs(a) + abs(b))
+    k = np.zeros(m.N)
+    k[2 * m.nv: 2 * m.nv + m.nk] = 1.0
+    k[2 * m.nv + m.nk:] = -1.0
+    Ak = _np(P.apply_operator(_t(k)))
+    assert np.abs(Ak).max() < 1e-14
+
+
+@pytest.mark.parametrize("n", [4, 33])
+@pytest.mark.parametrize("corner_mode", [0, 1])
+def test_assemble_rhs_matches_oracle(n, corner_mode):
+    print(f"[rhs] n={n} corner_mode={corner_mode}", flush=True)
+    m = Mesh(n)
+    nu = 0.3
+    s = System(m, nu=nu)
+    P = eth.Problem(n, nu=nu, lid_u=1.5, corner_mode=corner_mode, mq=eth.MQ_DIAG,
+                    max_batch=2)
+    f = gaussian_bumps(n, 1000)
+    b = _np(P.assemble_rhs(_t(f)))
+    ref = s.rhs(f, lid_dirichlet(m, 1.5, corner_mode))
+    assert rel_err(b, ref) < 1e-13
+    b0 = _np(P.assemble_rhs(None))
+    assert rel_err(b0, s.rhs(None, lid_dirichlet(m, 1.5, corner_mode))) < 1e-13
+    # batched forcing
+    F = torch.stack([_t(gaussian_bumps(n, 1001)), _t(gaussian_bumps(n, 1002))])
+    B = _np(P.assemble_rhs(F, batch=2))
+    for k in range(2):
+        assert rel_err(B[k], s.rhs(gaussian_bumps(n, 1001 + k), lid_dirichlet(m, 1.5, corner_mode))) < 1e-13
+
+
+def _oracle_prec(s, velocity, mq, lambdas=None, mq_lo=0.01):
+    gmg_kw = dict(lambdas=lambdas) if lambdas is not None else None
+    return opc.StokesBlockDiag(s, velocity, mq, mq_lo=mq_lo, mq_steps=20, gmg_kw=gmg_kw)
+
+
+def _oracle_lambdas(n):
+    g = opc.GMG(Mesh(n), opc.laplacian)
+    return g.lam
+
+
+@pytest.mark.parametrize("n,velocity,mq,prec,tol", [
+    (8, "exact", "diag", eth.FP64, 1e-12),
+    (16, "exact", "diag", eth.FP64, 1e-12),
+    (16, "gmg", "cheb_sgs", eth.FP64, 1e-11),
+    (48, "gmg", "cheb_sgs", eth.FP64, 1e-11),
+    (64, "gmg", "diag", eth.FP64, 1e-11),
+    (64, "gmg", "cheb_sgs", eth.MIXED, 2e-5),
+])
+def test_preconditioner_matches_oracle(n, velocity, mq, prec, tol):
+    print(f"[precond] n={n} {velocity} {mq} prec={prec}", flush=True)
+    m = Mesh(n)
+    nu = 0.5
+    s = System(m, nu=nu)
+    lam = _oracle_lambdas(n) if velocity == "gmg" else None
+    P = eth.Problem(n, nu=nu, velocity=eth.VEL_GMG if velocity == "gmg" else eth.VEL_EXACT,
+                    mq=eth.MQ_DIAG if mq == "diag" else eth.MQ_CHEB_SGS, precision=prec,
+                    gmg_lambda=lam)
+    r = uniform_vector(m.N, 7 + n)
+    r[: 2 * m.nv][s.vel_bnd] = 0.0
+    z = _np(P.apply_preconditioner(_t(r)))
+    Pref = _oracle_prec(s, velocity, mq, lambdas=lam)
+    zref = s.to_full(Pref(s.to_interior(r)))
+    o = 2 * m.nv
+    assert rel_err(z[:o], zref[:o]) < tol
+    assert rel_err(z[o:], zref[o:]) < tol
+    assert np.abs(z[:o][s.vel_bnd]).max() == 0.0
+
+
+def test_gpu_lanczos_lambda_close_to_exact():
+    """The set-up estimate of lambda_max(D^{-1}A) (30 Lanczos steps) is a
+    lower bound within 2% of the exact value on every smoothing level."""
+    n = 64
+    P = eth.Problem(n)
+    nlev, lam = P.levels()
+    exact = _oracle_lambdas(n)
+    assert nlev == len(exact) + 1
+    for a, e in zip(lam, exact):
+        assert e * 0.98 <= a <= e * (1 + 1e-8)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_solve_config1_exact_velocity_diag_mq(use_graph):
+    """Stokes cavity 16 x 16, lid (1,0), f = 0, exact A, diagonal M_Q with the
+    bordered projection, FP64 MINRES."""
+    n = 16
+    print(f"[solve c1] graph={use_graph}", flush=True)
+    m = Mesh(n)
+    s = System(m)
+    b_ref = s.rhs(None, lid_dirichlet(m))
+    xd = direct_solve(s, b_ref)
+    P = eth.Problem(n, velocity=eth.VEL_EXACT, mq=eth.MQ_DIAG)
+    b = P.assemble_rhs()
+    x, info = P.solve(b, rtol=1e-12, maxit=3000, use_graph=use_graph, true_residual=True)
+    assert info[0]["status"] == 0
+    assert rel_err(_np(x), xd) < 1e-8
+    # iteration count equals the oracle's MINRES with the same preconditioner
+    Pref = _oracle_prec(s, "exact", "diag")
+    _, oinfo = minres(lambda v: s.K @ v, s.to_interior(b_ref), Pref, tol=1e-12, maxit=3000)
+    assert abs(info[0]["iterations"] - oinfo["iterations"]) <= 2
+    # at the configured tolerance 1e-6
+    x6, info6 = P.solve(b, rtol=1e-6, use_graph=use_graph)
+    _, oinfo6 = minres(lambda v: s.K @ v, s.to_interior(b_ref), Pref, tol=1e-6, maxit=3000)
+    assert abs(info6[0]["iterations"] - oinfo6["iterations"]) <= 1
+
+
+@pytest.mark.parametrize("prec,tol_rel", [(eth.FP64, 1e-8), (eth.MIXED, 1e-6)])
+def test_solve_gmg_cheb_sgs_matches_direct(prec, tol_rel):
+    n = 64
+    print(f"[solve gmg] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    s = System(m)
+    xd = direct_solve(s, s.rhs(None, lid_dirichlet(m)))
+    P = eth.Problem(n, precision=prec)
+    b = P.assemble_rhs()
+    # an FP32 preconditioner limits the attainable MINRES accuracy, so the
+    # mixed run stops at 1e-8 (or its iteration limit) and is held to 1e-6
+    rtol = 1e-12 if prec == eth.FP64 else 1e-8
+    x, info = P.solve(b, rtol=rtol, maxit=600, use_graph=True, true_residual=True)
+    print(f"  iterations={info[0]['iterations']} status={info[0]['status']} "
+          f"true_rel={info[0]['rel_residual_true']:.2e}", flush=True)
+    assert info[0]["status"] in (0, eth.WMAXIT), info
+    if prec == eth.FP64:
+        assert info[0]["status"] == 0
+    assert rel_err(_np(x), xd) < tol_rel
+
+
+def test_solve_batched_forcing_matches_direct():
+    n = 32
+    B = 4
+    m = Mesh(n)
+    s = System(m)
+    P = eth.Problem(n, max_batch=B, precision=eth.MIXED)
+    F = torch.stack([_t(gaussian_bumps(n, 1000 + k)) for k in range(B)])
+    b = P.assemble_rhs(F, batch=B)
+    x, infos = P.solve(b, rtol=1e-8, maxit=600, use_graph=True)
+    X = _np(x)
+    for k in range(B):
+        xd = direct_solve(s, s.rhs(gaussian_bumps(n, 1000 + k), lid_dirichlet(m)))
+        assert infos[k]["status"] in (0, eth.WMAXIT)
+        assert rel_err(X[k], xd) < 1e-6
+
+
+def test_solve_x0_warm_start_and_zero_rhs():
+    n = 16
+    m = Mesh(n)
+    s = System(m)
+    P = eth.Problem(n, velocity=eth.VEL_EXACT, mq=eth.MQ_DIAG)
+    b = P.assemble_rhs()
+    xd = direct_solve(s, s.rhs(None, lid_dirichlet(m)))
+    xl, _ = P.solve(b, rtol=1e-3, maxit=2000)
+    x2, info2 = P.solve(b, rtol=1e-11, x0=xl)
+    assert info2[0]["status"] == 0
+    assert rel_err(_np(x2), xd) < 1e-8
+    # zero right-hand side: x = 0 immediately
+    z = torch.zeros_like(b)
+    x0, i0 = P.solve(z, rtol=1e-8)
+    assert i0[0]["iterations"] == 0 and float(x0.abs().max()) == 0.0
