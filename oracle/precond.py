@@ -197,12 +197,15 @@ def q2_prolongation(fine, coarse):
 
 
 def lambda_max_dinv(A):
-    """Largest eigenvalue of D^{-1} A for symmetric positive definite A."""
+    """Largest eigenvalue of D^{-1} A for symmetric positive definite A
+    (dense for small A, else ARPACK on D^{-1/2} A D^{-1/2} from a fixed start
+    vector, to about ten significant digits)."""
     d = 1.0 / np.sqrt(A.diagonal())
     S = sp.diags(d) @ A @ sp.diags(d)
     if S.shape[0] <= 400:
         return float(np.linalg.eigvalsh(S.toarray())[-1])
-    return float(spla.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-10)[0])
+    return float(spla.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-8,
+                            ncv=40, v0=np.ones(S.shape[0]))[0])
 
 
 class GMG:
