@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the enriched Taylor-Hood Stokes solver on one MI355X.
+
+Workload (one "step" = one complete preconditioned MINRES solve of an already
+assembled, HBM-resident right-hand side to |eta|/gamma_1 <= 1e-6):
+  Stokes lid-driven cavity on the unit square, n x n Q2 elements (default
+  n = 256: 526k velocity, 66k Q1 + 65.5k P0 pressure unknowns), lid (1,0),
+  f = 0, block-diagonal preconditioner = one geometric-multigrid V(2,2)
+  Chebyshev-smoothed cycle for the velocity block + 20 Chebyshev-SGS steps for
+  the singular pressure mass matrix with the null-vector projection.
+  `value` is the mixed-precision solver (FP32 preconditioner inside FP64
+  MINRES); the FP64 solver is timed on the same input and reported beside it.
+
+Prints ONE JSON line.  --gpus N with N > 1 is refused: this build runs on one
+GPU (the method would shard by mesh blocks with halo exchanges).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MI355X_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_solves(P, b, steps, warmup, rtol, use_graph):
+    import torch
+    x = torch.empty_like(b)
+    info = None
+    for _ in range(warmup):
+        _, info = P.solve(b, rtol=rtol, maxit=2000, use_graph=use_graph, out=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(steps):
+        _, info = P.solve(b, rtol=rtol, maxit=2000, use_graph=use_graph, out=x)
+        its.append(info[0]["iterations"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, its, info
+
+
+def cpu_baseline(n, iterations_per_solve, cpu_iters):
+    """The oracle (NumPy/SciPy, FP64, as it stands) on the same workload: a
+    bounded sample of `cpu_iters` MINRES iterations with the same
+    preconditioner algorithm, scaled to one solve by the GPU's iteration
+    count."""
+    from oracle.assemble import Mesh, System, lid_dirichlet
+    from oracle.krylov import minres
+    from oracle.precond import StokesBlockDiag
+
+    t0 = time.perf_counter()
+    m = Mesh(n)
+    s = System(m)
+    b = s.to_interior(s.rhs(None, lid_dirichlet(m)))
+    P = StokesBlockDiag(s, "gmg", "cheb_sgs", mq_lo=0.01, mq_steps=20)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    minres(lambda v: s.K @ v, b, P, tol=1e-30, maxit=cpu_iters)
+    dt = time.perf_counter() - t0
+    per_iter = dt / cpu_iters
+    per_solve = per_iter * iterations_per_solve
+    return {
+        "value": 1.0 / per_solve,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{cpu_iters} MINRES iterations of the NumPy/SciPy oracle at n={n} "
+                   f"(GMG V(2,2) + 20 Chebyshev-SGS steps, FP64; {dt:.1f} s, setup "
+                   f"{t_setup:.1f} s excluded), scaled by the GPU iteration count "
+                   f"{iterations_per_solve}; single-threaded SciPy sparse kernels"),
+        "seconds_per_iteration": per_iter,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--profile-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described but not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2303_10233_amd import eth
+
+    n = args.n
+    use_graph = not args.no_graph
+    log(f"n={n} steps={args.steps} warmup={args.warmup} graph={use_graph}")
+    results = {}
+    problems = {}
+    for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+        t0 = time.perf_counter()
+        P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0")
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        b = P.assemble_rhs()
+        dt, its, info = time_solves(P, b, args.steps, args.warmup, args.rtol, use_graph)
+        _, tinfo = P.solve(b, rtol=args.rtol, maxit=2000, use_graph=use_graph, true_residual=True)
+        results[name] = dict(seconds=dt, iterations=its, setup_s=setup_s,
+                             true_residual=tinfo[0]["rel_residual_true"],
+                             status=tinfo[0]["status"])
+        problems[name] = P
+        log(f"{name}: {args.steps / dt:.2f} solves/s, {1e3 * dt / args.steps:.2f} ms/solve, "
+            f"iterations {its[-1]}, true rel. residual {tinfo[0]['rel_residual_true']:.2e}, "
+            f"setup {setup_s:.2f} s")
+
+    mixed, fp64 = results["mixed"], results["fp64"]
+    equal_residual_ok = mixed["true_residual"] <= 2.0 * fp64["true_residual"]
+
+    # --- kernel timing (HIP events on the problem's stream) -------------------
+    Pm = problems["mixed"]
+    its_m = mixed["iterations"][-1]
+    levels, _ = Pm.levels()
+    # launches of each kernel per MINRES iteration (mixed solver, finest level
+    # for the multigrid kernels): V(2,2) with degree-2 Chebyshev = 1 pre-step
+    # kernel + 2 post-step kernels on the finest level; 20 fused Chebyshev-SGS
+    # steps; 1 saddle apply, 1 dot, 1 v update, 1 w/x update.
+    per_iter = {eth.K_SADDLE_APPLY: 1, eth.K_CHEB_STEP: 3, eth.K_RESTRICT: 1, eth.K_PROLONG: 1,
+                eth.K_MQ_CHEB_STEP: 20, eth.K_DOT: 1, eth.K_MINRES_V: 1, eth.K_MINRES_WX: 1}
+    kernels = {}
+    for k, cnt in per_iter.items():
+        ms, by = Pm.profile_kernel(k, reps=args.profile_reps)
+        kernels[eth.KERNEL_NAMES[k]] = dict(avg_us=1e3 * ms, bytes=by, gbs=by / (ms * 1e-3) / 1e9,
+                                            launches_per_iteration=cnt,
+                                            us_per_iteration=1e3 * ms * cnt)
+    dom = max(kernels, key=lambda k: kernels[k]["us_per_iteration"])
+    dk = kernels[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(dk["gbs"], 2),
+                "peak": MI355X_HBM_GBS, "unit": "GB/s",
+                "frac": round(dk["gbs"] / MI355X_HBM_GBS, 5), "traffic": None,
+                "bytes_per_launch": dk["bytes"], "avg_launch_us": round(dk["avg_us"], 3)}
+    log("kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us {v['gbs']:.0f}GB/s"
+                                for k, v in kernels.items()))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample ...")
+        cpu = cpu_baseline(n, its_m, args.cpu_iters)
+        log(f"oracle: {cpu['value']:.4g} solves/s ({cpu['seconds_per_iteration']:.2f} s/iteration)")
+
+    value = args.steps / mixed["seconds"]
+    out = {
+        "metric": "Krylov solves/sec at 1e-6 residual, mixed vs FP64 on 1 GPU; stencil HBM GB/s",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * mixed["seconds"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 Krylov + f32 preconditioner",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Stokes lid-driven cavity, unit square, {n}x{n} Q2 elements, "
+                        f"Q1+P0 pressure frame, MINRES rtol {args.rtol:g}, GMG V(2,2) Chebyshev "
+                        f"+ 20-step Chebyshev-SGS pressure mass, mixed precision",
+            "n": n,
+            "unknowns": 2 * (2 * n + 1) ** 2 + (n + 1) ** 2 + n * n,
+            "hip_graph": use_graph,
+        },
+        "iterations": its_m,
+        "true_rel_residual": mixed["true_residual"],
+        "fp64": {"value": round(args.steps / fp64["seconds"], 4), "unit": "solves/s",
+                 "ms_per_step": round(1e3 * fp64["seconds"] / args.steps, 4),
+                 "iterations": fp64["iterations"][-1], "true_rel_residual": fp64["true_residual"]},
+        "mixed_over_fp64": round(fp64["seconds"] / mixed["seconds"], 4),
+        "equal_residual_ok": bool(equal_residual_ok),
+        "roofline": roofline,
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernels.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -144,6 +144,24 @@ int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, dou
 int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, double* x,
               int64_t batch, int64_t ld, eth_solve_info* info);
 
+/* Kernel timing for roofline reporting.  Launches `reps` times the kernel
+ * `kernel` (ETH_K_*) exactly as one MINRES iteration launches it (same grid,
+ * same workspaces, finest level where a hierarchy is involved), between two
+ * HIP events recorded on the problem's stream, after a prior eth_solve has
+ * filled the workspaces.  Returns the average duration of one launch in
+ * *avg_ms and the algorithmic bytes one launch must move (reads + writes of
+ * the vectors it touches, without halo re-reads) in *bytes. */
+#define ETH_K_SADDLE_APPLY   0   /* a1: K x with the fused <Kx, x> partials          */
+#define ETH_K_CHEB_STEP      1   /* a3: one Chebyshev smoothing step, finest level    */
+#define ETH_K_RESTRICT       2   /* a3: fused residual + restriction, finest level    */
+#define ETH_K_PROLONG        3   /* a3: prolongation + correction, finest level       */
+#define ETH_K_MQ_CHEB_STEP   4   /* a4: one fused Chebyshev-SGS step (9 colour passes)*/
+#define ETH_K_DOT            5   /* a6: deterministic dot product over N              */
+#define ETH_K_MINRES_V       6   /* a6: Lanczos vector update                         */
+#define ETH_K_MINRES_WX      7   /* a6: w / x update                                  */
+int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, double* avg_ms,
+                       double* bytes);
+
 const char* eth_status_string(int status);
 /* message of the last failing call on this handle (or of the last failing
  * eth_setup when p is NULL); valid until the next call */

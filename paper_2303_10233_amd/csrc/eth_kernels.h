@@ -13,12 +13,25 @@ struct Gate {
 };
 inline Gate no_gate() { return Gate{nullptr, 0}; }
 
+// Per right-hand-side flag cleared (set to 0) by block (0,0,r) of a kernel
+// before anything else; used to retire the pending MINRES w/x update.
+struct ClearFlag {
+  int* p;
+  int stride;  // in ints
+  __device__ void apply(int r) const {
+    if (p && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0)
+      p[(long long)r * stride] = 0;
+  }
+};
+inline ClearFlag no_clear() { return ClearFlag{nullptr, 0}; }
+
 // ---------------- saddle-point operator (k_saddle.hip) ----------------------
 // y = K x on the full layout, FP64.  mode 0: boundary velocity inputs are
 // masked, boundary rows of y are 0.  Optional fused reduction of <y, x>.
 int saddle_blocks(const Geo& g);
 void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, long long ld,
-                         int batch, Gate gate, const RedCtx* dot, hipStream_t st);
+                         int batch, Gate gate, const RedCtx* dot, hipStream_t st,
+                         ClearFlag clear = no_clear());
 // Oseen: y = [nu A + N(w)] u + B^T p, B u  (transpose: N -> N^T)
 void launch_apply_oseen(const Geo& g, double nu, const double* wind, int transpose,
                         const double* x, double* y, long long ld, int batch, Gate gate,
@@ -50,8 +63,7 @@ void launch_copy_boundary(const Geo& g, const double* b, double* x, long long ld
 void launch_minres_v(long long n, const double* y, const double* v, double* vprev_io,
                      long long ld, int batch, const MinresScalars* s, hipStream_t st);
 void launch_minres_wx(long long n, const double* z, double* wprev_io, const double* w,
-                      double* x, long long ld, int batch, MinresScalars* s,
-                      unsigned* tickets, hipStream_t st);
+                      double* x, long long ld, int batch, const MinresScalars* s, hipStream_t st);
 // v = b - y with boundary rows zeroed (initial residual)
 void launch_residual_init(const Geo& g, const double* b, const double* y, double* v,
                           long long ld, int batch, hipStream_t st);
@@ -112,6 +124,10 @@ void launch_mq_colour(const Geo& g, const T* r, T* t, int colour, int batch, Gat
 template <typename T>
 void launch_mq_cheb_combine(const Geo& g, T* t, T* z, T* d, double a, double b, int first,
                             int batch, Gate gate, hipStream_t st);
+// one fused Chebyshev step (symmetric multicolour SGS sweep from zin + combine)
+template <typename T>
+void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d, double a,
+                          double b, int first, int batch, Gate gate, hipStream_t st);
 template <typename T>
 void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, int batch,
                            const double* coef, double scale, Gate gate, hipStream_t st);

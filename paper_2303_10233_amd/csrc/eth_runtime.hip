@@ -4,7 +4,9 @@
 // declared in eth.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 #include <string>
@@ -92,6 +94,7 @@ struct Problem {
   double* mq_coef2 = nullptr;        // batch
   double kDk = 0.0, kk = 0.0;
   std::vector<double> mq_a, mq_b;    // Chebyshev coefficients for the SGS iteration
+  bool fused_mq = true;              // one launch per Chebyshev step (ETH_DEBUG_UNFUSED_MQ=1: per colour)
   ScaleState* d_scale = nullptr;     // [4] scale epilogue states
 
   // Krylov workspace
@@ -103,7 +106,6 @@ struct Problem {
   int hist_len = 0;
   double* red_partials = nullptr;
   unsigned* red_tickets = nullptr;
-  unsigned* wx_tickets = nullptr;
   double* red_result = nullptr;      // batch * 4
   double* h_red = nullptr;           // pinned
   double* ub = nullptr;              // Dirichlet data (2 nv)
@@ -194,6 +196,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.precision != ETH_FP64 && d.precision != ETH_MIXED)
     throw std::invalid_argument("invalid precision");
   mixed = d.precision == ETH_MIXED;
+  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) fused_mq = (e[0] != '1');
   max_batch = d.max_batch > 0 ? d.max_batch : 1;
   st = static_cast<hipStream_t>(d.stream);
   g = make_geo(d.n, (d.x1 - d.x0) / d.n);
@@ -215,11 +218,9 @@ void Problem::setup(const eth_problem_desc& desc) {
   const int maxblocks = std::max(std::max(dot_blocks(g.N), saddle_blocks(g)), 4096);
   red_partials = alloc<double>((size_t)maxblocks * kMaxRedVals * max_batch);
   red_tickets = alloc<unsigned>(max_batch);
-  wx_tickets = alloc<unsigned>(max_batch);
   red_result = alloc<double>((size_t)kMaxRedVals * max_batch);
   ETH_HIP(hipHostMalloc((void**)&h_red, sizeof(double) * kMaxRedVals * max_batch, hipHostMallocDefault));
   ETH_HIP(hipMemsetAsync(red_tickets, 0, sizeof(unsigned) * max_batch, st));
-  ETH_HIP(hipMemsetAsync(wx_tickets, 0, sizeof(unsigned) * max_batch, st));
   ETH_HIP(hipMemsetAsync(d_ms, 0, sizeof(MinresScalars) * max_batch, st));
   ub = alloc<double>(2 * (size_t)g.nv);
   launch_dirichlet_lid(g, d.lid_u, d.corner_mode, ub, st);
@@ -440,10 +441,20 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
   RedCtx rin = red(nbk, 1, EPI_SCALE, &d_scale[1]);
   launch_mq_kdot<double>(g, r, ld, g.off_pk(), batch, rin, gate, st);
   launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);
-  static const int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
-  for (int k = 0; k < d.mq_steps; ++k) {
-    for (int c = 0; c < 9; ++c) launch_mq_colour<T>(g, rr, tt, order[c], batch, gate, st);
-    launch_mq_cheb_combine<T>(g, tt, zz, dd, mq_a[k], mq_b[k], k == 0, batch, gate, st);
+  if (fused_mq) {
+    // ping-pong between mq_z and mq_t; the result ends in zz
+    // step k reads zb[k&1] and writes zb[(k+1)&1]; the last step must write zz
+    T* zb[2] = {zz, tt};
+    if (d.mq_steps % 2 == 1) std::swap(zb[0], zb[1]);
+    for (int k = 0; k < d.mq_steps; ++k)
+      launch_mq_cheb_fused<T>(g, rr, zb[k & 1], zb[(k + 1) & 1], dd, mq_a[k], mq_b[k], k == 0,
+                              batch, gate, st);
+  } else {
+    static const int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
+    for (int k = 0; k < d.mq_steps; ++k) {
+      for (int c = 0; c < 9; ++c) launch_mq_colour<T>(g, rr, tt, order[c], batch, gate, st);
+      launch_mq_cheb_combine<T>(g, tt, zz, dd, mq_a[k], mq_b[k], k == 0, batch, gate, st);
+    }
   }
   RedCtx rout = red(nbk, 1, EPI_SCALE, &d_scale[2]);
   launch_mq_kdot<T>(g, zz, np, 0, batch, rout, gate, st);
@@ -478,12 +489,13 @@ void Problem::minres_iteration(int batch, int parity) {
   double* wp = kw[b];
   const Gate gate = active_gate();
   RedCtx rd = red(saddle_blocks(g), 1, EPI_MINRES_DELTA, d_ms);
-  launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st);
+  const ClearFlag clear_wx{&d_ms[0].wx_todo, (int)(sizeof(MinresScalars) / sizeof(int))};
+  launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st, clear_wx);
   launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st);   // vp <- v_{j+1}
   precond(vp, zn, ldw, batch, gate);
   RedCtx rg = red(dot_blocks(g.N), 1, EPI_MINRES_GAMMA, d_ms);
   launch_dot(g.N, zn, vp, ldw, batch, rg, gate, st);
-  launch_minres_wx(g.N, z, wp, w, kx, ldw, batch, d_ms, wx_tickets, st);   // wp <- w_{j+1}
+  launch_minres_wx(g.N, z, wp, w, kx, ldw, batch, d_ms, st);   // wp <- w_{j+1}
 }
 
 void Problem::run_iterations(int batch, int count, bool use_graph) {
@@ -778,6 +790,137 @@ int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, doubl
   if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
   if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
   return guarded(p, [&] { return p->impl.solve_minres(o, b, x, (int)batch, ld, info); });
+}
+
+int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, double* avg_ms,
+                       double* bytes) {
+  if (!p || !avg_ms || !bytes || reps < 1) return fail(p, ETH_EINVAL, "invalid argument");
+  if (batch < 1 || batch > p->impl.max_batch) return fail(p, ETH_EINVAL, "invalid batch");
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    const eth::Geo& g = P.g;
+    const int B = (int)batch;
+    const double N = (double)g.N;
+    const double es = P.mixed ? 4.0 : 8.0;
+    std::function<void()> launch;
+    double by = 0.0;
+    const eth::Gate gate = eth::no_gate();
+    switch (kernel) {
+      case ETH_K_SADDLE_APPLY: {
+        launch = [&] {
+          eth::RedCtx rd = P.red(eth::saddle_blocks(g), 1, eth::EPI_NONE, nullptr, P.red_result);
+          eth::launch_apply_stokes(g, P.d.nu, P.kz[0], P.ky, P.ldw, B, gate, &rd, P.st);
+        };
+        by = 16.0 * N;
+        break;
+      }
+      case ETH_K_CHEB_STEP:
+      case ETH_K_RESTRICT:
+      case ETH_K_PROLONG: {
+        if (P.lv.size() < 2) throw std::runtime_error("unsupported:no multigrid hierarchy");
+        const eth::Geo& gf = P.lv[0];
+        const eth::Geo& gc = P.lv[1];
+        const double vf = 2.0 * gf.nv, vc = 2.0 * gc.nv;
+        if (kernel == ETH_K_CHEB_STEP) {
+          launch = [&] {
+            if (P.mixed)
+              eth::launch_cheb_step<float>(gf, (float*)P.vb[0], (float*)P.vx[0], (float*)P.vxo[0],
+                                           0.5, 0.1, 1, 2 * B, nullptr, 0, 0.0, gate, B, P.st);
+            else
+              eth::launch_cheb_step<double>(gf, (double*)P.vb[0], (double*)P.vx[0],
+                                            (double*)P.vxo[0], 0.5, 0.1, 1, 2 * B, nullptr, 0, 0.0,
+                                            gate, B, P.st);
+          };
+          by = 4.0 * es * vf;   // read b, x, x_prev; write x_new
+        } else if (kernel == ETH_K_RESTRICT) {
+          launch = [&] {
+            if (P.mixed)
+              eth::launch_restrict<float>(gf, gc, (float*)P.vb[0], (float*)P.vx[0],
+                                          (float*)P.vb[1], (float*)P.vxo[1], 0.1, 2 * B, B, gate, P.st);
+            else
+              eth::launch_restrict<double>(gf, gc, (double*)P.vb[0], (double*)P.vx[0],
+                                           (double*)P.vb[1], (double*)P.vxo[1], 0.1, 2 * B, B, gate,
+                                           P.st);
+          };
+          by = 2.0 * es * vf + 2.0 * es * vc;
+        } else {
+          launch = [&] {
+            if (P.mixed)
+              eth::launch_prolong_add<float>(gf, gc, (float*)P.vx[1], (float*)P.vxo[0], 2 * B, B,
+                                             gate, P.st);
+            else
+              eth::launch_prolong_add<double>(gf, gc, (double*)P.vx[1], (double*)P.vxo[0], 2 * B,
+                                              B, gate, P.st);
+          };
+          by = es * vc + 2.0 * es * vf;
+        }
+        by *= B;
+        break;
+      }
+      case ETH_K_MQ_CHEB_STEP: {
+        if (!P.mq_r) throw std::runtime_error("unsupported:no Chebyshev-SGS workspace");
+        launch = [&] {
+          if (P.mixed)
+            eth::launch_mq_cheb_fused<float>(g, (float*)P.mq_r, (float*)P.mq_z, (float*)P.mq_t,
+                                             (float*)P.mq_d, 0.5, 0.1, 0, B, gate, P.st);
+          else
+            eth::launch_mq_cheb_fused<double>(g, (double*)P.mq_r, (double*)P.mq_z,
+                                              (double*)P.mq_t, (double*)P.mq_d, 0.5, 0.1, 0, B,
+                                              gate, P.st);
+        };
+        // read r, z_k, d; write z_{k+1}, d (pressure vectors of n_k + n_0)
+        by = 5.0 * es * (g.nk + g.n0) * B;
+        break;
+      }
+      case ETH_K_DOT: {
+        launch = [&] {
+          eth::RedCtx rc = P.red(eth::dot_blocks(g.N), 1, eth::EPI_NONE, nullptr, P.red_result);
+          eth::launch_dot(g.N, P.kz[0], P.kv[0], P.ldw, B, rc, gate, P.st);
+        };
+        by = 16.0 * N * B;
+        break;
+      }
+      case ETH_K_MINRES_V: {
+        launch = [&] {
+          eth::launch_minres_v(g.N, P.ky, P.kv[0], P.kw[0], P.ldw, B, P.d_ms, P.st);
+        };
+        by = 32.0 * N * B;
+        break;
+      }
+      case ETH_K_MINRES_WX: {
+        launch = [&] {
+          eth::launch_minres_wx(g.N, P.kz[0], P.kw[0], P.kw[1], P.ky, P.ldw, B, P.d_ms, P.st);
+        };
+        by = 48.0 * N * B;
+        break;
+      }
+      default:
+        throw std::invalid_argument("unknown kernel id");
+    }
+    if (kernel == ETH_K_SADDLE_APPLY) by *= B;
+    // keep the update kernels active (their gates read the MINRES flags)
+    for (int r = 0; r < B; ++r) {
+      P.h_ms[r].active = 1;
+      P.h_ms[r].wx_todo = 1;
+      P.h_ms[r].vy = 1.0;
+    }
+    ETH_HIP(hipMemcpyAsync(P.d_ms, P.h_ms, sizeof(eth::MinresScalars) * B, hipMemcpyHostToDevice, P.st));
+    hipEvent_t e0, e1;
+    ETH_HIP(hipEventCreate(&e0));
+    ETH_HIP(hipEventCreate(&e1));
+    launch();   // warm-up
+    ETH_HIP(hipEventRecord(e0, P.st));
+    for (int i = 0; i < reps; ++i) launch();
+    ETH_HIP(hipEventRecord(e1, P.st));
+    ETH_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
+    *bytes = by;
+    return ETH_OK;
+  });
 }
 
 const char* eth_status_string(int status) {

@@ -30,6 +30,34 @@ __device__ __forceinline__ double mq_diag(const Geo& g, long long i) {
   return h2 * (4.0 * mx * my) / 36.0;
 }
 
+
+// Gauss-Seidel update of one Q1 coefficient of M_Q t = r, in the storage
+// precision T.  tq9[(b+1)*3 + (a+1)] = t at Q1 node (c+a, d+b), te4[(b+1)*2 +
+// (a+1)] = t at element (c+a, d+b) (a, b in {-1, 0}); L*/R* flag whether the
+// node has a left/right (lower/upper) element column (row).
+//   (M_Q t)_a = (h^2/36) sum w_x w_y t + (h^2/4) sum_{elements} t_0,
+//   D_aa = h^2 m_x m_y / 9  with m = number of adjacent element columns/rows.
+template <typename T>
+__device__ __forceinline__ T q1_gs_update(T t, T r, const T* tq9, const T* te4, int Lx, int Rx,
+                                          int Ly, int Ry, T h2_36, T h2_4, T inv_h2_9) {
+  const T wx0 = T(Lx), wx1 = T(2 * (Lx + Rx)), wx2 = T(Rx);
+  const T wy0 = T(Ly), wy1 = T(2 * (Ly + Ry)), wy2 = T(Ry);
+  const T s0 = wx0 * tq9[0] + wx1 * tq9[1] + wx2 * tq9[2];
+  const T s1 = wx0 * tq9[3] + wx1 * tq9[4] + wx2 * tq9[5];
+  const T s2 = wx0 * tq9[6] + wx1 * tq9[7] + wx2 * tq9[8];
+  const T qk = (wy0 * s0 + wy1 * s1 + wy2 * s2) * h2_36;
+  const T e = (te4[0] * T(Lx * Ly) + te4[1] * T(Rx * Ly)) + (te4[2] * T(Lx * Ry) + te4[3] * T(Rx * Ry));
+  const T acc = qk + h2_4 * e;
+  return t + (r - acc) * (inv_h2_9 / T((Lx + Rx) * (Ly + Ry)));
+}
+
+// Gauss-Seidel update of one element coefficient: t_0 = r_0/h^2 - (sum of
+// the four vertex values)/4
+template <typename T>
+__device__ __forceinline__ T p0_gs_update(T r, T v00, T v10, T v01, T v11, T inv_h2) {
+  return r * inv_h2 - T(0.25) * ((v00 + v10) + (v01 + v11));
+}
+
 __global__ __launch_bounds__(NT) void k_mq_diag_dot(Geo g, const double* __restrict__ r,
                                                     long long ld, RedCtx rc, Gate gate) {
   __shared__ double sred[NT / 64];
@@ -111,41 +139,35 @@ __global__ void k_mq_colour(Geo g, const T* __restrict__ r, T* __restrict__ t, i
     const int c = 2 * (blockIdx.x * blockDim.x + threadIdx.x) + (colour & 1);
     const int d = 2 * (blockIdx.y * blockDim.y + threadIdx.y) + (colour >> 1);
     if (c > n || d > n) return;
-    const int lx = (c > 0), rx = (c < n), ly = (d > 0), ry = (d < n);
-    const double wx[3] = {(double)lx, 2.0 * (lx + rx), (double)rx};
-    const double wy[3] = {(double)ly, 2.0 * (ly + ry), (double)ry};
-    double acc = 0.0;
+    const int Lx = (c > 0), Rx = (c < n), Ly = (d > 0), Ry = (d < n);
+    T q9[9], e4[4];
 #pragma unroll
-    for (int b = -1; b <= 1; ++b) {
-      if (wy[b + 1] == 0.0) continue;
-      double s = 0.0;
+    for (int b = -1; b <= 1; ++b)
 #pragma unroll
       for (int a = -1; a <= 1; ++a) {
-        if (wx[a + 1] == 0.0) continue;
-        s += wx[a + 1] * (double)tk[(long long)(d + b) * (n + 1) + (c + a)];
+        const int cc = c + a, dd = d + b;
+        q9[(b + 1) * 3 + (a + 1)] =
+            (cc >= 0 && cc <= n && dd >= 0 && dd <= n) ? tk[(long long)dd * (n + 1) + cc] : T(0);
       }
-      acc += wy[b + 1] * s;
-    }
-    acc *= h2 / 36.0;
-    double e = 0.0;   // elements around the node
+#pragma unroll
     for (int b = -1; b <= 0; ++b)
+#pragma unroll
       for (int a = -1; a <= 0; ++a) {
         const int ex = c + a, ey = d + b;
-        if (ex >= 0 && ex < n && ey >= 0 && ey < n) e += (double)t0[(long long)ey * n + ex];
+        e4[(b + 1) * 2 + (a + 1)] =
+            (ex >= 0 && ex < n && ey >= 0 && ey < n) ? t0[(long long)ey * n + ex] : T(0);
       }
-    acc += 0.25 * h2 * e;
     const long long i = (long long)d * (n + 1) + c;
-    const double D = h2 * (4.0 * (lx + rx) * (ly + ry)) / 36.0;
-    tk[i] = (T)((double)tk[i] + ((double)rr[i] - acc) / D);
+    tk[i] = q1_gs_update<T>(tk[i], rr[i], q9, e4, Lx, Rx, Ly, Ry, T(h2 / 36.0), T(0.25 * h2),
+                            T(9.0 / h2));
   } else {
     const int ex = blockIdx.x * blockDim.x + threadIdx.x;
     const int ey = blockIdx.y * blockDim.y + threadIdx.y;
     if (ex >= n || ey >= n) return;
     const long long q = (long long)ey * (n + 1) + ex;
-    const double s = (double)tk[q] + (double)tk[q + 1] + (double)tk[q + n + 1] + (double)tk[q + n + 2];
     const long long e = (long long)ey * n + ex;
-    // t0 new = t0 + (r0 - h^2/4 s - h^2 t0) / h^2 = r0 / h^2 - s / 4
-    tk[g.nk + e] = (T)((double)rr[g.nk + e] / h2 - 0.25 * s);
+    tk[g.nk + e] = p0_gs_update<T>(rr[g.nk + e], tk[q], tk[q + 1], tk[q + n + 1], tk[q + n + 2],
+                                   T(1.0 / h2));
   }
 }
 
@@ -159,13 +181,14 @@ __global__ void k_mq_cheb_combine(Geo g, T* __restrict__ t, T* __restrict__ z, T
   const long long np = (long long)g.nk + g.n0;
   if (i >= np) return;
   const long long o = (long long)rhs * np + i;
-  const double zo = (double)z[o];
-  const double s = (double)t[o] - zo;
-  const double dn = first ? b * s : a * (double)d[o] + b * s;
-  const double zn = zo + dn;
-  d[o] = (T)dn;
-  z[o] = (T)zn;
-  t[o] = (T)zn;
+  const T ta = T(a), tb = T(b);
+  const T z0 = first ? T(0) : z[o];
+  const T sv = t[o] - z0;
+  const T dn = first ? tb * sv : ta * d[o] + tb * sv;
+  const T zn = z0 + dn;
+  d[o] = dn;
+  z[o] = zn;
+  t[o] = zn;
 }
 
 // out_p = scale * (z - coef k)
@@ -179,6 +202,131 @@ __global__ void k_mq_project_out(Geo g, const T* __restrict__ z, double* __restr
   if (i >= np) return;
   const double kv = (i < g.nk) ? 1.0 : -1.0;
   out[(long long)rhs * ld + g.off_pk() + i] = scale * ((double)z[(long long)rhs * np + i] - coef[rhs] * kv);
+}
+
+
+// ---------------------------------------------------------------------------
+// One Chebyshev step of the pressure-mass solve in a single launch: the
+// symmetric multicolour Gauss-Seidel sweep from z_k (colours 0,1,2,3,4,3,2,1,0)
+// is temporally blocked in LDS.  A block of 32 x 32 threads owns TQ x TQ Q1
+// nodes and the elements with the same lower-left vertex; it stages a region
+// widened by HALO nodes, runs the nine colour passes on the whole region (one
+// colour node per thread per pass; each pass can spread stale halo values
+// inward by one node at most, so the owned part is exact after nine passes)
+// and then forms
+//   s = t - z_k,  d = first ? b s : a d + b s,  z_{k+1} = z_k + d.
+// Node updates share q1_gs_update / p0_gs_update with the per-colour kernel,
+// so both give bit-identical sweeps.
+// ---------------------------------------------------------------------------
+constexpr int TQ = 32, HALO = 10;
+constexpr int RQ = TQ + 2 * HALO;       // staged Q1 nodes per side
+constexpr int RE = RQ - 1;              // staged elements per side
+constexpr int FT = 1024;                // threads per block (32 x 32)
+static_assert(TQ % 2 == 0 && HALO % 2 == 0, "parity of local and global indices must agree");
+static_assert((RQ - 2 + 1) / 2 <= 32, "one colour node per thread and pass");
+
+template <typename T>
+__global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict__ r,
+                                                      const T* __restrict__ zin,
+                                                      T* __restrict__ zout, T* __restrict__ d,
+                                                      double a, double b, int first, Gate gate) {
+  __shared__ T tq[RQ * RQ];
+  __shared__ T rq[RQ * RQ];
+  __shared__ T te[RE * RE];
+  __shared__ T re[RE * RE];
+  const int rhs = blockIdx.z;
+  if (gate.off(rhs)) return;
+  const int n = g.n;
+  const long long np = (long long)g.nk + g.n0;
+  const T* rr = r + (long long)rhs * np;
+  const T* zi = zin + (long long)rhs * np;
+  const int c0 = blockIdx.x * TQ, d0 = blockIdx.y * TQ;
+  const int gx = c0 - HALO, gy = d0 - HALO;      // global index of local 0
+  const double h2 = g.h * g.h;
+  const T h2_36 = T(h2 / 36.0), h2_4 = T(0.25 * h2), inv_h2_9 = T(9.0 / h2), inv_h2 = T(1.0 / h2);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * 32 + tx;
+  for (int k = tid; k < RQ * RQ; k += FT) {
+    const int lx = k % RQ, ly = k / RQ;
+    const int c = gx + lx, dd = gy + ly;
+    T tv = T(0), rv = T(0);
+    if (c >= 0 && c <= n && dd >= 0 && dd <= n) {
+      const long long q = (long long)dd * (n + 1) + c;
+      rv = rr[q];
+      if (!first) tv = zi[q];
+    }
+    tq[k] = tv;
+    rq[k] = rv;
+  }
+  for (int k = tid; k < RE * RE; k += FT) {
+    const int lx = k % RE, ly = k / RE;
+    const int e = gx + lx, f = gy + ly;
+    T tv = T(0), rv = T(0);
+    if (e >= 0 && e < n && f >= 0 && f < n) {
+      const long long q = g.nk + (long long)f * n + e;
+      rv = rr[q];
+      if (!first) tv = zi[q];
+    }
+    te[k] = tv;
+    re[k] = rv;
+  }
+  __syncthreads();
+  constexpr int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
+#pragma unroll 1
+  for (int pass = 0; pass < 9; ++pass) {
+    const int colour = order[pass];
+    if (colour < 4) {
+      const int lx = ((colour & 1) == 0 ? 2 : 1) + 2 * tx;
+      const int ly = ((colour >> 1) == 0 ? 2 : 1) + 2 * ty;
+      const int c = gx + lx, dd = gy + ly;
+      if (lx <= RQ - 2 && ly <= RQ - 2 && c >= 0 && c <= n && dd >= 0 && dd <= n) {
+        const int Lx = (c > 0), Rx = (c < n), Ly = (dd > 0), Ry = (dd < n);
+        T q9[9], e4[4];
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+          for (int aa = 0; aa < 3; ++aa) q9[bb * 3 + aa] = tq[(ly + bb - 1) * RQ + (lx + aa - 1)];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int aa = 0; aa < 2; ++aa) e4[bb * 2 + aa] = te[(ly + bb - 1) * RE + (lx + aa - 1)];
+        const int li = ly * RQ + lx;
+        tq[li] = q1_gs_update<T>(tq[li], rq[li], q9, e4, Lx, Rx, Ly, Ry, h2_36, h2_4, inv_h2_9);
+      }
+    } else {
+      for (int k = tid; k < RE * RE; k += FT) {
+        const int lx = k % RE, ly = k / RE;
+        const int e = gx + lx, f = gy + ly;
+        if (e < 0 || e >= n || f < 0 || f >= n) continue;
+        const int q = ly * RQ + lx;
+        te[k] = p0_gs_update<T>(re[k], tq[q], tq[q + 1], tq[q + RQ], tq[q + RQ + 1], inv_h2);
+      }
+    }
+    __syncthreads();
+  }
+  // Chebyshev combination on the owned nodes and elements (one each per thread)
+  T* zo = zout + (long long)rhs * np;
+  T* dr = d + (long long)rhs * np;
+  const T ta = T(a), tb = T(b);
+  {
+    const int c = c0 + tx, dd = d0 + ty;
+    if (c <= n && dd <= n) {
+      const long long q = (long long)dd * (n + 1) + c;
+      const T z0 = first ? T(0) : zi[q];
+      const T sv = tq[(ty + HALO) * RQ + (tx + HALO)] - z0;
+      const T dn = first ? tb * sv : ta * dr[q] + tb * sv;
+      dr[q] = dn;
+      zo[q] = z0 + dn;
+    }
+    if (c < n && dd < n) {
+      const long long q = g.nk + (long long)dd * n + c;
+      const T z0 = first ? T(0) : zi[q];
+      const T sv = te[(ty + HALO) * RE + (tx + HALO)] - z0;
+      const T dn = first ? tb * sv : ta * dr[q] + tb * sv;
+      dr[q] = dn;
+      zo[q] = z0 + dn;
+    }
+  }
 }
 
 inline unsigned nb(long long n) { return (unsigned)((n + 255) / 256); }
@@ -250,6 +398,16 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
   ETH_LAUNCH_CHECK();
 }
 
+
+template <typename T>
+void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d, double a,
+                          double b, int first, int batch, Gate gate, hipStream_t st) {
+  dim3 grid((g.n + 1 + TQ - 1) / TQ, (g.n + 1 + TQ - 1) / TQ, batch);
+  hipLaunchKernelGGL(k_mq_cheb_fused<T>, grid, dim3(32, 32), 0, st, g, r, zin, zout, d, a, b, first,
+                     gate);
+  ETH_LAUNCH_CHECK();
+}
+
 #define ETH_INST(T)                                                                               \
   template void launch_mq_kdot<T>(const Geo&, const T*, long long, long long, int, const RedCtx&,  \
                                   Gate, hipStream_t);                                              \
@@ -259,7 +417,9 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
   template void launch_mq_cheb_combine<T>(const Geo&, T*, T*, T*, double, double, int, int, Gate,  \
                                           hipStream_t);                                            \
   template void launch_mq_project_out<T>(const Geo&, const T*, double*, long long, int,            \
-                                         const double*, double, Gate, hipStream_t);
+                                         const double*, double, Gate, hipStream_t);               \
+  template void launch_mq_cheb_fused<T>(const Geo&, const T*, const T*, T*, T*, double, double,    \
+                                        int, int, Gate, hipStream_t);
 ETH_INST(double)
 ETH_INST(float)
 #undef ETH_INST

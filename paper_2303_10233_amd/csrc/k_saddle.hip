@@ -58,7 +58,7 @@ __global__ __launch_bounds__(NT) void k_saddle_stokes(Geo g, double nu, const do
                                                       long long ldx,
                                                       double* __restrict__ y, long long ld,
                                                       const double* __restrict__ f, long long ldf,
-                                                      Gate gate, RedCtx rc) {
+                                                      Gate gate, RedCtx rc, ClearFlag clear) {
   __shared__ double su[2][VY][VX];
   __shared__ double sf[MODE == 1 ? 2 : 1][MODE == 1 ? VY : 1][MODE == 1 ? VX : 1];
   __shared__ double spk[PY][PX];
@@ -66,6 +66,7 @@ __global__ __launch_bounds__(NT) void k_saddle_stokes(Geo g, double nu, const do
   __shared__ double sred[NT / 64];
 
   const int rhs = blockIdx.z;
+  clear.apply(rhs);
   if (gate.off(rhs)) return;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx;
@@ -286,16 +287,16 @@ int saddle_blocks(const Geo& g) {
 }
 
 void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, long long ld,
-                         int batch, Gate gate, const RedCtx* dot, hipStream_t st) {
+                         int batch, Gate gate, const RedCtx* dot, hipStream_t st, ClearFlag clear) {
   dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, batch);
   dim3 block(TX, TY);
   if (dot) {
     hipLaunchKernelGGL((k_saddle_stokes<0, true>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                       nullptr, 0LL, gate, *dot);
+                       nullptr, 0LL, gate, *dot, clear);
   } else {
     RedCtx none{};
     hipLaunchKernelGGL((k_saddle_stokes<0, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                       nullptr, 0LL, gate, none);
+                       nullptr, 0LL, gate, none, clear);
   }
   ETH_LAUNCH_CHECK();
 }
@@ -309,7 +310,7 @@ void launch_lift_rhs(const Geo& g, double nu, const double* wind, const double* 
   RedCtx none{};
   // every batch entry shares the same Dirichlet data: ld of the input is 0
   hipLaunchKernelGGL((k_saddle_stokes<1, false>), grid, block, 0, st, g, nu, ub, 0LL, b, ld, f, ldf,
-                     no_gate(), none);
+                     no_gate(), none, no_clear());
   ETH_LAUNCH_CHECK();
 }
 

@@ -7,7 +7,7 @@ namespace eth {
 namespace {
 
 constexpr int NT = 256;
-constexpr int kVecBlocksMax = 1024;   // grid-stride cap per RHS for reductions
+constexpr int kVecBlocksMax = 256;    // grid-stride cap per RHS for reductions
 
 __global__ __launch_bounds__(NT) void k_dot(long long n, const double* __restrict__ x,
                                             const double* __restrict__ y, long long ld,
@@ -101,11 +101,13 @@ __global__ void k_minres_v(long long n, const double* __restrict__ y, const doub
 }
 
 // w_{j+1} = wz*zhat_j - wp*w_{j-1} - wc*w_j (written over w_{j-1}); x += xc*w_{j+1}
+// Runs while the Givens step of this iteration is pending (wx_todo); the
+// flag is cleared by the first kernel of the next iteration.
 __global__ void k_minres_wx(long long n, const double* __restrict__ z, double* __restrict__ wp,
                             const double* __restrict__ w, double* __restrict__ x, long long ld,
-                            MinresScalars* __restrict__ s, unsigned* __restrict__ tickets) {
+                            const MinresScalars* __restrict__ s) {
   const int rhs = blockIdx.y;
-  MinresScalars& S = s[rhs];
+  const MinresScalars& S = s[rhs];
   if (!S.wx_todo) return;
   const double cz = S.wz, cp = S.wp, cw = S.wc, cx = S.xc;
   const long long o = (long long)rhs * ld;
@@ -114,17 +116,6 @@ __global__ void k_minres_wx(long long n, const double* __restrict__ z, double* _
     const double wn = cz * z[o + i] - cp * wp[o + i] - cw * w[o + i];
     wp[o + i] = wn;
     x[o + i] += cx * wn;
-  }
-  // the last block to finish marks the update as consumed
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atomicAdd(&tickets[rhs], 1u);
-    if (t == gridDim.x - 1) {
-      tickets[rhs] = 0u;
-      S.wx_todo = 0;
-      __threadfence();
-    }
   }
 }
 
@@ -222,10 +213,9 @@ void launch_minres_v(long long n, const double* y, const double* v, double* vpre
 }
 
 void launch_minres_wx(long long n, const double* z, double* wprev_io, const double* w,
-                      double* x, long long ld, int batch, MinresScalars* s,
-                      unsigned* tickets, hipStream_t st) {
+                      double* x, long long ld, int batch, const MinresScalars* s, hipStream_t st) {
   hipLaunchKernelGGL(k_minres_wx, dim3(update_blocks(n), batch), dim3(256), 0, st, n, z,
-                     wprev_io, w, x, ld, s, tickets);
+                     wprev_io, w, x, ld, s);
   ETH_LAUNCH_CHECK();
 }
 

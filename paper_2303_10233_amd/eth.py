@@ -77,9 +77,16 @@ class SolveInfo(ctypes.Structure):
 
 EXPORTED = [
     "eth_setup", "eth_destroy", "eth_vector_length", "eth_get_levels", "eth_assemble_rhs",
-    "eth_apply_operator", "eth_apply_preconditioner", "eth_solve", "eth_status_string",
-    "eth_last_error",
+    "eth_apply_operator", "eth_apply_preconditioner", "eth_solve", "eth_profile_kernel",
+    "eth_status_string", "eth_last_error",
 ]
+
+K_SADDLE_APPLY, K_CHEB_STEP, K_RESTRICT, K_PROLONG, K_MQ_CHEB_STEP, K_DOT, K_MINRES_V, K_MINRES_WX = range(8)
+KERNEL_NAMES = {
+    K_SADDLE_APPLY: "k_saddle_stokes", K_CHEB_STEP: "k_cheb_step", K_RESTRICT: "k_restrict",
+    K_PROLONG: "k_prolong_add", K_MQ_CHEB_STEP: "k_mq_cheb_fused", K_DOT: "k_dot",
+    K_MINRES_V: "k_minres_v", K_MINRES_WX: "k_minres_wx",
+}
 
 
 def load_library(path=LIB_PATH):
@@ -106,6 +113,9 @@ def load_library(path=LIB_PATH):
     lib.eth_apply_preconditioner.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
     lib.eth_solve.restype = ctypes.c_int
+    lib.eth_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, i64,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.eth_profile_kernel.restype = ctypes.c_int
     lib.eth_status_string.argtypes = [ctypes.c_int]
     lib.eth_status_string.restype = ctypes.c_char_p
     lib.eth_last_error.argtypes = [P]
@@ -244,6 +254,15 @@ class Problem:
         _check(lib().eth_apply_preconditioner(self._h, int(transpose), _ptr(r2), _ptr(z2), B, ld),
                self._h)
         return z
+
+    def profile_kernel(self, kernel, reps=50, batch=1):
+        """(average ms per launch, algorithmic bytes per launch) of one kernel
+        of the MINRES iteration, timed with HIP events on the problem's stream."""
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(lib().eth_profile_kernel(self._h, kernel, reps, batch, ctypes.byref(ms),
+                                        ctypes.byref(by)), self._h)
+        return ms.value, by.value
 
     def solve(self, b, rtol=1e-6, maxit=1000, x0=None, method=MINRES, restart=50, c_factor=10.0,
               canonicalize=True, use_graph=False, true_residual=False, out=None):

@@ -143,6 +143,23 @@ def test_preconditioner_matches_oracle(n, velocity, mq, prec, tol):
     assert np.abs(z[:o][s.vel_bnd]).max() == 0.0
 
 
+@pytest.mark.parametrize("n,prec", [(16, eth.FP64), (66, eth.FP64), (64, eth.MIXED)])
+def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
+    """The temporally blocked Chebyshev-SGS kernel (nine colour passes in LDS
+    per launch) reproduces the one-launch-per-colour sweep bit for bit."""
+    print(f"[fused mq] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    r = uniform_vector(m.N, 3 + n)
+    r[: 2 * m.nv][System(m).vel_bnd] = 0.0
+    P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG)
+    z_fused = _np(P.apply_preconditioner(_t(r)))
+    monkeypatch.setenv("ETH_DEBUG_UNFUSED_MQ", "1")
+    Q = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG)
+    z_plain = _np(Q.apply_preconditioner(_t(r)))
+    o = 2 * m.nv
+    assert np.array_equal(z_fused[o:], z_plain[o:])
+
+
 def test_gpu_lanczos_lambda_close_to_exact():
     """The set-up estimate of lambda_max(D^{-1}A) (30 Lanczos steps) is a
     lower bound within 2% of the exact value on every smoothing level."""
