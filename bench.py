@@ -62,7 +62,8 @@ def cpu_baseline(n, iterations_per_solve, cpu_iters):
     m = Mesh(n)
     s = System(m)
     b = s.to_interior(s.rhs(None, lid_dirichlet(m)))
-    P = StokesBlockDiag(s, "gmg", "cheb_sgs", mq_lo=0.01, mq_steps=20)
+    # same Chebyshev-SGS interval as the GPU default: [min(0.01, 0.4/n), 1]
+    P = StokesBlockDiag(s, "gmg", "cheb_sgs", mq_lo=min(0.01, 0.4 / n), mq_steps=20)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     minres(lambda v: s.K @ v, b, P, tol=1e-30, maxit=cpu_iters)

@@ -72,7 +72,7 @@ typedef struct {
   int32_t velocity_mode;     /* eth_velocity_mode; EXACT needs (2n-1)^2 <= 4096     */
   int32_t mq_mode;           /* eth_mq_mode (default ETH_MQ_CHEB_SGS)               */
   int32_t mq_steps;          /* Chebyshev steps for ETH_MQ_CHEB_SGS (default 20)    */
-  double mq_cheb_lo;         /* eigen-interval of M_SGS^{-1} M_Q (default 0.01)      */
+  double mq_cheb_lo;         /* eigen-interval of M_SGS^{-1} M_Q (default min(0.01, 0.4/n)) */
   double mq_cheb_hi;         /*   (default 1, the SGS bound)                        */
   int32_t gmg_coarse_n;      /* halve while n even and n > gmg_coarse_n (default 4) */
   int32_t gmg_degree;        /* Chebyshev smoothing degree, pre and post (default 2)*/

@@ -35,7 +35,7 @@ void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, lo
 // Oseen: y = [nu A + N(w)] u + B^T p, B u  (transpose: N -> N^T)
 void launch_apply_oseen(const Geo& g, double nu, const double* wind, int transpose,
                         const double* x, double* y, long long ld, int batch, Gate gate,
-                        const RedCtx* dot, hipStream_t st);
+                        const RedCtx* dot, hipStream_t st, ClearFlag clear = no_clear());
 // b = lifted RHS: interior rows (M_v f)_I - (F u_B)_I, pressure rows -B u_B,
 // boundary rows u_B.  ub: full-length velocity Dirichlet vector (2 nv).
 void launch_lift_rhs(const Geo& g, double nu, const double* wind, const double* ub,

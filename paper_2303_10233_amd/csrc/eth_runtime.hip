@@ -76,6 +76,7 @@ struct Problem {
   int max_batch = 1;
   long long ldw = 0;                 // internal stride of Krylov vectors
   bool mixed = false;
+  bool oseen = false;
   std::string err;
   std::vector<void*> allocs;
 
@@ -151,6 +152,15 @@ struct Problem {
     return Gate{&d_ms[0].active, (int)(sizeof(MinresScalars) / sizeof(int))};
   }
 
+  // K x (or K^T x) on the full layout
+  void apply_op(int transpose, const double* x, double* y, long long ld, int batch, Gate gate,
+                const RedCtx* dot, ClearFlag clear = no_clear()) {
+    if (oseen)
+      launch_apply_oseen(g, d.nu, d.wind, transpose, x, y, ld, batch, gate, dot, st, clear);
+    else
+      launch_apply_stokes(g, d.nu, x, y, ld, batch, gate, dot, st, clear);
+  }
+
   // ---------------------------------------------------------------- setup
   void setup(const eth_problem_desc& desc);
   void build_velocity();
@@ -179,12 +189,17 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (std::fabs((d.x1 - d.x0) - (d.y1 - d.y0)) > 1e-12 * (d.x1 - d.x0))
     throw std::invalid_argument("square domain required");
   if (!(d.nu > 0.0)) throw std::invalid_argument("nu must be > 0");
-  if (d.kind != ETH_STOKES) throw std::runtime_error("unsupported:kind");
+  if (d.kind != ETH_STOKES && d.kind != ETH_OSEEN) throw std::invalid_argument("invalid kind");
+  if (d.kind == ETH_OSEEN && !d.wind) throw std::invalid_argument("Oseen needs a wind");
+  oseen = d.kind == ETH_OSEEN;
   if (d.mq_mode == 0) d.mq_mode = ETH_MQ_CHEB_SGS;
   if (d.mq_mode != ETH_MQ_DIAG && d.mq_mode != ETH_MQ_CHEB_SGS)
     throw std::invalid_argument("invalid mq_mode");
   if (d.mq_steps <= 0) d.mq_steps = 20;
-  if (d.mq_cheb_lo <= 0.0) d.mq_cheb_lo = 0.01;
+  // lower end of the SGS-preconditioned M_Q interval: its smallest nonzero
+  // eigenvalue decays like h^2; 0.4/n (at most 0.01) is the best of the oracle
+  // sweeps at n = 128 and 256
+  if (d.mq_cheb_lo <= 0.0) d.mq_cheb_lo = std::min(0.01, 0.4 / d.n);
   if (d.mq_cheb_hi <= 0.0) d.mq_cheb_hi = 1.0;
   if (!(d.mq_cheb_hi > d.mq_cheb_lo)) throw std::invalid_argument("mq interval empty");
   if (d.gmg_coarse_n <= 0) d.gmg_coarse_n = 4;
@@ -748,7 +763,8 @@ int eth_assemble_rhs(eth_problem* p, const double* f_nodal, int64_t ld_f, double
   if (f_nodal && batch > 1 && ld_f < 2LL * p->impl.g.nv) return fail(p, ETH_EINVAL, "ld_f too small");
   return guarded(p, [&] {
     Problem& P = p->impl;
-    eth::launch_lift_rhs(P.g, P.d.nu, P.d.wind, P.ub, f_nodal, ld_f, b, ld, (int)batch, P.st);
+    eth::launch_lift_rhs(P.g, P.d.nu, P.oseen ? P.d.wind : nullptr, P.ub, f_nodal, ld_f, b, ld,
+                         (int)batch, P.st);
     return ETH_OK;
   });
 }
@@ -758,10 +774,9 @@ int eth_apply_operator(eth_problem* p, int transpose, const double* x, double* y
   if (!p || !x || !y) return fail(p, ETH_EINVAL, "NULL argument");
   if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
   if (x == y) return fail(p, ETH_EINVAL, "x and y must not alias");
-  (void)transpose;   // the Stokes operator is symmetric
   return guarded(p, [&] {
     Problem& P = p->impl;
-    eth::launch_apply_stokes(P.g, P.d.nu, x, y, ld, (int)batch, eth::no_gate(), nullptr, P.st);
+    P.apply_op(transpose, x, y, ld, (int)batch, eth::no_gate(), nullptr);
     return ETH_OK;
   });
 }
@@ -772,6 +787,7 @@ int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, dou
   if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
   if (r == z) return fail(p, ETH_EINVAL, "r and z must not alias");
   (void)transpose;   // the Stokes preconditioner is symmetric
+  if (p->impl.oseen) return fail(p, ETH_EUNSUPPORTED, "Oseen preconditioner not available yet");
   return guarded(p, [&] {
     Problem& P = p->impl;
     P.precond(r, z, ld, (int)batch, eth::no_gate());
@@ -788,6 +804,7 @@ int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, doubl
   if (opts) o = *opts;
   else o.canonicalize = 1;
   if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
+  if (p->impl.oseen) return fail(p, ETH_EUNSUPPORTED, "Oseen solves not available yet");
   if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
   return guarded(p, [&] { return p->impl.solve_minres(o, b, x, (int)batch, ld, info); });
 }

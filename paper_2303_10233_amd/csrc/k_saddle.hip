@@ -51,16 +51,145 @@ __host__ __device__ constexpr int m6(int j, int df) {
   return j == 0 ? 1 : (df == -1 ? 0 : 4);
 }
 
+// 4-point Gauss-Legendre rule on [0,1] and the 1-D Q2 basis / derivative
+// values at its points: GB[q][i] = phi_i(xi_q), GD[q][i] = phi_i'(xi_q).
+constexpr int NG = 4;
+__device__ __forceinline__ void gauss_tables(double* W, double (*GB)[3], double (*GD)[3]) {
+  const double t1 = 0.33998104358485626480, t2 = 0.86113631159405257522;
+  const double w1 = 0.65214515486254614263, w2 = 0.34785484513745385737;
+  const double xq[NG] = {0.5 * (1 - t2), 0.5 * (1 - t1), 0.5 * (1 + t1), 0.5 * (1 + t2)};
+  W[0] = 0.5 * w2;
+  W[1] = 0.5 * w1;
+  W[2] = 0.5 * w1;
+  W[3] = 0.5 * w2;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const double t = xq[q];
+    GB[q][0] = (1 - t) * (1 - 2 * t);
+    GB[q][1] = 4 * t * (1 - t);
+    GB[q][2] = t * (2 * t - 1);
+    GD[q][0] = 4 * t - 3;
+    GD[q][1] = 4 - 8 * t;
+    GD[q][2] = 4 * t - 1;
+  }
+}
+
+// Convection on one element, both velocity components, 4x4 Gauss: exact for
+// any Q2 wind (the integrand w phi_i d(phi_j) has degree <= 6 per direction).
+//   TRANS = false: out_i = int (w . grad u_h) phi_i       (N u)
+//   TRANS = true : out_i = int (w . grad phi_i) u_h       (N^T u)
+// u[c][j][i], w[c][j][i]: local nodal values (x index i); out[c][j][i].
+template <bool TRANS>
+__device__ inline void element_convection(const double (*u)[3][3], const double (*w)[3][3], double h,
+                                          double (*out)[3][3]) {
+  double W[NG], GB[NG][3], GD[NG][3];
+  gauss_tables(W, GB, GD);
+  double wq[2][NG][NG];   // wind at the Gauss points [comp][qy][qx]
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int qy = 0; qy < NG; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < NG; ++qx) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          double t = 0.0;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) t += GB[qx][i] * w[c][j][i];
+          a += GB[qy][j] * t;
+        }
+        wq[c][qy][qx] = a;
+      }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if constexpr (!TRANS) {
+      double cv[NG][NG];
+#pragma unroll
+      for (int qy = 0; qy < NG; ++qy)
+#pragma unroll
+        for (int qx = 0; qx < NG; ++qx) {
+          double ux = 0.0, uy = 0.0;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            double tx = 0.0, ty = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              tx += GD[qx][i] * u[c][j][i];
+              ty += GB[qx][i] * u[c][j][i];
+            }
+            ux += GB[qy][j] * tx;
+            uy += GD[qy][j] * ty;
+          }
+          cv[qy][qx] = W[qx] * W[qy] * (wq[0][qy][qx] * ux + wq[1][qy][qx] * uy);
+        }
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          double a = 0.0;
+#pragma unroll
+          for (int qy = 0; qy < NG; ++qy) {
+            double t = 0.0;
+#pragma unroll
+            for (int qx = 0; qx < NG; ++qx) t += GB[qx][i] * cv[qy][qx];
+            a += GB[qy][j] * t;
+          }
+          out[c][j][i] = h * a;
+        }
+    } else {
+      double gx[NG][NG], gy[NG][NG];
+#pragma unroll
+      for (int qy = 0; qy < NG; ++qy)
+#pragma unroll
+        for (int qx = 0; qx < NG; ++qx) {
+          double uv = 0.0;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) t += GB[qx][i] * u[c][j][i];
+            uv += GB[qy][j] * t;
+          }
+          const double wu = W[qx] * W[qy] * uv;
+          gx[qy][qx] = wq[0][qy][qx] * wu;
+          gy[qy][qx] = wq[1][qy][qx] * wu;
+        }
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          double a = 0.0;
+#pragma unroll
+          for (int qy = 0; qy < NG; ++qy) {
+            double tx = 0.0, ty = 0.0;
+#pragma unroll
+            for (int qx = 0; qx < NG; ++qx) {
+              tx += GD[qx][i] * gx[qy][qx];
+              ty += GB[qx][i] * gy[qy][qx];
+            }
+            a += GB[qy][j] * tx + GD[qy][j] * ty;
+          }
+          out[c][j][i] = h * a;
+        }
+    }
+  }
+}
+
 // MODE 0: operator apply (boundary velocity masked, boundary rows 0).
 // MODE 1: lift: y = [M_v f; 0] - K_unmasked [u_B; 0]; boundary rows = u_B.
-template <int MODE, bool DOT>
-__global__ __launch_bounds__(NT) void k_saddle_stokes(Geo g, double nu, const double* __restrict__ x,
-                                                      long long ldx,
-                                                      double* __restrict__ y, long long ld,
-                                                      const double* __restrict__ f, long long ldf,
-                                                      Gate gate, RedCtx rc, ClearFlag clear) {
+// CONV adds the convection N(w) (TRANS: N(w)^T) of the nodal Q2 wind.
+template <int MODE, bool DOT, bool CONV, bool TRANS>
+__global__ __launch_bounds__(NT) void k_saddle(Geo g, double nu, const double* __restrict__ x,
+                                               long long ldx,
+                                               double* __restrict__ y, long long ld,
+                                               const double* __restrict__ f, long long ldf,
+                                               const double* __restrict__ wind,
+                                               Gate gate, RedCtx rc, ClearFlag clear) {
   __shared__ double su[2][VY][VX];
   __shared__ double sf[MODE == 1 ? 2 : 1][MODE == 1 ? VY : 1][MODE == 1 ? VX : 1];
+  __shared__ double sw[CONV ? 2 : 1][CONV ? VY : 1][CONV ? VX : 1];
+  __shared__ double sN[CONV ? 2 : 1][CONV ? (TY + 1) * (TX + 1) : 1][9];
   __shared__ double spk[PY][PX];
   __shared__ double sp0[EY][EX];
   __shared__ double sred[NT / 64];
@@ -90,6 +219,16 @@ __global__ __launch_bounds__(NT) void k_saddle_stokes(Geo g, double nu, const do
     }
     su[0][ly][lx] = vx;
     su[1][ly][lx] = vy;
+    if constexpr (CONV) {
+      double wxv = 0.0, wyv = 0.0;
+      if (I >= 0 && I <= top && J >= 0 && J <= top) {
+        const long long o = (long long)J * nq + I;
+        wxv = wind[o];
+        wyv = wind[g.nv + o];
+      }
+      sw[0][ly][lx] = wxv;
+      sw[1][ly][lx] = wyv;
+    }
     if constexpr (MODE == 1) {
       double fx = 0.0, fy = 0.0;
       if (f && I >= 0 && I <= top && J >= 0 && J <= top) {
@@ -119,6 +258,35 @@ __global__ __launch_bounds__(NT) void k_saddle_stokes(Geo g, double nu, const do
     }
   }
   __syncthreads();
+
+  if constexpr (CONV) {
+    // convection of every element touching the block's cells:
+    // elements (ex0-1 .. ex0+TX-1) x (ey0-1 .. ey0+TY-1)
+    for (int k = tid; k < (TX + 1) * (TY + 1); k += NT) {
+      const int lex = k % (TX + 1), ley = k / (TX + 1);
+      const int e = ex0 - 1 + lex, ff = ey0 - 1 + ley;
+      if (e < 0 || e >= n || ff < 0 || ff >= n) continue;
+      double ul[2][3][3], wl[2][3][3], ol[2][3][3];
+      const int bx = 2 * lex, by = 2 * ley;   // local velocity index of node (2e, 2f)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            ul[c][j][i] = su[c][by + j][bx + i];
+            wl[c][j][i] = sw[c][by + j][bx + i];
+          }
+      element_convection<TRANS>(ul, wl, g.h, ol);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) sN[c][k][3 * j + i] = ol[c][j][i];
+    }
+    __syncthreads();
+  }
 
   const int ex = ex0 + tx, ey = ey0 + ty;
   const double h = g.h;
@@ -168,6 +336,27 @@ __global__ __launch_bounds__(NT) void k_saddle_stokes(Geo g, double nu, const do
           }
         }
         double vx = sA * ax, vy = sA * ay;
+        if constexpr (CONV) {
+          // elements containing node (2ex+i, 2ey+j): (ex-1+a', ey-1+b') for the
+          // vertex parities, local index (i + 2(1-a'), j + 2(1-b'))
+          double cx = 0.0, cy = 0.0;
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb) {
+            if (j == 1 && bb == 0) continue;
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa) {
+              if (i == 1 && aa == 0) continue;
+              const int e = ex - 1 + aa, ff = ey - 1 + bb;
+              if (e < 0 || e >= n || ff < 0 || ff >= n) continue;
+              const int k = (ty + bb) * (TX + 1) + (tx + aa);
+              const int li = i + 2 * (1 - aa), lj = j + 2 * (1 - bb);   // I - 2e, J - 2f
+              cx += sN[0][k][3 * lj + li];
+              cy += sN[1][k][3 * lj + li];
+            }
+          }
+          vx += cx;
+          vy += cy;
+        }
         if constexpr (MODE == 0) {
           double bx = 0.0, by = 0.0, b0x = 0.0, b0y = 0.0;
 #pragma unroll
@@ -291,12 +480,12 @@ void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, lo
   dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, batch);
   dim3 block(TX, TY);
   if (dot) {
-    hipLaunchKernelGGL((k_saddle_stokes<0, true>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                       nullptr, 0LL, gate, *dot, clear);
+    hipLaunchKernelGGL((k_saddle<0, true, false, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
+                       nullptr, 0LL, nullptr, gate, *dot, clear);
   } else {
     RedCtx none{};
-    hipLaunchKernelGGL((k_saddle_stokes<0, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                       nullptr, 0LL, gate, none, clear);
+    hipLaunchKernelGGL((k_saddle<0, false, false, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
+                       nullptr, 0LL, nullptr, gate, none, clear);
   }
   ETH_LAUNCH_CHECK();
 }
@@ -304,13 +493,41 @@ void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, lo
 void launch_lift_rhs(const Geo& g, double nu, const double* wind, const double* ub,
                      const double* f, long long ldf, double* b, long long ld, int batch,
                      hipStream_t st) {
-  (void)wind;
   dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, batch);
   dim3 block(TX, TY);
   RedCtx none{};
   // every batch entry shares the same Dirichlet data: ld of the input is 0
-  hipLaunchKernelGGL((k_saddle_stokes<1, false>), grid, block, 0, st, g, nu, ub, 0LL, b, ld, f, ldf,
-                     no_gate(), none, no_clear());
+  if (wind)
+    hipLaunchKernelGGL((k_saddle<1, false, true, false>), grid, block, 0, st, g, nu, ub, 0LL, b, ld,
+                       f, ldf, wind, no_gate(), none, no_clear());
+  else
+    hipLaunchKernelGGL((k_saddle<1, false, false, false>), grid, block, 0, st, g, nu, ub, 0LL, b, ld,
+                       f, ldf, nullptr, no_gate(), none, no_clear());
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_apply_oseen(const Geo& g, double nu, const double* wind, int transpose,
+                        const double* x, double* y, long long ld, int batch, Gate gate,
+                        const RedCtx* dot, hipStream_t st, ClearFlag clear) {
+  dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, batch);
+  dim3 block(TX, TY);
+  RedCtx none{};
+  const RedCtx rc = dot ? *dot : none;
+  if (transpose) {
+    if (dot)
+      hipLaunchKernelGGL((k_saddle<0, true, true, true>), grid, block, 0, st, g, nu, x, ld, y, ld,
+                         nullptr, 0LL, wind, gate, rc, clear);
+    else
+      hipLaunchKernelGGL((k_saddle<0, false, true, true>), grid, block, 0, st, g, nu, x, ld, y, ld,
+                         nullptr, 0LL, wind, gate, rc, clear);
+  } else {
+    if (dot)
+      hipLaunchKernelGGL((k_saddle<0, true, true, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
+                         nullptr, 0LL, wind, gate, rc, clear);
+    else
+      hipLaunchKernelGGL((k_saddle<0, false, true, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
+                         nullptr, 0LL, wind, gate, rc, clear);
+  }
   ETH_LAUNCH_CHECK();
 }
 

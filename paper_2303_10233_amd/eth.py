@@ -83,7 +83,7 @@ EXPORTED = [
 
 K_SADDLE_APPLY, K_CHEB_STEP, K_RESTRICT, K_PROLONG, K_MQ_CHEB_STEP, K_DOT, K_MINRES_V, K_MINRES_WX = range(8)
 KERNEL_NAMES = {
-    K_SADDLE_APPLY: "k_saddle_stokes", K_CHEB_STEP: "k_cheb_step", K_RESTRICT: "k_restrict",
+    K_SADDLE_APPLY: "k_saddle", K_CHEB_STEP: "k_cheb_step", K_RESTRICT: "k_restrict",
     K_PROLONG: "k_prolong_add", K_MQ_CHEB_STEP: "k_mq_cheb_fused", K_DOT: "k_dot",
     K_MINRES_V: "k_minres_v", K_MINRES_WX: "k_minres_wx",
 }

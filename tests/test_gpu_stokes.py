@@ -105,9 +105,14 @@ def test_assemble_rhs_matches_oracle(n, corner_mode):
         assert rel_err(B[k], s.rhs(gaussian_bumps(n, 1001 + k), lid_dirichlet(m, 1.5, corner_mode))) < 1e-13
 
 
-def _oracle_prec(s, velocity, mq, lambdas=None, mq_lo=0.01):
+def _mq_lo(n):
+    return min(0.01, 0.4 / n)
+
+
+def _oracle_prec(s, velocity, mq, lambdas=None, mq_lo=None):
     gmg_kw = dict(lambdas=lambdas) if lambdas is not None else None
-    return opc.StokesBlockDiag(s, velocity, mq, mq_lo=mq_lo, mq_steps=20, gmg_kw=gmg_kw)
+    lo = _mq_lo(s.mesh.n) if mq_lo is None else mq_lo
+    return opc.StokesBlockDiag(s, velocity, mq, mq_lo=lo, mq_steps=20, gmg_kw=gmg_kw)
 
 
 def _oracle_lambdas(n):
@@ -131,7 +136,7 @@ def test_preconditioner_matches_oracle(n, velocity, mq, prec, tol):
     lam = _oracle_lambdas(n) if velocity == "gmg" else None
     P = eth.Problem(n, nu=nu, velocity=eth.VEL_GMG if velocity == "gmg" else eth.VEL_EXACT,
                     mq=eth.MQ_DIAG if mq == "diag" else eth.MQ_CHEB_SGS, precision=prec,
-                    gmg_lambda=lam)
+                    gmg_lambda=lam, mq_cheb=(_mq_lo(n), 1.0))
     r = uniform_vector(m.N, 7 + n)
     r[: 2 * m.nv][s.vel_bnd] = 0.0
     z = _np(P.apply_preconditioner(_t(r)))
