@@ -381,3 +381,139 @@ def two_stage(system, b_full, eta=1e-6, c=10.0, restart=50, maxit=2000,
     info = dict(stage1=info1, stage2=info2, bnorm=bnorm, z_star=z_star, x_stage1=x0,
                 iterations=info1["iterations"] + info2["iterations"])
     return s.to_full(x, u_boundary=b_full[: 2 * m.nv]), info
+
+
+# -- inexact Oseen preconditioner pieces ---------------------------------------
+# The GPU path replaces the exact solves of M_1 and PCD by the iterations
+# below; the oracle implements the same algorithms so that preconditioner
+# applications can be compared directly.
+
+def inject_q2(field_fine, fine, coarse):
+    """Nodal values of a Q2 field at the coarse Q2 nodes (a subset of the fine
+    nodes): injection, component by component (layout [x | y])."""
+    r = fine.n // coarse.n
+    nc = coarse.nq
+    idx = (np.arange(nc)[:, None] * r * fine.nq + np.arange(nc)[None, :] * r).reshape(-1)
+    return np.concatenate([field_fine[: fine.nv][idx], field_fine[fine.nv:][idx]])
+
+
+def oseen_level_operator(fine_mesh, wind, nu):
+    """make_op for the GMG of F = nu A + N(w): on every level the wind is the
+    injection of the finest-level nodal wind."""
+    from .assemble import convection
+
+    def make(mesh):
+        w = wind if mesh.n == fine_mesh.n else inject_q2(wind, fine_mesh, mesh)
+        return nu * laplacian(mesh) + convection(mesh, w)
+    return make
+
+
+class GMGJacobi(GMG):
+    """V(nu1, nu2) cycle with damped Jacobi smoothing x <- x + omega D^{-1}(r - A x)
+    (suitable for the nonsymmetric convection-diffusion block F); exact solve on
+    the coarsest level."""
+
+    def __init__(self, mesh, make_op, omega=0.7, sweeps=2, coarse_n=32):
+        self.omega, self.sweeps = omega, sweeps
+        super().__init__(mesh, make_op, coarse_n=coarse_n, lambdas=[1.0] * 32)
+
+    def smooth(self, lvl, r, x):
+        A, dinv = self.A[lvl], self.dinv[lvl]
+        for _ in range(self.sweeps):
+            x = x + self.omega * dinv * (r - A @ x)
+        return x
+
+
+def q1_prolongation(fine, coarse):
+    """Bilinear interpolation of coarse Q1 functions at the fine Q1 nodes."""
+    r = fine.n // coarse.n
+    assert r == 2
+    nf, nc = fine.n + 1, coarse.n + 1
+
+    def p1(nf_, nc_):
+        P = np.zeros((nf_, nc_))
+        for i in range(nf_):
+            if i % 2 == 0:
+                P[i, i // 2] = 1.0
+            else:
+                P[i, i // 2] = P[i, i // 2 + 1] = 0.5
+        return sp.csr_matrix(P)
+    P1 = p1(nf, nc)
+    return sp.kron(P1, P1).tocsr()   # y index outer, x index inner
+
+
+def pressure_laplacian_Ap(mesh):
+    """A_p = B_1 diag(M_v)^{-1} B_1^T over the interior velocity nodes
+    (eq:discrete-commutator1x, with M the diagonal of the velocity mass)."""
+    from .assemble import System
+    s = System(mesh)
+    B1 = s.BI[: mesh.nk]
+    mv = s.Mv.diagonal()[s.vI]
+    return (B1 @ sp.diags(1.0 / mv) @ B1.T).tocsr()
+
+
+class ApGMG:
+    """A_p^+ r by one V(deg, deg) cycle of a Q1 geometric multigrid with
+    Chebyshev-Jacobi smoothing ([lo_frac, hi_frac] * lambda_max(D^{-1}A_p)),
+    bilinear transfers, re-discretised A_p on every level and the bordered
+    (pseudo-inverse) solve on the coarsest level; input and output are
+    projected onto the mean-zero vectors (A_p is singular with the constants)."""
+
+    def __init__(self, mesh, coarse_n=4, degree=2, lo_frac=0.3, hi_frac=1.1, lambdas=None):
+        self.ns = gmg_levels(mesh.n, coarse_n)
+        self.meshes = [Mesh(k, mesh.x0, mesh.x1, mesh.y0, mesh.y1) for k in self.ns]
+        self.A = [pressure_laplacian_Ap(m) for m in self.meshes]
+        self.P = [q1_prolongation(self.meshes[l], self.meshes[l + 1]) for l in range(len(self.ns) - 1)]
+        self.dinv = [1.0 / A.diagonal() for A in self.A]
+        if lambdas is None:
+            lambdas = [lambda_max_dinv(A) for A in self.A[:-1]]
+        self.lam = list(lambdas)
+        self.degree, self.lo_frac, self.hi_frac = degree, lo_frac, hi_frac
+        Ac = self.A[-1]
+        one = np.ones((Ac.shape[0], 1))
+        self.coarse = spla.splu(sp.bmat([[Ac, sp.csr_matrix(one)], [sp.csr_matrix(one.T), None]]).tocsc())
+
+    def smooth(self, lvl, r, x):
+        A, dinv, lam = self.A[lvl], self.dinv[lvl], self.lam[lvl]
+        return chebyshev(lambda v: A @ v, lambda v: dinv * v, r, x,
+                         self.lo_frac * lam, self.hi_frac * lam, self.degree)
+
+    def vcycle(self, lvl, r):
+        if lvl == len(self.A) - 1:
+            return self.coarse.solve(np.concatenate([r, [0.0]]))[:-1]
+        x = self.smooth(lvl, r, np.zeros_like(r))
+        rc = self.P[lvl].T @ (r - self.A[lvl] @ x)
+        x = x + self.P[lvl] @ self.vcycle(lvl + 1, rc)
+        return self.smooth(lvl, r, x)
+
+    def __call__(self, r):
+        r = r - r.mean()
+        z = self.vcycle(0, r)
+        return z - z.mean()
+
+
+class PCDStage1Inexact(PCDStage1):
+    """Stage-I PCD with the GPU's inexact pieces: F^{-1} by GMGJacobi,
+    Q_1^{-1} by `q1_steps` Chebyshev-Jacobi steps on Wathen's interval
+    [1/4, 9/4], A_p^+ by ApGMG."""
+
+    def __init__(self, system, velocity_solve, q1_steps=10, ap_kw=None):
+        super().__init__(system, velocity_solve=velocity_solve)
+        self.q1_steps = q1_steps
+        self.q1_dinv = 1.0 / self.Q1.diagonal()
+        self.apgmg = ApGMG(system.mesh, **(ap_kw or {}))
+
+    def q1_inv(self, r):
+        return chebyshev(lambda v: self.Q1 @ v, lambda v: self.q1_dinv * v, r, np.zeros_like(r),
+                         0.25, 2.25, self.q1_steps)
+
+    def schur_inv(self, rp):
+        return self.apgmg(self.F1 @ self.q1_inv(rp))
+
+
+def oseen_velocity_gmg(system, omega=0.7, sweeps=2, coarse_n=32):
+    """F^{-1} approximation for both velocity components of an Oseen system."""
+    g = GMGJacobi(system.mesh, oseen_level_operator(system.mesh, system.wind, system.nu),
+                  omega=omega, sweeps=sweeps, coarse_n=coarse_n)
+    m = g.A[0].shape[0]
+    return (lambda r: np.concatenate([g.vcycle(0, r[:m]), g.vcycle(0, r[m:])])), g
