@@ -74,8 +74,11 @@ typedef struct {
   int32_t mq_steps;          /* Chebyshev steps for ETH_MQ_CHEB_SGS (default 20)    */
   double mq_cheb_lo;         /* eigen-interval of M_SGS^{-1} M_Q (default min(0.01, 0.4/n)) */
   double mq_cheb_hi;         /*   (default 1, the SGS bound)                        */
-  int32_t gmg_coarse_n;      /* halve while n even and n > gmg_coarse_n (default 4) */
-  int32_t gmg_degree;        /* Chebyshev smoothing degree, pre and post (default 2)*/
+  int32_t gmg_coarse_n;      /* halve while n even and n > gmg_coarse_n (default 4;
+                                Oseen 32: coarse levels of the unstabilised F must
+                                keep a moderate cell Peclet number)                 */
+  int32_t gmg_degree;        /* smoothing steps pre and post (default 2): Chebyshev
+                                degree (Stokes) or damped-Jacobi sweeps (Oseen)     */
   double gmg_lo_frac;        /* smoother interval [lo_frac, hi_frac] * lambda_max    */
   double gmg_hi_frac;        /*   (defaults 0.3, 1.1)                               */
   const double* gmg_lambda;  /* host, optional: lambda_max(D^{-1}A) per smoothing
@@ -83,6 +86,10 @@ typedef struct {
   int32_t precision;         /* eth_precision: preconditioner in FP64 or FP32       */
   int32_t max_batch;         /* largest batch passed to any call (default 1)        */
   void* stream;              /* hipStream_t for every call (NULL: default stream)   */
+  /* Oseen (kind = ETH_OSEEN) preconditioners, Sec. 3 */
+  double gmg_omega;          /* damped-Jacobi weight of the F multigrid (0.7)       */
+  int32_t pcd_q1_steps;      /* Chebyshev-Jacobi steps for Q_1^{-1} in PCD (10)     */
+  int32_t gmres_restart;     /* largest FGMRES restart length, <= 63 (50)          */
 } eth_problem_desc;
 
 typedef struct {
@@ -131,18 +138,34 @@ int eth_assemble_rhs(eth_problem* p, const double* f_nodal, int64_t ld_f,
 int eth_apply_operator(eth_problem* p, int transpose, const double* x, double* y,
                        int64_t batch, int64_t ld);
 
-/* z = P^{-1} r: Stokes block-diagonal preconditioner diag(nu A~, M~_S/nu)
- * (eq:stokes_pre) with the bordered pressure solve of Sec. 2.2 (z_p is
- * orthogonal to k).  Boundary velocity entries of z are set to 0. */
+/* z = P^{-1} r.  Stokes: block-diagonal diag(nu A~, M~_S/nu) (eq:stokes_pre)
+ * with the bordered pressure solve of Sec. 2.2 (z_p orthogonal to k).
+ * Oseen: block upper-triangular M_1 = [F~, B^T; 0, -M~_Q/nu]
+ * (eq:nse-precon-ref): z_p = -nu M~_Q^+ r_p, z_u = F~^{-1}(r_u - B^T z_p).
+ * Boundary velocity entries of z are set to 0. */
 int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, double* z,
                              int64_t batch, int64_t ld);
 
 /* Solve K x = b (b from eth_assemble_rhs).  x receives the boundary data on
  * boundary rows, the Krylov solution elsewhere, the pressure canonicalised if
  * opts->canonicalize.  info: host array of `batch` entries, or NULL.
+ * Methods: ETH_MINRES (Stokes; alg:minres with P), ETH_FGMRES (Oseen, right
+ * preconditioned by M_1, restarted), ETH_TWO_STAGE (Oseen, Sec. 3.1: stage I
+ * FGMRES on the reduced system with PCD until ||r|| <= c*rtol*||b||, stage II
+ * FGMRES on the full system with M_1 from [u_1; q_1; 0] until rtol*||b||).
  * Returns the worst per-RHS status. */
 int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, double* x,
               int64_t batch, int64_t ld, eth_solve_info* info);
+
+/* Oseen only: the stage-I PCD preconditioner of the reduced Taylor-Hood
+ * system (Sec. 3.1, eq:reduced-system, eq:discrete-commutator1x):
+ * z_pk = -A_p^+ F_1 Q_1^{-1} r_pk, z_p0 = 0, z_u = F~^{-1}(r_u - B_1^T z_pk),
+ * with A_p = B_1 diag(M_v)^{-1} B_1^T; the p_0 part of r is ignored. */
+int eth_apply_pcd(eth_problem* p, const double* r, double* z, int64_t batch, int64_t ld);
+/* Oseen only: number of Q1 levels of the A_p multigrid inside PCD and its
+ * Chebyshev bounds lambda_max(D^{-1}A_p) per smoothing level (levels-1
+ * values); either pointer may be NULL */
+int eth_get_pcd_levels(const eth_problem* p, int32_t* levels, double* lambdas);
 
 /* Kernel timing for roofline reporting.  Launches `reps` times the kernel
  * `kernel` (ETH_K_*) exactly as one MINRES iteration launches it (same grid,

@@ -35,6 +35,15 @@ struct MinresScalars {
   double* hist;        // |eta|/gamma_1 per iteration (device, hist_len entries)
 };
 
+// Per right-hand side FGMRES record (restart length m <= 63).
+struct GmresScalars {
+  double beta, target, res, inv;   // ||r_0||, absolute tolerance, |g_{j+1}|, 1/h_{j+1,j}
+  int active;                      // Arnoldi steps of the current cycle still run
+  int update;                      // the cycle-end solution update is due
+  int converged, kend, iters, maxit, status, hist_len, m, pad;
+  double *H, *cs, *sn, *g, *y, *h1, *h2, *hist;   // device arrays of this RHS
+};
+
 struct ScaleState {
   double* out;
   double scale;

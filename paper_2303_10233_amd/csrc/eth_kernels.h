@@ -54,6 +54,8 @@ void launch_axpby(long long n, double a, const double* x, double b, double* y, l
 void launch_copy(long long n, const double* x, long long ldx, double* y, long long ldy,
                  int batch, hipStream_t st);
 void launch_fill(long long n, double v, double* y, long long ld, int batch, hipStream_t st);
+// y *= d pointwise on [0,n) (one vector)
+void launch_vmul(long long n, const double* d, double* y, hipStream_t st);
 // zero the boundary velocity rows of a full-layout vector
 void launch_zero_boundary(const Geo& g, double* y, long long ld, int batch, hipStream_t st);
 // x boundary rows <- b boundary rows
@@ -80,9 +82,12 @@ template <typename T>
 void launch_cheb_step(const Geo& g, const T* b, const T* x, T* xnew_io_prev, double alpha,
                       double beta, int has_prev, int nplanes, double* out64, long long ld64,
                       double out_scale, Gate gate, int batch, hipStream_t st);
+// b = r_u - sub_u (sub may be null), x = beta D^{-1} b (Laplacian diagonal)
 template <typename T>
 void launch_vcycle_entry(const Geo& g, const double* r, long long ld, T* b, T* x,
-                         double beta, int batch, Gate gate, hipStream_t st);
+                         double beta, int batch, Gate gate, hipStream_t st,
+                         const double* sub = nullptr);
+// xf == nullptr: bf already holds the fine residual
 template <typename T>
 void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* bc, T* xc,
                      double beta_c, int nplanes, int batch, Gate gate, hipStream_t st);
@@ -100,7 +105,7 @@ void launch_dense_solve(const Geo& g, const double* Ainv, int ni, const T* b, T*
 void launch_dense_laplacian(const Geo& g, double* A, int ni, hipStream_t st);
 void launch_gj_step(double* aug, int ni, int k, double* colbuf, double* rowbuf,
                     hipStream_t st);
-void launch_extract_inverse(const double* aug, int ni, double* Ainv, hipStream_t st);
+void launch_extract_inverse(const double* aug, int ni, double* Ainv, int symmetric, hipStream_t st);
 // setup helpers on one FP64 plane: mode 0: y = A x, mode 1: y = D^{-1} x
 // (interior nodes; boundary 0)
 void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStream_t st);
@@ -131,5 +136,62 @@ void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d,
 template <typename T>
 void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, int batch,
                            const double* coef, double scale, Gate gate, hipStream_t st);
+
+// ---------------- Oseen preconditioner pieces (k_oseen.hip) ------------------
+void launch_inject_wind(const Geo& gf, const Geo& gc, const double* wf, double* wc, hipStream_t st);
+void launch_cd_diag(const Geo& g, const double* wind, double nu, double* dF, hipStream_t st);
+void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* aug, int ni,
+                           hipStream_t st);
+// damped Jacobi step on F = nu A + N(w) (residual != 0: write b - F x instead)
+template <typename T>
+void launch_cd_step(const Geo& g, const double* wind, const double* dF, double nu, const T* b,
+                    const T* x, T* out, double omega, int residual, int nplanes, double* out64,
+                    long long ld64, double out_scale, Gate gate, hipStream_t st);
+template <typename T>
+void launch_q1mass_cheb(const Geo& g, const T* b, const T* x, T* xo, double alpha, double beta,
+                        int has_prev, int batch, Gate gate, hipStream_t st);
+template <typename T>
+void launch_f1_apply(const Geo& g, const double* wind, double nu, const T* x, T* y, int batch,
+                     Gate gate, hipStream_t st);
+// mode 0: out = A_p x; 1: Chebyshev step over out; 2: out = b - A_p x
+template <typename T>
+void launch_ap_op(const Geo& g, int mode, const T* b, const T* x, T* out, double alpha, double beta,
+                  int has_prev, const double* dAp, int batch, Gate gate, hipStream_t st);
+void launch_ap_diag(const Geo& g, double* dAp, hipStream_t st);
+template <typename T>
+void launch_q1_restrict(const Geo& gf, const Geo& gc, const T* rf, T* bc, T* xc, int batch, Gate gate,
+                        hipStream_t st);
+template <typename T>
+void launch_q1_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int batch, Gate gate,
+                           hipStream_t st);
+template <typename T>
+void launch_q1_sum(const Geo& g, const T* x, const RedCtx& rc, int batch, Gate gate, hipStream_t st);
+// out = scale * (x - sums/nk) on Q1 vectors (strides/offsets select full-layout p_k parts)
+template <typename TI, typename TO>
+void launch_q1_shift(const Geo& g, const TI* x, long long ldx, long long offx, TO* out, long long ldo,
+                     long long offo, const double* sums, double scale, int batch, Gate gate,
+                     hipStream_t st);
+void launch_unit_columns(double* cols, int ni, hipStream_t st);
+void launch_dense_ap_aug(const double* cols, int ni, double shift, double* aug, hipStream_t st);
+template <typename T>
+void launch_q1_dense_solve(const double* Ainv, int ni, const T* b, T* x, int batch, Gate gate,
+                           hipStream_t st);
+
+// ---------------- FGMRES (k_gmres.hip) ----------------------------------------
+int gmres_blocks(long long N);
+// partials: 64 * gmres_blocks(N) doubles per RHS; tickets: one per RHS
+void launch_gm_mdot(long long N, int nv, const double* V, const double* w, long long ld, int batch,
+                    double* partials, unsigned* tickets, GmresScalars* S, int which, hipStream_t st);
+void launch_gm_maxpy(long long N, int nv, const double* V, double* w, long long ld, int batch,
+                     const GmresScalars* S, int which, hipStream_t st);
+void launch_gm_norm_givens(long long N, int j, const double* w, long long ld, int batch, double* partials,
+                           unsigned* tickets, GmresScalars* S, hipStream_t st);
+void launch_gm_scale(long long N, double* v, long long ld, int batch, const GmresScalars* S, hipStream_t st);
+void launch_gm_beta(long long N, const double* v, long long ld, int batch, double* partials,
+                    unsigned* tickets, GmresScalars* S, hipStream_t st);
+void launch_gm_finish(long long N, const double* Z, double* x, long long ld, int batch, GmresScalars* S,
+                      hipStream_t st);
+void launch_gm_zero_range(double* x, long long ld, long long off, long long count, int batch,
+                          const GmresScalars* S, hipStream_t st);
 
 }  // namespace eth

@@ -111,6 +111,26 @@ struct Problem {
   double* h_red = nullptr;           // pinned
   double* ub = nullptr;              // Dirichlet data (2 nv)
 
+  // Oseen: velocity multigrid on F, PCD Q1 hierarchy, FGMRES workspace
+  double* wind0 = nullptr;                  // internal copy of the finest nodal wind
+  std::vector<double*> lwind, ldF;          // wind and diag(F) per velocity level
+  std::vector<Geo> qlv;                     // Q1 levels of the A_p multigrid
+  std::vector<double> qlam;
+  std::vector<std::vector<double>> qca, qcb;
+  std::vector<void*> qb, qx, qxo;
+  std::vector<double*> qdAp;
+  double* qAinv = nullptr;
+  int q_coarse_ni = 0;
+  void *pa = nullptr, *pb = nullptr, *pc = nullptr;   // PCD chain buffers [batch][n_k]
+  double* q1sums = nullptr;
+  std::vector<double> q1a, q1b;             // Chebyshev coefficients for Q_1 (Wathen interval)
+  int gm_m = 0;
+  double *gV = nullptr, *gZ = nullptr, *gArr = nullptr, *gpart = nullptr, *ghist = nullptr;
+  unsigned* gtick = nullptr;
+  GmresScalars* d_gm = nullptr;
+  GmresScalars* h_gm = nullptr;
+  std::vector<double> h_bnorm;
+
   // graph cache (keyed by batch); graphs are captured and replayed on the
   // internal stream gst, joined to the caller's stream with events
   hipGraphExec_t gexec = nullptr;
@@ -135,6 +155,7 @@ struct Problem {
     for (void* p : allocs) (void)hipFree(p);
     if (h_ms) (void)hipHostFree(h_ms);
     if (h_red) (void)hipHostFree(h_red);
+    if (h_gm) (void)hipHostFree(h_gm);
   }
 
   RedCtx red(int nblocks, int nvals, int epi, void* state, double* result = nullptr) {
@@ -171,8 +192,32 @@ struct Problem {
   template <typename T>
   void vcycle(const double* r, double* z, long long ld, int batch, Gate gate);
   template <typename T>
-  void mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate);
+  void mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
+  void mq_solve(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
   void precond(const double* r, double* z, long long ld, int batch, Gate gate);
+
+  // ------------------------------------------------------------ Oseen
+  void build_oseen_velocity();
+  void build_pcd();
+  void build_gmres();
+  double lanczos_generic(long long len, const std::function<void(const double*, double*)>& apply,
+                         const std::function<void(const double*, double*)>& dinv, int steps,
+                         bool mean_zero);
+  template <typename T>
+  void vcycle_F(const double* r, const double* sub, double* z, long long ld, int batch, Gate gate);
+  template <typename T>
+  void ap_vcycle(int batch, Gate gate);
+  template <typename T>
+  void pcd_schur(const double* r, double* z, long long ld, int batch, Gate gate);
+  // kind 1: M_1, kind 2: stage-I PCD; r, z internal vectors (stride ldw)
+  void precond_oseen(int kind, const double* r, double* z, int batch, Gate gate);
+  Gate gm_gate() const {
+    return Gate{&d_gm[0].active, (int)(sizeof(GmresScalars) / sizeof(int))};
+  }
+  void run_fgmres(int kind, bool reduced, const double* b, double* x, int batch, int m, int maxit,
+                  const std::vector<double>& atol);
+  int solve_oseen(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
+                  eth_solve_info* info);
 
   // ---------------------------------------------------------------- solve
   void minres_iteration(int batch, int parity);
@@ -202,7 +247,11 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.mq_cheb_lo <= 0.0) d.mq_cheb_lo = std::min(0.01, 0.4 / d.n);
   if (d.mq_cheb_hi <= 0.0) d.mq_cheb_hi = 1.0;
   if (!(d.mq_cheb_hi > d.mq_cheb_lo)) throw std::invalid_argument("mq interval empty");
-  if (d.gmg_coarse_n <= 0) d.gmg_coarse_n = 4;
+  if (d.gmg_coarse_n <= 0) d.gmg_coarse_n = oseen ? 32 : 4;
+  if (d.gmg_omega <= 0.0) d.gmg_omega = 0.7;
+  if (d.pcd_q1_steps <= 0) d.pcd_q1_steps = 10;
+  if (d.gmres_restart <= 0) d.gmres_restart = 50;
+  if (d.gmres_restart > 63) throw std::invalid_argument("gmres_restart must be <= 63");
   if (d.gmg_degree <= 0) d.gmg_degree = 2;
   if (d.gmg_lo_frac <= 0.0) d.gmg_lo_frac = 0.3;
   if (d.gmg_hi_frac <= 0.0) d.gmg_hi_frac = 1.1;
@@ -241,7 +290,16 @@ void Problem::setup(const eth_problem_desc& desc) {
   launch_dirichlet_lid(g, d.lid_u, d.corner_mode, ub, st);
   d_scale = alloc<ScaleState>(4);
 
-  build_velocity();
+  if (oseen) {
+    wind0 = alloc<double>(2 * (size_t)g.nv);
+    ETH_HIP(hipMemcpyAsync(wind0, d.wind, 2 * sizeof(double) * g.nv, hipMemcpyDeviceToDevice, st));
+    d.wind = wind0;
+    build_oseen_velocity();
+    build_pcd();
+    build_gmres();
+  } else {
+    build_velocity();
+  }
   build_pressure();
   ETH_HIP(hipStreamSynchronize(st));
 }
@@ -324,7 +382,7 @@ void Problem::build_velocity() {
     Ainv = alloc<double>((size_t)ni * ni);
     launch_dense_laplacian(gc, aug, ni, st);
     for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
-    launch_extract_inverse(aug, ni, Ainv, st);
+    launch_extract_inverse(aug, ni, Ainv, 1, st);
   }
   const int L = (int)lv.size();
   lam.assign(std::max(L - 1, 0), 0.0);
@@ -446,7 +504,7 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
 }
 
 template <typename T>
-void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate) {
+void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale) {
   T* rr = static_cast<T*>(mq_r);
   T* zz = static_cast<T*>(mq_z);
   T* tt = static_cast<T*>(mq_t);
@@ -473,22 +531,26 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
   }
   RedCtx rout = red(nbk, 1, EPI_SCALE, &d_scale[2]);
   launch_mq_kdot<T>(g, zz, np, 0, batch, rout, gate, st);
-  launch_mq_project_out<T>(g, zz, z, ld, batch, mq_coef2, d.nu, gate, st);
+  launch_mq_project_out<T>(g, zz, z, ld, batch, mq_coef2, scale, gate, st);
+}
+
+void Problem::mq_solve(const double* r, double* z, long long ld, int batch, Gate gate, double scale) {
+  if (d.mq_mode == ETH_MQ_DIAG) {
+    const long long np = (long long)g.nk + g.n0;
+    RedCtx rc = red(dot_blocks(np), 1, EPI_SCALE, &d_scale[0]);
+    launch_mq_diag_dot(g, r, ld, batch, rc, gate, st);
+    launch_mq_diag_apply(g, r, z, ld, batch, mq_coef, scale, gate, st);
+  } else if (mixed) {
+    mq_cheb<float>(r, z, ld, batch, gate, scale);
+  } else {
+    mq_cheb<double>(r, z, ld, batch, gate, scale);
+  }
 }
 
 void Problem::precond(const double* r, double* z, long long ld, int batch, Gate gate) {
   if (mixed) vcycle<float>(r, z, ld, batch, gate);
   else vcycle<double>(r, z, ld, batch, gate);
-  if (d.mq_mode == ETH_MQ_DIAG) {
-    const long long np = (long long)g.nk + g.n0;
-    RedCtx rc = red(dot_blocks(np), 1, EPI_SCALE, &d_scale[0]);
-    launch_mq_diag_dot(g, r, ld, batch, rc, gate, st);
-    launch_mq_diag_apply(g, r, z, ld, batch, mq_coef, d.nu, gate, st);
-  } else if (mixed) {
-    mq_cheb<float>(r, z, ld, batch, gate);
-  } else {
-    mq_cheb<double>(r, z, ld, batch, gate);
-  }
+  mq_solve(r, z, ld, batch, gate, d.nu);
 }
 
 // ---------------------------------------------------------------- MINRES
@@ -668,6 +730,475 @@ int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, i
   return worst;
 }
 
+// ============================================================================
+// Oseen (Sec. 3)
+// ============================================================================
+double Problem::lanczos_generic(long long len,
+                                const std::function<void(const double*, double*)>& apply,
+                                const std::function<void(const double*, double*)>& dinv, int steps,
+                                bool mean_zero) {
+  // PCG (Jacobi) on A x = b; its coefficients give the Lanczos tridiagonal of
+  // D^{-1}A, whose largest Ritz value is returned.
+  double* r = alloc<double>(len);
+  double* z = alloc<double>(len);
+  double* p = alloc<double>(len);
+  double* q = alloc<double>(len);
+  std::vector<double> h(len);
+  unsigned long long sd = 0x2545F4914F6CDD1DULL;
+  double mean = 0.0;
+  for (long long i = 0; i < len; ++i) {
+    sd = sd * 6364136223846793005ULL + 1442695040888963407ULL;
+    h[i] = (double)((sd >> 11) & ((1ULL << 53) - 1)) / (double)(1ULL << 53) - 0.5;
+    mean += h[i];
+  }
+  if (mean_zero)
+    for (auto& v : h) v -= mean / len;
+  ETH_HIP(hipMemcpyAsync(r, h.data(), len * sizeof(double), hipMemcpyHostToDevice, st));
+  auto dot = [&](const double* a, const double* b) {
+    RedCtx rc = red(dot_blocks(len), 1, EPI_NONE, nullptr, red_result);
+    launch_dot(len, a, b, 0, 1, rc, no_gate(), st);
+    ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double), hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    return h_red[0];
+  };
+  dinv(r, z);
+  launch_copy(len, z, 0, p, 0, 1, st);
+  double rz = dot(r, z);
+  std::vector<double> al, be;
+  for (int k = 0; k < steps; ++k) {
+    apply(p, q);
+    const double pq = dot(p, q);
+    if (!(pq > 0.0)) break;
+    const double alpha = rz / pq;
+    launch_axpby(len, -alpha, q, 1.0, r, 0, 1, st);
+    dinv(r, z);
+    const double rzn = dot(r, z);
+    const double beta = rzn / rz;
+    al.push_back(alpha);
+    be.push_back(beta);
+    launch_axpby(len, 1.0, z, beta, p, 0, 1, st);
+    rz = rzn;
+    if (!(rz > 0.0)) break;
+  }
+  const int m = (int)al.size();
+  std::vector<double> ta(m), tb(m > 0 ? m - 1 : 0);
+  for (int k = 0; k < m; ++k) {
+    ta[k] = 1.0 / al[k] + (k > 0 ? be[k - 1] / al[k - 1] : 0.0);
+    if (k + 1 < m) tb[k] = std::sqrt(be[k]) / al[k];
+  }
+  return m > 0 ? tridiag_max_eig(ta, tb) : 1.0;
+}
+
+void Problem::build_oseen_velocity() {
+  lv.clear();
+  lv.push_back(g);
+  if (d.velocity_mode == ETH_VEL_GMG) {
+    int n = d.n;
+    double h = g.h;
+    while (n % 2 == 0 && n > d.gmg_coarse_n) {
+      n /= 2;
+      h *= 2.0;
+      lv.push_back(make_geo(n, h));
+    }
+  }
+  const int L = (int)lv.size();
+  lwind.assign(L, nullptr);
+  ldF.assign(L, nullptr);
+  lwind[0] = wind0;
+  for (int l = 0; l < L; ++l) {
+    if (l > 0) {
+      lwind[l] = alloc<double>(2 * (size_t)lv[l].nv);
+      launch_inject_wind(g, lv[l], wind0, lwind[l], st);
+    }
+    ldF[l] = alloc<double>(lv[l].nv);
+    launch_cd_diag(lv[l], lwind[l], d.nu, ldF[l], st);
+  }
+  const Geo& gc = lv.back();
+  coarse_ni = (gc.nq - 2) * (gc.nq - 2);
+  if (coarse_ni > 4225)
+    throw std::runtime_error("unsupported:coarsest mesh too large for the dense solve");
+  dense_gbuf = alloc<double>((size_t)2 * coarse_ni * max_batch);
+  {
+    // dense inverse of the coarsest F (nonsymmetric, positive real: no pivoting)
+    const int ni = coarse_ni;
+    double* aug = alloc<double>((size_t)ni * 2 * ni);
+    double* col = alloc<double>(ni);
+    double* row = alloc<double>(2 * (size_t)ni);
+    Ainv = alloc<double>((size_t)ni * ni);
+    launch_dense_convdiff(gc, lwind[L - 1], d.nu, aug, ni, st);
+    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
+    launch_extract_inverse(aug, ni, Ainv, 0, st);
+  }
+  vb.assign(L, nullptr);
+  vx.assign(L, nullptr);
+  vxo.assign(L, nullptr);
+  const size_t es = mixed ? sizeof(float) : sizeof(double);
+  for (int l = 0; l < L; ++l) {
+    const size_t n = (size_t)2 * max_batch * lv[l].nv * es;
+    vb[l] = alloc<char>(n);
+    vx[l] = alloc<char>(n);
+    vxo[l] = alloc<char>(n);
+    ETH_HIP(hipMemsetAsync(vb[l], 0, n, st));
+    ETH_HIP(hipMemsetAsync(vx[l], 0, n, st));
+    ETH_HIP(hipMemsetAsync(vxo[l], 0, n, st));
+  }
+}
+
+void Problem::build_pcd() {
+  // Q1 hierarchy for A_p (halve while even and > 4)
+  qlv.clear();
+  qlv.push_back(g);
+  {
+    int n = d.n;
+    double h = g.h;
+    while (n % 2 == 0 && n > 4) {
+      n /= 2;
+      h *= 2.0;
+      qlv.push_back(make_geo(n, h));
+    }
+  }
+  const int LQ = (int)qlv.size();
+  const size_t es = mixed ? sizeof(float) : sizeof(double);
+  qb.assign(LQ, nullptr);
+  qx.assign(LQ, nullptr);
+  qxo.assign(LQ, nullptr);
+  qdAp.assign(LQ, nullptr);
+  for (int l = 0; l < LQ; ++l) {
+    const size_t n = (size_t)max_batch * qlv[l].nk * es;
+    qb[l] = alloc<char>(n);
+    qx[l] = alloc<char>(n);
+    qxo[l] = alloc<char>(n);
+    qdAp[l] = alloc<double>(qlv[l].nk);
+    launch_ap_diag(qlv[l], qdAp[l], st);
+  }
+  qlam.assign(std::max(LQ - 1, 0), 0.0);
+  qca.assign(qlam.size(), {});
+  qcb.assign(qlam.size(), {});
+  for (int l = 0; l + 1 < LQ; ++l) {
+    const Geo ql = qlv[l];
+    auto apply = [&, ql](const double* x, double* y) {
+      launch_ap_op<double>(ql, 0, nullptr, x, y, 0.0, 0.0, 0, nullptr, 1, no_gate(), st);
+    };
+    // Jacobi scaling z = D^{-1} r with D = diag(A_p)
+    double* inv = alloc<double>(ql.nk);
+    {
+      std::vector<double> hd(ql.nk);
+      ETH_HIP(hipMemcpyAsync(hd.data(), qdAp[l], ql.nk * sizeof(double), hipMemcpyDeviceToHost, st));
+      ETH_HIP(hipStreamSynchronize(st));
+      for (auto& v : hd) v = 1.0 / v;
+      ETH_HIP(hipMemcpyAsync(inv, hd.data(), ql.nk * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    auto dinv = [&, ql, inv](const double* x, double* y) {
+      launch_copy(ql.nk, x, 0, y, 0, 1, st);
+      launch_vmul(ql.nk, inv, y, st);
+    };
+    qlam[l] = lanczos_generic(ql.nk, apply, dinv, 30, true);
+    cheb_coefs(d.gmg_lo_frac * qlam[l], d.gmg_hi_frac * qlam[l], d.gmg_degree, qca[l], qcb[l]);
+  }
+  // coarsest: inverse of A_p + s 1 1^T (s = mean diagonal / n_k), SPD
+  {
+    const Geo& gc = qlv.back();
+    const int ni = gc.nk;
+    if (ni > 4225)
+      throw std::runtime_error("unsupported:coarsest Q1 mesh of the PCD multigrid too large");
+    q_coarse_ni = ni;
+    double* cols = alloc<double>((size_t)ni * ni);
+    double* acols = alloc<double>((size_t)ni * ni);
+    launch_unit_columns(cols, ni, st);
+    launch_ap_op<double>(gc, 0, nullptr, cols, acols, 0.0, 0.0, 0, nullptr, ni, no_gate(), st);
+    std::vector<double> hd(ni);
+    ETH_HIP(hipMemcpyAsync(hd.data(), qdAp.back(), ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    double mean = 0.0;
+    for (double v : hd) mean += v / ni;
+    double* aug = alloc<double>((size_t)ni * 2 * ni);
+    double* col = alloc<double>(ni);
+    double* row = alloc<double>(2 * (size_t)ni);
+    qAinv = alloc<double>((size_t)ni * ni);
+    launch_dense_ap_aug(acols, ni, mean / ni, aug, st);
+    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
+    launch_extract_inverse(aug, ni, qAinv, 1, st);
+  }
+  const size_t nq1 = (size_t)max_batch * g.nk * es;
+  pa = alloc<char>(nq1);
+  pb = alloc<char>(nq1);
+  pc = alloc<char>(nq1);
+  q1sums = alloc<double>(max_batch);
+  cheb_coefs(0.25, 2.25, d.pcd_q1_steps, q1a, q1b);   // Wathen's interval for Q1 mass
+}
+
+void Problem::build_gmres() {
+  gm_m = d.gmres_restart;
+  const size_t vec = (size_t)ldw * max_batch;
+  gV = alloc<double>(vec * (gm_m + 1));
+  gZ = alloc<double>(vec * gm_m);
+  const size_t per = (size_t)(gm_m + 1) * gm_m + 7 * 64;
+  gArr = alloc<double>(per * max_batch);
+  gpart = alloc<double>((size_t)64 * 256 * max_batch);
+  gtick = alloc<unsigned>(max_batch);
+  ETH_HIP(hipMemsetAsync(gtick, 0, sizeof(unsigned) * max_batch, st));
+  ghist = alloc<double>((size_t)hist_len * max_batch);
+  d_gm = alloc<GmresScalars>(max_batch);
+  ETH_HIP(hipHostMalloc((void**)&h_gm, sizeof(GmresScalars) * max_batch, hipHostMallocDefault));
+  h_bnorm.assign(max_batch, 0.0);
+}
+
+template <typename T>
+void Problem::vcycle_F(const double* r, const double* sub, double* z, long long ld, int batch,
+                       Gate gate) {
+  const int L = (int)lv.size();
+  std::vector<T*> b(L), x(L), xo(L);
+  for (int l = 0; l < L; ++l) {
+    b[l] = static_cast<T*>(vb[l]);
+    x[l] = static_cast<T*>(vx[l]);
+    xo[l] = static_cast<T*>(vxo[l]);
+  }
+  const int np = 2 * batch, deg = d.gmg_degree;
+  const double om = d.gmg_omega;
+  launch_vcycle_entry<T>(lv[0], r, ld, b[0], x[0], 0.0, batch, gate, st, sub);   // x = 0
+  for (int l = 0; l + 1 < L; ++l) {
+    for (int k = 0; k < deg; ++k) {
+      launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np, nullptr, 0, 0.0,
+                        gate, st);
+      std::swap(x[l], xo[l]);
+    }
+    launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 1, np, nullptr, 0, 0.0,
+                      gate, st);
+    launch_restrict<T>(lv[l], lv[l + 1], xo[l], nullptr, b[l + 1], x[l + 1], 0.0, np, batch, gate, st);
+  }
+  launch_dense_solve<T>(lv[L - 1], Ainv, coarse_ni, b[L - 1], L == 1 ? nullptr : x[L - 1], np,
+                        L == 1 ? z : nullptr, ld, 1.0, nullptr, 0, dense_gbuf, batch, gate, st);
+  if (L == 1) {
+    launch_zero_boundary(lv[0], z, ld, batch, st);
+    return;
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    launch_prolong_add<T>(lv[l], lv[l + 1], x[l + 1], x[l], np, batch, gate, st);
+    for (int k = 0; k < deg; ++k) {
+      const bool last = (l == 0 && k == deg - 1);
+      launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np,
+                        last ? z : nullptr, ld, 1.0, gate, st);
+      if (!last) std::swap(x[l], xo[l]);
+    }
+  }
+}
+
+// A_p^+ on qb[0] -> qx[0] (one V-cycle; both input and output mean-projected
+// by the caller)
+template <typename T>
+void Problem::ap_vcycle(int batch, Gate gate) {
+  const int LQ = (int)qlv.size();
+  std::vector<T*> b(LQ), x(LQ), xo(LQ);
+  for (int l = 0; l < LQ; ++l) {
+    b[l] = static_cast<T*>(qb[l]);
+    x[l] = static_cast<T*>(qx[l]);
+    xo[l] = static_cast<T*>(qxo[l]);
+  }
+  const int deg = d.gmg_degree;
+  for (int l = 0; l + 1 < LQ; ++l) {
+    for (int k = 0; k < deg; ++k) {
+      launch_ap_op<T>(qlv[l], 1, b[l], x[l], xo[l], qca[l][k], qcb[l][k], k == 0 ? 0 : 1, qdAp[l],
+                      batch, gate, st);
+      std::swap(x[l], xo[l]);
+    }
+    launch_ap_op<T>(qlv[l], 2, b[l], x[l], xo[l], 0.0, 0.0, 0, qdAp[l], batch, gate, st);
+    launch_q1_restrict<T>(qlv[l], qlv[l + 1], xo[l], b[l + 1], x[l + 1], batch, gate, st);
+  }
+  launch_q1_dense_solve<T>(qAinv, q_coarse_ni, b[LQ - 1], x[LQ - 1], batch, gate, st);
+  for (int l = LQ - 2; l >= 0; --l) {
+    launch_q1_prolong_add<T>(qlv[l], qlv[l + 1], x[l + 1], x[l], batch, gate, st);
+    for (int k = 0; k < deg; ++k) {
+      launch_ap_op<T>(qlv[l], 1, b[l], x[l], xo[l], qca[l][k], qcb[l][k], k == 0 ? 0 : 1, qdAp[l],
+                      batch, gate, st);
+      std::swap(x[l], xo[l]);
+    }
+  }
+  // the result must end in qx[0]
+  if (x[0] != static_cast<T*>(qx[0]))
+    launch_q1_shift<T, T>(qlv[0], x[0], qlv[0].nk, 0, static_cast<T*>(qx[0]), qlv[0].nk, 0, nullptr, 1.0,
+                          batch, gate, st);
+}
+
+// z_pk = -A_p^+ F_1 Q_1^{-1} r_pk, z_p0 = 0
+template <typename T>
+void Problem::pcd_schur(const double* r, double* z, long long ld, int batch, Gate gate) {
+  T* A = static_cast<T*>(pa);
+  T* B = static_cast<T*>(pb);
+  T* C = static_cast<T*>(pc);
+  const long long nk = g.nk;
+  launch_q1_shift<double, T>(g, r, ld, g.off_pk(), A, nk, 0, nullptr, 1.0, batch, gate, st);
+  // Q_1^{-1}: Chebyshev-Jacobi on [1/4, 9/4]
+  T* cur = B;
+  T* oth = C;
+  launch_q1mass_cheb<T>(g, A, nullptr, cur, 0.0, q1b[0], 0, batch, gate, st);
+  for (int k = 1; k < d.pcd_q1_steps; ++k) {
+    launch_q1mass_cheb<T>(g, A, cur, oth, q1a[k], q1b[k], k == 1 ? 2 : 1, batch, gate, st);
+    std::swap(cur, oth);
+  }
+  // F_1 q
+  launch_f1_apply<T>(g, wind0, d.nu, cur, A, batch, gate, st);
+  // A_p^+ with mean projection on input and output
+  RedCtx rs = red(dot_blocks(nk), 1, EPI_NONE, nullptr, q1sums);
+  launch_q1_sum<T>(g, A, rs, batch, gate, st);
+  launch_q1_shift<T, T>(g, A, nk, 0, static_cast<T*>(qb[0]), nk, 0, q1sums, 1.0, batch, gate, st);
+  launch_q1_shift<T, T>(g, A, nk, 0, static_cast<T*>(qx[0]), nk, 0, nullptr, 0.0, batch, gate, st);
+  ap_vcycle<T>(batch, gate);
+  launch_q1_sum<T>(g, static_cast<T*>(qx[0]), rs, batch, gate, st);
+  launch_q1_shift<T, double>(g, static_cast<T*>(qx[0]), nk, 0, z, ld, g.off_pk(), q1sums, -1.0, batch,
+                             gate, st);
+}
+
+void Problem::precond_oseen(int kind, const double* r, double* z, int batch, Gate gate) {
+  const GmresScalars* gs = (gate.p == gm_gate().p) ? d_gm : nullptr;
+  if (kind == 2) {
+    if (mixed) pcd_schur<float>(r, z, ldw, batch, gate);
+    else pcd_schur<double>(r, z, ldw, batch, gate);
+    launch_gm_zero_range(z, ldw, g.off_p0(), g.n0, batch, gs, st);
+  } else {
+    mq_solve(r, z, ldw, batch, gate, -d.nu);
+  }
+  // z_u = F~^{-1}(r_u - B^T z_p): B^T z_p from the Stokes kernel with nu = 0
+  launch_gm_zero_range(z, ldw, 0, 2LL * g.nv, batch, gs, st);
+  launch_apply_stokes(g, 0.0, z, ky, ldw, batch, gate, nullptr, st);
+  if (mixed) vcycle_F<float>(r, ky, z, ldw, batch, gate);
+  else vcycle_F<double>(r, ky, z, ldw, batch, gate);
+}
+
+// Restarted FGMRES on the internal vectors b, x (stride ldw); kind selects
+// the preconditioner (1: M_1, 2: PCD), reduced the stage-I operator (the p_0
+// rows of K x are dropped).  atol: absolute tolerance per RHS.
+void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int batch, int m,
+                         int maxit, const std::vector<double>& atol) {
+  const size_t per = (size_t)(gm_m + 1) * gm_m + 7 * 64;
+  for (int r = 0; r < batch; ++r) {
+    GmresScalars& G = h_gm[r];
+    std::memset(&G, 0, sizeof(G));
+    G.target = atol[r];
+    G.m = m;
+    G.maxit = maxit;
+    double* base = gArr + per * r;
+    G.H = base;
+    G.cs = base + (size_t)(gm_m + 1) * gm_m;
+    G.sn = G.cs + 64;
+    G.g = G.sn + 64;
+    G.y = G.g + 64;
+    G.h1 = G.y + 64;
+    G.h2 = G.h1 + 64;
+    G.hist = ghist + (size_t)hist_len * r;
+    G.hist_len = hist_len;
+  }
+  ETH_HIP(hipMemcpyAsync(d_gm, h_gm, sizeof(GmresScalars) * batch, hipMemcpyHostToDevice, st));
+  const Gate gate = gm_gate();
+  const long long N = g.N;
+  auto V = [&](int i) { return gV + (size_t)i * batch * ldw; };
+  auto Z = [&](int i) { return gZ + (size_t)i * batch * ldw; };
+  auto op = [&](const double* in, double* out, Gate gt) {
+    apply_op(0, in, out, ldw, batch, gt, nullptr);
+    if (reduced) launch_gm_zero_range(out, ldw, g.off_p0(), g.n0, batch, gt.p ? d_gm : nullptr, st);
+  };
+  for (int cycle = 0; cycle < 100000; ++cycle) {
+    op(x, ky, no_gate());
+    launch_residual_init(g, b, ky, V(0), ldw, batch, st);
+    launch_gm_beta(N, V(0), ldw, batch, gpart, gtick, d_gm, st);
+    launch_gm_scale(N, V(0), ldw, batch, d_gm, st);
+    for (int j = 0; j < m; ++j) {
+      precond_oseen(kind, V(j), Z(j), batch, gate);
+      op(Z(j), V(j + 1), gate);
+      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, gtick, d_gm, 0, st);
+      launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 0, st);
+      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, gtick, d_gm, 1, st);
+      launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 1, st);
+      launch_gm_norm_givens(N, j, V(j + 1), ldw, batch, gpart, gtick, d_gm, st);
+      launch_gm_scale(N, V(j + 1), ldw, batch, d_gm, st);
+      if ((j + 1) % 8 == 0 && j + 1 < m) {
+        ETH_HIP(hipMemcpyAsync(h_gm, d_gm, sizeof(GmresScalars) * batch, hipMemcpyDeviceToHost, st));
+        ETH_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int r = 0; r < batch; ++r) any = any || h_gm[r].active;
+        if (!any) break;
+      }
+    }
+    launch_gm_finish(N, gZ, x, ldw, batch, d_gm, st);
+    ETH_HIP(hipMemcpyAsync(h_gm, d_gm, sizeof(GmresScalars) * batch, hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    bool more = false;
+    for (int r = 0; r < batch; ++r) {
+      const GmresScalars& G = h_gm[r];
+      if (!G.converged && G.status >= 0 && G.iters < maxit) more = true;
+    }
+    if (!more) {
+      // confirm with the true residual of the final iterate
+      op(x, ky, no_gate());
+      launch_residual_init(g, b, ky, V(0), ldw, batch, st);
+      launch_gm_beta(N, V(0), ldw, batch, gpart, gtick, d_gm, st);
+      ETH_HIP(hipMemcpyAsync(h_gm, d_gm, sizeof(GmresScalars) * batch, hipMemcpyDeviceToHost, st));
+      ETH_HIP(hipStreamSynchronize(st));
+      break;
+    }
+  }
+}
+
+int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
+                         eth_solve_info* info) {
+  const double eta = o.rtol > 0 ? o.rtol : 1e-6;
+  const int maxit = o.maxit > 0 ? o.maxit : 1000;
+  const int m = o.restart > 0 ? o.restart : gm_m;
+  if (m > gm_m) throw std::invalid_argument("restart exceeds the gmres_restart of the problem");
+  const double c = o.c_factor > 0 ? o.c_factor : 10.0;
+  launch_copy(g.N, b, ld, kb, ldw, batch, st);
+  launch_zero_boundary(g, kb, ldw, batch, st);
+  RedCtx rn = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
+  launch_dot(g.N, kb, kb, ldw, batch, rn, no_gate(), st);
+  ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+  if (o.use_x0) {
+    launch_copy(g.N, x, ld, kx, ldw, batch, st);
+    launch_zero_boundary(g, kx, ldw, batch, st);
+  } else {
+    launch_fill(g.N, 0.0, kx, ldw, batch, st);
+  }
+  ETH_HIP(hipStreamSynchronize(st));
+  std::vector<double> bn(batch);
+  for (int r = 0; r < batch; ++r) bn[r] = std::sqrt(h_red[r]);
+  std::vector<int> it1(batch, 0);
+  if (o.method == ETH_TWO_STAGE) {
+    // stage I: reduced system [F B_1^T; B_1 0], RHS without the P0 rows
+    launch_copy(g.N, kb, ldw, kv[0], ldw, batch, st);
+    launch_gm_zero_range(kv[0], ldw, g.off_p0(), g.n0, batch, nullptr, st);
+    launch_gm_zero_range(kx, ldw, g.off_p0(), g.n0, batch, nullptr, st);
+    std::vector<double> a1(batch);
+    for (int r = 0; r < batch; ++r) a1[r] = c * eta * bn[r];
+    run_fgmres(2, true, kv[0], kx, batch, m, maxit, a1);
+    for (int r = 0; r < batch; ++r) it1[r] = h_gm[r].iters;
+  }
+  std::vector<double> a2(batch);
+  for (int r = 0; r < batch; ++r) a2[r] = eta * bn[r];
+  run_fgmres(1, false, kb, kx, batch, m, std::max(1, maxit), a2);
+  // output
+  launch_copy(g.N, kx, ldw, x, ld, batch, st);
+  launch_copy_boundary(g, b, x, ld, batch, st);
+  if (o.canonicalize) {
+    launch_pressure_sums(g, x, ld, batch, red_partials, red_tickets, red_result, st);
+    launch_pressure_shift(g, x, ld, batch, red_result, st);
+  }
+  ETH_HIP(hipStreamSynchronize(st));
+  int worst = ETH_OK;
+  for (int r = 0; r < batch; ++r) {
+    const GmresScalars& G = h_gm[r];
+    int status = G.status;
+    if (status == kStOK && !G.converged) status = ETH_WMAXIT;
+    if (info) {
+      info[r].status = status;
+      info[r].iterations = G.iters + it1[r];
+      info[r].stage1_iterations = it1[r];
+      info[r].rel_residual_est = bn[r] > 0 ? G.beta / bn[r] : 0.0;
+      info[r].rel_residual_true = bn[r] > 0 ? G.beta / bn[r] : 0.0;
+    }
+    if (status < 0) worst = std::min(worst, status);
+    else if (worst >= 0) worst = std::max(worst, status);
+  }
+  return worst;
+}
+
 }  // namespace eth
 
 // =============================================================================
@@ -786,13 +1317,42 @@ int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, dou
   if (!p || !r || !z) return fail(p, ETH_EINVAL, "NULL argument");
   if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
   if (r == z) return fail(p, ETH_EINVAL, "r and z must not alias");
-  (void)transpose;   // the Stokes preconditioner is symmetric
-  if (p->impl.oseen) return fail(p, ETH_EUNSUPPORTED, "Oseen preconditioner not available yet");
+  if (transpose) return fail(p, ETH_EUNSUPPORTED, "transposed preconditioner not available");
   return guarded(p, [&] {
     Problem& P = p->impl;
-    P.precond(r, z, ld, (int)batch, eth::no_gate());
+    if (P.oseen) {
+      // the Oseen pieces work on the internal vector stride
+      eth::launch_copy(P.g.N, r, ld, P.kv[0], P.ldw, (int)batch, P.st);
+      P.precond_oseen(1, P.kv[0], P.kz[0], (int)batch, eth::no_gate());
+      eth::launch_copy(P.g.N, P.kz[0], P.ldw, z, ld, (int)batch, P.st);
+    } else {
+      P.precond(r, z, ld, (int)batch, eth::no_gate());
+    }
     return ETH_OK;
   });
+}
+
+int eth_apply_pcd(eth_problem* p, const double* r, double* z, int64_t batch, int64_t ld) {
+  if (!p || !r || !z) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  if (r == z) return fail(p, ETH_EINVAL, "r and z must not alias");
+  if (!p->impl.oseen) return fail(p, ETH_EUNSUPPORTED, "PCD is built for Oseen problems only");
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    eth::launch_copy(P.g.N, r, ld, P.kv[0], P.ldw, (int)batch, P.st);
+    P.precond_oseen(2, P.kv[0], P.kz[0], (int)batch, eth::no_gate());
+    eth::launch_copy(P.g.N, P.kz[0], P.ldw, z, ld, (int)batch, P.st);
+    return ETH_OK;
+  });
+}
+
+int eth_get_pcd_levels(const eth_problem* p, int32_t* levels, double* lambdas) {
+  if (!p) return ETH_EINVAL;
+  if (!p->impl.oseen) return ETH_EUNSUPPORTED;
+  if (levels) *levels = (int32_t)p->impl.qlv.size();
+  if (lambdas)
+    for (size_t i = 0; i < p->impl.qlam.size(); ++i) lambdas[i] = p->impl.qlam[i];
+  return ETH_OK;
 }
 
 int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, double* x,
@@ -801,11 +1361,19 @@ int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, doubl
   if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
   if (b == x) return fail(p, ETH_EINVAL, "b and x must not alias");
   eth_solve_opts o{};
-  if (opts) o = *opts;
-  else o.canonicalize = 1;
-  if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
-  if (p->impl.oseen) return fail(p, ETH_EUNSUPPORTED, "Oseen solves not available yet");
+  if (opts) {
+    o = *opts;
+  } else {
+    o.canonicalize = 1;
+    o.method = p->impl.oseen ? ETH_TWO_STAGE : ETH_MINRES;
+  }
   if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
+  if (p->impl.oseen) {
+    if (o.method != ETH_FGMRES && o.method != ETH_TWO_STAGE)
+      return fail(p, ETH_EUNSUPPORTED, "Oseen systems are solved by FGMRES or TWO_STAGE");
+    return guarded(p, [&] { return p->impl.solve_oseen(o, b, x, (int)batch, ld, info); });
+  }
+  if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
   return guarded(p, [&] { return p->impl.solve_minres(o, b, x, (int)batch, ld, info); });
 }
 

@@ -104,8 +104,9 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
 
 // b = r_u (velocity part of an FP64 vector), x = beta D^{-1} b
 template <typename T>
-__global__ void k_vcycle_entry(Geo g, const double* __restrict__ r, long long ld,
-                               T* __restrict__ b, T* __restrict__ x, double beta, Gate gate) {
+__global__ void k_vcycle_entry(Geo g, const double* __restrict__ r, const double* __restrict__ sub,
+                               long long ld, T* __restrict__ b, T* __restrict__ x, double beta,
+                               Gate gate) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int rhs = blockIdx.y;
   if (gate.off(rhs)) return;
@@ -118,7 +119,9 @@ __global__ void k_vcycle_entry(Geo g, const double* __restrict__ r, long long ld
     x[o] = T(0);
     return;
   }
-  const T bv = (T)r[(long long)rhs * ld + k];
+  const double rv = sub ? r[(long long)rhs * ld + k] - sub[(long long)rhs * ld + k]
+                        : r[(long long)rhs * ld + k];
+  const T bv = (T)rv;
   b[o] = bv;
   x[o] = (T)(beta * (double)bv * 90.0 / diag90(I & 1, J & 1));
 }
@@ -134,8 +137,9 @@ constexpr int CT = 16;                  // coarse tile side
 constexpr int RF = 2 * CT + 5;          // fine residual patch side
 constexpr int XF = RF + 4;              // fine iterate patch side
 
-// Coarse rhs b_c = P^T (b_f - A_f x_f); x_c = beta_c D_c^{-1} b_c
-template <typename T>
+// Coarse rhs b_c = P^T (b_f - A_f x_f); x_c = beta_c D_c^{-1} b_c.
+// RES_GIVEN: bf already holds the fine residual (xf unused), b_c = P^T bf.
+template <typename T, bool RES_GIVEN>
 __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __restrict__ bf,
                                                  const T* __restrict__ xf, T* __restrict__ bc,
                                                  T* __restrict__ xc, double beta_c, Gate gate) {
@@ -148,19 +152,22 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   const int C0x = blockIdx.x * CT, C0y = blockIdx.y * CT;
   const int F0x = 2 * C0x - 3, F0y = 2 * C0y - 3;     // residual patch origin
   const int tid = threadIdx.x;
-  for (int k = tid; k < XF * XF; k += NT) {
-    const int lx = k % XF, ly = k / XF;
-    const int I = F0x - 2 + lx, J = F0y - 2 + ly;
-    sx[k] = (I >= 0 && I <= topf && J >= 0 && J <= topf) ? xf[pf + (long long)J * nqf + I] : T(0);
+  if constexpr (!RES_GIVEN) {
+    for (int k = tid; k < XF * XF; k += NT) {
+      const int lx = k % XF, ly = k / XF;
+      const int I = F0x - 2 + lx, J = F0y - 2 + ly;
+      sx[k] = (I >= 0 && I <= topf && J >= 0 && J <= topf) ? xf[pf + (long long)J * nqf + I] : T(0);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int k = tid; k < RF * RF; k += NT) {
     const int lx = k % RF, ly = k / RF;
     const int I = F0x + lx, J = F0y + ly;
     double r = 0.0;
-    if (I > 0 && I < topf && J > 0 && J < topf)
-      r = (double)bf[pf + (long long)J * nqf + I] -
-          lap90<T, XF>(sx, lx + 2, ly + 2, I & 1, J & 1) / 90.0;
+    if (I > 0 && I < topf && J > 0 && J < topf) {
+      r = (double)bf[pf + (long long)J * nqf + I];
+      if constexpr (!RES_GIVEN) r -= lap90<T, XF>(sx, lx + 2, ly + 2, I & 1, J & 1) / 90.0;
+    }
     sr[k] = r;
   }
   __syncthreads();
@@ -344,12 +351,14 @@ __global__ void k_gj_update(double* __restrict__ aug, int ni, int k, const doubl
   else aug[t] -= col[i] * row[j];
 }
 
-__global__ void k_extract_inverse(const double* __restrict__ aug, int ni, double* __restrict__ Ainv) {
+__global__ void k_extract_inverse(const double* __restrict__ aug, int ni, double* __restrict__ Ainv,
+                                  int symmetric) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)ni * ni) return;
   const int i = (int)(t / ni), j = (int)(t % ni);
-  // symmetrise: the inverse of the symmetric Laplacian is symmetric
-  Ainv[t] = 0.5 * (aug[(long long)i * 2 * ni + ni + j] + aug[(long long)j * 2 * ni + ni + i]);
+  // the inverse of a symmetric matrix is symmetrised against rounding
+  Ainv[t] = symmetric ? 0.5 * (aug[(long long)i * 2 * ni + ni + j] + aug[(long long)j * 2 * ni + ni + i])
+                      : aug[(long long)i * 2 * ni + ni + j];
 }
 
 // mode 0: y = A x, mode 1: y = D^{-1} x, on one FP64 plane (interior nodes; boundary 0)
@@ -393,10 +402,10 @@ void launch_cheb_step(const Geo& g, const T* b, const T* x, T* xo, double alpha,
 
 template <typename T>
 void launch_vcycle_entry(const Geo& g, const double* r, long long ld, T* b, T* x, double beta,
-                         int batch, Gate gate, hipStream_t st) {
+                         int batch, Gate gate, hipStream_t st, const double* sub) {
   const long long n = 2LL * g.nv;
   hipLaunchKernelGGL(k_vcycle_entry<T>, dim3((unsigned)((n + 255) / 256), batch), dim3(256), 0, st,
-                     g, r, ld, b, x, beta, gate);
+                     g, r, sub, ld, b, x, beta, gate);
   ETH_LAUNCH_CHECK();
 }
 
@@ -405,7 +414,10 @@ void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* 
                      double beta_c, int nplanes, int batch, Gate gate, hipStream_t st) {
   (void)batch;
   dim3 grid((gc.nq + CT - 1) / CT, (gc.nq + CT - 1) / CT, nplanes);
-  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate);
+  if (xf)
+    hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate);
+  else
+    hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate);
   ETH_LAUNCH_CHECK();
 }
 
@@ -458,10 +470,10 @@ void launch_gj_step(double* aug, int ni, int k, double* colbuf, double* rowbuf, 
   ETH_LAUNCH_CHECK();
 }
 
-void launch_extract_inverse(const double* aug, int ni, double* Ainv, hipStream_t st) {
+void launch_extract_inverse(const double* aug, int ni, double* Ainv, int symmetric, hipStream_t st) {
   const long long n = (long long)ni * ni;
   hipLaunchKernelGGL(k_extract_inverse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, aug, ni,
-                     Ainv);
+                     Ainv, symmetric);
   ETH_LAUNCH_CHECK();
 }
 
@@ -476,7 +488,7 @@ void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStre
   template void launch_cheb_step<T>(const Geo&, const T*, const T*, T*, double, double, int, int, \
                                     double*, long long, double, Gate, int, hipStream_t);         \
   template void launch_vcycle_entry<T>(const Geo&, const double*, long long, T*, T*, double, int, \
-                                       Gate, hipStream_t);                                       \
+                                       Gate, hipStream_t, const double*);                        \
   template void launch_restrict<T>(const Geo&, const Geo&, const T*, const T*, T*, T*, double,    \
                                    int, int, Gate, hipStream_t);                                 \
   template void launch_prolong_add<T>(const Geo&, const Geo&, const T*, T*, int, int, Gate,       \

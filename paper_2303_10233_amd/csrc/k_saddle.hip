@@ -16,6 +16,7 @@
 // nodes (2ex+i, 2ey+j), i,j in {0,1}, of both components, the Q1 node
 // (ex, ey) and the element (ex, ey).  A 32 x 8 block of cells stages its
 // velocity patch (halo 2 nodes), Q1 patch (halo 1) and P0 patch in LDS.
+#include "eth_fem.h"
 #include "eth_kernels.h"
 #include "eth_reduce.h"
 
@@ -27,14 +28,6 @@ constexpr int VX = 2 * TX + 4, VY = 2 * TY + 4;
 constexpr int PX = TX + 2, PY = TY + 2;
 constexpr int EX = TX + 1, EY = TY + 1;
 
-__host__ __device__ constexpr int K1(int p, int o) {
-  return p == 0 ? (o == 0 ? 14 : (o == -1 || o == 1) ? -8 : 1)
-                : (o == 0 ? 16 : (o == -1 || o == 1) ? -8 : 0);
-}
-__host__ __device__ constexpr int M1(int p, int o) {
-  return p == 0 ? (o == 0 ? 8 : (o == -1 || o == 1) ? 2 : -1)
-                : (o == 0 ? 16 : (o == -1 || o == 1) ? 2 : 0);
-}
 // 6 * G(c - ex) for a velocity node of parity i (dc in -1..1)
 __host__ __device__ constexpr int G6(int i, int dc) {
   return i == 0 ? (dc == -1 ? 1 : dc == 0 ? 0 : -1) : (dc == -1 ? 0 : dc == 0 ? 4 : -4);
@@ -49,131 +42,6 @@ __host__ __device__ constexpr int g1(int i, int de) {
 }
 __host__ __device__ constexpr int m6(int j, int df) {
   return j == 0 ? 1 : (df == -1 ? 0 : 4);
-}
-
-// 4-point Gauss-Legendre rule on [0,1] and the 1-D Q2 basis / derivative
-// values at its points: GB[q][i] = phi_i(xi_q), GD[q][i] = phi_i'(xi_q).
-constexpr int NG = 4;
-__device__ __forceinline__ void gauss_tables(double* W, double (*GB)[3], double (*GD)[3]) {
-  const double t1 = 0.33998104358485626480, t2 = 0.86113631159405257522;
-  const double w1 = 0.65214515486254614263, w2 = 0.34785484513745385737;
-  const double xq[NG] = {0.5 * (1 - t2), 0.5 * (1 - t1), 0.5 * (1 + t1), 0.5 * (1 + t2)};
-  W[0] = 0.5 * w2;
-  W[1] = 0.5 * w1;
-  W[2] = 0.5 * w1;
-  W[3] = 0.5 * w2;
-#pragma unroll
-  for (int q = 0; q < NG; ++q) {
-    const double t = xq[q];
-    GB[q][0] = (1 - t) * (1 - 2 * t);
-    GB[q][1] = 4 * t * (1 - t);
-    GB[q][2] = t * (2 * t - 1);
-    GD[q][0] = 4 * t - 3;
-    GD[q][1] = 4 - 8 * t;
-    GD[q][2] = 4 * t - 1;
-  }
-}
-
-// Convection on one element, both velocity components, 4x4 Gauss: exact for
-// any Q2 wind (the integrand w phi_i d(phi_j) has degree <= 6 per direction).
-//   TRANS = false: out_i = int (w . grad u_h) phi_i       (N u)
-//   TRANS = true : out_i = int (w . grad phi_i) u_h       (N^T u)
-// u[c][j][i], w[c][j][i]: local nodal values (x index i); out[c][j][i].
-template <bool TRANS>
-__device__ inline void element_convection(const double (*u)[3][3], const double (*w)[3][3], double h,
-                                          double (*out)[3][3]) {
-  double W[NG], GB[NG][3], GD[NG][3];
-  gauss_tables(W, GB, GD);
-  double wq[2][NG][NG];   // wind at the Gauss points [comp][qy][qx]
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int qy = 0; qy < NG; ++qy)
-#pragma unroll
-      for (int qx = 0; qx < NG; ++qx) {
-        double a = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          double t = 0.0;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) t += GB[qx][i] * w[c][j][i];
-          a += GB[qy][j] * t;
-        }
-        wq[c][qy][qx] = a;
-      }
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    if constexpr (!TRANS) {
-      double cv[NG][NG];
-#pragma unroll
-      for (int qy = 0; qy < NG; ++qy)
-#pragma unroll
-        for (int qx = 0; qx < NG; ++qx) {
-          double ux = 0.0, uy = 0.0;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            double tx = 0.0, ty = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-              tx += GD[qx][i] * u[c][j][i];
-              ty += GB[qx][i] * u[c][j][i];
-            }
-            ux += GB[qy][j] * tx;
-            uy += GD[qy][j] * ty;
-          }
-          cv[qy][qx] = W[qx] * W[qy] * (wq[0][qy][qx] * ux + wq[1][qy][qx] * uy);
-        }
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          double a = 0.0;
-#pragma unroll
-          for (int qy = 0; qy < NG; ++qy) {
-            double t = 0.0;
-#pragma unroll
-            for (int qx = 0; qx < NG; ++qx) t += GB[qx][i] * cv[qy][qx];
-            a += GB[qy][j] * t;
-          }
-          out[c][j][i] = h * a;
-        }
-    } else {
-      double gx[NG][NG], gy[NG][NG];
-#pragma unroll
-      for (int qy = 0; qy < NG; ++qy)
-#pragma unroll
-        for (int qx = 0; qx < NG; ++qx) {
-          double uv = 0.0;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            double t = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) t += GB[qx][i] * u[c][j][i];
-            uv += GB[qy][j] * t;
-          }
-          const double wu = W[qx] * W[qy] * uv;
-          gx[qy][qx] = wq[0][qy][qx] * wu;
-          gy[qy][qx] = wq[1][qy][qx] * wu;
-        }
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          double a = 0.0;
-#pragma unroll
-          for (int qy = 0; qy < NG; ++qy) {
-            double tx = 0.0, ty = 0.0;
-#pragma unroll
-            for (int qx = 0; qx < NG; ++qx) {
-              tx += GD[qx][i] * gx[qy][qx];
-              ty += GB[qx][i] * gy[qy][qx];
-            }
-            a += GB[qy][j] * tx + GD[qy][j] * ty;
-          }
-          out[c][j][i] = h * a;
-        }
-    }
-  }
 }
 
 // MODE 0: operator apply (boundary velocity masked, boundary rows 0).

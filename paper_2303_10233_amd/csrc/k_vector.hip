@@ -39,6 +39,11 @@ __global__ void k_copy(long long n, const double* __restrict__ x, long long ldx,
   y[(long long)blockIdx.y * ldy + i] = x[(long long)blockIdx.y * ldx + i];
 }
 
+__global__ void k_vmul(long long n, const double* __restrict__ d, double* __restrict__ y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] *= d[i];
+}
+
 __global__ void k_fill(long long n, double v, double* __restrict__ y, long long ld) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -175,6 +180,11 @@ void launch_copy(long long n, const double* x, long long ldx, double* y, long lo
 
 void launch_fill(long long n, double v, double* y, long long ld, int batch, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256), batch), dim3(256), 0, st, n, v, y, ld);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_vmul(long long n, const double* d, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_vmul, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d, y);
   ETH_LAUNCH_CHECK();
 }
 

@@ -45,6 +45,9 @@ class ProblemDesc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("max_batch", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("gmg_omega", ctypes.c_double),
+        ("pcd_q1_steps", ctypes.c_int32),
+        ("gmres_restart", ctypes.c_int32),
     ]
 
 
@@ -111,6 +114,10 @@ def load_library(path=LIB_PATH):
     lib.eth_apply_operator.restype = ctypes.c_int
     lib.eth_apply_preconditioner.argtypes = [P, ctypes.c_int, P, P, i64, i64]
     lib.eth_apply_preconditioner.restype = ctypes.c_int
+    lib.eth_apply_pcd.argtypes = [P, P, P, i64, i64]
+    lib.eth_apply_pcd.restype = ctypes.c_int
+    lib.eth_get_pcd_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.eth_get_pcd_levels.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
     lib.eth_solve.restype = ctypes.c_int
     lib.eth_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, i64,
@@ -168,7 +175,8 @@ class Problem:
     def __init__(self, n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
                  kind=STOKES, wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0,
                  mq_cheb=(0.0, 0.0), gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0),
-                 gmg_lambda=None, precision=FP64, max_batch=1, device=None):
+                 gmg_lambda=None, precision=FP64, max_batch=1, device=None, gmg_omega=0.0,
+                 pcd_q1_steps=0, gmres_restart=0):
         self.device = torch.device("cuda" if device is None else device)
         L = lib()
         d = ProblemDesc()
@@ -193,6 +201,10 @@ class Problem:
             d.gmg_lambda = self._lam
         d.precision = precision
         d.max_batch = max_batch
+        d.gmg_omega = gmg_omega
+        d.pcd_q1_steps = pcd_q1_steps
+        d.gmres_restart = gmres_restart
+        self.kind = kind
         with torch.cuda.device(self.device):
             d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         h = ctypes.c_void_p()
@@ -226,6 +238,16 @@ class Problem:
         _check(L.eth_get_levels(self._h, None, lam), self._h)
         return lv.value, [lam[i] for i in range(max(lv.value - 1, 0))]
 
+    def pcd_levels(self):
+        """Oseen: (Q1 levels of the A_p multigrid, lambda_max(D^{-1}A_p) per
+        smoothing level)."""
+        L = lib()
+        lv = ctypes.c_int32()
+        _check(L.eth_get_pcd_levels(self._h, ctypes.byref(lv), None), self._h)
+        lam = (ctypes.c_double * max(lv.value, 1))()
+        _check(L.eth_get_pcd_levels(self._h, None, lam), self._h)
+        return lv.value, [lam[i] for i in range(max(lv.value - 1, 0))]
+
     def empty(self, batch=1):
         shape = (self.N,) if batch == 1 else (batch, self.N)
         return torch.empty(shape, dtype=torch.float64, device=self.device)
@@ -255,6 +277,14 @@ class Problem:
                self._h)
         return z
 
+    def apply_pcd(self, r):
+        """Oseen: the stage-I PCD preconditioner applied to r (see eth.h)."""
+        z = torch.empty_like(r)
+        r2, B, ld = _as_batch(r, self.N)
+        z2, _, _ = _as_batch(z, self.N)
+        _check(lib().eth_apply_pcd(self._h, _ptr(r2), _ptr(z2), B, ld), self._h)
+        return z
+
     def profile_kernel(self, kernel, reps=50, batch=1):
         """(average ms per launch, algorithmic bytes per launch) of one kernel
         of the MINRES iteration, timed with HIP events on the problem's stream."""
@@ -264,8 +294,11 @@ class Problem:
                                         ctypes.byref(by)), self._h)
         return ms.value, by.value
 
-    def solve(self, b, rtol=1e-6, maxit=1000, x0=None, method=MINRES, restart=50, c_factor=10.0,
+    def solve(self, b, rtol=1e-6, maxit=1000, x0=None, method=None, restart=0, c_factor=10.0,
               canonicalize=True, use_graph=False, true_residual=False, out=None):
+        """method None: MINRES for Stokes, TWO_STAGE for Oseen."""
+        if method is None:
+            method = TWO_STAGE if self.kind == OSEEN else MINRES
         x = out if out is not None else torch.empty_like(b)
         if x0 is not None:
             x.copy_(x0)
