@@ -141,7 +141,11 @@ int eth_apply_operator(eth_problem* p, int transpose, const double* x, double* y
 /* z = P^{-1} r.  Stokes: block-diagonal diag(nu A~, M~_S/nu) (eq:stokes_pre)
  * with the bordered pressure solve of Sec. 2.2 (z_p orthogonal to k).
  * Oseen: block upper-triangular M_1 = [F~, B^T; 0, -M~_Q/nu]
- * (eq:nse-precon-ref): z_p = -nu M~_Q^+ r_p, z_u = F~^{-1}(r_u - B^T z_p).
+ * (eq:nse-precon-ref): z_p = -nu M~_Q^+ r_p, z_u = F~^{-1}(r_u - B^T z_p);
+ * transpose = 1 gives the same preconditioner for the transposed system
+ * K^T = [F^T B^T; B 0], i.e. with F~^{-T} (one multigrid cycle on F^T) in
+ * place of F~^{-1} -- the preconditioner of eth_solve_adjoint.  Stokes: the
+ * preconditioner is symmetric and transpose is ignored.
  * Boundary velocity entries of z are set to 0. */
 int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, double* z,
                              int64_t batch, int64_t ld);
@@ -160,12 +164,48 @@ int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, doubl
 /* Oseen only: the stage-I PCD preconditioner of the reduced Taylor-Hood
  * system (Sec. 3.1, eq:reduced-system, eq:discrete-commutator1x):
  * z_pk = -A_p^+ F_1 Q_1^{-1} r_pk, z_p0 = 0, z_u = F~^{-1}(r_u - B_1^T z_pk),
- * with A_p = B_1 diag(M_v)^{-1} B_1^T; the p_0 part of r is ignored. */
-int eth_apply_pcd(eth_problem* p, const double* r, double* z, int64_t batch, int64_t ld);
+ * with A_p = B_1 diag(M_v)^{-1} B_1^T; the p_0 part of r is ignored.
+ * transpose = 1: the same construction for the transposed reduced system
+ * [F^T B_1^T; B_1 0] (stage I of the adjoint): the Schur complement S^T is
+ * approximated by A_p F_1^{-T} Q_1, so z_pk = -Q_1^{-1} F_1^T A_p^+ r_pk and
+ * z_u = F~^{-T}(r_u - B_1^T z_pk). */
+int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int64_t batch,
+                  int64_t ld);
 /* Oseen only: number of Q1 levels of the A_p multigrid inside PCD and its
  * Chebyshev bounds lambda_max(D^{-1}A_p) per smoothing level (levels-1
  * values); either pointer may be NULL */
 int eth_get_pcd_levels(const eth_problem* p, int32_t* levels, double* lambdas);
+
+/* Discrete adjoint (K^T lambda = g) of a solve, for gradients of
+ * J(x(f, nu)) through the lifted system (eq:saddle_point, eq:oseen-system).
+ * g: device, batch x ld, dJ/dx on the full layout; its boundary velocity
+ * rows are ignored and the means of its p_k and p_0 blocks are removed
+ * first (that component lies in null(K) and has no adjoint).  lambda
+ * receives the adjoint with zero boundary velocity rows, the pressure
+ * canonicalised if opts->canonicalize.  Stokes: MINRES with the forward
+ * preconditioner (K is symmetric).  Oseen: K^T = [F^T B^T; B 0] has the
+ * structure of K with F^T for F, and is solved like K: ETH_TWO_STAGE (the
+ * default) runs stage I with the transposed PCD (eth_apply_pcd, transpose =
+ * 1) and stage II with [F~^T B^T; 0 -M~_Q/nu]; ETH_FGMRES only the latter.
+ * opts NULL: defaults with canonicalize = 1.  Returns the worst per-RHS
+ * status. */
+int eth_solve_adjoint(eth_problem* p, const eth_solve_opts* opts, const double* g,
+                      double* lambda, int64_t batch, int64_t ld, eth_solve_info* info);
+/* dJ/df = M_v lambda~ on all 2(2n+1)^2 nodal forces, lambda~ = the velocity of
+ * lambda with its boundary rows zeroed (b_u = (M_v f)_I).  dJdf: device,
+ * batch x ld_f (ld_f >= 2(2n+1)^2 when batch > 1). */
+int eth_grad_forcing(eth_problem* p, const double* lambda, int64_t ld, double* dJdf,
+                     int64_t ld_f, int64_t batch);
+/* dJ/dnu = -lambda_u^T (A u)_I per RHS, u = the full velocity of x (boundary
+ * values included: K depends on nu through nu A_II, b through -nu A_IB u_B).
+ * lambda and x: batch x ld; dJdnu: device, batch doubles. */
+int eth_grad_viscosity(eth_problem* p, const double* lambda, const double* x, double* dJdnu,
+                       int64_t batch, int64_t ld);
+/* J = 1/2 (u - u_t)^T M_v (u - u_t) over all velocity nodes, u and u_t the
+ * velocities of x and x_target (batch x ld).  J: device, batch doubles.
+ * grad (device, batch x ld, or NULL): dJ/dx = [M_v (u - u_t); 0]. */
+int eth_misfit(eth_problem* p, const double* x, const double* x_target, double* J,
+               double* grad, int64_t batch, int64_t ld);
 
 /* Kernel timing for roofline reporting.  Launches `reps` times the kernel
  * `kernel` (ETH_K_*) exactly as one MINRES iteration launches it (same grid,

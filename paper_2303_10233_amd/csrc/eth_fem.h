@@ -142,18 +142,20 @@ __device__ inline void element_convection(const double (*u)[3][3], const double 
 }
 
 
-// Convection on one element for ONE velocity component: out_i = int (w . grad u_h) phi_i
-template <typename TW>
+// Convection on one element for ONE velocity component:
+//   TRANS = false: out_i = int (w . grad u_h) phi_i   (N u)
+//   TRANS = true : out_i = int (w . grad phi_i) u_h   (N^T u)
+template <typename TW, bool TRANS = false>
 __device__ inline void element_convection1(const double (*u)[3], const TW (*w)[3][3], double h,
                                            double (*out)[3]) {
   double W[NG], GB[NG][3], GD[NG][3];
   gauss_tables(W, GB, GD);
-  double cv[NG][NG];
+  double c0[NG][NG], c1[NG][NG];
 #pragma unroll
   for (int qy = 0; qy < NG; ++qy)
 #pragma unroll
     for (int qx = 0; qx < NG; ++qx) {
-      double wx = 0.0, wy = 0.0, ux = 0.0, uy = 0.0;
+      double wx = 0.0, wy = 0.0, ux = 0.0, uy = 0.0, uv = 0.0;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         double tw0 = 0.0, tw1 = 0.0, tx = 0.0, ty = 0.0;
@@ -161,15 +163,24 @@ __device__ inline void element_convection1(const double (*u)[3], const TW (*w)[3
         for (int i = 0; i < 3; ++i) {
           tw0 += GB[qx][i] * (double)w[0][j][i];
           tw1 += GB[qx][i] * (double)w[1][j][i];
-          tx += GD[qx][i] * u[j][i];
+          if constexpr (!TRANS) tx += GD[qx][i] * u[j][i];
           ty += GB[qx][i] * u[j][i];
         }
         wx += GB[qy][j] * tw0;
         wy += GB[qy][j] * tw1;
-        ux += GB[qy][j] * tx;
-        uy += GD[qy][j] * ty;
+        if constexpr (!TRANS) {
+          ux += GB[qy][j] * tx;
+          uy += GD[qy][j] * ty;
+        } else {
+          uv += GB[qy][j] * ty;
+        }
       }
-      cv[qy][qx] = W[qx] * W[qy] * (wx * ux + wy * uy);
+      if constexpr (!TRANS) {
+        c0[qy][qx] = W[qx] * W[qy] * (wx * ux + wy * uy);
+      } else {
+        c0[qy][qx] = W[qx] * W[qy] * wx * uv;   // pairs with d(phi_i)/dx
+        c1[qy][qx] = W[qx] * W[qy] * wy * uv;   // pairs with d(phi_i)/dy
+      }
     }
 #pragma unroll
   for (int j = 0; j < 3; ++j)
@@ -178,10 +189,20 @@ __device__ inline void element_convection1(const double (*u)[3], const TW (*w)[3
       double a = 0.0;
 #pragma unroll
       for (int qy = 0; qy < NG; ++qy) {
-        double t = 0.0;
+        if constexpr (!TRANS) {
+          double t = 0.0;
 #pragma unroll
-        for (int qx = 0; qx < NG; ++qx) t += GB[qx][i] * cv[qy][qx];
-        a += GB[qy][j] * t;
+          for (int qx = 0; qx < NG; ++qx) t += GB[qx][i] * c0[qy][qx];
+          a += GB[qy][j] * t;
+        } else {
+          double tx = 0.0, ty = 0.0;
+#pragma unroll
+          for (int qx = 0; qx < NG; ++qx) {
+            tx += GD[qx][i] * c0[qy][qx];
+            ty += GB[qx][i] * c1[qy][qx];
+          }
+          a += GB[qy][j] * tx + GD[qy][j] * ty;
+        }
       }
       out[j][i] = h * a;
     }

@@ -142,17 +142,20 @@ void launch_inject_wind(const Geo& gf, const Geo& gc, const double* wf, double* 
 void launch_cd_diag(const Geo& g, const double* wind, double nu, double* dF, hipStream_t st);
 void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* aug, int ni,
                            hipStream_t st);
-// damped Jacobi step on F = nu A + N(w) (residual != 0: write b - F x instead)
+// damped Jacobi step on F = nu A + N(w) (residual != 0: write b - F x instead;
+// transpose != 0: F^T)
 template <typename T>
 void launch_cd_step(const Geo& g, const double* wind, const double* dF, double nu, const T* b,
                     const T* x, T* out, double omega, int residual, int nplanes, double* out64,
-                    long long ld64, double out_scale, Gate gate, hipStream_t st);
+                    long long ld64, double out_scale, Gate gate, hipStream_t st, int transpose = 0);
+// at = a^T for a dense ni x ni matrix
+void launch_transpose(const double* a, int ni, double* at, hipStream_t st);
 template <typename T>
 void launch_q1mass_cheb(const Geo& g, const T* b, const T* x, T* xo, double alpha, double beta,
                         int has_prev, int batch, Gate gate, hipStream_t st);
 template <typename T>
 void launch_f1_apply(const Geo& g, const double* wind, double nu, const T* x, T* y, int batch,
-                     Gate gate, hipStream_t st);
+                     Gate gate, hipStream_t st, int transpose = 0);
 // mode 0: out = A_p x; 1: Chebyshev step over out; 2: out = b - A_p x
 template <typename T>
 void launch_ap_op(const Geo& g, int mode, const T* b, const T* x, T* out, double alpha, double beta,
@@ -176,6 +179,19 @@ void launch_dense_ap_aug(const double* cols, int ni, double shift, double* aug, 
 template <typename T>
 void launch_q1_dense_solve(const double* Ainv, int ni, const T* b, T* x, int batch, Gate gate,
                            hipStream_t st);
+
+// ---------------- adjoint (k_adjoint.hip) -------------------------------------
+// blocks of one RHS in the adjoint reductions (partials needed per value)
+int adjoint_blocks(const Geo& g);
+// e = x - xt (xt may be null; boundary nodes of e zeroed when mask_boundary),
+// y = M_v e on all 2 nv velocity nodes (y may be null), and, with
+// half_energy, result[rhs] = e^T M_v e / 2
+void launch_velocity_mass(const Geo& g, const double* x, long long ldx, const double* xt, long long ldt,
+                          int mask_boundary, double* y, long long ldy, const RedCtx* half_energy, int batch,
+                          hipStream_t st);
+// result[rhs] = -lambda_u^T (A u)_I with u the full velocity of x
+void launch_grad_viscosity(const Geo& g, const double* lam, long long ldl, const double* x, long long ldx,
+                           const RedCtx& rc, int batch, hipStream_t st);
 
 // ---------------- FGMRES (k_gmres.hip) ----------------------------------------
 int gmres_blocks(long long N);

@@ -10,6 +10,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/eth.h"
@@ -85,6 +86,7 @@ struct Problem {
   std::vector<double> lam;           // lambda_max(D^-1 A) per smoothing level
   std::vector<std::vector<double>> ca, cb;   // Chebyshev coefficients per level
   double* Ainv = nullptr;            // dense inverse on the coarsest level
+  double* AinvT = nullptr;           // its transpose (Oseen: coarse solve with F^T)
   int coarse_ni = 0;
   double* dense_gbuf = nullptr;
   std::vector<void*> vb, vx, vxo;    // per-level plane buffers (T)
@@ -204,25 +206,31 @@ struct Problem {
                          const std::function<void(const double*, double*)>& dinv, int steps,
                          bool mean_zero);
   template <typename T>
-  void vcycle_F(const double* r, const double* sub, double* z, long long ld, int batch, Gate gate);
+  void vcycle_F(const double* r, const double* sub, double* z, long long ld, int batch, Gate gate,
+                bool trans);
   template <typename T>
   void ap_vcycle(int batch, Gate gate);
   template <typename T>
-  void pcd_schur(const double* r, double* z, long long ld, int batch, Gate gate);
-  // kind 1: M_1, kind 2: stage-I PCD; r, z internal vectors (stride ldw)
+  void pcd_schur(const double* r, double* z, long long ld, int batch, Gate gate, bool trans);
+  // kind 1: M_1, kind 2: stage-I PCD; kinds 3 and 4: the same for the
+  // transposed system [F^T B^T; B 0] (velocity block F^T, Schur complement
+  // S^T); r, z internal vectors (stride ldw)
   void precond_oseen(int kind, const double* r, double* z, int batch, Gate gate);
   Gate gm_gate() const {
     return Gate{&d_gm[0].active, (int)(sizeof(GmresScalars) / sizeof(int))};
   }
   void run_fgmres(int kind, bool reduced, const double* b, double* x, int batch, int m, int maxit,
-                  const std::vector<double>& atol);
+                  const std::vector<double>& atol, bool transpose = false);
   int solve_oseen(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
-                  eth_solve_info* info);
+                  eth_solve_info* info, bool adjoint = false);
 
   // ---------------------------------------------------------------- solve
   void minres_iteration(int batch, int parity);
   int solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
-                   eth_solve_info* info);
+                   eth_solve_info* info, bool adjoint = false);
+  // Krylov RHS kb from b: boundary rows zeroed; for the adjoint also the
+  // pressure block means removed (the part of g in null(K) has no adjoint)
+  void load_rhs(const double* b, long long ld, int batch, bool adjoint);
   void run_iterations(int batch, int count, bool use_graph);
 };
 
@@ -279,7 +287,8 @@ void Problem::setup(const eth_problem_desc& desc) {
   ETH_HIP(hipHostMalloc((void**)&h_ms, sizeof(MinresScalars) * max_batch, hipHostMallocDefault));
   hist_len = 4097;
   d_hist = alloc<double>((size_t)hist_len * max_batch);
-  const int maxblocks = std::max(std::max(dot_blocks(g.N), saddle_blocks(g)), 4096);
+  const int maxblocks =
+      std::max(std::max(std::max(dot_blocks(g.N), saddle_blocks(g)), adjoint_blocks(g)), 4096);
   red_partials = alloc<double>((size_t)maxblocks * kMaxRedVals * max_batch);
   red_tickets = alloc<unsigned>(max_batch);
   red_result = alloc<double>((size_t)kMaxRedVals * max_batch);
@@ -614,13 +623,21 @@ void Problem::run_iterations(int batch, int count, bool use_graph) {
   ETH_HIP(hipStreamWaitEvent(caller, ev_join, 0));
 }
 
-int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch,
-                          long long ld, eth_solve_info* info) {
-  const double tol = o.rtol > 0 ? o.rtol : 1e-8;
-  const int maxit = o.maxit > 0 ? o.maxit : 1000;
+void Problem::load_rhs(const double* b, long long ld, int batch, bool adjoint) {
   // Krylov RHS: b with the boundary rows zeroed (they carry Dirichlet data)
   launch_copy(g.N, b, ld, kb, ldw, batch, st);
   launch_zero_boundary(g, kb, ldw, batch, st);
+  if (adjoint) {
+    launch_pressure_sums(g, kb, ldw, batch, red_partials, red_tickets, red_result, st);
+    launch_pressure_shift(g, kb, ldw, batch, red_result, st);
+  }
+}
+
+int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch,
+                          long long ld, eth_solve_info* info, bool adjoint) {
+  const double tol = o.rtol > 0 ? o.rtol : 1e-8;
+  const int maxit = o.maxit > 0 ? o.maxit : 1000;
+  load_rhs(b, ld, batch, adjoint);
   // initial residual v1 = b - K x0
   if (o.use_x0) {
     launch_copy(g.N, x, ld, kx, ldw, batch, st);
@@ -690,14 +707,14 @@ int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, i
   }
   // output: x = interior solution + Dirichlet rows, canonical pressure
   launch_copy(g.N, kx, ldw, x, ld, batch, st);
-  launch_copy_boundary(g, b, x, ld, batch, st);
+  if (!adjoint) launch_copy_boundary(g, b, x, ld, batch, st);
   if (o.canonicalize) {
     launch_pressure_sums(g, x, ld, batch, red_partials, red_tickets, red_result, st);
     launch_pressure_shift(g, x, ld, batch, red_result, st);
   }
   std::vector<double> true_rel(batch, -1.0);
   if (o.true_residual) {
-    launch_apply_stokes(g, d.nu, x, ky, ldw, batch, no_gate(), nullptr, st);
+    launch_apply_stokes(g, d.nu, kx, ky, ldw, batch, no_gate(), nullptr, st);
     // ky <- kb - K x (boundary rows zero); reuse kv[1] for the residual
     launch_residual_init(g, kb, ky, kv[1], ldw, batch, st);
     RedCtx r1 = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
@@ -828,6 +845,8 @@ void Problem::build_oseen_velocity() {
     launch_dense_convdiff(gc, lwind[L - 1], d.nu, aug, ni, st);
     for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
     launch_extract_inverse(aug, ni, Ainv, 0, st);
+    AinvT = alloc<double>((size_t)ni * ni);
+    launch_transpose(Ainv, ni, AinvT, st);
   }
   vb.assign(L, nullptr);
   vx.assign(L, nullptr);
@@ -945,7 +964,8 @@ void Problem::build_gmres() {
 
 template <typename T>
 void Problem::vcycle_F(const double* r, const double* sub, double* z, long long ld, int batch,
-                       Gate gate) {
+                       Gate gate, bool trans) {
+  const int tr = trans ? 1 : 0;
   const int L = (int)lv.size();
   std::vector<T*> b(L), x(L), xo(L);
   for (int l = 0; l < L; ++l) {
@@ -959,14 +979,14 @@ void Problem::vcycle_F(const double* r, const double* sub, double* z, long long 
   for (int l = 0; l + 1 < L; ++l) {
     for (int k = 0; k < deg; ++k) {
       launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np, nullptr, 0, 0.0,
-                        gate, st);
+                        gate, st, tr);
       std::swap(x[l], xo[l]);
     }
     launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 1, np, nullptr, 0, 0.0,
-                      gate, st);
+                      gate, st, tr);
     launch_restrict<T>(lv[l], lv[l + 1], xo[l], nullptr, b[l + 1], x[l + 1], 0.0, np, batch, gate, st);
   }
-  launch_dense_solve<T>(lv[L - 1], Ainv, coarse_ni, b[L - 1], L == 1 ? nullptr : x[L - 1], np,
+  launch_dense_solve<T>(lv[L - 1], trans ? AinvT : Ainv, coarse_ni, b[L - 1], L == 1 ? nullptr : x[L - 1], np,
                         L == 1 ? z : nullptr, ld, 1.0, nullptr, 0, dense_gbuf, batch, gate, st);
   if (L == 1) {
     launch_zero_boundary(lv[0], z, ld, batch, st);
@@ -977,7 +997,7 @@ void Problem::vcycle_F(const double* r, const double* sub, double* z, long long 
     for (int k = 0; k < deg; ++k) {
       const bool last = (l == 0 && k == deg - 1);
       launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np,
-                        last ? z : nullptr, ld, 1.0, gate, st);
+                        last ? z : nullptr, ld, 1.0, gate, st, tr);
       if (!last) std::swap(x[l], xo[l]);
     }
   }
@@ -1019,40 +1039,55 @@ void Problem::ap_vcycle(int batch, Gate gate) {
                           batch, gate, st);
 }
 
-// z_pk = -A_p^+ F_1 Q_1^{-1} r_pk, z_p0 = 0
+// z_pk = -A_p^+ F_1 Q_1^{-1} r_pk (trans: the Schur approximation of the
+// transposed system, z_pk = -Q_1^{-1} F_1^T A_p^+ r_pk); z_p0 is left alone
 template <typename T>
-void Problem::pcd_schur(const double* r, double* z, long long ld, int batch, Gate gate) {
+void Problem::pcd_schur(const double* r, double* z, long long ld, int batch, Gate gate, bool trans) {
   T* A = static_cast<T*>(pa);
   T* B = static_cast<T*>(pb);
   T* C = static_cast<T*>(pc);
+  T* qb0 = static_cast<T*>(qb[0]);
+  T* qx0 = static_cast<T*>(qx[0]);
   const long long nk = g.nk;
-  launch_q1_shift<double, T>(g, r, ld, g.off_pk(), A, nk, 0, nullptr, 1.0, batch, gate, st);
-  // Q_1^{-1}: Chebyshev-Jacobi on [1/4, 9/4]
-  T* cur = B;
-  T* oth = C;
-  launch_q1mass_cheb<T>(g, A, nullptr, cur, 0.0, q1b[0], 0, batch, gate, st);
-  for (int k = 1; k < d.pcd_q1_steps; ++k) {
-    launch_q1mass_cheb<T>(g, A, cur, oth, q1a[k], q1b[k], k == 1 ? 2 : 1, batch, gate, st);
-    std::swap(cur, oth);
-  }
-  // F_1 q
-  launch_f1_apply<T>(g, wind0, d.nu, cur, A, batch, gate, st);
-  // A_p^+ with mean projection on input and output
   RedCtx rs = red(dot_blocks(nk), 1, EPI_NONE, nullptr, q1sums);
-  launch_q1_sum<T>(g, A, rs, batch, gate, st);
-  launch_q1_shift<T, T>(g, A, nk, 0, static_cast<T*>(qb[0]), nk, 0, q1sums, 1.0, batch, gate, st);
-  launch_q1_shift<T, T>(g, A, nk, 0, static_cast<T*>(qx[0]), nk, 0, nullptr, 0.0, batch, gate, st);
-  ap_vcycle<T>(batch, gate);
-  launch_q1_sum<T>(g, static_cast<T*>(qx[0]), rs, batch, gate, st);
-  launch_q1_shift<T, double>(g, static_cast<T*>(qx[0]), nk, 0, z, ld, g.off_pk(), q1sums, -1.0, batch,
-                             gate, st);
+  // A_p^+ of A into the target, mean projection on input and output
+  auto ap_pinv = [&](T* src, auto* dst, long long ldd, long long offd, double scale) {
+    launch_q1_sum<T>(g, src, rs, batch, gate, st);
+    launch_q1_shift<T, T>(g, src, nk, 0, qb0, nk, 0, q1sums, 1.0, batch, gate, st);
+    launch_q1_shift<T, T>(g, src, nk, 0, qx0, nk, 0, nullptr, 0.0, batch, gate, st);
+    ap_vcycle<T>(batch, gate);
+    launch_q1_sum<T>(g, qx0, rs, batch, gate, st);
+    launch_q1_shift<T, std::remove_pointer_t<decltype(dst)>>(g, qx0, nk, 0, dst, ldd, offd, q1sums, scale,
+                                                            batch, gate, st);
+  };
+  // Q_1^{-1} b: Chebyshev-Jacobi on [1/4, 9/4]; returns the buffer holding it
+  auto q1_inv = [&](T* b, T* cur, T* oth) {
+    launch_q1mass_cheb<T>(g, b, nullptr, cur, 0.0, q1b[0], 0, batch, gate, st);
+    for (int k = 1; k < d.pcd_q1_steps; ++k) {
+      launch_q1mass_cheb<T>(g, b, cur, oth, q1a[k], q1b[k], k == 1 ? 2 : 1, batch, gate, st);
+      std::swap(cur, oth);
+    }
+    return cur;
+  };
+  launch_q1_shift<double, T>(g, r, ld, g.off_pk(), A, nk, 0, nullptr, 1.0, batch, gate, st);
+  if (!trans) {
+    T* q = q1_inv(A, B, C);
+    launch_f1_apply<T>(g, wind0, d.nu, q, A, batch, gate, st, 0);
+    ap_pinv(A, z, ld, g.off_pk(), -1.0);
+  } else {
+    ap_pinv(A, A, nk, 0, 1.0);
+    launch_f1_apply<T>(g, wind0, d.nu, A, B, batch, gate, st, 1);
+    T* q = q1_inv(B, C, A);
+    launch_q1_shift<T, double>(g, q, nk, 0, z, ld, g.off_pk(), nullptr, -1.0, batch, gate, st);
+  }
 }
 
 void Problem::precond_oseen(int kind, const double* r, double* z, int batch, Gate gate) {
   const GmresScalars* gs = (gate.p == gm_gate().p) ? d_gm : nullptr;
-  if (kind == 2) {
-    if (mixed) pcd_schur<float>(r, z, ldw, batch, gate);
-    else pcd_schur<double>(r, z, ldw, batch, gate);
+  const bool tr = (kind == 3 || kind == 4);
+  if (kind == 2 || kind == 4) {
+    if (mixed) pcd_schur<float>(r, z, ldw, batch, gate, tr);
+    else pcd_schur<double>(r, z, ldw, batch, gate, tr);
     launch_gm_zero_range(z, ldw, g.off_p0(), g.n0, batch, gs, st);
   } else {
     mq_solve(r, z, ldw, batch, gate, -d.nu);
@@ -1060,15 +1095,15 @@ void Problem::precond_oseen(int kind, const double* r, double* z, int batch, Gat
   // z_u = F~^{-1}(r_u - B^T z_p): B^T z_p from the Stokes kernel with nu = 0
   launch_gm_zero_range(z, ldw, 0, 2LL * g.nv, batch, gs, st);
   launch_apply_stokes(g, 0.0, z, ky, ldw, batch, gate, nullptr, st);
-  if (mixed) vcycle_F<float>(r, ky, z, ldw, batch, gate);
-  else vcycle_F<double>(r, ky, z, ldw, batch, gate);
+  if (mixed) vcycle_F<float>(r, ky, z, ldw, batch, gate, tr);
+  else vcycle_F<double>(r, ky, z, ldw, batch, gate, tr);
 }
 
 // Restarted FGMRES on the internal vectors b, x (stride ldw); kind selects
 // the preconditioner (1: M_1, 2: PCD), reduced the stage-I operator (the p_0
 // rows of K x are dropped).  atol: absolute tolerance per RHS.
 void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int batch, int m,
-                         int maxit, const std::vector<double>& atol) {
+                         int maxit, const std::vector<double>& atol, bool transpose) {
   const size_t per = (size_t)(gm_m + 1) * gm_m + 7 * 64;
   for (int r = 0; r < batch; ++r) {
     GmresScalars& G = h_gm[r];
@@ -1093,7 +1128,7 @@ void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int
   auto V = [&](int i) { return gV + (size_t)i * batch * ldw; };
   auto Z = [&](int i) { return gZ + (size_t)i * batch * ldw; };
   auto op = [&](const double* in, double* out, Gate gt) {
-    apply_op(0, in, out, ldw, batch, gt, nullptr);
+    apply_op(transpose ? 1 : 0, in, out, ldw, batch, gt, nullptr);
     if (reduced) launch_gm_zero_range(out, ldw, g.off_p0(), g.n0, batch, gt.p ? d_gm : nullptr, st);
   };
   for (int cycle = 0; cycle < 100000; ++cycle) {
@@ -1139,14 +1174,13 @@ void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int
 }
 
 int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
-                         eth_solve_info* info) {
+                         eth_solve_info* info, bool adjoint) {
   const double eta = o.rtol > 0 ? o.rtol : 1e-6;
   const int maxit = o.maxit > 0 ? o.maxit : 1000;
   const int m = o.restart > 0 ? o.restart : gm_m;
   if (m > gm_m) throw std::invalid_argument("restart exceeds the gmres_restart of the problem");
   const double c = o.c_factor > 0 ? o.c_factor : 10.0;
-  launch_copy(g.N, b, ld, kb, ldw, batch, st);
-  launch_zero_boundary(g, kb, ldw, batch, st);
+  load_rhs(b, ld, batch, adjoint);
   RedCtx rn = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
   launch_dot(g.N, kb, kb, ldw, batch, rn, no_gate(), st);
   ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
@@ -1161,21 +1195,22 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
   for (int r = 0; r < batch; ++r) bn[r] = std::sqrt(h_red[r]);
   std::vector<int> it1(batch, 0);
   if (o.method == ETH_TWO_STAGE) {
-    // stage I: reduced system [F B_1^T; B_1 0], RHS without the P0 rows
+    // stage I: reduced system [F B_1^T; B_1 0] (adjoint: its transpose), RHS
+    // without the P0 rows
     launch_copy(g.N, kb, ldw, kv[0], ldw, batch, st);
     launch_gm_zero_range(kv[0], ldw, g.off_p0(), g.n0, batch, nullptr, st);
     launch_gm_zero_range(kx, ldw, g.off_p0(), g.n0, batch, nullptr, st);
     std::vector<double> a1(batch);
     for (int r = 0; r < batch; ++r) a1[r] = c * eta * bn[r];
-    run_fgmres(2, true, kv[0], kx, batch, m, maxit, a1);
+    run_fgmres(adjoint ? 4 : 2, true, kv[0], kx, batch, m, maxit, a1, adjoint);
     for (int r = 0; r < batch; ++r) it1[r] = h_gm[r].iters;
   }
   std::vector<double> a2(batch);
   for (int r = 0; r < batch; ++r) a2[r] = eta * bn[r];
-  run_fgmres(1, false, kb, kx, batch, m, std::max(1, maxit), a2);
+  run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint);
   // output
   launch_copy(g.N, kx, ldw, x, ld, batch, st);
-  launch_copy_boundary(g, b, x, ld, batch, st);
+  if (!adjoint) launch_copy_boundary(g, b, x, ld, batch, st);
   if (o.canonicalize) {
     launch_pressure_sums(g, x, ld, batch, red_partials, red_tickets, red_result, st);
     launch_pressure_shift(g, x, ld, batch, red_result, st);
@@ -1317,22 +1352,84 @@ int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, dou
   if (!p || !r || !z) return fail(p, ETH_EINVAL, "NULL argument");
   if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
   if (r == z) return fail(p, ETH_EINVAL, "r and z must not alias");
-  if (transpose) return fail(p, ETH_EUNSUPPORTED, "transposed preconditioner not available");
   return guarded(p, [&] {
     Problem& P = p->impl;
     if (P.oseen) {
       // the Oseen pieces work on the internal vector stride
       eth::launch_copy(P.g.N, r, ld, P.kv[0], P.ldw, (int)batch, P.st);
-      P.precond_oseen(1, P.kv[0], P.kz[0], (int)batch, eth::no_gate());
+      P.precond_oseen(transpose ? 3 : 1, P.kv[0], P.kz[0], (int)batch, eth::no_gate());
       eth::launch_copy(P.g.N, P.kz[0], P.ldw, z, ld, (int)batch, P.st);
     } else {
-      P.precond(r, z, ld, (int)batch, eth::no_gate());
+      P.precond(r, z, ld, (int)batch, eth::no_gate());   // symmetric: transpose is the same
     }
     return ETH_OK;
   });
 }
 
-int eth_apply_pcd(eth_problem* p, const double* r, double* z, int64_t batch, int64_t ld) {
+int eth_solve_adjoint(eth_problem* p, const eth_solve_opts* opts, const double* g, double* lambda,
+                      int64_t batch, int64_t ld, eth_solve_info* info) {
+  if (!p || !g || !lambda) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  if (g == lambda) return fail(p, ETH_EINVAL, "g and lambda must not alias");
+  eth_solve_opts o{};
+  if (opts) {
+    o = *opts;
+  } else {
+    o.canonicalize = 1;
+    o.method = p->impl.oseen ? ETH_TWO_STAGE : ETH_MINRES;
+  }
+  if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
+  if (p->impl.oseen) {
+    if (o.method != ETH_FGMRES && o.method != ETH_TWO_STAGE)
+      return fail(p, ETH_EUNSUPPORTED, "Oseen adjoints are solved by FGMRES or TWO_STAGE");
+    return guarded(p, [&] { return p->impl.solve_oseen(o, g, lambda, (int)batch, ld, info, true); });
+  }
+  if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
+  return guarded(p, [&] { return p->impl.solve_minres(o, g, lambda, (int)batch, ld, info, true); });
+}
+
+int eth_grad_forcing(eth_problem* p, const double* lambda, int64_t ld, double* dJdf, int64_t ld_f,
+                     int64_t batch) {
+  if (!p || !lambda || !dJdf) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  if (batch > 1 && ld_f < 2LL * p->impl.g.nv) return fail(p, ETH_EINVAL, "ld_f too small");
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    eth::launch_velocity_mass(P.g, lambda, ld, nullptr, 0, 1, dJdf, ld_f, nullptr, (int)batch, P.st);
+    return ETH_OK;
+  });
+}
+
+int eth_grad_viscosity(eth_problem* p, const double* lambda, const double* x, double* dJdnu,
+                       int64_t batch, int64_t ld) {
+  if (!p || !lambda || !x || !dJdnu) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    eth::RedCtx rc = P.red(0, 1, eth::EPI_NONE, nullptr, dJdnu);
+    eth::launch_grad_viscosity(P.g, lambda, ld, x, ld, rc, (int)batch, P.st);
+    return ETH_OK;
+  });
+}
+
+int eth_misfit(eth_problem* p, const double* x, const double* x_target, double* J, double* grad,
+               int64_t batch, int64_t ld) {
+  if (!p || !x || !x_target || !J) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    eth::RedCtx rc = P.red(0, 1, eth::EPI_NONE, nullptr, J);
+    if (grad) {
+      const long long np = (long long)P.g.nk + P.g.n0;
+      eth::launch_fill(np, 0.0, grad + P.g.off_pk(), ld, (int)batch, P.st);
+    }
+    eth::launch_velocity_mass(P.g, x, ld, x_target, ld, 0, grad, ld, &rc, (int)batch, P.st);
+    return ETH_OK;
+  });
+}
+
+int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int64_t batch,
+                  int64_t ld) {
   if (!p || !r || !z) return fail(p, ETH_EINVAL, "NULL argument");
   if (!check_batch(p, batch, ld)) return fail(p, ETH_EINVAL, "invalid batch or ld");
   if (r == z) return fail(p, ETH_EINVAL, "r and z must not alias");
@@ -1340,7 +1437,7 @@ int eth_apply_pcd(eth_problem* p, const double* r, double* z, int64_t batch, int
   return guarded(p, [&] {
     Problem& P = p->impl;
     eth::launch_copy(P.g.N, r, ld, P.kv[0], P.ldw, (int)batch, P.st);
-    P.precond_oseen(2, P.kv[0], P.kz[0], (int)batch, eth::no_gate());
+    P.precond_oseen(transpose ? 4 : 2, P.kv[0], P.kz[0], (int)batch, eth::no_gate());
     eth::launch_copy(P.g.N, P.kz[0], P.ldw, z, ld, (int)batch, P.st);
     return ETH_OK;
   });

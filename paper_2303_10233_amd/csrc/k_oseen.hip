@@ -121,8 +121,9 @@ __global__ void k_dense_convdiff(Geo g, const double* __restrict__ wind, double 
 // One damped Jacobi step (MODE 0: out = x + omega D_F^{-1}(b - F x)) or the
 // residual (MODE 1: out = b - F x) on the planes [rhs][component][nv] of a
 // multigrid level; with out64 (MODE 0) the result goes, times out_scale, to
-// the velocity part of FP64 vectors instead.
-template <typename T, int MODE>
+// the velocity part of FP64 vectors instead.  TRANS: F^T = nu A + N^T (same
+// diagonal).
+template <typename T, int MODE, bool TRANS>
 __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict__ wind,
                                                 const double* __restrict__ dF, double nu,
                                                 const T* __restrict__ b, const T* __restrict__ x,
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict_
         wl[0][j][i] = sw[0][2 * ley + j][2 * lex + i];
         wl[1][j][i] = sw[1][2 * ley + j][2 * lex + i];
       }
-    element_convection1<double>(ul, wl, g.h, ol);
+    element_convection1<double, TRANS>(ul, wl, g.h, ol);
     for (int j = 0; j < 3; ++j)
       for (int i = 0; i < 3; ++i) sN[k][3 * j + i] = ol[j][i];
   }
@@ -263,7 +264,8 @@ __global__ void k_q1mass_cheb(Geo g, const T* __restrict__ b, const T* __restric
 }
 
 // y = F_1 x on Q1 vectors: F_1 = nu int grad psi_j . grad psi_i + int (w . grad psi_j) psi_i
-template <typename T>
+// (TRANS: y = F_1^T x, convection int (w . grad psi_i) psi_j)
+template <typename T, bool TRANS>
 __global__ void k_f1_apply(Geo g, const double* __restrict__ wind, double nu,
                            const T* __restrict__ x, T* __restrict__ y, Gate gate) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,9 +308,17 @@ __global__ void k_f1_apply(Geo g, const double* __restrict__ wind, double nu,
               wx += bb * w[0][j][i];
               wy += bb * w[1][j][i];
             }
-          const double ddx = (xl[0][1] - xl[0][0]) * py[0] + (xl[1][1] - xl[1][0]) * py[1];
-          const double ddy = (xl[1][0] - xl[0][0]) * px[0] + (xl[1][1] - xl[0][1]) * px[1];
-          s += g.h * W[qx] * W[qy] * px[ax] * py[ay] * (wx * ddx + wy * ddy);
+          if constexpr (!TRANS) {
+            const double ddx = (xl[0][1] - xl[0][0]) * py[0] + (xl[1][1] - xl[1][0]) * py[1];
+            const double ddy = (xl[1][0] - xl[0][0]) * px[0] + (xl[1][1] - xl[0][1]) * px[1];
+            s += g.h * W[qx] * W[qy] * px[ax] * py[ay] * (wx * ddx + wy * ddy);
+          } else {
+            // d psi_a / d xi = (2 ax - 1) py[ay], d psi_a / d eta = (2 ay - 1) px[ax]
+            const double xv = xl[0][0] * px[0] * py[0] + xl[0][1] * px[1] * py[0] +
+                              xl[1][0] * px[0] * py[1] + xl[1][1] * px[1] * py[1];
+            const double dpx = (2 * ax - 1) * py[ay], dpy = (2 * ay - 1) * px[ax];
+            s += g.h * W[qx] * W[qy] * xv * (wx * dpx + wy * dpy);
+          }
         }
       }
       acc += s;
@@ -532,6 +542,13 @@ __global__ void k_q1_dense_solve(const double* __restrict__ Ainv, int ni, const 
   }
 }
 
+__global__ void k_transpose(const double* __restrict__ a, int ni, double* __restrict__ at) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)ni * ni) return;
+  const int i = (int)(t / ni), j = (int)(t % ni);
+  at[(long long)j * ni + i] = a[t];
+}
+
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -552,14 +569,12 @@ void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* 
 template <typename T>
 void launch_cd_step(const Geo& g, const double* wind, const double* dF, double nu, const T* b,
                     const T* x, T* out, double omega, int residual, int nplanes, double* out64,
-                    long long ld64, double out_scale, Gate gate, hipStream_t st) {
+                    long long ld64, double out_scale, Gate gate, hipStream_t st, int transpose) {
   dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, nplanes);
-  if (residual)
-    hipLaunchKernelGGL((k_cd_step<T, 1>), grid, dim3(TX, TY), 0, st, g, wind, dF, nu, b, x, out, omega,
-                       out64, ld64, out_scale, gate);
-  else
-    hipLaunchKernelGGL((k_cd_step<T, 0>), grid, dim3(TX, TY), 0, st, g, wind, dF, nu, b, x, out, omega,
-                       out64, ld64, out_scale, gate);
+  auto kern = residual ? (transpose ? k_cd_step<T, 1, true> : k_cd_step<T, 1, false>)
+                       : (transpose ? k_cd_step<T, 0, true> : k_cd_step<T, 0, false>);
+  hipLaunchKernelGGL(kern, grid, dim3(TX, TY), 0, st, g, wind, dF, nu, b, x, out, omega, out64, ld64,
+                     out_scale, gate);
   ETH_LAUNCH_CHECK();
 }
 template <typename T>
@@ -571,8 +586,13 @@ void launch_q1mass_cheb(const Geo& g, const T* b, const T* x, T* xo, double alph
 }
 template <typename T>
 void launch_f1_apply(const Geo& g, const double* wind, double nu, const T* x, T* y, int batch,
-                     Gate gate, hipStream_t st) {
-  hipLaunchKernelGGL(k_f1_apply<T>, dim3(nb(g.nk), batch), dim3(256), 0, st, g, wind, nu, x, y, gate);
+                     Gate gate, hipStream_t st, int transpose) {
+  if (transpose)
+    hipLaunchKernelGGL((k_f1_apply<T, true>), dim3(nb(g.nk), batch), dim3(256), 0, st, g, wind, nu, x, y,
+                       gate);
+  else
+    hipLaunchKernelGGL((k_f1_apply<T, false>), dim3(nb(g.nk), batch), dim3(256), 0, st, g, wind, nu, x, y,
+                       gate);
   ETH_LAUNCH_CHECK();
 }
 template <typename T>
@@ -617,6 +637,10 @@ void launch_q1_shift(const Geo& g, const TI* x, long long ldx, long long offx, T
                      ldo, offo, sums, scale, gate);
   ETH_LAUNCH_CHECK();
 }
+void launch_transpose(const double* a, int ni, double* at, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose, dim3(nb((long long)ni * ni)), dim3(256), 0, st, a, ni, at);
+  ETH_LAUNCH_CHECK();
+}
 void launch_unit_columns(double* cols, int ni, hipStream_t st) {
   hipLaunchKernelGGL(k_unit_columns, dim3(nb((long long)ni * ni)), dim3(256), 0, st, cols, ni);
   ETH_LAUNCH_CHECK();
@@ -634,11 +658,12 @@ void launch_q1_dense_solve(const double* Ainv, int ni, const T* b, T* x, int bat
 
 #define ETH_INST(T)                                                                                  \
   template void launch_cd_step<T>(const Geo&, const double*, const double*, double, const T*, const T*, \
-                                  T*, double, int, int, double*, long long, double, Gate, hipStream_t); \
+                                  T*, double, int, int, double*, long long, double, Gate, hipStream_t, \
+                                  int);                                                               \
   template void launch_q1mass_cheb<T>(const Geo&, const T*, const T*, T*, double, double, int, int,    \
                                       Gate, hipStream_t);                                             \
   template void launch_f1_apply<T>(const Geo&, const double*, double, const T*, T*, int, Gate,          \
-                                   hipStream_t);                                                     \
+                                   hipStream_t, int);                                                \
   template void launch_ap_op<T>(const Geo&, int, const T*, const T*, T*, double, double, int,          \
                                 const double*, int, Gate, hipStream_t);                              \
   template void launch_q1_restrict<T>(const Geo&, const Geo&, const T*, T*, T*, int, Gate, hipStream_t);\

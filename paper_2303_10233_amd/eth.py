@@ -114,11 +114,20 @@ def load_library(path=LIB_PATH):
     lib.eth_apply_operator.restype = ctypes.c_int
     lib.eth_apply_preconditioner.argtypes = [P, ctypes.c_int, P, P, i64, i64]
     lib.eth_apply_preconditioner.restype = ctypes.c_int
-    lib.eth_apply_pcd.argtypes = [P, P, P, i64, i64]
+    lib.eth_apply_pcd.argtypes = [P, ctypes.c_int, P, P, i64, i64]
     lib.eth_apply_pcd.restype = ctypes.c_int
     lib.eth_get_pcd_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.eth_get_pcd_levels.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
+    lib.eth_solve_adjoint.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64,
+                                      ctypes.POINTER(SolveInfo)]
+    lib.eth_solve_adjoint.restype = ctypes.c_int
+    lib.eth_grad_forcing.argtypes = [P, P, i64, P, i64, i64]
+    lib.eth_grad_forcing.restype = ctypes.c_int
+    lib.eth_grad_viscosity.argtypes = [P, P, P, P, i64, i64]
+    lib.eth_grad_viscosity.restype = ctypes.c_int
+    lib.eth_misfit.argtypes = [P, P, P, P, P, i64, i64]
+    lib.eth_misfit.restype = ctypes.c_int
     lib.eth_solve.restype = ctypes.c_int
     lib.eth_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, i64,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -277,12 +286,13 @@ class Problem:
                self._h)
         return z
 
-    def apply_pcd(self, r):
-        """Oseen: the stage-I PCD preconditioner applied to r (see eth.h)."""
+    def apply_pcd(self, r, transpose=False):
+        """Oseen: the stage-I PCD preconditioner applied to r (transpose: the
+        one of the transposed system; see eth.h)."""
         z = torch.empty_like(r)
         r2, B, ld = _as_batch(r, self.N)
         z2, _, _ = _as_batch(z, self.N)
-        _check(lib().eth_apply_pcd(self._h, _ptr(r2), _ptr(z2), B, ld), self._h)
+        _check(lib().eth_apply_pcd(self._h, int(transpose), _ptr(r2), _ptr(z2), B, ld), self._h)
         return z
 
     def profile_kernel(self, kernel, reps=50, batch=1):
@@ -311,3 +321,109 @@ class Problem:
         st = lib().eth_solve(self._h, ctypes.byref(o), _ptr(b2), _ptr(x2), B, ld, infos)
         _check(st, self._h)
         return x, [infos[i].as_dict() for i in range(B)]
+
+    def solve_adjoint(self, g, rtol=1e-6, maxit=1000, method=None, restart=0, canonicalize=True,
+                      true_residual=False, out=None):
+        """lambda with K^T lambda = g (see eth_solve_adjoint).  method None:
+        MINRES for Stokes, TWO_STAGE for Oseen."""
+        if method is None:
+            method = TWO_STAGE if self.kind == OSEEN else MINRES
+        lam = out if out is not None else torch.empty_like(g)
+        g2, B, ld = _as_batch(g, self.N)
+        l2, _, _ = _as_batch(lam, self.N)
+        o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=10.0,
+                      canonicalize=int(canonicalize), use_x0=0, use_graph=0,
+                      true_residual=int(true_residual))
+        infos = (SolveInfo * B)()
+        st = lib().eth_solve_adjoint(self._h, ctypes.byref(o), _ptr(g2), _ptr(l2), B, ld, infos)
+        _check(st, self._h)
+        return lam, [infos[i].as_dict() for i in range(B)]
+
+    def grad_forcing(self, lam):
+        """dJ/df = M_v lambda~ over all nodal forces, shape (..., 2 nv)."""
+        l2, B, ld = _as_batch(lam, self.N)
+        shape = (2 * self.nv,) if lam.dim() == 1 else (B, 2 * self.nv)
+        out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        _check(lib().eth_grad_forcing(self._h, _ptr(l2), ld, _ptr(out), 2 * self.nv, B), self._h)
+        return out
+
+    def grad_viscosity(self, lam, x):
+        """dJ/dnu = -lambda_u^T (A u)_I per right-hand side."""
+        l2, B, ld = _as_batch(lam, self.N)
+        x2, _, ldx = _as_batch(x, self.N)
+        if ldx != ld:
+            raise ValueError("lambda and x need the same stride")
+        out = torch.empty((B,), dtype=torch.float64, device=self.device)
+        _check(lib().eth_grad_viscosity(self._h, _ptr(l2), _ptr(x2), _ptr(out), B, ld), self._h)
+        return out if lam.dim() > 1 else out[0]
+
+    def misfit(self, x, x_target, grad=True):
+        """(J, dJ/dx) with J = 1/2 (u - u_t)^T M_v (u - u_t) over all velocity
+        nodes; dJ/dx = [M_v (u - u_t); 0] (None unless grad)."""
+        x2, B, ld = _as_batch(x, self.N)
+        t2, _, ldt = _as_batch(x_target, self.N)
+        if ldt != ld:
+            raise ValueError("x and x_target need the same stride")
+        J = torch.empty((B,), dtype=torch.float64, device=self.device)
+        gr = torch.empty_like(x) if grad else None
+        g2 = _as_batch(gr, self.N)[0] if grad else None
+        _check(lib().eth_misfit(self._h, _ptr(x2), _ptr(t2), _ptr(J), _ptr(g2), B, ld), self._h)
+        return (J if x.dim() > 1 else J[0]), gr
+
+
+class FlowSolve(torch.autograd.Function):
+    """x = K(nu)^{-1} b(f, nu) for a Stokes or Oseen Problem, differentiable in
+    the nodal forcing f (2 nv, or batch x 2 nv) and the viscosity nu (a 0-d
+    tensor equal to the problem's nu).  The backward pass is the hand-written
+    discrete adjoint: lambda = K^{-T} grad_x (eth_solve_adjoint), then
+    dJ/df = M_v lambda~ and dJ/dnu = -lambda_u^T (A u)_I."""
+
+    @staticmethod
+    def forward(ctx, f, nu, problem, rtol=1e-10, maxit=2000):
+        if abs(float(nu) - problem.nu) > 1e-14 * abs(problem.nu):
+            raise ValueError("nu must equal the viscosity the problem was set up with")
+        batch = 1 if f.dim() == 1 else f.shape[0]
+        b = problem.assemble_rhs(f.detach().contiguous(), batch=batch)
+        x, info = problem.solve(b, rtol=rtol, maxit=maxit)
+        if any(i["status"] != 0 for i in info):
+            raise EthError(info[0]["status"], "forward solve did not converge")
+        ctx.problem, ctx.rtol, ctx.maxit = problem, rtol, maxit
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        P = ctx.problem
+        lam, info = P.solve_adjoint(gx.contiguous(), rtol=ctx.rtol, maxit=ctx.maxit)
+        if any(i["status"] != 0 for i in info):
+            raise EthError(info[0]["status"], "adjoint solve did not converge")
+        gf = P.grad_forcing(lam) if ctx.needs_input_grad[0] else None
+        gnu = None
+        if ctx.needs_input_grad[1]:
+            gnu = P.grad_viscosity(lam, x)
+            gnu = gnu.sum() if gnu.dim() > 0 else gnu
+        return gf, gnu, None, None, None
+
+
+StokesSolve = FlowSolve
+
+
+class L2Misfit(torch.autograd.Function):
+    """J = 1/2 (u - u_t)^T M_v (u - u_t) (summed over a batch); backward
+    M_v (u - u_t) into the velocity rows, 0 into the pressure rows."""
+
+    @staticmethod
+    def forward(ctx, x, x_target, problem):
+        J, g = problem.misfit(x.detach().contiguous(), x_target.detach().contiguous(), grad=True)
+        ctx.save_for_backward(g)
+        return J.sum()
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (g,) = ctx.saved_tensors
+        return gJ * g, None, None
+
+
+def l2_misfit(x, x_target, problem):
+    return L2Misfit.apply(x, x_target, problem)

@@ -211,3 +211,45 @@ def test_two_stage_batched_forcing_and_warm_start():
     Xz, iz = P.solve(Z, rtol=1e-7, method=eth.FGMRES)
     assert all(i["iterations"] == 0 for i in iz)
     assert float(torch.abs(Xz).max()) == 0.0
+
+
+def _oracle_vel_T(s):
+    """F~^{-T}: exact for a single-level hierarchy, else the same V-cycle on the
+    transposed level operators."""
+    m = s.mesh
+    if len(opc.gmg_levels(m.n, 32)) == 1:
+        import scipy.sparse.linalg as spla
+        return spla.splu(s.FI.T.tocsc()).solve
+    mk = opc.oseen_level_operator(m, s.wind, s.nu)
+    gT = opc.GMGJacobi(m, lambda mm: mk(mm).T.tocsr(), omega=0.7, sweeps=2, coarse_n=32)
+    k = gT.A[0].shape[0]
+    return lambda v: np.concatenate([gT.vcycle(0, v[:k]), gT.vcycle(0, v[k:])])
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_transposed_preconditioners_match_oracle(n):
+    """The preconditioners of the transposed system used by the adjoint:
+    [F~^T B^T; 0 -M~_Q/nu] and the transposed PCD -Q_1^{-1} F_1^T A_p^+."""
+    print(f"[oseen transposed preconditioners] n={n}", flush=True)
+    nu = 0.01
+    m, s, P = _setup(n, nu)
+    r = uniform_vector(m.N, 17 + n)
+    r[: 2 * m.nv][s.vel_bnd] = 0.0
+    velT = _oracle_vel_T(s)
+    o = 2 * m.nv
+    z = _np(P.apply_preconditioner(_t(r), transpose=True))
+    MT = opc.OseenM1(s, velocity_solve=velT, mq=opc.MQChebSGS(m, s.MQ, _mq_lo(n), 1.0, 20))
+    zref = s.to_full(MT(s.to_interior(r)))
+    assert rel_err(z[:o], zref[:o]) < 1e-11
+    assert rel_err(z[o:], zref[o:]) < 1e-11
+    # transposed PCD from the oracle's pieces
+    zp = _np(P.apply_pcd(_t(r), transpose=True))
+    pc = _oracle_pcd(s, P)
+    ri = s.to_interior(r)
+    rp = ri[s.nI: s.nI + m.nk]
+    qp = -pc.q1_inv(pc.F1.T @ pc.apgmg(rp))
+    qu = velT(ri[: s.nI] - pc.B1.T @ qp)
+    zref = s.to_full(np.concatenate([qu, qp, np.zeros(m.n0)]))
+    assert rel_err(zp[:o], zref[:o]) < 1e-11
+    assert rel_err(zp[o:o + m.nk], zref[o:o + m.nk]) < 1e-11
+    assert np.abs(zp[o + m.nk:]).max() == 0.0
