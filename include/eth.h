@@ -207,6 +207,30 @@ int eth_grad_viscosity(eth_problem* p, const double* lambda, const double* x, do
 int eth_misfit(eth_problem* p, const double* x, const double* x_target, double* J,
                double* grad, int64_t batch, int64_t ld);
 
+/* Ragged batches: several Stokes problems of different sizes (e.g. cavities
+ * of 32..256 elements per side) solved together.  Every problem gets its own
+ * stream and workspaces; eth_batch_solve starts all MINRES solves, keeps each
+ * one's iteration chunks (hipGraph replays) queued on its own stream and
+ * polls their device-side convergence flags without blocking, so the
+ * problems run concurrently on the GPU.  descs[i] as for eth_setup (kind must
+ * be ETH_STOKES); descs[0].stream is the caller's stream: eth_batch_solve
+ * waits for the work already queued on it and makes it wait for the results.
+ * Each problem takes one right-hand side. */
+typedef struct eth_batch eth_batch;
+int eth_batch_setup(const eth_problem_desc* descs, int32_t count, eth_batch** out);
+int eth_batch_count(const eth_batch* b);
+/* borrowed handle of problem i (for eth_assemble_rhs, eth_apply_operator, ...);
+ * owned by the batch, valid until eth_batch_destroy.  Calls on it are ordered
+ * on the problem's own stream. */
+int eth_batch_problem(eth_batch* b, int32_t i, eth_problem** out);
+/* b[i], x[i]: device vectors of problem i (length eth_vector_length of it);
+ * opts as for eth_solve (method ETH_MINRES); infos: host array of count
+ * entries or NULL.  Returns the worst status. */
+int eth_batch_solve(eth_batch* b, const eth_solve_opts* opts, const double* const* bvecs,
+                    double* const* xvecs, eth_solve_info* infos);
+const char* eth_batch_last_error(const eth_batch* b);
+int eth_batch_destroy(eth_batch* b);
+
 /* Kernel timing for roofline reporting.  Launches `reps` times the kernel
  * `kernel` (ETH_K_*) exactly as one MINRES iteration launches it (same grid,
  * same workspaces, finest level where a hierarchy is involved), between two

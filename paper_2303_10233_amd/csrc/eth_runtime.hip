@@ -139,6 +139,7 @@ struct Problem {
   int gexec_batch = -1;
   hipStream_t gst = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool own_stream = false;           // st was created by the library (ragged batches)
 
   template <typename T>
   T* alloc(size_t count) {
@@ -153,6 +154,8 @@ struct Problem {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_poll) (void)hipEventDestroy(ev_poll);
+    if (own_stream && st) (void)hipStreamDestroy(st);
     if (gst) (void)hipStreamDestroy(gst);
     for (void* p : allocs) (void)hipFree(p);
     if (h_ms) (void)hipHostFree(h_ms);
@@ -225,6 +228,26 @@ struct Problem {
                   eth_solve_info* info, bool adjoint = false);
 
   // ---------------------------------------------------------------- solve
+  // a MINRES solve split into phases, so that several problems can iterate
+  // concurrently on their own streams (eth_batch_solve)
+  struct MinresRun {
+    eth_solve_opts o{};
+    const double* b = nullptr;
+    double* x = nullptr;
+    int batch = 1;
+    long long ld = 0;
+    bool adjoint = false;
+    double tol = 0.0, prev_rel = 1.0;
+    int maxit = 0, done = 0, chunk = 8, prev_it = 0;
+    bool use_graph = false;
+  };
+  hipEvent_t ev_poll = nullptr;
+  void minres_begin(MinresRun& R);
+  void minres_enqueue_chunk(MinresRun& R);
+  // true once the iteration has ended and the output copies are enqueued;
+  // block = false returns false at once while the last chunk still runs
+  bool minres_poll(MinresRun& R, bool block);
+  int minres_finish(MinresRun& R, eth_solve_info* info);
   void minres_iteration(int batch, int parity);
   int solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
                    eth_solve_info* info, bool adjoint = false);
@@ -271,6 +294,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) fused_mq = (e[0] != '1');
   max_batch = d.max_batch > 0 ? d.max_batch : 1;
   st = static_cast<hipStream_t>(d.stream);
+  ETH_HIP(hipEventCreateWithFlags(&ev_poll, hipEventDisableTiming));
   g = make_geo(d.n, (d.x1 - d.x0) / d.n);
   ldw = (g.N + 63) / 64 * 64;
 
@@ -633,14 +657,20 @@ void Problem::load_rhs(const double* b, long long ld, int batch, bool adjoint) {
   }
 }
 
-int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch,
-                          long long ld, eth_solve_info* info, bool adjoint) {
-  const double tol = o.rtol > 0 ? o.rtol : 1e-8;
-  const int maxit = o.maxit > 0 ? o.maxit : 1000;
-  load_rhs(b, ld, batch, adjoint);
+void Problem::minres_begin(MinresRun& R) {
+  const eth_solve_opts& o = R.o;
+  const int batch = R.batch;
+  R.tol = o.rtol > 0 ? o.rtol : 1e-8;
+  R.maxit = o.maxit > 0 ? o.maxit : 1000;
+  R.use_graph = o.use_graph != 0;
+  R.done = 0;
+  R.chunk = 8;
+  R.prev_rel = 1.0;
+  R.prev_it = 0;
+  load_rhs(R.b, R.ld, batch, R.adjoint);
   // initial residual v1 = b - K x0
   if (o.use_x0) {
-    launch_copy(g.N, x, ld, kx, ldw, batch, st);
+    launch_copy(g.N, R.x, R.ld, kx, ldw, batch, st);
     launch_zero_boundary(g, kx, ldw, batch, st);
     launch_apply_stokes(g, d.nu, kx, ky, ldw, batch, no_gate(), nullptr, st);
     launch_residual_init(g, kb, ky, kv[0], ldw, batch, st);
@@ -653,47 +683,57 @@ int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, i
   launch_fill(g.N, 0.0, kw[1], ldw, batch, st);
   // scalar state
   for (int r = 0; r < batch; ++r) {
-    MinresScalars& s = h_ms[r];
-    std::memset(&s, 0, sizeof(s));
-    s.tol = tol;
-    s.maxit = maxit;
-    s.hist = d_hist + (size_t)r * hist_len;
-    s.hist_len = hist_len;
-    s.active = 1;
+    MinresScalars& sc = h_ms[r];
+    std::memset(&sc, 0, sizeof(sc));
+    sc.tol = R.tol;
+    sc.maxit = R.maxit;
+    sc.hist = d_hist + (size_t)r * hist_len;
+    sc.hist_len = hist_len;
+    sc.active = 1;
   }
   ETH_HIP(hipMemcpyAsync(d_ms, h_ms, sizeof(MinresScalars) * batch, hipMemcpyHostToDevice, st));
   // z1 = P^{-1} v1, gamma_1
   precond(kv[0], kz[0], ldw, batch, no_gate());
   RedCtx ri = red(dot_blocks(g.N), 1, EPI_MINRES_INIT, d_ms);
   launch_dot(g.N, kz[0], kv[0], ldw, batch, ri, no_gate(), st);
-  // iterate in chunks, predicting the remaining count from the recent rate
-  const bool use_graph = o.use_graph != 0;
-  int done = 0;
-  int chunk = 8;
-  double prev_rel = 1.0;
-  int prev_it = 0;
-  while (true) {
-    run_iterations(batch, chunk, use_graph);
-    done += chunk;
-    ETH_HIP(hipMemcpyAsync(h_ms, d_ms, sizeof(MinresScalars) * batch, hipMemcpyDeviceToHost, st));
-    ETH_HIP(hipStreamSynchronize(st));
-    bool any = false;
-    double worst_rel = 0.0;
-    int it = 0;
-    for (int r = 0; r < batch; ++r) {
-      if (h_ms[r].active) {
-        any = true;
-        worst_rel = std::max(worst_rel, h_ms[r].rel);
-        it = std::max(it, h_ms[r].iters);
-      }
+  minres_enqueue_chunk(R);
+}
+
+// enqueue R.chunk iterations, then the copy of the scalars to the host and
+// the event that marks it
+void Problem::minres_enqueue_chunk(MinresRun& R) {
+  run_iterations(R.batch, R.chunk, R.use_graph);
+  R.done += R.chunk;
+  ETH_HIP(hipMemcpyAsync(h_ms, d_ms, sizeof(MinresScalars) * R.batch, hipMemcpyDeviceToHost, st));
+  ETH_HIP(hipEventRecord(ev_poll, st));
+}
+
+bool Problem::minres_poll(MinresRun& R, bool block) {
+  if (block) {
+    ETH_HIP(hipEventSynchronize(ev_poll));
+  } else {
+    const hipError_t q = hipEventQuery(ev_poll);
+    if (q == hipErrorNotReady) return false;
+    ETH_HIP(q);
+  }
+  const int batch = R.batch;
+  bool any = false;
+  double worst_rel = 0.0;
+  int it = 0;
+  for (int r = 0; r < batch; ++r) {
+    if (h_ms[r].active) {
+      any = true;
+      worst_rel = std::max(worst_rel, h_ms[r].rel);
+      it = std::max(it, h_ms[r].iters);
     }
-    if (!any || done >= maxit + 2) break;
-    // predict remaining iterations from the observed rate
+  }
+  if (any && R.done < R.maxit + 2) {
+    // iterate in chunks, predicting the remaining count from the recent rate
     int next = 8;
-    if (it > prev_it && worst_rel > 0 && prev_rel > worst_rel) {
-      const double rate = std::pow(worst_rel / prev_rel, 1.0 / (it - prev_it));
+    if (it > R.prev_it && worst_rel > 0 && R.prev_rel > worst_rel) {
+      const double rate = std::pow(worst_rel / R.prev_rel, 1.0 / (it - R.prev_it));
       if (rate < 1.0 && rate > 0.0) {
-        const double rem = std::log(tol / worst_rel) / std::log(rate);
+        const double rem = std::log(R.tol / worst_rel) / std::log(rate);
         next = (int)std::ceil(rem) + 1;
       } else {
         next = 16;
@@ -701,21 +741,28 @@ int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, i
     }
     next = std::max(2, std::min(next, 64));
     next += next & 1;
-    prev_rel = worst_rel;
-    prev_it = it;
-    chunk = next;
+    R.prev_rel = worst_rel;
+    R.prev_it = it;
+    R.chunk = next;
+    minres_enqueue_chunk(R);
+    return false;
   }
   // output: x = interior solution + Dirichlet rows, canonical pressure
-  launch_copy(g.N, kx, ldw, x, ld, batch, st);
-  if (!adjoint) launch_copy_boundary(g, b, x, ld, batch, st);
-  if (o.canonicalize) {
-    launch_pressure_sums(g, x, ld, batch, red_partials, red_tickets, red_result, st);
-    launch_pressure_shift(g, x, ld, batch, red_result, st);
+  launch_copy(g.N, kx, ldw, R.x, R.ld, batch, st);
+  if (!R.adjoint) launch_copy_boundary(g, R.b, R.x, R.ld, batch, st);
+  if (R.o.canonicalize) {
+    launch_pressure_sums(g, R.x, R.ld, batch, red_partials, red_tickets, red_result, st);
+    launch_pressure_shift(g, R.x, R.ld, batch, red_result, st);
   }
+  return true;
+}
+
+int Problem::minres_finish(MinresRun& R, eth_solve_info* info) {
+  const int batch = R.batch;
   std::vector<double> true_rel(batch, -1.0);
-  if (o.true_residual) {
+  if (R.o.true_residual) {
     launch_apply_stokes(g, d.nu, kx, ky, ldw, batch, no_gate(), nullptr, st);
-    // ky <- kb - K x (boundary rows zero); reuse kv[1] for the residual
+    // kv[1] <- kb - K x (boundary rows zero)
     launch_residual_init(g, kb, ky, kv[1], ldw, batch, st);
     RedCtx r1 = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
     launch_dot(g.N, kv[1], kv[1], ldw, batch, r1, no_gate(), st);
@@ -731,20 +778,35 @@ int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, i
   ETH_HIP(hipStreamSynchronize(st));
   int worst = ETH_OK;
   for (int r = 0; r < batch; ++r) {
-    const MinresScalars& s = h_ms[r];
-    int status = s.status;
-    if (status == kStOK && s.active) status = ETH_WMAXIT;
+    const MinresScalars& sc = h_ms[r];
+    int status = sc.status;
+    if (status == kStOK && sc.active) status = ETH_WMAXIT;
     if (info) {
       info[r].status = status;
-      info[r].iterations = s.iters;
+      info[r].iterations = sc.iters;
       info[r].stage1_iterations = 0;
-      info[r].rel_residual_est = s.rel;
+      info[r].rel_residual_est = sc.rel;
       info[r].rel_residual_true = true_rel[r];
     }
     if (status < 0) worst = std::min(worst, status);
     else if (worst >= 0) worst = std::max(worst, status);
   }
   return worst;
+}
+
+int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch,
+                          long long ld, eth_solve_info* info, bool adjoint) {
+  MinresRun R;
+  R.o = o;
+  R.b = b;
+  R.x = x;
+  R.batch = batch;
+  R.ld = ld;
+  R.adjoint = adjoint;
+  minres_begin(R);
+  while (!minres_poll(R, true)) {
+  }
+  return minres_finish(R, info);
 }
 
 // ============================================================================
@@ -1426,6 +1488,159 @@ int eth_misfit(eth_problem* p, const double* x, const double* x_target, double* 
     eth::launch_velocity_mass(P.g, x, ld, x_target, ld, 0, grad, ld, &rc, (int)batch, P.st);
     return ETH_OK;
   });
+}
+
+// ------------------------------------------------------------ ragged batches
+}  // extern "C"
+
+struct eth_batch {
+  std::vector<eth_problem*> probs;
+  hipStream_t caller = nullptr;
+  hipEvent_t ev_in = nullptr;
+  std::vector<hipEvent_t> ev_out;
+  std::string err;
+  ~eth_batch() {
+    for (auto* p : probs) {
+      if (!p) continue;
+      (void)hipStreamSynchronize(p->impl.st);
+      delete p;
+    }
+    for (auto e : ev_out) (void)hipEventDestroy(e);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+  }
+};
+
+extern "C" {
+
+int eth_batch_setup(const eth_problem_desc* descs, int32_t count, eth_batch** out) {
+  if (!out) return fail(nullptr, ETH_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || count < 1) return fail(nullptr, ETH_EINVAL, "descs is NULL or count < 1");
+  for (int i = 0; i < count; ++i)
+    if (descs[i].kind != ETH_STOKES)
+      return fail(nullptr, ETH_EUNSUPPORTED, "ragged batches hold Stokes problems");
+  std::unique_ptr<eth_batch> B(new (std::nothrow) eth_batch());
+  if (!B) return fail(nullptr, ETH_ENOMEM, "host allocation failed");
+  B->caller = static_cast<hipStream_t>(descs[0].stream);
+  try {
+    ETH_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    for (int i = 0; i < count; ++i) {
+      eth_problem_desc d = descs[i];
+      hipStream_t s = nullptr;
+      ETH_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      d.stream = s;
+      eth_problem* p = new eth_problem();
+      p->impl.own_stream = true;   // set before setup: the stream is released with the problem
+      p->impl.st = s;
+      B->probs.push_back(p);
+      p->impl.setup(d);
+      hipEvent_t e = nullptr;
+      ETH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      B->ev_out.push_back(e);
+    }
+  } catch (const eth::HipError& e) {
+    return fail(nullptr, ETH_EDEVICE, e.where + ": " + hipGetErrorString(e.err));
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, ETH_ENOMEM, "device allocation failed");
+  } catch (const std::invalid_argument& e) {
+    return fail(nullptr, ETH_EINVAL, e.what());
+  } catch (const std::runtime_error& e) {
+    const std::string m = e.what();
+    return (m.rfind("unsupported:", 0) == 0) ? fail(nullptr, ETH_EUNSUPPORTED, m.substr(12))
+                                             : fail(nullptr, ETH_EDEVICE, m);
+  }
+  *out = B.release();
+  return ETH_OK;
+}
+
+int eth_batch_count(const eth_batch* b) { return b ? (int)b->probs.size() : -1; }
+
+int eth_batch_problem(eth_batch* b, int32_t i, eth_problem** out) {
+  if (!b || !out || i < 0 || i >= (int)b->probs.size()) return ETH_EINVAL;
+  *out = b->probs[i];
+  return ETH_OK;
+}
+
+int eth_batch_solve(eth_batch* bt, const eth_solve_opts* opts, const double* const* b, double* const* x,
+                    eth_solve_info* infos) {
+  if (!bt || !b || !x) return ETH_EINVAL;
+  const int count = (int)bt->probs.size();
+  for (int i = 0; i < count; ++i) {
+    if (!b[i] || !x[i] || b[i] == x[i]) {
+      bt->err = "NULL or aliased b/x";
+      return ETH_EINVAL;
+    }
+  }
+  eth_solve_opts o{};
+  if (opts) o = *opts;
+  else o.canonicalize = 1;
+  if (o.method != ETH_MINRES || o.maxit > 4096) {
+    bt->err = "ragged batches run MINRES with maxit <= 4096";
+    return ETH_EINVAL;
+  }
+  try {
+    std::vector<Problem::MinresRun> runs(count);
+    std::vector<char> done(count, 0);
+    ETH_HIP(hipEventRecord(bt->ev_in, bt->caller));
+    for (int i = 0; i < count; ++i) {
+      Problem& P = bt->probs[i]->impl;
+      ETH_HIP(hipStreamWaitEvent(P.st, bt->ev_in, 0));
+      Problem::MinresRun& R = runs[i];
+      R.o = o;
+      R.b = b[i];
+      R.x = x[i];
+      R.batch = 1;
+      R.ld = P.g.N;
+      P.minres_begin(R);
+    }
+    int pending = count;
+    while (pending > 0) {
+      bool progress = false;
+      for (int i = 0; i < count; ++i) {
+        if (done[i]) continue;
+        if (bt->probs[i]->impl.minres_poll(runs[i], false)) {
+          done[i] = 1;
+          --pending;
+          progress = true;
+        }
+      }
+      if (!progress) {
+        // wait for the first unfinished problem; the others keep running
+        for (int i = 0; i < count; ++i) {
+          if (done[i]) continue;
+          if (bt->probs[i]->impl.minres_poll(runs[i], true)) {
+            done[i] = 1;
+            --pending;
+          }
+          break;
+        }
+      }
+    }
+    int worst = ETH_OK;
+    for (int i = 0; i < count; ++i) {
+      Problem& P = bt->probs[i]->impl;
+      const int st = P.minres_finish(runs[i], infos ? &infos[i] : nullptr);
+      ETH_HIP(hipEventRecord(bt->ev_out[i], P.st));
+      ETH_HIP(hipStreamWaitEvent(bt->caller, bt->ev_out[i], 0));
+      if (st < 0) worst = std::min(worst, st);
+      else if (worst >= 0) worst = std::max(worst, st);
+    }
+    return worst;
+  } catch (const eth::HipError& e) {
+    bt->err = e.where + ": " + hipGetErrorString(e.err);
+    return ETH_EDEVICE;
+  } catch (const std::exception& e) {
+    bt->err = e.what();
+    return ETH_EDEVICE;
+  }
+}
+
+const char* eth_batch_last_error(const eth_batch* b) { return b ? b->err.c_str() : ""; }
+
+int eth_batch_destroy(eth_batch* b) {
+  if (!b) return ETH_EINVAL;
+  delete b;
+  return ETH_OK;
 }
 
 int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int64_t batch,

@@ -119,6 +119,19 @@ def load_library(path=LIB_PATH):
     lib.eth_get_pcd_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.eth_get_pcd_levels.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
+    lib.eth_batch_setup.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int32, ctypes.POINTER(P)]
+    lib.eth_batch_setup.restype = ctypes.c_int
+    lib.eth_batch_count.argtypes = [P]
+    lib.eth_batch_count.restype = ctypes.c_int
+    lib.eth_batch_problem.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
+    lib.eth_batch_problem.restype = ctypes.c_int
+    lib.eth_batch_solve.argtypes = [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(P), ctypes.POINTER(P),
+                                    ctypes.POINTER(SolveInfo)]
+    lib.eth_batch_solve.restype = ctypes.c_int
+    lib.eth_batch_last_error.argtypes = [P]
+    lib.eth_batch_last_error.restype = ctypes.c_char_p
+    lib.eth_batch_destroy.argtypes = [P]
+    lib.eth_batch_destroy.restype = ctypes.c_int
     lib.eth_solve_adjoint.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64,
                                       ctypes.POINTER(SolveInfo)]
     lib.eth_solve_adjoint.restype = ctypes.c_int
@@ -178,6 +191,41 @@ def _as_batch(t, N):
     return t, t.shape[0], (t.stride(0) if t.shape[0] > 1 else t.shape[1])
 
 
+def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0, kind=STOKES,
+               wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0, mq_cheb=(0.0, 0.0),
+               gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0), gmg_lambda=None, precision=FP64,
+               max_batch=1, device=None, gmg_omega=0.0, pcd_q1_steps=0, gmres_restart=0):
+    """A filled ProblemDesc and the Python objects it points into."""
+    d = ProblemDesc()
+    d.n = n
+    d.x0, d.x1, d.y0, d.y1 = domain
+    d.kind = kind
+    d.nu = nu
+    d.wind = _ptr(wind) if wind is not None else None
+    d.lid_u = lid_u
+    d.corner_mode = corner_mode
+    d.velocity_mode = velocity
+    d.mq_mode = mq
+    d.mq_steps = mq_steps
+    d.mq_cheb_lo, d.mq_cheb_hi = mq_cheb
+    d.gmg_coarse_n = gmg_coarse_n
+    d.gmg_degree = gmg_degree
+    d.gmg_lo_frac, d.gmg_hi_frac = gmg_frac
+    lam = None
+    if gmg_lambda is not None:
+        lam = (ctypes.c_double * len(gmg_lambda))(*gmg_lambda)
+        d.gmg_lambda = lam
+    d.precision = precision
+    d.max_batch = max_batch
+    d.gmg_omega = gmg_omega
+    d.pcd_q1_steps = pcd_q1_steps
+    d.gmres_restart = gmres_restart
+    dev = torch.device("cuda" if device is None else device)
+    with torch.cuda.device(dev):
+        d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return d, (wind, lam)
+
+
 class Problem:
     """A discrete enriched Taylor-Hood Stokes problem on the GPU (see eth.h)."""
 
@@ -186,51 +234,30 @@ class Problem:
                  mq_cheb=(0.0, 0.0), gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0),
                  gmg_lambda=None, precision=FP64, max_batch=1, device=None, gmg_omega=0.0,
                  pcd_q1_steps=0, gmres_restart=0):
-        self.device = torch.device("cuda" if device is None else device)
-        L = lib()
-        d = ProblemDesc()
-        d.n = n
-        d.x0, d.x1, d.y0, d.y1 = domain
-        d.kind = kind
-        d.nu = nu
-        self._wind = wind
-        d.wind = _ptr(wind) if wind is not None else None
-        d.lid_u = lid_u
-        d.corner_mode = corner_mode
-        d.velocity_mode = velocity
-        d.mq_mode = mq
-        d.mq_steps = mq_steps
-        d.mq_cheb_lo, d.mq_cheb_hi = mq_cheb
-        d.gmg_coarse_n = gmg_coarse_n
-        d.gmg_degree = gmg_degree
-        d.gmg_lo_frac, d.gmg_hi_frac = gmg_frac
-        self._lam = None
-        if gmg_lambda is not None:
-            self._lam = (ctypes.c_double * len(gmg_lambda))(*gmg_lambda)
-            d.gmg_lambda = self._lam
-        d.precision = precision
-        d.max_batch = max_batch
-        d.gmg_omega = gmg_omega
-        d.pcd_q1_steps = pcd_q1_steps
-        d.gmres_restart = gmres_restart
-        self.kind = kind
-        with torch.cuda.device(self.device):
-            d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        d, keep = _make_desc(**{k: v for k, v in locals().items() if k not in ("self", "__class__")})
+        self._keep = keep
         h = ctypes.c_void_p()
-        _check(L.eth_setup(ctypes.byref(d), ctypes.byref(h)))
+        _check(lib().eth_setup(ctypes.byref(d), ctypes.byref(h)))
+        self._attach(h, d, device, owned=True)
+
+    def _attach(self, h, d, device, owned):
+        self.device = torch.device("cuda" if device is None else device)
         self._h = h
-        self.n = n
-        self.nu = nu
-        self.max_batch = max_batch
-        self.N = int(L.eth_vector_length(h))
-        nq = 2 * n + 1
+        self._owned = owned
+        self.n = d.n
+        self.nu = d.nu
+        self.kind = d.kind
+        self.max_batch = max(d.max_batch, 1)
+        self.N = int(lib().eth_vector_length(h))
+        nq = 2 * self.n + 1
         self.nv = nq * nq
-        self.nk = (n + 1) ** 2
-        self.n0 = n * n
+        self.nk = (self.n + 1) ** 2
+        self.n0 = self.n * self.n
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().eth_destroy(self._h)
+            if self._owned:
+                lib().eth_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -427,3 +454,71 @@ class L2Misfit(torch.autograd.Function):
 
 def l2_misfit(x, x_target, problem):
     return L2Misfit.apply(x, x_target, problem)
+
+
+class RaggedBatch:
+    """Stokes problems of different sizes solved together (eth_batch_*): one
+    stream and workspace set per problem, all MINRES solves in flight at
+    once.  `sizes`: elements per side of each problem; the keyword arguments
+    are those of Problem (shared by all)."""
+
+    def __init__(self, sizes, **kw):
+        kw.setdefault("device", None)
+        self.device = torch.device("cuda" if kw["device"] is None else kw["device"])
+        descs = (ProblemDesc * len(sizes))()
+        self._keep = []
+        for i, n in enumerate(sizes):
+            d, keep = _make_desc(n, **kw)
+            descs[i] = d
+            self._keep.append(keep)
+        h = ctypes.c_void_p()
+        _check(lib().eth_batch_setup(descs, len(sizes), ctypes.byref(h)))
+        self._h = h
+        self.problems = []
+        for i in range(len(sizes)):
+            ph = ctypes.c_void_p()
+            _check(lib().eth_batch_problem(h, i, ctypes.byref(ph)))
+            p = Problem.__new__(Problem)
+            p._attach(ph, descs[i], kw["device"], owned=False)
+            self.problems.append(p)
+
+    def __len__(self):
+        return len(self.problems)
+
+    def assemble_rhs(self):
+        """Lifted right-hand sides (lid, f = 0) of every problem, ordered on the
+        caller's stream."""
+        out = []
+        for p in self.problems:
+            out.append(p.assemble_rhs())
+        torch.cuda.synchronize(self.device)
+        return out
+
+    def solve(self, bs, rtol=1e-6, maxit=1000, use_graph=True, true_residual=False, out=None):
+        xs = out if out is not None else [torch.empty_like(b) for b in bs]
+        for p, b, x in zip(self.problems, bs, xs):
+            if b.numel() < p.N or x.numel() < p.N or b.dtype != torch.float64:
+                raise ValueError("each b/x must be a float64 vector of its problem's length")
+        n = len(self.problems)
+        B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        X = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        o = SolveOpts(method=MINRES, rtol=rtol, maxit=maxit, restart=0, c_factor=10.0, canonicalize=1,
+                      use_x0=0, use_graph=int(use_graph), true_residual=int(true_residual))
+        infos = (SolveInfo * n)()
+        st = lib().eth_batch_solve(self._h, ctypes.byref(o), B, X, infos)
+        if st < 0:
+            raise EthError(st, lib().eth_batch_last_error(self._h).decode())
+        return xs, [infos[i].as_dict() for i in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for p in self.problems:
+                p._h = None
+            lib().eth_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
