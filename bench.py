@@ -83,6 +83,124 @@ def cpu_baseline(n, iterations_per_solve, cpu_iters):
     }
 
 
+def bench_oseen(n, nu, prec, steps, rtol, maxit=1000):
+    """Two-stage PCD FGMRES(50) on the recirculating-wind Oseen problem."""
+    import torch
+    from paper_2303_10233_amd import eth
+    from paper_2303_10233_amd.workloads import recirculating_wind
+    w = torch.as_tensor(recirculating_wind(n), dtype=torch.float64, device="cuda:0")
+    t0 = time.perf_counter()
+    P = eth.Problem(n, domain=(-1.0, 1.0, -1.0, 1.0), nu=nu, kind=eth.OSEEN, wind=w, precision=prec)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    b = P.assemble_rhs()
+    x, info = P.solve(b, rtol=rtol, maxit=maxit, method=eth.TWO_STAGE)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, info = P.solve(b, rtol=rtol, maxit=maxit, method=eth.TWO_STAGE, out=x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    i = info[0]
+    P.close()
+    return dict(n=n, nu=nu, solves_per_s=round(1.0 / dt, 4), ms_per_solve=round(1e3 * dt, 3),
+                iterations=i["iterations"], stage1_iterations=i["stage1_iterations"],
+                rel_residual=i["rel_residual_true"], status=i["status"], setup_s=round(setup, 3))
+
+
+def bench_batch(n, nrhs, prec, steps, rtol):
+    """Lockstep MINRES over nrhs bump-forced right-hand sides on one mesh."""
+    import torch
+    from paper_2303_10233_amd import eth
+    from paper_2303_10233_amd.workloads import gaussian_bumps
+    P = eth.Problem(n, precision=prec, max_batch=nrhs)
+    F = torch.stack([torch.as_tensor(gaussian_bumps(n, 1000 + k), dtype=torch.float64, device="cuda:0")
+                     for k in range(nrhs)])
+    B = P.assemble_rhs(F, batch=nrhs)
+    X = torch.empty_like(B)
+    P.solve(B, rtol=rtol, maxit=2000, use_graph=True, out=X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = P.solve(B, rtol=rtol, maxit=2000, use_graph=True, out=X)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    its = [i["iterations"] for i in info]
+    P.close()
+    return dict(n=n, rhs=nrhs, solves_per_s=round(nrhs / dt, 3), ms_per_batch=round(1e3 * dt, 3),
+                iterations_max=max(its), iterations_min=min(its),
+                all_converged=all(i["status"] == 0 for i in info))
+
+
+def bench_ragged(prec, steps, rtol):
+    """32 cavities n_i = 32 + 16 (i mod 15) solved together."""
+    import torch
+    from paper_2303_10233_amd import eth
+    sizes = [32 + 16 * (i % 15) for i in range(32)]
+    t0 = time.perf_counter()
+    R = eth.RaggedBatch(sizes, precision=prec)
+    setup = time.perf_counter() - t0
+    bs = R.assemble_rhs()
+    xs, infos = R.solve(bs, rtol=rtol, maxit=2000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xs, infos = R.solve(bs, rtol=rtol, maxit=2000, out=xs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # the same problems one after another on one stream, for comparison
+    t0 = time.perf_counter()
+    for p, b, x in zip(R.problems, bs, xs):
+        p.solve(b, rtol=rtol, maxit=2000, use_graph=True, out=x)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    dofs = sum(p.N for p in R.problems)
+    R.close()
+    return dict(cavities=len(sizes), total_dofs=dofs, solves_per_s=round(len(sizes) / dt, 3),
+                ms_per_batch=round(1e3 * dt, 3), ms_sequential=round(1e3 * seq, 3),
+                iterations_max=max(i["iterations"] for i in infos),
+                all_converged=all(i["status"] == 0 for i in infos), setup_s=round(setup, 2))
+
+
+def microbench(reps):
+    """Kernel bandwidth at sizes whose vectors exceed the 256 MB Infinity Cache:
+    Stokes n = 2048 (one FP64 vector 336 MB) and n = 512 x 16 right-hand sides,
+    Oseen n = 2048.  Algorithmic bytes per launch / average launch time."""
+    import torch
+    from paper_2303_10233_amd import eth
+    from paper_2303_10233_amd.workloads import recirculating_wind
+    out = []
+    stokes_k = [eth.K_SADDLE_APPLY, eth.K_CHEB_STEP, eth.K_RESTRICT, eth.K_PROLONG, eth.K_MQ_CHEB_STEP,
+                eth.K_DOT, eth.K_MINRES_V, eth.K_MINRES_WX]
+    cases = [("stokes", 2048, 1, eth.FP64), ("stokes", 2048, 1, eth.MIXED),
+             ("stokes", 512, 16, eth.FP64), ("stokes", 512, 16, eth.MIXED),
+             ("oseen", 2048, 1, eth.FP64), ("oseen", 2048, 1, eth.MIXED)]
+    for kind, n, nrhs, prec in cases:
+        if kind == "stokes":
+            P = eth.Problem(n, precision=prec, max_batch=nrhs)
+            ks = stokes_k if prec == eth.FP64 else [eth.K_CHEB_STEP, eth.K_RESTRICT, eth.K_PROLONG,
+                                                     eth.K_MQ_CHEB_STEP]
+        else:
+            w = torch.as_tensor(recirculating_wind(n), dtype=torch.float64, device="cuda:0")
+            P = eth.Problem(n, domain=(-1.0, 1.0, -1.0, 1.0), nu=0.01, kind=eth.OSEEN, wind=w,
+                            precision=prec, max_batch=nrhs)
+            ks = ([eth.K_OSEEN_APPLY, eth.K_CD_STEP, eth.K_GM_MDOT, eth.K_GM_MAXPY] if prec == eth.FP64
+                  else [eth.K_CD_STEP])
+        torch.cuda.synchronize()
+        for k in ks:
+            ms, by = P.profile_kernel(k, reps=reps, batch=nrhs)
+            gbs = by / (ms * 1e-3) / 1e9
+            out.append(dict(workload=f"{kind} n={n} rhs={nrhs}", precision="mixed" if prec else "fp64",
+                            kernel=eth.KERNEL_NAMES[k], avg_us=round(1e3 * ms, 2), bytes=by,
+                            gbs=round(gbs, 1), frac=round(gbs / MI355X_HBM_GBS, 4)))
+            log(f"micro {kind} n={n} x{nrhs} {out[-1]['precision']} {out[-1]['kernel']}: "
+                f"{out[-1]['avg_us']} us, {out[-1]['gbs']} GB/s")
+        P.close()
+        del P
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +212,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--profile-reps", type=int, default=50)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the Oseen, 64-RHS and ragged-batch measurements")
+    ap.add_argument("--extra-steps", type=int, default=3)
+    ap.add_argument("--no-micro", action="store_true",
+                    help="skip the kernel bandwidth measurements at n = 2048 and 512 x 16")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -152,6 +275,30 @@ def main():
     log("kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us {v['gbs']:.0f}GB/s"
                                 for k, v in kernels.items()))
 
+    extra = None
+    if not args.no_extra:
+        extra = {"oseen": [], "batch64": {}, "ragged": {}}
+        for on in (128, 256):
+            for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+                r = bench_oseen(on, 0.01, prec, args.extra_steps, args.rtol)
+                r["precision"] = name
+                extra["oseen"].append(r)
+                log(f"oseen n={on} nu=1/100 {name}: {r['solves_per_s']} solves/s, "
+                    f"{r['iterations']} its ({r['stage1_iterations']} stage I)")
+        r = bench_oseen(128, 0.001, eth.MIXED, 1, args.rtol, maxit=300)
+        r["precision"] = "mixed"
+        r["note"] = ("nu = 1/1000 (cell Peclet 15.6): the unstabilised damped-Jacobi F multigrid "
+                     "diverges; reported with maxit 300")
+        extra["oseen"].append(r)
+        log(f"oseen n=128 nu=1/1000: status {r['status']}, residual {r['rel_residual']:.2e}")
+        for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+            extra["batch64"][name] = bench_batch(128, 64, prec, args.extra_steps, args.rtol)
+            log(f"batch64 {name}: {extra['batch64'][name]}")
+            extra["ragged"][name] = bench_ragged(prec, args.extra_steps, args.rtol)
+            log(f"ragged {name}: {extra['ragged'][name]}")
+
+    micro = None if args.no_micro else microbench(20)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")
@@ -191,6 +338,8 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        "other_workloads": extra,
+        "microbench": micro,
     }
     print(json.dumps(out), flush=True)
 

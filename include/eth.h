@@ -232,7 +232,7 @@ const char* eth_batch_last_error(const eth_batch* b);
 int eth_batch_destroy(eth_batch* b);
 
 /* Kernel timing for roofline reporting.  Launches `reps` times the kernel
- * `kernel` (ETH_K_*) exactly as one MINRES iteration launches it (same grid,
+ * `kernel` (ETH_K_*) exactly as one Krylov iteration launches it (same grid,
  * same workspaces, finest level where a hierarchy is involved), between two
  * HIP events recorded on the problem's stream, after a prior eth_solve has
  * filled the workspaces.  Returns the average duration of one launch in
@@ -246,6 +246,10 @@ int eth_batch_destroy(eth_batch* b);
 #define ETH_K_DOT            5   /* a6: deterministic dot product over N              */
 #define ETH_K_MINRES_V       6   /* a6: Lanczos vector update                         */
 #define ETH_K_MINRES_WX      7   /* a6: w / x update                                  */
+#define ETH_K_OSEEN_APPLY    8   /* a2: K x for Oseen, fused <Kx, x> partials          */
+#define ETH_K_CD_STEP        9   /* a3: damped-Jacobi step on F, finest level          */
+#define ETH_K_GM_MDOT       10   /* a7: CGS multi-dot against m/2 Arnoldi vectors      */
+#define ETH_K_GM_MAXPY      11   /* a7: CGS update with m/2 Arnoldi vectors            */
 int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, double* avg_ms,
                        double* bytes);
 

@@ -66,12 +66,11 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // Reduction context: every block of right-hand side `rhs` writes one partial
-// (or `nvals` partials) and takes a ticket; the last block sums the partials
-// in block order and hands the totals to an epilogue.
+// (or `nvals` partials); a second kernel sums them in block order and hands
+// the totals to an epilogue (eth_reduce.h).
 constexpr int kMaxRedVals = 4;
 struct RedCtx {
   double* partials;    // [batch][nvals][nblocks]
-  unsigned* tickets;   // [batch], zero between launches (reset by last block)
   double* result;      // [batch][nvals] totals (may be null)
   int nblocks;         // blocks per right-hand side
   int nvals;           // values reduced per block (<= kMaxRedVals)

@@ -29,6 +29,11 @@ inline ClearFlag no_clear() { return ClearFlag{nullptr, 0}; }
 // y = K x on the full layout, FP64.  mode 0: boundary velocity inputs are
 // masked, boundary rows of y are 0.  Optional fused reduction of <y, x>.
 int saddle_blocks(const Geo& g);
+// node-parallel apply (k_apply.hip): wind == nullptr for Stokes; blocks per RHS
+int apply_blocks(const Geo& g);
+void launch_apply(const Geo& g, double nu, const double* wind, int transpose, const double* x, double* y,
+                  long long ld, int batch, Gate gate, const RedCtx* dot, hipStream_t st,
+                  ClearFlag clear = no_clear());
 void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, long long ld,
                          int batch, Gate gate, const RedCtx* dot, hipStream_t st,
                          ClearFlag clear = no_clear());
@@ -45,6 +50,10 @@ void launch_dirichlet_lid(const Geo& g, double lid_u, int corner_mode, double* u
                           hipStream_t st);
 
 // ---------------- vector kernels (k_vector.hip) ------------------------------
+// Second stage of a reduction (eth_reduce.h): totals of the block partials in
+// block order, result and epilogue; nothing to do for a single block.  Every
+// launcher of a reducing kernel calls it right after the kernel.
+void launch_reduce_finish(const RedCtx& rc, int batch, Gate gate, hipStream_t st);
 void launch_dot(long long n, const double* x, const double* y, long long ld, int batch,
                 const RedCtx& rc, Gate gate, hipStream_t st);
 int dot_blocks(long long n);
@@ -71,7 +80,7 @@ void launch_residual_init(const Geo& g, const double* b, const double* y, double
                           long long ld, int batch, hipStream_t st);
 // pressure block sums (p_k, p_0) per RHS -> out[2*rhs + {0,1}]
 void launch_pressure_sums(const Geo& g, const double* x, long long ld, int batch,
-                          double* partials, unsigned* tickets, double* out, hipStream_t st);
+                          double* partials, double* out, hipStream_t st);
 void launch_pressure_shift(const Geo& g, double* x, long long ld, int batch,
                            const double* sums, hipStream_t st);
 
@@ -195,16 +204,17 @@ void launch_grad_viscosity(const Geo& g, const double* lam, long long ldl, const
 
 // ---------------- FGMRES (k_gmres.hip) ----------------------------------------
 int gmres_blocks(long long N);
-// partials: 64 * gmres_blocks(N) doubles per RHS; tickets: one per RHS
+// partials: 64 * gmres_blocks(N) doubles per RHS.  Each reduction is a
+// partial-sum kernel followed by a one-block-per-RHS finish kernel.
 void launch_gm_mdot(long long N, int nv, const double* V, const double* w, long long ld, int batch,
-                    double* partials, unsigned* tickets, GmresScalars* S, int which, hipStream_t st);
+                    double* partials, GmresScalars* S, int which, hipStream_t st);
 void launch_gm_maxpy(long long N, int nv, const double* V, double* w, long long ld, int batch,
                      const GmresScalars* S, int which, hipStream_t st);
 void launch_gm_norm_givens(long long N, int j, const double* w, long long ld, int batch, double* partials,
-                           unsigned* tickets, GmresScalars* S, hipStream_t st);
+                           GmresScalars* S, hipStream_t st);
 void launch_gm_scale(long long N, double* v, long long ld, int batch, const GmresScalars* S, hipStream_t st);
-void launch_gm_beta(long long N, const double* v, long long ld, int batch, double* partials,
-                    unsigned* tickets, GmresScalars* S, hipStream_t st);
+void launch_gm_beta(long long N, const double* v, long long ld, int batch, double* partials, GmresScalars* S,
+                    hipStream_t st);
 void launch_gm_finish(long long N, const double* Z, double* x, long long ld, int batch, GmresScalars* S,
                       hipStream_t st);
 void launch_gm_zero_range(double* x, long long ld, long long off, long long count, int batch,

@@ -108,7 +108,6 @@ struct Problem {
   double* d_hist = nullptr;
   int hist_len = 0;
   double* red_partials = nullptr;
-  unsigned* red_tickets = nullptr;
   double* red_result = nullptr;      // batch * 4
   double* h_red = nullptr;           // pinned
   double* ub = nullptr;              // Dirichlet data (2 nv)
@@ -128,7 +127,6 @@ struct Problem {
   std::vector<double> q1a, q1b;             // Chebyshev coefficients for Q_1 (Wathen interval)
   int gm_m = 0;
   double *gV = nullptr, *gZ = nullptr, *gArr = nullptr, *gpart = nullptr, *ghist = nullptr;
-  unsigned* gtick = nullptr;
   GmresScalars* d_gm = nullptr;
   GmresScalars* h_gm = nullptr;
   std::vector<double> h_bnorm;
@@ -166,7 +164,6 @@ struct Problem {
   RedCtx red(int nblocks, int nvals, int epi, void* state, double* result = nullptr) {
     RedCtx rc{};
     rc.partials = red_partials;
-    rc.tickets = red_tickets;
     rc.result = result;
     rc.nblocks = nblocks;
     rc.nvals = nvals;
@@ -314,10 +311,8 @@ void Problem::setup(const eth_problem_desc& desc) {
   const int maxblocks =
       std::max(std::max(std::max(dot_blocks(g.N), saddle_blocks(g)), adjoint_blocks(g)), 4096);
   red_partials = alloc<double>((size_t)maxblocks * kMaxRedVals * max_batch);
-  red_tickets = alloc<unsigned>(max_batch);
   red_result = alloc<double>((size_t)kMaxRedVals * max_batch);
   ETH_HIP(hipHostMalloc((void**)&h_red, sizeof(double) * kMaxRedVals * max_batch, hipHostMallocDefault));
-  ETH_HIP(hipMemsetAsync(red_tickets, 0, sizeof(unsigned) * max_batch, st));
   ETH_HIP(hipMemsetAsync(d_ms, 0, sizeof(MinresScalars) * max_batch, st));
   ub = alloc<double>(2 * (size_t)g.nv);
   launch_dirichlet_lid(g, d.lid_u, d.corner_mode, ub, st);
@@ -652,7 +647,7 @@ void Problem::load_rhs(const double* b, long long ld, int batch, bool adjoint) {
   launch_copy(g.N, b, ld, kb, ldw, batch, st);
   launch_zero_boundary(g, kb, ldw, batch, st);
   if (adjoint) {
-    launch_pressure_sums(g, kb, ldw, batch, red_partials, red_tickets, red_result, st);
+    launch_pressure_sums(g, kb, ldw, batch, red_partials, red_result, st);
     launch_pressure_shift(g, kb, ldw, batch, red_result, st);
   }
 }
@@ -751,7 +746,7 @@ bool Problem::minres_poll(MinresRun& R, bool block) {
   launch_copy(g.N, kx, ldw, R.x, R.ld, batch, st);
   if (!R.adjoint) launch_copy_boundary(g, R.b, R.x, R.ld, batch, st);
   if (R.o.canonicalize) {
-    launch_pressure_sums(g, R.x, R.ld, batch, red_partials, red_tickets, red_result, st);
+    launch_pressure_sums(g, R.x, R.ld, batch, red_partials, red_result, st);
     launch_pressure_shift(g, R.x, R.ld, batch, red_result, st);
   }
   return true;
@@ -1015,9 +1010,7 @@ void Problem::build_gmres() {
   gZ = alloc<double>(vec * gm_m);
   const size_t per = (size_t)(gm_m + 1) * gm_m + 7 * 64;
   gArr = alloc<double>(per * max_batch);
-  gpart = alloc<double>((size_t)64 * 256 * max_batch);
-  gtick = alloc<unsigned>(max_batch);
-  ETH_HIP(hipMemsetAsync(gtick, 0, sizeof(unsigned) * max_batch, st));
+  gpart = alloc<double>((size_t)64 * gmres_blocks(g.N) * max_batch);
   ghist = alloc<double>((size_t)hist_len * max_batch);
   d_gm = alloc<GmresScalars>(max_batch);
   ETH_HIP(hipHostMalloc((void**)&h_gm, sizeof(GmresScalars) * max_batch, hipHostMallocDefault));
@@ -1196,16 +1189,16 @@ void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int
   for (int cycle = 0; cycle < 100000; ++cycle) {
     op(x, ky, no_gate());
     launch_residual_init(g, b, ky, V(0), ldw, batch, st);
-    launch_gm_beta(N, V(0), ldw, batch, gpart, gtick, d_gm, st);
+    launch_gm_beta(N, V(0), ldw, batch, gpart, d_gm, st);
     launch_gm_scale(N, V(0), ldw, batch, d_gm, st);
     for (int j = 0; j < m; ++j) {
       precond_oseen(kind, V(j), Z(j), batch, gate);
       op(Z(j), V(j + 1), gate);
-      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, gtick, d_gm, 0, st);
+      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, d_gm, 0, st);
       launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 0, st);
-      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, gtick, d_gm, 1, st);
+      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, d_gm, 1, st);
       launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 1, st);
-      launch_gm_norm_givens(N, j, V(j + 1), ldw, batch, gpart, gtick, d_gm, st);
+      launch_gm_norm_givens(N, j, V(j + 1), ldw, batch, gpart, d_gm, st);
       launch_gm_scale(N, V(j + 1), ldw, batch, d_gm, st);
       if ((j + 1) % 8 == 0 && j + 1 < m) {
         ETH_HIP(hipMemcpyAsync(h_gm, d_gm, sizeof(GmresScalars) * batch, hipMemcpyDeviceToHost, st));
@@ -1227,7 +1220,7 @@ void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int
       // confirm with the true residual of the final iterate
       op(x, ky, no_gate());
       launch_residual_init(g, b, ky, V(0), ldw, batch, st);
-      launch_gm_beta(N, V(0), ldw, batch, gpart, gtick, d_gm, st);
+      launch_gm_beta(N, V(0), ldw, batch, gpart, d_gm, st);
       ETH_HIP(hipMemcpyAsync(h_gm, d_gm, sizeof(GmresScalars) * batch, hipMemcpyDeviceToHost, st));
       ETH_HIP(hipStreamSynchronize(st));
       break;
@@ -1274,7 +1267,7 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
   launch_copy(g.N, kx, ldw, x, ld, batch, st);
   if (!adjoint) launch_copy_boundary(g, b, x, ld, batch, st);
   if (o.canonicalize) {
-    launch_pressure_sums(g, x, ld, batch, red_partials, red_tickets, red_result, st);
+    launch_pressure_sums(g, x, ld, batch, red_partials, red_result, st);
     launch_pressure_shift(g, x, ld, batch, red_result, st);
   }
   ETH_HIP(hipStreamSynchronize(st));
@@ -1789,6 +1782,66 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
           eth::launch_minres_wx(g.N, P.kz[0], P.kw[0], P.kw[1], P.ky, P.ldw, B, P.d_ms, P.st);
         };
         by = 48.0 * N * B;
+        break;
+      }
+      case ETH_K_OSEEN_APPLY: {
+        if (!P.oseen) throw std::runtime_error("unsupported:not an Oseen problem");
+        launch = [&] {
+          eth::RedCtx rd = P.red(eth::saddle_blocks(g), 1, eth::EPI_NONE, nullptr, P.red_result);
+          eth::launch_apply_oseen(g, P.d.nu, P.d.wind, 0, P.kz[0], P.ky, P.ldw, B, gate, &rd, P.st);
+        };
+        by = 16.0 * N * B + 16.0 * g.nv;   // x read, y written; the wind (2 planes) once
+        break;
+      }
+      case ETH_K_CD_STEP: {
+        if (!P.oseen || P.lv.empty()) throw std::runtime_error("unsupported:not an Oseen problem");
+        const eth::Geo& gf = P.lv[0];
+        launch = [&] {
+          if (P.mixed)
+            eth::launch_cd_step<float>(gf, P.lwind[0], P.ldF[0], P.d.nu, (float*)P.vb[0], (float*)P.vx[0],
+                                       (float*)P.vxo[0], P.d.gmg_omega, 0, 2 * B, nullptr, 0, 0.0, gate,
+                                       P.st);
+          else
+            eth::launch_cd_step<double>(gf, P.lwind[0], P.ldF[0], P.d.nu, (double*)P.vb[0],
+                                        (double*)P.vx[0], (double*)P.vxo[0], P.d.gmg_omega, 0, 2 * B,
+                                        nullptr, 0, 0.0, gate, P.st);
+        };
+        // per plane: read b, x, write x_new; the wind (2 planes) and diag(F) once
+        by = 2.0 * B * 3.0 * es * gf.nv + 24.0 * gf.nv;
+        break;
+      }
+      case ETH_K_GM_MDOT:
+      case ETH_K_GM_MAXPY: {
+        if (!P.oseen) throw std::runtime_error("unsupported:not an Oseen problem");
+        const int nvec = std::max(1, P.gm_m / 2);   // the average Arnoldi position of a cycle
+        const size_t per = (size_t)(P.gm_m + 1) * P.gm_m + 7 * 64;
+        for (int r = 0; r < B; ++r) {
+          eth::GmresScalars& G = P.h_gm[r];
+          std::memset(&G, 0, sizeof(G));
+          G.active = 1;
+          G.m = P.gm_m;
+          double* base = P.gArr + per * r;
+          G.H = base;
+          G.cs = base + (size_t)(P.gm_m + 1) * P.gm_m;
+          G.sn = G.cs + 64;
+          G.g = G.sn + 64;
+          G.y = G.g + 64;
+          G.h1 = G.y + 64;
+          G.h2 = G.h1 + 64;
+        }
+        ETH_HIP(hipMemcpyAsync(P.d_gm, P.h_gm, sizeof(eth::GmresScalars) * B, hipMemcpyHostToDevice, P.st));
+        ETH_HIP(hipMemsetAsync(P.gV, 0, sizeof(double) * P.ldw * B * (nvec + 1), P.st));
+        double* w = P.gV + (size_t)nvec * B * P.ldw;
+        if (kernel == ETH_K_GM_MDOT) {
+          launch = [&, nvec, w] {
+            eth::launch_gm_mdot(g.N, nvec, P.gV, w, P.ldw, B, P.gpart, P.d_gm, 0, P.st);
+          };
+          by = 8.0 * N * B * (nvec + 1);
+        } else {
+          eth::launch_gm_mdot(g.N, nvec, P.gV, w, P.ldw, B, P.gpart, P.d_gm, 0, P.st);
+          launch = [&, nvec, w] { eth::launch_gm_maxpy(g.N, nvec, P.gV, w, P.ldw, B, P.d_gm, 0, P.st); };
+          by = 8.0 * N * B * (nvec + 2);
+        }
         break;
       }
       default:

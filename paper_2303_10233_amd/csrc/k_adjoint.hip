@@ -125,6 +125,7 @@ void launch_velocity_mass(const Geo& g, const double* x, long long ldx, const do
   else
     hipLaunchKernelGGL(k_velocity_mass<false>, grid, dim3(NT), 0, st, g, x, ldx, xt, ldt, y, ldy, rc, reduce);
   ETH_LAUNCH_CHECK();
+  if (reduce) launch_reduce_finish(rc, batch, no_gate(), st);
 }
 
 void launch_grad_viscosity(const Geo& g, const double* lam, long long ldl, const double* x, long long ldx,
@@ -134,6 +135,7 @@ void launch_grad_viscosity(const Geo& g, const double* lam, long long ldl, const
   rc.nblocks = (int)(grid.x * grid.y);
   hipLaunchKernelGGL(k_grad_viscosity, grid, dim3(NT), 0, st, g, lam, ldl, x, ldx, rc);
   ETH_LAUNCH_CHECK();
+  launch_reduce_finish(rc, batch, no_gate(), st);
 }
 
 }  // namespace eth

@@ -19,27 +19,12 @@ __device__ inline const double* vec(const double* base, int i, int batch, int rh
   return base + ((long long)i * batch + rhs) * ld;
 }
 
-// Deterministic block partial -> last block sums in block order -> out[k]
-__device__ inline bool take_ticket(unsigned* tickets, int rhs, int nblocks, int* s_last) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned t = atomicAdd(&tickets[rhs], 1u);
-    *s_last = (t == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  if (*s_last) __threadfence();
-  return *s_last != 0;
-}
-
-// h_i = <v_i, w> for i = 0..nv-1  (written to out[rhs*stride + i])
+// h_i = <v_i, w> for i = 0..nv-1: block partials P[i * nb + block]
 __global__ __launch_bounds__(NT) void k_gm_mdot(long long N, int nv, const double* __restrict__ V,
                                                 const double* __restrict__ w, long long ld, int batch,
                                                 double* __restrict__ partials,
-                                                unsigned* __restrict__ tickets,
-                                                GmresScalars* __restrict__ S, int which) {
+                                                const GmresScalars* __restrict__ S) {
   __shared__ double sred[NT / 64];
-  __shared__ int s_last;
   const int rhs = blockIdx.y;
   if (!S[rhs].active) return;
   const double* wr = w + (long long)rhs * ld;
@@ -59,21 +44,49 @@ __global__ __launch_bounds__(NT) void k_gm_mdot(long long N, int nv, const doubl
     for (int c = 0; c < CH; ++c) {
       if (i0 + c >= nv) break;
       const double t = block_sum<NT>(acc[c], sred);
-      if (threadIdx.x == 0)
-        __hip_atomic_store(&P[(long long)(i0 + c) * nb + blockIdx.x], t, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x == 0) P[(long long)(i0 + c) * nb + blockIdx.x] = t;
     }
   }
-  if (!take_ticket(tickets, rhs, nb, &s_last)) return;
+}
+
+// the multi-dot totals in block order, one wave per coefficient
+__global__ __launch_bounds__(NT) void k_gm_mdot_finish(int nv, int nb, const double* __restrict__ partials,
+                                                       GmresScalars* __restrict__ S, int which) {
+  const int rhs = blockIdx.x;
+  if (!S[rhs].active) return;
+  const double* P = partials + (long long)rhs * 64 * nb;
   double* out = which == 0 ? S[rhs].h1 : S[rhs].h2;
-  for (int i = 0; i < nv; ++i) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nv; i += NT / 64) {
     double a = 0.0;
-    for (int b = threadIdx.x; b < nb; b += NT)
-      a += __hip_atomic_load(&P[(long long)i * nb + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a = block_sum<NT>(a, sred);
-    if (threadIdx.x == 0) out[i] = a;
+    for (int b = lane; b < nb; b += 64) a += P[(long long)i * nb + b];
+    a = wave_sum(a);
+    if (lane == 0) out[i] = a;
   }
-  if (threadIdx.x == 0) tickets[rhs] = 0u;
+}
+
+// block partials of ||w||^2; mode 0: RHS whose Arnoldi step runs, mode 1:
+// RHS not yet converged (restart)
+__global__ __launch_bounds__(NT) void k_gm_sumsq(long long N, const double* __restrict__ w, long long ld,
+                                                 double* __restrict__ partials,
+                                                 const GmresScalars* __restrict__ S, int mode) {
+  __shared__ double sred[NT / 64];
+  const int rhs = blockIdx.y;
+  const GmresScalars& G = S[rhs];
+  if (mode == 0 ? !G.active : (G.converged || G.status < 0)) return;
+  const double* wr = w + (long long)rhs * ld;
+  const int nb = gridDim.x;
+  double a = 0.0;
+  for (long long k = (long long)blockIdx.x * NT + threadIdx.x; k < N; k += (long long)nb * NT)
+    a += wr[k] * wr[k];
+  const double t = block_sum<NT>(a, sred);
+  if (threadIdx.x == 0) partials[(long long)rhs * 64 * nb + blockIdx.x] = t;
+}
+
+__device__ inline double sum_partials(const double* __restrict__ P, int nb, double* sred) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NT) s += P[b];
+  return block_sum<NT>(s, sred);
 }
 
 // w -= sum_{i<nv} c_i v_i   (c = h1 or h2 of the record)
@@ -94,32 +107,16 @@ __global__ void k_gm_maxpy(long long N, int nv, const double* __restrict__ V, do
   }
 }
 
-// ||w||^2, then the Givens step for column j of the Hessenberg matrix
-__global__ __launch_bounds__(NT) void k_gm_norm_givens(long long N, int j, const double* __restrict__ w,
-                                                       long long ld, double* __restrict__ partials,
-                                                       unsigned* __restrict__ tickets,
-                                                       GmresScalars* __restrict__ S) {
+// ||w||^2 from the partials, then the Givens step for column j of the
+// Hessenberg matrix
+__global__ __launch_bounds__(NT) void k_gm_givens(int j, int nb, const double* __restrict__ partials,
+                                                  GmresScalars* __restrict__ S) {
   __shared__ double sred[NT / 64];
-  __shared__ int s_last;
-  const int rhs = blockIdx.y;
+  const int rhs = blockIdx.x;
   GmresScalars& G = S[rhs];
   if (!G.active) return;
-  const double* wr = w + (long long)rhs * ld;
-  const int nb = gridDim.x;
-  double a = 0.0;
-  for (long long k = (long long)blockIdx.x * NT + threadIdx.x; k < N; k += (long long)nb * NT)
-    a += wr[k] * wr[k];
-  const double t = block_sum<NT>(a, sred);
-  double* P = partials + (long long)rhs * 64 * nb;
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&P[blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!take_ticket(tickets, rhs, nb, &s_last)) return;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += NT)
-    s += __hip_atomic_load(&P[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  s = block_sum<NT>(s, sred);
+  const double s = sum_partials(partials + (long long)rhs * 64 * nb, nb, sred);
   if (threadIdx.x != 0) return;
-  tickets[rhs] = 0u;
   const int m1 = G.m + 1;
   double* Hc = G.H + (long long)j * m1;
   for (int i = 0; i <= j; ++i) Hc[i] = G.h1[i] + G.h2[i];
@@ -170,31 +167,14 @@ __global__ void k_gm_scale(long long N, double* __restrict__ v, long long ld, co
 }
 
 // restart: beta = ||r_0|| -> g = [beta, 0, ...], convergence test, flags
-__global__ __launch_bounds__(NT) void k_gm_beta(long long N, const double* __restrict__ v, long long ld,
-                                                double* __restrict__ partials,
-                                                unsigned* __restrict__ tickets,
+__global__ __launch_bounds__(NT) void k_gm_beta(int nb, const double* __restrict__ partials,
                                                 GmresScalars* __restrict__ S) {
   __shared__ double sred[NT / 64];
-  __shared__ int s_last;
-  const int rhs = blockIdx.y;
+  const int rhs = blockIdx.x;
   GmresScalars& G = S[rhs];
   if (G.converged || G.status < 0) return;
-  const double* vr = v + (long long)rhs * ld;
-  const int nb = gridDim.x;
-  double a = 0.0;
-  for (long long k = (long long)blockIdx.x * NT + threadIdx.x; k < N; k += (long long)nb * NT)
-    a += vr[k] * vr[k];
-  const double t = block_sum<NT>(a, sred);
-  double* P = partials + (long long)rhs * 64 * nb;
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&P[blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!take_ticket(tickets, rhs, nb, &s_last)) return;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += NT)
-    s += __hip_atomic_load(&P[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  s = block_sum<NT>(s, sred);
+  const double s = sum_partials(partials + (long long)rhs * 64 * nb, nb, sred);
   if (threadIdx.x != 0) return;
-  tickets[rhs] = 0u;
   const double beta = sqrt(s);
   G.beta = beta;
   G.res = beta;
@@ -262,9 +242,11 @@ __global__ void k_gm_zero_range(double* __restrict__ x, long long ld, long long 
     x[(long long)rhs * ld + off + k] = 0.0;
 }
 
+constexpr int kGmBlocksMax = 1024;   // partial sums per RHS: 64 * kGmBlocksMax
+
 unsigned blocks(long long n) {
   long long b = (n + 1023) / 1024;
-  return (unsigned)(b < 1 ? 1 : (b > 256 ? 256 : b));
+  return (unsigned)(b < 1 ? 1 : (b > kGmBlocksMax ? kGmBlocksMax : b));
 }
 
 }  // namespace
@@ -272,9 +254,11 @@ unsigned blocks(long long n) {
 int gmres_blocks(long long N) { return (int)blocks(N); }
 
 void launch_gm_mdot(long long N, int nv, const double* V, const double* w, long long ld, int batch,
-                    double* partials, unsigned* tickets, GmresScalars* S, int which, hipStream_t st) {
-  hipLaunchKernelGGL(k_gm_mdot, dim3(blocks(N), batch), dim3(NT), 0, st, N, nv, V, w, ld, batch, partials,
-                     tickets, S, which);
+                    double* partials, GmresScalars* S, int which, hipStream_t st) {
+  const unsigned nb = blocks(N);
+  hipLaunchKernelGGL(k_gm_mdot, dim3(nb, batch), dim3(NT), 0, st, N, nv, V, w, ld, batch, partials, S);
+  ETH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gm_mdot_finish, dim3(batch), dim3(NT), 0, st, nv, (int)nb, partials, S, which);
   ETH_LAUNCH_CHECK();
 }
 void launch_gm_maxpy(long long N, int nv, const double* V, double* w, long long ld, int batch,
@@ -283,18 +267,23 @@ void launch_gm_maxpy(long long N, int nv, const double* V, double* w, long long 
   ETH_LAUNCH_CHECK();
 }
 void launch_gm_norm_givens(long long N, int j, const double* w, long long ld, int batch, double* partials,
-                           unsigned* tickets, GmresScalars* S, hipStream_t st) {
-  hipLaunchKernelGGL(k_gm_norm_givens, dim3(blocks(N), batch), dim3(NT), 0, st, N, j, w, ld, partials,
-                     tickets, S);
+                           GmresScalars* S, hipStream_t st) {
+  const unsigned nb = blocks(N);
+  hipLaunchKernelGGL(k_gm_sumsq, dim3(nb, batch), dim3(NT), 0, st, N, w, ld, partials, S, 0);
+  ETH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gm_givens, dim3(batch), dim3(NT), 0, st, j, (int)nb, partials, S);
   ETH_LAUNCH_CHECK();
 }
 void launch_gm_scale(long long N, double* v, long long ld, int batch, const GmresScalars* S, hipStream_t st) {
   hipLaunchKernelGGL(k_gm_scale, dim3(blocks(N), batch), dim3(256), 0, st, N, v, ld, S, 0);
   ETH_LAUNCH_CHECK();
 }
-void launch_gm_beta(long long N, const double* v, long long ld, int batch, double* partials,
-                    unsigned* tickets, GmresScalars* S, hipStream_t st) {
-  hipLaunchKernelGGL(k_gm_beta, dim3(blocks(N), batch), dim3(NT), 0, st, N, v, ld, partials, tickets, S);
+void launch_gm_beta(long long N, const double* v, long long ld, int batch, double* partials, GmresScalars* S,
+                    hipStream_t st) {
+  const unsigned nb = blocks(N);
+  hipLaunchKernelGGL(k_gm_sumsq, dim3(nb, batch), dim3(NT), 0, st, N, v, ld, partials, S, 1);
+  ETH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gm_beta, dim3(batch), dim3(NT), 0, st, (int)nb, partials, S);
   ETH_LAUNCH_CHECK();
 }
 void launch_gm_finish(long long N, const double* Z, double* x, long long ld, int batch, GmresScalars* S,

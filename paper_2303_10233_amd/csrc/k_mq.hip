@@ -337,6 +337,7 @@ void launch_mq_diag_dot(const Geo& g, const double* r, long long ld, int batch, 
                         Gate gate, hipStream_t st) {
   hipLaunchKernelGGL(k_mq_diag_dot, dim3(rc.nblocks, batch), dim3(NT), 0, st, g, r, ld, rc, gate);
   ETH_LAUNCH_CHECK();
+  launch_reduce_finish(rc, batch, gate, st);
 }
 
 void launch_mq_diag_apply(const Geo& g, const double* r, double* z, long long ld, int batch,
@@ -352,6 +353,7 @@ void launch_mq_kdot(const Geo& g, const T* x, long long ldx, long long off, int 
                     const RedCtx& rc, Gate gate, hipStream_t st) {
   hipLaunchKernelGGL(k_mq_kdot<T>, dim3(rc.nblocks, batch), dim3(NT), 0, st, g, x, ldx, off, rc, gate);
   ETH_LAUNCH_CHECK();
+  launch_reduce_finish(rc, batch, gate, st);
 }
 
 template <typename T>

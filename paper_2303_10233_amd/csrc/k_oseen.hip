@@ -628,6 +628,7 @@ template <typename T>
 void launch_q1_sum(const Geo& g, const T* x, const RedCtx& rc, int batch, Gate gate, hipStream_t st) {
   hipLaunchKernelGGL(k_q1_sum<T>, dim3(rc.nblocks, batch), dim3(256), 0, st, g, x, rc, gate);
   ETH_LAUNCH_CHECK();
+  launch_reduce_finish(rc, batch, gate, st);
 }
 template <typename TI, typename TO>
 void launch_q1_shift(const Geo& g, const TI* x, long long ldx, long long offx, TO* out, long long ldo,

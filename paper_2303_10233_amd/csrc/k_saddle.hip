@@ -339,23 +339,11 @@ __global__ void k_dirichlet_lid(Geo g, double lid_u, int corner_mode, double* ub
 
 }  // namespace
 
-int saddle_blocks(const Geo& g) {
-  return ((g.n + 1 + TX - 1) / TX) * ((g.n + 1 + TY - 1) / TY);
-}
+int saddle_blocks(const Geo& g) { return apply_blocks(g); }
 
 void launch_apply_stokes(const Geo& g, double nu, const double* x, double* y, long long ld,
                          int batch, Gate gate, const RedCtx* dot, hipStream_t st, ClearFlag clear) {
-  dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, batch);
-  dim3 block(TX, TY);
-  if (dot) {
-    hipLaunchKernelGGL((k_saddle<0, true, false, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                       nullptr, 0LL, nullptr, gate, *dot, clear);
-  } else {
-    RedCtx none{};
-    hipLaunchKernelGGL((k_saddle<0, false, false, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                       nullptr, 0LL, nullptr, gate, none, clear);
-  }
-  ETH_LAUNCH_CHECK();
+  launch_apply(g, nu, nullptr, 0, x, y, ld, batch, gate, dot, st, clear);
 }
 
 void launch_lift_rhs(const Geo& g, double nu, const double* wind, const double* ub,
@@ -377,26 +365,7 @@ void launch_lift_rhs(const Geo& g, double nu, const double* wind, const double* 
 void launch_apply_oseen(const Geo& g, double nu, const double* wind, int transpose,
                         const double* x, double* y, long long ld, int batch, Gate gate,
                         const RedCtx* dot, hipStream_t st, ClearFlag clear) {
-  dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, batch);
-  dim3 block(TX, TY);
-  RedCtx none{};
-  const RedCtx rc = dot ? *dot : none;
-  if (transpose) {
-    if (dot)
-      hipLaunchKernelGGL((k_saddle<0, true, true, true>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                         nullptr, 0LL, wind, gate, rc, clear);
-    else
-      hipLaunchKernelGGL((k_saddle<0, false, true, true>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                         nullptr, 0LL, wind, gate, rc, clear);
-  } else {
-    if (dot)
-      hipLaunchKernelGGL((k_saddle<0, true, true, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                         nullptr, 0LL, wind, gate, rc, clear);
-    else
-      hipLaunchKernelGGL((k_saddle<0, false, true, false>), grid, block, 0, st, g, nu, x, ld, y, ld,
-                         nullptr, 0LL, wind, gate, rc, clear);
-  }
-  ETH_LAUNCH_CHECK();
+  launch_apply(g, nu, wind, transpose, x, y, ld, batch, gate, dot, st, clear);
 }
 
 void launch_dirichlet_lid(const Geo& g, double lid_u, int corner_mode, double* ub,

@@ -7,7 +7,7 @@ namespace eth {
 namespace {
 
 constexpr int NT = 256;
-constexpr int kVecBlocksMax = 256;    // grid-stride cap per RHS for reductions
+constexpr int kVecBlocksMax = 512;    // grid-stride cap per RHS for reductions
 
 __global__ __launch_bounds__(NT) void k_dot(long long n, const double* __restrict__ x,
                                             const double* __restrict__ y, long long ld,
@@ -17,10 +17,18 @@ __global__ __launch_bounds__(NT) void k_dot(long long n, const double* __restric
   if (gate.off(rhs)) return;
   const double* xr = x + (long long)rhs * ld;
   const double* yr = y + (long long)rhs * ld;
-  double a = 0.0;
-  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
-    a += xr[i] * yr[i];
-  double v[1] = {a};
+  // four independent partial sums keep four loads of each vector in flight
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const long long stride = (long long)gridDim.x * NT;
+  long long i = (long long)blockIdx.x * NT + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    a0 += xr[i] * yr[i];
+    a1 += xr[i + stride] * yr[i + stride];
+    a2 += xr[i + 2 * stride] * yr[i + 2 * stride];
+    a3 += xr[i + 3 * stride] * yr[i + 3 * stride];
+  }
+  for (; i < n; i += stride) a0 += xr[i] * yr[i];
+  double v[1] = {(a0 + a1) + (a2 + a3)};
   reduce_and_finish<NT>(rc, rhs, blockIdx.x, v, sred);
 }
 
@@ -149,9 +157,33 @@ __global__ void k_pressure_shift(Geo g, double* __restrict__ x, long long ld,
   x[(long long)rhs * ld + g.off_pk() + i] -= m;
 }
 
+__global__ __launch_bounds__(NT) void k_reduce_finish(RedCtx rc, Gate gate) {
+  __shared__ double sred[NT / 64];
+  const int rhs = blockIdx.x;
+  if (gate.off(rhs)) return;
+  double tot[kMaxRedVals];
+  for (int k = 0; k < rc.nvals; ++k) {
+    const double* p = rc.partials + ((long long)rhs * rc.nvals + k) * rc.nblocks;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < rc.nblocks; i += NT) a += p[i];
+    tot[k] = block_sum<NT>(a, sred);
+  }
+  if (threadIdx.x == 0) {
+    if (rc.result)
+      for (int k = 0; k < rc.nvals; ++k) rc.result[(long long)rhs * rc.nvals + k] = tot[k];
+    if (rc.epi) run_epilogue(rc.epi, rc.epi_state, rhs, tot);
+  }
+}
+
 inline unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
 
 }  // namespace
+
+void launch_reduce_finish(const RedCtx& rc, int batch, Gate gate, hipStream_t st) {
+  if (rc.nblocks <= 1) return;
+  hipLaunchKernelGGL(k_reduce_finish, dim3(batch), dim3(NT), 0, st, rc, gate);
+  ETH_LAUNCH_CHECK();
+}
 
 int dot_blocks(long long n) {
   long long b = (n + NT * 4 - 1) / (NT * 4);
@@ -164,6 +196,7 @@ void launch_dot(long long n, const double* x, const double* y, long long ld, int
                 const RedCtx& rc, Gate gate, hipStream_t st) {
   hipLaunchKernelGGL(k_dot, dim3(rc.nblocks, batch), dim3(NT), 0, st, n, x, y, ld, rc, gate);
   ETH_LAUNCH_CHECK();
+  launch_reduce_finish(rc, batch, gate, st);
 }
 
 void launch_axpby(long long n, double a, const double* x, double b, double* y, long long ld,
@@ -230,15 +263,15 @@ void launch_minres_wx(long long n, const double* z, double* wprev_io, const doub
 }
 
 void launch_pressure_sums(const Geo& g, const double* x, long long ld, int batch,
-                          double* partials, unsigned* tickets, double* out, hipStream_t st) {
+                          double* partials, double* out, hipStream_t st) {
   RedCtx rc{};
   rc.partials = partials;
-  rc.tickets = tickets;
   rc.result = out;
   rc.nblocks = dot_blocks((long long)g.nk + g.n0);
   rc.nvals = 2;
   hipLaunchKernelGGL(k_pressure_sums, dim3(rc.nblocks, batch), dim3(NT), 0, st, g, x, ld, rc);
   ETH_LAUNCH_CHECK();
+  launch_reduce_finish(rc, batch, no_gate(), st);
 }
 
 void launch_pressure_shift(const Geo& g, double* x, long long ld, int batch,
