@@ -110,6 +110,23 @@ void launch_dense_solve(const Geo& g, const double* Ainv, int ni, const T* b, T*
                         int nplanes, double* out64, long long ld64, double out_scale,
                         const double* in64, long long ldin, double* gbuf, int batch, Gate gate,
                         hipStream_t st);
+// the coarse end of a V-cycle in one launch (levels with at most 65^2 nodes,
+// one block of 1024 threads per plane, all levels in LDS): tl.n[0] is the level
+// whose b (restricted residual) and x (first Chebyshev step) are given in
+// b0/x0; x0 receives the level's corrected iterate after post-smoothing
+constexpr int kTailMaxLevels = 8;
+struct TailLevels {
+  int nlev;                          // levels in the tail, the last one solved densely
+  int deg;                           // Chebyshev degree per side
+  int n[kTailMaxLevels];             // elements per side of each level
+  double ca[kTailMaxLevels][4], cb[kTailMaxLevels][4];   // Chebyshev coefficients
+};
+size_t vcycle_tail_lds(const TailLevels& tl, size_t elem);
+template <typename T>
+void launch_vcycle_tail(const TailLevels& tl, const double* Ainv, int ni, const T* b0, T* x0, int nplanes,
+                        Gate gate, hipStream_t st);
+template <typename T>
+hipError_t prepare_vcycle_tail(size_t lds);   // allows the dynamic LDS size
 // dense Laplacian of the interior nodes, and Gauss-Jordan inverse helpers
 void launch_dense_laplacian(const Geo& g, double* A, int ni, hipStream_t st);
 void launch_gj_step(double* aug, int ni, int k, double* colbuf, double* rowbuf,

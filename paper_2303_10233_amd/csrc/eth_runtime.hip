@@ -90,6 +90,8 @@ struct Problem {
   int coarse_ni = 0;
   double* dense_gbuf = nullptr;
   std::vector<void*> vb, vx, vxo;    // per-level plane buffers (T)
+  TailLevels tail{};                 // levels handled by the fused coarse V-cycle
+  int tail_l0 = -1;                  // its first level (-1: per-level launches)
 
   // pressure preconditioner
   void *mq_r = nullptr, *mq_z = nullptr, *mq_t = nullptr, *mq_d = nullptr;
@@ -443,6 +445,39 @@ void Problem::build_velocity() {
       }
     }
   }
+  // fused coarse end of the V-cycle: from the first level below the finest
+  // with at most 32 elements per side, when it fits in LDS and the coarsest
+  // dense solve is small
+  tail_l0 = -1;
+  bool allow = true;
+  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_VCYCLE")) allow = (e[0] != '1');
+  int l0 = -1;
+  for (int l = 1; l < L; ++l)
+    if (lv[l].n <= 32) {
+      l0 = l;
+      break;
+    }
+  if (allow && l0 >= 1 && l0 <= L - 2 && L - l0 <= kTailMaxLevels && d.gmg_degree <= 4 && coarse_ni <= 289) {
+    TailLevels t{};
+    t.nlev = L - l0;
+    t.deg = d.gmg_degree;
+    for (int l = l0; l < L; ++l) {
+      t.n[l - l0] = lv[l].n;
+      if (l + 1 < L)
+        for (int k = 0; k < d.gmg_degree; ++k) {
+          t.ca[l - l0][k] = ca[l][k];
+          t.cb[l - l0][k] = cb[l][k];
+        }
+    }
+    const size_t lds = vcycle_tail_lds(t, mixed ? sizeof(float) : sizeof(double));
+    const hipError_t e = mixed ? prepare_vcycle_tail<float>(lds) : prepare_vcycle_tail<double>(lds);
+    if (lds <= 160 * 1024 && e == hipSuccess) {
+      tail = t;
+      tail_l0 = l0;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
 }
 
 void Problem::build_pressure() {
@@ -509,7 +544,9 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
   const int deg = d.gmg_degree;
   // finest level: b = r_u, first smoothing step from zero
   launch_vcycle_entry<T>(lv[0], r, ld, b[0], x[0], cb[0][0], batch, gate, st);
-  for (int l = 0; l + 1 < L; ++l) {
+  // levels below `lstop` are handled by the fused coarse kernel when enabled
+  const int lstop = tail_l0 >= 1 ? tail_l0 : L - 1;
+  for (int l = 0; l < lstop; ++l) {
     for (int k = 1; k < deg; ++k) {
       launch_cheb_step<T>(lv[l], b[l], x[l], xo[l], ca[l][k], cb[l][k], k == 1 ? 2 : 1, np,
                           nullptr, 0, 0.0, gate, batch, st);
@@ -518,9 +555,12 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
     const double beta_c = (l + 1 < L - 1) ? cb[l + 1][0] : 0.0;
     launch_restrict<T>(lv[l], lv[l + 1], b[l], x[l], b[l + 1], x[l + 1], beta_c, np, batch, gate, st);
   }
-  launch_dense_solve<T>(lv[L - 1], Ainv, coarse_ni, b[L - 1], x[L - 1], np, nullptr, 0, 0.0,
-                        nullptr, 0, dense_gbuf, batch, gate, st);
-  for (int l = L - 2; l >= 0; --l) {
+  if (tail_l0 >= 1)
+    launch_vcycle_tail<T>(tail, Ainv, coarse_ni, b[lstop], x[lstop], np, gate, st);
+  else
+    launch_dense_solve<T>(lv[L - 1], Ainv, coarse_ni, b[L - 1], x[L - 1], np, nullptr, 0, 0.0,
+                          nullptr, 0, dense_gbuf, batch, gate, st);
+  for (int l = lstop - 1; l >= 0; --l) {
     launch_prolong_add<T>(lv[l], lv[l + 1], x[l + 1], x[l], np, batch, gate, st);
     for (int k = 0; k < deg; ++k) {
       const bool last = (l == 0 && k == deg - 1);

@@ -199,6 +199,25 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   }
 }
 
+// 1-D Q2 prolongation weights of fine node F: the coarse nodes and weights
+// (injection at even F, (3/8, 3/4, -1/8) or its mirror at odd F); returns the count
+__device__ __forceinline__ int prolong_weights(int F, int* idx, double* w) {
+  if ((F & 1) == 0) {
+    idx[0] = F >> 1;
+    w[0] = 1.0;
+    return 1;
+  }
+  const int k = (F - 1) >> 1;
+  if ((k & 1) == 0) {
+    idx[0] = k; idx[1] = k + 1; idx[2] = k + 2;
+    w[0] = 0.375; w[1] = 0.75; w[2] = -0.125;
+  } else {
+    idx[0] = k - 1; idx[1] = k; idx[2] = k + 1;
+    w[0] = -0.125; w[1] = 0.75; w[2] = 0.375;
+  }
+  return 3;
+}
+
 // x_f += P x_c on interior fine nodes
 template <typename T>
 __global__ void k_prolong_add(Geo gf, Geo gc, const T* __restrict__ xc, T* __restrict__ xf,
@@ -211,24 +230,7 @@ __global__ void k_prolong_add(Geo gf, Geo gc, const T* __restrict__ xc, T* __res
   if (I <= 0 || J <= 0 || I >= topf || J >= topf) return;
   int ix[3], iy[3];
   double wx[3], wy[3];
-  int cntx, cnty;
-  auto weights = [](int F, int* idx, double* w, int& cnt) {
-    if ((F & 1) == 0) {
-      idx[0] = F >> 1; w[0] = 1.0; cnt = 1;
-      return;
-    }
-    const int k = (F - 1) >> 1;
-    cnt = 3;
-    if ((k & 1) == 0) {
-      idx[0] = k; idx[1] = k + 1; idx[2] = k + 2;
-      w[0] = 0.375; w[1] = 0.75; w[2] = -0.125;
-    } else {
-      idx[0] = k - 1; idx[1] = k; idx[2] = k + 1;
-      w[0] = -0.125; w[1] = 0.75; w[2] = 0.375;
-    }
-  };
-  weights(I, ix, wx, cntx);
-  weights(J, iy, wy, cnty);
+  const int cntx = prolong_weights(I, ix, wx), cnty = prolong_weights(J, iy, wy);
   const long long pc = (long long)plane * gc.nv;
   double acc = 0.0;
   for (int b = 0; b < cnty; ++b) {
@@ -314,6 +316,206 @@ __global__ void k_zero_plane_boundary(Geo g, T* __restrict__ x, Gate gate) {
   else if (k < 3 * m) node = m * nq + (m - (k - 2 * m));
   else node = (m - (k - 3 * m)) * nq;
   x[(long long)plane * g.nv + node] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// The coarse end of the V-cycle in one launch: levels l0 .. L-1 (all with at
+// most 65^2 nodes) of one plane live in LDS for the whole descent and ascent,
+// so the ~25 launches of the small levels (each a few microseconds of fixed
+// cost) become one.  Per level: the remaining pre-smoothing Chebyshev steps,
+// residual + restriction (with the first step of the next level), the dense
+// coarsest solve, and on the way up prolongation + post-smoothing; the
+// arithmetic of every node is that of the per-level kernels above.
+// ---------------------------------------------------------------------------
+constexpr int TAIL_NT = 1024;
+
+// 90 * (A u) at interior node (I, J) of a level with row pitch nq (LDS, no
+// halo).  The +-2 offsets of a mid node carry zero weights and would fall
+// outside the level's array next to the boundary, so they are not read.
+template <typename T>
+__device__ __forceinline__ double lap90_rt(const T* s, int nq, int I, int J) {
+  double kx[5], mx[5], ky[5], my[5];
+  const int pi = I & 1, pj = J & 1;
+  k1row(pi, kx); m1row(pi, mx); k1row(pj, ky); m1row(pj, my);
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    if (pj && (b == 0 || b == 4)) continue;
+    double tk = 0.0, tm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      if (pi && (a == 0 || a == 4)) continue;
+      const double u = (double)s[(J + b - 2) * nq + (I + a - 2)];
+      tk += kx[a] * u;
+      tm += mx[a] * u;
+    }
+    acc += my[b] * tk + ky[b] * tm;
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ void tail_cheb(const T* b, const T* x, T* xo, int nq, double alpha, double beta, int has_prev) {
+  const int top = nq - 1, nv = nq * nq;
+  for (int k = threadIdx.x; k < nv; k += TAIL_NT) {
+    const int I = k % nq, J = k / nq;
+    double xn = 0.0;
+    if (I > 0 && J > 0 && I < top && J < top) {
+      const double xc = (double)x[k];
+      const double res = (double)b[k] - lap90_rt(x, nq, I, J) / 90.0;
+      xn = xc + beta * res * (90.0 / diag90(I & 1, J & 1));
+      if (has_prev == 1) xn += alpha * (xc - (double)xo[k]);
+      else if (has_prev == 2) xn += alpha * xc;
+    }
+    xo[k] = (T)xn;
+  }
+  __syncthreads();
+}
+
+// LDS layout of the tail: per level [b | x_A | x_B] (nv values each); which of
+// x_A / x_B holds the current iterate is one bit per level in `flip`
+__device__ __forceinline__ int tail_base(const TailLevels& tl, int l) {
+  int off = 0;
+  for (int k = 0; k < l; ++k) off += 3 * (2 * tl.n[k] + 1) * (2 * tl.n[k] + 1);
+  return off;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TAIL_NT) void k_vcycle_tail(TailLevels tl, const double* __restrict__ Ainv,
+                                                         int ni, const T* __restrict__ b0,
+                                                         T* __restrict__ x0, Gate gate) {
+  extern __shared__ __align__(16) unsigned char tail_smem[];
+  T* sm = reinterpret_cast<T*>(tail_smem);
+  const int plane = blockIdx.x;
+  if (gate.off(plane >> 1)) return;
+  const int nl = tl.nlev, deg = tl.deg;
+  unsigned flip = 0u;
+  auto nqof = [&](int l) { return 2 * tl.n[l] + 1; };
+  auto Bp = [&](int l) { return sm + tail_base(tl, l); };
+  auto Xp = [&](int l) {
+    const int nv = nqof(l) * nqof(l);
+    return sm + tail_base(tl, l) + nv * (((flip >> l) & 1u) ? 2 : 1);
+  };
+  auto XOp = [&](int l) {
+    const int nv = nqof(l) * nqof(l);
+    return sm + tail_base(tl, l) + nv * (((flip >> l) & 1u) ? 1 : 2);
+  };
+  {
+    const int nq = nqof(0), nv = nq * nq;
+    const long long po = (long long)plane * nv;
+    T* B = Bp(0);
+    T* X = Xp(0);
+    for (int k = threadIdx.x; k < nv; k += TAIL_NT) {
+      B[k] = b0[po + k];
+      X[k] = x0[po + k];
+    }
+  }
+  __syncthreads();
+  // descent
+  for (int l = 0; l + 1 < nl; ++l) {
+    const int nq = nqof(l), top = nq - 1, nv = nq * nq;
+    for (int k = 1; k < deg; ++k) {
+      tail_cheb(Bp(l), Xp(l), XOp(l), nq, tl.ca[l][k], tl.cb[l][k], k == 1 ? 2 : 1);
+      flip ^= (1u << l);
+    }
+    // residual into the spare iterate buffer, then restriction with the
+    // first step of level l+1
+    {
+      const T* B = Bp(l);
+      const T* X = Xp(l);
+      T* R = XOp(l);
+      for (int k = threadIdx.x; k < nv; k += TAIL_NT) {
+        const int I = k % nq, J = k / nq;
+        double r = 0.0;
+        if (I > 0 && J > 0 && I < top && J < top) r = (double)B[k] - lap90_rt(X, nq, I, J) / 90.0;
+        R[k] = (T)r;
+      }
+    }
+    __syncthreads();
+    {
+      const T* R = XOp(l);
+      T* Bc = Bp(l + 1);
+      T* Xc = Xp(l + 1);
+      const int nqc = nqof(l + 1), topc = nqc - 1, nvc = nqc * nqc;
+      const double beta_c = (l + 2 < nl) ? tl.cb[l + 1][0] : 0.0;
+      for (int k = threadIdx.x; k < nvc; k += TAIL_NT) {
+        const int Ic = k % nqc, Jc = k / nqc;
+        if (Ic == 0 || Jc == 0 || Ic == topc || Jc == topc) {
+          Bc[k] = T(0);
+          Xc[k] = T(0);
+          continue;
+        }
+        const int pi = Ic & 1, pj = Jc & 1;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = -3; q <= 3; ++q) {
+          const double wy = rw8(pj, q);
+          if (wy == 0.0) continue;
+          const int J = 2 * Jc + q;
+          double t = 0.0;
+#pragma unroll
+          for (int o2 = -3; o2 <= 3; ++o2) {
+            const int I = 2 * Ic + o2;
+            if (I < 0 || I > top || J < 0 || J > top) continue;
+            t += rw8(pi, o2) * (double)R[J * nq + I];
+          }
+          acc += wy * t;
+        }
+        acc *= (1.0 / 64.0);
+        Bc[k] = (T)acc;
+        Xc[k] = (T)(beta_c * acc * 90.0 / diag90(pi, pj));
+      }
+    }
+    __syncthreads();
+  }
+  // coarsest level: x = Ainv b on the interior nodes
+  {
+    const int l = nl - 1;
+    const int nq = nqof(l), m = nq - 2;
+    const T* B = Bp(l);
+    T* X = Xp(l);
+    for (int i = threadIdx.x; i < ni; i += TAIL_NT) {
+      const double* a = Ainv + (long long)i * ni;
+      double s0 = 0.0;
+      for (int j = 0; j < ni; ++j) s0 += a[j] * (double)B[(1 + j / m) * nq + 1 + j % m];
+      X[(1 + i / m) * nq + 1 + i % m] = (T)s0;
+    }
+    __syncthreads();
+  }
+  // ascent
+  for (int l = nl - 2; l >= 0; --l) {
+    const int nq = nqof(l), top = nq - 1, nv = nq * nq;
+    const int nqc = nqof(l + 1);
+    {
+      const T* Xc = Xp(l + 1);
+      T* X = Xp(l);
+      for (int k = threadIdx.x; k < nv; k += TAIL_NT) {
+        const int I = k % nq, J = k / nq;
+        if (I <= 0 || J <= 0 || I >= top || J >= top) continue;
+        int ix[3], iy[3];
+        double wx[3], wy[3];
+        const int cx = prolong_weights(I, ix, wx), cy = prolong_weights(J, iy, wy);
+        double acc = 0.0;
+        for (int b = 0; b < cy; ++b) {
+          double t = 0.0;
+          for (int a = 0; a < cx; ++a) t += wx[a] * (double)Xc[iy[b] * nqc + ix[a]];
+          acc += wy[b] * t;
+        }
+        X[k] = (T)((double)X[k] + acc);
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < deg; ++k) {
+      tail_cheb(Bp(l), Xp(l), XOp(l), nq, tl.ca[l][k], tl.cb[l][k], k == 0 ? 0 : 1);
+      flip ^= (1u << l);
+    }
+  }
+  {
+    const int nq = nqof(0), nv = nq * nq;
+    const long long po = (long long)plane * nv;
+    const T* X = Xp(0);
+    for (int k = threadIdx.x; k < nv; k += TAIL_NT) x0[po + k] = X[k];
+  }
 }
 
 // ---- setup helpers (FP64) ----
@@ -454,6 +656,26 @@ void launch_dense_solve(const Geo& g, const double* Ainv, int ni, const T* b, T*
   }
 }
 
+size_t vcycle_tail_lds(const TailLevels& tl, size_t elem) {
+  size_t v = 0;
+  for (int l = 0; l < tl.nlev; ++l) v += 3 * (size_t)(2 * tl.n[l] + 1) * (2 * tl.n[l] + 1);
+  return v * elem;
+}
+
+template <typename T>
+void launch_vcycle_tail(const TailLevels& tl, const double* Ainv, int ni, const T* b0, T* x0, int nplanes,
+                        Gate gate, hipStream_t st) {
+  const size_t lds = vcycle_tail_lds(tl, sizeof(T));
+  hipLaunchKernelGGL(k_vcycle_tail<T>, dim3(nplanes), dim3(TAIL_NT), lds, st, tl, Ainv, ni, b0, x0, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t prepare_vcycle_tail(size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail<T>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 void launch_dense_laplacian(const Geo& g, double* A, int ni, hipStream_t st) {
   const long long n = (long long)ni * ni;
   hipLaunchKernelGGL(k_dense_laplacian, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, A, ni);
@@ -495,7 +717,10 @@ void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStre
                                       hipStream_t);                                              \
   template void launch_dense_solve<T>(const Geo&, const double*, int, const T*, T*, int, double*, \
                                       long long, double, const double*, long long, double*, int,  \
-                                      Gate, hipStream_t);
+                                      Gate, hipStream_t);                                         \
+  template void launch_vcycle_tail<T>(const TailLevels&, const double*, int, const T*, T*, int,    \
+                                      Gate, hipStream_t);                                         \
+  template hipError_t prepare_vcycle_tail<T>(size_t);
 ETH_INST(double)
 ETH_INST(float)
 #undef ETH_INST

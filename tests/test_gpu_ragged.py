@@ -29,19 +29,22 @@ def test_ragged_equals_standalone(prec, graph):
     print(f"[ragged] sizes={sizes} prec={prec} graph={graph}", flush=True)
     R = eth.RaggedBatch(sizes, precision=prec)
     bs = R.assemble_rhs()
-    xs, infos = R.solve(bs, rtol=1e-10, maxit=2000, use_graph=graph, true_residual=True)
+    # an FP32 preconditioner is symmetric only to FP32 rounding: ask mixed
+    # precision for the configured 1e-6, FP64 for 1e-10
+    rtol = 1e-10 if prec == eth.FP64 else 1e-6
+    xs, infos = R.solve(bs, rtol=rtol, maxit=2000, use_graph=graph, true_residual=True)
     torch.cuda.synchronize()
     for n, b, x, info in zip(sizes, bs, xs, infos):
         assert info["status"] == 0
         P = eth.Problem(n, precision=prec)
-        xr, ir = P.solve(P.assemble_rhs(), rtol=1e-10, maxit=2000, use_graph=graph)
+        xr, ir = P.solve(P.assemble_rhs(), rtol=rtol, maxit=2000, use_graph=graph)
         assert ir[0]["iterations"] == info["iterations"]
         assert torch.equal(x, xr)
-        assert info["rel_residual_true"] < 1e-8
+        assert info["rel_residual_true"] < 100 * rtol
     m = Mesh(8)
     s = System(m)
     xd = direct_solve(s, s.rhs(None, lid_dirichlet(m)))
-    assert rel_err(xs[0].cpu().numpy(), xd) < 1e-8
+    assert rel_err(xs[0].cpu().numpy(), xd) < (1e-8 if prec == eth.FP64 else 1e-4)
     R.close()
 
 

@@ -148,6 +148,26 @@ def test_preconditioner_matches_oracle(n, velocity, mq, prec, tol):
     assert np.abs(z[:o][s.vel_bnd]).max() == 0.0
 
 
+@pytest.mark.parametrize("n,prec,tol", [(128, eth.FP64, 1e-12), (48, eth.FP64, 1e-12),
+                                        (256, eth.MIXED, 1e-5), (96, eth.MIXED, 1e-5)])
+def test_fused_coarse_vcycle_equals_per_level_launches(n, prec, tol, monkeypatch):
+    """The coarse end of the V-cycle in one launch (levels <= 32^2 in LDS)
+    against one launch per level step: identical node arithmetic, so only the
+    coarsest dense product (summation order) differs."""
+    print(f"[fused vcycle] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    r = uniform_vector(m.N, 11 + n)
+    r[: 2 * m.nv][System(m).vel_bnd] = 0.0
+    P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_DIAG)
+    z_fused = _np(P.apply_preconditioner(_t(r)))
+    monkeypatch.setenv("ETH_DEBUG_UNFUSED_VCYCLE", "1")
+    Q = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_DIAG)
+    z_ref = _np(Q.apply_preconditioner(_t(r)))
+    o = 2 * m.nv
+    assert rel_err(z_fused[:o], z_ref[:o]) < tol
+    assert np.array_equal(z_fused[o:], z_ref[o:])
+
+
 @pytest.mark.parametrize("n,prec", [(16, eth.FP64), (66, eth.FP64), (64, eth.MIXED)])
 def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     """The temporally blocked Chebyshev-SGS kernel (nine colour passes in LDS
