@@ -65,6 +65,51 @@ __device__ inline double block_sum(double v, double* sh) {
   return t;
 }
 
+// ----------------------------------------------------------------------------
+// Staging of a tile into LDS with every global load issued before the first
+// LDS store: a grid-stride loop that loads and stores per iteration waits for
+// each load in turn, and at a few hundred nanoseconds per L2/HBM round trip
+// that serial chain dominates the small kernels.  load(k, a, b) fills the two
+// values of staged entry k (0 <= k < COUNT).
+// ----------------------------------------------------------------------------
+template <int NT, int COUNT, typename T, typename Load>
+__device__ __forceinline__ void stage2(T* __restrict__ d0, T* __restrict__ d1, int tid, Load load) {
+  constexpr int IT = (COUNT + NT - 1) / NT;
+  T a[IT], b[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int k = tid + i * NT;
+    a[i] = T(0);
+    b[i] = T(0);
+    if (k < COUNT) load(k, a[i], b[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int k = tid + i * NT;
+    if (k < COUNT) {
+      d0[k] = a[i];
+      d1[k] = b[i];
+    }
+  }
+}
+
+template <int NT, int COUNT, typename T, typename Load>
+__device__ __forceinline__ void stage1(T* __restrict__ d0, int tid, Load load) {
+  constexpr int IT = (COUNT + NT - 1) / NT;
+  T a[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int k = tid + i * NT;
+    a[i] = T(0);
+    if (k < COUNT) load(k, a[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int k = tid + i * NT;
+    if (k < COUNT) d0[k] = a[i];
+  }
+}
+
 // Reduction context: every block of right-hand side `rhs` writes one partial
 // (or `nvals` partials); a second kernel sums them in block order and hands
 // the totals to an epilogue (eth_reduce.h).

@@ -66,39 +66,33 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
   const double* xr = x + (long long)rhs * ld;
   double* yr = y + (long long)rhs * ld;
 
-  // ---- stage the patches (boundary velocity masked) ----
-  for (int k = tid; k < UX * UY; k += NTA) {
-    const int lx = k % UX, ly = k / UX;
-    const int I = I0 - 2 + lx, J = J0 - 2 + ly;
-    double vx = 0.0, vy = 0.0;
+  // ---- stage the patches (boundary velocity masked); all loads in flight ----
+  stage2<NTA, UX * UY>(&su[0][0][0], &su[1][0][0], tid, [&](int k, double& vx, double& vy) {
+    const int I = I0 - 2 + k % UX, J = J0 - 2 + k / UX;
     if (I >= 1 && I < top && J >= 1 && J < top) {
       const long long o = (long long)J * nq + I;
       vx = xr[o];
       vy = xr[g.nv + o];
     }
-    su[0][ly][lx] = vx;
-    su[1][ly][lx] = vy;
-    if constexpr (CONV) {
-      double w0 = 0.0, w1 = 0.0;
+  });
+  if constexpr (CONV) {
+    stage2<NTA, UX * UY>(&sw[0][0][0], &sw[1][0][0], tid, [&](int k, double& w0, double& w1) {
+      const int I = I0 - 2 + k % UX, J = J0 - 2 + k / UX;
       if (I >= 0 && I <= top && J >= 0 && J <= top) {
         const long long o = (long long)J * nq + I;
         w0 = wind[o];
         w1 = wind[g.nv + o];
       }
-      sw[0][ly][lx] = w0;
-      sw[1][ly][lx] = w1;
-    }
+    });
   }
-  for (int k = tid; k < QX * QY; k += NTA) {
-    const int lx = k % QX, ly = k / QX;
-    const int c = c0 - 1 + lx, d = d0 - 1 + ly;
-    spk[ly][lx] = (c >= 0 && c <= n && d >= 0 && d <= n) ? xr[g.off_pk() + (long long)d * (n + 1) + c] : 0.0;
-  }
-  for (int k = tid; k < EXP * EYP; k += NTA) {
-    const int lx = k % EXP, ly = k / EXP;
-    const int e = c0 - 1 + lx, f = d0 - 1 + ly;
-    sp0[ly][lx] = (e >= 0 && e < n && f >= 0 && f < n) ? xr[g.off_p0() + (long long)f * n + e] : 0.0;
-  }
+  stage1<NTA, QX * QY>(&spk[0][0], tid, [&](int k, double& v) {
+    const int c = c0 - 1 + k % QX, d = d0 - 1 + k / QX;
+    if (c >= 0 && c <= n && d >= 0 && d <= n) v = xr[g.off_pk() + (long long)d * (n + 1) + c];
+  });
+  stage1<NTA, EXP * EYP>(&sp0[0][0], tid, [&](int k, double& v) {
+    const int e = c0 - 1 + k % EXP, f = d0 - 1 + k / EXP;
+    if (e >= 0 && e < n && f >= 0 && f < n) v = xr[g.off_p0() + (long long)f * n + e];
+  });
   if (off) return;   // uniform per block; the gate load overlapped the staging loads
   __syncthreads();
 

@@ -68,11 +68,10 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
   const long long po = (long long)plane * g.nv;
   const int I0 = blockIdx.x * NX, J0 = blockIdx.y * NY;
   const int tid = threadIdx.x;
-  for (int k = tid; k < HX * HY; k += NT) {
-    const int lx = k % HX, ly = k / HX;
-    const int I = I0 + lx - 2, J = J0 + ly - 2;
-    s[k] = (I >= 0 && I <= top && J >= 0 && J <= top) ? x[po + (long long)J * nq + I] : T(0);
-  }
+  stage1<NT, HX * HY>(s, tid, [&](int k, T& v) {
+    const int I = I0 + k % HX - 2, J = J0 + k / HX - 2;
+    if (I >= 0 && I <= top && J >= 0 && J <= top) v = x[po + (long long)J * nq + I];
+  });
   __syncthreads();
   const int tx = tid & 63, ty = tid >> 6;
   const int I = I0 + tx;
@@ -152,20 +151,34 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   const int C0x = blockIdx.x * CT, C0y = blockIdx.y * CT;
   const int F0x = 2 * C0x - 3, F0y = 2 * C0y - 3;     // residual patch origin
   const int tid = threadIdx.x;
-  if constexpr (!RES_GIVEN) {
-    for (int k = tid; k < XF * XF; k += NT) {
-      const int lx = k % XF, ly = k / XF;
-      const int I = F0x - 2 + lx, J = F0y - 2 + ly;
-      sx[k] = (I >= 0 && I <= topf && J >= 0 && J <= topf) ? xf[pf + (long long)J * nqf + I] : T(0);
+  // fine right-hand side of the residual patch, loaded before anything waits
+  constexpr int RIT = (RF * RF + NT - 1) / NT;
+  T bv[RIT];
+#pragma unroll
+  for (int i = 0; i < RIT; ++i) {
+    const int k = tid + i * NT;
+    bv[i] = T(0);
+    if (k < RF * RF) {
+      const int I = F0x + k % RF, J = F0y + k / RF;
+      if (I > 0 && I < topf && J > 0 && J < topf) bv[i] = bf[pf + (long long)J * nqf + I];
     }
+  }
+  if constexpr (!RES_GIVEN) {
+    stage1<NT, XF * XF>(sx, tid, [&](int k, T& v) {
+      const int I = F0x - 2 + k % XF, J = F0y - 2 + k / XF;
+      if (I >= 0 && I <= topf && J >= 0 && J <= topf) v = xf[pf + (long long)J * nqf + I];
+    });
     __syncthreads();
   }
-  for (int k = tid; k < RF * RF; k += NT) {
+#pragma unroll
+  for (int i = 0; i < RIT; ++i) {
+    const int k = tid + i * NT;
+    if (k >= RF * RF) break;
     const int lx = k % RF, ly = k / RF;
     const int I = F0x + lx, J = F0y + ly;
     double r = 0.0;
     if (I > 0 && I < topf && J > 0 && J < topf) {
-      r = (double)bf[pf + (long long)J * nqf + I];
+      r = (double)bv[i];
       if constexpr (!RES_GIVEN) r -= lap90<T, XF>(sx, lx + 2, ly + 2, I & 1, J & 1) / 90.0;
     }
     sr[k] = r;
@@ -405,9 +418,23 @@ __global__ __launch_bounds__(TAIL_NT) void k_vcycle_tail(TailLevels tl, const do
     const long long po = (long long)plane * nv;
     T* B = Bp(0);
     T* X = Xp(0);
-    for (int k = threadIdx.x; k < nv; k += TAIL_NT) {
-      B[k] = b0[po + k];
-      X[k] = x0[po + k];
+    constexpr int IT = 5;   // issue five pairs of loads before the stores
+    for (int k0 = threadIdx.x; k0 < nv; k0 += IT * TAIL_NT) {
+      T bv[IT], xv[IT];
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int k = k0 + i * TAIL_NT;
+        bv[i] = k < nv ? b0[po + k] : T(0);
+        xv[i] = k < nv ? x0[po + k] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int k = k0 + i * TAIL_NT;
+        if (k < nv) {
+          B[k] = bv[i];
+          X[k] = xv[i];
+        }
+      }
     }
   }
   __syncthreads();

@@ -40,6 +40,8 @@ __device__ __forceinline__ double mq_diag(const Geo& g, long long i) {
 template <typename T>
 __device__ __forceinline__ T q1_gs_update(T t, T r, const T* tq9, const T* te4, int Lx, int Rx,
                                           int Ly, int Ry, T h2_36, T h2_4, T inv_h2_9) {
+  // no fused multiply-adds: the fused and the per-colour kernels must round alike
+#pragma clang fp contract(off)
   const T wx0 = T(Lx), wx1 = T(2 * (Lx + Rx)), wx2 = T(Rx);
   const T wy0 = T(Ly), wy1 = T(2 * (Ly + Ry)), wy2 = T(Ry);
   const T s0 = wx0 * tq9[0] + wx1 * tq9[1] + wx2 * tq9[2];
@@ -55,6 +57,7 @@ __device__ __forceinline__ T q1_gs_update(T t, T r, const T* tq9, const T* te4, 
 // the four vertex values)/4
 template <typename T>
 __device__ __forceinline__ T p0_gs_update(T r, T v00, T v10, T v01, T v11, T inv_h2) {
+#pragma clang fp contract(off)
   return r * inv_h2 - T(0.25) * ((v00 + v10) + (v01 + v11));
 }
 
@@ -171,6 +174,16 @@ __global__ void k_mq_colour(Geo g, const T* __restrict__ r, T* __restrict__ t, i
   }
 }
 
+// Chebyshev combination of one entry: s = t - z0, d = first ? b s : a d + b s;
+// returns z0 + d (the new d in dn)
+template <typename T>
+__device__ __forceinline__ T cheb_combine(T t, T z0, T d, T a, T b, int first, T& dn) {
+#pragma clang fp contract(off)
+  const T sv = t - z0;
+  dn = first ? b * sv : a * d + b * sv;
+  return z0 + dn;
+}
+
 // s = t - z;  d = first ? b*s : a*d + b*s;  z += d;  t = z
 template <typename T>
 __global__ void k_mq_cheb_combine(Geo g, T* __restrict__ t, T* __restrict__ z, T* __restrict__ d,
@@ -183,9 +196,8 @@ __global__ void k_mq_cheb_combine(Geo g, T* __restrict__ t, T* __restrict__ z, T
   const long long o = (long long)rhs * np + i;
   const T ta = T(a), tb = T(b);
   const T z0 = first ? T(0) : z[o];
-  const T sv = t[o] - z0;
-  const T dn = first ? tb * sv : ta * d[o] + tb * sv;
-  const T zn = z0 + dn;
+  T dn;
+  const T zn = cheb_combine<T>(t[o], z0, first ? T(0) : d[o], ta, tb, first, dn);
   d[o] = dn;
   z[o] = zn;
   t[o] = zn;
@@ -246,30 +258,40 @@ __global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict
   const T h2_36 = T(h2 / 36.0), h2_4 = T(0.25 * h2), inv_h2_9 = T(9.0 / h2), inv_h2 = T(1.0 / h2);
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * 32 + tx;
-  for (int k = tid; k < RQ * RQ; k += FT) {
-    const int lx = k % RQ, ly = k / RQ;
-    const int c = gx + lx, dd = gy + ly;
-    T tv = T(0), rv = T(0);
+  T* zo = zout + (long long)rhs * np;
+  T* dr = d + (long long)rhs * np;
+  // the owned node / element values of z_k and d, fetched before the staging
+  // so that their latency overlaps it
+  const int oc = c0 + tx, od = d0 + ty;
+  const bool own_q = (oc <= n && od <= n), own_e = (oc < n && od < n);
+  const long long oq = (long long)od * (n + 1) + oc, oe = g.nk + (long long)od * n + oc;
+  T z0q = T(0), d0q = T(0), z0e = T(0), d0e = T(0);
+  if (!first) {
+    if (own_q) {
+      z0q = zi[oq];
+      d0q = dr[oq];
+    }
+    if (own_e) {
+      z0e = zi[oe];
+      d0e = dr[oe];
+    }
+  }
+  stage2<FT, RQ * RQ>(tq, rq, tid, [&](int k, T& tv, T& rv) {
+    const int c = gx + k % RQ, dd = gy + k / RQ;
     if (c >= 0 && c <= n && dd >= 0 && dd <= n) {
       const long long q = (long long)dd * (n + 1) + c;
       rv = rr[q];
       if (!first) tv = zi[q];
     }
-    tq[k] = tv;
-    rq[k] = rv;
-  }
-  for (int k = tid; k < RE * RE; k += FT) {
-    const int lx = k % RE, ly = k / RE;
-    const int e = gx + lx, f = gy + ly;
-    T tv = T(0), rv = T(0);
+  });
+  stage2<FT, RE * RE>(te, re, tid, [&](int k, T& tv, T& rv) {
+    const int e = gx + k % RE, f = gy + k / RE;
     if (e >= 0 && e < n && f >= 0 && f < n) {
       const long long q = g.nk + (long long)f * n + e;
       rv = rr[q];
       if (!first) tv = zi[q];
     }
-    te[k] = tv;
-    re[k] = rv;
-  }
+  });
   __syncthreads();
   constexpr int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
 #pragma unroll 1
@@ -305,27 +327,18 @@ __global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict
     __syncthreads();
   }
   // Chebyshev combination on the owned nodes and elements (one each per thread)
-  T* zo = zout + (long long)rhs * np;
-  T* dr = d + (long long)rhs * np;
   const T ta = T(a), tb = T(b);
-  {
-    const int c = c0 + tx, dd = d0 + ty;
-    if (c <= n && dd <= n) {
-      const long long q = (long long)dd * (n + 1) + c;
-      const T z0 = first ? T(0) : zi[q];
-      const T sv = tq[(ty + HALO) * RQ + (tx + HALO)] - z0;
-      const T dn = first ? tb * sv : ta * dr[q] + tb * sv;
-      dr[q] = dn;
-      zo[q] = z0 + dn;
-    }
-    if (c < n && dd < n) {
-      const long long q = g.nk + (long long)dd * n + c;
-      const T z0 = first ? T(0) : zi[q];
-      const T sv = te[(ty + HALO) * RE + (tx + HALO)] - z0;
-      const T dn = first ? tb * sv : ta * dr[q] + tb * sv;
-      dr[q] = dn;
-      zo[q] = z0 + dn;
-    }
+  if (own_q) {
+    T dn;
+    const T zn = cheb_combine<T>(tq[(ty + HALO) * RQ + (tx + HALO)], z0q, d0q, ta, tb, first, dn);
+    dr[oq] = dn;
+    zo[oq] = zn;
+  }
+  if (own_e) {
+    T dn;
+    const T zn = cheb_combine<T>(te[(ty + HALO) * RE + (tx + HALO)], z0e, d0e, ta, tb, first, dn);
+    dr[oe] = dn;
+    zo[oe] = zn;
   }
 }
 
