@@ -451,9 +451,11 @@ void Problem::build_velocity() {
   tail_l0 = -1;
   bool allow = true;
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_VCYCLE")) allow = (e[0] != '1');
+  int tail_max_n = 16;   // largest level (elements per side) inside the fused tail
+  if (const char* e = std::getenv("ETH_TAIL_MAX_N")) tail_max_n = std::max(2, std::min(32, std::atoi(e)));
   int l0 = -1;
   for (int l = 1; l < L; ++l)
-    if (lv[l].n <= 32) {
+    if (lv[l].n <= tail_max_n) {
       l0 = l;
       break;
     }

@@ -495,17 +495,20 @@ __global__ __launch_bounds__(TAIL_NT) void k_vcycle_tail(TailLevels tl, const do
     }
     __syncthreads();
   }
-  // coarsest level: x = Ainv b on the interior nodes
+  // coarsest level: x = Ainv b on the interior nodes, one wave per row and
+  // the lanes along the row (independent loads, a shuffle sum per row)
   {
     const int l = nl - 1;
     const int nq = nqof(l), m = nq - 2;
     const T* B = Bp(l);
     T* X = Xp(l);
-    for (int i = threadIdx.x; i < ni; i += TAIL_NT) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = wave; i < ni; i += TAIL_NT / 64) {
       const double* a = Ainv + (long long)i * ni;
       double s0 = 0.0;
-      for (int j = 0; j < ni; ++j) s0 += a[j] * (double)B[(1 + j / m) * nq + 1 + j % m];
-      X[(1 + i / m) * nq + 1 + i % m] = (T)s0;
+      for (int j = lane; j < ni; j += 64) s0 += a[j] * (double)B[(1 + j / m) * nq + 1 + j % m];
+      s0 = wave_sum(s0);
+      if (lane == 0) X[(1 + i / m) * nq + 1 + i % m] = (T)s0;
     }
     __syncthreads();
   }

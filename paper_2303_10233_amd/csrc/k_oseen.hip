@@ -140,20 +140,18 @@ __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict_
   const int n = g.n, nq = g.nq, top = 2 * n;
   const long long po = (long long)plane * g.nv;
   const int I0 = 2 * ex0 - 2, J0 = 2 * ey0 - 2;
-  for (int k = tid; k < VX * VY; k += NT) {
-    const int lx = k % VX, ly = k / VX;
-    const int I = I0 + lx, J = J0 + ly;
-    double xv = 0.0, w0 = 0.0, w1 = 0.0;
+  stage2<NT, VX * VY>(&sw[0][0][0], &sw[1][0][0], tid, [&](int k, double& w0, double& w1) {
+    const int I = I0 + k % VX, J = J0 + k / VX;
     if (I >= 0 && I <= top && J >= 0 && J <= top) {
       const long long o = (long long)J * nq + I;
-      if (I > 0 && J > 0 && I < top && J < top) xv = (double)x[po + o];
       w0 = wind[o];
       w1 = wind[g.nv + o];
     }
-    sx[ly][lx] = xv;
-    sw[0][ly][lx] = w0;
-    sw[1][ly][lx] = w1;
-  }
+  });
+  stage1<NT, VX * VY>(&sx[0][0], tid, [&](int k, double& xv) {
+    const int I = I0 + k % VX, J = J0 + k / VX;
+    if (I > 0 && J > 0 && I < top && J < top) xv = (double)x[po + (long long)J * nq + I];
+  });
   __syncthreads();
   for (int k = tid; k < (TX + 1) * (TY + 1); k += NT) {
     const int lex = k % (TX + 1), ley = k / (TX + 1);
@@ -360,11 +358,10 @@ __global__ __launch_bounds__(QX * QY) void k_ap_op(Geo g, const T* __restrict__ 
   const int c0 = blockIdx.x * QX, d0 = blockIdx.y * QY;
   const int n = g.n, top = 2 * n;
   const T* xr = x + (long long)rhs * g.nk;
-  for (int k = tid; k < XQX * XQY; k += QX * QY) {
-    const int lx = k % XQX, ly = k / XQX;
-    const int c = c0 - 2 + lx, d = d0 - 2 + ly;
-    sx[ly][lx] = (c >= 0 && c <= n && d >= 0 && d <= n) ? (double)xr[(long long)d * (n + 1) + c] : 0.0;
-  }
+  stage1<QX * QY, XQX * XQY>(&sx[0][0], tid, [&](int k, double& v) {
+    const int c = c0 - 2 + k % XQX, d = d0 - 2 + k / XQX;
+    if (c >= 0 && c <= n && d >= 0 && d <= n) v = (double)xr[(long long)d * (n + 1) + c];
+  });
   __syncthreads();
   const double h = g.h, h2 = h * h;
   const double sB = -h / 36.0;
@@ -530,15 +527,18 @@ __global__ void k_unit_columns(double* __restrict__ cols, int ni) {
 }
 
 // Q1 dense solve x = Ainv b per RHS (small coarsest level; one block per RHS)
+// (one wave per row, lanes along the row: independent loads, a shuffle sum)
 template <typename T>
 __global__ void k_q1_dense_solve(const double* __restrict__ Ainv, int ni, const T* __restrict__ b,
                                  T* __restrict__ x, Gate gate) {
   const int rhs = blockIdx.x;
   if (gate.off(rhs)) return;
-  for (int i = threadIdx.x; i < ni; i += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wave; i < ni; i += nw) {
     double s = 0.0;
-    for (int j = 0; j < ni; ++j) s += Ainv[(long long)i * ni + j] * (double)b[(long long)rhs * ni + j];
-    x[(long long)rhs * ni + i] = (T)s;
+    for (int j = lane; j < ni; j += 64) s += Ainv[(long long)i * ni + j] * (double)b[(long long)rhs * ni + j];
+    s = wave_sum(s);
+    if (lane == 0) x[(long long)rhs * ni + i] = (T)s;
   }
 }
 
