@@ -162,6 +162,44 @@ def bench_ragged(prec, steps, rtol):
                 all_converged=all(i["status"] == 0 for i in infos), setup_s=round(setup, 2))
 
 
+def bench_adjoint(kind, n, prec, steps, rtol):
+    """One gradient evaluation = forward solve at f0 + misfit + adjoint solve +
+    dJ/df + dJ/dnu, for J = 1/2 ||u - u_t||^2_{M_v} with u_t the solution for
+    bumps(seed 5000) and f0 = 1/2 bumps(seed 4999)."""
+    import torch
+    from paper_2303_10233_amd import eth
+    from paper_2303_10233_amd.workloads import gaussian_bumps, recirculating_wind
+    if kind == "oseen":
+        dom = (-1.0, 1.0, -1.0, 1.0)
+        w = torch.as_tensor(recirculating_wind(n), dtype=torch.float64, device="cuda:0")
+        P = eth.Problem(n, domain=dom, nu=0.01, kind=eth.OSEEN, wind=w, precision=prec)
+    else:
+        dom = (0.0, 1.0, 0.0, 1.0)
+        P = eth.Problem(n, precision=prec)
+    ft = torch.as_tensor(gaussian_bumps(n, 5000, *dom), dtype=torch.float64, device="cuda:0")
+    f0 = torch.as_tensor(0.5 * gaussian_bumps(n, 4999, *dom), dtype=torch.float64, device="cuda:0")
+    xt, _ = P.solve(P.assemble_rhs(ft), rtol=rtol, maxit=2000)
+    b0 = P.assemble_rhs(f0)
+
+    def gradient():
+        x, i1 = P.solve(b0, rtol=rtol, maxit=2000)
+        J, g = P.misfit(x, xt)
+        lam, i2 = P.solve_adjoint(g, rtol=rtol, maxit=2000)
+        return P.grad_forcing(lam), P.grad_viscosity(lam, x), i1[0], i2[0]
+
+    gradient()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gf, gnu, i1, i2 = gradient()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    P.close()
+    return dict(kind=kind, n=n, gradients_per_s=round(1.0 / dt, 4), ms_per_gradient=round(1e3 * dt, 3),
+                forward_iterations=i1["iterations"], adjoint_iterations=i2["iterations"],
+                forward_status=i1["status"], adjoint_status=i2["status"], dJdnu=float(gnu))
+
+
 def microbench(reps):
     """Kernel bandwidth at sizes whose vectors exceed the 256 MB Infinity Cache:
     Stokes n = 2048 (one FP64 vector 336 MB) and n = 512 x 16 right-hand sides,
@@ -291,6 +329,14 @@ def main():
                      "diverges; reported with maxit 300")
         extra["oseen"].append(r)
         log(f"oseen n=128 nu=1/1000: status {r['status']}, residual {r['rel_residual']:.2e}")
+        extra["adjoint"] = []
+        for kind, an in (("stokes", 512), ("oseen", 256)):
+            for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+                r = bench_adjoint(kind, an, prec, max(1, args.extra_steps - 1), args.rtol)
+                r["precision"] = name
+                extra["adjoint"].append(r)
+                log(f"adjoint {kind} n={an} {name}: {r['gradients_per_s']} gradients/s "
+                    f"({r['forward_iterations']} + {r['adjoint_iterations']} its)")
         for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
             extra["batch64"][name] = bench_batch(128, 64, prec, args.extra_steps, args.rtol)
             log(f"batch64 {name}: {extra['batch64'][name]}")

@@ -231,6 +231,17 @@ int eth_batch_solve(eth_batch* b, const eth_solve_opts* opts, const double* cons
 const char* eth_batch_last_error(const eth_batch* b);
 int eth_batch_destroy(eth_batch* b);
 
+/* EST-MINRES estimate of the discrete inf-sup constant (Sec. 2.4,
+ * eq:inf-sup_eig) from the last MINRES solve of right-hand side `rhs`
+ * (Stokes): the Lanczos scalars delta_j, gamma_j of alg:minres are recorded
+ * on the device during the solve; the harmonic Ritz values theta of the
+ * preconditioned matrix follow from them, and with the negative theta closest
+ * to zero gamma^2 = theta (theta - 1) (the eigenvalues (1 +- sqrt(1 + 4
+ * sigma))/2 of diag(A, M_Q)^{-1} K).  The estimate is of the preconditioned
+ * operator actually used (exact blocks give the inf-sup constant itself).
+ * gamma2, theta (may be NULL), steps (may be NULL): host outputs. */
+int eth_infsup_estimate(eth_problem* p, int64_t rhs, double* gamma2, double* theta, int32_t* steps);
+
 /* Kernel timing for roofline reporting.  Launches `reps` times the kernel
  * `kernel` (ETH_K_*) exactly as one Krylov iteration launches it (same grid,
  * same workspaces, finest level where a hierarchy is involved), between two

@@ -33,6 +33,8 @@ struct MinresScalars {
   int wx_todo;         // 1 when the w/x update of the last Givens step is pending
   int iters, maxit, status, hist_len;
   double* hist;        // |eta|/gamma_1 per iteration (device, hist_len entries)
+  double* hist_delta;  // delta_j at j-1 (the Lanczos tridiagonal, for EST-MINRES)
+  double* hist_gamma;  // gamma_j at j-1 (gamma_1 = ||r_0||_{P^{-1}} first)
 };
 
 // Per right-hand side FGMRES record (restart length m <= 63).
@@ -69,6 +71,7 @@ __device__ inline void minres_init(MinresScalars& s, double g2) {
   s.status = kStOK;
   s.active = (g > 0.0) ? 1 : 0;
   if (s.hist && s.hist_len > 0) s.hist[0] = 1.0;
+  if (s.hist_gamma && s.hist_len > 0) s.hist_gamma[0] = g;
 }
 
 __device__ inline void minres_delta(MinresScalars& s, double kzz) {
@@ -78,6 +81,7 @@ __device__ inline void minres_delta(MinresScalars& s, double kzz) {
   s.vy = 1.0 / g;
   s.va = delta / g;
   s.vb = (s.iters > 0) ? g / s.gamma_prev : 0.0;   // gamma_0 v_0 term is zero at j = 1
+  if (s.hist_delta && s.iters < s.hist_len) s.hist_delta[s.iters] = delta;
 }
 
 __device__ inline void minres_gamma(MinresScalars& s, double g2) {
@@ -110,6 +114,7 @@ __device__ inline void minres_gamma(MinresScalars& s, double g2) {
   s.iters += 1;
   s.rel = fabs(s.eta) / s.gamma1;
   if (s.hist && s.iters < s.hist_len) s.hist[s.iters] = s.rel;
+  if (s.hist_gamma && s.iters < s.hist_len) s.hist_gamma[s.iters] = gn;
   s.wx_todo = 1;
   if (s.rel <= s.tol || gn == 0.0) {
     s.active = 0;

@@ -70,6 +70,76 @@ static double tridiag_max_eig(const std::vector<double>& a, const std::vector<do
   return hi;
 }
 
+// EST-MINRES: the harmonic Ritz values theta of the Lanczos process after k
+// steps satisfy (T_k^2 + beta^2 e_k e_k^T) y = theta T_k y, T_k =
+// tridiag(gamma_{j+1}, delta_j, gamma_{j+1}), beta = gamma_{k+1}.  With
+// G = T_k^2 + beta^2 e_k e_k^T (symmetric positive definite) the values
+// mu = 1/theta are the eigenvalues of the pencil T y = mu G y; the number of
+// them below s equals the number of negative pivots of the symmetric
+// pentadiagonal T - s G (Sylvester's law of inertia), so the most negative mu
+// (the negative theta closest to zero) follows by bisection.  Returns false
+// when there is no negative mu.
+static bool most_negative_pencil_eig(const std::vector<double>& delta, const std::vector<double>& gam,
+                                     double* mu_out) {
+  const int k = (int)delta.size();
+  auto t = [&](int i, int j) -> double {   // T_k entry
+    if (i == j) return delta[i];
+    if (j == i + 1 || i == j + 1) return gam[std::max(i, j)];   // gamma_{max+1} (0-based list)
+    return 0.0;
+  };
+  auto gent = [&](int i, int j) -> double {   // (T^2 + beta^2 e_k e_k^T)_{ij}
+    double s = 0.0;
+    for (int l = std::max(0, std::max(i, j) - 1); l <= std::min(k - 1, std::min(i, j) + 1); ++l)
+      s += t(i, l) * t(l, j);
+    if (i == k - 1 && j == k - 1) s += gam[k] * gam[k];
+    return s;
+  };
+  // the five diagonals of G
+  std::vector<double> g0(k), g1(k, 0.0), g2(k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    g0[i] = gent(i, i);
+    if (i + 1 < k) g1[i] = gent(i, i + 1);
+    if (i + 2 < k) g2[i] = gent(i, i + 2);
+  }
+  auto count_below = [&](double sgm) {
+    // LDL^T of the band matrix C = T - sgm G (bandwidth 2), no pivoting
+    std::vector<double> d(k), l1(k, 0.0), l2(k, 0.0);   // l1[i] = L(i, i-1), l2[i] = L(i, i-2)
+    int neg = 0;
+    double scale = 0.0;
+    for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(delta[i]) + std::fabs(sgm) * g0[i]);
+    const double tiny = 1e-300 + 1e-14 * scale;
+    for (int i = 0; i < k; ++i) {
+      const double c0 = t(i, i) - sgm * g0[i];
+      const double c1 = (i >= 1) ? t(i, i - 1) - sgm * g1[i - 1] : 0.0;   // C(i, i-1)
+      const double c2 = (i >= 2) ? -sgm * g2[i - 2] : 0.0;                 // C(i, i-2)
+      if (i >= 2) l2[i] = c2 / d[i - 2];
+      if (i >= 1) {
+        double v = c1;
+        if (i >= 2) v -= l2[i] * d[i - 2] * l1[i - 1];
+        l1[i] = v / d[i - 1];
+      }
+      double di = c0;
+      if (i >= 1) di -= l1[i] * l1[i] * d[i - 1];
+      if (i >= 2) di -= l2[i] * l2[i] * d[i - 2];
+      if (std::fabs(di) < tiny) di = -tiny;
+      d[i] = di;
+      if (di < 0.0) ++neg;
+    }
+    return neg;
+  };
+  if (count_below(0.0) == 0) return false;
+  double lo = -1.0;
+  for (int it = 0; it < 400 && count_below(lo) > 0; ++it) lo *= 2.0;
+  double hi = 0.0;
+  for (int it = 0; it < 200; ++it) {   // the smallest eigenvalue lies in (lo, hi]
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  *mu_out = hi;
+  return true;
+}
+
 struct Problem {
   eth_problem_desc d{};
   Geo g{};
@@ -108,6 +178,9 @@ struct Problem {
   MinresScalars* d_ms = nullptr;
   MinresScalars* h_ms = nullptr;     // pinned host mirror
   double* d_hist = nullptr;
+  double* d_hist_delta = nullptr;    // Lanczos delta_j / gamma_j of the last MINRES solve
+  double* d_hist_gamma = nullptr;
+  bool have_lanczos = false;
   int hist_len = 0;
   double* red_partials = nullptr;
   double* red_result = nullptr;      // batch * 4
@@ -310,6 +383,8 @@ void Problem::setup(const eth_problem_desc& desc) {
   ETH_HIP(hipHostMalloc((void**)&h_ms, sizeof(MinresScalars) * max_batch, hipHostMallocDefault));
   hist_len = 4097;
   d_hist = alloc<double>((size_t)hist_len * max_batch);
+  d_hist_delta = alloc<double>((size_t)hist_len * max_batch);
+  d_hist_gamma = alloc<double>((size_t)hist_len * max_batch);
   const int maxblocks =
       std::max(std::max(std::max(dot_blocks(g.N), saddle_blocks(g)), adjoint_blocks(g)), 4096);
   red_partials = alloc<double>((size_t)maxblocks * kMaxRedVals * max_batch);
@@ -725,9 +800,12 @@ void Problem::minres_begin(MinresRun& R) {
     sc.tol = R.tol;
     sc.maxit = R.maxit;
     sc.hist = d_hist + (size_t)r * hist_len;
+    sc.hist_delta = d_hist_delta + (size_t)r * hist_len;
+    sc.hist_gamma = d_hist_gamma + (size_t)r * hist_len;
     sc.hist_len = hist_len;
     sc.active = 1;
   }
+  have_lanczos = !R.adjoint;
   ETH_HIP(hipMemcpyAsync(d_ms, h_ms, sizeof(MinresScalars) * batch, hipMemcpyHostToDevice, st));
   // z1 = P^{-1} v1, gamma_1
   precond(kv[0], kz[0], ldw, batch, no_gate());
@@ -1676,6 +1754,32 @@ int eth_batch_destroy(eth_batch* b) {
   if (!b) return ETH_EINVAL;
   delete b;
   return ETH_OK;
+}
+
+int eth_infsup_estimate(eth_problem* p, int64_t rhs, double* gamma2, double* theta, int32_t* steps) {
+  if (!p || !gamma2) return fail(p, ETH_EINVAL, "NULL argument");
+  Problem& P = p->impl;
+  if (P.oseen) return fail(p, ETH_EUNSUPPORTED, "the inf-sup estimate belongs to MINRES (Stokes)");
+  if (!P.have_lanczos) return fail(p, ETH_EINVAL, "no MINRES solve recorded yet");
+  if (rhs < 0 || rhs >= P.max_batch) return fail(p, ETH_EINVAL, "invalid rhs index");
+  return guarded(p, [&] {
+    const int k = std::min(P.h_ms[rhs].iters, P.hist_len - 1);
+    if (k < 1) throw std::invalid_argument("no Lanczos step recorded");
+    std::vector<double> dl(k), gm(k + 1);
+    ETH_HIP(hipMemcpyAsync(dl.data(), P.d_hist_delta + (size_t)rhs * P.hist_len, sizeof(double) * k,
+                           hipMemcpyDeviceToHost, P.st));
+    ETH_HIP(hipMemcpyAsync(gm.data(), P.d_hist_gamma + (size_t)rhs * P.hist_len, sizeof(double) * (k + 1),
+                           hipMemcpyDeviceToHost, P.st));
+    ETH_HIP(hipStreamSynchronize(P.st));
+    double mu = 0.0;
+    if (!eth::most_negative_pencil_eig(dl, gm, &mu))
+      throw std::invalid_argument("no negative harmonic Ritz value yet");
+    const double th = 1.0 / mu;
+    *gamma2 = th * (th - 1.0);
+    if (theta) *theta = th;
+    if (steps) *steps = k;
+    return ETH_OK;
+  });
 }
 
 int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int64_t batch,

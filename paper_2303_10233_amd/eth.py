@@ -121,6 +121,9 @@ def load_library(path=LIB_PATH):
     lib.eth_get_pcd_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.eth_get_pcd_levels.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
+    lib.eth_infsup_estimate.argtypes = [P, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32)]
+    lib.eth_infsup_estimate.restype = ctypes.c_int
     lib.eth_batch_setup.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int32, ctypes.POINTER(P)]
     lib.eth_batch_setup.restype = ctypes.c_int
     lib.eth_batch_count.argtypes = [P]
@@ -350,6 +353,15 @@ class Problem:
         st = lib().eth_solve(self._h, ctypes.byref(o), _ptr(b2), _ptr(x2), B, ld, infos)
         _check(st, self._h)
         return x, [infos[i].as_dict() for i in range(B)]
+
+    def infsup_estimate(self, rhs=0):
+        """EST-MINRES (gamma^2, theta, Lanczos steps) from the last MINRES solve."""
+        g2 = ctypes.c_double()
+        th = ctypes.c_double()
+        k = ctypes.c_int32()
+        _check(lib().eth_infsup_estimate(self._h, rhs, ctypes.byref(g2), ctypes.byref(th), ctypes.byref(k)),
+               self._h)
+        return g2.value, th.value, k.value
 
     def solve_adjoint(self, g, rtol=1e-6, maxit=1000, method=None, restart=0, canonicalize=True,
                       true_residual=False, out=None):

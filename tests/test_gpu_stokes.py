@@ -274,3 +274,27 @@ def test_solve_x0_warm_start_and_zero_rhs():
     z = torch.zeros_like(b)
     x0, i0 = P.solve(z, rtol=1e-8)
     assert i0[0]["iterations"] == 0 and float(x0.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("n,velocity,mq", [(8, "exact", "diag"), (16, "exact", "diag"), (32, "gmg", "cheb_sgs")])
+def test_est_minres_matches_oracle(n, velocity, mq):
+    """The inf-sup estimate from the Lanczos scalars recorded on the device
+    during the GPU solve against the oracle's estimate from its own MINRES
+    with the same preconditioner (Sec. 2.4)."""
+    from oracle.infsup import est_minres
+    print(f"[est-minres] n={n} {velocity} {mq}", flush=True)
+    m = Mesh(n)
+    s = System(m)
+    lam = _oracle_lambdas(n) if velocity == "gmg" else None
+    P = eth.Problem(n, velocity=eth.VEL_GMG if velocity == "gmg" else eth.VEL_EXACT,
+                    mq=eth.MQ_DIAG if mq == "diag" else eth.MQ_CHEB_SGS, gmg_lambda=lam,
+                    mq_cheb=(_mq_lo(n), 1.0))
+    b = P.assemble_rhs()
+    _, info = P.solve(b, rtol=1e-10, maxit=3000)
+    g2, th, k = P.infsup_estimate(0)
+    bref = s.to_interior(s.rhs(None, lid_dirichlet(m)))
+    _, oinfo = minres(lambda v: s.K @ v, bref, _oracle_prec(s, velocity, mq, lambdas=lam), tol=1e-10, maxit=3000)
+    og2, oth = est_minres(oinfo["delta"], oinfo["gamma"])
+    assert abs(k - oinfo["iterations"]) <= 1
+    assert th < 0
+    assert abs(g2 - og2) <= 1e-6 * og2
