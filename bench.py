@@ -329,6 +329,18 @@ def main():
                      "diverges; reported with maxit 300")
         extra["oseen"].append(r)
         log(f"oseen n=128 nu=1/1000: status {r['status']}, residual {r['rel_residual']:.2e}")
+        extra["stokes_schur_mq"] = {}
+        for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+            Ps = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_SCHUR_GMG)
+            bs = Ps.assemble_rhs()
+            dt, its, _ = time_solves(Ps, bs, args.steps, args.warmup, args.rtol, use_graph)
+            _, ti = Ps.solve(bs, rtol=args.rtol, maxit=2000, use_graph=use_graph, true_residual=True)
+            extra["stokes_schur_mq"][name] = dict(
+                solves_per_s=round(args.steps / dt, 4), ms_per_solve=round(1e3 * dt / args.steps, 3),
+                iterations=its[-1], true_rel_residual=ti[0]["rel_residual_true"],
+                note="pressure mass by P0 elimination + Q1 multigrid for S_k (mesh independent)")
+            log(f"stokes n={n} schur-gmg M_Q {name}: {extra['stokes_schur_mq'][name]}")
+            Ps.close()
         extra["adjoint"] = []
         for kind, an in (("stokes", 512), ("oseen", 256)):
             for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):

@@ -53,8 +53,12 @@ typedef enum { ETH_STOKES = 0, ETH_OSEEN = 1 } eth_kind;
 typedef enum { ETH_FP64 = 0, ETH_MIXED = 1 } eth_precision;
 /* velocity block of the preconditioner */
 typedef enum { ETH_VEL_GMG = 0, ETH_VEL_EXACT = 1 } eth_velocity_mode;
-/* pressure block: M_S in the bordered system [[M_S, k], [k^T, 0]] (Sec. 2.2) */
-typedef enum { ETH_MQ_DIAG = 1, ETH_MQ_CHEB_SGS = 2 } eth_mq_mode;
+/* pressure block: M_S in the bordered system [[M_S, k], [k^T, 0]] (Sec. 2.2).
+ * ETH_MQ_SCHUR_GMG: elimination of the P0 block (Q_0 = h^2 I, Sec. 2.3),
+ * z_k = B (r_k - R^T Q_0^{-1} r_0), z_0 = Q_0^{-1}(r_0 - R z_k), with B one Q1
+ * multigrid V-cycle for S_k = Q_k - R^T Q_0^{-1} R and k-projection of input
+ * and output: mesh independent, unlike the Chebyshev-SGS solve. */
+typedef enum { ETH_MQ_DIAG = 1, ETH_MQ_CHEB_SGS = 2, ETH_MQ_SCHUR_GMG = 3 } eth_mq_mode;
 typedef enum { ETH_MINRES = 0, ETH_FGMRES = 1, ETH_TWO_STAGE = 2 } eth_method;
 
 /*
@@ -171,10 +175,11 @@ int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, doubl
  * z_u = F~^{-T}(r_u - B_1^T z_pk). */
 int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int64_t batch,
                   int64_t ld);
-/* Oseen only: number of Q1 levels of the A_p multigrid inside PCD and its
- * Chebyshev bounds lambda_max(D^{-1}A_p) per smoothing level (levels-1
- * values); either pointer may be NULL */
-int eth_get_pcd_levels(const eth_problem* p, int32_t* levels, double* lambdas);
+/* The Q1 multigrid of the problem -- A_p inside PCD (Oseen) or S_k of
+ * ETH_MQ_SCHUR_GMG (Stokes) -- : number of levels and the Chebyshev bounds
+ * lambda_max(D^{-1} A_l) per smoothing level (levels-1 values); either pointer
+ * may be NULL.  ETH_EUNSUPPORTED when the problem has none. */
+int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas);
 
 /* Discrete adjoint (K^T lambda = g) of a solve, for gradients of
  * J(x(f, nu)) through the lifted system (eq:saddle_point, eq:oseen-system).

@@ -33,7 +33,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .assemble import Mesh, laplacian, frame_null_vector, q1_mass, \
-    q1_convection_diffusion, velocity_mass
+    q1_convection_diffusion, velocity_mass, pressure_mass
 from .krylov import fgmres
 
 
@@ -276,7 +276,7 @@ class StokesBlockDiag:
     z_u = (nu A~)^{-1} r_u,  z_p = nu * M~_S^{+} r_p."""
 
     def __init__(self, system, velocity="exact", mq="exact", mq_lo=None,
-                 mq_steps=20, gmg_kw=None):
+                 mq_steps=20, gmg_kw=None, schur_kw=None):
         s = system
         self.s = s
         self.nI = s.nI
@@ -293,6 +293,8 @@ class StokesBlockDiag:
             self.mq = MQDiag(s.mesh, s.MQ)
         elif mq == "cheb_sgs":
             self.mq = MQChebSGS(s.mesh, s.MQ, lo=mq_lo, steps=mq_steps)
+        elif mq == "schur_gmg":
+            self.mq = MQSchurGMG(s.mesh, s.MQ, **(schur_kw or {}))
         else:
             raise ValueError(mq)
 
@@ -517,3 +519,91 @@ def oseen_velocity_gmg(system, omega=0.7, sweeps=2, coarse_n=32):
                   omega=omega, sweeps=sweeps, coarse_n=coarse_n)
     m = g.A[0].shape[0]
     return (lambda r: np.concatenate([g.vcycle(0, r[:m]), g.vcycle(0, r[m:])])), g
+
+
+# -- mesh-independent pressure-mass solve by P0 elimination (Sec. 2.3 variant) --
+
+def schur_Sk(mesh):
+    """S_k = Q_k - R^T Q_0^{-1} R: the Q1 block of M_Q after eliminating the
+    P0 block (Q_0 = h^2 I).  Symmetric positive semi-definite with null space
+    the constants (M_Q k = 0); pT S_k p is the squared L2 distance of the Q1
+    function p from its element means."""
+    M = pressure_mass(mesh).tocsr()
+    nk = mesh.nk
+    Qk = M[:nk, :nk]
+    R = M[nk:, :nk]
+    q0 = M[nk:, nk:].diagonal()
+    return (Qk - R.T @ sp.diags(1.0 / q0) @ R).tocsr()
+
+
+class Q1GMG:
+    """One V(deg, deg) cycle of a Q1 geometric multigrid for a symmetric
+    positive semi-definite operator whose null space is the constants (input
+    and output projected onto mean-zero vectors): Chebyshev-Jacobi smoothing
+    on [lo_frac, hi_frac] * lambda_max(D^{-1} A_l), bilinear transfers and a
+    bordered solve on the coarsest level.  ops[l] is the level-l operator."""
+
+    def __init__(self, meshes, ops, degree=2, lo_frac=0.3, hi_frac=1.1, lambdas=None):
+        self.meshes, self.A = meshes, ops
+        self.P = [q1_prolongation(meshes[l], meshes[l + 1]) for l in range(len(meshes) - 1)]
+        self.dinv = [1.0 / A.diagonal() for A in self.A]
+        if lambdas is None:
+            lambdas = [lambda_max_dinv(A) for A in self.A[:-1]]
+        self.lam = list(lambdas)
+        self.degree, self.lo_frac, self.hi_frac = degree, lo_frac, hi_frac
+        Ac = self.A[-1]
+        one = np.ones((Ac.shape[0], 1))
+        self.coarse = spla.splu(sp.bmat([[Ac, sp.csr_matrix(one)], [sp.csr_matrix(one.T), None]]).tocsc())
+
+    def smooth(self, lvl, r, x):
+        A, dinv, lam = self.A[lvl], self.dinv[lvl], self.lam[lvl]
+        return chebyshev(lambda v: A @ v, lambda v: dinv * v, r, x,
+                         self.lo_frac * lam, self.hi_frac * lam, self.degree)
+
+    def vcycle(self, lvl, r):
+        if lvl == len(self.A) - 1:
+            return self.coarse.solve(np.concatenate([r, [0.0]]))[:-1]
+        x = self.smooth(lvl, r, np.zeros_like(r))
+        rc = self.P[lvl].T @ (r - self.A[lvl] @ x)
+        x = x + self.P[lvl] @ self.vcycle(lvl + 1, rc)
+        return self.smooth(lvl, r, x)
+
+    def __call__(self, r):
+        r = r - r.mean()
+        z = self.vcycle(0, r)
+        return z - z.mean()
+
+
+class MQSchurGMG:
+    """M_Q^+ approximated through the block factorisation of M_Q by its P0
+    block (Q_0 = h^2 I):
+        z_k = B (r_k - R^T Q_0^{-1} r_0),   z_0 = Q_0^{-1} (r_0 - R z_k),
+    B one Q1GMG cycle for S_k (schur_Sk) whose coarse operators are the
+    re-discretised S_k scaled by (h / h_l)^2 (S_k behaves like h^2 times a
+    Laplacian, so this matches the Galerkin coarse operator on smooth modes),
+    input and output projected onto k^perp as in MQChebSGS.  Symmetric
+    positive semi-definite; mesh-independent where the Chebyshev-SGS solve
+    is not (a NEXT item of the build: parity unpinned against the paper)."""
+
+    def __init__(self, mesh, MQ, coarse_n=4, degree=2, lo_frac=0.3, hi_frac=1.1, lambdas=None):
+        M = MQ.tocsr()
+        nk = mesh.nk
+        self.nk = nk
+        self.R = M[nk:, :nk].tocsr()
+        self.q0inv = 1.0 / M[nk:, nk:].diagonal()
+        self.k = frame_null_vector(mesh)
+        self.kk = float(self.k @ self.k)
+        ns = gmg_levels(mesh.n, coarse_n)
+        meshes = [Mesh(k, mesh.x0, mesh.x1, mesh.y0, mesh.y1) for k in ns]
+        ops = [schur_Sk(m) * (mesh.h / m.h) ** 2 for m in meshes]
+        self.gmg = Q1GMG(meshes, ops, degree, lo_frac, hi_frac, lambdas)
+
+    def project(self, v):
+        return v - (float(self.k @ v) / self.kk) * self.k
+
+    def __call__(self, r):
+        r = self.project(r)
+        rk, r0 = r[: self.nk], r[self.nk:]
+        zk = self.gmg(rk - self.R.T @ (self.q0inv * r0))
+        z0 = self.q0inv * (r0 - self.R @ zk)
+        return self.project(np.concatenate([zk, z0]))

@@ -219,6 +219,20 @@ void launch_velocity_mass(const Geo& g, const double* x, long long ldx, const do
 void launch_grad_viscosity(const Geo& g, const double* lam, long long ldl, const double* x, long long ldx,
                            const RedCtx& rc, int batch, hipStream_t st);
 
+// ---------------- M_Q by P0 elimination (k_schur.hip) --------------------------
+// S_k on Q1 vectors [batch][nk] of a level, scaled by h2 (the finest h^2):
+// mode 0: out = S x; 1: Chebyshev-Jacobi step over out; 2: out = b - S x
+template <typename T>
+void launch_sk_op(const Geo& g, double h2, int mode, const T* b, const T* x, T* out, double alpha, double beta,
+                  int has_prev, int batch, Gate gate, hipStream_t st);
+void launch_sk_diag_inv(const Geo& g, double h2, double* dinv, hipStream_t st);
+// b = r_k - R^T Q_0^{-1} r_0 and x = 0 (r: projected pressure vectors)
+template <typename T>
+void launch_schur_rhs(const Geo& g, const T* r, T* bq, T* xq, int batch, Gate gate, hipStream_t st);
+// z = [z_k; Q_0^{-1}(r_0 - R z_k)]
+template <typename T>
+void launch_schur_p0(const Geo& g, const T* r, const T* zk, T* z, int batch, Gate gate, hipStream_t st);
+
 // ---------------- FGMRES (k_gmres.hip) ----------------------------------------
 int gmres_blocks(long long N);
 // partials: 64 * gmres_blocks(N) doubles per RHS.  Each reduction is a

@@ -169,6 +169,14 @@ struct Problem {
   double* mq_coef2 = nullptr;        // batch
   double kDk = 0.0, kk = 0.0;
   std::vector<double> mq_a, mq_b;    // Chebyshev coefficients for the SGS iteration
+  // M_Q by P0 elimination: Q1 multigrid for S_k
+  std::vector<Geo> slv;
+  std::vector<double> slam;
+  std::vector<std::vector<double>> sca, scb;
+  std::vector<void*> sb, sx, sxo;
+  double* sAinv = nullptr;
+  int s_coarse_ni = 0;
+  double* ssums = nullptr;
   bool fused_mq = true;              // one launch per Chebyshev step (ETH_DEBUG_UNFUSED_MQ=1: per colour)
   ScaleState* d_scale = nullptr;     // [4] scale epilogue states
 
@@ -271,6 +279,11 @@ struct Problem {
   template <typename T>
   void mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
   void mq_solve(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
+  void build_schur();
+  template <typename T>
+  void schur_vcycle(int batch, Gate gate);
+  template <typename T>
+  void mq_schur(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
   void precond(const double* r, double* z, long long ld, int batch, Gate gate);
 
   // ------------------------------------------------------------ Oseen
@@ -341,7 +354,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.kind == ETH_OSEEN && !d.wind) throw std::invalid_argument("Oseen needs a wind");
   oseen = d.kind == ETH_OSEEN;
   if (d.mq_mode == 0) d.mq_mode = ETH_MQ_CHEB_SGS;
-  if (d.mq_mode != ETH_MQ_DIAG && d.mq_mode != ETH_MQ_CHEB_SGS)
+  if (d.mq_mode != ETH_MQ_DIAG && d.mq_mode != ETH_MQ_CHEB_SGS && d.mq_mode != ETH_MQ_SCHUR_GMG)
     throw std::invalid_argument("invalid mq_mode");
   if (d.mq_steps <= 0) d.mq_steps = 20;
   // lower end of the SGS-preconditioned M_Q interval: its smallest nonzero
@@ -577,6 +590,15 @@ void Problem::build_pressure() {
   hs[2] = ScaleState{mq_coef2, 1.0 / kk};
   hs[3] = ScaleState{mq_coef, 1.0};
   ETH_HIP(hipMemcpyAsync(d_scale, hs, sizeof(hs), hipMemcpyHostToDevice, st));
+  if (d.mq_mode == ETH_MQ_SCHUR_GMG) {
+    const size_t n = (size_t)max_batch * (g.nk + g.n0);
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    mq_r = alloc<char>(n * es);
+    mq_z = alloc<char>(n * es);
+    mq_t = alloc<char>(n * es);
+    mq_d = alloc<char>(n * es);
+    build_schur();
+  }
   if (d.mq_mode == ETH_MQ_CHEB_SGS) {
     const size_t n = (size_t)max_batch * (g.nk + g.n0);
     const size_t es = mixed ? sizeof(float) : sizeof(double);
@@ -685,11 +707,143 @@ void Problem::mq_solve(const double* r, double* z, long long ld, int batch, Gate
     RedCtx rc = red(dot_blocks(np), 1, EPI_SCALE, &d_scale[0]);
     launch_mq_diag_dot(g, r, ld, batch, rc, gate, st);
     launch_mq_diag_apply(g, r, z, ld, batch, mq_coef, scale, gate, st);
+  } else if (d.mq_mode == ETH_MQ_SCHUR_GMG) {
+    if (mixed) mq_schur<float>(r, z, ld, batch, gate, scale);
+    else mq_schur<double>(r, z, ld, batch, gate, scale);
   } else if (mixed) {
     mq_cheb<float>(r, z, ld, batch, gate, scale);
   } else {
     mq_cheb<double>(r, z, ld, batch, gate, scale);
   }
+}
+
+void Problem::build_schur() {
+  slv.clear();
+  slv.push_back(g);
+  {
+    int n = d.n;
+    double h = g.h;
+    while (n % 2 == 0 && n > 4) {
+      n /= 2;
+      h *= 2.0;
+      slv.push_back(make_geo(n, h));
+    }
+  }
+  const int LS = (int)slv.size();
+  const double h2 = g.h * g.h;   // every level uses the finest h^2 (see k_schur.hip)
+  const size_t es = mixed ? sizeof(float) : sizeof(double);
+  sb.assign(LS, nullptr);
+  sx.assign(LS, nullptr);
+  sxo.assign(LS, nullptr);
+  for (int l = 0; l < LS; ++l) {
+    const size_t n = (size_t)max_batch * slv[l].nk * es;
+    sb[l] = alloc<char>(n);
+    sx[l] = alloc<char>(n);
+    sxo[l] = alloc<char>(n);
+  }
+  slam.assign(std::max(LS - 1, 0), 0.0);
+  sca.assign(slam.size(), {});
+  scb.assign(slam.size(), {});
+  for (int l = 0; l + 1 < LS; ++l) {
+    const Geo ql = slv[l];
+    double* inv = alloc<double>(ql.nk);
+    launch_sk_diag_inv(ql, h2, inv, st);
+    auto apply = [&, ql](const double* x, double* y) {
+      launch_sk_op<double>(ql, h2, 0, nullptr, x, y, 0.0, 0.0, 0, 1, no_gate(), st);
+    };
+    auto dinv = [&, ql, inv](const double* x, double* y) {
+      launch_copy(ql.nk, x, 0, y, 0, 1, st);
+      launch_vmul(ql.nk, inv, y, st);
+    };
+    slam[l] = lanczos_generic(ql.nk, apply, dinv, 30, true);
+    cheb_coefs(d.gmg_lo_frac * slam[l], d.gmg_hi_frac * slam[l], d.gmg_degree, sca[l], scb[l]);
+  }
+  // coarsest: inverse of S + s 1 1^T (s = mean diagonal / n_k)
+  {
+    const Geo& gc = slv.back();
+    const int ni = gc.nk;
+    if (ni > 4225) throw std::runtime_error("unsupported:coarsest Q1 mesh of the S_k multigrid too large");
+    s_coarse_ni = ni;
+    double* cols = alloc<double>((size_t)ni * ni);
+    double* acols = alloc<double>((size_t)ni * ni);
+    launch_unit_columns(cols, ni, st);
+    launch_sk_op<double>(gc, h2, 0, nullptr, cols, acols, 0.0, 0.0, 0, ni, no_gate(), st);
+    double* inv = alloc<double>(ni);
+    launch_sk_diag_inv(gc, h2, inv, st);
+    std::vector<double> hd(ni);
+    ETH_HIP(hipMemcpyAsync(hd.data(), inv, ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    double mean = 0.0;
+    for (double v : hd) mean += (1.0 / v) / ni;
+    double* aug = alloc<double>((size_t)ni * 2 * ni);
+    double* col = alloc<double>(ni);
+    double* row = alloc<double>(2 * (size_t)ni);
+    sAinv = alloc<double>((size_t)ni * ni);
+    launch_dense_ap_aug(acols, ni, mean / ni, aug, st);
+    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
+    launch_extract_inverse(aug, ni, sAinv, 1, st);
+  }
+  ssums = alloc<double>(max_batch);
+}
+
+// S_k^+ on sb[0] -> sx[0] (one V-cycle; mean projections by the caller)
+template <typename T>
+void Problem::schur_vcycle(int batch, Gate gate) {
+  const int LS = (int)slv.size();
+  const double h2 = g.h * g.h;
+  std::vector<T*> b(LS), x(LS), xo(LS);
+  for (int l = 0; l < LS; ++l) {
+    b[l] = static_cast<T*>(sb[l]);
+    x[l] = static_cast<T*>(sx[l]);
+    xo[l] = static_cast<T*>(sxo[l]);
+  }
+  const int deg = d.gmg_degree;
+  for (int l = 0; l + 1 < LS; ++l) {
+    for (int k = 0; k < deg; ++k) {
+      launch_sk_op<T>(slv[l], h2, 1, b[l], x[l], xo[l], sca[l][k], scb[l][k], k == 0 ? 0 : 1, batch, gate, st);
+      std::swap(x[l], xo[l]);
+    }
+    launch_sk_op<T>(slv[l], h2, 2, b[l], x[l], xo[l], 0.0, 0.0, 0, batch, gate, st);
+    launch_q1_restrict<T>(slv[l], slv[l + 1], xo[l], b[l + 1], x[l + 1], batch, gate, st);
+  }
+  launch_q1_dense_solve<T>(sAinv, s_coarse_ni, b[LS - 1], x[LS - 1], batch, gate, st);
+  for (int l = LS - 2; l >= 0; --l) {
+    launch_q1_prolong_add<T>(slv[l], slv[l + 1], x[l + 1], x[l], batch, gate, st);
+    for (int k = 0; k < deg; ++k) {
+      launch_sk_op<T>(slv[l], h2, 1, b[l], x[l], xo[l], sca[l][k], scb[l][k], k == 0 ? 0 : 1, batch, gate, st);
+      std::swap(x[l], xo[l]);
+    }
+  }
+  if (x[0] != static_cast<T*>(sx[0]))
+    launch_q1_shift<T, T>(slv[0], x[0], slv[0].nk, 0, static_cast<T*>(sx[0]), slv[0].nk, 0, nullptr, 1.0,
+                          batch, gate, st);
+}
+
+template <typename T>
+void Problem::mq_schur(const double* r, double* z, long long ld, int batch, Gate gate, double scale) {
+  T* rr = static_cast<T*>(mq_r);
+  T* zz = static_cast<T*>(mq_z);
+  T* tt = static_cast<T*>(mq_t);
+  T* dd = static_cast<T*>(mq_d);
+  const long long np = (long long)g.nk + g.n0;
+  const long long nk = g.nk;
+  const int nbk = dot_blocks(np);
+  RedCtx rin = red(nbk, 1, EPI_SCALE, &d_scale[1]);
+  launch_mq_kdot<double>(g, r, ld, g.off_pk(), batch, rin, gate, st);
+  launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);
+  T* b0 = static_cast<T*>(sb[0]);
+  T* x0 = static_cast<T*>(sx[0]);
+  launch_schur_rhs<T>(g, rr, b0, x0, batch, gate, st);
+  RedCtx rs = red(dot_blocks(nk), 1, EPI_NONE, nullptr, ssums);
+  launch_q1_sum<T>(g, b0, rs, batch, gate, st);
+  launch_q1_shift<T, T>(g, b0, nk, 0, b0, nk, 0, ssums, 1.0, batch, gate, st);
+  schur_vcycle<T>(batch, gate);
+  launch_q1_sum<T>(g, x0, rs, batch, gate, st);
+  launch_q1_shift<T, T>(g, x0, nk, 0, x0, nk, 0, ssums, 1.0, batch, gate, st);
+  launch_schur_p0<T>(g, rr, x0, zz, batch, gate, st);
+  RedCtx rout = red(nbk, 1, EPI_SCALE, &d_scale[2]);
+  launch_mq_kdot<T>(g, zz, np, 0, batch, rout, gate, st);
+  launch_mq_project_out<T>(g, zz, z, ld, batch, mq_coef2, scale, gate, st);
 }
 
 void Problem::precond(const double* r, double* z, long long ld, int batch, Gate gate) {
@@ -1797,12 +1951,23 @@ int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int
   });
 }
 
-int eth_get_pcd_levels(const eth_problem* p, int32_t* levels, double* lambdas) {
+int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas) {
   if (!p) return ETH_EINVAL;
-  if (!p->impl.oseen) return ETH_EUNSUPPORTED;
-  if (levels) *levels = (int32_t)p->impl.qlv.size();
+  const Problem& P = p->impl;
+  const std::vector<eth::Geo>* lv = nullptr;
+  const std::vector<double>* lam = nullptr;
+  if (P.oseen) {
+    lv = &P.qlv;
+    lam = &P.qlam;
+  } else if (!P.slv.empty()) {
+    lv = &P.slv;
+    lam = &P.slam;
+  } else {
+    return ETH_EUNSUPPORTED;
+  }
+  if (levels) *levels = (int32_t)lv->size();
   if (lambdas)
-    for (size_t i = 0; i < p->impl.qlam.size(); ++i) lambdas[i] = p->impl.qlam[i];
+    for (size_t i = 0; i < lam->size(); ++i) lambdas[i] = (*lam)[i];
   return ETH_OK;
 }
 

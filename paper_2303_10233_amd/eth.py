@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libeth.so")
 STOKES, OSEEN = 0, 1
 FP64, MIXED = 0, 1
 VEL_GMG, VEL_EXACT = 0, 1
-MQ_DIAG, MQ_CHEB_SGS = 1, 2
+MQ_DIAG, MQ_CHEB_SGS, MQ_SCHUR_GMG = 1, 2, 3
 MINRES, FGMRES, TWO_STAGE = 0, 1, 2
 OK, EINVAL, EDEVICE, ENOMEM, EINCONSISTENT, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 WMAXIT = 1
@@ -118,8 +118,8 @@ def load_library(path=LIB_PATH):
     lib.eth_apply_preconditioner.restype = ctypes.c_int
     lib.eth_apply_pcd.argtypes = [P, ctypes.c_int, P, P, i64, i64]
     lib.eth_apply_pcd.restype = ctypes.c_int
-    lib.eth_get_pcd_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
-    lib.eth_get_pcd_levels.restype = ctypes.c_int
+    lib.eth_get_q1_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.eth_get_q1_levels.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
     lib.eth_infsup_estimate.argtypes = [P, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -279,15 +279,17 @@ class Problem:
         _check(L.eth_get_levels(self._h, None, lam), self._h)
         return lv.value, [lam[i] for i in range(max(lv.value - 1, 0))]
 
-    def pcd_levels(self):
-        """Oseen: (Q1 levels of the A_p multigrid, lambda_max(D^{-1}A_p) per
-        smoothing level)."""
+    def q1_levels(self):
+        """(levels, lambda_max(D^{-1}A_l) per smoothing level) of the Q1
+        multigrid: A_p inside PCD (Oseen) or S_k of MQ_SCHUR_GMG (Stokes)."""
         L = lib()
         lv = ctypes.c_int32()
-        _check(L.eth_get_pcd_levels(self._h, ctypes.byref(lv), None), self._h)
+        _check(L.eth_get_q1_levels(self._h, ctypes.byref(lv), None), self._h)
         lam = (ctypes.c_double * max(lv.value, 1))()
-        _check(L.eth_get_pcd_levels(self._h, None, lam), self._h)
+        _check(L.eth_get_q1_levels(self._h, None, lam), self._h)
         return lv.value, [lam[i] for i in range(max(lv.value - 1, 0))]
+
+    pcd_levels = q1_levels
 
     def empty(self, batch=1):
         shape = (self.N,) if batch == 1 else (batch, self.N)

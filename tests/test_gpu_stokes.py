@@ -298,3 +298,49 @@ def test_est_minres_matches_oracle(n, velocity, mq):
     assert abs(k - oinfo["iterations"]) <= 1
     assert th < 0
     assert abs(g2 - og2) <= 1e-6 * og2
+
+
+@pytest.mark.parametrize("n,prec,tol", [(16, eth.FP64, 1e-11), (64, eth.FP64, 1e-11), (64, eth.MIXED, 2e-5)])
+def test_schur_gmg_preconditioner_matches_oracle(n, prec, tol):
+    """M_Q^+ by elimination of the P0 block with a Q1 multigrid for S_k
+    (the GPU's Lanczos bounds passed to the oracle)."""
+    print(f"[schur mq] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    nu = 0.5
+    s = System(m, nu=nu)
+    lam = _oracle_lambdas(n)
+    P = eth.Problem(n, nu=nu, velocity=eth.VEL_GMG, mq=eth.MQ_SCHUR_GMG, precision=prec, gmg_lambda=lam)
+    _, slam = P.q1_levels()
+    r = uniform_vector(m.N, 21 + n)
+    r[: 2 * m.nv][s.vel_bnd] = 0.0
+    z = _np(P.apply_preconditioner(_t(r)))
+    Pref = opc.StokesBlockDiag(s, "gmg", "schur_gmg", gmg_kw=dict(lambdas=lam), schur_kw=dict(lambdas=slam))
+    zref = s.to_full(Pref(s.to_interior(r)))
+    o = 2 * m.nv
+    assert rel_err(z[:o], zref[:o]) < tol
+    assert rel_err(z[o:], zref[o:]) < tol
+
+
+@pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
+def test_schur_gmg_solve_is_mesh_independent(prec):
+    """MINRES with the P0-elimination M_Q: iteration counts of the oracle with
+    the same preconditioner (+-1) and mesh independent from 32^2 to 128^2."""
+    its = []
+    for n in (32, 64, 128):
+        m = Mesh(n)
+        s = System(m)
+        P = eth.Problem(n, velocity=eth.VEL_GMG, mq=eth.MQ_SCHUR_GMG, precision=prec)
+        b = P.assemble_rhs()
+        x, info = P.solve(b, rtol=1e-6, true_residual=True)
+        assert info[0]["status"] == 0
+        its.append(info[0]["iterations"])
+        if n == 64:
+            _, slam = P.q1_levels()
+            _, vlam = P.levels()
+            Pref = opc.StokesBlockDiag(s, "gmg", "schur_gmg", gmg_kw=dict(lambdas=vlam),
+                                       schur_kw=dict(lambdas=slam))
+            _, oinfo = minres(lambda v: s.K @ v, s.to_interior(s.rhs(None, lid_dirichlet(m))), Pref,
+                              tol=1e-6, maxit=1000)
+            assert abs(info[0]["iterations"] - oinfo["iterations"]) <= 1
+    print(f"  iterations {its}", flush=True)
+    assert max(its) - min(its) <= 3
