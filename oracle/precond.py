@@ -583,7 +583,11 @@ class MQSchurGMG:
     Laplacian, so this matches the Galerkin coarse operator on smooth modes),
     input and output projected onto k^perp as in MQChebSGS.  Symmetric
     positive semi-definite; mesh-independent where the Chebyshev-SGS solve
-    is not (a NEXT item of the build: parity unpinned against the paper)."""
+    is not.  Pinned by: the elimination with an exact S_k^+ equals the
+    bordered M_Q^+ solve; pT S_k p is the distance of p from its element
+    means; the V-cycle contracts at an h-independent rate.  The multigrid
+    itself is a design of this implementation (the paper only names the
+    P0 elimination), so its exact output has no value to be pinned to."""
 
     def __init__(self, mesh, MQ, coarse_n=4, degree=2, lo_frac=0.3, hi_frac=1.1, lambdas=None):
         M = MQ.tocsr()
