@@ -289,8 +289,6 @@ class Problem:
         _check(L.eth_get_q1_levels(self._h, None, lam), self._h)
         return lv.value, [lam[i] for i in range(max(lv.value - 1, 0))]
 
-    pcd_levels = q1_levels
-
     def empty(self, batch=1):
         shape = (self.N,) if batch == 1 else (batch, self.N)
         return torch.empty(shape, dtype=torch.float64, device=self.device)

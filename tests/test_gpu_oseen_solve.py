@@ -70,7 +70,7 @@ def _oracle_m1(s, mq="cheb_sgs"):
 
 def _oracle_pcd(s, P):
     vel, _ = opc.oseen_velocity_gmg(s)
-    _, lam = P.pcd_levels()
+    _, lam = P.q1_levels()
     return opc.PCDStage1Inexact(s, vel, q1_steps=10, ap_kw=dict(lambdas=lam))
 
 
@@ -110,7 +110,7 @@ def test_m1_diag_mq_batched():
 def test_pcd_lambdas_close_to_oracle():
     n = 64
     m, s, P = _setup(n, 0.01)
-    levels, lam = P.pcd_levels()
+    levels, lam = P.q1_levels()
     g = opc.ApGMG(m)
     assert levels == len(g.ns) == 5
     for a, b in zip(lam, g.lam):
