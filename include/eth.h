@@ -266,6 +266,7 @@ int eth_infsup_estimate(eth_problem* p, int64_t rhs, double* gamma2, double* the
 #define ETH_K_CD_STEP        9   /* a3: damped-Jacobi step on F, finest level          */
 #define ETH_K_GM_MDOT       10   /* a7: CGS multi-dot against m/2 Arnoldi vectors      */
 #define ETH_K_GM_MAXPY      11   /* a7: CGS update with m/2 Arnoldi vectors            */
+#define ETH_K_COPY          12   /* plain copy of N doubles (calibrates byte counters)  */
 int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, double* avg_ms,
                        double* bytes);
 

@@ -2155,6 +2155,11 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
         }
         break;
       }
+      case ETH_K_COPY: {
+        launch = [&] { eth::launch_copy(g.N, P.kz[0], P.ldw, P.kz[1], P.ldw, B, P.st); };
+        by = 16.0 * N * B;   // read + write of N doubles per RHS: the calibration of byte counters
+        break;
+      }
       default:
         throw std::invalid_argument("unknown kernel id");
     }

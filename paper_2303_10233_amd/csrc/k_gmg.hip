@@ -63,7 +63,7 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
                                                   double out_scale, Gate gate) {
   __shared__ T s[HY * HX];
   const int plane = blockIdx.z;
-  if (gate.off(plane >> 1)) return;
+  const bool off = gate.off(plane >> 1);   // tested after the staging (overlapped load)
   const int nq = g.nq, top = nq - 1;
   const long long po = (long long)plane * g.nv;
   const int I0 = blockIdx.x * NX, J0 = blockIdx.y * NY;
@@ -72,6 +72,7 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
     const int I = I0 + k % HX - 2, J = J0 + k / HX - 2;
     if (I >= 0 && I <= top && J >= 0 && J <= top) v = x[po + (long long)J * nq + I];
   });
+  if (off) return;   // uniform per block
   __syncthreads();
   const int tx = tid & 63, ty = tid >> 6;
   const int I = I0 + tx;
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   __shared__ T sx[XF * XF];
   __shared__ double sr[RF * RF];
   const int plane = blockIdx.z;
-  if (gate.off(plane >> 1)) return;
+  const bool off = gate.off(plane >> 1);   // tested after the staging (overlapped load)
   const int nqf = gf.nq, topf = nqf - 1, nqc = gc.nq, topc = nqc - 1;
   const long long pf = (long long)plane * gf.nv, pc = (long long)plane * gc.nv;
   const int C0x = blockIdx.x * CT, C0y = blockIdx.y * CT;
@@ -168,8 +169,9 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
       const int I = F0x - 2 + k % XF, J = F0y - 2 + k / XF;
       if (I >= 0 && I <= topf && J >= 0 && J <= topf) v = xf[pf + (long long)J * nqf + I];
     });
-    __syncthreads();
   }
+  if (off) return;   // uniform per block
+  if constexpr (!RES_GIVEN) __syncthreads();
 #pragma unroll
   for (int i = 0; i < RIT; ++i) {
     const int k = tid + i * NT;

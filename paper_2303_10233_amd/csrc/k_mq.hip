@@ -247,7 +247,7 @@ __global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict
   __shared__ T te[RE * RE];
   __shared__ T re[RE * RE];
   const int rhs = blockIdx.z;
-  if (gate.off(rhs)) return;
+  const bool off = gate.off(rhs);   // tested after the staging, so its load overlaps them
   const int n = g.n;
   const long long np = (long long)g.nk + g.n0;
   const T* rr = r + (long long)rhs * np;
@@ -292,6 +292,7 @@ __global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict
       if (!first) tv = zi[q];
     }
   });
+  if (off) return;   // uniform per block
   __syncthreads();
   constexpr int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
 #pragma unroll 1
