@@ -407,6 +407,7 @@ def main():
             "n": n,
             "unknowns": 2 * (2 * n + 1) ** 2 + (n + 1) ** 2 + n * n,
             "hip_graph": use_graph,
+            "mq_tile": {"mixed": problems["mixed"].mq_tile()[0], "fp64": problems["fp64"].mq_tile()[0]},
         },
         "iterations": its_m,
         "true_rel_residual": mixed["true_residual"],

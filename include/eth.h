@@ -94,6 +94,9 @@ typedef struct {
   double gmg_omega;          /* damped-Jacobi weight of the F multigrid (0.7)       */
   int32_t pcd_q1_steps;      /* Chebyshev-Jacobi steps for Q_1^{-1} in PCD (10)     */
   int32_t gmres_restart;     /* largest FGMRES restart length, <= 63 (50)          */
+  int32_t mq_tile;           /* ETH_MQ_CHEB_SGS: Q1 nodes per side of the blocks of
+                                the fused Chebyshev step, 16, 32 or 64 (64 with
+                                ETH_MIXED only); 0: the fastest, timed at setup  */
 } eth_problem_desc;
 
 typedef struct {
@@ -180,6 +183,10 @@ int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int
  * lambda_max(D^{-1} A_l) per smoothing level (levels-1 values); either pointer
  * may be NULL.  ETH_EUNSUPPORTED when the problem has none. */
 int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas);
+/* Tile sides of the fused Chebyshev step of ETH_MQ_CHEB_SGS in use for one
+ * right-hand side (tile_1) and for max_batch of them (tile_max); either
+ * pointer may be NULL.  ETH_EUNSUPPORTED for other mq_mode values. */
+int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max);
 
 /* Discrete adjoint (K^T lambda = g) of a solve, for gradients of
  * J(x(f, nu)) through the lifted system (eq:saddle_point, eq:oseen-system).

@@ -156,9 +156,10 @@ template <typename T>
 void launch_mq_cheb_combine(const Geo& g, T* t, T* z, T* d, double a, double b, int first,
                             int batch, Gate gate, hipStream_t st);
 // one fused Chebyshev step (symmetric multicolour SGS sweep from zin + combine)
+// on tiles of tile x tile Q1 nodes (16, 32; 64 in FP32 only)
 template <typename T>
 void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d, double a,
-                          double b, int first, int batch, Gate gate, hipStream_t st);
+                          double b, int first, int batch, Gate gate, hipStream_t st, int tile);
 template <typename T>
 void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, int batch,
                            const double* coef, double scale, Gate gate, hipStream_t st);

@@ -178,6 +178,13 @@ struct Problem {
   int s_coarse_ni = 0;
   double* ssums = nullptr;
   bool fused_mq = true;              // one launch per Chebyshev step (ETH_DEBUG_UNFUSED_MQ=1: per colour)
+  // tile side of the fused Chebyshev step, chosen at set-up for batch 1
+  // (lo) and for max_batch (hi)
+  int mq_tile_lo = 32, mq_tile_hi = 32;
+  int mq_tile_for(int batch) const {
+    return (long long)batch * batch > max_batch ? mq_tile_hi : mq_tile_lo;
+  }
+  int tune_mq_tile(int batch);
   ScaleState* d_scale = nullptr;     // [4] scale epilogue states
 
   // Krylov workspace
@@ -368,6 +375,10 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.pcd_q1_steps <= 0) d.pcd_q1_steps = 10;
   if (d.gmres_restart <= 0) d.gmres_restart = 50;
   if (d.gmres_restart > 63) throw std::invalid_argument("gmres_restart must be <= 63");
+  if (d.mq_tile != 0 && d.mq_tile != 16 && d.mq_tile != 32 && d.mq_tile != 64)
+    throw std::invalid_argument("mq_tile must be 0, 16, 32 or 64");
+  if (d.mq_tile == 64 && d.precision != ETH_MIXED)
+    throw std::invalid_argument("mq_tile 64 needs the FP32 preconditioner");
   if (d.gmg_degree <= 0) d.gmg_degree = 2;
   if (d.gmg_lo_frac <= 0.0) d.gmg_lo_frac = 0.3;
   if (d.gmg_hi_frac <= 0.0) d.gmg_hi_frac = 1.1;
@@ -619,7 +630,65 @@ void Problem::build_pressure() {
       mq_b[k] = 2.0 * rn / delta;
       rho = rn;
     }
+    if (d.mq_tile != 0) {
+      mq_tile_lo = mq_tile_hi = d.mq_tile;
+    } else {
+      mq_tile_lo = tune_mq_tile(1);
+      mq_tile_hi = max_batch > 1 ? tune_mq_tile(max_batch) : mq_tile_lo;
+    }
   }
+}
+
+// The fastest tile side of the fused Chebyshev step for `batch` right-hand
+// sides on this mesh: each candidate is timed with events over a few launches
+// on the (zeroed) workspace.  Small meshes favour small tiles (more blocks in
+// flight), large meshes large ones (less halo recomputation).
+int Problem::tune_mq_tile(int batch) {
+  const size_t bytes = (size_t)max_batch * (g.nk + g.n0) * (mixed ? sizeof(float) : sizeof(double));
+  ETH_HIP(hipMemsetAsync(mq_r, 0, bytes, st));
+  ETH_HIP(hipMemsetAsync(mq_z, 0, bytes, st));
+  ETH_HIP(hipMemsetAsync(mq_t, 0, bytes, st));
+  ETH_HIP(hipMemsetAsync(mq_d, 0, bytes, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ETH_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    throw std::runtime_error("hipEventCreate failed");
+  }
+  const int cands[3] = {16, 32, 64};
+  int best = 32;
+  float best_ms = 0.0f;
+  try {
+    for (int t : cands) {
+      if (t == 64 && !mixed) continue;
+      auto launch = [&] {
+        if (mixed)
+          launch_mq_cheb_fused<float>(g, (float*)mq_r, (float*)mq_z, (float*)mq_t, (float*)mq_d, 0.5,
+                                      0.1, 0, batch, no_gate(), st, t);
+        else
+          launch_mq_cheb_fused<double>(g, (double*)mq_r, (double*)mq_z, (double*)mq_t, (double*)mq_d,
+                                       0.5, 0.1, 0, batch, no_gate(), st, t);
+      };
+      for (int i = 0; i < 3; ++i) launch();
+      ETH_HIP(hipEventRecord(e0, st));
+      for (int i = 0; i < 10; ++i) launch();
+      ETH_HIP(hipEventRecord(e1, st));
+      ETH_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (best_ms == 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -688,7 +757,7 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
     if (d.mq_steps % 2 == 1) std::swap(zb[0], zb[1]);
     for (int k = 0; k < d.mq_steps; ++k)
       launch_mq_cheb_fused<T>(g, rr, zb[k & 1], zb[(k + 1) & 1], dd, mq_a[k], mq_b[k], k == 0,
-                              batch, gate, st);
+                              batch, gate, st, mq_tile_for(batch));
   } else {
     static const int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
     for (int k = 0; k < d.mq_steps; ++k) {
@@ -1971,6 +2040,15 @@ int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas) {
   return ETH_OK;
 }
 
+int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max) {
+  if (!p) return ETH_EINVAL;
+  const Problem& P = p->impl;
+  if (P.d.mq_mode != ETH_MQ_CHEB_SGS) return ETH_EUNSUPPORTED;
+  if (tile_1) *tile_1 = P.mq_tile_lo;
+  if (tile_max) *tile_max = P.mq_tile_hi;
+  return ETH_OK;
+}
+
 int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, double* x,
               int64_t batch, int64_t ld, eth_solve_info* info) {
   if (!p || !b || !x) return fail(p, ETH_EINVAL, "NULL argument");
@@ -2063,11 +2141,12 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
         launch = [&] {
           if (P.mixed)
             eth::launch_mq_cheb_fused<float>(g, (float*)P.mq_r, (float*)P.mq_z, (float*)P.mq_t,
-                                             (float*)P.mq_d, 0.5, 0.1, 0, B, gate, P.st);
+                                             (float*)P.mq_d, 0.5, 0.1, 0, B, gate, P.st,
+                                             P.mq_tile_for(B));
           else
             eth::launch_mq_cheb_fused<double>(g, (double*)P.mq_r, (double*)P.mq_z,
                                               (double*)P.mq_t, (double*)P.mq_d, 0.5, 0.1, 0, B,
-                                              gate, P.st);
+                                              gate, P.st, P.mq_tile_for(B));
         };
         // read r, z_k, d; write z_{k+1}, d (pressure vectors of n_k + n_0)
         by = 5.0 * es * (g.nk + g.n0) * B;

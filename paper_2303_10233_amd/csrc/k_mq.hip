@@ -16,6 +16,8 @@
 #include "eth_kernels.h"
 #include "eth_reduce.h"
 
+#include <stdexcept>
+
 namespace eth {
 namespace {
 
@@ -220,28 +222,39 @@ __global__ void k_mq_project_out(Geo g, const T* __restrict__ z, double* __restr
 // ---------------------------------------------------------------------------
 // One Chebyshev step of the pressure-mass solve in a single launch: the
 // symmetric multicolour Gauss-Seidel sweep from z_k (colours 0,1,2,3,4,3,2,1,0)
-// is temporally blocked in LDS.  A block of 32 x 32 threads owns TQ x TQ Q1
-// nodes and the elements with the same lower-left vertex; it stages a region
-// widened by HALO nodes, runs the nine colour passes on the whole region (one
-// colour node per thread per pass; each pass can spread stale halo values
-// inward by one node at most, so the owned part is exact after nine passes)
-// and then forms
+// is temporally blocked in LDS.  A block owns TQ x TQ Q1 nodes and the
+// elements with the same lower-left vertex; it stages a region widened by
+// HALO nodes, runs the nine colour passes on the whole region (each pass can
+// spread stale halo values inward by one node at most, so the owned part is
+// exact after nine passes) and then forms
 //   s = t - z_k,  d = first ? b s : a d + b s,  z_{k+1} = z_k + d.
+// The tile side TQ (16, 32 or 64) is chosen per problem by timing the
+// candidates at set-up: small meshes want many blocks, large meshes less
+// halo (the redundancy is ((TQ + 2 HALO) / TQ)^2).
 // Node updates share q1_gs_update / p0_gs_update with the per-colour kernel,
-// so both give bit-identical sweeps.
+// so every tile size gives the bit-identical sweep.
 // ---------------------------------------------------------------------------
-constexpr int TQ = 32, HALO = 10;
-constexpr int RQ = TQ + 2 * HALO;       // staged Q1 nodes per side
-constexpr int RE = RQ - 1;              // staged elements per side
-constexpr int FT = 1024;                // threads per block (32 x 32)
-static_assert(TQ % 2 == 0 && HALO % 2 == 0, "parity of local and global indices must agree");
-static_assert((RQ - 2 + 1) / 2 <= 32, "one colour node per thread and pass");
+constexpr int HALO = 10;
+static_assert(HALO % 2 == 0, "parity of local and global indices must agree");
 
-template <typename T>
-__global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict__ r,
-                                                      const T* __restrict__ zin,
-                                                      T* __restrict__ zout, T* __restrict__ d,
-                                                      double a, double b, int first, Gate gate) {
+template <int TQ>
+struct MqTile {
+  static constexpr int RQ = TQ + 2 * HALO;        // staged Q1 nodes per side
+  static constexpr int RE = RQ - 1;               // staged elements per side
+  static constexpr int NC = (RQ - 1) / 2;         // colour nodes per side and pass
+  // threads: one per colour node of a pass where that fits a block
+  static constexpr int FT = TQ >= 32 ? 1024 : 64 * ((NC * NC + 63) / 64);
+  static constexpr int OWN = (TQ * TQ + FT - 1) / FT;   // owned nodes per thread
+  static_assert(TQ % 2 == 0, "parity of local and global indices must agree");
+};
+
+template <typename T, int TQ>
+__global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T* __restrict__ r,
+                                                                  const T* __restrict__ zin,
+                                                                  T* __restrict__ zout, T* __restrict__ d,
+                                                                  double a, double b, int first, Gate gate) {
+  using Tl = MqTile<TQ>;
+  constexpr int RQ = Tl::RQ, RE = Tl::RE, NC = Tl::NC, FT = Tl::FT, OWN = Tl::OWN;
   __shared__ T tq[RQ * RQ];
   __shared__ T rq[RQ * RQ];
   __shared__ T te[RE * RE];
@@ -256,24 +269,28 @@ __global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict
   const int gx = c0 - HALO, gy = d0 - HALO;      // global index of local 0
   const double h2 = g.h * g.h;
   const T h2_36 = T(h2 / 36.0), h2_4 = T(0.25 * h2), inv_h2_9 = T(9.0 / h2), inv_h2 = T(1.0 / h2);
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int tid = ty * 32 + tx;
+  const int tid = threadIdx.x;
   T* zo = zout + (long long)rhs * np;
   T* dr = d + (long long)rhs * np;
   // the owned node / element values of z_k and d, fetched before the staging
   // so that their latency overlaps it
-  const int oc = c0 + tx, od = d0 + ty;
-  const bool own_q = (oc <= n && od <= n), own_e = (oc < n && od < n);
-  const long long oq = (long long)od * (n + 1) + oc, oe = g.nk + (long long)od * n + oc;
-  T z0q = T(0), d0q = T(0), z0e = T(0), d0e = T(0);
-  if (!first) {
-    if (own_q) {
-      z0q = zi[oq];
-      d0q = dr[oq];
-    }
-    if (own_e) {
-      z0e = zi[oe];
-      d0e = dr[oe];
+  T z0q[OWN], d0q[OWN], z0e[OWN], d0e[OWN];
+#pragma unroll
+  for (int i = 0; i < OWN; ++i) {
+    const int idx = tid + i * FT, ox = idx % TQ, oy = idx / TQ;
+    const int oc = c0 + ox, od = d0 + oy;
+    z0q[i] = d0q[i] = z0e[i] = d0e[i] = T(0);
+    if (!first && idx < TQ * TQ) {
+      if (oc <= n && od <= n) {
+        const long long oq = (long long)od * (n + 1) + oc;
+        z0q[i] = zi[oq];
+        d0q[i] = dr[oq];
+      }
+      if (oc < n && od < n) {
+        const long long oe = g.nk + (long long)od * n + oc;
+        z0e[i] = zi[oe];
+        d0e[i] = dr[oe];
+      }
     }
   }
   stage2<FT, RQ * RQ>(tq, rq, tid, [&](int k, T& tv, T& rv) {
@@ -299,10 +316,11 @@ __global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict
   for (int pass = 0; pass < 9; ++pass) {
     const int colour = order[pass];
     if (colour < 4) {
-      const int lx = ((colour & 1) == 0 ? 2 : 1) + 2 * tx;
-      const int ly = ((colour >> 1) == 0 ? 2 : 1) + 2 * ty;
-      const int c = gx + lx, dd = gy + ly;
-      if (lx <= RQ - 2 && ly <= RQ - 2 && c >= 0 && c <= n && dd >= 0 && dd <= n) {
+      for (int idx = tid; idx < NC * NC; idx += FT) {
+        const int lx = ((colour & 1) == 0 ? 2 : 1) + 2 * (idx % NC);
+        const int ly = ((colour >> 1) == 0 ? 2 : 1) + 2 * (idx / NC);
+        const int c = gx + lx, dd = gy + ly;
+        if (lx > RQ - 2 || ly > RQ - 2 || c < 0 || c > n || dd < 0 || dd > n) continue;
         const int Lx = (c > 0), Rx = (c < n), Ly = (dd > 0), Ry = (dd < n);
         T q9[9], e4[4];
 #pragma unroll
@@ -327,19 +345,27 @@ __global__ __launch_bounds__(FT) void k_mq_cheb_fused(Geo g, const T* __restrict
     }
     __syncthreads();
   }
-  // Chebyshev combination on the owned nodes and elements (one each per thread)
+  // Chebyshev combination on the owned nodes and elements
   const T ta = T(a), tb = T(b);
-  if (own_q) {
-    T dn;
-    const T zn = cheb_combine<T>(tq[(ty + HALO) * RQ + (tx + HALO)], z0q, d0q, ta, tb, first, dn);
-    dr[oq] = dn;
-    zo[oq] = zn;
-  }
-  if (own_e) {
-    T dn;
-    const T zn = cheb_combine<T>(te[(ty + HALO) * RE + (tx + HALO)], z0e, d0e, ta, tb, first, dn);
-    dr[oe] = dn;
-    zo[oe] = zn;
+#pragma unroll
+  for (int i = 0; i < OWN; ++i) {
+    const int idx = tid + i * FT, ox = idx % TQ, oy = idx / TQ;
+    if (idx >= TQ * TQ) break;
+    const int oc = c0 + ox, od = d0 + oy;
+    if (oc <= n && od <= n) {
+      const long long oq = (long long)od * (n + 1) + oc;
+      T dn;
+      const T zn = cheb_combine<T>(tq[(oy + HALO) * RQ + (ox + HALO)], z0q[i], d0q[i], ta, tb, first, dn);
+      dr[oq] = dn;
+      zo[oq] = zn;
+    }
+    if (oc < n && od < n) {
+      const long long oe = g.nk + (long long)od * n + oc;
+      T dn;
+      const T zn = cheb_combine<T>(te[(oy + HALO) * RE + (ox + HALO)], z0e[i], d0e[i], ta, tb, first, dn);
+      dr[oe] = dn;
+      zo[oe] = zn;
+    }
   }
 }
 
@@ -416,11 +442,22 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
 
 
 template <typename T>
-void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d, double a,
-                          double b, int first, int batch, Gate gate, hipStream_t st) {
-  dim3 grid((g.n + 1 + TQ - 1) / TQ, (g.n + 1 + TQ - 1) / TQ, batch);
-  hipLaunchKernelGGL(k_mq_cheb_fused<T>, grid, dim3(32, 32), 0, st, g, r, zin, zout, d, a, b, first,
-                     gate);
+void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d, double a, double b,
+                          int first, int batch, Gate gate, hipStream_t st, int tile) {
+#define ETH_MQF(TQ)                                                                                    \
+  hipLaunchKernelGGL((k_mq_cheb_fused<T, TQ>),                                                        \
+                     dim3((g.n + 1 + TQ - 1) / TQ, (g.n + 1 + TQ - 1) / TQ, batch),                   \
+                     dim3(MqTile<TQ>::FT), 0, st, g, r, zin, zout, d, a, b, first, gate)
+  if (tile == 16) {
+    ETH_MQF(16);
+  } else if (tile == 64) {
+    // the 84^2 + 83^2 staged values of two arrays fit the LDS in FP32 only
+    if constexpr (sizeof(T) == 4) ETH_MQF(64);
+    else throw std::invalid_argument("M_Q tile 64 needs the FP32 preconditioner");
+  } else {
+    ETH_MQF(32);
+  }
+#undef ETH_MQF
   ETH_LAUNCH_CHECK();
 }
 
@@ -435,7 +472,7 @@ void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d,
   template void launch_mq_project_out<T>(const Geo&, const T*, double*, long long, int,            \
                                          const double*, double, Gate, hipStream_t);               \
   template void launch_mq_cheb_fused<T>(const Geo&, const T*, const T*, T*, T*, double, double,    \
-                                        int, int, Gate, hipStream_t);
+                                        int, int, Gate, hipStream_t, int);
 ETH_INST(double)
 ETH_INST(float)
 #undef ETH_INST

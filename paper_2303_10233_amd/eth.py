@@ -48,6 +48,7 @@ class ProblemDesc(ctypes.Structure):
         ("gmg_omega", ctypes.c_double),
         ("pcd_q1_steps", ctypes.c_int32),
         ("gmres_restart", ctypes.c_int32),
+        ("mq_tile", ctypes.c_int32),
     ]
 
 
@@ -120,6 +121,8 @@ def load_library(path=LIB_PATH):
     lib.eth_apply_pcd.restype = ctypes.c_int
     lib.eth_get_q1_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.eth_get_q1_levels.restype = ctypes.c_int
+    lib.eth_get_mq_tile.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.eth_get_mq_tile.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
     lib.eth_infsup_estimate.argtypes = [P, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -199,7 +202,8 @@ def _as_batch(t, N):
 def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0, kind=STOKES,
                wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0, mq_cheb=(0.0, 0.0),
                gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0), gmg_lambda=None, precision=FP64,
-               max_batch=1, device=None, gmg_omega=0.0, pcd_q1_steps=0, gmres_restart=0):
+               max_batch=1, device=None, gmg_omega=0.0, pcd_q1_steps=0, gmres_restart=0,
+               mq_tile=0):
     """A filled ProblemDesc and the Python objects it points into."""
     d = ProblemDesc()
     d.n = n
@@ -225,6 +229,7 @@ def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
     d.gmg_omega = gmg_omega
     d.pcd_q1_steps = pcd_q1_steps
     d.gmres_restart = gmres_restart
+    d.mq_tile = mq_tile
     dev = torch.device("cuda" if device is None else device)
     with torch.cuda.device(dev):
         d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -238,7 +243,7 @@ class Problem:
                  kind=STOKES, wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0,
                  mq_cheb=(0.0, 0.0), gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0),
                  gmg_lambda=None, precision=FP64, max_batch=1, device=None, gmg_omega=0.0,
-                 pcd_q1_steps=0, gmres_restart=0):
+                 pcd_q1_steps=0, gmres_restart=0, mq_tile=0):
         d, keep = _make_desc(**{k: v for k, v in locals().items() if k not in ("self", "__class__")})
         self._keep = keep
         h = ctypes.c_void_p()
@@ -288,6 +293,13 @@ class Problem:
         lam = (ctypes.c_double * max(lv.value, 1))()
         _check(L.eth_get_q1_levels(self._h, None, lam), self._h)
         return lv.value, [lam[i] for i in range(max(lv.value - 1, 0))]
+
+    def mq_tile(self):
+        """(tile side for one RHS, for max_batch RHS) of the fused Chebyshev
+        step of MQ_CHEB_SGS, chosen at set-up unless mq_tile was given."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().eth_get_mq_tile(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
+        return a.value, b.value
 
     def empty(self, batch=1):
         shape = (self.N,) if batch == 1 else (batch, self.N)

@@ -168,21 +168,36 @@ def test_fused_coarse_vcycle_equals_per_level_launches(n, prec, tol, monkeypatch
     assert np.array_equal(z_fused[o:], z_ref[o:])
 
 
-@pytest.mark.parametrize("n,prec", [(16, eth.FP64), (66, eth.FP64), (64, eth.MIXED)])
+@pytest.mark.parametrize("n,prec", [(16, eth.FP64), (66, eth.FP64), (64, eth.MIXED), (132, eth.MIXED)])
 def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     """The temporally blocked Chebyshev-SGS kernel (nine colour passes in LDS
-    per launch) reproduces the one-launch-per-colour sweep bit for bit."""
-    print(f"[fused mq] n={n} prec={prec}", flush=True)
+    per launch) reproduces the one-launch-per-colour sweep bit for bit, for
+    every tile side (n + 1 nodes per side leave ragged edge tiles)."""
     m = Mesh(n)
     r = uniform_vector(m.N, 3 + n)
     r[: 2 * m.nv][System(m).vel_bnd] = 0.0
-    P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG)
-    z_fused = _np(P.apply_preconditioner(_t(r)))
+    o = 2 * m.nv
+    tiles = [16, 32] + ([64] if prec == eth.MIXED else [])
+    z_fused = {}
+    for tile in tiles:
+        print(f"[fused mq] n={n} prec={prec} tile={tile}", flush=True)
+        P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_tile=tile)
+        assert P.mq_tile() == (tile, tile)
+        z_fused[tile] = _np(P.apply_preconditioner(_t(r)))
+    A = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG)
+    assert A.mq_tile()[0] in tiles
     monkeypatch.setenv("ETH_DEBUG_UNFUSED_MQ", "1")
     Q = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG)
     z_plain = _np(Q.apply_preconditioner(_t(r)))
-    o = 2 * m.nv
-    assert np.array_equal(z_fused[o:], z_plain[o:])
+    for tile in tiles:
+        assert np.array_equal(z_fused[tile][o:], z_plain[o:]), tile
+
+
+def test_mq_tile_rejects_unsupported_sides():
+    with pytest.raises(Exception):
+        eth.Problem(16, mq_tile=24)
+    with pytest.raises(Exception):
+        eth.Problem(16, precision=eth.FP64, mq_tile=64)
 
 
 def test_gpu_lanczos_lambda_close_to_exact():
