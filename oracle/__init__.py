@@ -19,7 +19,11 @@ direct    bordered sparse direct solve, canonicalisation, adjoint gradients
 krylov    preconditioned MINRES (alg:minres) and flexible GMRES (Sec. 3)
 precond   block preconditioners P1, diagonal / Chebyshev-SGS pressure-mass
           solves (Sec. 2.2-2.3), geometric multigrid, PCD (Sec. 3.1) and the
-          two-stage driver (Sec. 3.1, full-system / reduced-system)
+          two-stage driver (Sec. 3.1, full-system / reduced-system), the
+          P0-elimination multigrid for M_Q (Sec. 2.3)
+infsup    inf-sup constant (Sec. 2.4) and its EST-MINRES estimate
+picard    fixed-point (Picard) steps of the steady Navier-Stokes equations
+          that produce the Oseen systems of Sec. 3, and their residual
 
 Every function is pinned by a test in ``tests/test_oracle_*.py`` against a
 closed form, a brute-force computation or an identity the paper states; the

@@ -175,10 +175,17 @@ def lid_dirichlet(mesh, lid_u=1.0, corner_mode=0):
     """Full-length velocity vector (2 n_v) holding the Dirichlet data of a
     driven cavity: u = (lid_u, 0) on the top wall y = y1, zero elsewhere.
     corner_mode 0 ("watertight") sets the two top corners to zero,
-    corner_mode 1 ("leaky") gives them the lid value."""
+    corner_mode 1 ("leaky") gives them the lid value, corner_mode 2
+    ("regularised", the enclosed-flow example of Sec. 3 on [-1, 1]^2) uses
+    u_x = lid_u (1 - xi^4) with xi the top-wall coordinate mapped to [-1, 1]."""
     nq = mesh.nq
     ux = np.zeros(mesh.nv)
     top = (nq - 1) * nq + np.arange(nq)
+    if corner_mode == 2:
+        X, _ = mesh.q2_coords()
+        xi = 2.0 * (X.ravel()[top] - mesh.x0) / (mesh.x1 - mesh.x0) - 1.0
+        ux[top] = lid_u * (1.0 - xi ** 4)
+        return np.concatenate([ux, np.zeros(mesh.nv)])
     ux[top] = lid_u
     if corner_mode == 0:
         ux[top[0]] = 0.0
