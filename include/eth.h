@@ -72,7 +72,10 @@ typedef struct {
   double nu;                 /* viscosity, > 0 (Stokes: -nu Lap u + grad p = f)     */
   const double* wind;        /* Oseen: device, 2(2n+1)^2 nodal Q2 wind [w_x|w_y]    */
   double lid_u;              /* tangential lid velocity on y = y1                   */
-  int32_t corner_mode;       /* 0: top corners get 0 (watertight); 1: lid value     */
+  int32_t corner_mode;       /* 0: top corners get 0 (watertight); 1: lid value;
+                                2: regularised lid lid_u (1 - xi^4), xi in [-1, 1]
+                                across the top wall (the enclosed-flow example of
+                                Sec. 3)                                           */
   int32_t velocity_mode;     /* eth_velocity_mode; EXACT needs (2n-1)^2 <= 4096     */
   int32_t mq_mode;           /* eth_mq_mode (default ETH_MQ_CHEB_SGS)               */
   int32_t mq_steps;          /* Chebyshev steps for ETH_MQ_CHEB_SGS (default 20)    */
@@ -187,6 +190,27 @@ int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas);
  * right-hand side (tile_1) and for max_batch of them (tile_max); either
  * pointer may be NULL.  ETH_EUNSUPPORTED for other mq_mode values. */
 int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max);
+
+/* Replace the nodal Q2 wind of an Oseen problem (device, 2(2n+1)^2
+ * [w_x|w_y], the w_h of eq:generic-conv-diff) and rebuild what depends on it:
+ * the wind and the F diagonal of every multigrid level and the dense inverse
+ * of the coarsest F.  Allocates nothing; stream-ordered; the wind is copied.
+ * ETH_EUNSUPPORTED for Stokes problems. */
+int eth_set_wind(eth_problem* p, const double* wind);
+
+/* Picard iteration for the steady Navier-Stokes equations (Sec. 3: the wind
+ * is the velocity of the most recent nonlinear iterate).  x (device, full
+ * layout, one right-hand side) holds the current iterate on entry, e.g. the
+ * Stokes solution with the same boundary data; each of `steps` steps sets the
+ * wind to the velocity of x (eth_set_wind), lifts the right-hand side
+ * (eth_assemble_rhs with f_nodal, NULL: f = 0) and solves the Oseen system
+ * with x as the initial guess (opts->use_x0 is forced to 1; opts NULL:
+ * ETH_TWO_STAGE, canonicalize = 1).  On return x is the last iterate and the
+ * problem holds its wind, so eth_solve then solves the Oseen system of the
+ * next step.  info: NULL or `steps` entries, one per step.  Returns the worst
+ * status; a negative status ends the iteration at once. */
+int eth_picard(eth_problem* p, const eth_solve_opts* opts, int32_t steps, const double* f_nodal,
+               double* x, eth_solve_info* info);
 
 /* Discrete adjoint (K^T lambda = g) of a solve, for gradients of
  * J(x(f, nu)) through the lifted system (eq:saddle_point, eq:oseen-system).

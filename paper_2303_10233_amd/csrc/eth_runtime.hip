@@ -204,6 +204,8 @@ struct Problem {
 
   // Oseen: velocity multigrid on F, PCD Q1 hierarchy, FGMRES workspace
   double* wind0 = nullptr;                  // internal copy of the finest nodal wind
+  double *f_aug = nullptr, *f_col = nullptr, *f_row = nullptr;   // coarse F Gauss-Jordan workspace
+  double* pic_b = nullptr;                  // right-hand side of a Picard step (N)
   std::vector<double*> lwind, ldF;          // wind and diag(F) per velocity level
   std::vector<Geo> qlv;                     // Q1 levels of the A_p multigrid
   std::vector<double> qlam;
@@ -295,6 +297,9 @@ struct Problem {
 
   // ------------------------------------------------------------ Oseen
   void build_oseen_velocity();
+  void refresh_wind();
+  int picard(const eth_solve_opts& o, int steps, const double* f_nodal, double* x,
+             eth_solve_info* info);
   void build_pcd();
   void build_gmres();
   double lanczos_generic(long long len, const std::function<void(const double*, double*)>& apply,
@@ -359,6 +364,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (!(d.nu > 0.0)) throw std::invalid_argument("nu must be > 0");
   if (d.kind != ETH_STOKES && d.kind != ETH_OSEEN) throw std::invalid_argument("invalid kind");
   if (d.kind == ETH_OSEEN && !d.wind) throw std::invalid_argument("Oseen needs a wind");
+  if (d.corner_mode < 0 || d.corner_mode > 2) throw std::invalid_argument("corner_mode must be 0, 1 or 2");
   oseen = d.kind == ETH_OSEEN;
   if (d.mq_mode == 0) d.mq_mode = ETH_MQ_CHEB_SGS;
   if (d.mq_mode != ETH_MQ_DIAG && d.mq_mode != ETH_MQ_CHEB_SGS && d.mq_mode != ETH_MQ_SCHUR_GMG)
@@ -423,6 +429,7 @@ void Problem::setup(const eth_problem_desc& desc) {
     wind0 = alloc<double>(2 * (size_t)g.nv);
     ETH_HIP(hipMemcpyAsync(wind0, d.wind, 2 * sizeof(double) * g.nv, hipMemcpyDeviceToDevice, st));
     d.wind = wind0;
+    pic_b = alloc<double>(g.N);
     build_oseen_velocity();
     build_pcd();
     build_gmres();
@@ -1223,31 +1230,20 @@ void Problem::build_oseen_velocity() {
   ldF.assign(L, nullptr);
   lwind[0] = wind0;
   for (int l = 0; l < L; ++l) {
-    if (l > 0) {
-      lwind[l] = alloc<double>(2 * (size_t)lv[l].nv);
-      launch_inject_wind(g, lv[l], wind0, lwind[l], st);
-    }
+    if (l > 0) lwind[l] = alloc<double>(2 * (size_t)lv[l].nv);
     ldF[l] = alloc<double>(lv[l].nv);
-    launch_cd_diag(lv[l], lwind[l], d.nu, ldF[l], st);
   }
   const Geo& gc = lv.back();
   coarse_ni = (gc.nq - 2) * (gc.nq - 2);
   if (coarse_ni > 4225)
     throw std::runtime_error("unsupported:coarsest mesh too large for the dense solve");
   dense_gbuf = alloc<double>((size_t)2 * coarse_ni * max_batch);
-  {
-    // dense inverse of the coarsest F (nonsymmetric, positive real: no pivoting)
-    const int ni = coarse_ni;
-    double* aug = alloc<double>((size_t)ni * 2 * ni);
-    double* col = alloc<double>(ni);
-    double* row = alloc<double>(2 * (size_t)ni);
-    Ainv = alloc<double>((size_t)ni * ni);
-    launch_dense_convdiff(gc, lwind[L - 1], d.nu, aug, ni, st);
-    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
-    launch_extract_inverse(aug, ni, Ainv, 0, st);
-    AinvT = alloc<double>((size_t)ni * ni);
-    launch_transpose(Ainv, ni, AinvT, st);
-  }
+  f_aug = alloc<double>((size_t)coarse_ni * 2 * coarse_ni);
+  f_col = alloc<double>(coarse_ni);
+  f_row = alloc<double>(2 * (size_t)coarse_ni);
+  Ainv = alloc<double>((size_t)coarse_ni * coarse_ni);
+  AinvT = alloc<double>((size_t)coarse_ni * coarse_ni);
+  refresh_wind();
   vb.assign(L, nullptr);
   vx.assign(L, nullptr);
   vxo.assign(L, nullptr);
@@ -1261,6 +1257,24 @@ void Problem::build_oseen_velocity() {
     ETH_HIP(hipMemsetAsync(vx[l], 0, n, st));
     ETH_HIP(hipMemsetAsync(vxo[l], 0, n, st));
   }
+}
+
+// Everything of the Oseen preconditioners that depends on the wind: the wind
+// of each multigrid level (injection), the diagonals of F per level and the
+// dense inverse of the coarsest F (nonsymmetric, positive real: Gauss-Jordan
+// without pivoting) with its transpose.  F_1 of the PCD reads the finest wind
+// when applied.  Allocates nothing.
+void Problem::refresh_wind() {
+  const int L = (int)lv.size();
+  for (int l = 0; l < L; ++l) {
+    if (l > 0) launch_inject_wind(g, lv[l], wind0, lwind[l], st);
+    launch_cd_diag(lv[l], lwind[l], d.nu, ldF[l], st);
+  }
+  const int ni = coarse_ni;
+  launch_dense_convdiff(lv.back(), lwind[L - 1], d.nu, f_aug, ni, st);
+  for (int k = 0; k < ni; ++k) launch_gj_step(f_aug, ni, k, f_col, f_row, st);
+  launch_extract_inverse(f_aug, ni, Ainv, 0, st);
+  launch_transpose(Ainv, ni, AinvT, st);
 }
 
 void Problem::build_pcd() {
@@ -1628,6 +1642,31 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
     }
     if (status < 0) worst = std::min(worst, status);
     else if (worst >= 0) worst = std::max(worst, status);
+  }
+  return worst;
+}
+
+// Picard (fixed-point) linearisation of the steady Navier-Stokes equations
+// (Sec. 3: the wind of eq:generic-conv-diff is the velocity of the latest
+// nonlinear iterate): each step takes the wind from the velocity of x, lifts
+// the right-hand side with it and solves the Oseen system from x.
+int Problem::picard(const eth_solve_opts& o, int steps, const double* f_nodal, double* x,
+                    eth_solve_info* info) {
+  eth_solve_opts os = o;
+  os.use_x0 = 1;
+  int worst = ETH_OK;
+  for (int s = 0; s < steps; ++s) {
+    ETH_HIP(hipMemcpyAsync(wind0, x, 2 * sizeof(double) * g.nv, hipMemcpyDeviceToDevice, st));
+    refresh_wind();
+    launch_lift_rhs(g, d.nu, wind0, ub, f_nodal, 2LL * g.nv, pic_b, g.N, 1, st);
+    const int status = solve_oseen(os, pic_b, x, 1, g.N, info ? info + s : nullptr, false);
+    if (status < 0) return status;
+    worst = std::max(worst, status);
+  }
+  // the wind of the next step: the system a following solve sees
+  if (steps > 0) {
+    ETH_HIP(hipMemcpyAsync(wind0, x, 2 * sizeof(double) * g.nv, hipMemcpyDeviceToDevice, st));
+    refresh_wind();
   }
   return worst;
 }
@@ -2069,6 +2108,35 @@ int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, doubl
   }
   if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
   return guarded(p, [&] { return p->impl.solve_minres(o, b, x, (int)batch, ld, info); });
+}
+
+int eth_set_wind(eth_problem* p, const double* wind) {
+  if (!p || !wind) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!p->impl.oseen) return fail(p, ETH_EUNSUPPORTED, "the problem has no wind (Stokes)");
+  return guarded(p, [&] {
+    Problem& P = p->impl;
+    ETH_HIP(hipMemcpyAsync(P.wind0, wind, 2 * sizeof(double) * P.g.nv, hipMemcpyDeviceToDevice, P.st));
+    P.refresh_wind();
+    return ETH_OK;
+  });
+}
+
+int eth_picard(eth_problem* p, const eth_solve_opts* opts, int32_t steps, const double* f_nodal,
+               double* x, eth_solve_info* info) {
+  if (!p || !x) return fail(p, ETH_EINVAL, "NULL argument");
+  if (!p->impl.oseen) return fail(p, ETH_EUNSUPPORTED, "Picard steps need an Oseen problem");
+  if (steps < 0) return fail(p, ETH_EINVAL, "steps must be >= 0");
+  eth_solve_opts o{};
+  if (opts) {
+    o = *opts;
+  } else {
+    o.canonicalize = 1;
+    o.method = ETH_TWO_STAGE;
+  }
+  if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
+  if (o.method != ETH_FGMRES && o.method != ETH_TWO_STAGE)
+    return fail(p, ETH_EUNSUPPORTED, "Oseen systems are solved by FGMRES or TWO_STAGE");
+  return guarded(p, [&] { return p->impl.picard(o, steps, f_nodal, x, info); });
 }
 
 int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, double* avg_ms,

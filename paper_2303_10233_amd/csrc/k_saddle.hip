@@ -333,6 +333,11 @@ __global__ void k_dirichlet_lid(Geo g, double lid_u, int corner_mode, double* ub
   if (comp == 0 && J == g.nq - 1) {
     v = lid_u;
     if (corner_mode == 0 && (I == 0 || I == g.nq - 1)) v = 0.0;
+    if (corner_mode == 2) {
+      // regularised lid lid_u (1 - xi^4), xi in [-1, 1] across the top wall
+      const double xi = 2.0 * I / (g.nq - 1) - 1.0, xi2 = xi * xi;
+      v = lid_u * (1.0 - xi2 * xi2);
+    }
   }
   ub[k] = v;
 }

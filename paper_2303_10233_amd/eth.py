@@ -144,6 +144,10 @@ def load_library(path=LIB_PATH):
                                       ctypes.POINTER(SolveInfo)]
     lib.eth_solve_adjoint.restype = ctypes.c_int
     lib.eth_grad_forcing.argtypes = [P, P, i64, P, i64, i64]
+    lib.eth_set_wind.argtypes = [P, P]
+    lib.eth_set_wind.restype = ctypes.c_int
+    lib.eth_picard.argtypes = [P, ctypes.POINTER(SolveOpts), ctypes.c_int32, P, P, ctypes.POINTER(SolveInfo)]
+    lib.eth_picard.restype = ctypes.c_int
     lib.eth_grad_forcing.restype = ctypes.c_int
     lib.eth_grad_viscosity.argtypes = [P, P, P, P, i64, i64]
     lib.eth_grad_viscosity.restype = ctypes.c_int
@@ -391,6 +395,29 @@ class Problem:
         st = lib().eth_solve_adjoint(self._h, ctypes.byref(o), _ptr(g2), _ptr(l2), B, ld, infos)
         _check(st, self._h)
         return lam, [infos[i].as_dict() for i in range(B)]
+
+    def set_wind(self, wind):
+        """Replace the nodal Q2 wind [w_x | w_y] (2 nv, float64, on the device)
+        and rebuild what depends on it (see eth_set_wind)."""
+        if wind.dtype != torch.float64 or wind.numel() < 2 * self.nv or not wind.is_contiguous():
+            raise ValueError("wind must be a contiguous float64 tensor of 2 nv values")
+        _check(lib().eth_set_wind(self._h, _ptr(wind)), self._h)
+
+    def picard(self, x, steps, f=None, rtol=1e-6, maxit=1000, method=TWO_STAGE, restart=0,
+               c_factor=10.0, canonicalize=True):
+        """`steps` Picard steps from the iterate x (updated in place): each sets
+        the wind to the velocity of x and solves the Oseen system from x.
+        Returns x and one info dict per step."""
+        if x.dtype != torch.float64 or x.numel() != self.N or not x.is_contiguous():
+            raise ValueError("x must be one contiguous float64 vector of length N")
+        if f is not None and (f.dtype != torch.float64 or f.numel() < 2 * self.nv):
+            raise ValueError("f must be a float64 tensor of 2 nv nodal forces")
+        o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=c_factor,
+                      canonicalize=int(canonicalize), use_x0=1, use_graph=0, true_residual=0)
+        infos = (SolveInfo * max(steps, 1))()
+        st = lib().eth_picard(self._h, ctypes.byref(o), steps, None if f is None else _ptr(f), _ptr(x), infos)
+        _check(st, self._h)
+        return x, [infos[i].as_dict() for i in range(steps)]
 
     def grad_forcing(self, lam):
         """dJ/df = M_v lambda~ over all nodal forces, shape (..., 2 nv)."""
