@@ -130,6 +130,41 @@ def bench_oseen(n, nu, prec, steps, rtol, maxit=1000):
                 rel_residual=i["rel_residual_true"], status=i["status"], setup_s=round(setup, 3))
 
 
+def bench_picard(n, nu, prec, steps, rtol, picard_steps=5, maxit=1000):
+    """Enclosed flow on [-1, 1]^2 with the regularised lid 1 - x^4 (Re = 2/nu):
+    Stokes start, `picard_steps` fixed-point steps (each a two-stage PCD
+    solve from the previous iterate), then the Oseen system they produce is
+    solved from zero `steps` times."""
+    import torch
+    from paper_2303_10233_amd import eth
+    dom = (-1.0, 1.0, -1.0, 1.0)
+    S = eth.Problem(n, domain=dom, nu=nu, corner_mode=2, precision=prec)
+    x, _ = S.solve(S.assemble_rhs(), rtol=rtol, maxit=maxit)
+    S.close()
+    P = eth.Problem(n, domain=dom, nu=nu, kind=eth.OSEEN, wind=x[: 2 * (2 * n + 1) ** 2].contiguous(),
+                    corner_mode=2, precision=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, pinfo = P.picard(x, picard_steps, rtol=rtol, maxit=maxit)
+    torch.cuda.synchronize()
+    t_picard = time.perf_counter() - t0
+    b = P.assemble_rhs()
+    y, info = P.solve(b, rtol=rtol, maxit=maxit)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        y, info = P.solve(b, rtol=rtol, maxit=maxit, out=y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    i = info[0]
+    P.close()
+    return dict(n=n, nu=nu, reynolds=round(2.0 / nu, 3), solves_per_s=round(1.0 / dt, 4),
+                ms_per_solve=round(1e3 * dt, 3), iterations=i["iterations"],
+                stage1_iterations=i["stage1_iterations"], rel_residual=i["rel_residual_true"],
+                status=i["status"], picard_seconds=round(t_picard, 4),
+                picard_iterations=[p["iterations"] for p in pinfo])
+
+
 def bench_batch(n, nrhs, prec, steps, rtol):
     """Lockstep MINRES over nrhs bump-forced right-hand sides on one mesh."""
     import torch
@@ -352,6 +387,15 @@ def main():
                      "diverges; reported with maxit 300")
         extra["oseen"].append(r)
         log(f"oseen n=128 nu=1/1000: status {r['status']}, residual {r['rel_residual']:.2e}")
+        extra["oseen_picard"] = []
+        for on in (128, 256):
+            for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+                r = bench_picard(on, 0.01, prec, args.extra_steps, args.rtol)
+                r["precision"] = name
+                extra["oseen_picard"].append(r)
+                log(f"cavity Re=200 n={on} {name}: {r['solves_per_s']} solves/s, {r['iterations']} its "
+                    f"({r['stage1_iterations']} stage I); 5 Picard steps {r['picard_seconds']} s "
+                    f"{r['picard_iterations']}")
         extra["stokes_schur_mq"] = {}
         for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
             Ps = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_SCHUR_GMG)

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libeth.so")
 ARCH = os.environ.get("ETH_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_saddle.hip", "k_vector.hip", "k_gmg.hip", "k_mq.hip", "k_oseen.hip", "k_gmres.hip", "k_adjoint.hip", "k_apply.hip", "k_schur.hip",
+SOURCES = ["k_saddle.hip", "k_vector.hip", "k_gmg.hip", "k_mq.hip", "k_oseen.hip", "k_gmres.hip", "k_adjoint.hip", "k_apply.hip", "k_schur.hip", "k_dense.hip",
            "eth_runtime.hip"]
 
 FLAGS = [

@@ -167,8 +167,14 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
 // ---------------- Oseen preconditioner pieces (k_oseen.hip) ------------------
 void launch_inject_wind(const Geo& gf, const Geo& gc, const double* wf, double* wc, hipStream_t st);
 void launch_cd_diag(const Geo& g, const double* wind, double nu, double* dF, hipStream_t st);
-void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* aug, int ni,
+// the coarse F as a dense row-major ni x ni matrix (A zero on entry)
+void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* A, int ni,
                            hipStream_t st);
+// in-place inverse of a dense row-major matrix whose leading principal blocks
+// are nonsingular (blocked Gauss-Jordan, no pivoting); work holds
+// dense_inverse_work(ni) doubles (k_dense.hip)
+size_t dense_inverse_work(int ni);
+void launch_dense_inverse(double* A, int ni, double* work, hipStream_t st);
 // damped Jacobi step on F = nu A + N(w) (residual != 0: write b - F x instead;
 // transpose != 0: F^T)
 template <typename T>

@@ -204,7 +204,7 @@ struct Problem {
 
   // Oseen: velocity multigrid on F, PCD Q1 hierarchy, FGMRES workspace
   double* wind0 = nullptr;                  // internal copy of the finest nodal wind
-  double *f_aug = nullptr, *f_col = nullptr, *f_row = nullptr;   // coarse F Gauss-Jordan workspace
+  double* f_work = nullptr;                 // blocked Gauss-Jordan workspace of the coarse F
   double* pic_b = nullptr;                  // right-hand side of a Picard step (N)
   std::vector<double*> lwind, ldF;          // wind and diag(F) per velocity level
   std::vector<Geo> qlv;                     // Q1 levels of the A_p multigrid
@@ -1238,9 +1238,7 @@ void Problem::build_oseen_velocity() {
   if (coarse_ni > 4225)
     throw std::runtime_error("unsupported:coarsest mesh too large for the dense solve");
   dense_gbuf = alloc<double>((size_t)2 * coarse_ni * max_batch);
-  f_aug = alloc<double>((size_t)coarse_ni * 2 * coarse_ni);
-  f_col = alloc<double>(coarse_ni);
-  f_row = alloc<double>(2 * (size_t)coarse_ni);
+  f_work = alloc<double>(dense_inverse_work(coarse_ni));
   Ainv = alloc<double>((size_t)coarse_ni * coarse_ni);
   AinvT = alloc<double>((size_t)coarse_ni * coarse_ni);
   refresh_wind();
@@ -1261,8 +1259,8 @@ void Problem::build_oseen_velocity() {
 
 // Everything of the Oseen preconditioners that depends on the wind: the wind
 // of each multigrid level (injection), the diagonals of F per level and the
-// dense inverse of the coarsest F (nonsymmetric, positive real: Gauss-Jordan
-// without pivoting) with its transpose.  F_1 of the PCD reads the finest wind
+// dense inverse of the coarsest F (nonsymmetric, positive real: blocked
+// Gauss-Jordan without pivoting) with its transpose.  F_1 of the PCD reads the finest wind
 // when applied.  Allocates nothing.
 void Problem::refresh_wind() {
   const int L = (int)lv.size();
@@ -1271,9 +1269,9 @@ void Problem::refresh_wind() {
     launch_cd_diag(lv[l], lwind[l], d.nu, ldF[l], st);
   }
   const int ni = coarse_ni;
-  launch_dense_convdiff(lv.back(), lwind[L - 1], d.nu, f_aug, ni, st);
-  for (int k = 0; k < ni; ++k) launch_gj_step(f_aug, ni, k, f_col, f_row, st);
-  launch_extract_inverse(f_aug, ni, Ainv, 0, st);
+  launch_fill((long long)ni * ni, 0.0, Ainv, 0, 1, st);
+  launch_dense_convdiff(lv.back(), lwind[L - 1], d.nu, Ainv, ni, st);
+  launch_dense_inverse(Ainv, ni, f_work, st);
   launch_transpose(Ainv, ni, AinvT, st);
 }
 

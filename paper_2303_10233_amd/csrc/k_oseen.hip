@@ -87,21 +87,24 @@ __global__ void k_cd_diag(Geo g, const double* __restrict__ wind, double nu, dou
 }
 
 // Dense [F | I] on the interior nodes (coarsest level): one thread per row
+// The coarse F = nu A + N(w) on the interior nodes of one level as a dense
+// row-major matrix (A must be zero on entry); one thread per row, visiting
+// only the (at most 2 x 2) elements that hold the row's node.
 __global__ void k_dense_convdiff(Geo g, const double* __restrict__ wind, double nu,
-                                 double* __restrict__ aug, int ni) {
+                                 double* __restrict__ A, int ni) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= ni) return;
   const int m = g.nq - 2;
   const int I = 1 + row % m, J = 1 + row / m;
-  double* a = aug + (long long)row * 2 * ni;
-  for (int k = 0; k < 2 * ni; ++k) a[k] = 0.0;
-  a[ni + row] = 1.0;
+  double* a = A + (long long)row * ni;
   const double Ke[3][3] = {{7, -8, 1}, {-8, 16, -8}, {1, -8, 7}};
   const double Me[3][3] = {{4, 2, -1}, {2, 16, 2}, {-1, 2, 4}};
-  for (int f = 0; f < g.n; ++f) {
+  const int f_lo = J >= 2 ? (J - 1) / 2 : 0, f_hi = J / 2 < g.n - 1 ? J / 2 : g.n - 1;
+  const int e_lo = I >= 2 ? (I - 1) / 2 : 0, e_hi = I / 2 < g.n - 1 ? I / 2 : g.n - 1;
+  for (int f = f_lo; f <= f_hi; ++f) {
     const int ly = J - 2 * f;
     if (ly < 0 || ly > 2) continue;
-    for (int e = 0; e < g.n; ++e) {
+    for (int e = e_lo; e <= e_hi; ++e) {
       const int lx = I - 2 * e;
       if (lx < 0 || lx > 2) continue;
       double w[2][3][3], row9[9];
@@ -542,13 +545,6 @@ __global__ void k_q1_dense_solve(const double* __restrict__ Ainv, int ni, const 
   }
 }
 
-__global__ void k_transpose(const double* __restrict__ a, int ni, double* __restrict__ at) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)ni * ni) return;
-  const int i = (int)(t / ni), j = (int)(t % ni);
-  at[(long long)j * ni + i] = a[t];
-}
-
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -561,9 +557,9 @@ void launch_cd_diag(const Geo& g, const double* wind, double nu, double* dF, hip
   hipLaunchKernelGGL(k_cd_diag, dim3(nb(g.nv)), dim3(256), 0, st, g, wind, nu, dF);
   ETH_LAUNCH_CHECK();
 }
-void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* aug, int ni,
+void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* A, int ni,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_dense_convdiff, dim3(nb(ni, 64)), dim3(64), 0, st, g, wind, nu, aug, ni);
+  hipLaunchKernelGGL(k_dense_convdiff, dim3(nb(ni, 64)), dim3(64), 0, st, g, wind, nu, A, ni);
   ETH_LAUNCH_CHECK();
 }
 template <typename T>
@@ -636,10 +632,6 @@ void launch_q1_shift(const Geo& g, const TI* x, long long ldx, long long offx, T
                      hipStream_t st) {
   hipLaunchKernelGGL((k_q1_shift<TI, TO>), dim3(nb(g.nk), batch), dim3(256), 0, st, g, x, ldx, offx, out,
                      ldo, offo, sums, scale, gate);
-  ETH_LAUNCH_CHECK();
-}
-void launch_transpose(const double* a, int ni, double* at, hipStream_t st) {
-  hipLaunchKernelGGL(k_transpose, dim3(nb((long long)ni * ni)), dim3(256), 0, st, a, ni, at);
   ETH_LAUNCH_CHECK();
 }
 void launch_unit_columns(double* cols, int ni, hipStream_t st) {
