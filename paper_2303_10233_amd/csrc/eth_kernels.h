@@ -129,9 +129,6 @@ template <typename T>
 hipError_t prepare_vcycle_tail(size_t lds);   // allows the dynamic LDS size
 // dense Laplacian of the interior nodes, and Gauss-Jordan inverse helpers
 void launch_dense_laplacian(const Geo& g, double* A, int ni, hipStream_t st);
-void launch_gj_step(double* aug, int ni, int k, double* colbuf, double* rowbuf,
-                    hipStream_t st);
-void launch_extract_inverse(const double* aug, int ni, double* Ainv, int symmetric, hipStream_t st);
 // setup helpers on one FP64 plane: mode 0: y = A x, mode 1: y = D^{-1} x
 // (interior nodes; boundary 0)
 void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStream_t st);
@@ -175,6 +172,8 @@ void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* 
 // dense_inverse_work(ni) doubles (k_dense.hip)
 size_t dense_inverse_work(int ni);
 void launch_dense_inverse(double* A, int ni, double* work, hipStream_t st);
+// A = (A + A^T) / 2 in place (the inverse of a symmetric matrix, against rounding)
+void launch_symmetrize(double* A, int ni, hipStream_t st);
 // damped Jacobi step on F = nu A + N(w) (residual != 0: write b - F x instead;
 // transpose != 0: F^T)
 template <typename T>
@@ -208,7 +207,7 @@ void launch_q1_shift(const Geo& g, const TI* x, long long ldx, long long offx, T
                      long long offo, const double* sums, double scale, int batch, Gate gate,
                      hipStream_t st);
 void launch_unit_columns(double* cols, int ni, hipStream_t st);
-void launch_dense_ap_aug(const double* cols, int ni, double shift, double* aug, hipStream_t st);
+void launch_dense_sym_shift(const double* cols, int ni, double shift, double* A, hipStream_t st);
 template <typename T>
 void launch_q1_dense_solve(const double* Ainv, int ni, const T* b, T* x, int batch, Gate gate,
                            hipStream_t st);

@@ -512,13 +512,11 @@ void Problem::build_velocity() {
   // dense inverse of the coarsest-level Laplacian (Gauss-Jordan, SPD, no pivoting)
   {
     const int ni = coarse_ni;
-    double* aug = alloc<double>((size_t)ni * 2 * ni);
-    double* col = alloc<double>(ni);
-    double* row = alloc<double>(2 * (size_t)ni);
+    double* work = alloc<double>(dense_inverse_work(ni));
     Ainv = alloc<double>((size_t)ni * ni);
-    launch_dense_laplacian(gc, aug, ni, st);
-    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
-    launch_extract_inverse(aug, ni, Ainv, 1, st);
+    launch_dense_laplacian(gc, Ainv, ni, st);
+    launch_dense_inverse(Ainv, ni, work, st);
+    launch_symmetrize(Ainv, ni, st);
   }
   const int L = (int)lv.size();
   lam.assign(std::max(L - 1, 0), 0.0);
@@ -851,13 +849,11 @@ void Problem::build_schur() {
     ETH_HIP(hipStreamSynchronize(st));
     double mean = 0.0;
     for (double v : hd) mean += (1.0 / v) / ni;
-    double* aug = alloc<double>((size_t)ni * 2 * ni);
-    double* col = alloc<double>(ni);
-    double* row = alloc<double>(2 * (size_t)ni);
+    double* work = alloc<double>(dense_inverse_work(ni));
     sAinv = alloc<double>((size_t)ni * ni);
-    launch_dense_ap_aug(acols, ni, mean / ni, aug, st);
-    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
-    launch_extract_inverse(aug, ni, sAinv, 1, st);
+    launch_dense_sym_shift(acols, ni, mean / ni, sAinv, st);
+    launch_dense_inverse(sAinv, ni, work, st);
+    launch_symmetrize(sAinv, ni, st);
   }
   ssums = alloc<double>(max_batch);
 }
@@ -1342,13 +1338,11 @@ void Problem::build_pcd() {
     ETH_HIP(hipStreamSynchronize(st));
     double mean = 0.0;
     for (double v : hd) mean += v / ni;
-    double* aug = alloc<double>((size_t)ni * 2 * ni);
-    double* col = alloc<double>(ni);
-    double* row = alloc<double>(2 * (size_t)ni);
+    double* work = alloc<double>(dense_inverse_work(ni));
     qAinv = alloc<double>((size_t)ni * ni);
-    launch_dense_ap_aug(acols, ni, mean / ni, aug, st);
-    for (int k = 0; k < ni; ++k) launch_gj_step(aug, ni, k, col, row, st);
-    launch_extract_inverse(aug, ni, qAinv, 1, st);
+    launch_dense_sym_shift(acols, ni, mean / ni, qAinv, st);
+    launch_dense_inverse(qAinv, ni, work, st);
+    launch_symmetrize(qAinv, ni, st);
   }
   const size_t nq1 = (size_t)max_batch * g.nk * es;
   pa = alloc<char>(nq1);

@@ -165,7 +165,24 @@ __global__ __launch_bounds__(256) void k_transpose_tiled(const double* __restric
   }
 }
 
+__global__ void k_symmetrize(double* __restrict__ A, int ni) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)ni * ni) return;
+  const int i = (int)(t / ni), j = (int)(t % ni);
+  if (j <= i) return;   // each pair once, by the thread of its upper entry
+  const long long o = (long long)j * ni + i;
+  const double v = 0.5 * (A[t] + A[o]);
+  A[t] = v;
+  A[o] = v;
+}
+
 }  // namespace
+
+void launch_symmetrize(double* A, int ni, hipStream_t st) {
+  const long long n = (long long)ni * ni;
+  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, ni);
+  ETH_LAUNCH_CHECK();
+}
 
 size_t dense_inverse_work(int ni) { return (size_t)BK * BK + 2 * (size_t)BK * ni; }
 

@@ -564,35 +564,7 @@ __global__ void k_dense_laplacian(Geo g, double* __restrict__ A, int ni) {
     k1row(Ii & 1, kx); m1row(Ii & 1, mx); k1row(Ji & 1, ky); m1row(Ji & 1, my);
     v = (kx[dx + 2] * my[dy + 2] + mx[dx + 2] * ky[dy + 2]) / 90.0;
   }
-  A[(long long)i * 2 * ni + j] = v;             // augmented [A | I]
-  A[(long long)i * 2 * ni + ni + j] = (i == j) ? 1.0 : 0.0;
-}
-
-__global__ void k_gj_pivot(double* __restrict__ aug, int ni, int k, double* __restrict__ col,
-                           double* __restrict__ row) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const double piv = aug[(long long)k * 2 * ni + k];
-  if (t < ni) col[t] = aug[(long long)t * 2 * ni + k];
-  if (t < 2 * ni) row[t] = aug[(long long)k * 2 * ni + t] / piv;
-}
-
-__global__ void k_gj_update(double* __restrict__ aug, int ni, int k, const double* __restrict__ col,
-                            const double* __restrict__ row) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)ni * 2 * ni) return;
-  const int i = (int)(t / (2 * ni)), j = (int)(t % (2 * ni));
-  if (i == k) aug[t] = row[j];
-  else aug[t] -= col[i] * row[j];
-}
-
-__global__ void k_extract_inverse(const double* __restrict__ aug, int ni, double* __restrict__ Ainv,
-                                  int symmetric) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)ni * ni) return;
-  const int i = (int)(t / ni), j = (int)(t % ni);
-  // the inverse of a symmetric matrix is symmetrised against rounding
-  Ainv[t] = symmetric ? 0.5 * (aug[(long long)i * 2 * ni + ni + j] + aug[(long long)j * 2 * ni + ni + i])
-                      : aug[(long long)i * 2 * ni + ni + j];
+  A[k] = v;
 }
 
 // mode 0: y = A x, mode 1: y = D^{-1} x, on one FP64 plane (interior nodes; boundary 0)
@@ -711,23 +683,6 @@ hipError_t prepare_vcycle_tail(size_t lds) {
 void launch_dense_laplacian(const Geo& g, double* A, int ni, hipStream_t st) {
   const long long n = (long long)ni * ni;
   hipLaunchKernelGGL(k_dense_laplacian, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, A, ni);
-  ETH_LAUNCH_CHECK();
-}
-
-void launch_gj_step(double* aug, int ni, int k, double* colbuf, double* rowbuf, hipStream_t st) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3((2 * ni + 255) / 256), dim3(256), 0, st, aug, ni, k, colbuf,
-                     rowbuf);
-  ETH_LAUNCH_CHECK();
-  const long long n = (long long)ni * 2 * ni;
-  hipLaunchKernelGGL(k_gj_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, aug, ni, k,
-                     colbuf, rowbuf);
-  ETH_LAUNCH_CHECK();
-}
-
-void launch_extract_inverse(const double* aug, int ni, double* Ainv, int symmetric, hipStream_t st) {
-  const long long n = (long long)ni * ni;
-  hipLaunchKernelGGL(k_extract_inverse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, aug, ni,
-                     Ainv, symmetric);
   ETH_LAUNCH_CHECK();
 }
 

@@ -514,13 +514,13 @@ __global__ void k_q1_shift(Geo g, const TI* __restrict__ x, long long ldx, long 
 }
 
 // dense [A_p + s 1 1^T | I] from the columns A_p e_j (stored as a batch)
-__global__ void k_dense_ap_aug(const double* __restrict__ cols, int ni, double shift,
-                               double* __restrict__ aug) {
+// A = (C + C^T)/2 + shift 1 1^T from the columns C of a symmetric operator
+__global__ void k_dense_sym_shift(const double* __restrict__ cols, int ni, double shift,
+                                  double* __restrict__ A) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)ni * ni) return;
   const int i = (int)(t / ni), j = (int)(t % ni);
-  aug[(long long)i * 2 * ni + j] = 0.5 * (cols[(long long)j * ni + i] + cols[(long long)i * ni + j]) + shift;
-  aug[(long long)i * 2 * ni + ni + j] = (i == j) ? 1.0 : 0.0;
+  A[t] = 0.5 * (cols[(long long)j * ni + i] + cols[(long long)i * ni + j]) + shift;
 }
 
 __global__ void k_unit_columns(double* __restrict__ cols, int ni) {
@@ -638,8 +638,8 @@ void launch_unit_columns(double* cols, int ni, hipStream_t st) {
   hipLaunchKernelGGL(k_unit_columns, dim3(nb((long long)ni * ni)), dim3(256), 0, st, cols, ni);
   ETH_LAUNCH_CHECK();
 }
-void launch_dense_ap_aug(const double* cols, int ni, double shift, double* aug, hipStream_t st) {
-  hipLaunchKernelGGL(k_dense_ap_aug, dim3(nb((long long)ni * ni)), dim3(256), 0, st, cols, ni, shift, aug);
+void launch_dense_sym_shift(const double* cols, int ni, double shift, double* A, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_sym_shift, dim3(nb((long long)ni * ni)), dim3(256), 0, st, cols, ni, shift, A);
   ETH_LAUNCH_CHECK();
 }
 template <typename T>
