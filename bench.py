@@ -35,11 +35,12 @@ def log(msg):
 KERNEL_SOURCES = {"k_mq_cheb_fused": "k_mq.hip", "k_apply": "k_apply.hip", "k_cheb_step": "k_gmg.hip"}
 
 
-def measured_traffic(kernel, n):
+def measured_traffic(kernel, n, variant):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a
-    plain copy of known size), or None when there is none for this workload
-    or the kernel source changed since the counters were taken."""
+    plain copy of known size), or None when there is none for this workload,
+    the counters were read on another template variant (`variant`, the full
+    kernel name), or the kernel source changed since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_stokes{n}_traffic.json")
     src = KERNEL_SOURCES.get(kernel)
@@ -49,7 +50,7 @@ def measured_traffic(kernel, n):
         rec = json.load(f)
     with open(os.path.join(ROOT, "paper_2303_10233_amd", "csrc", src), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    if rec.get("source_sha256") != sha or (variant and rec.get("kernel") != variant):
         return None
     return rec.get("bytes_per_launch")
 
@@ -296,6 +297,34 @@ def microbench(reps):
     return out
 
 
+def counters_run(n, reps, tile):
+    """The launches that the byte counters are read on (run under
+    `rocprofv3 --pmc FETCH_SIZE` and then `--pmc WRITE_SIZE`): the dominant
+    kernel of the headline workload (the fused Chebyshev-SGS step, mixed,
+    n x n) and plain copies of known size, at n and at n = 2048 (336 MB per
+    vector, beyond every cache), `reps` launches each.  The tile side of the
+    fused step is fixed (`tile`, the one set-up picks for this workload when
+    timed without a profiler: under the counters every launch is serialised
+    and timing-based choices would differ between runs).  Prints the launch
+    record the reduction script needs."""
+    import torch
+    from paper_2303_10233_amd import eth
+    rec = {"n": n, "reps": reps, "launches": []}
+    for nn, kernels in ((n, (eth.K_MQ_CHEB_STEP, eth.K_COPY)), (2048, (eth.K_COPY,))):
+        P = eth.Problem(nn, precision=eth.MIXED, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0",
+                        mq_tile=tile)
+        torch.cuda.synchronize()
+        for k in kernels:
+            ms, by = P.profile_kernel(k, reps=reps)
+            rec["launches"].append(dict(n=nn, kernel=eth.KERNEL_NAMES[k], bytes_per_launch=by,
+                                        avg_us=round(1e3 * ms, 3), mq_tile=P.mq_tile()[0]))
+            log(f"counters n={nn} {eth.KERNEL_NAMES[k]}: {by:.0f} B, {1e3 * ms:.2f} us")
+        P.close()
+        del P
+        torch.cuda.empty_cache()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,14 +334,20 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--profile-reps", type=int, default=50)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the Oseen, 64-RHS and ragged-batch measurements")
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--no-micro", action="store_true",
                     help="skip the kernel bandwidth measurements at n = 2048 and 512 x 16")
+    ap.add_argument("--counters", action="store_true",
+                    help="only the launches read by the rocprofv3 byte counters (see counters_run)")
+    ap.add_argument("--mq-tile", type=int, default=16, help="tile side of the fused M_Q step in --counters")
     args = ap.parse_args()
+    if args.counters:
+        counters_run(args.n, args.profile_reps, args.mq_tile)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(multi-GPU sharding is described but not built)"}))
@@ -366,7 +401,9 @@ def main():
     dk = kernels[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(dk["gbs"], 2),
                 "peak": MI355X_HBM_GBS, "unit": "GB/s",
-                "frac": round(dk["gbs"] / MI355X_HBM_GBS, 5), "traffic": measured_traffic(dom, n),
+                "frac": round(dk["gbs"] / MI355X_HBM_GBS, 5),
+                "traffic": measured_traffic(dom, n, f"k_mq_cheb_fused<float, {Pm.mq_tile()[0]}>"
+                                            if dom == "k_mq_cheb_fused" else None),
                 "bytes_per_launch": dk["bytes"], "avg_launch_us": round(dk["avg_us"], 3)}
     log("kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us {v['gbs']:.0f}GB/s"
                                 for k, v in kernels.items()))

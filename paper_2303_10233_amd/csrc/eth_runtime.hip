@@ -660,32 +660,38 @@ int Problem::tune_mq_tile(int batch) {
     (void)hipEventDestroy(e0);
     throw std::runtime_error("hipEventCreate failed");
   }
-  const int cands[3] = {16, 32, 64};
+  // candidates are timed in interleaved rounds after a common warm-up, and
+  // each keeps its fastest round, so that a clock ramp at set-up does not
+  // favour the later ones
+  std::vector<int> cands = {16, 32};
+  if (mixed) cands.push_back(64);
+  std::vector<float> best_ms(cands.size(), 0.0f);
   int best = 32;
-  float best_ms = 0.0f;
   try {
-    for (int t : cands) {
-      if (t == 64 && !mixed) continue;
-      auto launch = [&] {
-        if (mixed)
-          launch_mq_cheb_fused<float>(g, (float*)mq_r, (float*)mq_z, (float*)mq_t, (float*)mq_d, 0.5,
-                                      0.1, 0, batch, no_gate(), st, t);
-        else
-          launch_mq_cheb_fused<double>(g, (double*)mq_r, (double*)mq_z, (double*)mq_t, (double*)mq_d,
-                                       0.5, 0.1, 0, batch, no_gate(), st, t);
-      };
-      for (int i = 0; i < 3; ++i) launch();
-      ETH_HIP(hipEventRecord(e0, st));
-      for (int i = 0; i < 10; ++i) launch();
-      ETH_HIP(hipEventRecord(e1, st));
-      ETH_HIP(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (best_ms == 0.0f || ms < best_ms) {
-        best_ms = ms;
-        best = t;
+    auto launch = [&](int t) {
+      if (mixed)
+        launch_mq_cheb_fused<float>(g, (float*)mq_r, (float*)mq_z, (float*)mq_t, (float*)mq_d, 0.5, 0.1,
+                                    0, batch, no_gate(), st, t);
+      else
+        launch_mq_cheb_fused<double>(g, (double*)mq_r, (double*)mq_z, (double*)mq_t, (double*)mq_d,
+                                     0.5, 0.1, 0, batch, no_gate(), st, t);
+    };
+    for (int t : cands)
+      for (int i = 0; i < 20; ++i) launch(t);
+    for (int round = 0; round < 3; ++round)
+      for (size_t c = 0; c < cands.size(); ++c) {
+        ETH_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < 10; ++i) launch(cands[c]);
+        ETH_HIP(hipEventRecord(e1, st));
+        ETH_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (round == 0 || ms < best_ms[c]) best_ms[c] = ms;
       }
-    }
+    size_t bi = 0;
+    for (size_t c = 1; c < cands.size(); ++c)
+      if (best_ms[c] < best_ms[bi]) bi = c;
+    best = cands[bi];
   } catch (...) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
