@@ -229,6 +229,11 @@ struct Problem {
   int gexec_batch = -1;
   hipStream_t gst = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Stokes: the pressure block of the block-diagonal preconditioner runs on
+  // pst concurrently with the velocity V-cycle (fork / join by events; inside
+  // a captured graph the two become parallel branches)
+  hipStream_t pst = nullptr;
+  hipEvent_t ev_pf = nullptr, ev_pj = nullptr;
   bool own_stream = false;           // st was created by the library (ragged batches)
 
   template <typename T>
@@ -244,6 +249,9 @@ struct Problem {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_pf) (void)hipEventDestroy(ev_pf);
+    if (ev_pj) (void)hipEventDestroy(ev_pj);
+    if (pst) (void)hipStreamDestroy(pst);
     if (ev_poll) (void)hipEventDestroy(ev_poll);
     if (own_stream && st) (void)hipStreamDestroy(st);
     if (gst) (void)hipStreamDestroy(gst);
@@ -435,6 +443,11 @@ void Problem::setup(const eth_problem_desc& desc) {
     build_gmres();
   } else {
     build_velocity();
+    if (!std::getenv("ETH_DEBUG_SERIAL_PRECOND")) {
+      ETH_HIP(hipStreamCreateWithFlags(&pst, hipStreamNonBlocking));
+      ETH_HIP(hipEventCreateWithFlags(&ev_pf, hipEventDisableTiming));
+      ETH_HIP(hipEventCreateWithFlags(&ev_pj, hipEventDisableTiming));
+    }
   }
   build_pressure();
   ETH_HIP(hipStreamSynchronize(st));
@@ -925,9 +938,27 @@ void Problem::mq_schur(const double* r, double* z, long long ld, int batch, Gate
 }
 
 void Problem::precond(const double* r, double* z, long long ld, int batch, Gate gate) {
+  // the two diagonal blocks read disjoint parts of r and write disjoint parts
+  // of z, and share no workspace
+  if (pst) {
+    ETH_HIP(hipEventRecord(ev_pf, st));
+    ETH_HIP(hipStreamWaitEvent(pst, ev_pf, 0));
+    {
+      struct Restore {
+        hipStream_t& s;
+        hipStream_t v;
+        ~Restore() { s = v; }
+      } restore{st, st};
+      st = pst;
+      mq_solve(r, z, ld, batch, gate, d.nu);
+    }
+    ETH_HIP(hipEventRecord(ev_pj, pst));
+  } else {
+    mq_solve(r, z, ld, batch, gate, d.nu);
+  }
   if (mixed) vcycle<float>(r, z, ld, batch, gate);
   else vcycle<double>(r, z, ld, batch, gate);
-  mq_solve(r, z, ld, batch, gate, d.nu);
+  if (pst) ETH_HIP(hipStreamWaitEvent(st, ev_pj, 0));
 }
 
 // ---------------------------------------------------------------- MINRES

@@ -193,6 +193,29 @@ def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
         assert np.array_equal(z_fused[tile][o:], z_plain[o:]), tile
 
 
+@pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
+def test_concurrent_blocks_equal_serial_preconditioner(prec, monkeypatch):
+    """The pressure block runs on a second stream beside the V-cycle (a
+    parallel branch of the captured graph): preconditioner and graph-replayed
+    solves are bit for bit those of the serial order."""
+    n = 64
+    print(f"[concurrent precond] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    r = uniform_vector(m.N, 17)
+    r[: 2 * m.nv][System(m).vel_bnd] = 0.0
+    P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_tile=16)
+    z1 = _np(P.apply_preconditioner(_t(r)))
+    b = P.assemble_rhs()
+    x1, i1 = P.solve(b, rtol=1e-10, maxit=500, use_graph=True)
+    monkeypatch.setenv("ETH_DEBUG_SERIAL_PRECOND", "1")
+    Q = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_tile=16)
+    z2 = _np(Q.apply_preconditioner(_t(r)))
+    x2, i2 = Q.solve(Q.assemble_rhs(), rtol=1e-10, maxit=500, use_graph=True)
+    assert np.array_equal(z1, z2)
+    assert i1[0]["iterations"] == i2[0]["iterations"]
+    assert torch.equal(x1, x2)
+
+
 def test_mq_tile_rejects_unsupported_sides():
     with pytest.raises(Exception):
         eth.Problem(16, mq_tile=24)
