@@ -245,6 +245,11 @@ struct MqTile {
   // threads: one per colour node of a pass where that fits a block
   static constexpr int FT = TQ >= 32 ? 1024 : 64 * ((NC * NC + 63) / 64);
   static constexpr int OWN = (TQ * TQ + FT - 1) / FT;   // owned nodes per thread
+  // right-hand sides of the thread's nodes kept in registers across passes
+  // and z_k, d of its owned nodes fetched before the sweep (TQ = 64 reads
+  // them when needed: two nodes per colour, seven elements and four owned
+  // nodes per thread would exceed the register budget of 1024 threads)
+  static constexpr bool CACHE_R = TQ <= 32;
   static_assert(TQ % 2 == 0, "parity of local and global indices must agree");
 };
 
@@ -274,22 +279,26 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
   T* dr = d + (long long)rhs * np;
   // the owned node / element values of z_k and d, fetched before the staging
   // so that their latency overlaps it
-  T z0q[OWN], d0q[OWN], z0e[OWN], d0e[OWN];
+  constexpr bool PF = Tl::CACHE_R;   // TQ = 64 reads them at the end instead (registers)
+  constexpr int OWP = PF ? OWN : 1;
+  T z0q[OWP], d0q[OWP], z0e[OWP], d0e[OWP];
+  if constexpr (PF) {
 #pragma unroll
-  for (int i = 0; i < OWN; ++i) {
-    const int idx = tid + i * FT, ox = idx % TQ, oy = idx / TQ;
-    const int oc = c0 + ox, od = d0 + oy;
-    z0q[i] = d0q[i] = z0e[i] = d0e[i] = T(0);
-    if (!first && idx < TQ * TQ) {
-      if (oc <= n && od <= n) {
-        const long long oq = (long long)od * (n + 1) + oc;
-        z0q[i] = zi[oq];
-        d0q[i] = dr[oq];
-      }
-      if (oc < n && od < n) {
-        const long long oe = g.nk + (long long)od * n + oc;
-        z0e[i] = zi[oe];
-        d0e[i] = dr[oe];
+    for (int i = 0; i < OWN; ++i) {
+      const int idx = tid + i * FT, ox = idx % TQ, oy = idx / TQ;
+      const int oc = c0 + ox, od = d0 + oy;
+      z0q[i] = d0q[i] = z0e[i] = d0e[i] = T(0);
+      if (!first && idx < TQ * TQ) {
+        if (oc <= n && od <= n) {
+          const long long oq = (long long)od * (n + 1) + oc;
+          z0q[i] = zi[oq];
+          d0q[i] = dr[oq];
+        }
+        if (oc < n && od < n) {
+          const long long oe = g.nk + (long long)od * n + oc;
+          z0e[i] = zi[oe];
+          d0e[i] = dr[oe];
+        }
       }
     }
   }
@@ -310,37 +319,79 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
     }
   });
   if (off) return;   // uniform per block
+  // A thread updates the same node of a colour (and the same elements) in
+  // every pass: their LDS indices, boundary flags and right-hand sides are
+  // set up once here, so that a pass is only the stencil loads, the update
+  // and the barrier.
+  constexpr int CPT = (NC * NC + FT - 1) / FT;   // nodes per thread and colour
+  constexpr int EPT = (RE * RE + FT - 1) / FT;   // elements per thread
+  // qi: LDS index of the node (-1: none); qf: boundary flags Lx | Rx << 1 |
+  // Ly << 2 | Ry << 3 and the local row ly << 4 (the lower-left element of
+  // the node is at qi - RQ - ly in the element array)
+  int qi[4][CPT], qf[4][CPT];
+#pragma unroll
+  for (int colour = 0; colour < 4; ++colour)
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int idx = tid + j * FT;
+      const int lx = ((colour & 1) == 0 ? 2 : 1) + 2 * (idx % NC);
+      const int ly = ((colour >> 1) == 0 ? 2 : 1) + 2 * (idx / NC);
+      const int c = gx + lx, dd = gy + ly;
+      const bool ok = idx < NC * NC && lx <= RQ - 2 && ly <= RQ - 2 && c >= 0 && c <= n && dd >= 0 && dd <= n;
+      qi[colour][j] = ok ? ly * RQ + lx : -1;
+      qf[colour][j] = (c > 0) | ((c < n) << 1) | ((dd > 0) << 2) | ((dd < n) << 3) | (ly << 4);
+    }
+  // ek: element index k | local row << 16 (-1: none); its lower-left node is
+  // at k + row in the node array
+  static_assert(RE * RE < (1 << 16), "element index must fit 16 bits");
+  int ek[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int k = tid + j * FT, lx = k % RE, ly = k / RE;
+    const int e = gx + lx, f = gy + ly;
+    const bool ok = k < RE * RE && e >= 0 && e < n && f >= 0 && f < n;
+    ek[j] = ok ? (k | (ly << 16)) : -1;
+  }
   __syncthreads();
+  constexpr bool CR = Tl::CACHE_R;
+  T qr[4][CR ? CPT : 1], er[CR ? EPT : 1];
+  if constexpr (CR) {
+#pragma unroll
+    for (int colour = 0; colour < 4; ++colour)
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) qr[colour][j] = qi[colour][j] >= 0 ? rq[qi[colour][j]] : T(0);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) er[j] = ek[j] >= 0 ? re[ek[j] & 0xffff] : T(0);
+  }
   constexpr int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
-#pragma unroll 1
+#pragma unroll
   for (int pass = 0; pass < 9; ++pass) {
     const int colour = order[pass];
     if (colour < 4) {
-      for (int idx = tid; idx < NC * NC; idx += FT) {
-        const int lx = ((colour & 1) == 0 ? 2 : 1) + 2 * (idx % NC);
-        const int ly = ((colour >> 1) == 0 ? 2 : 1) + 2 * (idx / NC);
-        const int c = gx + lx, dd = gy + ly;
-        if (lx > RQ - 2 || ly > RQ - 2 || c < 0 || c > n || dd < 0 || dd > n) continue;
-        const int Lx = (c > 0), Rx = (c < n), Ly = (dd > 0), Ry = (dd < n);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        const int li = qi[colour][j];
+        if (li < 0) continue;
+        const int fl = qf[colour][j], eb = li - RQ - (fl >> 4);
         T q9[9], e4[4];
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-          for (int aa = 0; aa < 3; ++aa) q9[bb * 3 + aa] = tq[(ly + bb - 1) * RQ + (lx + aa - 1)];
+          for (int aa = 0; aa < 3; ++aa) q9[bb * 3 + aa] = tq[li + (bb - 1) * RQ + (aa - 1)];
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-          for (int aa = 0; aa < 2; ++aa) e4[bb * 2 + aa] = te[(ly + bb - 1) * RE + (lx + aa - 1)];
-        const int li = ly * RQ + lx;
-        tq[li] = q1_gs_update<T>(tq[li], rq[li], q9, e4, Lx, Rx, Ly, Ry, h2_36, h2_4, inv_h2_9);
+          for (int aa = 0; aa < 2; ++aa) e4[bb * 2 + aa] = te[eb + bb * RE + aa];
+        tq[li] = q1_gs_update<T>(q9[4], CR ? qr[colour][CR ? j : 0] : rq[li], q9, e4, fl & 1, (fl >> 1) & 1, (fl >> 2) & 1,
+                                 (fl >> 3) & 1, h2_36, h2_4, inv_h2_9);
       }
     } else {
-      for (int k = tid; k < RE * RE; k += FT) {
-        const int lx = k % RE, ly = k / RE;
-        const int e = gx + lx, f = gy + ly;
-        if (e < 0 || e >= n || f < 0 || f >= n) continue;
-        const int q = ly * RQ + lx;
-        te[k] = p0_gs_update<T>(re[k], tq[q], tq[q + 1], tq[q + RQ], tq[q + RQ + 1], inv_h2);
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int v = ek[j];
+        if (v < 0) continue;
+        const int k = v & 0xffff, q = k + (v >> 16);
+        te[k] = p0_gs_update<T>(CR ? er[CR ? j : 0] : re[k], tq[q], tq[q + 1], tq[q + RQ], tq[q + RQ + 1], inv_h2);
       }
     }
     __syncthreads();
@@ -355,14 +406,18 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
     if (oc <= n && od <= n) {
       const long long oq = (long long)od * (n + 1) + oc;
       T dn;
-      const T zn = cheb_combine<T>(tq[(oy + HALO) * RQ + (ox + HALO)], z0q[i], d0q[i], ta, tb, first, dn);
+      const T zq = PF ? z0q[PF ? i : 0] : (first ? T(0) : zi[oq]);
+      const T dq = PF ? d0q[PF ? i : 0] : (first ? T(0) : dr[oq]);
+      const T zn = cheb_combine<T>(tq[(oy + HALO) * RQ + (ox + HALO)], zq, dq, ta, tb, first, dn);
       dr[oq] = dn;
       zo[oq] = zn;
     }
     if (oc < n && od < n) {
       const long long oe = g.nk + (long long)od * n + oc;
       T dn;
-      const T zn = cheb_combine<T>(te[(oy + HALO) * RE + (ox + HALO)], z0e[i], d0e[i], ta, tb, first, dn);
+      const T ze = PF ? z0e[PF ? i : 0] : (first ? T(0) : zi[oe]);
+      const T de = PF ? d0e[PF ? i : 0] : (first ? T(0) : dr[oe]);
+      const T zn = cheb_combine<T>(te[(oy + HALO) * RE + (ox + HALO)], ze, de, ta, tb, first, dn);
       dr[oe] = dn;
       zo[oe] = zn;
     }
