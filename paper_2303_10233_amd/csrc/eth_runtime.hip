@@ -773,16 +773,23 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
   const int nbk = dot_blocks(np);
   RedCtx rin = red(nbk, 1, EPI_SCALE, &d_scale[1]);
   launch_mq_kdot<double>(g, r, ld, g.off_pk(), batch, rin, gate, st);
-  launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);
   if (fused_mq) {
     // ping-pong between mq_z and mq_t; the result ends in zz
-    // step k reads zb[k&1] and writes zb[(k+1)&1]; the last step must write zz
+    // step k reads zb[k&1] and writes zb[(k+1)&1]; the last step must write zz.
+    // The first step takes r from the FP64 vectors with the input projection
+    // (no separate projection launch).  k^T z of the output projection stays a
+    // kernel of its own: reduced by the fused step, its summation order would
+    // follow the tile side, which set-up picks by timing, and results would
+    // then differ in the last bits between otherwise identical problems.
     T* zb[2] = {zz, tt};
     if (d.mq_steps % 2 == 1) std::swap(zb[0], zb[1]);
+    const int tile = mq_tile_for(batch);
+    const MqSource src{r, ld, mq_coef};
     for (int k = 0; k < d.mq_steps; ++k)
-      launch_mq_cheb_fused<T>(g, rr, zb[k & 1], zb[(k + 1) & 1], dd, mq_a[k], mq_b[k], k == 0,
-                              batch, gate, st, mq_tile_for(batch));
+      launch_mq_cheb_fused<T>(g, rr, zb[k & 1], zb[(k + 1) & 1], dd, mq_a[k], mq_b[k], k == 0, batch,
+                              gate, st, tile, k == 0 ? &src : nullptr);
   } else {
+    launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);
     static const int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
     for (int k = 0; k < d.mq_steps; ++k) {
       for (int c = 0; c < 9; ++c) launch_mq_colour<T>(g, rr, tt, order[c], batch, gate, st);

@@ -253,11 +253,15 @@ struct MqTile {
   static_assert(TQ % 2 == 0, "parity of local and global indices must agree");
 };
 
+// src (first step only, may be null): take r from the FP64 vectors, projected
+// on k^perp as r - coef k, and store it to the workspace r (owned entries) for
+// the later steps.
 template <typename T, int TQ>
-__global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T* __restrict__ r,
+__global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __restrict__ r,
                                                                   const T* __restrict__ zin,
                                                                   T* __restrict__ zout, T* __restrict__ d,
-                                                                  double a, double b, int first, Gate gate) {
+                                                                  double a, double b, int first, Gate gate,
+                                                                  MqSource src) {
   using Tl = MqTile<TQ>;
   constexpr int RQ = Tl::RQ, RE = Tl::RE, NC = Tl::NC, FT = Tl::FT, OWN = Tl::OWN;
   __shared__ T tq[RQ * RQ];
@@ -268,7 +272,9 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
   const bool off = gate.off(rhs);   // tested after the staging, so its load overlaps them
   const int n = g.n;
   const long long np = (long long)g.nk + g.n0;
-  const T* rr = r + (long long)rhs * np;
+  T* rr = r + (long long)rhs * np;
+  const double* r64 = src.r ? src.r + (long long)rhs * src.ld + g.off_pk() : nullptr;
+  const double cf = src.r ? src.coef[rhs] : 0.0;
   const T* zi = zin + (long long)rhs * np;
   const int c0 = blockIdx.x * TQ, d0 = blockIdx.y * TQ;
   const int gx = c0 - HALO, gy = d0 - HALO;      // global index of local 0
@@ -302,11 +308,12 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
       }
     }
   }
+  // (the projection is the expression of k_mq_project_in, so both paths agree bit for bit)
   stage2<FT, RQ * RQ>(tq, rq, tid, [&](int k, T& tv, T& rv) {
     const int c = gx + k % RQ, dd = gy + k / RQ;
     if (c >= 0 && c <= n && dd >= 0 && dd <= n) {
       const long long q = (long long)dd * (n + 1) + c;
-      rv = rr[q];
+      rv = r64 ? (T)(r64[q] - cf * 1.0) : rr[q];
       if (!first) tv = zi[q];
     }
   });
@@ -314,7 +321,7 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
     const int e = gx + k % RE, f = gy + k / RE;
     if (e >= 0 && e < n && f >= 0 && f < n) {
       const long long q = g.nk + (long long)f * n + e;
-      rv = rr[q];
+      rv = r64 ? (T)(r64[q] - cf * -1.0) : rr[q];
       if (!first) tv = zi[q];
     }
   });
@@ -411,6 +418,7 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
       const T zn = cheb_combine<T>(tq[(oy + HALO) * RQ + (ox + HALO)], zq, dq, ta, tb, first, dn);
       dr[oq] = dn;
       zo[oq] = zn;
+      if (r64) rr[oq] = rq[(oy + HALO) * RQ + (ox + HALO)];
     }
     if (oc < n && od < n) {
       const long long oe = g.nk + (long long)od * n + oc;
@@ -420,6 +428,7 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, const T
       const T zn = cheb_combine<T>(te[(oy + HALO) * RE + (ox + HALO)], ze, de, ta, tb, first, dn);
       dr[oe] = dn;
       zo[oe] = zn;
+      if (r64) rr[oe] = re[(oy + HALO) * RE + (ox + HALO)];
     }
   }
 }
@@ -497,24 +506,27 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
 
 
 template <typename T>
-void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d, double a, double b,
-                          int first, int batch, Gate gate, hipStream_t st, int tile) {
+void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, T* d, double a, double b,
+                          int first, int batch, Gate gate, hipStream_t st, int tile, const MqSource* src) {
+  if (tile == 64 && sizeof(T) != 4) throw std::invalid_argument("M_Q tile 64 needs the FP32 preconditioner");
+  const int tq = (tile == 16 || tile == 64) ? tile : 32;
+  const MqSource s = src ? *src : MqSource{};
 #define ETH_MQF(TQ)                                                                                    \
   hipLaunchKernelGGL((k_mq_cheb_fused<T, TQ>),                                                        \
                      dim3((g.n + 1 + TQ - 1) / TQ, (g.n + 1 + TQ - 1) / TQ, batch),                   \
-                     dim3(MqTile<TQ>::FT), 0, st, g, r, zin, zout, d, a, b, first, gate)
-  if (tile == 16) {
+                     dim3(MqTile<TQ>::FT), 0, st, g, r, zin, zout, d, a, b, first, gate, s)
+  if (tq == 16) {
     ETH_MQF(16);
-  } else if (tile == 64) {
+  } else if (tq == 64) {
     // the 84^2 + 83^2 staged values of two arrays fit the LDS in FP32 only
     if constexpr (sizeof(T) == 4) ETH_MQF(64);
-    else throw std::invalid_argument("M_Q tile 64 needs the FP32 preconditioner");
   } else {
     ETH_MQF(32);
   }
 #undef ETH_MQF
   ETH_LAUNCH_CHECK();
 }
+
 
 #define ETH_INST(T)                                                                               \
   template void launch_mq_kdot<T>(const Geo&, const T*, long long, long long, int, const RedCtx&,  \
@@ -526,8 +538,8 @@ void launch_mq_cheb_fused(const Geo& g, const T* r, const T* zin, T* zout, T* d,
                                           hipStream_t);                                            \
   template void launch_mq_project_out<T>(const Geo&, const T*, double*, long long, int,            \
                                          const double*, double, Gate, hipStream_t);               \
-  template void launch_mq_cheb_fused<T>(const Geo&, const T*, const T*, T*, T*, double, double,    \
-                                        int, int, Gate, hipStream_t, int);
+  template void launch_mq_cheb_fused<T>(const Geo&, T*, const T*, T*, T*, double, double, int, int,  \
+                                        Gate, hipStream_t, int, const MqSource*);
 ETH_INST(double)
 ETH_INST(float)
 #undef ETH_INST
