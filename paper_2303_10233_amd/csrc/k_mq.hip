@@ -268,6 +268,9 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
   __shared__ T rq[RQ * RQ];
   __shared__ T te[RE * RE];
   __shared__ T re[RE * RE];
+  // the pressure solve is the longer of the two concurrent preconditioner
+  // branches: its waves issue first on a SIMD shared with the V-cycle's
+  __builtin_amdgcn_s_setprio(2);
   const int rhs = blockIdx.z;
   const bool off = gate.off(rhs);   // tested after the staging, so its load overlaps them
   const int n = g.n;
