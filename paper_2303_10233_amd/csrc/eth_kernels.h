@@ -103,11 +103,11 @@ void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* 
 template <typename T>
 void launch_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int nplanes,
                         int batch, Gate gate, hipStream_t st);
-// dense coarse solve: x = Ainv * b on the interior nodes of each plane
+// dense coarse solve: x = Ainv * b on the interior nodes of each plane, with
+// the FP32 copy AinvF of the inverse when given; gbuf: 2*ni*batch doubles
 template <typename T>
-// gbuf: 2*ni*batch doubles of scratch, used when ni exceeds the LDS staging limit
-void launch_dense_solve(const Geo& g, const double* Ainv, int ni, const T* b, T* x,
-                        int nplanes, double* out64, long long ld64, double out_scale,
+void launch_dense_solve(const Geo& g, const double* Ainv, const float* AinvF, int ni, const T* b,
+                        T* x, int nplanes, double* out64, long long ld64, double out_scale,
                         const double* in64, long long ldin, double* gbuf, int batch, Gate gate,
                         hipStream_t st);
 // the coarse end of a V-cycle in one launch (levels with at most 65^2 nodes,
@@ -182,6 +182,8 @@ size_t dense_inverse_work(int ni);
 void launch_dense_inverse(double* A, int ni, double* work, hipStream_t st);
 // A = (A + A^T) / 2 in place (the inverse of a symmetric matrix, against rounding)
 void launch_symmetrize(double* A, int ni, hipStream_t st);
+// f = (float)a, n values
+void launch_to_float(const double* a, float* f, long long n, hipStream_t st);
 // damped Jacobi step on F = nu A + N(w) (residual != 0: write b - F x instead;
 // transpose != 0: F^T)
 template <typename T>

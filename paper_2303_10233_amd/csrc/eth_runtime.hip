@@ -159,6 +159,7 @@ struct Problem {
   double* AinvT = nullptr;           // its transpose (Oseen: coarse solve with F^T)
   int coarse_ni = 0;
   double* dense_gbuf = nullptr;
+  float *AinvF = nullptr, *AinvTF = nullptr;   // FP32 copies of the coarse inverses (mixed precision)
   std::vector<void*> vb, vx, vxo;    // per-level plane buffers (T)
   TailLevels tail{};                 // levels handled by the fused coarse V-cycle
   int tail_l0 = -1;                  // its first level (-1: per-level launches)
@@ -530,6 +531,10 @@ void Problem::build_velocity() {
     launch_dense_laplacian(gc, Ainv, ni, st);
     launch_dense_inverse(Ainv, ni, work, st);
     launch_symmetrize(Ainv, ni, st);
+    if (mixed) {
+      AinvF = alloc<float>((size_t)ni * ni);
+      launch_to_float(Ainv, AinvF, (long long)ni * ni, st);
+    }
   }
   const int L = (int)lv.size();
   lam.assign(std::max(L - 1, 0), 0.0);
@@ -721,7 +726,7 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
   const int L = (int)lv.size();
   const double sc = 1.0 / d.nu;
   if (L == 1) {
-    launch_dense_solve<T>(lv[0], Ainv, coarse_ni, nullptr, nullptr, 2 * batch, z, ld, sc, r, ld,
+    launch_dense_solve<T>(lv[0], Ainv, AinvF, coarse_ni, nullptr, nullptr, 2 * batch, z, ld, sc, r, ld,
                           dense_gbuf, batch, gate, st);
     launch_zero_boundary(lv[0], z, ld, batch, st);
     return;
@@ -750,7 +755,7 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
   if (tail_l0 >= 1)
     launch_vcycle_tail<T>(tail, Ainv, coarse_ni, b[lstop], x[lstop], np, gate, st);
   else
-    launch_dense_solve<T>(lv[L - 1], Ainv, coarse_ni, b[L - 1], x[L - 1], np, nullptr, 0, 0.0,
+    launch_dense_solve<T>(lv[L - 1], Ainv, AinvF, coarse_ni, b[L - 1], x[L - 1], np, nullptr, 0, 0.0,
                           nullptr, 0, dense_gbuf, batch, gate, st);
   for (int l = lstop - 1; l >= 0; --l) {
     launch_prolong_add<T>(lv[l], lv[l + 1], x[l + 1], x[l], np, batch, gate, st);
@@ -1281,6 +1286,10 @@ void Problem::build_oseen_velocity() {
   f_work = alloc<double>(dense_inverse_work(coarse_ni));
   Ainv = alloc<double>((size_t)coarse_ni * coarse_ni);
   AinvT = alloc<double>((size_t)coarse_ni * coarse_ni);
+  if (mixed) {
+    AinvF = alloc<float>((size_t)coarse_ni * coarse_ni);
+    AinvTF = alloc<float>((size_t)coarse_ni * coarse_ni);
+  }
   refresh_wind();
   vb.assign(L, nullptr);
   vx.assign(L, nullptr);
@@ -1313,6 +1322,10 @@ void Problem::refresh_wind() {
   launch_dense_convdiff(lv.back(), lwind[L - 1], d.nu, Ainv, ni, st);
   launch_dense_inverse(Ainv, ni, f_work, st);
   launch_transpose(Ainv, ni, AinvT, st);
+  if (AinvF) {
+    launch_to_float(Ainv, AinvF, (long long)ni * ni, st);
+    launch_to_float(AinvT, AinvTF, (long long)ni * ni, st);
+  }
 }
 
 void Problem::build_pcd() {
@@ -1434,7 +1447,8 @@ void Problem::vcycle_F(const double* r, const double* sub, double* z, long long 
                       gate, st, tr);
     launch_restrict<T>(lv[l], lv[l + 1], xo[l], nullptr, b[l + 1], x[l + 1], 0.0, np, batch, gate, st);
   }
-  launch_dense_solve<T>(lv[L - 1], trans ? AinvT : Ainv, coarse_ni, b[L - 1], L == 1 ? nullptr : x[L - 1], np,
+  launch_dense_solve<T>(lv[L - 1], trans ? AinvT : Ainv, trans ? AinvTF : AinvF, coarse_ni, b[L - 1],
+                        L == 1 ? nullptr : x[L - 1], np,
                         L == 1 ? z : nullptr, ld, 1.0, nullptr, 0, dense_gbuf, batch, gate, st);
   if (L == 1) {
     launch_zero_boundary(lv[0], z, ld, batch, st);

@@ -176,7 +176,17 @@ __global__ void k_symmetrize(double* __restrict__ A, int ni) {
   A[o] = v;
 }
 
+__global__ void k_to_float(const double* __restrict__ a, float* __restrict__ f, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = (float)a[i];
+}
+
 }  // namespace
+
+void launch_to_float(const double* a, float* f, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, f, n);
+  ETH_LAUNCH_CHECK();
+}
 
 void launch_symmetrize(double* A, int ni, hipStream_t st) {
   const long long n = (long long)ni * ni;

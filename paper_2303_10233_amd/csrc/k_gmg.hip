@@ -258,61 +258,79 @@ __global__ void k_prolong_add(Geo gf, Geo gc, const T* __restrict__ xc, T* __res
 }
 
 // Dense solve x = Ainv b on the ni interior nodes of the two planes of one
-// RHS.  Input from T planes or (in64) from an FP64 vector; output to T planes
-// or (out64, times out_scale) to an FP64 vector.
-constexpr int DS_ROWS = 16;    // rows per block (4 waves x 4 rows)
-// The gathered right-hand sides (2 ni values) are staged in LDS when they fit
-// (ni <= DS_LDS_MAX); otherwise every row reads them from global memory.
-constexpr int DS_LDS_MAX = 3969;
-template <typename T, bool STAGE>
-__global__ __launch_bounds__(NT) void k_dense_solve(Geo g, const double* __restrict__ Ainv, int ni,
-                                                    const T* __restrict__ b, T* __restrict__ x,
-                                                    double* __restrict__ out64, long long ld64,
-                                                    double out_scale,
-                                                    const double* __restrict__ in64, long long ldin,
-                                                    Gate gate) {
-  extern __shared__ double sb[];   // 2 * ni when STAGE
+// RHS, in two launches: the interior values of both planes are gathered into
+// a contiguous FP64 buffer (from T planes or, in64, from an FP64 vector), then
+// every wave multiplies two rows of Ainv (FP64, or its FP32 copy in mixed
+// precision: the matrix read is the cost) with both gathered planes, eight
+// loads in flight per lane, FP64 sums.  Output to T planes or (out64, times
+// out_scale) to an FP64 vector.
+template <typename T>
+__global__ void k_dense_gather(Geo g, int ni, const T* __restrict__ b, const double* __restrict__ in64,
+                               long long ldin, double* __restrict__ gb, Gate gate) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (gate.off(rhs) || k >= 2 * ni) return;
+  const int nq = g.nq, m = nq - 2;
+  const int comp = k / ni, i = k % ni;
+  const long long node = (long long)(1 + i / m) * nq + (1 + i % m);
+  gb[(long long)rhs * 2 * ni + k] = in64 ? in64[(long long)rhs * ldin + (long long)comp * g.nv + node]
+                                         : (double)b[((long long)rhs * 2 + comp) * g.nv + node];
+}
+
+constexpr int DS_WAVES = 4, DS_RW = 2;   // waves per block, rows per wave
+template <typename T, typename M>
+__global__ __launch_bounds__(64 * DS_WAVES) void k_dense_mv(Geo g, const M* __restrict__ A, int ni,
+                                                            const double* __restrict__ gb,
+                                                            T* __restrict__ x, double* __restrict__ out64,
+                                                            long long ld64, double out_scale, Gate gate) {
   const int rhs = blockIdx.y;
   if (gate.off(rhs)) return;
-  const int nq = g.nq, m = nq - 2;   // interior nodes per side
-  auto load = [&](int k) -> double {
-    const int comp = k / ni, i = k % ni;
-    const int I = 1 + i % m, J = 1 + i / m;
-    const long long node = (long long)J * nq + I;
-    return in64 ? in64[(long long)rhs * ldin + (long long)comp * g.nv + node]
-                : (double)b[((long long)rhs * 2 + comp) * g.nv + node];
-  };
-  if constexpr (STAGE) {
-    for (int k = threadIdx.x; k < 2 * ni; k += NT) sb[k] = load(k);
-    __syncthreads();
-  }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int rr = 0; rr < DS_ROWS / 4; ++rr) {
-    const int row = blockIdx.x * DS_ROWS + wid * (DS_ROWS / 4) + rr;
-    if (row >= ni) break;
-    const double* a = Ainv + (long long)row * ni;
-    double s0 = 0.0, s1 = 0.0;
-    for (int j = lane; j < ni; j += 64) {
-      const double av = a[j];
-      if constexpr (STAGE) {
-        s0 += av * sb[j];
-        s1 += av * sb[ni + j];
-      } else {
-        s0 += av * load(j);
-        s1 += av * load(ni + j);
-      }
-    }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    if (lane == 0) {
-      const int I = 1 + row % m, J = 1 + row / m;
-      const long long node = (long long)J * nq + I;
+  const int row0 = (blockIdx.x * DS_WAVES + wid) * DS_RW;
+  if (row0 >= ni) return;
+  const bool two = row0 + 1 < ni;
+  const M* a0 = A + (long long)row0 * ni;
+  const M* a1 = two ? a0 + ni : a0;
+  const double* u = gb + (long long)rhs * 2 * ni;
+  const double* v = u + ni;
+  double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+  int j = lane;
+  for (; j + 64 < ni; j += 128) {
+    const double p0 = (double)a0[j], p1 = (double)a1[j], q0 = (double)a0[j + 64], q1 = (double)a1[j + 64];
+    const double u0 = u[j], v0 = v[j], u1 = u[j + 64], v1 = v[j + 64];
+    // each lane sums its columns in increasing order (j, j + 64, ...)
+    s00 = fma(p0, u0, s00);
+    s01 = fma(p0, v0, s01);
+    s10 = fma(p1, u0, s10);
+    s11 = fma(p1, v0, s11);
+    s00 = fma(q0, u1, s00);
+    s01 = fma(q0, v1, s01);
+    s10 = fma(q1, u1, s10);
+    s11 = fma(q1, v1, s11);
+  }
+  if (j < ni) {
+    const double p0 = (double)a0[j], p1 = (double)a1[j];
+    s00 = fma(p0, u[j], s00);
+    s01 = fma(p0, v[j], s01);
+    s10 = fma(p1, u[j], s10);
+    s11 = fma(p1, v[j], s11);
+  }
+  s00 = wave_sum(s00);
+  s01 = wave_sum(s01);
+  s10 = wave_sum(s10);
+  s11 = wave_sum(s11);
+  if (lane == 0) {
+    const int nq = g.nq, m = nq - 2;
+    for (int r = 0; r < (two ? 2 : 1); ++r) {
+      const int row = row0 + r;
+      const long long node = (long long)(1 + row / m) * nq + (1 + row % m);
+      const double su = r == 0 ? s00 : s10, sv = r == 0 ? s01 : s11;
       if (out64) {
-        out64[(long long)rhs * ld64 + node] = out_scale * s0;
-        out64[(long long)rhs * ld64 + g.nv + node] = out_scale * s1;
+        out64[(long long)rhs * ld64 + node] = out_scale * su;
+        out64[(long long)rhs * ld64 + g.nv + node] = out_scale * sv;
       } else {
-        x[((long long)rhs * 2) * g.nv + node] = (T)s0;
-        x[((long long)rhs * 2 + 1) * g.nv + node] = (T)s1;
+        x[((long long)rhs * 2) * g.nv + node] = (T)su;
+        x[((long long)rhs * 2 + 1) * g.nv + node] = (T)sv;
       }
     }
   }
@@ -638,19 +656,20 @@ void launch_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int np
 }
 
 template <typename T>
-void launch_dense_solve(const Geo& g, const double* Ainv, int ni, const T* b, T* x, int nplanes,
-                        double* out64, long long ld64, double out_scale, const double* in64,
+void launch_dense_solve(const Geo& g, const double* Ainv, const float* AinvF, int ni, const T* b, T* x,
+                        int nplanes, double* out64, long long ld64, double out_scale, const double* in64,
                         long long ldin, double* gbuf, int batch, Gate gate, hipStream_t st) {
   (void)nplanes;
-  (void)gbuf;
-  dim3 grid((ni + DS_ROWS - 1) / DS_ROWS, batch);
-  if (ni <= DS_LDS_MAX) {
-    hipLaunchKernelGGL((k_dense_solve<T, true>), grid, dim3(NT), sizeof(double) * 2 * ni, st, g,
-                       Ainv, ni, b, x, out64, ld64, out_scale, in64, ldin, gate);
-  } else {
-    hipLaunchKernelGGL((k_dense_solve<T, false>), grid, dim3(NT), 0, st, g, Ainv, ni, b, x, out64,
-                       ld64, out_scale, in64, ldin, gate);
-  }
+  hipLaunchKernelGGL(k_dense_gather<T>, dim3((2 * ni + 255) / 256, batch), dim3(256), 0, st, g, ni, b, in64,
+                     ldin, gbuf, gate);
+  ETH_LAUNCH_CHECK();
+  const dim3 grid((ni + DS_WAVES * DS_RW - 1) / (DS_WAVES * DS_RW), batch);
+  if (AinvF)
+    hipLaunchKernelGGL((k_dense_mv<T, float>), grid, dim3(64 * DS_WAVES), 0, st, g, AinvF, ni, gbuf, x, out64,
+                       ld64, out_scale, gate);
+  else
+    hipLaunchKernelGGL((k_dense_mv<T, double>), grid, dim3(64 * DS_WAVES), 0, st, g, Ainv, ni, gbuf, x, out64,
+                       ld64, out_scale, gate);
   ETH_LAUNCH_CHECK();
   if (!out64) {
     const int nb = 4 * (g.nq - 1);
@@ -702,7 +721,7 @@ void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStre
                                    int, int, Gate, hipStream_t);                                 \
   template void launch_prolong_add<T>(const Geo&, const Geo&, const T*, T*, int, int, Gate,       \
                                       hipStream_t);                                              \
-  template void launch_dense_solve<T>(const Geo&, const double*, int, const T*, T*, int, double*, \
+  template void launch_dense_solve<T>(const Geo&, const double*, const float*, int, const T*, T*, int, double*, \
                                       long long, double, const double*, long long, double*, int,  \
                                       Gate, hipStream_t);                                         \
   template void launch_vcycle_tail<T>(const TailLevels&, const double*, int, const T*, T*, int,    \
