@@ -49,20 +49,19 @@ __global__ __launch_bounds__(NT) void k_gm_mdot(long long N, int nv, const doubl
   }
 }
 
-// the multi-dot totals in block order, one wave per coefficient
-__global__ __launch_bounds__(NT) void k_gm_mdot_finish(int nv, int nb, const double* __restrict__ partials,
+// the multi-dot totals in block order, one single-wave block per coefficient
+// (all coefficients in parallel)
+__global__ __launch_bounds__(64) void k_gm_mdot_finish(int nb, const double* __restrict__ partials,
                                                        GmresScalars* __restrict__ S, int which) {
-  const int rhs = blockIdx.x;
+  const int i = blockIdx.x, rhs = blockIdx.y;
   if (!S[rhs].active) return;
   const double* P = partials + (long long)rhs * 64 * nb;
   double* out = which == 0 ? S[rhs].h1 : S[rhs].h2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < nv; i += NT / 64) {
-    double a = 0.0;
-    for (int b = lane; b < nb; b += 64) a += P[(long long)i * nb + b];
-    a = wave_sum(a);
-    if (lane == 0) out[i] = a;
-  }
+  const int lane = threadIdx.x;
+  double a = 0.0;
+  for (int b = lane; b < nb; b += 64) a += P[(long long)i * nb + b];
+  a = wave_sum(a);
+  if (lane == 0) out[i] = a;
 }
 
 // block partials of ||w||^2; mode 0: RHS whose Arnoldi step runs, mode 1:
@@ -112,44 +111,55 @@ __global__ void k_gm_maxpy(long long N, int nv, const double* __restrict__ V, do
 __global__ __launch_bounds__(NT) void k_gm_givens(int j, int nb, const double* __restrict__ partials,
                                                   GmresScalars* __restrict__ S) {
   __shared__ double sred[NT / 64];
+  __shared__ double hc[66], lcs[64], lsn[64];
   const int rhs = blockIdx.x;
   GmresScalars& G = S[rhs];
   if (!G.active) return;
   const double s = sum_partials(partials + (long long)rhs * 64 * nb, nb, sred);
-  if (threadIdx.x != 0) return;
+  // the new Hessenberg column and the earlier rotations are read in parallel;
+  // the rotation recurrence then runs on LDS values
   const int m1 = G.m + 1;
   double* Hc = G.H + (long long)j * m1;
-  for (int i = 0; i <= j; ++i) Hc[i] = G.h1[i] + G.h2[i];
-  const double hn = sqrt(s);
-  Hc[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t0 = G.cs[i] * Hc[i] + G.sn[i] * Hc[i + 1];
-    Hc[i + 1] = -G.sn[i] * Hc[i] + G.cs[i] * Hc[i + 1];
-    Hc[i] = t0;
+  for (int i = threadIdx.x; i <= j; i += NT) hc[i] = G.h1[i] + G.h2[i];
+  for (int i = threadIdx.x; i < j; i += NT) {
+    lcs[i] = G.cs[i];
+    lsn[i] = G.sn[i];
   }
-  const double r = hypot(Hc[j], Hc[j + 1]);
-  double c = 1.0, sn = 0.0;
-  if (r > 0.0) {
-    c = Hc[j] / r;
-    sn = Hc[j + 1] / r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(s);
+    hc[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t0 = lcs[i] * hc[i] + lsn[i] * hc[i + 1];
+      hc[i + 1] = -lsn[i] * hc[i] + lcs[i] * hc[i + 1];
+      hc[i] = t0;
+    }
+    const double r = hypot(hc[j], hc[j + 1]);
+    double c = 1.0, sn = 0.0;
+    if (r > 0.0) {
+      c = hc[j] / r;
+      sn = hc[j + 1] / r;
+    }
+    G.cs[j] = c;
+    G.sn[j] = sn;
+    hc[j] = r;
+    hc[j + 1] = 0.0;
+    G.g[j + 1] = -sn * G.g[j];
+    G.g[j] = c * G.g[j];
+    G.res = fabs(G.g[j + 1]);
+    G.iters += 1;
+    G.kend = j + 1;
+    if (G.hist && G.iters < G.hist_len) G.hist[G.iters] = G.res;
+    G.inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (!(G.res == G.res) || r == 0.0) {   // NaN or singular Hessenberg column
+      G.status = kStBreakdown;
+      G.active = 0;
+    } else if (G.res <= G.target || hn == 0.0 || j == G.m - 1 || G.iters >= G.maxit) {
+      G.active = 0;
+    }
   }
-  G.cs[j] = c;
-  G.sn[j] = sn;
-  Hc[j] = r;
-  Hc[j + 1] = 0.0;
-  G.g[j + 1] = -sn * G.g[j];
-  G.g[j] = c * G.g[j];
-  G.res = fabs(G.g[j + 1]);
-  G.iters += 1;
-  G.kend = j + 1;
-  if (G.hist && G.iters < G.hist_len) G.hist[G.iters] = G.res;
-  G.inv = hn > 0.0 ? 1.0 / hn : 0.0;
-  if (!(G.res == G.res) || r == 0.0) {   // NaN or singular Hessenberg column
-    G.status = kStBreakdown;
-    G.active = 0;
-  } else if (G.res <= G.target || hn == 0.0 || j == G.m - 1 || G.iters >= G.maxit) {
-    G.active = 0;
-  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += NT) Hc[i] = hc[i];
 }
 
 // V[i] *= inv  (the pending normalisation of the new Arnoldi vector)
@@ -258,7 +268,7 @@ void launch_gm_mdot(long long N, int nv, const double* V, const double* w, long 
   const unsigned nb = blocks(N);
   hipLaunchKernelGGL(k_gm_mdot, dim3(nb, batch), dim3(NT), 0, st, N, nv, V, w, ld, batch, partials, S);
   ETH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gm_mdot_finish, dim3(batch), dim3(NT), 0, st, nv, (int)nb, partials, S, which);
+  hipLaunchKernelGGL(k_gm_mdot_finish, dim3(nv, batch), dim3(64), 0, st, (int)nb, partials, S, which);
   ETH_LAUNCH_CHECK();
 }
 void launch_gm_maxpy(long long N, int nv, const double* V, double* w, long long ld, int batch,
