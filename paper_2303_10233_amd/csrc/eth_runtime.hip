@@ -12,6 +12,8 @@
 #include <string>
 #include <type_traits>
 #include <vector>
+#include <map>
+#include <array>
 
 #include "../../include/eth.h"
 #include "eth_kernels.h"
@@ -228,6 +230,8 @@ struct Problem {
   // internal stream gst, joined to the caller's stream with events
   hipGraphExec_t gexec = nullptr;
   int gexec_batch = -1;
+  // captured Arnoldi chunks of FGMRES: (kind, reduced, transpose, batch, j0, j1) -> graph
+  std::map<std::array<int, 6>, hipGraphExec_t> gm_graphs;
   hipStream_t gst = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // Stokes: the pressure block of the block-diagonal preconditioner runs on
@@ -248,6 +252,7 @@ struct Problem {
 
   ~Problem() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto& kv : gm_graphs) (void)hipGraphExecDestroy(kv.second);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_pf) (void)hipEventDestroy(ev_pf);
@@ -328,8 +333,12 @@ struct Problem {
   Gate gm_gate() const {
     return Gate{&d_gm[0].active, (int)(sizeof(GmresScalars) / sizeof(int))};
   }
+  // Arnoldi steps j0 .. j1-1 of the current FGMRES cycle (kernels only)
+  void arnoldi_steps(int kind, bool reduced, bool transpose, int batch, int j0, int j1);
+  // the same, replayed from a graph captured on first use
+  void arnoldi_steps_graph(int kind, bool reduced, bool transpose, int batch, int j0, int j1);
   void run_fgmres(int kind, bool reduced, const double* b, double* x, int batch, int m, int maxit,
-                  const std::vector<double>& atol, bool transpose = false);
+                  const std::vector<double>& atol, bool transpose = false, bool use_graph = false);
   int solve_oseen(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
                   eth_solve_info* info, bool adjoint = false);
 
@@ -1564,8 +1573,66 @@ void Problem::precond_oseen(int kind, const double* r, double* z, int batch, Gat
 // Restarted FGMRES on the internal vectors b, x (stride ldw); kind selects
 // the preconditioner (1: M_1, 2: PCD), reduced the stage-I operator (the p_0
 // rows of K x are dropped).  atol: absolute tolerance per RHS.
+void Problem::arnoldi_steps(int kind, bool reduced, bool transpose, int batch, int j0, int j1) {
+  const Gate gate = gm_gate();
+  const long long N = g.N;
+  auto V = [&](int i) { return gV + (size_t)i * batch * ldw; };
+  auto Z = [&](int i) { return gZ + (size_t)i * batch * ldw; };
+  for (int j = j0; j < j1; ++j) {
+    precond_oseen(kind, V(j), Z(j), batch, gate);
+    apply_op(transpose ? 1 : 0, Z(j), V(j + 1), ldw, batch, gate, nullptr);
+    if (reduced) launch_gm_zero_range(V(j + 1), ldw, g.off_p0(), g.n0, batch, d_gm, st);
+    launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, d_gm, 0, st);
+    launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 0, st);
+    launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, d_gm, 1, st);
+    launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 1, st);
+    launch_gm_norm_givens(N, j, V(j + 1), ldw, batch, gpart, d_gm, st);
+    launch_gm_scale(N, V(j + 1), ldw, batch, d_gm, st);
+  }
+}
+
+void Problem::arnoldi_steps_graph(int kind, bool reduced, bool transpose, int batch, int j0, int j1) {
+  if (!gst) {
+    ETH_HIP(hipStreamCreateWithFlags(&gst, hipStreamNonBlocking));
+    ETH_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    ETH_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  }
+  hipStream_t caller = st;
+  ETH_HIP(hipEventRecord(ev_fork, caller));
+  ETH_HIP(hipStreamWaitEvent(gst, ev_fork, 0));
+  st = gst;
+  struct Restore {
+    hipStream_t& s;
+    hipStream_t v;
+    ~Restore() { s = v; }
+  } restore{st, caller};
+  const std::array<int, 6> key{kind, reduced ? 1 : 0, transpose ? 1 : 0, batch, j0, j1};
+  auto it = gm_graphs.find(key);
+  if (it == gm_graphs.end()) {
+    hipGraph_t graph;
+    ETH_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      arnoldi_steps(kind, reduced, transpose, batch, j0, j1);
+    } catch (...) {
+      hipGraph_t discard;
+      (void)hipStreamEndCapture(st, &discard);
+      if (discard) (void)hipGraphDestroy(discard);
+      throw;
+    }
+    ETH_HIP(hipStreamEndCapture(st, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    ETH_HIP(e);
+    it = gm_graphs.emplace(key, exec).first;
+  }
+  ETH_HIP(hipGraphLaunch(it->second, gst));
+  ETH_HIP(hipEventRecord(ev_join, gst));
+  ETH_HIP(hipStreamWaitEvent(caller, ev_join, 0));
+}
+
 void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int batch, int m,
-                         int maxit, const std::vector<double>& atol, bool transpose) {
+                         int maxit, const std::vector<double>& atol, bool transpose, bool use_graph) {
   const size_t per = (size_t)(gm_m + 1) * gm_m + 7 * 64;
   for (int r = 0; r < batch; ++r) {
     GmresScalars& G = h_gm[r];
@@ -1598,16 +1665,13 @@ void Problem::run_fgmres(int kind, bool reduced, const double* b, double* x, int
     launch_residual_init(g, b, ky, V(0), ldw, batch, st);
     launch_gm_beta(N, V(0), ldw, batch, gpart, d_gm, st);
     launch_gm_scale(N, V(0), ldw, batch, d_gm, st);
-    for (int j = 0; j < m; ++j) {
-      precond_oseen(kind, V(j), Z(j), batch, gate);
-      op(Z(j), V(j + 1), gate);
-      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, d_gm, 0, st);
-      launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 0, st);
-      launch_gm_mdot(N, j + 1, gV, V(j + 1), ldw, batch, gpart, d_gm, 1, st);
-      launch_gm_maxpy(N, j + 1, gV, V(j + 1), ldw, batch, d_gm, 1, st);
-      launch_gm_norm_givens(N, j, V(j + 1), ldw, batch, gpart, d_gm, st);
-      launch_gm_scale(N, V(j + 1), ldw, batch, d_gm, st);
-      if ((j + 1) % 8 == 0 && j + 1 < m) {
+    // chunks of 8 Arnoldi steps; steps after convergence are gated off on
+    // the device, and the host looks at the flags between chunks
+    for (int j0 = 0; j0 < m; j0 += 8) {
+      const int j1 = std::min(j0 + 8, m);
+      if (use_graph) arnoldi_steps_graph(kind, reduced, transpose, batch, j0, j1);
+      else arnoldi_steps(kind, reduced, transpose, batch, j0, j1);
+      if (j1 < m) {
         ETH_HIP(hipMemcpyAsync(h_gm, d_gm, sizeof(GmresScalars) * batch, hipMemcpyDeviceToHost, st));
         ETH_HIP(hipStreamSynchronize(st));
         bool any = false;
@@ -1664,12 +1728,12 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
     launch_gm_zero_range(kx, ldw, g.off_p0(), g.n0, batch, nullptr, st);
     std::vector<double> a1(batch);
     for (int r = 0; r < batch; ++r) a1[r] = c * eta * bn[r];
-    run_fgmres(adjoint ? 4 : 2, true, kv[0], kx, batch, m, maxit, a1, adjoint);
+    run_fgmres(adjoint ? 4 : 2, true, kv[0], kx, batch, m, maxit, a1, adjoint, o.use_graph != 0);
     for (int r = 0; r < batch; ++r) it1[r] = h_gm[r].iters;
   }
   std::vector<double> a2(batch);
   for (int r = 0; r < batch; ++r) a2[r] = eta * bn[r];
-  run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint);
+  run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint, o.use_graph != 0);
   // output
   launch_copy(g.N, kx, ldw, x, ld, batch, st);
   if (!adjoint) launch_copy_boundary(g, b, x, ld, batch, st);

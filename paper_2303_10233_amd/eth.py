@@ -380,7 +380,7 @@ class Problem:
         return g2.value, th.value, k.value
 
     def solve_adjoint(self, g, rtol=1e-6, maxit=1000, method=None, restart=0, canonicalize=True,
-                      true_residual=False, out=None):
+                      true_residual=False, out=None, use_graph=False):
         """lambda with K^T lambda = g (see eth_solve_adjoint).  method None:
         MINRES for Stokes, TWO_STAGE for Oseen."""
         if method is None:
@@ -389,7 +389,7 @@ class Problem:
         g2, B, ld = _as_batch(g, self.N)
         l2, _, _ = _as_batch(lam, self.N)
         o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=10.0,
-                      canonicalize=int(canonicalize), use_x0=0, use_graph=0,
+                      canonicalize=int(canonicalize), use_x0=0, use_graph=int(use_graph),
                       true_residual=int(true_residual))
         infos = (SolveInfo * B)()
         st = lib().eth_solve_adjoint(self._h, ctypes.byref(o), _ptr(g2), _ptr(l2), B, ld, infos)
@@ -404,7 +404,7 @@ class Problem:
         _check(lib().eth_set_wind(self._h, _ptr(wind)), self._h)
 
     def picard(self, x, steps, f=None, rtol=1e-6, maxit=1000, method=TWO_STAGE, restart=0,
-               c_factor=10.0, canonicalize=True):
+               c_factor=10.0, canonicalize=True, use_graph=False):
         """`steps` Picard steps from the iterate x (updated in place): each sets
         the wind to the velocity of x and solves the Oseen system from x.
         Returns x and one info dict per step."""
@@ -413,7 +413,7 @@ class Problem:
         if f is not None and (f.dtype != torch.float64 or f.numel() < 2 * self.nv):
             raise ValueError("f must be a float64 tensor of 2 nv nodal forces")
         o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=c_factor,
-                      canonicalize=int(canonicalize), use_x0=1, use_graph=0, true_residual=0)
+                      canonicalize=int(canonicalize), use_x0=1, use_graph=int(use_graph), true_residual=0)
         infos = (SolveInfo * max(steps, 1))()
         st = lib().eth_picard(self._h, ctypes.byref(o), steps, None if f is None else _ptr(f), _ptr(x), infos)
         _check(st, self._h)

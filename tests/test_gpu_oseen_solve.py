@@ -190,6 +190,29 @@ def test_two_stage_n64_nu100(prec):
     assert info[0]["iterations"] <= 160
 
 
+@pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
+def test_graph_replayed_fgmres_equals_eager(prec):
+    """FGMRES with its Arnoldi steps replayed from captured graphs (chunks of
+    eight steps) gives bit for bit the eager result: two-stage and M_1-only
+    solves, a batch of two right-hand sides, and the adjoint (transposed)
+    solve; the second solve replays the cached graphs."""
+    n = 32
+    print(f"[fgmres graph] n={n} prec={prec}", flush=True)
+    m, s, P = _setup(n, 0.01, prec=prec, max_batch=2)
+    f = np.stack([gaussian_bumps(n, 1200 + i, -1, 1, -1, 1) for i in range(2)])
+    B = P.assemble_rhs(_t(f), batch=2)
+    for method in (eth.TWO_STAGE, eth.FGMRES):
+        xe, ie = P.solve(B, rtol=1e-8, maxit=600, method=method, restart=20)
+        for rep in range(2):
+            xg, ig = P.solve(B, rtol=1e-8, maxit=600, method=method, restart=20, use_graph=True)
+            assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
+            assert torch.equal(xg, xe), (method, rep)
+    g = _t(uniform_vector(P.N, 77))
+    le, _ = P.solve_adjoint(g, rtol=1e-8, maxit=600)
+    lg, _ = P.solve_adjoint(g, rtol=1e-8, maxit=600, use_graph=True)
+    assert torch.equal(lg, le)
+
+
 def test_two_stage_batched_forcing_and_warm_start():
     n, nu = 32, 0.05
     m, s, P = _setup(n, nu, max_batch=2)
