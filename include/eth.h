@@ -109,7 +109,10 @@ typedef struct {
   int32_t maxit;             /* iteration limit (default 1000)                      */
   int32_t restart;           /* FGMRES restart length (default 50)                  */
   double c_factor;           /* two-stage: stage-I factor c (default 10)           */
-  int32_t canonicalize;      /* 1: subtract the means of p_k and p_0 (default)      */
+  int32_t canonicalize;      /* 1: subtract the means of p_k and p_0 (default); 0:
+                                the pressure is one representative of its class
+                                modulo null(K) (MINRES may leave a multiple of
+                                the frame null vector k in it)                    */
   int32_t use_x0;            /* 1: x holds the initial guess on entry               */
   int32_t use_graph;         /* 1: replay the iteration as a captured hipGraph      */
   int32_t true_residual;     /* 1: compute ||b - K x||/||b|| into info (default 0)   */

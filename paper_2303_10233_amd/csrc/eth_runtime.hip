@@ -300,14 +300,18 @@ struct Problem {
   template <typename T>
   void vcycle(const double* r, double* z, long long ld, int batch, Gate gate);
   template <typename T>
-  void mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
-  void mq_solve(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
+  void mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale,
+               bool project_out = true);
+  void mq_solve(const double* r, double* z, long long ld, int batch, Gate gate, double scale,
+                bool project_out = true);
   void build_schur();
   template <typename T>
   void schur_vcycle(int batch, Gate gate);
   template <typename T>
   void mq_schur(const double* r, double* z, long long ld, int batch, Gate gate, double scale);
-  void precond(const double* r, double* z, long long ld, int batch, Gate gate);
+  // in_krylov: inside MINRES, where the k component of the pressure output
+  // is left in place (see mq_cheb)
+  void precond(const double* r, double* z, long long ld, int batch, Gate gate, bool in_krylov = false);
 
   // ------------------------------------------------------------ Oseen
   void build_oseen_velocity();
@@ -777,8 +781,14 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
   }
 }
 
+// project_out = false leaves out the final projection on k^perp: inside
+// MINRES the output z only enters K z (B^T k = 0) and inner products with
+// vectors whose pressure part is orthogonal to k (the pressure rows of K
+// produce B u, and k^T B = 0), so every MINRES scalar is the same, and the k
+// component that x picks up is removed with the pressure means at the end.
 template <typename T>
-void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale) {
+void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale,
+                      bool project_out) {
   T* rr = static_cast<T*>(mq_r);
   T* zz = static_cast<T*>(mq_z);
   T* tt = static_cast<T*>(mq_t);
@@ -799,9 +809,14 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
     if (d.mq_steps % 2 == 1) std::swap(zb[0], zb[1]);
     const int tile = mq_tile_for(batch);
     const MqSource src{r, ld, mq_coef};
-    for (int k = 0; k < d.mq_steps; ++k)
+    const MqSink sink{z, ld, scale};
+    for (int k = 0; k < d.mq_steps; ++k) {
+      const bool last = k + 1 == d.mq_steps;
       launch_mq_cheb_fused<T>(g, rr, zb[k & 1], zb[(k + 1) & 1], dd, mq_a[k], mq_b[k], k == 0, batch,
-                              gate, st, tile, k == 0 ? &src : nullptr);
+                              gate, st, tile, k == 0 ? &src : nullptr,
+                              last && !project_out ? &sink : nullptr);
+    }
+    if (!project_out) return;   // the last step wrote scale * z to the output
   } else {
     launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);
     static const int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
@@ -815,7 +830,8 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
   launch_mq_project_out<T>(g, zz, z, ld, batch, mq_coef2, scale, gate, st);
 }
 
-void Problem::mq_solve(const double* r, double* z, long long ld, int batch, Gate gate, double scale) {
+void Problem::mq_solve(const double* r, double* z, long long ld, int batch, Gate gate, double scale,
+                       bool project_out) {
   if (d.mq_mode == ETH_MQ_DIAG) {
     const long long np = (long long)g.nk + g.n0;
     RedCtx rc = red(dot_blocks(np), 1, EPI_SCALE, &d_scale[0]);
@@ -825,9 +841,9 @@ void Problem::mq_solve(const double* r, double* z, long long ld, int batch, Gate
     if (mixed) mq_schur<float>(r, z, ld, batch, gate, scale);
     else mq_schur<double>(r, z, ld, batch, gate, scale);
   } else if (mixed) {
-    mq_cheb<float>(r, z, ld, batch, gate, scale);
+    mq_cheb<float>(r, z, ld, batch, gate, scale, project_out);
   } else {
-    mq_cheb<double>(r, z, ld, batch, gate, scale);
+    mq_cheb<double>(r, z, ld, batch, gate, scale, project_out);
   }
 }
 
@@ -958,7 +974,7 @@ void Problem::mq_schur(const double* r, double* z, long long ld, int batch, Gate
   launch_mq_project_out<T>(g, zz, z, ld, batch, mq_coef2, scale, gate, st);
 }
 
-void Problem::precond(const double* r, double* z, long long ld, int batch, Gate gate) {
+void Problem::precond(const double* r, double* z, long long ld, int batch, Gate gate, bool in_krylov) {
   // the two diagonal blocks read disjoint parts of r and write disjoint parts
   // of z, and share no workspace
   if (pst) {
@@ -971,11 +987,11 @@ void Problem::precond(const double* r, double* z, long long ld, int batch, Gate 
         ~Restore() { s = v; }
       } restore{st, st};
       st = pst;
-      mq_solve(r, z, ld, batch, gate, d.nu);
+      mq_solve(r, z, ld, batch, gate, d.nu, !in_krylov);
     }
     ETH_HIP(hipEventRecord(ev_pj, pst));
   } else {
-    mq_solve(r, z, ld, batch, gate, d.nu);
+    mq_solve(r, z, ld, batch, gate, d.nu, !in_krylov);
   }
   if (mixed) vcycle<float>(r, z, ld, batch, gate);
   else vcycle<double>(r, z, ld, batch, gate);
@@ -998,7 +1014,7 @@ void Problem::minres_iteration(int batch, int parity) {
   const ClearFlag clear_wx{&d_ms[0].wx_todo, (int)(sizeof(MinresScalars) / sizeof(int))};
   launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st, clear_wx);
   launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st);   // vp <- v_{j+1}
-  precond(vp, zn, ldw, batch, gate);
+  precond(vp, zn, ldw, batch, gate, true);
   RedCtx rg = red(dot_blocks(g.N), 1, EPI_MINRES_GAMMA, d_ms);
   launch_dot(g.N, zn, vp, ldw, batch, rg, gate, st);
   launch_minres_wx(g.N, z, wp, w, kx, ldw, batch, d_ms, st);   // wp <- w_{j+1}
@@ -1092,7 +1108,7 @@ void Problem::minres_begin(MinresRun& R) {
   have_lanczos = !R.adjoint;
   ETH_HIP(hipMemcpyAsync(d_ms, h_ms, sizeof(MinresScalars) * batch, hipMemcpyHostToDevice, st));
   // z1 = P^{-1} v1, gamma_1
-  precond(kv[0], kz[0], ldw, batch, no_gate());
+  precond(kv[0], kz[0], ldw, batch, no_gate(), true);
   RedCtx ri = red(dot_blocks(g.N), 1, EPI_MINRES_INIT, d_ms);
   launch_dot(g.N, kz[0], kv[0], ldw, batch, ri, no_gate(), st);
   minres_enqueue_chunk(R);

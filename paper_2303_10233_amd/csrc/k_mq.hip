@@ -255,13 +255,14 @@ struct MqTile {
 
 // src (first step only, may be null): take r from the FP64 vectors, projected
 // on k^perp as r - coef k, and store it to the workspace r (owned entries) for
-// the later steps.
+// the later steps.  sink (last step only, may be null): write scale z_{k+1}
+// straight to the pressure part of the FP64 vectors instead of the workspace.
 template <typename T, int TQ>
 __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __restrict__ r,
                                                                   const T* __restrict__ zin,
                                                                   T* __restrict__ zout, T* __restrict__ d,
                                                                   double a, double b, int first, Gate gate,
-                                                                  MqSource src) {
+                                                                  MqSource src, MqSink sink) {
   using Tl = MqTile<TQ>;
   constexpr int RQ = Tl::RQ, RE = Tl::RE, NC = Tl::NC, FT = Tl::FT, OWN = Tl::OWN;
   __shared__ T tq[RQ * RQ];
@@ -278,6 +279,7 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
   T* rr = r + (long long)rhs * np;
   const double* r64 = src.r ? src.r + (long long)rhs * src.ld + g.off_pk() : nullptr;
   const double cf = src.r ? src.coef[rhs] : 0.0;
+  double* o64 = sink.out ? sink.out + (long long)rhs * sink.ld + g.off_pk() : nullptr;
   const T* zi = zin + (long long)rhs * np;
   const int c0 = blockIdx.x * TQ, d0 = blockIdx.y * TQ;
   const int gx = c0 - HALO, gy = d0 - HALO;      // global index of local 0
@@ -419,8 +421,12 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
       const T zq = PF ? z0q[PF ? i : 0] : (first ? T(0) : zi[oq]);
       const T dq = PF ? d0q[PF ? i : 0] : (first ? T(0) : dr[oq]);
       const T zn = cheb_combine<T>(tq[(oy + HALO) * RQ + (ox + HALO)], zq, dq, ta, tb, first, dn);
-      dr[oq] = dn;
-      zo[oq] = zn;
+      if (o64) {
+        o64[oq] = sink.scale * (double)zn;
+      } else {
+        dr[oq] = dn;
+        zo[oq] = zn;
+      }
       if (r64) rr[oq] = rq[(oy + HALO) * RQ + (ox + HALO)];
     }
     if (oc < n && od < n) {
@@ -429,8 +435,12 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
       const T ze = PF ? z0e[PF ? i : 0] : (first ? T(0) : zi[oe]);
       const T de = PF ? d0e[PF ? i : 0] : (first ? T(0) : dr[oe]);
       const T zn = cheb_combine<T>(te[(oy + HALO) * RE + (ox + HALO)], ze, de, ta, tb, first, dn);
-      dr[oe] = dn;
-      zo[oe] = zn;
+      if (o64) {
+        o64[oe] = sink.scale * (double)zn;
+      } else {
+        dr[oe] = dn;
+        zo[oe] = zn;
+      }
       if (r64) rr[oe] = re[(oy + HALO) * RE + (ox + HALO)];
     }
   }
@@ -510,14 +520,16 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
 
 template <typename T>
 void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, T* d, double a, double b,
-                          int first, int batch, Gate gate, hipStream_t st, int tile, const MqSource* src) {
+                          int first, int batch, Gate gate, hipStream_t st, int tile, const MqSource* src,
+                          const MqSink* sink) {
   if (tile == 64 && sizeof(T) != 4) throw std::invalid_argument("M_Q tile 64 needs the FP32 preconditioner");
   const int tq = (tile == 16 || tile == 64) ? tile : 32;
   const MqSource s = src ? *src : MqSource{};
+  const MqSink k = sink ? *sink : MqSink{};
 #define ETH_MQF(TQ)                                                                                    \
   hipLaunchKernelGGL((k_mq_cheb_fused<T, TQ>),                                                        \
                      dim3((g.n + 1 + TQ - 1) / TQ, (g.n + 1 + TQ - 1) / TQ, batch),                   \
-                     dim3(MqTile<TQ>::FT), 0, st, g, r, zin, zout, d, a, b, first, gate, s)
+                     dim3(MqTile<TQ>::FT), 0, st, g, r, zin, zout, d, a, b, first, gate, s, k)
   if (tq == 16) {
     ETH_MQF(16);
   } else if (tq == 64) {
@@ -542,7 +554,7 @@ void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, T* d, doubl
   template void launch_mq_project_out<T>(const Geo&, const T*, double*, long long, int,            \
                                          const double*, double, Gate, hipStream_t);               \
   template void launch_mq_cheb_fused<T>(const Geo&, T*, const T*, T*, T*, double, double, int, int,  \
-                                        Gate, hipStream_t, int, const MqSource*);
+                                        Gate, hipStream_t, int, const MqSource*, const MqSink*);
 ETH_INST(double)
 ETH_INST(float)
 #undef ETH_INST
