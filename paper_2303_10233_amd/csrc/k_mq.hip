@@ -237,21 +237,47 @@ __global__ void k_mq_project_out(Geo g, const T* __restrict__ z, double* __restr
 constexpr int HALO = 10;
 static_assert(HALO % 2 == 0, "parity of local and global indices must agree");
 
+// LDS layout: the staged nodes (and elements) are split into four arrays by
+// the parity of their local (x, y) index, each row-major with QW = RQ / 2
+// entries per row.  A colour pass then reads and writes consecutive entries
+// of each array from consecutive lanes (no bank conflicts, where a row-major
+// layout has every lane of a pass on even or on odd banks), and the offsets
+// of the nine neighbours and four elements of a node are constants of the
+// colour.  The arrays start QS apart, QS = 16 (mod 32), so that lanes that
+// alternate between two of them (the element pass) hit different banks.
 template <int TQ>
 struct MqTile {
-  static constexpr int RQ = TQ + 2 * HALO;        // staged Q1 nodes per side
+  static constexpr int RQ = TQ + 2 * HALO;        // staged Q1 nodes per side (even)
   static constexpr int RE = RQ - 1;               // staged elements per side
-  static constexpr int NC = (RQ - 1) / 2;         // colour nodes per side and pass
-  // threads: one per colour node of a pass where that fits a block
-  static constexpr int FT = TQ >= 32 ? 1024 : 64 * ((NC * NC + 63) / 64);
+  static constexpr int QW = RQ / 2;               // entries per row of a parity array
+  static constexpr int QS = QW * QW + (48 - (QW * QW) % 32) % 32;   // array stride
+  static constexpr int NC = QW - 1;               // colour nodes per side and pass
+  // threads: one per entry of a parity array where that fits a block (so a
+  // colour pass and each quarter of the element pass take one round)
+  static constexpr int FT = TQ >= 32 ? 1024 : 64 * ((QW * QW + 63) / 64);
   static constexpr int OWN = (TQ * TQ + FT - 1) / FT;   // owned nodes per thread
   // right-hand sides of the thread's nodes kept in registers across passes
   // and z_k, d of its owned nodes fetched before the sweep (TQ = 64 reads
-  // them when needed: two nodes per colour, seven elements and four owned
+  // them when needed: two nodes per colour, eight elements and four owned
   // nodes per thread would exceed the register budget of 1024 threads)
   static constexpr bool CACHE_R = TQ <= 32;
   static_assert(TQ % 2 == 0, "parity of local and global indices must agree");
+  static_assert(QS % 32 == 16, "parity arrays must start on opposite bank halves");
 };
+
+// index in the parity arrays of local node (or element) (x, y)
+template <int QW, int QS>
+__device__ __forceinline__ int par_idx(int x, int y) {
+  return ((x & 1) + 2 * (y & 1)) * QS + (x >> 1) + (y >> 1) * QW;
+}
+// floor(v / 2) for v in {-1, 0, 1, 2}
+__host__ __device__ constexpr int fl2(int v) { return v < 0 ? -1 : v / 2; }
+// offset from the base hx + hy*QW of a node of parity (px, py) to the node
+// (or element) whose local index differs by (dx, dy)
+template <int QW, int QS>
+__host__ __device__ constexpr int par_off(int px, int py, int dx, int dy) {
+  return QS * (((px + dx) & 1) + 2 * ((py + dy) & 1)) + fl2(px + dx) + QW * fl2(py + dy);
+}
 
 // src (first step only, may be null): take r from the FP64 vectors, projected
 // on k^perp as r - coef k, and store it to the workspace r (owned entries) for
@@ -264,11 +290,12 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
                                                                   double a, double b, int first, Gate gate,
                                                                   MqSource src, MqSink sink) {
   using Tl = MqTile<TQ>;
-  constexpr int RQ = Tl::RQ, RE = Tl::RE, NC = Tl::NC, FT = Tl::FT, OWN = Tl::OWN;
-  __shared__ T tq[RQ * RQ];
-  __shared__ T rq[RQ * RQ];
-  __shared__ T te[RE * RE];
-  __shared__ T re[RE * RE];
+  constexpr int RQ = Tl::RQ, RE = Tl::RE, QW = Tl::QW, QS = Tl::QS, NC = Tl::NC, FT = Tl::FT,
+                OWN = Tl::OWN;
+  __shared__ T tq[4 * QS];
+  __shared__ T rq[4 * QS];
+  __shared__ T te[4 * QS];
+  __shared__ T re[4 * QS];
   // the pressure solve is the longer of the two concurrent preconditioner
   // branches: its waves issue first on a SIMD shared with the V-cycle's
   __builtin_amdgcn_s_setprio(2);
@@ -313,97 +340,163 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
       }
     }
   }
+  // staging: every global load of the region before the first LDS store (in
+  // two rounds, nodes then elements, for FP64 tiles of 1024 threads, whose
+  // registers would not hold both)
   // (the projection is the expression of k_mq_project_in, so both paths agree bit for bit)
-  stage2<FT, RQ * RQ>(tq, rq, tid, [&](int k, T& tv, T& rv) {
-    const int c = gx + k % RQ, dd = gy + k / RQ;
-    if (c >= 0 && c <= n && dd >= 0 && dd <= n) {
-      const long long q = (long long)dd * (n + 1) + c;
-      rv = r64 ? (T)(r64[q] - cf * 1.0) : rr[q];
-      if (!first) tv = zi[q];
+  auto stage_elements = [&]() {
+    constexpr int IE = (RE * RE + FT - 1) / FT;
+    T tw[IE], rw[IE];
+#pragma unroll
+    for (int i = 0; i < IE; ++i) {
+      const int k = tid + i * FT;
+      tw[i] = rw[i] = T(0);
+      const int e = gx + k % RE, f = gy + k / RE;
+      if (k < RE * RE && e >= 0 && e < n && f >= 0 && f < n) {
+        const long long q = g.nk + (long long)f * n + e;
+        rw[i] = r64 ? (T)(r64[q] - cf * -1.0) : rr[q];
+        if (!first) tw[i] = zi[q];
+      }
     }
-  });
-  stage2<FT, RE * RE>(te, re, tid, [&](int k, T& tv, T& rv) {
-    const int e = gx + k % RE, f = gy + k / RE;
-    if (e >= 0 && e < n && f >= 0 && f < n) {
-      const long long q = g.nk + (long long)f * n + e;
-      rv = r64 ? (T)(r64[q] - cf * -1.0) : rr[q];
-      if (!first) tv = zi[q];
+    return [&, tw, rw]() {
+#pragma unroll
+      for (int i = 0; i < IE; ++i) {
+        const int k = tid + i * FT;
+        if (k < RE * RE) {
+          const int li = par_idx<QW, QS>(k % RE, k / RE);
+          te[li] = tw[i];
+          re[li] = rw[i];
+        }
+      }
+    };
+  };
+  constexpr bool TWO_ROUNDS = sizeof(T) == 8 && TQ >= 32;
+  {
+    constexpr int IQ = (RQ * RQ + FT - 1) / FT;
+    T tv[IQ], rv[IQ];
+#pragma unroll
+    for (int i = 0; i < IQ; ++i) {
+      const int k = tid + i * FT;
+      tv[i] = rv[i] = T(0);
+      const int c = gx + k % RQ, dd = gy + k / RQ;
+      if (k < RQ * RQ && c >= 0 && c <= n && dd >= 0 && dd <= n) {
+        const long long q = (long long)dd * (n + 1) + c;
+        rv[i] = r64 ? (T)(r64[q] - cf * 1.0) : rr[q];
+        if (!first) tv[i] = zi[q];
+      }
     }
-  });
+    if constexpr (!TWO_ROUNDS) {
+      auto store_elements = stage_elements();
+#pragma unroll
+      for (int i = 0; i < IQ; ++i) {
+        const int k = tid + i * FT;
+        if (k < RQ * RQ) {
+          const int li = par_idx<QW, QS>(k % RQ, k / RQ);
+          tq[li] = tv[i];
+          rq[li] = rv[i];
+        }
+      }
+      store_elements();
+    } else {
+#pragma unroll
+      for (int i = 0; i < IQ; ++i) {
+        const int k = tid + i * FT;
+        if (k < RQ * RQ) {
+          const int li = par_idx<QW, QS>(k % RQ, k / RQ);
+          tq[li] = tv[i];
+          rq[li] = rv[i];
+        }
+      }
+    }
+  }
+  if constexpr (TWO_ROUNDS) stage_elements()();
   if (off) return;   // uniform per block
   // A thread updates the same node of a colour (and the same elements) in
-  // every pass: their LDS indices, boundary flags and right-hand sides are
-  // set up once here, so that a pass is only the stencil loads, the update
-  // and the barrier.
+  // every pass: the base index hx + hy*QW of each, its boundary flags and its
+  // right-hand side are set up once here, so that a pass is only the stencil
+  // loads, the update and the barrier.
   constexpr int CPT = (NC * NC + FT - 1) / FT;   // nodes per thread and colour
-  constexpr int EPT = (RE * RE + FT - 1) / FT;   // elements per thread
-  // qi: LDS index of the node (-1: none); qf: boundary flags Lx | Rx << 1 |
-  // Ly << 2 | Ry << 3 and the local row ly << 4 (the lower-left element of
-  // the node is at qi - RQ - ly in the element array)
-  int qi[4][CPT], qf[4][CPT];
+  constexpr int EPQ = (QW * QW + FT - 1) / FT;   // elements per thread and parity array
+  static_assert(4 * EPQ <= 32, "element validity bits");
+  // qb: base | Lx << 16 | Rx << 17 | Ly << 18 | Ry << 19 (-1: none)
+  int qb[4][CPT];
 #pragma unroll
   for (int colour = 0; colour < 4; ++colour)
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
+      const int px = colour & 1, py = colour >> 1;
       const int idx = tid + j * FT;
-      const int lx = ((colour & 1) == 0 ? 2 : 1) + 2 * (idx % NC);
-      const int ly = ((colour >> 1) == 0 ? 2 : 1) + 2 * (idx / NC);
-      const int c = gx + lx, dd = gy + ly;
-      const bool ok = idx < NC * NC && lx <= RQ - 2 && ly <= RQ - 2 && c >= 0 && c <= n && dd >= 0 && dd <= n;
-      qi[colour][j] = ok ? ly * RQ + lx : -1;
-      qf[colour][j] = (c > 0) | ((c < n) << 1) | ((dd > 0) << 2) | ((dd < n) << 3) | (ly << 4);
+      const int hx = idx % NC + 1 - px, hy = idx / NC + 1 - py;
+      const int c = gx + 2 * hx + px, dd = gy + 2 * hy + py;
+      const bool ok = idx < NC * NC && c >= 0 && c <= n && dd >= 0 && dd <= n;
+      qb[colour][j] = ok ? (hx + hy * QW) | ((c > 0) << 16) | ((c < n) << 17) | ((dd > 0) << 18) |
+                               ((dd < n) << 19)
+                         : -1;
     }
-  // ek: element index k | local row << 16 (-1: none); its lower-left node is
-  // at k + row in the node array
-  static_assert(RE * RE < (1 << 16), "element index must fit 16 bits");
-  int ek[EPT];
+  // element of parity array p (qx = p & 1, qy = p >> 1), entry j = tid + i*FT
+  unsigned emask = 0;
 #pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int k = tid + j * FT, lx = k % RE, ly = k / RE;
-    const int e = gx + lx, f = gy + ly;
-    const bool ok = k < RE * RE && e >= 0 && e < n && f >= 0 && f < n;
-    ek[j] = ok ? (k | (ly << 16)) : -1;
-  }
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int i = 0; i < EPQ; ++i) {
+      const int qx = p & 1, qy = p >> 1;
+      const int jj = tid + i * FT, hx = jj % QW, hy = jj / QW;
+      const int e = gx + 2 * hx + qx, f = gy + 2 * hy + qy;
+      const bool ok = jj < QW * QW && hx < QW - qx && hy < QW - qy && e >= 0 && e < n && f >= 0 && f < n;
+      emask |= (ok ? 1u : 0u) << (p * EPQ + i);
+    }
   __syncthreads();
   constexpr bool CR = Tl::CACHE_R;
-  T qr[4][CR ? CPT : 1], er[CR ? EPT : 1];
+  T qr[4][CR ? CPT : 1], er[4][CR ? EPQ : 1];
   if constexpr (CR) {
 #pragma unroll
     for (int colour = 0; colour < 4; ++colour)
 #pragma unroll
-      for (int j = 0; j < CPT; ++j) qr[colour][j] = qi[colour][j] >= 0 ? rq[qi[colour][j]] : T(0);
+      for (int j = 0; j < CPT; ++j)
+        qr[colour][j] = qb[colour][j] >= 0 ? rq[colour * QS + (qb[colour][j] & 0xffff)] : T(0);
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) er[j] = ek[j] >= 0 ? re[ek[j] & 0xffff] : T(0);
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int i = 0; i < EPQ; ++i)
+        er[p][i] = (emask >> (p * EPQ + i)) & 1u ? re[p * QS + tid + i * FT] : T(0);
   }
   constexpr int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
 #pragma unroll
   for (int pass = 0; pass < 9; ++pass) {
     const int colour = order[pass];
     if (colour < 4) {
+      const int px = colour & 1, py = colour >> 1;
 #pragma unroll
       for (int j = 0; j < CPT; ++j) {
-        const int li = qi[colour][j];
-        if (li < 0) continue;
-        const int fl = qf[colour][j], eb = li - RQ - (fl >> 4);
+        const int v = qb[colour][j];
+        if (v < 0) continue;
+        const int base = v & 0xffff;
         T q9[9], e4[4];
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-          for (int aa = 0; aa < 3; ++aa) q9[bb * 3 + aa] = tq[li + (bb - 1) * RQ + (aa - 1)];
+          for (int aa = 0; aa < 3; ++aa) q9[bb * 3 + aa] = tq[base + par_off<QW, QS>(px, py, aa - 1, bb - 1)];
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-          for (int aa = 0; aa < 2; ++aa) e4[bb * 2 + aa] = te[eb + bb * RE + aa];
-        tq[li] = q1_gs_update<T>(q9[4], CR ? qr[colour][CR ? j : 0] : rq[li], q9, e4, fl & 1, (fl >> 1) & 1, (fl >> 2) & 1,
-                                 (fl >> 3) & 1, h2_36, h2_4, inv_h2_9);
+          for (int aa = 0; aa < 2; ++aa) e4[bb * 2 + aa] = te[base + par_off<QW, QS>(px, py, aa - 1, bb - 1)];
+        const int li = base + par_off<QW, QS>(px, py, 0, 0);
+        tq[li] = q1_gs_update<T>(q9[4], CR ? qr[colour][CR ? j : 0] : rq[li], q9, e4, (v >> 16) & 1,
+                                 (v >> 17) & 1, (v >> 18) & 1, (v >> 19) & 1, h2_36, h2_4, inv_h2_9);
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const int v = ek[j];
-        if (v < 0) continue;
-        const int k = v & 0xffff, q = k + (v >> 16);
-        te[k] = p0_gs_update<T>(CR ? er[CR ? j : 0] : re[k], tq[q], tq[q + 1], tq[q + RQ], tq[q + RQ + 1], inv_h2);
+      for (int p = 0; p < 4; ++p) {
+        const int qx = p & 1, qy = p >> 1;
+#pragma unroll
+        for (int i = 0; i < EPQ; ++i) {
+          if (!((emask >> (p * EPQ + i)) & 1u)) continue;
+          const int base = tid + i * FT, k = p * QS + base;
+          te[k] = p0_gs_update<T>(CR ? er[p][CR ? i : 0] : re[k], tq[base + par_off<QW, QS>(qx, qy, 0, 0)],
+                                  tq[base + par_off<QW, QS>(qx, qy, 1, 0)],
+                                  tq[base + par_off<QW, QS>(qx, qy, 0, 1)],
+                                  tq[base + par_off<QW, QS>(qx, qy, 1, 1)], inv_h2);
+        }
       }
     }
     __syncthreads();
@@ -415,33 +508,34 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
     const int idx = tid + i * FT, ox = idx % TQ, oy = idx / TQ;
     if (idx >= TQ * TQ) break;
     const int oc = c0 + ox, od = d0 + oy;
+    const int lo = par_idx<QW, QS>(ox + HALO, oy + HALO);
     if (oc <= n && od <= n) {
       const long long oq = (long long)od * (n + 1) + oc;
       T dn;
       const T zq = PF ? z0q[PF ? i : 0] : (first ? T(0) : zi[oq]);
       const T dq = PF ? d0q[PF ? i : 0] : (first ? T(0) : dr[oq]);
-      const T zn = cheb_combine<T>(tq[(oy + HALO) * RQ + (ox + HALO)], zq, dq, ta, tb, first, dn);
+      const T zn = cheb_combine<T>(tq[lo], zq, dq, ta, tb, first, dn);
       if (o64) {
         o64[oq] = sink.scale * (double)zn;
       } else {
         dr[oq] = dn;
         zo[oq] = zn;
       }
-      if (r64) rr[oq] = rq[(oy + HALO) * RQ + (ox + HALO)];
+      if (r64) rr[oq] = rq[lo];
     }
     if (oc < n && od < n) {
       const long long oe = g.nk + (long long)od * n + oc;
       T dn;
       const T ze = PF ? z0e[PF ? i : 0] : (first ? T(0) : zi[oe]);
       const T de = PF ? d0e[PF ? i : 0] : (first ? T(0) : dr[oe]);
-      const T zn = cheb_combine<T>(te[(oy + HALO) * RE + (ox + HALO)], ze, de, ta, tb, first, dn);
+      const T zn = cheb_combine<T>(te[lo], ze, de, ta, tb, first, dn);
       if (o64) {
         o64[oe] = sink.scale * (double)zn;
       } else {
         dr[oe] = dn;
         zo[oe] = zn;
       }
-      if (r64) rr[oe] = re[(oy + HALO) * RE + (ox + HALO)];
+      if (r64) rr[oe] = re[lo];
     }
   }
 }
