@@ -391,7 +391,8 @@ def main():
     # kernel + 2 post-step kernels on the finest level; 20 fused Chebyshev-SGS
     # steps; 1 saddle apply, 1 dot, 1 v update, 1 w/x update.
     per_iter = {eth.K_SADDLE_APPLY: 1, eth.K_CHEB_STEP: 3, eth.K_RESTRICT: 1, eth.K_PROLONG: 1,
-                eth.K_MQ_CHEB_STEP: 20, eth.K_DOT: 1, eth.K_MINRES_V: 1, eth.K_MINRES_WX: 1,
+                eth.K_MQ_CHEB_STEP: 20 // Pm.mq_variant()[1], eth.K_DOT: 1, eth.K_MINRES_V: 1,
+                eth.K_MINRES_WX: 1,
                 eth.K_COPY: 0}   # the plain copy calibrates the byte counters of a profiler run
     kernels = {}
     for k, cnt in per_iter.items():
@@ -491,6 +492,8 @@ def main():
             "unknowns": 2 * (2 * n + 1) ** 2 + (n + 1) ** 2 + n * n,
             "hip_graph": use_graph,
             "mq_tile": {"mixed": problems["mixed"].mq_tile()[0], "fp64": problems["fp64"].mq_tile()[0]},
+            "mq_steps_per_launch": {"mixed": problems["mixed"].mq_variant()[1],
+                                    "fp64": problems["fp64"].mq_variant()[1]},
         },
         "iterations": its_m,
         "true_rel_residual": mixed["true_residual"],

@@ -100,6 +100,9 @@ typedef struct {
   int32_t mq_tile;           /* ETH_MQ_CHEB_SGS: Q1 nodes per side of the blocks of
                                 the fused Chebyshev step, 16, 32 or 64 (64 with
                                 ETH_MIXED only); 0: the fastest, timed at setup  */
+  int32_t mq_fuse_steps;     /* Chebyshev steps per launch, 1 or 2 (2 needs tile
+                                16 and ETH_MIXED); 0: 1 when mq_tile is given,
+                                else timed at setup                             */
 } eth_problem_desc;
 
 typedef struct {
@@ -189,10 +192,12 @@ int eth_apply_pcd(eth_problem* p, int transpose, const double* r, double* z, int
  * lambda_max(D^{-1} A_l) per smoothing level (levels-1 values); either pointer
  * may be NULL.  ETH_EUNSUPPORTED when the problem has none. */
 int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas);
-/* Tile sides of the fused Chebyshev step of ETH_MQ_CHEB_SGS in use for one
- * right-hand side (tile_1) and for max_batch of them (tile_max); either
- * pointer may be NULL.  ETH_EUNSUPPORTED for other mq_mode values. */
-int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max);
+/* Variant of the fused Chebyshev step of ETH_MQ_CHEB_SGS in use for one
+ * right-hand side (tile side tile_1, Chebyshev steps per launch steps_1) and
+ * for max_batch of them (tile_max, steps_max); any pointer may be NULL.
+ * ETH_EUNSUPPORTED for other mq_mode values. */
+int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max, int32_t* steps_1,
+                    int32_t* steps_max);
 
 /* Replace the nodal Q2 wind of an Oseen problem (device, 2(2n+1)^2
  * [w_x|w_y], the w_h of eq:generic-conv-diff) and rebuild what depends on it:

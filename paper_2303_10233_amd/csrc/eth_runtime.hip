@@ -167,7 +167,7 @@ struct Problem {
   int tail_l0 = -1;                  // its first level (-1: per-level launches)
 
   // pressure preconditioner
-  void *mq_r = nullptr, *mq_z = nullptr, *mq_t = nullptr, *mq_d = nullptr;
+  void *mq_r = nullptr, *mq_z = nullptr, *mq_t = nullptr, *mq_d = nullptr, *mq_d2 = nullptr;
   double* mq_coef = nullptr;         // batch
   double* mq_coef2 = nullptr;        // batch
   double kDk = 0.0, kk = 0.0;
@@ -183,11 +183,18 @@ struct Problem {
   bool fused_mq = true;              // one launch per Chebyshev step (ETH_DEBUG_UNFUSED_MQ=1: per colour)
   // tile side of the fused Chebyshev step, chosen at set-up for batch 1
   // (lo) and for max_batch (hi)
-  int mq_tile_lo = 32, mq_tile_hi = 32;
-  int mq_tile_for(int batch) const {
-    return (long long)batch * batch > max_batch ? mq_tile_hi : mq_tile_lo;
+  // variant of the fused Chebyshev step: tile side and steps per launch
+  struct MqVariant {
+    int tile = 32, steps = 1;
+  };
+  MqVariant mq_var_lo, mq_var_hi;
+  MqVariant mq_variant_for(int batch) const {
+    return (long long)batch * batch > max_batch ? mq_var_hi : mq_var_lo;
   }
-  int tune_mq_tile(int batch);
+  MqVariant tune_mq_variant(int batch);
+  template <typename T>
+  void mq_chain(const MqVariant& v, T* rr, T* zz, T* tt, const double* r, long long ld, double* z,
+                double scale, bool sink_out, int batch, Gate gate);
   ScaleState* d_scale = nullptr;     // [4] scale epilogue states
 
   // Krylov workspace
@@ -407,6 +414,9 @@ void Problem::setup(const eth_problem_desc& desc) {
     throw std::invalid_argument("mq_tile must be 0, 16, 32 or 64");
   if (d.mq_tile == 64 && d.precision != ETH_MIXED)
     throw std::invalid_argument("mq_tile 64 needs the FP32 preconditioner");
+  if (d.mq_fuse_steps < 0 || d.mq_fuse_steps > 2) throw std::invalid_argument("mq_fuse_steps must be 0, 1 or 2");
+  if (d.mq_fuse_steps == 2 && ((d.mq_tile != 0 && d.mq_tile != 16) || d.precision != ETH_MIXED))
+    throw std::invalid_argument("two Chebyshev steps per launch need mq_tile 16 and ETH_MIXED");
   if (d.gmg_degree <= 0) d.gmg_degree = 2;
   if (d.gmg_lo_frac <= 0.0) d.gmg_lo_frac = 0.3;
   if (d.gmg_hi_frac <= 0.0) d.gmg_hi_frac = 1.1;
@@ -653,6 +663,7 @@ void Problem::build_pressure() {
     mq_z = alloc<char>(n * es);
     mq_t = alloc<char>(n * es);
     mq_d = alloc<char>(n * es);
+    mq_d2 = alloc<char>(n * es);
     // Chebyshev semi-iteration: step k uses a_k d_{k-1} + b_k s_k
     const double lo = d.mq_cheb_lo, hi = d.mq_cheb_hi;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
@@ -667,24 +678,28 @@ void Problem::build_pressure() {
       rho = rn;
     }
     if (d.mq_tile != 0) {
-      mq_tile_lo = mq_tile_hi = d.mq_tile;
+      mq_var_lo.tile = mq_var_hi.tile = d.mq_tile;
+      mq_var_lo.steps = mq_var_hi.steps = d.mq_fuse_steps > 0 ? d.mq_fuse_steps : 1;
     } else {
-      mq_tile_lo = tune_mq_tile(1);
-      mq_tile_hi = max_batch > 1 ? tune_mq_tile(max_batch) : mq_tile_lo;
+      mq_var_lo = tune_mq_variant(1);
+      mq_var_hi = max_batch > 1 ? tune_mq_variant(max_batch) : mq_var_lo;
     }
   }
 }
 
-// The fastest tile side of the fused Chebyshev step for `batch` right-hand
-// sides on this mesh: each candidate is timed with events over a few launches
-// on the (zeroed) workspace.  Small meshes favour small tiles (more blocks in
-// flight), large meshes large ones (less halo recomputation).
-int Problem::tune_mq_tile(int batch) {
+// The fastest variant of the fused Chebyshev step (tile side, one or two
+// steps per launch) for `batch` right-hand sides on this mesh: each candidate
+// is timed with events over a few launches on the (zeroed) workspace, per
+// Chebyshev step.  Small meshes favour small tiles (more blocks in flight),
+// large meshes large ones (less halo recomputation); two steps per launch
+// trade a wider halo for half the launches.
+Problem::MqVariant Problem::tune_mq_variant(int batch) {
   const size_t bytes = (size_t)max_batch * (g.nk + g.n0) * (mixed ? sizeof(float) : sizeof(double));
   ETH_HIP(hipMemsetAsync(mq_r, 0, bytes, st));
   ETH_HIP(hipMemsetAsync(mq_z, 0, bytes, st));
   ETH_HIP(hipMemsetAsync(mq_t, 0, bytes, st));
   ETH_HIP(hipMemsetAsync(mq_d, 0, bytes, st));
+  ETH_HIP(hipMemsetAsync(mq_d2, 0, bytes, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ETH_HIP(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -694,21 +709,29 @@ int Problem::tune_mq_tile(int batch) {
   // candidates are timed in interleaved rounds after a common warm-up, and
   // each keeps its fastest round, so that a clock ramp at set-up does not
   // favour the later ones
-  std::vector<int> cands = {16, 32};
-  if (mixed) cands.push_back(64);
+  std::vector<MqVariant> cands;
+  const int fs = d.mq_fuse_steps;
+  for (int t : {16, 32, 64}) {
+    if (t == 64 && !mixed) continue;
+    if (fs != 2) cands.push_back(MqVariant{t, 1});
+    if (t == 16 && fs != 1 && d.mq_steps >= 2 && mixed) cands.push_back(MqVariant{t, 2});
+  }
+  if (cands.empty()) cands.push_back(MqVariant{16, 1});
   std::vector<float> best_ms(cands.size(), 0.0f);
-  int best = 32;
+  MqVariant best = cands[0];
   try {
-    auto launch = [&](int t) {
+    auto launch = [&](const MqVariant& v) {
       if (mixed)
-        launch_mq_cheb_fused<float>(g, (float*)mq_r, (float*)mq_z, (float*)mq_t, (float*)mq_d, 0.5, 0.1,
-                                    0, batch, no_gate(), st, t);
+        launch_mq_cheb_fused<float>(g, (float*)mq_r, (float*)mq_z, (float*)mq_t, (float*)mq_d,
+                                    v.steps == 2 ? (float*)mq_d2 : (float*)mq_d, 0.5, 0.1, 0.5, 0.1,
+                                    v.steps, 0, batch, no_gate(), st, v.tile);
       else
         launch_mq_cheb_fused<double>(g, (double*)mq_r, (double*)mq_z, (double*)mq_t, (double*)mq_d,
-                                     0.5, 0.1, 0, batch, no_gate(), st, t);
+                                     v.steps == 2 ? (double*)mq_d2 : (double*)mq_d, 0.5, 0.1, 0.5, 0.1,
+                                     v.steps, 0, batch, no_gate(), st, v.tile);
     };
-    for (int t : cands)
-      for (int i = 0; i < 20; ++i) launch(t);
+    for (const auto& v : cands)
+      for (int i = 0; i < 20; ++i) launch(v);
     for (int round = 0; round < 3; ++round)
       for (size_t c = 0; c < cands.size(); ++c) {
         ETH_HIP(hipEventRecord(e0, st));
@@ -717,6 +740,7 @@ int Problem::tune_mq_tile(int batch) {
         ETH_HIP(hipEventSynchronize(e1));
         float ms = 0.0f;
         ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms /= (float)cands[c].steps;
         if (round == 0 || ms < best_ms[c]) best_ms[c] = ms;
       }
     size_t bi = 0;
@@ -731,6 +755,43 @@ int Problem::tune_mq_tile(int batch) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return best;
+}
+
+// The Chebyshev steps of the pressure-mass solve with the fused kernel: z
+// ping-pongs between zz and tt (the result ends in zz), and d between mq_d and
+// mq_d2 across two-step launches (which read d over their whole region).  The
+// first launch takes r from the FP64 vectors with the input projection; with
+// sink_out the last one writes scale * z to the FP64 vectors instead of zz.
+template <typename T>
+void Problem::mq_chain(const MqVariant& v, T* rr, T* zz, T* tt, const double* r, long long ld, double* z,
+                       double scale, bool sink_out, int batch, Gate gate) {
+  const int m = d.mq_steps;
+  std::vector<int> per;   // Chebyshev steps of each launch
+  for (int k = 0; k < m;) {
+    const int s = (v.steps == 2 && k + 1 < m) ? 2 : 1;
+    per.push_back(s);
+    k += s;
+  }
+  const int nl = (int)per.size();
+  T* zb[2] = {zz, tt};
+  T* db[2] = {static_cast<T*>(mq_d), static_cast<T*>(mq_d2)};
+  int zc = nl & 1, dc = 0;   // launch i reads zb[zc], writes zb[zc ^ 1]; zb[nl parity] ends in zz
+  const MqSource src{r, ld, mq_coef};
+  const MqSink sink{z, ld, scale};
+  int k = 0;
+  for (int i = 0; i < nl; ++i) {
+    const bool last = i + 1 == nl;
+    const int s = per[i];
+    T* din = db[dc];
+    T* dout = s == 2 ? db[dc ^ 1] : db[dc];
+    launch_mq_cheb_fused<T>(g, rr, zb[zc], zb[zc ^ 1], din, dout, mq_a[k], mq_b[k],
+                            s == 2 ? mq_a[k + 1] : 0.0, s == 2 ? mq_b[k + 1] : 0.0, s, k == 0, batch, gate,
+                            st, s == 2 ? 16 : v.tile, k == 0 ? &src : nullptr,
+                            last && sink_out ? &sink : nullptr);
+    zc ^= 1;
+    if (s == 2) dc ^= 1;
+    k += s;
+  }
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -805,17 +866,7 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
     // kernel of its own: reduced by the fused step, its summation order would
     // follow the tile side, which set-up picks by timing, and results would
     // then differ in the last bits between otherwise identical problems.
-    T* zb[2] = {zz, tt};
-    if (d.mq_steps % 2 == 1) std::swap(zb[0], zb[1]);
-    const int tile = mq_tile_for(batch);
-    const MqSource src{r, ld, mq_coef};
-    const MqSink sink{z, ld, scale};
-    for (int k = 0; k < d.mq_steps; ++k) {
-      const bool last = k + 1 == d.mq_steps;
-      launch_mq_cheb_fused<T>(g, rr, zb[k & 1], zb[(k + 1) & 1], dd, mq_a[k], mq_b[k], k == 0, batch,
-                              gate, st, tile, k == 0 ? &src : nullptr,
-                              last && !project_out ? &sink : nullptr);
-    }
+    mq_chain<T>(mq_variant_for(batch), rr, zz, tt, r, ld, z, scale, !project_out, batch, gate);
     if (!project_out) return;   // the last step wrote scale * z to the output
   } else {
     launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);
@@ -2209,12 +2260,15 @@ int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas) {
   return ETH_OK;
 }
 
-int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max) {
+int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max, int32_t* steps_1,
+                    int32_t* steps_max) {
   if (!p) return ETH_EINVAL;
   const Problem& P = p->impl;
   if (P.d.mq_mode != ETH_MQ_CHEB_SGS) return ETH_EUNSUPPORTED;
-  if (tile_1) *tile_1 = P.mq_tile_lo;
-  if (tile_max) *tile_max = P.mq_tile_hi;
+  if (tile_1) *tile_1 = P.mq_var_lo.tile;
+  if (tile_max) *tile_max = P.mq_var_hi.tile;
+  if (steps_1) *steps_1 = P.mq_var_lo.steps;
+  if (steps_max) *steps_max = P.mq_var_hi.steps;
   return ETH_OK;
 }
 
@@ -2336,17 +2390,20 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
       }
       case ETH_K_MQ_CHEB_STEP: {
         if (!P.mq_r) throw std::runtime_error("unsupported:no Chebyshev-SGS workspace");
-        launch = [&] {
+        const Problem::MqVariant v = P.mq_variant_for(B);
+        launch = [&, v] {
           if (P.mixed)
             eth::launch_mq_cheb_fused<float>(g, (float*)P.mq_r, (float*)P.mq_z, (float*)P.mq_t,
-                                             (float*)P.mq_d, 0.5, 0.1, 0, B, gate, P.st,
-                                             P.mq_tile_for(B));
+                                             (float*)P.mq_d, v.steps == 2 ? (float*)P.mq_d2 : (float*)P.mq_d,
+                                             0.5, 0.1, 0.5, 0.1, v.steps, 0, B, gate, P.st, v.tile);
           else
-            eth::launch_mq_cheb_fused<double>(g, (double*)P.mq_r, (double*)P.mq_z,
-                                              (double*)P.mq_t, (double*)P.mq_d, 0.5, 0.1, 0, B,
-                                              gate, P.st, P.mq_tile_for(B));
+            eth::launch_mq_cheb_fused<double>(g, (double*)P.mq_r, (double*)P.mq_z, (double*)P.mq_t,
+                                              (double*)P.mq_d,
+                                              v.steps == 2 ? (double*)P.mq_d2 : (double*)P.mq_d, 0.5, 0.1,
+                                              0.5, 0.1, v.steps, 0, B, gate, P.st, v.tile);
         };
-        // read r, z_k, d; write z_{k+1}, d (pressure vectors of n_k + n_0)
+        // one launch (of v.steps Chebyshev steps): read r, z_k, d; write
+        // z_{k+v.steps}, d (pressure vectors of n_k + n_0)
         by = 5.0 * es * (g.nk + g.n0) * B;
         break;
       }

@@ -228,14 +228,18 @@ __global__ void k_mq_project_out(Geo g, const T* __restrict__ z, double* __restr
 // spread stale halo values inward by one node at most, so the owned part is
 // exact after nine passes) and then forms
 //   s = t - z_k,  d = first ? b s : a d + b s,  z_{k+1} = z_k + d.
-// The tile side TQ (16, 32 or 64) is chosen per problem by timing the
+// ST = 2 runs two Chebyshev steps per launch on a region widened by 20: the
+// first combination is formed on the whole region (z_k and d held in
+// registers per staged node), the second sweep starts from it, and the
+// owned part is exact after eighteen passes.
+// The tile side TQ (16, 32 or 64) and ST are chosen per problem by timing the
 // candidates at set-up: small meshes want many blocks, large meshes less
-// halo (the redundancy is ((TQ + 2 HALO) / TQ)^2).
+// halo (the redundancy is ((TQ + 2 HALO) / TQ)^2 per launch).
 // Node updates share q1_gs_update / p0_gs_update with the per-colour kernel,
 // so every tile size gives the bit-identical sweep.
 // ---------------------------------------------------------------------------
-constexpr int HALO = 10;
-static_assert(HALO % 2 == 0, "parity of local and global indices must agree");
+constexpr int HALO1 = 10;   // halo of one step (nine passes), even
+static_assert(HALO1 % 2 == 0, "parity of local and global indices must agree");
 
 // LDS layout: the staged nodes (and elements) are split into four arrays by
 // the parity of their local (x, y) index, each row-major with QW = RQ / 2
@@ -245,8 +249,9 @@ static_assert(HALO % 2 == 0, "parity of local and global indices must agree");
 // of the nine neighbours and four elements of a node are constants of the
 // colour.  The arrays start QS apart, QS = 16 (mod 32), so that lanes that
 // alternate between two of them (the element pass) hit different banks.
-template <int TQ>
+template <int TQ, int ST = 1>
 struct MqTile {
+  static constexpr int HALO = HALO1 * ST;
   static constexpr int RQ = TQ + 2 * HALO;        // staged Q1 nodes per side (even)
   static constexpr int RE = RQ - 1;               // staged elements per side
   static constexpr int QW = RQ / 2;               // entries per row of a parity array
@@ -263,6 +268,7 @@ struct MqTile {
   static constexpr bool CACHE_R = TQ <= 32;
   static_assert(TQ % 2 == 0, "parity of local and global indices must agree");
   static_assert(QS % 32 == 16, "parity arrays must start on opposite bank halves");
+  static_assert(ST == 1 || TQ == 16, "two steps per launch: 16 x 16 tiles only (and FP32)");
 };
 
 // index in the parity arrays of local node (or element) (x, y)
@@ -283,15 +289,19 @@ __host__ __device__ constexpr int par_off(int px, int py, int dx, int dy) {
 // on k^perp as r - coef k, and store it to the workspace r (owned entries) for
 // the later steps.  sink (last step only, may be null): write scale z_{k+1}
 // straight to the pressure part of the FP64 vectors instead of the workspace.
-template <typename T, int TQ>
-__global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __restrict__ r,
-                                                                  const T* __restrict__ zin,
-                                                                  T* __restrict__ zout, T* __restrict__ d,
-                                                                  double a, double b, int first, Gate gate,
-                                                                  MqSource src, MqSink sink) {
-  using Tl = MqTile<TQ>;
+// din / dout: the Chebyshev direction d before and after (the same array for
+// ST = 1, where a block touches only its owned entries; two arrays for ST = 2,
+// which reads d over its whole region).
+template <typename T, int TQ, int ST>
+__global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T* __restrict__ r,
+                                                                      const T* __restrict__ zin,
+                                                                      T* __restrict__ zout, const T* din,
+                                                                      T* dout, double a, double b, double a2,
+                                                                      double b2, int first, Gate gate,
+                                                                      MqSource src, MqSink sink) {
+  using Tl = MqTile<TQ, ST>;
   constexpr int RQ = Tl::RQ, RE = Tl::RE, QW = Tl::QW, QS = Tl::QS, NC = Tl::NC, FT = Tl::FT,
-                OWN = Tl::OWN;
+                OWN = Tl::OWN, HALO = Tl::HALO;
   __shared__ T tq[4 * QS];
   __shared__ T rq[4 * QS];
   __shared__ T te[4 * QS];
@@ -314,10 +324,12 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
   const T h2_36 = T(h2 / 36.0), h2_4 = T(0.25 * h2), inv_h2_9 = T(9.0 / h2), inv_h2 = T(1.0 / h2);
   const int tid = threadIdx.x;
   T* zo = zout + (long long)rhs * np;
-  T* dr = d + (long long)rhs * np;
+  const T* dr = din + (long long)rhs * np;
+  T* dw = dout + (long long)rhs * np;
   // the owned node / element values of z_k and d, fetched before the staging
   // so that their latency overlaps it
-  constexpr bool PF = Tl::CACHE_R;   // TQ = 64 reads them at the end instead (registers)
+  // (two steps per launch keep z_k and d of every staged node instead)
+  constexpr bool PF = Tl::CACHE_R && ST == 1;   // TQ = 64 reads them at the end instead (registers)
   constexpr int OWP = PF ? OWN : 1;
   T z0q[OWP], d0q[OWP], z0e[OWP], d0e[OWP];
   if constexpr (PF) {
@@ -344,72 +356,88 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
   // two rounds, nodes then elements, for FP64 tiles of 1024 threads, whose
   // registers would not hold both)
   // (the projection is the expression of k_mq_project_in, so both paths agree bit for bit)
-  auto stage_elements = [&]() {
-    constexpr int IE = (RE * RE + FT - 1) / FT;
-    T tw[IE], rw[IE];
-#pragma unroll
-    for (int i = 0; i < IE; ++i) {
-      const int k = tid + i * FT;
-      tw[i] = rw[i] = T(0);
-      const int e = gx + k % RE, f = gy + k / RE;
-      if (k < RE * RE && e >= 0 && e < n && f >= 0 && f < n) {
-        const long long q = g.nk + (long long)f * n + e;
-        rw[i] = r64 ? (T)(r64[q] - cf * -1.0) : rr[q];
-        if (!first) tw[i] = zi[q];
+  constexpr int IQ = (RQ * RQ + FT - 1) / FT, IE = (RE * RE + FT - 1) / FT;
+  // two steps per launch: z_k and d at every staged node / element
+  constexpr int KQ = ST == 2 ? IQ : 1, KE = ST == 2 ? IE : 1;
+  T zk[KQ], dk[KQ], zke[KE], dke[KE];
+  auto load_node = [&](int k, T& tv, T& rv, T& dv) {
+    tv = rv = dv = T(0);
+    const int c = gx + k % RQ, dd = gy + k / RQ;
+    if (k < RQ * RQ && c >= 0 && c <= n && dd >= 0 && dd <= n) {
+      const long long q = (long long)dd * (n + 1) + c;
+      rv = r64 ? (T)(r64[q] - cf * 1.0) : rr[q];
+      if (!first) {
+        tv = zi[q];
+        if constexpr (ST == 2) dv = dr[q];
       }
     }
-    return [&, tw, rw]() {
-#pragma unroll
-      for (int i = 0; i < IE; ++i) {
-        const int k = tid + i * FT;
-        if (k < RE * RE) {
-          const int li = par_idx<QW, QS>(k % RE, k / RE);
-          te[li] = tw[i];
-          re[li] = rw[i];
-        }
-      }
-    };
   };
-  constexpr bool TWO_ROUNDS = sizeof(T) == 8 && TQ >= 32;
-  {
-    constexpr int IQ = (RQ * RQ + FT - 1) / FT;
-    T tv[IQ], rv[IQ];
+  auto load_element = [&](int k, T& tv, T& rv, T& dv) {
+    tv = rv = dv = T(0);
+    const int e = gx + k % RE, f = gy + k / RE;
+    if (k < RE * RE && e >= 0 && e < n && f >= 0 && f < n) {
+      const long long q = g.nk + (long long)f * n + e;
+      rv = r64 ? (T)(r64[q] - cf * -1.0) : rr[q];
+      if (!first) {
+        tv = zi[q];
+        if constexpr (ST == 2) dv = dr[q];
+      }
+    }
+  };
+  auto store_nodes = [&](const T* tv, const T* rv) {
 #pragma unroll
     for (int i = 0; i < IQ; ++i) {
       const int k = tid + i * FT;
-      tv[i] = rv[i] = T(0);
-      const int c = gx + k % RQ, dd = gy + k / RQ;
-      if (k < RQ * RQ && c >= 0 && c <= n && dd >= 0 && dd <= n) {
-        const long long q = (long long)dd * (n + 1) + c;
-        rv[i] = r64 ? (T)(r64[q] - cf * 1.0) : rr[q];
-        if (!first) tv[i] = zi[q];
+      if (k < RQ * RQ) {
+        const int li = par_idx<QW, QS>(k % RQ, k / RQ);
+        tq[li] = tv[i];
+        rq[li] = rv[i];
       }
     }
-    if constexpr (!TWO_ROUNDS) {
-      auto store_elements = stage_elements();
+  };
+  auto store_elements = [&](const T* tw, const T* rw) {
 #pragma unroll
-      for (int i = 0; i < IQ; ++i) {
-        const int k = tid + i * FT;
-        if (k < RQ * RQ) {
-          const int li = par_idx<QW, QS>(k % RQ, k / RQ);
-          tq[li] = tv[i];
-          rq[li] = rv[i];
-        }
+    for (int i = 0; i < IE; ++i) {
+      const int k = tid + i * FT;
+      if (k < RE * RE) {
+        const int li = par_idx<QW, QS>(k % RE, k / RE);
+        te[li] = tw[i];
+        re[li] = rw[i];
       }
-      store_elements();
-    } else {
+    }
+  };
+  if constexpr (sizeof(T) == 8 && TQ >= 32) {
+    {
+      T tv[IQ], rv[IQ], dv;
+#pragma unroll
+      for (int i = 0; i < IQ; ++i) load_node(tid + i * FT, tv[i], rv[i], dv);
+      store_nodes(tv, rv);
+    }
+    T tw[IE], rw[IE], dx;
+#pragma unroll
+    for (int i = 0; i < IE; ++i) load_element(tid + i * FT, tw[i], rw[i], dx);
+    store_elements(tw, rw);
+  } else {
+    T tv[IQ], rv[IQ], dv[IQ], tw[IE], rw[IE], de[IE];
+#pragma unroll
+    for (int i = 0; i < IQ; ++i) load_node(tid + i * FT, tv[i], rv[i], dv[i]);
+#pragma unroll
+    for (int i = 0; i < IE; ++i) load_element(tid + i * FT, tw[i], rw[i], de[i]);
+    store_nodes(tv, rv);
+    store_elements(tw, rw);
+    if constexpr (ST == 2) {
 #pragma unroll
       for (int i = 0; i < IQ; ++i) {
-        const int k = tid + i * FT;
-        if (k < RQ * RQ) {
-          const int li = par_idx<QW, QS>(k % RQ, k / RQ);
-          tq[li] = tv[i];
-          rq[li] = rv[i];
-        }
+        zk[i] = tv[i];
+        dk[i] = dv[i];
+      }
+#pragma unroll
+      for (int i = 0; i < IE; ++i) {
+        zke[i] = tw[i];
+        dke[i] = de[i];
       }
     }
   }
-  if constexpr (TWO_ROUNDS) stage_elements()();
   if (off) return;   // uniform per block
   // A thread updates the same node of a colour (and the same elements) in
   // every pass: the base index hx + hy*QW of each, its boundary flags and its
@@ -460,6 +488,7 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
       for (int i = 0; i < EPQ; ++i)
         er[p][i] = (emask >> (p * EPQ + i)) & 1u ? re[p * QS + tid + i * FT] : T(0);
   }
+  auto sweep = [&]() {
   constexpr int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
 #pragma unroll
   for (int pass = 0; pass < 9; ++pass) {
@@ -501,8 +530,76 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
     }
     __syncthreads();
   }
-  // Chebyshev combination on the owned nodes and elements
+  };
+  sweep();
   const T ta = T(a), tb = T(b);
+  if constexpr (ST == 2) {
+    // first combination on the whole region, the second sweep from it
+#pragma unroll
+    for (int i = 0; i < IQ; ++i) {
+      const int k = tid + i * FT;
+      if (k < RQ * RQ) {
+        const int li = par_idx<QW, QS>(k % RQ, k / RQ);
+        T dn;
+        zk[i] = cheb_combine<T>(tq[li], zk[i], dk[i], ta, tb, first, dn);
+        dk[i] = dn;
+        tq[li] = zk[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IE; ++i) {
+      const int k = tid + i * FT;
+      if (k < RE * RE) {
+        const int li = par_idx<QW, QS>(k % RE, k / RE);
+        T dn;
+        zke[i] = cheb_combine<T>(te[li], zke[i], dke[i], ta, tb, first, dn);
+        dke[i] = dn;
+        te[li] = zke[i];
+      }
+    }
+    __syncthreads();
+    sweep();
+    // second combination on the owned nodes and elements, in staging order
+    const T ta2 = T(a2), tb2 = T(b2);
+#pragma unroll
+    for (int i = 0; i < IQ; ++i) {
+      const int k = tid + i * FT, lx = k % RQ, ly = k / RQ;
+      const int c = gx + lx, dd = gy + ly;
+      if (k >= RQ * RQ || lx < HALO || lx >= HALO + TQ || ly < HALO || ly >= HALO + TQ || c > n || dd > n)
+        continue;
+      const int li = par_idx<QW, QS>(lx, ly);
+      const long long oq = (long long)dd * (n + 1) + c;
+      T dn;
+      const T zn = cheb_combine<T>(tq[li], zk[i], dk[i], ta2, tb2, 0, dn);
+      if (o64) {
+        o64[oq] = sink.scale * (double)zn;
+      } else {
+        dw[oq] = dn;
+        zo[oq] = zn;
+      }
+      if (r64) rr[oq] = rq[li];
+    }
+#pragma unroll
+    for (int i = 0; i < IE; ++i) {
+      const int k = tid + i * FT, lx = k % RE, ly = k / RE;
+      const int e = gx + lx, f = gy + ly;
+      if (k >= RE * RE || lx < HALO || lx >= HALO + TQ || ly < HALO || ly >= HALO + TQ || e >= n || f >= n)
+        continue;
+      const int li = par_idx<QW, QS>(lx, ly);
+      const long long oe = g.nk + (long long)f * n + e;
+      T dn;
+      const T zn = cheb_combine<T>(te[li], zke[i], dke[i], ta2, tb2, 0, dn);
+      if (o64) {
+        o64[oe] = sink.scale * (double)zn;
+      } else {
+        dw[oe] = dn;
+        zo[oe] = zn;
+      }
+      if (r64) rr[oe] = re[li];
+    }
+    return;
+  }
+  // Chebyshev combination on the owned nodes and elements
 #pragma unroll
   for (int i = 0; i < OWN; ++i) {
     const int idx = tid + i * FT, ox = idx % TQ, oy = idx / TQ;
@@ -518,7 +615,7 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
       if (o64) {
         o64[oq] = sink.scale * (double)zn;
       } else {
-        dr[oq] = dn;
+        dw[oq] = dn;
         zo[oq] = zn;
       }
       if (r64) rr[oq] = rq[lo];
@@ -532,7 +629,7 @@ __global__ __launch_bounds__(MqTile<TQ>::FT) void k_mq_cheb_fused(Geo g, T* __re
       if (o64) {
         o64[oe] = sink.scale * (double)zn;
       } else {
-        dr[oe] = dn;
+        dw[oe] = dn;
         zo[oe] = zn;
       }
       if (r64) rr[oe] = re[lo];
@@ -613,29 +710,35 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
 
 
 template <typename T>
-void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, T* d, double a, double b,
-                          int first, int batch, Gate gate, hipStream_t st, int tile, const MqSource* src,
-                          const MqSink* sink) {
+void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, const T* din, T* dout, double a,
+                          double b, double a2, double b2, int steps, int first, int batch, Gate gate,
+                          hipStream_t st, int tile, const MqSource* src, const MqSink* sink) {
   if (tile == 64 && sizeof(T) != 4) throw std::invalid_argument("M_Q tile 64 needs the FP32 preconditioner");
+  if (steps == 2 && (tile != 16 || din == dout))
+    throw std::invalid_argument("two M_Q steps per launch need 16 x 16 tiles and separate d arrays");
   const int tq = (tile == 16 || tile == 64) ? tile : 32;
   const MqSource s = src ? *src : MqSource{};
   const MqSink k = sink ? *sink : MqSink{};
-#define ETH_MQF(TQ)                                                                                    \
-  hipLaunchKernelGGL((k_mq_cheb_fused<T, TQ>),                                                        \
+#define ETH_MQF(TQ, ST)                                                                                \
+  hipLaunchKernelGGL((k_mq_cheb_fused<T, TQ, ST>),                                                    \
                      dim3((g.n + 1 + TQ - 1) / TQ, (g.n + 1 + TQ - 1) / TQ, batch),                   \
-                     dim3(MqTile<TQ>::FT), 0, st, g, r, zin, zout, d, a, b, first, gate, s, k)
-  if (tq == 16) {
-    ETH_MQF(16);
+                     dim3(MqTile<TQ, ST>::FT), 0, st, g, r, zin, zout, din, dout, a, b, a2, b2, first, \
+                     gate, s, k)
+  if (steps == 2) {
+    // FP32 only: z_k and d of every staged entry would not fit FP64 registers
+    if constexpr (sizeof(T) == 4) ETH_MQF(16, 2);
+    else throw std::invalid_argument("two M_Q steps per launch need the FP32 preconditioner");
+  } else if (tq == 16) {
+    ETH_MQF(16, 1);
   } else if (tq == 64) {
     // the 84^2 + 83^2 staged values of two arrays fit the LDS in FP32 only
-    if constexpr (sizeof(T) == 4) ETH_MQF(64);
+    if constexpr (sizeof(T) == 4) ETH_MQF(64, 1);
   } else {
-    ETH_MQF(32);
+    ETH_MQF(32, 1);
   }
 #undef ETH_MQF
   ETH_LAUNCH_CHECK();
 }
-
 
 #define ETH_INST(T)                                                                               \
   template void launch_mq_kdot<T>(const Geo&, const T*, long long, long long, int, const RedCtx&,  \
@@ -647,8 +750,9 @@ void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, T* d, doubl
                                           hipStream_t);                                            \
   template void launch_mq_project_out<T>(const Geo&, const T*, double*, long long, int,            \
                                          const double*, double, Gate, hipStream_t);               \
-  template void launch_mq_cheb_fused<T>(const Geo&, T*, const T*, T*, T*, double, double, int, int,  \
-                                        Gate, hipStream_t, int, const MqSource*, const MqSink*);
+  template void launch_mq_cheb_fused<T>(const Geo&, T*, const T*, T*, const T*, T*, double, double,  \
+                                        double, double, int, int, int, Gate, hipStream_t, int,          \
+                                        const MqSource*, const MqSink*);
 ETH_INST(double)
 ETH_INST(float)
 #undef ETH_INST

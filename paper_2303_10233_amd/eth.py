@@ -49,6 +49,7 @@ class ProblemDesc(ctypes.Structure):
         ("pcd_q1_steps", ctypes.c_int32),
         ("gmres_restart", ctypes.c_int32),
         ("mq_tile", ctypes.c_int32),
+        ("mq_fuse_steps", ctypes.c_int32),
     ]
 
 
@@ -121,7 +122,7 @@ def load_library(path=LIB_PATH):
     lib.eth_apply_pcd.restype = ctypes.c_int
     lib.eth_get_q1_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.eth_get_q1_levels.restype = ctypes.c_int
-    lib.eth_get_mq_tile.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.eth_get_mq_tile.argtypes = [P] + [ctypes.POINTER(ctypes.c_int32)] * 4
     lib.eth_get_mq_tile.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
     lib.eth_infsup_estimate.argtypes = [P, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -207,7 +208,7 @@ def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
                wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0, mq_cheb=(0.0, 0.0),
                gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0), gmg_lambda=None, precision=FP64,
                max_batch=1, device=None, gmg_omega=0.0, pcd_q1_steps=0, gmres_restart=0,
-               mq_tile=0):
+               mq_tile=0, mq_fuse_steps=0):
     """A filled ProblemDesc and the Python objects it points into."""
     d = ProblemDesc()
     d.n = n
@@ -234,6 +235,7 @@ def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
     d.pcd_q1_steps = pcd_q1_steps
     d.gmres_restart = gmres_restart
     d.mq_tile = mq_tile
+    d.mq_fuse_steps = mq_fuse_steps
     dev = torch.device("cuda" if device is None else device)
     with torch.cuda.device(dev):
         d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -247,7 +249,7 @@ class Problem:
                  kind=STOKES, wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0,
                  mq_cheb=(0.0, 0.0), gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0),
                  gmg_lambda=None, precision=FP64, max_batch=1, device=None, gmg_omega=0.0,
-                 pcd_q1_steps=0, gmres_restart=0, mq_tile=0):
+                 pcd_q1_steps=0, gmres_restart=0, mq_tile=0, mq_fuse_steps=0):
         d, keep = _make_desc(**{k: v for k, v in locals().items() if k not in ("self", "__class__")})
         self._keep = keep
         h = ctypes.c_void_p()
@@ -301,9 +303,15 @@ class Problem:
     def mq_tile(self):
         """(tile side for one RHS, for max_batch RHS) of the fused Chebyshev
         step of MQ_CHEB_SGS, chosen at set-up unless mq_tile was given."""
-        a, b = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().eth_get_mq_tile(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
-        return a.value, b.value
+        return self.mq_variant()[0::2]
+
+    def mq_variant(self):
+        """(tile_1, steps_1, tile_max, steps_max): tile side and Chebyshev
+        steps per launch of the fused step for one RHS and for max_batch."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().eth_get_mq_tile(self._h, ctypes.byref(v[0]), ctypes.byref(v[2]), ctypes.byref(v[1]),
+                                     ctypes.byref(v[3])), self._h)
+        return tuple(x.value for x in v)
 
     def empty(self, batch=1):
         shape = (self.N,) if batch == 1 else (batch, self.N)

@@ -192,6 +192,36 @@ def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     z_plain = _np(Q.apply_preconditioner(_t(r)))
     for tile in tiles:
         assert np.array_equal(z_fused[tile][o:], z_plain[o:]), tile
+    if prec == eth.MIXED:
+        # two Chebyshev steps per launch (halo 20), also with an odd step count
+        for steps in (20, 7):
+            print(f"[fused mq] n={n} two steps per launch, mq_steps={steps}", flush=True)
+            monkeypatch.delenv("ETH_DEBUG_UNFUSED_MQ")
+            A2 = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_tile=16, mq_fuse_steps=2,
+                             mq_steps=steps)
+            assert A2.mq_variant()[:2] == (16, 2)
+            z2 = _np(A2.apply_preconditioner(_t(r)))
+            monkeypatch.setenv("ETH_DEBUG_UNFUSED_MQ", "1")
+            Q2 = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_steps=steps)   # per colour
+            zq = _np(Q2.apply_preconditioner(_t(r)))
+            assert np.array_equal(z2[o:], zq[o:]), steps
+
+
+def test_two_steps_per_launch_solve_equals_one():
+    """MINRES with the two-step fused kernel (the last launch writing straight
+    to the FP64 vector) gives the one-step result bit for bit."""
+    n = 64
+    P1 = eth.Problem(n, precision=eth.MIXED, mq_tile=16, mq_fuse_steps=1)
+    P2 = eth.Problem(n, precision=eth.MIXED, mq_tile=16, mq_fuse_steps=2)
+    b = P1.assemble_rhs()
+    x1, i1 = P1.solve(b, rtol=1e-8, maxit=500, use_graph=True)
+    x2, i2 = P2.solve(b, rtol=1e-8, maxit=500, use_graph=True)
+    assert i1[0]["iterations"] == i2[0]["iterations"]
+    assert torch.equal(x1, x2)
+    with pytest.raises(Exception):
+        eth.Problem(16, precision=eth.FP64, mq_fuse_steps=2)
+    with pytest.raises(Exception):
+        eth.Problem(16, precision=eth.MIXED, mq_tile=32, mq_fuse_steps=2)
 
 
 @pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
