@@ -319,7 +319,8 @@ def counters_run(n, reps, tile):
         for k in kernels:
             ms, by = P.profile_kernel(k, reps=reps)
             rec["launches"].append(dict(n=nn, kernel=eth.KERNEL_NAMES[k], bytes_per_launch=by,
-                                        avg_us=round(1e3 * ms, 3), mq_tile=P.mq_tile()[0]))
+                                        avg_us=round(1e3 * ms, 3), mq_tile=P.mq_variant()[0],
+                                        mq_steps_per_launch=P.mq_variant()[1]))
             log(f"counters n={nn} {eth.KERNEL_NAMES[k]}: {by:.0f} B, {1e3 * ms:.2f} us")
         P.close()
         del P
@@ -405,7 +406,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(dk["gbs"], 2),
                 "peak": MI355X_HBM_GBS, "unit": "GB/s",
                 "frac": round(dk["gbs"] / MI355X_HBM_GBS, 5),
-                "traffic": measured_traffic(dom, n, f"k_mq_cheb_fused<float, {Pm.mq_tile()[0]}>"
+                "traffic": measured_traffic(dom, n, "k_mq_cheb_fused<float, %d, %d>" % Pm.mq_variant()[:2]
                                             if dom == "k_mq_cheb_fused" else None),
                 "bytes_per_launch": dk["bytes"], "avg_launch_us": round(dk["avg_us"], 3)}
     log("kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us {v['gbs']:.0f}GB/s"

@@ -48,10 +48,11 @@ def copy_grid(n):
     return -(-vector_length(n) // 256) * 256
 
 
-def mq_grid(n, tile, halo=10):
-    """work-items of k_mq_cheb_fused<T, tile> on one right-hand side"""
-    nc = (tile + 2 * halo - 1) // 2
-    threads = 1024 if tile >= 32 else 64 * (-(-nc * nc // 64))
+def mq_grid(n, tile, steps=1):
+    """work-items of k_mq_cheb_fused<T, tile, steps> on one right-hand side
+    (one thread per entry of a parity array of the staged region for tile 16)"""
+    qw = tile // 2 + 10 * steps
+    threads = 1024 if tile >= 32 else 64 * (-(-qw * qw // 64))
     return (-(-(n + 1) // tile)) ** 2 * threads
 
 
@@ -74,8 +75,9 @@ def main():
     write = per_dispatch(a.write, "WRITE_SIZE")
     if a.kernel != "k_mq_cheb_fused":
         raise SystemExit("only the fused Chebyshev-SGS step is described here")
-    name = f"{a.kernel}<float, {target['mq_tile']}>"
-    grid = mq_grid(n, target["mq_tile"])
+    steps = target.get("mq_steps_per_launch", 1)
+    name = f"{a.kernel}<float, {target['mq_tile']}, {steps}>"
+    grid = mq_grid(n, target["mq_tile"], steps)
     f_kib, nf = pick(fetch, name, grid)
     w_kib, nw = pick(write, name, grid)
     cf_big, _ = pick(fetch, "k_copy", copy_grid(2048))
