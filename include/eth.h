@@ -259,7 +259,9 @@ int eth_misfit(eth_problem* p, const double* x, const double* x_target, double* 
  * problems run concurrently on the GPU.  descs[i] as for eth_setup (kind must
  * be ETH_STOKES); descs[0].stream is the caller's stream: eth_batch_solve
  * waits for the work already queued on it and makes it wait for the results.
- * Each problem takes one right-hand side. */
+ * Each problem takes one right-hand side.  Members run their preconditioner
+ * blocks one after the other (the batch itself is the concurrency), and
+ * mq_fuse_steps = 0 means one Chebyshev step per launch here. */
 typedef struct eth_batch eth_batch;
 int eth_batch_setup(const eth_problem_desc* descs, int32_t count, eth_batch** out);
 int eth_batch_count(const eth_batch* b);

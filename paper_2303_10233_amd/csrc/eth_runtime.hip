@@ -467,7 +467,10 @@ void Problem::setup(const eth_problem_desc& desc) {
     build_gmres();
   } else {
     build_velocity();
-    if (!std::getenv("ETH_DEBUG_SERIAL_PRECOND")) {
+    // members of a ragged batch run concurrently with each other instead: a
+    // second branch per member would only multiply the streams sharing the
+    // few hardware queues
+    if (!own_stream && !std::getenv("ETH_DEBUG_SERIAL_PRECOND")) {
       ETH_HIP(hipStreamCreateWithFlags(&pst, hipStreamNonBlocking));
       ETH_HIP(hipEventCreateWithFlags(&ev_pf, hipEventDisableTiming));
       ETH_HIP(hipEventCreateWithFlags(&ev_pj, hipEventDisableTiming));
@@ -1075,6 +1078,26 @@ void Problem::run_iterations(int batch, int count, bool use_graph) {
   // `count` is even: the buffer roles repeat every two iterations
   if (!use_graph) {
     for (int i = 0; i < count; ++i) minres_iteration(batch, i & 1);
+    return;
+  }
+  if (own_stream) {
+    // a ragged-batch member captures and replays on its own stream: one
+    // stream per member spreads the members evenly over the hardware queues
+    if (!gexec || gexec_batch != batch) {
+      if (gexec) {
+        ETH_HIP(hipGraphExecDestroy(gexec));
+        gexec = nullptr;
+      }
+      hipGraph_t graph;
+      ETH_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      minres_iteration(batch, 0);
+      minres_iteration(batch, 1);
+      ETH_HIP(hipStreamEndCapture(st, &graph));
+      ETH_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      ETH_HIP(hipGraphDestroy(graph));
+      gexec_batch = batch;
+    }
+    for (int i = 0; i < count; i += 2) ETH_HIP(hipGraphLaunch(gexec, st));
     return;
   }
   if (!gst) {
@@ -2082,6 +2105,10 @@ int eth_batch_setup(const eth_problem_desc* descs, int32_t count, eth_batch** ou
     ETH_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     for (int i = 0; i < count; ++i) {
       eth_problem_desc d = descs[i];
+      // one Chebyshev step per launch unless asked: the two-step launch's
+      // 832-thread blocks fill whole CUs, and members mixing the two variants
+      // were measured to run one after another instead of together
+      if (d.mq_fuse_steps == 0) d.mq_fuse_steps = 1;
       hipStream_t s = nullptr;
       ETH_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
       d.stream = s;
