@@ -145,64 +145,95 @@ __device__ inline void element_convection(const double (*u)[3][3], const double 
 // Convection on one element for ONE velocity component:
 //   TRANS = false: out_i = int (w . grad u_h) phi_i   (N u)
 //   TRANS = true : out_i = int (w . grad phi_i) u_h   (N^T u)
-template <typename TW, bool TRANS = false>
-__device__ inline void element_convection1(const double (*u)[3], const TW (*w)[3][3], double h,
-                                           double (*out)[3]) {
-  double W[NG], GB[NG][3], GD[NG][3];
-  gauss_tables(W, GB, GD);
-  double c0[NG][NG], c1[NG][NG];
+// by sum factorisation over the 4 x 4 Gauss points (x first, then y), in the
+// arithmetic type C (FP32 inside the mixed-precision smoother).
+template <typename C, typename TW, bool TRANS = false>
+__device__ inline void element_convection1(const C (*u)[3], const TW (*w)[3][3], C h, C (*out)[3]) {
+  double Wd[NG], GBd[NG][3], GDd[NG][3];
+  gauss_tables(Wd, GBd, GDd);
+  C W[NG], GB[NG][3], GD[NG][3];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    W[q] = (C)Wd[q];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      GB[q][i] = (C)GBd[q][i];
+      GD[q][i] = (C)GDd[q][i];
+    }
+  }
+  // along x: row j of the element at Gauss abscissa qx
+  C wx1[3][NG], wy1[3][NG], ud1[3][NG], ub1[3][NG];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int qx = 0; qx < NG; ++qx) {
+      C a = 0, b = 0, c = 0, d = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        a += GB[qx][i] * (C)w[0][j][i];
+        b += GB[qx][i] * (C)w[1][j][i];
+        c += GD[qx][i] * u[j][i];
+        d += GB[qx][i] * u[j][i];
+      }
+      wx1[j][qx] = a;
+      wy1[j][qx] = b;
+      ud1[j][qx] = c;
+      ub1[j][qx] = d;
+    }
+  // along y: the Gauss point values, weighted
+  C c0[NG][NG], c1[NG][NG];
 #pragma unroll
   for (int qy = 0; qy < NG; ++qy)
 #pragma unroll
     for (int qx = 0; qx < NG; ++qx) {
-      double wx = 0.0, wy = 0.0, ux = 0.0, uy = 0.0, uv = 0.0;
+      C wx = 0, wy = 0, ux = 0, uy = 0, uv = 0;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        double tw0 = 0.0, tw1 = 0.0, tx = 0.0, ty = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          tw0 += GB[qx][i] * (double)w[0][j][i];
-          tw1 += GB[qx][i] * (double)w[1][j][i];
-          if constexpr (!TRANS) tx += GD[qx][i] * u[j][i];
-          ty += GB[qx][i] * u[j][i];
-        }
-        wx += GB[qy][j] * tw0;
-        wy += GB[qy][j] * tw1;
+        wx += GB[qy][j] * wx1[j][qx];
+        wy += GB[qy][j] * wy1[j][qx];
         if constexpr (!TRANS) {
-          ux += GB[qy][j] * tx;
-          uy += GD[qy][j] * ty;
+          ux += GB[qy][j] * ud1[j][qx];
+          uy += GD[qy][j] * ub1[j][qx];
         } else {
-          uv += GB[qy][j] * ty;
+          uv += GB[qy][j] * ub1[j][qx];
         }
       }
+      const C ww = W[qx] * W[qy];
       if constexpr (!TRANS) {
-        c0[qy][qx] = W[qx] * W[qy] * (wx * ux + wy * uy);
+        c0[qy][qx] = ww * (wx * ux + wy * uy);
       } else {
-        c0[qy][qx] = W[qx] * W[qy] * wx * uv;   // pairs with d(phi_i)/dx
-        c1[qy][qx] = W[qx] * W[qy] * wy * uv;   // pairs with d(phi_i)/dy
+        c0[qy][qx] = ww * wx * uv;   // pairs with d(phi_i)/dx
+        c1[qy][qx] = ww * wy * uv;   // pairs with d(phi_i)/dy
       }
+    }
+  // test functions: x first, then y
+  C s0[NG][3], s1[NG][3];
+#pragma unroll
+  for (int qy = 0; qy < NG; ++qy)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      C a = 0, b = 0;
+#pragma unroll
+      for (int qx = 0; qx < NG; ++qx) {
+        if constexpr (!TRANS) {
+          a += GB[qx][i] * c0[qy][qx];
+        } else {
+          a += GD[qx][i] * c0[qy][qx];
+          b += GB[qx][i] * c1[qy][qx];
+        }
+      }
+      s0[qy][i] = a;
+      s1[qy][i] = b;
     }
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      double a = 0.0;
+      C a = 0;
 #pragma unroll
       for (int qy = 0; qy < NG; ++qy) {
-        if constexpr (!TRANS) {
-          double t = 0.0;
-#pragma unroll
-          for (int qx = 0; qx < NG; ++qx) t += GB[qx][i] * c0[qy][qx];
-          a += GB[qy][j] * t;
-        } else {
-          double tx = 0.0, ty = 0.0;
-#pragma unroll
-          for (int qx = 0; qx < NG; ++qx) {
-            tx += GD[qx][i] * c0[qy][qx];
-            ty += GB[qx][i] * c1[qy][qx];
-          }
-          a += GB[qy][j] * tx + GD[qy][j] * ty;
-        }
+        if constexpr (!TRANS) a += GB[qy][j] * s0[qy][i];
+        else a += GB[qy][j] * s0[qy][i] + GD[qy][j] * s1[qy][i];
       }
       out[j][i] = h * a;
     }

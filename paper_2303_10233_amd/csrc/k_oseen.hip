@@ -126,6 +126,8 @@ __global__ void k_dense_convdiff(Geo g, const double* __restrict__ wind, double 
 // multigrid level; with out64 (MODE 0) the result goes, times out_scale, to
 // the velocity part of FP64 vectors instead.  TRANS: F^T = nu A + N^T (same
 // diagonal).
+// The element convection and the stencil sums run in the storage type T
+// (FP32 in the mixed-precision preconditioner).
 template <typename T, int MODE, bool TRANS>
 __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict__ wind,
                                                 const double* __restrict__ dF, double nu,
@@ -133,9 +135,10 @@ __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict_
                                                 T* __restrict__ out, double omega,
                                                 double* __restrict__ out64, long long ld64,
                                                 double out_scale, Gate gate) {
-  __shared__ double sx[VY][VX];
-  __shared__ double sw[2][VY][VX];
-  __shared__ double sN[(TY + 1) * (TX + 1)][9];
+  using C = T;
+  __shared__ C sx[VY][VX];
+  __shared__ C sw[2][VY][VX];
+  __shared__ C sN[(TY + 1) * (TX + 1)][9];
   const int plane = blockIdx.z;
   if (gate.off(plane >> 1)) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
@@ -143,31 +146,31 @@ __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict_
   const int n = g.n, nq = g.nq, top = 2 * n;
   const long long po = (long long)plane * g.nv;
   const int I0 = 2 * ex0 - 2, J0 = 2 * ey0 - 2;
-  stage2<NT, VX * VY>(&sw[0][0][0], &sw[1][0][0], tid, [&](int k, double& w0, double& w1) {
+  stage2<NT, VX * VY>(&sw[0][0][0], &sw[1][0][0], tid, [&](int k, C& w0, C& w1) {
     const int I = I0 + k % VX, J = J0 + k / VX;
     if (I >= 0 && I <= top && J >= 0 && J <= top) {
       const long long o = (long long)J * nq + I;
-      w0 = wind[o];
-      w1 = wind[g.nv + o];
+      w0 = (C)wind[o];
+      w1 = (C)wind[g.nv + o];
     }
   });
-  stage1<NT, VX * VY>(&sx[0][0], tid, [&](int k, double& xv) {
+  stage1<NT, VX * VY>(&sx[0][0], tid, [&](int k, C& xv) {
     const int I = I0 + k % VX, J = J0 + k / VX;
-    if (I > 0 && J > 0 && I < top && J < top) xv = (double)x[po + (long long)J * nq + I];
+    if (I > 0 && J > 0 && I < top && J < top) xv = (C)x[po + (long long)J * nq + I];
   });
   __syncthreads();
   for (int k = tid; k < (TX + 1) * (TY + 1); k += NT) {
     const int lex = k % (TX + 1), ley = k / (TX + 1);
     const int e = ex0 - 1 + lex, f = ey0 - 1 + ley;
     if (e < 0 || e >= n || f < 0 || f >= n) continue;
-    double ul[3][3], wl[2][3][3], ol[3][3];
+    C ul[3][3], wl[2][3][3], ol[3][3];
     for (int j = 0; j < 3; ++j)
       for (int i = 0; i < 3; ++i) {
         ul[j][i] = sx[2 * ley + j][2 * lex + i];
         wl[0][j][i] = sw[0][2 * ley + j][2 * lex + i];
         wl[1][j][i] = sw[1][2 * ley + j][2 * lex + i];
       }
-    element_convection1<double, TRANS>(ul, wl, g.h, ol);
+    element_convection1<C, C, TRANS>(ul, wl, (C)g.h, ol);
     for (int j = 0; j < 3; ++j)
       for (int i = 0; i < 3; ++i) sN[k][3 * j + i] = ol[j][i];
   }
@@ -185,15 +188,15 @@ __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict_
       double res = 0.0, xn = 0.0;
       if (!bnd) {
         const int lx = 2 * tx + i + 2, ly = 2 * ty + j + 2;
-        double ax = 0.0;
+        C ax = 0;
 #pragma unroll
         for (int bb = -2; bb <= 2; ++bb)
 #pragma unroll
           for (int aa = -2; aa <= 2; ++aa) {
             const int c = K1(i, aa) * M1(j, bb) + M1(i, aa) * K1(j, bb);
-            if (c != 0) ax += c * sx[ly + bb][lx + aa];
+            if (c != 0) ax += (C)c * sx[ly + bb][lx + aa];
           }
-        double cv = 0.0;
+        C cv = 0;
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb) {
           if (j == 1 && bb == 0) continue;
@@ -206,8 +209,8 @@ __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict_
             cv += sN[k][3 * (j + 2 * (1 - bb)) + (i + 2 * (1 - aa))];
           }
         }
-        res = (double)b[po + o] - (nu / 90.0 * ax + cv);
-        xn = sx[ly][lx] + omega * res / dF[o];
+        res = (double)b[po + o] - ((double)(C)(nu / 90.0) * (double)ax + (double)cv);
+        xn = (double)sx[ly][lx] + omega * res / dF[o];
       }
       if constexpr (MODE == 1) {
         out[po + o] = (T)res;
