@@ -692,10 +692,13 @@ void Problem::build_pressure() {
 
 // The fastest variant of the fused Chebyshev step (tile side, one or two
 // steps per launch) for `batch` right-hand sides on this mesh: each candidate
-// is timed with events over a few launches on the (zeroed) workspace, per
-// Chebyshev step.  Small meshes favour small tiles (more blocks in flight),
-// large meshes large ones (less halo recomputation); two steps per launch
-// trade a wider halo for half the launches.
+// is timed with events on zeroed vectors, per Chebyshev step over a few
+// launches, or, where the pressure solve runs beside the velocity V-cycle,
+// per application of the whole preconditioner (a variant that is faster
+// alone can hold more of the CUs the V-cycle shares).  Small meshes favour
+// small tiles (more blocks in flight), large meshes large ones (less halo
+// recomputation); two steps per launch trade a wider halo for half the
+// launches.
 Problem::MqVariant Problem::tune_mq_variant(int batch) {
   const size_t bytes = (size_t)max_batch * (g.nk + g.n0) * (mixed ? sizeof(float) : sizeof(double));
   ETH_HIP(hipMemsetAsync(mq_r, 0, bytes, st));
@@ -722,6 +725,7 @@ Problem::MqVariant Problem::tune_mq_variant(int batch) {
   if (cands.empty()) cands.push_back(MqVariant{16, 1});
   std::vector<float> best_ms(cands.size(), 0.0f);
   MqVariant best = cands[0];
+  const MqVariant keep_lo = mq_var_lo, keep_hi = mq_var_hi;   // set per candidate in context
   try {
     auto launch = [&](const MqVariant& v) {
       if (mixed)
@@ -733,17 +737,28 @@ Problem::MqVariant Problem::tune_mq_variant(int batch) {
                                      v.steps == 2 ? (double*)mq_d2 : (double*)mq_d, 0.5, 0.1, 0.5, 0.1,
                                      v.steps, 0, batch, no_gate(), st, v.tile);
     };
+    const bool in_context = pst != nullptr && cands.size() > 1;
+    if (in_context) ETH_HIP(hipMemsetAsync(kv[0], 0, (size_t)ldw * batch * sizeof(double), st));
+    auto unit = [&](const MqVariant& v) {
+      if (in_context) {
+        mq_var_lo = mq_var_hi = v;
+        precond(kv[0], kz[0], ldw, batch, no_gate(), true);
+      } else {
+        launch(v);
+      }
+    };
+    const int warm = in_context ? 3 : 20, reps = in_context ? 5 : 10;
     for (const auto& v : cands)
-      for (int i = 0; i < 20; ++i) launch(v);
+      for (int i = 0; i < warm; ++i) unit(v);
     for (int round = 0; round < 3; ++round)
       for (size_t c = 0; c < cands.size(); ++c) {
         ETH_HIP(hipEventRecord(e0, st));
-        for (int i = 0; i < 10; ++i) launch(cands[c]);
+        for (int i = 0; i < reps; ++i) unit(cands[c]);
         ETH_HIP(hipEventRecord(e1, st));
         ETH_HIP(hipEventSynchronize(e1));
         float ms = 0.0f;
         ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
-        ms /= (float)cands[c].steps;
+        if (!in_context) ms /= (float)cands[c].steps;
         if (round == 0 || ms < best_ms[c]) best_ms[c] = ms;
       }
     size_t bi = 0;
@@ -751,10 +766,14 @@ Problem::MqVariant Problem::tune_mq_variant(int batch) {
       if (best_ms[c] < best_ms[bi]) bi = c;
     best = cands[bi];
   } catch (...) {
+    mq_var_lo = keep_lo;
+    mq_var_hi = keep_hi;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     throw;
   }
+  mq_var_lo = keep_lo;
+  mq_var_hi = keep_hi;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return best;

@@ -223,7 +223,10 @@ __global__ void k_mq_project_out(Geo g, const T* __restrict__ z, double* __restr
 // One Chebyshev step of the pressure-mass solve in a single launch: the
 // symmetric multicolour Gauss-Seidel sweep from z_k (colours 0,1,2,3,4,3,2,1,0)
 // is temporally blocked in LDS.  A block owns TQ x TQ Q1 nodes and the
-// elements with the same lower-left vertex; it stages a region widened by
+// elements with the same lower-left vertex (the last block of a row or column
+// of tiles also owns node n of its rows or columns: its halo on that side
+// lies outside the mesh, so the grid is ceil(n / TQ) blocks per side, 16 x 16
+// = one per CU for n = 256 and TQ = 16); it stages a region widened by
 // HALO nodes, runs the nine colour passes on the whole region (each pass can
 // spread stale halo values inward by one node at most, so the owned part is
 // exact after nine passes) and then forms
@@ -319,6 +322,7 @@ __global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T
   double* o64 = sink.out ? sink.out + (long long)rhs * sink.ld + g.off_pk() : nullptr;
   const T* zi = zin + (long long)rhs * np;
   const int c0 = blockIdx.x * TQ, d0 = blockIdx.y * TQ;
+  const bool last_x = blockIdx.x == gridDim.x - 1, last_y = blockIdx.y == gridDim.y - 1;
   const int gx = c0 - HALO, gy = d0 - HALO;      // global index of local 0
   const double h2 = g.h * g.h;
   const T h2_36 = T(h2 / 36.0), h2_4 = T(0.25 * h2), inv_h2_9 = T(9.0 / h2), inv_h2 = T(1.0 / h2);
@@ -565,7 +569,8 @@ __global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T
     for (int i = 0; i < IQ; ++i) {
       const int k = tid + i * FT, lx = k % RQ, ly = k / RQ;
       const int c = gx + lx, dd = gy + ly;
-      if (k >= RQ * RQ || lx < HALO || lx >= HALO + TQ || ly < HALO || ly >= HALO + TQ || c > n || dd > n)
+      if (k >= RQ * RQ || lx < HALO || (lx >= HALO + TQ && !last_x) || ly < HALO ||
+          (ly >= HALO + TQ && !last_y) || c > n || dd > n)
         continue;
       const int li = par_idx<QW, QS>(lx, ly);
       const long long oq = (long long)dd * (n + 1) + c;
@@ -600,6 +605,17 @@ __global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T
     return;
   }
   // Chebyshev combination on the owned nodes and elements
+  auto finish = [&](long long q, int lo, T zq, T dq, const T* tl, const T* rl) {
+    T dn;
+    const T zn = cheb_combine<T>(tl[lo], zq, dq, ta, tb, first, dn);
+    if (o64) {
+      o64[q] = sink.scale * (double)zn;
+    } else {
+      dw[q] = dn;
+      zo[q] = zn;
+    }
+    if (r64) rr[q] = rl[lo];
+  };
 #pragma unroll
   for (int i = 0; i < OWN; ++i) {
     const int idx = tid + i * FT, ox = idx % TQ, oy = idx / TQ;
@@ -608,31 +624,29 @@ __global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T
     const int lo = par_idx<QW, QS>(ox + HALO, oy + HALO);
     if (oc <= n && od <= n) {
       const long long oq = (long long)od * (n + 1) + oc;
-      T dn;
       const T zq = PF ? z0q[PF ? i : 0] : (first ? T(0) : zi[oq]);
       const T dq = PF ? d0q[PF ? i : 0] : (first ? T(0) : dr[oq]);
-      const T zn = cheb_combine<T>(tq[lo], zq, dq, ta, tb, first, dn);
-      if (o64) {
-        o64[oq] = sink.scale * (double)zn;
-      } else {
-        dw[oq] = dn;
-        zo[oq] = zn;
-      }
-      if (r64) rr[oq] = rq[lo];
+      finish(oq, lo, zq, dq, tq, rq);
     }
     if (oc < n && od < n) {
       const long long oe = g.nk + (long long)od * n + oc;
-      T dn;
       const T ze = PF ? z0e[PF ? i : 0] : (first ? T(0) : zi[oe]);
       const T de = PF ? d0e[PF ? i : 0] : (first ? T(0) : dr[oe]);
-      const T zn = cheb_combine<T>(te[lo], ze, de, ta, tb, first, dn);
-      if (o64) {
-        o64[oe] = sink.scale * (double)zn;
-      } else {
-        dw[oe] = dn;
-        zo[oe] = zn;
-      }
-      if (r64) rr[oe] = re[lo];
+      finish(oe, lo, ze, de, te, re);
+    }
+  }
+  // node n of the rows / columns of the last tiles (column ox = TQ, row
+  // oy = TQ, their corner), one per thread on the threads the loop above left
+  // idle where there are any (2 TQ + 1 <= FT)
+  if (last_x || last_y) {
+    const int x = (tid + FT - (TQ * TQ) % FT) % FT;
+    const int ox = x < TQ ? TQ : (x < 2 * TQ ? x - TQ : TQ);
+    const int oy = x < TQ ? x : TQ;
+    const int oc = c0 + ox, od = d0 + oy;
+    const bool mine = x < 2 * TQ + 1 && (ox < TQ || last_x) && (oy < TQ || last_y) && oc <= n && od <= n;
+    if (mine) {
+      const long long oq = (long long)od * (n + 1) + oc;
+      finish(oq, par_idx<QW, QS>(ox + HALO, oy + HALO), first ? T(0) : zi[oq], first ? T(0) : dr[oq], tq, rq);
     }
   }
 }
@@ -721,7 +735,7 @@ void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, const T* di
   const MqSink k = sink ? *sink : MqSink{};
 #define ETH_MQF(TQ, ST)                                                                                \
   hipLaunchKernelGGL((k_mq_cheb_fused<T, TQ, ST>),                                                    \
-                     dim3((g.n + 1 + TQ - 1) / TQ, (g.n + 1 + TQ - 1) / TQ, batch),                   \
+                     dim3((g.n + TQ - 1) / TQ, (g.n + TQ - 1) / TQ, batch),                           \
                      dim3(MqTile<TQ, ST>::FT), 0, st, g, r, zin, zout, din, dout, a, b, a2, b2, first, \
                      gate, s, k)
   if (steps == 2) {
