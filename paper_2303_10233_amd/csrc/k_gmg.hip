@@ -68,36 +68,80 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
   const long long po = (long long)plane * g.nv;
   const int I0 = blockIdx.x * NX, J0 = blockIdx.y * NY;
   const int tid = threadIdx.x;
+  // a thread takes four consecutive rows of one column: the x-direction sums
+  // (K and M rows of its column parity) of each of the eight staged rows
+  // they touch are formed once and shared by the rows above and below, five
+  // LDS loads per staged row instead of twenty-five per node (the sums are
+  // those of lap90, in the same order).  Its b and x_prev values are loaded
+  // with the staging, before the barrier.
+  constexpr int RPT = NY / 4;             // rows per thread
+  const int tx = tid & 63, ty = tid >> 6;
+  const int I = I0 + tx, Jt = J0 + RPT * ty;
+  T bv[RPT], pv[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int J = Jt + r;
+    bv[r] = pv[r] = T(0);
+    if (I > 0 && J > 0 && I < top && J < top) {
+      const long long o = po + (long long)J * nq + I;
+      bv[r] = b[o];
+      if (has_prev == 1) pv[r] = xo[o];
+    }
+  }
   stage1<NT, HX * HY>(s, tid, [&](int k, T& v) {
     const int I = I0 + k % HX - 2, J = J0 + k / HX - 2;
     if (I >= 0 && I <= top && J >= 0 && J <= top) v = x[po + (long long)J * nq + I];
   });
   if (off) return;   // uniform per block
   __syncthreads();
-  const int tx = tid & 63, ty = tid >> 6;
-  const int I = I0 + tx;
-  if (I > top) return;
+  if (I > top || Jt > top) return;
   const int pi = I & 1;
+  double kx[5], mx[5];
+  k1row(pi, kx);
+  m1row(pi, mx);
+  double tk[RPT + 4], tm[RPT + 4], xcen[RPT + 4];
+  const int lx = tx + 2;
+  // x-direction sums of staged row RPT * ty + j, formed just before first use
+  auto xsums = [&](int j) {
+    const T* row = s + (RPT * ty + j) * HX + lx - 2;
+    double a = 0.0, c = 0.0;
 #pragma unroll
-  for (int r = 0; r < NY / 4; ++r) {
-    const int J = J0 + ty + 4 * r;
+    for (int q = 0; q < 5; ++q) {
+      const double u = (double)row[q];
+      a += kx[q] * u;
+      c += mx[q] * u;
+      if (q == 2) xcen[j] = u;
+    }
+    tk[j] = a;
+    tm[j] = c;
+  };
+#pragma unroll
+  for (int j = 0; j < 4; ++j) xsums(j);
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int J = Jt + r;
     if (J > top) break;
-    const long long o = po + (long long)J * nq + I;
+    xsums(r + 4);
     double xn = 0.0;
     if (I > 0 && J > 0 && I < top && J < top) {
       const int pj = J & 1;
-      const int lx = tx + 2, ly = ty + 4 * r + 2;
-      const double xc = (double)s[ly * HX + lx];
-      const double res = (double)b[o] - lap90<T, HX>(s, lx, ly, pi, pj) / 90.0;
+      double ky[5], my[5];
+      k1row(pj, ky);
+      m1row(pj, my);
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc += my[q] * tk[r + q] + ky[q] * tm[r + q];
+      const double xc = xcen[r + 2];
+      const double res = (double)bv[r] - acc / 90.0;
       xn = xc + beta * res * (90.0 / diag90(pi, pj));
-      if (has_prev == 1) xn += alpha * (xc - (double)xo[o]);
+      if (has_prev == 1) xn += alpha * (xc - (double)pv[r]);
       else if (has_prev == 2) xn += alpha * xc;
     }
     if (out64) {
       out64[(long long)(plane >> 1) * ld64 + (long long)(plane & 1) * g.nv +
             (long long)J * nq + I] = out_scale * xn;
     } else {
-      xo[o] = (T)xn;
+      xo[po + (long long)J * nq + I] = (T)xn;
     }
   }
 }
@@ -152,17 +196,23 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   const int C0x = blockIdx.x * CT, C0y = blockIdx.y * CT;
   const int F0x = 2 * C0x - 3, F0y = 2 * C0y - 3;     // residual patch origin
   const int tid = threadIdx.x;
-  // fine right-hand side of the residual patch, loaded before anything waits
-  constexpr int RIT = (RF * RF + NT - 1) / NT;
-  T bv[RIT];
+  // The residual patch is computed by RG groups of RF threads: a thread takes
+  // one column and RR consecutive rows, and forms the x-direction sums of
+  // each staged row of its window once (five LDS loads per staged row instead
+  // of twenty-five per node; the sums are those of lap90, in the same order).
+  // Its fine right-hand side values are loaded before anything waits.
+  constexpr int RG = 6, RR = (RF + RG - 1) / RG;
+  static_assert(RF * RG <= NT, "residual groups must fit the block");
+  const int rcol = tid % RF, rgrp = tid / RF, ly0 = rgrp * RR;
+  const bool rt = rgrp < RG;
+  const int Ir = F0x + rcol;
+  T bv[RR];
 #pragma unroll
-  for (int i = 0; i < RIT; ++i) {
-    const int k = tid + i * NT;
+  for (int i = 0; i < RR; ++i) {
+    const int J = F0y + ly0 + i;
     bv[i] = T(0);
-    if (k < RF * RF) {
-      const int I = F0x + k % RF, J = F0y + k / RF;
-      if (I > 0 && I < topf && J > 0 && J < topf) bv[i] = bf[pf + (long long)J * nqf + I];
-    }
+    if (rt && ly0 + i < RF && Ir > 0 && Ir < topf && J > 0 && J < topf)
+      bv[i] = bf[pf + (long long)J * nqf + Ir];
   }
   if constexpr (!RES_GIVEN) {
     stage1<NT, XF * XF>(sx, tid, [&](int k, T& v) {
@@ -172,18 +222,52 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   }
   if (off) return;   // uniform per block
   if constexpr (!RES_GIVEN) __syncthreads();
+  if (rt) {
+    double tk[RES_GIVEN ? 1 : RR + 4], tm[RES_GIVEN ? 1 : RR + 4];
+    double kx[5], mx[5];
+    k1row(Ir & 1, kx);
+    m1row(Ir & 1, mx);
+    // x-direction sums of staged row ly0 + j (rows past the patch feed no
+    // residual row); formed just before first use so that few are live
+    auto xsums = [&](int j) {
+      double a = 0.0, c = 0.0;
+      if (ly0 + j < XF) {
+        const T* row = sx + (ly0 + j) * XF + rcol;
 #pragma unroll
-  for (int i = 0; i < RIT; ++i) {
-    const int k = tid + i * NT;
-    if (k >= RF * RF) break;
-    const int lx = k % RF, ly = k / RF;
-    const int I = F0x + lx, J = F0y + ly;
-    double r = 0.0;
-    if (I > 0 && I < topf && J > 0 && J < topf) {
-      r = (double)bv[i];
-      if constexpr (!RES_GIVEN) r -= lap90<T, XF>(sx, lx + 2, ly + 2, I & 1, J & 1) / 90.0;
+        for (int q = 0; q < 5; ++q) {
+          const double u = (double)row[q];
+          a += kx[q] * u;
+          c += mx[q] * u;
+        }
+      }
+      tk[j] = a;
+      tm[j] = c;
+    };
+    if constexpr (!RES_GIVEN) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xsums(j);
     }
-    sr[k] = r;
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+      const int ly = ly0 + i;
+      if (ly >= RF) break;
+      if constexpr (!RES_GIVEN) xsums(i + 4);
+      const int J = F0y + ly;
+      double r = 0.0;
+      if (Ir > 0 && Ir < topf && J > 0 && J < topf) {
+        r = (double)bv[i];
+        if constexpr (!RES_GIVEN) {
+          double ky[5], my[5];
+          k1row(J & 1, ky);
+          m1row(J & 1, my);
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) acc += my[q] * tk[i + q] + ky[q] * tm[i + q];
+          r -= acc / 90.0;
+        }
+      }
+      sr[ly * RF + rcol] = r;
+    }
   }
   __syncthreads();
   for (int k = tid; k < CT * CT; k += NT) {
@@ -233,28 +317,66 @@ __device__ __forceinline__ int prolong_weights(int F, int* idx, double* w) {
   return 3;
 }
 
-// x_f += P x_c on interior fine nodes
+// x_f += P x_c on interior fine nodes.  A thread takes one fine column I
+// and the four fine rows 4e .. 4e+3 inside coarse element row e: it combines
+// the three coarse rows 2e .. 2e+2 in x once (an even I injects one coarse
+// column, written as three terms with weights (1, 0, 0), so no lane of a wave
+// branches) and forms its four rows from them, so that a fine node costs
+// about two coarse loads instead of up to nine.  The sums are the same
+// expressions in the same order as the one-node-per-thread form.
 template <typename T>
-__global__ void k_prolong_add(Geo gf, Geo gc, const T* __restrict__ xc, T* __restrict__ xf,
-                              Gate gate) {
+__global__ __launch_bounds__(256) void k_prolong_add(Geo gf, Geo gc, const T* __restrict__ xc,
+                                                     T* __restrict__ xf, Gate gate) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  const int e = blockIdx.y * blockDim.y + threadIdx.y;
   const int plane = blockIdx.z;
   if (gate.off(plane >> 1)) return;
-  const int topf = gf.nq - 1;
-  if (I <= 0 || J <= 0 || I >= topf || J >= topf) return;
-  int ix[3], iy[3];
-  double wx[3], wy[3];
-  const int cntx = prolong_weights(I, ix, wx), cnty = prolong_weights(J, iy, wy);
-  const long long pc = (long long)plane * gc.nv;
-  double acc = 0.0;
-  for (int b = 0; b < cnty; ++b) {
-    double t = 0.0;
-    for (int a = 0; a < cntx; ++a) t += wx[a] * (double)xc[pc + (long long)iy[b] * gc.nq + ix[a]];
-    acc += wy[b] * t;
+  const int topf = gf.nq - 1, nce = (gc.nq - 1) / 2;   // coarse elements per side
+  if (I <= 0 || I >= topf || e >= nce) return;
+  int ix0, ix1, ix2;
+  double wx0, wx1, wx2;
+  if ((I & 1) == 0) {
+    ix0 = ix1 = ix2 = I >> 1;
+    wx0 = 1.0; wx1 = 0.0; wx2 = 0.0;
+  } else {
+    const int k = (I - 1) >> 1;
+    if ((k & 1) == 0) {
+      ix0 = k; ix1 = k + 1; ix2 = k + 2;
+      wx0 = 0.375; wx1 = 0.75; wx2 = -0.125;
+    } else {
+      ix0 = k - 1; ix1 = k; ix2 = k + 1;
+      wx0 = -0.125; wx1 = 0.75; wx2 = 0.375;
+    }
   }
-  const long long o = (long long)plane * gf.nv + (long long)J * gf.nq + I;
-  xf[o] = (T)((double)xf[o] + acc);
+  const T* c0 = xc + (long long)plane * gc.nv + (long long)(2 * e) * gc.nq;
+  double t[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const T* row = c0 + (long long)b * gc.nq;
+    double v = 0.0;
+    v += wx0 * (double)row[ix0];
+    v += wx1 * (double)row[ix1];
+    v += wx2 * (double)row[ix2];
+    t[b] = v;
+  }
+  T* f = xf + (long long)plane * gf.nv + (long long)(4 * e) * gf.nq + I;
+  const long long q = gf.nq;
+  // fine row 4e injects coarse row 2e, 4e+2 injects 2e+1; 4e+1 and 4e+3
+  // take (3/8, 3/4, -1/8) and (-1/8, 3/4, 3/8) of rows 2e .. 2e+2
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  a0 += 1.0 * t[0];
+  a1 += 0.375 * t[0];
+  a1 += 0.75 * t[1];
+  a1 += -0.125 * t[2];
+  a2 += 1.0 * t[1];
+  a3 += -0.125 * t[0];
+  a3 += 0.75 * t[1];
+  a3 += 0.375 * t[2];
+  const T f0 = e > 0 ? f[0] : T(0), f1 = f[q], f2 = f[2 * q], f3 = f[3 * q];
+  if (e > 0) f[0] = (T)((double)f0 + a0);   // fine row 0 is the boundary
+  f[q] = (T)((double)f1 + a1);
+  f[2 * q] = (T)((double)f2 + a2);
+  f[3 * q] = (T)((double)f3 + a3);
 }
 
 // Dense solve x = Ainv b on the ni interior nodes of the two planes of one
@@ -649,8 +771,11 @@ template <typename T>
 void launch_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int nplanes, int batch,
                         Gate gate, hipStream_t st) {
   (void)batch;
+  if (gf.nq - 1 != 2 * (gc.nq - 1) || (gc.nq - 1) % 2 != 0)
+    throw std::invalid_argument("prolongation needs a fine level of twice the coarse elements");
+  const int nce = (gc.nq - 1) / 2;
   dim3 block(64, 4);
-  dim3 grid((gf.nq + 63) / 64, (gf.nq + 3) / 4, nplanes);
+  dim3 grid((gf.nq - 1 + 63) / 64, (nce + 3) / 4, nplanes);
   hipLaunchKernelGGL(k_prolong_add<T>, grid, block, 0, st, gf, gc, xc, xf, gate);
   ETH_LAUNCH_CHECK();
 }

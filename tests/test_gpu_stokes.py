@@ -172,8 +172,9 @@ def test_fused_coarse_vcycle_equals_per_level_launches(n, prec, tol, monkeypatch
 def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     """The temporally blocked Chebyshev-SGS kernel (nine colour passes in LDS
     per launch, the input projection folded into the first) reproduces the
-    one-launch-per-colour sweep bit for bit, for every tile side (n + 1 nodes
-    per side leave ragged edge tiles)."""
+    one-launch-per-colour sweep bit for bit, for every tile side: n a multiple
+    of the side (the last tiles of each row and column also own node n), n
+    below it (one tile), and ragged edge tiles."""
     m = Mesh(n)
     r = uniform_vector(m.N, 3 + n)
     r[: 2 * m.nv][System(m).vel_bnd] = 0.0
