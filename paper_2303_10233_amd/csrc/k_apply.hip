@@ -27,6 +27,7 @@ namespace {
 constexpr int AX = 64, AY = 4, RPT = 4;        // threads (x, y); rows per thread
 constexpr int TYN = AY * RPT;                  // 16 velocity rows per tile
 constexpr int NTA = AX * AY;
+static_assert(RPT % 2 == 0, "rows 2m and 2m+1 of a thread share their pressure rows");
 constexpr int UX = AX + 4, UY = TYN + 4;       // velocity patch with halo 2
 constexpr int QX = AX / 2 + 2, QY = TYN / 2 + 2;   // Q1 nodes c0-1 .. c0+AX/2
 constexpr int EXP = AX / 2 + 1, EYP = TYN / 2 + 1;  // elements c0-1 .. c0+AX/2-1
@@ -141,8 +142,9 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
       mc[a] = pi ? m1c(1, a - 2) : m1c(0, a - 2);
     }
     double tK[2][RPT + 4], tM[2][RPT + 4];
-#pragma unroll
-    for (int r = 0; r < RPT + 4; ++r) {
+    // x-direction sums of patch row lr0 + r, formed just before first use
+    // so that few of them are live at once
+    auto xsums = [&](int r) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         double sk = 0.0, sm = 0.0;
@@ -155,11 +157,29 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
         tK[c][r] = sk;
         tM[c][r] = sm;
       }
-    }
+    };
+#pragma unroll
+    for (int r = 0; r < 4; ++r) xsums(r);
     const int ex = I >> 1, lq = ex - (c0 - 1);   // local Q1 / element column of the node
+    double pq[3][3], pz[2][2];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
+      xsums(r + 4);
       const int J = J0 + lr0 + r;
+      // rows 2m and 2m+1 share ey = J / 2 (J0 + lr0 is a multiple of 4):
+      // their Q1 rows ey-1..ey+1 and P0 rows ey-1, ey are copied once (in
+      // the patches whatever J is)
+      const int lqy = (J >> 1) - (d0 - 1);
+      if ((r & 1) == 0) {
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd)
+#pragma unroll
+          for (int dc = 0; dc < 3; ++dc) pq[dd][dc] = spk[lqy + dd - 1][lq + dc - 1];
+#pragma unroll
+        for (int df = 0; df < 2; ++df)
+#pragma unroll
+          for (int de = 0; de < 2; ++de) pz[df][de] = sp0[lqy + df - 1][lq + de - 1];
+      }
       if (I > top || J > top) continue;
       const long long o = (long long)J * nq + I;
       if (I == 0 || J == 0 || I == top || J == top) {
@@ -179,13 +199,12 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
       vx *= sA;
       vy *= sA;
       // B^T p: Q1 part (rows ey-1..ey+1 of the Q1 patch) and P0 part
-      const int ey = J >> 1, lqy = ey - (d0 - 1);
       double bx = 0.0, by = 0.0;
 #pragma unroll
       for (int dd = -1; dd <= 1; ++dd)
 #pragma unroll
         for (int dc = -1; dc <= 1; ++dc) {
-          const double p = spk[lqy + dd][lq + dc];
+          const double p = pq[dd + 1][dc + 1];
           bx += G6(pi, dc) * Mq6(pj, dd) * p;
           by += Mq6(pi, dc) * G6(pj, dd) * p;
         }
@@ -194,7 +213,7 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
       for (int df = -1; df <= 0; ++df)
 #pragma unroll
         for (int de = -1; de <= 0; ++de) {
-          const double p = sp0[lqy + df][lq + de];
+          const double p = pz[df + 1][de + 1];
           b0x += g1(pi, de) * m6(pj, df) * p;
           b0y += m6(pi, de) * g1(pj, df) * p;
         }
@@ -208,7 +227,7 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
 #pragma unroll
           for (int aa = 0; aa < 2; ++aa) {
             if (pi == 1 && aa == 0) continue;
-            const int e = ex - 1 + aa, f = ey - 1 + bb;
+            const int e = ex - 1 + aa, f = (J >> 1) - 1 + bb;
             if (e < 0 || e >= n || f < 0 || f >= n) continue;
             const int k = (lqy - 1 + bb) * EXP + (lq - 1 + aa);
             const int li = pi + 2 * (1 - aa), lj = pj + 2 * (1 - bb);
@@ -236,33 +255,39 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
       const double Mx[5] = {0.0, 2.0 * Lx, 1.0 * Lx + 1.0 * Rx, 2.0 * Rx, 0.0};
       const double Gy[5] = {-1.0 * Ly, -4.0 * Ly, 5.0 * Ly - 5.0 * Ry, 4.0 * Ry, 1.0 * Ry};
       const double My[5] = {0.0, 2.0 * Ly, 1.0 * Ly + 1.0 * Ry, 2.0 * Ry, 0.0};
-      double s = 0.0;
+      constexpr double g0[3] = {-1.0, 0.0, 1.0};
+      constexpr double m0[3] = {1.0, 4.0, 1.0};
+      // the P0 row of element (c, d) reads the 3 x 3 corner of the Q1 row's
+      // 5 x 5 window: both come from one pass over the window's rows
+      double s = 0.0, s0 = 0.0;
 #pragma unroll
       for (int q = -2; q <= 2; ++q) {
+        double u0[5], u1[5];
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          u0[o + 2] = su[0][ly + q][lx + o];
+          u1[o + 2] = su[1][ly + q][lx + o];
+        }
         double a1 = 0.0, a2 = 0.0;
 #pragma unroll
         for (int o = -2; o <= 2; ++o) {
-          a1 += Gx[o + 2] * su[0][ly + q][lx + o];
-          a2 += Mx[o + 2] * su[1][ly + q][lx + o];
+          a1 += Gx[o + 2] * u0[o + 2];
+          a2 += Mx[o + 2] * u1[o + 2];
         }
         s += My[q + 2] * a1 + Gy[q + 2] * a2;
+        if (q >= 0) {
+#pragma unroll
+          for (int o = 0; o <= 2; ++o) s0 += g0[o] * m0[q] * u0[o + 2] + m0[o] * g0[q] * u1[o + 2];
+        }
       }
       const double v = sB * s;
       yr[g.off_pk() + (long long)d * (n + 1) + c] = v;
       if constexpr (DOT) acc += v * spk[qd + 1][qc + 1];
-    }
-    if (c < n && d < n) {
-      constexpr double g0[3] = {-1.0, 0.0, 1.0};
-      constexpr double m0[3] = {1.0, 4.0, 1.0};
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q <= 2; ++q)
-#pragma unroll
-        for (int o = 0; o <= 2; ++o)
-          s += g0[o] * m0[q] * su[0][ly + q][lx + o] + m0[o] * g0[q] * su[1][ly + q][lx + o];
-      const double v = sB0 * s;
-      yr[g.off_p0() + (long long)d * n + c] = v;
-      if constexpr (DOT) acc += v * sp0[qd + 1][qc + 1];
+      if (c < n && d < n) {
+        const double v0 = sB0 * s0;
+        yr[g.off_p0() + (long long)d * n + c] = v0;
+        if constexpr (DOT) acc += v0 * sp0[qd + 1][qc + 1];
+      }
     }
   }
   if constexpr (DOT) {
