@@ -347,7 +347,15 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="only the launches read by the rocprofv3 byte counters (see counters_run)")
     ap.add_argument("--mq-tile", type=int, default=16, help="tile side of the fused M_Q step in --counters")
+    ap.add_argument("--mq-variant", default="auto",
+                    help="fused M_Q step of the headline solves as TILExSTEPS (e.g. 16x1), or auto (set-up "
+                         "timing); a profiler serialises the two preconditioner branches, so a profiled run "
+                         "fixes the variant the unprofiled run picks")
     args = ap.parse_args()
+    mq_kw = {}
+    if args.mq_variant != "auto":
+        t, st = args.mq_variant.lower().split("x")
+        mq_kw = dict(mq_tile=int(t), mq_fuse_steps=int(st))
     if args.counters:
         counters_run(args.n, args.profile_reps, args.mq_tile)
         return
@@ -366,7 +374,8 @@ def main():
     problems = {}
     for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
         t0 = time.perf_counter()
-        P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0")
+        P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0",
+                        **mq_kw)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         b = P.assemble_rhs()
