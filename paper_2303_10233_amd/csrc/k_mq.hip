@@ -39,9 +39,16 @@ __device__ __forceinline__ double mq_diag(const Geo& g, long long i) {
 // node has a left/right (lower/upper) element column (row).
 //   (M_Q t)_a = (h^2/36) sum w_x w_y t + (h^2/4) sum_{elements} t_0,
 //   D_aa = h^2 m_x m_y / 9  with m = number of adjacent element columns/rows.
+// The inverse diagonal factor inv_h2_9 / (m_x m_y) of a node, with m_x = Lx +
+// Rx and m_y = Ly + Ry: a division, formed once per node where the node is
+// updated in many passes.
 template <typename T>
-__device__ __forceinline__ T q1_gs_update(T t, T r, const T* tq9, const T* te4, int Lx, int Rx,
-                                          int Ly, int Ry, T h2_36, T h2_4, T inv_h2_9) {
+__device__ __forceinline__ T q1_gs_scale(int Lx, int Rx, int Ly, int Ry, T inv_h2_9) {
+  return inv_h2_9 / T((Lx + Rx) * (Ly + Ry));
+}
+template <typename T>
+__device__ __forceinline__ T q1_gs_update_s(T t, T r, const T* tq9, const T* te4, int Lx, int Rx,
+                                            int Ly, int Ry, T h2_36, T h2_4, T scale) {
   // no fused multiply-adds: the fused and the per-colour kernels must round alike
 #pragma clang fp contract(off)
   const T wx0 = T(Lx), wx1 = T(2 * (Lx + Rx)), wx2 = T(Rx);
@@ -52,7 +59,13 @@ __device__ __forceinline__ T q1_gs_update(T t, T r, const T* tq9, const T* te4, 
   const T qk = (wy0 * s0 + wy1 * s1 + wy2 * s2) * h2_36;
   const T e = (te4[0] * T(Lx * Ly) + te4[1] * T(Rx * Ly)) + (te4[2] * T(Lx * Ry) + te4[3] * T(Rx * Ry));
   const T acc = qk + h2_4 * e;
-  return t + (r - acc) * (inv_h2_9 / T((Lx + Rx) * (Ly + Ry)));
+  return t + (r - acc) * scale;
+}
+template <typename T>
+__device__ __forceinline__ T q1_gs_update(T t, T r, const T* tq9, const T* te4, int Lx, int Rx,
+                                          int Ly, int Ry, T h2_36, T h2_4, T inv_h2_9) {
+  return q1_gs_update_s<T>(t, r, tq9, te4, Lx, Rx, Ly, Ry, h2_36, h2_4,
+                           q1_gs_scale<T>(Lx, Rx, Ly, Ry, inv_h2_9));
 }
 
 // Gauss-Seidel update of one element coefficient: t_0 = r_0/h^2 - (sum of
@@ -479,13 +492,21 @@ __global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T
     }
   __syncthreads();
   constexpr bool CR = Tl::CACHE_R;
-  T qr[4][CR ? CPT : 1], er[4][CR ? EPQ : 1];
+  // with CR the right-hand sides of the thread's nodes are kept in registers
+  // across the passes, with CS also their inverse diagonal factors (not for
+  // FP64 32 x 32 tiles, whose 1024 threads have no registers to spare)
+  constexpr bool CS = CR && !(sizeof(T) == 8 && TQ >= 32);
+  T qr[4][CR ? CPT : 1], er[4][CR ? EPQ : 1], qsc[4][CS ? CPT : 1];
   if constexpr (CR) {
 #pragma unroll
     for (int colour = 0; colour < 4; ++colour)
 #pragma unroll
-      for (int j = 0; j < CPT; ++j)
-        qr[colour][j] = qb[colour][j] >= 0 ? rq[colour * QS + (qb[colour][j] & 0xffff)] : T(0);
+      for (int j = 0; j < CPT; ++j) {
+        const int v = qb[colour][j];
+        qr[colour][j] = v >= 0 ? rq[colour * QS + (v & 0xffff)] : T(0);
+        if constexpr (CS)
+          qsc[colour][j] = q1_gs_scale<T>((v >> 16) & 1, (v >> 17) & 1, (v >> 18) & 1, (v >> 19) & 1, inv_h2_9);
+      }
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -514,8 +535,10 @@ __global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T
 #pragma unroll
           for (int aa = 0; aa < 2; ++aa) e4[bb * 2 + aa] = te[base + par_off<QW, QS>(px, py, aa - 1, bb - 1)];
         const int li = base + par_off<QW, QS>(px, py, 0, 0);
-        tq[li] = q1_gs_update<T>(q9[4], CR ? qr[colour][CR ? j : 0] : rq[li], q9, e4, (v >> 16) & 1,
-                                 (v >> 17) & 1, (v >> 18) & 1, (v >> 19) & 1, h2_36, h2_4, inv_h2_9);
+        const int Lx = (v >> 16) & 1, Rx = (v >> 17) & 1, Ly = (v >> 18) & 1, Ry = (v >> 19) & 1;
+        const T sc = CS ? qsc[colour][CS ? j : 0] : q1_gs_scale<T>(Lx, Rx, Ly, Ry, inv_h2_9);
+        tq[li] = q1_gs_update_s<T>(q9[4], CR ? qr[colour][CR ? j : 0] : rq[li], q9, e4, Lx, Rx, Ly, Ry, h2_36,
+                                   h2_4, sc);
       }
     } else {
 #pragma unroll
