@@ -47,19 +47,25 @@ __device__ __forceinline__ T q1_gs_scale(int Lx, int Rx, int Ly, int Ry, T inv_h
   return inv_h2_9 / T((Lx + Rx) * (Ly + Ry));
 }
 template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+template <typename T>
 __device__ __forceinline__ T q1_gs_update_s(T t, T r, const T* tq9, const T* te4, int Lx, int Rx,
                                             int Ly, int Ry, T h2_36, T h2_4, T scale) {
-  // no fused multiply-adds: the fused and the per-colour kernels must round alike
+  // every fused multiply-add is written out (and no other contraction is
+  // allowed), so the fused and the per-colour kernels round alike
 #pragma clang fp contract(off)
   const T wx0 = T(Lx), wx1 = T(2 * (Lx + Rx)), wx2 = T(Rx);
   const T wy0 = T(Ly), wy1 = T(2 * (Ly + Ry)), wy2 = T(Ry);
-  const T s0 = wx0 * tq9[0] + wx1 * tq9[1] + wx2 * tq9[2];
-  const T s1 = wx0 * tq9[3] + wx1 * tq9[4] + wx2 * tq9[5];
-  const T s2 = wx0 * tq9[6] + wx1 * tq9[7] + wx2 * tq9[8];
-  const T qk = (wy0 * s0 + wy1 * s1 + wy2 * s2) * h2_36;
-  const T e = (te4[0] * T(Lx * Ly) + te4[1] * T(Rx * Ly)) + (te4[2] * T(Lx * Ry) + te4[3] * T(Rx * Ry));
-  const T acc = qk + h2_4 * e;
-  return t + (r - acc) * scale;
+  const T s0 = fma_t(wx2, tq9[2], fma_t(wx1, tq9[1], wx0 * tq9[0]));
+  const T s1 = fma_t(wx2, tq9[5], fma_t(wx1, tq9[4], wx0 * tq9[3]));
+  const T s2 = fma_t(wx2, tq9[8], fma_t(wx1, tq9[7], wx0 * tq9[6]));
+  const T qk = fma_t(wy2, s2, fma_t(wy1, s1, wy0 * s0)) * h2_36;
+  const T e = fma_t(te4[1], T(Rx * Ly), te4[0] * T(Lx * Ly)) + fma_t(te4[3], T(Rx * Ry), te4[2] * T(Lx * Ry));
+  const T acc = fma_t(h2_4, e, qk);
+  return fma_t(r - acc, scale, t);
 }
 template <typename T>
 __device__ __forceinline__ T q1_gs_update(T t, T r, const T* tq9, const T* te4, int Lx, int Rx,
