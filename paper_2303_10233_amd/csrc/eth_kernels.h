@@ -161,7 +161,7 @@ void launch_mq_cheb_combine(const Geo& g, T* t, T* z, T* d, double a, double b, 
 struct MqSource {
   const double* r;     // full FP64 vectors (pressure part at off_pk), null: none
   long long ld;
-  const double* coef;  // [batch] coefficient of k removed from r
+  const double* coef;  // [batch] coefficient of k removed from r, null: none
 };
 struct MqSink {
   double* out;         // full FP64 vectors (pressure part at off_pk), null: none

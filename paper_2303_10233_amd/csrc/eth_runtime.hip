@@ -194,7 +194,7 @@ struct Problem {
   MqVariant tune_mq_variant(int batch);
   template <typename T>
   void mq_chain(const MqVariant& v, T* rr, T* zz, T* tt, const double* r, long long ld, double* z,
-                double scale, bool sink_out, int batch, Gate gate);
+                double scale, bool sink_out, bool project_in, int batch, Gate gate);
   ScaleState* d_scale = nullptr;     // [4] scale epilogue states
 
   // Krylov workspace
@@ -786,7 +786,7 @@ Problem::MqVariant Problem::tune_mq_variant(int batch) {
 // sink_out the last one writes scale * z to the FP64 vectors instead of zz.
 template <typename T>
 void Problem::mq_chain(const MqVariant& v, T* rr, T* zz, T* tt, const double* r, long long ld, double* z,
-                       double scale, bool sink_out, int batch, Gate gate) {
+                       double scale, bool sink_out, bool project_in, int batch, Gate gate) {
   const int m = d.mq_steps;
   std::vector<int> per;   // Chebyshev steps of each launch
   for (int k = 0; k < m;) {
@@ -798,7 +798,7 @@ void Problem::mq_chain(const MqVariant& v, T* rr, T* zz, T* tt, const double* r,
   T* zb[2] = {zz, tt};
   T* db[2] = {static_cast<T*>(mq_d), static_cast<T*>(mq_d2)};
   int zc = nl & 1, dc = 0;   // launch i reads zb[zc], writes zb[zc ^ 1]; zb[nl parity] ends in zz
-  const MqSource src{r, ld, mq_coef};
+  const MqSource src{r, ld, project_in ? mq_coef : nullptr};
   const MqSink sink{z, ld, scale};
   int k = 0;
   for (int i = 0; i < nl; ++i) {
@@ -869,6 +869,11 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
 // vectors whose pressure part is orthogonal to k (the pressure rows of K
 // produce B u, and k^T B = 0), so every MINRES scalar is the same, and the k
 // component that x picks up is removed with the pressure means at the end.
+// For the same reason the fused path then also leaves out the input
+// projection: the residual it is applied to is orthogonal to k already
+// (b's pressure part is -B u_B, K's pressure rows are B u), so the
+// projection would only remove rounding, at the price of a reduction and
+// its finishing launch on the critical branch.
 template <typename T>
 void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate gate, double scale,
                       bool project_out) {
@@ -879,7 +884,8 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
   const long long np = (long long)g.nk + g.n0;
   const int nbk = dot_blocks(np);
   RedCtx rin = red(nbk, 1, EPI_SCALE, &d_scale[1]);
-  launch_mq_kdot<double>(g, r, ld, g.off_pk(), batch, rin, gate, st);
+  const bool project_in = project_out || !fused_mq;
+  if (project_in) launch_mq_kdot<double>(g, r, ld, g.off_pk(), batch, rin, gate, st);
   if (fused_mq) {
     // ping-pong between mq_z and mq_t; the result ends in zz
     // step k reads zb[k&1] and writes zb[(k+1)&1]; the last step must write zz.
@@ -888,7 +894,7 @@ void Problem::mq_cheb(const double* r, double* z, long long ld, int batch, Gate 
     // kernel of its own: reduced by the fused step, its summation order would
     // follow the tile side, which set-up picks by timing, and results would
     // then differ in the last bits between otherwise identical problems.
-    mq_chain<T>(mq_variant_for(batch), rr, zz, tt, r, ld, z, scale, !project_out, batch, gate);
+    mq_chain<T>(mq_variant_for(batch), rr, zz, tt, r, ld, z, scale, !project_out, project_in, batch, gate);
     if (!project_out) return;   // the last step wrote scale * z to the output
   } else {
     launch_mq_project_in<T>(g, r, ld, rr, zz, tt, dd, batch, mq_coef, gate, st);

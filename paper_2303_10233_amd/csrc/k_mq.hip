@@ -308,7 +308,7 @@ __host__ __device__ constexpr int par_off(int px, int py, int dx, int dy) {
 }
 
 // src (first step only, may be null): take r from the FP64 vectors, projected
-// on k^perp as r - coef k, and store it to the workspace r (owned entries) for
+// on k^perp as r - coef k (coef null: as it is), and store it to the workspace r (owned entries) for
 // the later steps.  sink (last step only, may be null): write scale z_{k+1}
 // straight to the pressure part of the FP64 vectors instead of the workspace.
 // din / dout: the Chebyshev direction d before and after (the same array for
@@ -337,7 +337,7 @@ __global__ __launch_bounds__((MqTile<TQ, ST>::FT)) void k_mq_cheb_fused(Geo g, T
   const long long np = (long long)g.nk + g.n0;
   T* rr = r + (long long)rhs * np;
   const double* r64 = src.r ? src.r + (long long)rhs * src.ld + g.off_pk() : nullptr;
-  const double cf = src.r ? src.coef[rhs] : 0.0;
+  const double cf = (src.r && src.coef) ? src.coef[rhs] : 0.0;
   double* o64 = sink.out ? sink.out + (long long)rhs * sink.ld + g.off_pk() : nullptr;
   const T* zi = zin + (long long)rhs * np;
   const int c0 = blockIdx.x * TQ, d0 = blockIdx.y * TQ;
