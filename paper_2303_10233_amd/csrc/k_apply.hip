@@ -52,7 +52,7 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
                                                ClearFlag clear) {
   __shared__ double su[2][UY][UX];
   __shared__ double sw[CONV ? 2 : 1][CONV ? UY : 1][CONV ? UX : 1];
-  __shared__ double sN[CONV ? 2 : 1][CONV ? EXP * EYP : 1][9];
+  __shared__ double sc[CONV ? 2 : 1][CONV ? UY : 1][CONV ? UX : 1];   // N(w) u (or N(w)^T u) per patch node
   __shared__ double spk[QY][QX];
   __shared__ double sp0[EYP][EXP];
   __shared__ double sred[NTA / 64];
@@ -94,35 +94,45 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
     const int e = c0 - 1 + k % EXP, f = d0 - 1 + k / EXP;
     if (e >= 0 && e < n && f >= 0 && f < n) v = xr[g.off_p0() + (long long)f * n + e];
   });
+  if constexpr (CONV) {
+    for (int k = tid; k < 2 * UY * UX; k += NTA) (&sc[0][0][0])[k] = 0.0;
+  }
   if (off) return;   // uniform per block; the gate load overlapped the staging loads
   __syncthreads();
 
   if constexpr (CONV) {
-    // elements (c0-1 .. c0+AX/2-1) x (d0-1 .. d0+TYN/2-1)
-    for (int k = tid; k < EXP * EYP; k += NTA) {
-      const int lex = k % EXP, ley = k / EXP;
-      const int e = c0 - 1 + lex, f = d0 - 1 + ley;
-      if (e < 0 || e >= n || f < 0 || f >= n) continue;
-      double ul[2][3][3], wl[2][3][3], ol[2][3][3];
-      const int bx = 2 * lex, by = 2 * ley;   // local index of node (2e, 2f)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
+    // elements (c0-1 .. c0+AX/2-1) x (d0-1 .. d0+TYN/2-1) in four classes by
+    // the parity of their local index: elements of one class share no node,
+    // so each adds its nine values to the node accumulator without conflict,
+    // and the classes follow one another (a fixed summation order per node).
+    // One thread per element and velocity component.
+#pragma unroll 1
+    for (int cl = 0; cl < 4; ++cl) {
+      const int qx = cl & 1, qy = cl >> 1;
+      const int cxn = (EXP - qx + 1) / 2, cyn = (EYP - qy + 1) / 2, cnt = cxn * cyn;
+      for (int m = tid; m < 2 * cnt; m += NTA) {
+        const int c = m / cnt, idx = m % cnt;
+        const int lex = qx + 2 * (idx % cxn), ley = qy + 2 * (idx / cxn);
+        const int e = c0 - 1 + lex, f = d0 - 1 + ley;
+        if (e < 0 || e >= n || f < 0 || f >= n) continue;
+        const int bx = 2 * lex, by = 2 * ley;   // local index of node (2e, 2f)
+        double wl[2][3][3], ul[3][3], ol[3][3];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            ul[c][j][i] = su[c][by + j][bx + i];
-            wl[c][j][i] = sw[c][by + j][bx + i];
+            wl[0][j][i] = sw[0][by + j][bx + i];
+            wl[1][j][i] = sw[1][by + j][bx + i];
+            ul[j][i] = su[c][by + j][bx + i];
           }
-      element_convection<TRANS>(ul, wl, g.h, ol);
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
+        element_convection1<double, double, TRANS>(ul, wl, g.h, ol);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-          for (int i = 0; i < 3; ++i) sN[c][k][3 * j + i] = ol[c][j][i];
+          for (int i = 0; i < 3; ++i) sc[c][by + j][bx + i] += ol[j][i];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   const double h = g.h;
@@ -220,23 +230,8 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
       vx += sB * bx + sB0 * b0x;
       vy += sB * by + sB0 * b0y;
       if constexpr (CONV) {
-        double cx = 0.0, cy = 0.0;
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb) {
-          if (pj == 1 && bb == 0) continue;
-#pragma unroll
-          for (int aa = 0; aa < 2; ++aa) {
-            if (pi == 1 && aa == 0) continue;
-            const int e = ex - 1 + aa, f = (J >> 1) - 1 + bb;
-            if (e < 0 || e >= n || f < 0 || f >= n) continue;
-            const int k = (lqy - 1 + bb) * EXP + (lq - 1 + aa);
-            const int li = pi + 2 * (1 - aa), lj = pj + 2 * (1 - bb);
-            cx += sN[0][k][3 * lj + li];
-            cy += sN[1][k][3 * lj + li];
-          }
-        }
-        vx += cx;
-        vy += cy;
+        vx += sc[0][lr0 + r + 2][lx];
+        vy += sc[1][lr0 + r + 2][lx];
       }
       yr[o] = vx;
       yr[g.nv + o] = vy;
