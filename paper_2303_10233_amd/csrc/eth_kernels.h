@@ -195,7 +195,7 @@ void launch_to_float(const double* a, float* f, long long n, hipStream_t st);
 // damped Jacobi step on F = nu A + N(w) (residual != 0: write b - F x instead;
 // transpose != 0: F^T)
 template <typename T>
-void launch_cd_step(const Geo& g, const double* wind, const double* dF, double nu, const T* b,
+void launch_cd_step(const Geo& g, const T* wind, const double* dF, double nu, const T* b,
                     const T* x, T* out, double omega, int residual, int nplanes, double* out64,
                     long long ld64, double out_scale, Gate gate, hipStream_t st, int transpose = 0);
 // at = a^T for a dense ni x ni matrix

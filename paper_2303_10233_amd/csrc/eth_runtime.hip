@@ -217,6 +217,17 @@ struct Problem {
   double* f_work = nullptr;                 // blocked Gauss-Jordan workspace of the coarse F
   double* pic_b = nullptr;                  // right-hand side of a Picard step (N)
   std::vector<double*> lwind, ldF;          // wind and diag(F) per velocity level
+  std::vector<float*> lwindF;               // FP32 copy of each level's wind (mixed precision)
+  // the wind of level l in the smoother's storage type
+  template <typename T>
+  const T* level_wind(int l) const {
+    if constexpr (sizeof(T) == 4) {
+      if (!lwindF[l]) throw std::logic_error("FP32 wind copy missing");
+      return lwindF[l];
+    } else {
+      return lwind[l];
+    }
+  }
   std::vector<Geo> qlv;                     // Q1 levels of the A_p multigrid
   std::vector<double> qlam;
   std::vector<std::vector<double>> qca, qcb;
@@ -1398,9 +1409,11 @@ void Problem::build_oseen_velocity() {
   lwind.assign(L, nullptr);
   ldF.assign(L, nullptr);
   lwind[0] = wind0;
+  lwindF.assign(L, nullptr);
   for (int l = 0; l < L; ++l) {
     if (l > 0) lwind[l] = alloc<double>(2 * (size_t)lv[l].nv);
     ldF[l] = alloc<double>(lv[l].nv);
+    if (mixed) lwindF[l] = alloc<float>(2 * (size_t)lv[l].nv);
   }
   const Geo& gc = lv.back();
   coarse_ni = (gc.nq - 2) * (gc.nq - 2);
@@ -1440,6 +1453,9 @@ void Problem::refresh_wind() {
   for (int l = 0; l < L; ++l) {
     if (l > 0) launch_inject_wind(g, lv[l], wind0, lwind[l], st);
     launch_cd_diag(lv[l], lwind[l], d.nu, ldF[l], st);
+    // the FP32 smoother rounds the wind to FP32 as it stages it: a rounded
+    // copy gives the same values at half the bytes
+    if (lwindF[l]) launch_to_float(lwind[l], lwindF[l], 2LL * lv[l].nv, st);
   }
   const int ni = coarse_ni;
   launch_fill((long long)ni * ni, 0.0, Ainv, 0, 1, st);
@@ -1563,11 +1579,11 @@ void Problem::vcycle_F(const double* r, const double* sub, double* z, long long 
   launch_vcycle_entry<T>(lv[0], r, ld, b[0], x[0], 0.0, batch, gate, st, sub);   // x = 0
   for (int l = 0; l + 1 < L; ++l) {
     for (int k = 0; k < deg; ++k) {
-      launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np, nullptr, 0, 0.0,
+      launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np, nullptr, 0, 0.0,
                         gate, st, tr);
       std::swap(x[l], xo[l]);
     }
-    launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 1, np, nullptr, 0, 0.0,
+    launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], d.nu, b[l], x[l], xo[l], om, 1, np, nullptr, 0, 0.0,
                       gate, st, tr);
     launch_restrict<T>(lv[l], lv[l + 1], xo[l], nullptr, b[l + 1], x[l + 1], 0.0, np, batch, gate, st);
   }
@@ -1582,7 +1598,7 @@ void Problem::vcycle_F(const double* r, const double* sub, double* z, long long 
     launch_prolong_add<T>(lv[l], lv[l + 1], x[l + 1], x[l], np, batch, gate, st);
     for (int k = 0; k < deg; ++k) {
       const bool last = (l == 0 && k == deg - 1);
-      launch_cd_step<T>(lv[l], lwind[l], ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np,
+      launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np,
                         last ? z : nullptr, ld, 1.0, gate, st, tr);
       if (!last) std::swap(x[l], xo[l]);
     }
@@ -2495,7 +2511,7 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
         const eth::Geo& gf = P.lv[0];
         launch = [&] {
           if (P.mixed)
-            eth::launch_cd_step<float>(gf, P.lwind[0], P.ldF[0], P.d.nu, (float*)P.vb[0], (float*)P.vx[0],
+            eth::launch_cd_step<float>(gf, P.level_wind<float>(0), P.ldF[0], P.d.nu, (float*)P.vb[0], (float*)P.vx[0],
                                        (float*)P.vxo[0], P.d.gmg_omega, 0, 2 * B, nullptr, 0, 0.0, gate,
                                        P.st);
           else

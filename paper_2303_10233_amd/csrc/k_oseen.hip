@@ -127,9 +127,10 @@ __global__ void k_dense_convdiff(Geo g, const double* __restrict__ wind, double 
 // the velocity part of FP64 vectors instead.  TRANS: F^T = nu A + N^T (same
 // diagonal).
 // The element convection and the stencil sums run in the storage type T
-// (FP32 in the mixed-precision preconditioner).
+// (FP32 in the mixed-precision preconditioner), and the wind comes in T too
+// (the level's wind rounded once at set-up).
 template <typename T, int MODE, bool TRANS>
-__global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict__ wind,
+__global__ __launch_bounds__(NT) void k_cd_step(Geo g, const T* __restrict__ wind,
                                                 const double* __restrict__ dF, double nu,
                                                 const T* __restrict__ b, const T* __restrict__ x,
                                                 T* __restrict__ out, double omega,
@@ -177,6 +178,26 @@ __global__ __launch_bounds__(NT) void k_cd_step(Geo g, const double* __restrict_
   __syncthreads();
   const int ex = ex0 + tx, ey = ey0 + ty;
   if (ex > n || ey > n) return;
+  // a value of boundary node (I, J): zero (the residual and the step are zero there)
+  auto write_zero = [&](int I, int J) {
+    if (I > top || J > top) return;
+    const long long o = (long long)J * nq + I;
+    if constexpr (MODE == 1) out[po + o] = T(0);
+    else if (out64) out64[(long long)(plane >> 1) * ld64 + (long long)(plane & 1) * g.nv + o] = 0.0;
+    else out[po + o] = T(0);
+  };
+  // the grid covers elements 0 .. n-1 (ceil(n / TX) x ceil(n / TY) tiles);
+  // where no tile reaches ex = n (or ey = n), the last element column (row)
+  // also writes boundary node column (row) 2n
+  if (ex == n - 1 && n % TX == 0) {
+    write_zero(top, 2 * ey);
+    write_zero(top, 2 * ey + 1);
+    if (ey == n - 1 && n % TY == 0) write_zero(top, top);
+  }
+  if (ey == n - 1 && n % TY == 0) {
+    write_zero(2 * ex, top);
+    write_zero(2 * ex + 1, top);
+  }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
 #pragma unroll
@@ -566,10 +587,10 @@ void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* 
   ETH_LAUNCH_CHECK();
 }
 template <typename T>
-void launch_cd_step(const Geo& g, const double* wind, const double* dF, double nu, const T* b,
+void launch_cd_step(const Geo& g, const T* wind, const double* dF, double nu, const T* b,
                     const T* x, T* out, double omega, int residual, int nplanes, double* out64,
                     long long ld64, double out_scale, Gate gate, hipStream_t st, int transpose) {
-  dim3 grid((g.n + 1 + TX - 1) / TX, (g.n + 1 + TY - 1) / TY, nplanes);
+  dim3 grid((g.n + TX - 1) / TX, (g.n + TY - 1) / TY, nplanes);
   auto kern = residual ? (transpose ? k_cd_step<T, 1, true> : k_cd_step<T, 1, false>)
                        : (transpose ? k_cd_step<T, 0, true> : k_cd_step<T, 0, false>);
   hipLaunchKernelGGL(kern, grid, dim3(TX, TY), 0, st, g, wind, dF, nu, b, x, out, omega, out64, ld64,
@@ -653,7 +674,7 @@ void launch_q1_dense_solve(const double* Ainv, int ni, const T* b, T* x, int bat
 }
 
 #define ETH_INST(T)                                                                                  \
-  template void launch_cd_step<T>(const Geo&, const double*, const double*, double, const T*, const T*, \
+  template void launch_cd_step<T>(const Geo&, const T*, const double*, double, const T*, const T*, \
                                   T*, double, int, int, double*, long long, double, Gate, hipStream_t, \
                                   int);                                                               \
   template void launch_q1mass_cheb<T>(const Geo&, const T*, const T*, T*, double, double, int, int,    \

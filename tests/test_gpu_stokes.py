@@ -168,7 +168,8 @@ def test_fused_coarse_vcycle_equals_per_level_launches(n, prec, tol, monkeypatch
     assert np.array_equal(z_fused[o:], z_ref[o:])
 
 
-@pytest.mark.parametrize("n,prec", [(16, eth.FP64), (66, eth.FP64), (64, eth.MIXED), (132, eth.MIXED)])
+@pytest.mark.parametrize("n,prec", [(8, eth.FP64), (16, eth.FP64), (66, eth.FP64), (12, eth.MIXED),
+                                    (64, eth.MIXED), (132, eth.MIXED)])
 def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     """The temporally blocked Chebyshev-SGS kernel (nine colour passes in LDS
     per launch, the input projection folded into the first) reproduces the
