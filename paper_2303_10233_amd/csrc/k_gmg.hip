@@ -20,16 +20,19 @@ namespace {
 constexpr int NX = 64, NY = 16, NT = 256;   // smoother tile (nodes), 4 nodes per thread
 constexpr int HX = NX + 4, HY = NY + 4;
 
-__device__ __forceinline__ void k1row(int p, double* k) {
+template <typename A>
+__device__ __forceinline__ void k1row(int p, A* k) {
   if (p == 0) { k[0] = 1; k[1] = -8; k[2] = 14; k[3] = -8; k[4] = 1; }
   else        { k[0] = 0; k[1] = -8; k[2] = 16; k[3] = -8; k[4] = 0; }
 }
-__device__ __forceinline__ void m1row(int p, double* m) {
+template <typename A>
+__device__ __forceinline__ void m1row(int p, A* m) {
   if (p == 0) { m[0] = -1; m[1] = 2; m[2] = 8; m[3] = 2; m[4] = -1; }
   else        { m[0] = 0; m[1] = 2; m[2] = 16; m[3] = 2; m[4] = 0; }
 }
-__device__ __forceinline__ double diag90(int pi, int pj) {
-  return (pi + pj == 0) ? 224.0 : (pi + pj == 1) ? 352.0 : 512.0;
+template <typename A = double>
+__device__ __forceinline__ A diag90(int pi, int pj) {
+  return (pi + pj == 0) ? A(224) : (pi + pj == 1) ? A(352) : A(512);
 }
 
 // 90 * (A u)(node) from a staged patch s (row pitch P), centre at (lx, ly)
@@ -96,18 +99,19 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
   __syncthreads();
   if (I > top || Jt > top) return;
   const int pi = I & 1;
-  double kx[5], mx[5];
+  using A = T;   // arithmetic in the storage type (FP32 in mixed precision)
+  A kx[5], mx[5];
   k1row(pi, kx);
   m1row(pi, mx);
-  double tk[RPT + 4], tm[RPT + 4], xcen[RPT + 4];
+  A tk[RPT + 4], tm[RPT + 4], xcen[RPT + 4];
   const int lx = tx + 2;
   // x-direction sums of staged row RPT * ty + j, formed just before first use
   auto xsums = [&](int j) {
     const T* row = s + (RPT * ty + j) * HX + lx - 2;
-    double a = 0.0, c = 0.0;
+    A a = 0, c = 0;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      const double u = (double)row[q];
+      const A u = (A)row[q];
       a += kx[q] * u;
       c += mx[q] * u;
       if (q == 2) xcen[j] = u;
@@ -117,29 +121,30 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
   };
 #pragma unroll
   for (int j = 0; j < 4; ++j) xsums(j);
+  const A ta = (A)alpha, tb = (A)beta;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int J = Jt + r;
     if (J > top) break;
     xsums(r + 4);
-    double xn = 0.0;
+    A xn = 0;
     if (I > 0 && J > 0 && I < top && J < top) {
       const int pj = J & 1;
-      double ky[5], my[5];
+      A ky[5], my[5];
       k1row(pj, ky);
       m1row(pj, my);
-      double acc = 0.0;
+      A acc = 0;
 #pragma unroll
       for (int q = 0; q < 5; ++q) acc += my[q] * tk[r + q] + ky[q] * tm[r + q];
-      const double xc = xcen[r + 2];
-      const double res = (double)bv[r] - acc / 90.0;
-      xn = xc + beta * res * (90.0 / diag90(pi, pj));
-      if (has_prev == 1) xn += alpha * (xc - (double)pv[r]);
-      else if (has_prev == 2) xn += alpha * xc;
+      const A xc = xcen[r + 2];
+      const A res = (A)bv[r] - acc / A(90);
+      xn = xc + tb * res * (A(90) / diag90<A>(pi, pj));
+      if (has_prev == 1) xn += ta * (xc - (A)pv[r]);
+      else if (has_prev == 2) xn += ta * xc;
     }
     if (out64) {
       out64[(long long)(plane >> 1) * ld64 + (long long)(plane & 1) * g.nv +
-            (long long)J * nq + I] = out_scale * xn;
+            (long long)J * nq + I] = out_scale * (double)xn;
     } else {
       xo[po + (long long)J * nq + I] = (T)xn;
     }
@@ -172,9 +177,10 @@ __global__ void k_vcycle_entry(Geo g, const double* __restrict__ r, const double
 
 // 1-D restriction weight (times 8) of fine offset o in -3..3 for a coarse
 // node of parity p (0 vertex, 1 mid)
-__device__ __forceinline__ double rw8(int p, int o) {
-  if (p == 0) return o == 0 ? 8.0 : (o == 1 || o == -1) ? 3.0 : (o == 3 || o == -3) ? -1.0 : 0.0;
-  return o == 0 ? 8.0 : (o == 1 || o == -1) ? 6.0 : 0.0;
+template <typename A = double>
+__device__ __forceinline__ A rw8(int p, int o) {
+  if (p == 0) return o == 0 ? A(8) : (o == 1 || o == -1) ? A(3) : (o == 3 || o == -3) ? A(-1) : A(0);
+  return o == 0 ? A(8) : (o == 1 || o == -1) ? A(6) : A(0);
 }
 
 constexpr int CT = 16;                  // coarse tile side
@@ -187,8 +193,9 @@ template <typename T, bool RES_GIVEN>
 __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __restrict__ bf,
                                                  const T* __restrict__ xf, T* __restrict__ bc,
                                                  T* __restrict__ xc, double beta_c, Gate gate) {
+  using A = T;   // arithmetic in the storage type (FP32 in mixed precision)
   __shared__ T sx[XF * XF];
-  __shared__ double sr[RF * RF];
+  __shared__ A sr[RF * RF];
   const int plane = blockIdx.z;
   const bool off = gate.off(plane >> 1);   // tested after the staging (overlapped load)
   const int nqf = gf.nq, topf = nqf - 1, nqc = gc.nq, topc = nqc - 1;
@@ -223,19 +230,19 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   if (off) return;   // uniform per block
   if constexpr (!RES_GIVEN) __syncthreads();
   if (rt) {
-    double tk[RES_GIVEN ? 1 : RR + 4], tm[RES_GIVEN ? 1 : RR + 4];
-    double kx[5], mx[5];
+    A tk[RES_GIVEN ? 1 : RR + 4], tm[RES_GIVEN ? 1 : RR + 4];
+    A kx[5], mx[5];
     k1row(Ir & 1, kx);
     m1row(Ir & 1, mx);
     // x-direction sums of staged row ly0 + j (rows past the patch feed no
     // residual row); formed just before first use so that few are live
     auto xsums = [&](int j) {
-      double a = 0.0, c = 0.0;
+      A a = 0, c = 0;
       if (ly0 + j < XF) {
         const T* row = sx + (ly0 + j) * XF + rcol;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          const double u = (double)row[q];
+          const A u = (A)row[q];
           a += kx[q] * u;
           c += mx[q] * u;
         }
@@ -253,17 +260,17 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
       if (ly >= RF) break;
       if constexpr (!RES_GIVEN) xsums(i + 4);
       const int J = F0y + ly;
-      double r = 0.0;
+      A r = 0;
       if (Ir > 0 && Ir < topf && J > 0 && J < topf) {
-        r = (double)bv[i];
+        r = (A)bv[i];
         if constexpr (!RES_GIVEN) {
-          double ky[5], my[5];
+          A ky[5], my[5];
           k1row(J & 1, ky);
           m1row(J & 1, my);
-          double acc = 0.0;
+          A acc = 0;
 #pragma unroll
           for (int q = 0; q < 5; ++q) acc += my[q] * tk[i + q] + ky[q] * tm[i + q];
-          r -= acc / 90.0;
+          r -= acc / A(90);
         }
       }
       sr[ly * RF + rcol] = r;
@@ -282,19 +289,19 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
     }
     const int pi = Ic & 1, pj = Jc & 1;
     const int lx = 2 * cx + 3, ly = 2 * cy + 3;
-    double acc = 0.0;
+    A acc = 0;
 #pragma unroll
     for (int q = -3; q <= 3; ++q) {
-      const double wy = rw8(pj, q);
-      if (wy == 0.0) continue;
-      double t = 0.0;
+      const A wy = rw8<A>(pj, q);
+      if (wy == A(0)) continue;
+      A t = 0;
 #pragma unroll
-      for (int o2 = -3; o2 <= 3; ++o2) t += rw8(pi, o2) * sr[(ly + q) * RF + lx + o2];
+      for (int o2 = -3; o2 <= 3; ++o2) t += rw8<A>(pi, o2) * sr[(ly + q) * RF + lx + o2];
       acc += wy * t;
     }
-    acc *= (1.0 / 64.0);
+    acc *= A(1.0 / 64.0);
     bc[o] = (T)acc;
-    xc[o] = (T)(beta_c * acc * 90.0 / diag90(pi, pj));
+    xc[o] = (T)(A(beta_c) * acc * A(90) / diag90<A>(pi, pj));
   }
 }
 

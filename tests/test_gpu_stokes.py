@@ -249,6 +249,25 @@ def test_concurrent_blocks_equal_serial_preconditioner(prec, monkeypatch):
     assert torch.equal(x1, x2)
 
 
+@pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
+def test_timed_variant_solve_equals_forced_variant(prec):
+    """The fused pressure-mass variant that set-up picks by timing (on whole
+    applications of the concurrent preconditioner) is one of the offered
+    ones, and a problem built with that variant forced solves bit for bit
+    the same."""
+    n = 64
+    A = eth.Problem(n, precision=prec)
+    tile, steps, tile_hi, steps_hi = A.mq_variant()
+    assert (tile, steps) in [(16, 1), (32, 1), (16, 2), (64, 1)]
+    assert steps == 1 or (prec == eth.MIXED and tile == 16)
+    F = eth.Problem(n, precision=prec, mq_tile=tile, mq_fuse_steps=steps)
+    b = A.assemble_rhs()
+    xa, ia = A.solve(b, rtol=1e-8, maxit=500, use_graph=True)
+    xf, jf = F.solve(b, rtol=1e-8, maxit=500, use_graph=True)
+    assert ia[0]["iterations"] == jf[0]["iterations"]
+    assert torch.equal(xa, xf)
+
+
 def test_mq_tile_rejects_unsupported_sides():
     with pytest.raises(Exception):
         eth.Problem(16, mq_tile=24)
