@@ -2519,8 +2519,9 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
                                         (double*)P.vx[0], (double*)P.vxo[0], P.d.gmg_omega, 0, 2 * B,
                                         nullptr, 0, 0.0, gate, P.st);
         };
-        // per plane: read b, x, write x_new; the wind (2 planes) and diag(F) once
-        by = 2.0 * B * 3.0 * es * gf.nv + 24.0 * gf.nv;
+        // per plane: read b, x, write x_new; the wind (2 planes, in the storage
+        // type) and diag(F) (FP64) once
+        by = 2.0 * B * 3.0 * es * gf.nv + (2.0 * es + 8.0) * gf.nv;
         break;
       }
       case ETH_K_GM_MDOT:
