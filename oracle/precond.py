@@ -413,7 +413,9 @@ def oseen_level_operator(fine_mesh, wind, nu):
 class GMGJacobi(GMG):
     """V(nu1, nu2) cycle with damped Jacobi smoothing x <- x + omega D^{-1}(r - A x)
     (suitable for the nonsymmetric convection-diffusion block F); exact solve on
-    the coarsest level."""
+    the coarsest level.  Parity unpinned as a whole (a design of this
+    implementation; the paper uses AMG); pinned by contraction on the Oseen
+    operator and by the two-stage solve reaching the direct solution."""
 
     def __init__(self, mesh, make_op, omega=0.7, sweeps=2, coarse_n=32):
         self.omega, self.sweeps = omega, sweeps
@@ -459,7 +461,9 @@ class ApGMG:
     Chebyshev-Jacobi smoothing ([lo_frac, hi_frac] * lambda_max(D^{-1}A_p)),
     bilinear transfers, re-discretised A_p on every level and the bordered
     (pseudo-inverse) solve on the coarsest level; input and output are
-    projected onto the mean-zero vectors (A_p is singular with the constants)."""
+    projected onto the mean-zero vectors (A_p is singular with the constants).
+    Parity unpinned as a whole (design choices the paper leaves open); pinned
+    by exactness on one level and contraction."""
 
     def __init__(self, mesh, coarse_n=4, degree=2, lo_frac=0.3, hi_frac=1.1, lambdas=None):
         self.ns = gmg_levels(mesh.n, coarse_n)
@@ -497,7 +501,9 @@ class ApGMG:
 class PCDStage1Inexact(PCDStage1):
     """Stage-I PCD with the GPU's inexact pieces: F^{-1} by GMGJacobi,
     Q_1^{-1} by `q1_steps` Chebyshev-Jacobi steps on Wathen's interval
-    [1/4, 9/4], A_p^+ by ApGMG."""
+    [1/4, 9/4], A_p^+ by ApGMG.  Parity unpinned as an operator (its pieces'
+    multigrids are); pinned by the two-stage solve reaching the direct
+    solution."""
 
     def __init__(self, system, velocity_solve, q1_steps=10, ap_kw=None):
         super().__init__(system, velocity_solve=velocity_solve)
@@ -514,7 +520,8 @@ class PCDStage1Inexact(PCDStage1):
 
 
 def oseen_velocity_gmg(system, omega=0.7, sweeps=2, coarse_n=32):
-    """F^{-1} approximation for both velocity components of an Oseen system."""
+    """F^{-1} approximation for both velocity components of an Oseen system
+    (parity unpinned as a whole, see GMGJacobi)."""
     g = GMGJacobi(system.mesh, oseen_level_operator(system.mesh, system.wind, system.nu),
                   omega=omega, sweeps=sweeps, coarse_n=coarse_n)
     m = g.A[0].shape[0]
@@ -541,7 +548,8 @@ class Q1GMG:
     positive semi-definite operator whose null space is the constants (input
     and output projected onto mean-zero vectors): Chebyshev-Jacobi smoothing
     on [lo_frac, hi_frac] * lambda_max(D^{-1} A_l), bilinear transfers and a
-    bordered solve on the coarsest level.  ops[l] is the level-l operator."""
+    bordered solve on the coarsest level.  ops[l] is the level-l operator.
+    Parity unpinned as a whole; pinned by mesh-independent contraction on S_k."""
 
     def __init__(self, meshes, ops, degree=2, lo_frac=0.3, hi_frac=1.1, lambdas=None):
         self.meshes, self.A = meshes, ops
