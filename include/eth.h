@@ -98,11 +98,12 @@ typedef struct {
   int32_t pcd_q1_steps;      /* Chebyshev-Jacobi steps for Q_1^{-1} in PCD (10)     */
   int32_t gmres_restart;     /* largest FGMRES restart length, <= 63 (50)          */
   int32_t mq_tile;           /* ETH_MQ_CHEB_SGS: Q1 nodes per side of the blocks of
-                                the fused Chebyshev step, 16, 32 or 64 (64 with
-                                ETH_MIXED only); 0: the fastest, timed at setup  */
+                                the fused Chebyshev step, 16, 24, 32 or 64 (64
+                                with ETH_MIXED only); 0: the fastest, timed at
+                                setup                                           */
   int32_t mq_fuse_steps;     /* Chebyshev steps per launch, 1 or 2 (2 needs tile
-                                16 and ETH_MIXED); 0: 1 when mq_tile is given,
-                                else timed at setup                             */
+                                16 or 24 and ETH_MIXED); 0: 1 when mq_tile is
+                                given, else timed at setup                      */
 } eth_problem_desc;
 
 typedef struct {

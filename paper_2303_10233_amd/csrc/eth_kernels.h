@@ -153,8 +153,8 @@ template <typename T>
 void launch_mq_cheb_combine(const Geo& g, T* t, T* z, T* d, double a, double b, int first,
                             int batch, Gate gate, hipStream_t st);
 // one fused Chebyshev step (symmetric multicolour SGS sweep from zin + combine)
-// on tiles of tile x tile Q1 nodes (16, 32; 64 in FP32 only), or two steps
-// (steps = 2, coefficients a, b then a2, b2; tile 16, din != dout).  src (first
+// on tiles of tile x tile Q1 nodes (16, 24, 32; 64 in FP32 only), or two steps
+// (steps = 2, coefficients a, b then a2, b2; tile 16 or 24, din != dout).  src (first
 // step, optional): r comes from the FP64 vectors projected by coef and is
 // stored to the workspace r.  sink (last step, optional): the result goes,
 // times scale, to the pressure part of FP64 vectors (zout and d untouched).

@@ -421,13 +421,14 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.pcd_q1_steps <= 0) d.pcd_q1_steps = 10;
   if (d.gmres_restart <= 0) d.gmres_restart = 50;
   if (d.gmres_restart > 63) throw std::invalid_argument("gmres_restart must be <= 63");
-  if (d.mq_tile != 0 && d.mq_tile != 16 && d.mq_tile != 32 && d.mq_tile != 64)
-    throw std::invalid_argument("mq_tile must be 0, 16, 32 or 64");
+  if (d.mq_tile != 0 && d.mq_tile != 16 && d.mq_tile != 24 && d.mq_tile != 32 && d.mq_tile != 64)
+    throw std::invalid_argument("mq_tile must be 0, 16, 24, 32 or 64");
   if (d.mq_tile == 64 && d.precision != ETH_MIXED)
     throw std::invalid_argument("mq_tile 64 needs the FP32 preconditioner");
   if (d.mq_fuse_steps < 0 || d.mq_fuse_steps > 2) throw std::invalid_argument("mq_fuse_steps must be 0, 1 or 2");
-  if (d.mq_fuse_steps == 2 && ((d.mq_tile != 0 && d.mq_tile != 16) || d.precision != ETH_MIXED))
-    throw std::invalid_argument("two Chebyshev steps per launch need mq_tile 16 and ETH_MIXED");
+  if (d.mq_fuse_steps == 2 &&
+      ((d.mq_tile != 0 && d.mq_tile != 16 && d.mq_tile != 24) || d.precision != ETH_MIXED))
+    throw std::invalid_argument("two Chebyshev steps per launch need mq_tile 16 or 24 and ETH_MIXED");
   if (d.gmg_degree <= 0) d.gmg_degree = 2;
   if (d.gmg_lo_frac <= 0.0) d.gmg_lo_frac = 0.3;
   if (d.gmg_hi_frac <= 0.0) d.gmg_hi_frac = 1.1;
@@ -728,10 +729,10 @@ Problem::MqVariant Problem::tune_mq_variant(int batch) {
   // favour the later ones
   std::vector<MqVariant> cands;
   const int fs = d.mq_fuse_steps;
-  for (int t : {16, 32, 64}) {
+  for (int t : {16, 24, 32, 64}) {
     if (t == 64 && !mixed) continue;
     if (fs != 2) cands.push_back(MqVariant{t, 1});
-    if (t == 16 && fs != 1 && d.mq_steps >= 2 && mixed) cands.push_back(MqVariant{t, 2});
+    if ((t == 16 || t == 24) && fs != 1 && d.mq_steps >= 2 && mixed) cands.push_back(MqVariant{t, 2});
   }
   if (cands.empty()) cands.push_back(MqVariant{16, 1});
   std::vector<float> best_ms(cands.size(), 0.0f);

@@ -254,7 +254,7 @@ __global__ void k_mq_project_out(Geo g, const T* __restrict__ z, double* __restr
 // first combination is formed on the whole region (z_k and d held in
 // registers per staged node), the second sweep starts from it, and the
 // owned part is exact after eighteen passes.
-// The tile side TQ (16, 32 or 64) and ST are chosen per problem by timing the
+// The tile side TQ (16, 24, 32 or 64) and ST are chosen per problem by timing the
 // candidates at set-up: small meshes want many blocks, large meshes less
 // halo (the redundancy is ((TQ + 2 HALO) / TQ)^2 per launch).
 // Node updates share q1_gs_update / p0_gs_update with the per-colour kernel,
@@ -290,7 +290,7 @@ struct MqTile {
   static constexpr bool CACHE_R = TQ <= 32;
   static_assert(TQ % 2 == 0, "parity of local and global indices must agree");
   static_assert(QS % 32 == 16, "parity arrays must start on opposite bank halves");
-  static_assert(ST == 1 || TQ == 16, "two steps per launch: 16 x 16 tiles only (and FP32)");
+  static_assert(ST == 1 || TQ == 16 || TQ == 24, "two steps per launch: 16 x 16 or 24 x 24 tiles (and FP32)");
 };
 
 // index in the parity arrays of local node (or element) (x, y)
@@ -757,9 +757,9 @@ void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, const T* di
                           double b, double a2, double b2, int steps, int first, int batch, Gate gate,
                           hipStream_t st, int tile, const MqSource* src, const MqSink* sink) {
   if (tile == 64 && sizeof(T) != 4) throw std::invalid_argument("M_Q tile 64 needs the FP32 preconditioner");
-  if (steps == 2 && (tile != 16 || din == dout))
-    throw std::invalid_argument("two M_Q steps per launch need 16 x 16 tiles and separate d arrays");
-  const int tq = (tile == 16 || tile == 64) ? tile : 32;
+  if (steps == 2 && ((tile != 16 && tile != 24) || din == dout))
+    throw std::invalid_argument("two M_Q steps per launch need 16 x 16 or 24 x 24 tiles and separate d arrays");
+  const int tq = (tile == 16 || tile == 24 || tile == 64) ? tile : 32;
   const MqSource s = src ? *src : MqSource{};
   const MqSink k = sink ? *sink : MqSink{};
 #define ETH_MQF(TQ, ST)                                                                                \
@@ -769,10 +769,16 @@ void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, const T* di
                      gate, s, k)
   if (steps == 2) {
     // FP32 only: z_k and d of every staged entry would not fit FP64 registers
-    if constexpr (sizeof(T) == 4) ETH_MQF(16, 2);
-    else throw std::invalid_argument("two M_Q steps per launch need the FP32 preconditioner");
+    if constexpr (sizeof(T) == 4) {
+      if (tq == 24) ETH_MQF(24, 2);
+      else ETH_MQF(16, 2);
+    } else {
+      throw std::invalid_argument("two M_Q steps per launch need the FP32 preconditioner");
+    }
   } else if (tq == 16) {
     ETH_MQF(16, 1);
+  } else if (tq == 24) {
+    ETH_MQF(24, 1);
   } else if (tq == 64) {
     // the 84^2 + 83^2 staged values of two arrays fit the LDS in FP32 only
     if constexpr (sizeof(T) == 4) ETH_MQF(64, 1);

@@ -51,7 +51,7 @@ def copy_grid(n):
 def mq_grid(n, tile, steps=1):
     """work-items of k_mq_cheb_fused<T, tile, steps> on one right-hand side
     (ceil(n / tile) blocks per side, the last ones owning node n; one thread
-    per entry of a parity array of the staged region for tile 16)"""
+    per entry of a parity array of the staged region for tiles below 32)"""
     qw = tile // 2 + 10 * steps
     threads = 1024 if tile >= 32 else 64 * (-(-qw * qw // 64))
     return (-(-n // tile)) ** 2 * threads

@@ -78,7 +78,7 @@ def test_bench_refuses_more_than_one_gpu():
 def test_counter_grid_matches_the_launch_geometry():
     """traffic.mq_grid must name the work-items of the fused step's launch:
     ceil(n / tile)^2 blocks (the last tiles own node n) of 64 * ceil(QW^2 / 64)
-    threads for 16 x 16 tiles (QW = tile / 2 + 10 * steps) and 1024 threads
+    threads for tiles below 32 (QW = tile / 2 + 10 * steps) and 1024 threads
     for larger tiles."""
     from paper_2303_10233_amd.traffic import mq_grid
     assert mq_grid(256, 16) == 16 * 16 * 384
@@ -86,3 +86,5 @@ def test_counter_grid_matches_the_launch_geometry():
     assert mq_grid(256, 32) == 8 * 8 * 1024
     assert mq_grid(250, 16) == 16 * 16 * 384
     assert mq_grid(257, 64) == 5 * 5 * 1024
+    assert mq_grid(256, 24) == 11 * 11 * 512
+    assert mq_grid(256, 24, 2) == 11 * 11 * 1024

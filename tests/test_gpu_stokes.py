@@ -180,7 +180,7 @@ def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     r = uniform_vector(m.N, 3 + n)
     r[: 2 * m.nv][System(m).vel_bnd] = 0.0
     o = 2 * m.nv
-    tiles = [16, 32] + ([64] if prec == eth.MIXED else [])
+    tiles = [16, 24, 32] + ([64] if prec == eth.MIXED else [])
     z_fused = {}
     for tile in tiles:
         print(f"[fused mq] n={n} prec={prec} tile={tile}", flush=True)
@@ -197,16 +197,17 @@ def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     if prec == eth.MIXED:
         # two Chebyshev steps per launch (halo 20), also with an odd step count
         for steps in (20, 7):
-            print(f"[fused mq] n={n} two steps per launch, mq_steps={steps}", flush=True)
-            monkeypatch.delenv("ETH_DEBUG_UNFUSED_MQ")
-            A2 = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_tile=16, mq_fuse_steps=2,
-                             mq_steps=steps)
-            assert A2.mq_variant()[:2] == (16, 2)
-            z2 = _np(A2.apply_preconditioner(_t(r)))
             monkeypatch.setenv("ETH_DEBUG_UNFUSED_MQ", "1")
             Q2 = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_steps=steps)   # per colour
             zq = _np(Q2.apply_preconditioner(_t(r)))
-            assert np.array_equal(z2[o:], zq[o:]), steps
+            monkeypatch.delenv("ETH_DEBUG_UNFUSED_MQ")
+            for tile in (16, 24):
+                print(f"[fused mq] n={n} two steps per launch, tile {tile}, mq_steps={steps}", flush=True)
+                A2 = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq_tile=tile, mq_fuse_steps=2,
+                                 mq_steps=steps)
+                assert A2.mq_variant()[:2] == (tile, 2)
+                z2 = _np(A2.apply_preconditioner(_t(r)))
+                assert np.array_equal(z2[o:], zq[o:]), (tile, steps)
 
 
 def test_two_steps_per_launch_solve_equals_one():
@@ -258,8 +259,8 @@ def test_timed_variant_solve_equals_forced_variant(prec):
     n = 64
     A = eth.Problem(n, precision=prec)
     tile, steps, tile_hi, steps_hi = A.mq_variant()
-    assert (tile, steps) in [(16, 1), (32, 1), (16, 2), (64, 1)]
-    assert steps == 1 or (prec == eth.MIXED and tile == 16)
+    assert (tile, steps) in [(16, 1), (24, 1), (32, 1), (16, 2), (24, 2), (64, 1)]
+    assert steps == 1 or (prec == eth.MIXED and tile in (16, 24))
     F = eth.Problem(n, precision=prec, mq_tile=tile, mq_fuse_steps=steps)
     b = A.assemble_rhs()
     xa, ia = A.solve(b, rtol=1e-8, maxit=500, use_graph=True)
@@ -270,7 +271,9 @@ def test_timed_variant_solve_equals_forced_variant(prec):
 
 def test_mq_tile_rejects_unsupported_sides():
     with pytest.raises(Exception):
-        eth.Problem(16, mq_tile=24)
+        eth.Problem(16, mq_tile=20)
+    with pytest.raises(Exception):
+        eth.Problem(16, precision=eth.MIXED, mq_tile=64, mq_fuse_steps=2)
     with pytest.raises(Exception):
         eth.Problem(16, precision=eth.FP64, mq_tile=64)
 
