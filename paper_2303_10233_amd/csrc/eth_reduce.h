@@ -1,5 +1,5 @@
 // Deterministic two-stage reductions.  Every block of a reducing kernel
-// stores its block sums; the totals are formed in block order by a small
+// stores its block sums; the totals are formed in a fixed order by a small
 // second kernel (launch_reduce_finish, k_vector.hip) that also runs the
 // epilogue.  A kernel boundary orders the partial sums before their use, so
 // no block waits on another and no device-wide fence is taken per block

@@ -157,18 +157,32 @@ __global__ void k_pressure_shift(Geo g, double* __restrict__ x, long long ld,
   x[(long long)rhs * ld + g.off_pk() + i] -= m;
 }
 
-__global__ __launch_bounds__(NT) void k_reduce_finish(RedCtx rc, Gate gate) {
-  __shared__ double sred[NT / 64];
+// One wave per right-hand side: every lane sums its partials (eight loads in
+// flight per lane and round, a fixed order), then a shuffle reduction; no LDS
+// and no barrier, since this launch sits between two dependent kernels of
+// the Krylov iteration.
+constexpr int FIN_LOADS = 8;
+__global__ __launch_bounds__(kWave) void k_reduce_finish(RedCtx rc, Gate gate) {
   const int rhs = blockIdx.x;
   if (gate.off(rhs)) return;
+  const int lane = threadIdx.x;
   double tot[kMaxRedVals];
   for (int k = 0; k < rc.nvals; ++k) {
     const double* p = rc.partials + ((long long)rhs * rc.nvals + k) * rc.nblocks;
     double a = 0.0;
-    for (int i = threadIdx.x; i < rc.nblocks; i += NT) a += p[i];
-    tot[k] = block_sum<NT>(a, sred);
+    for (int base = 0; base < rc.nblocks; base += kWave * FIN_LOADS) {
+      double v[FIN_LOADS];
+#pragma unroll
+      for (int j = 0; j < FIN_LOADS; ++j) {
+        const int i = base + j * kWave + lane;
+        v[j] = i < rc.nblocks ? p[i] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < FIN_LOADS; ++j) a += v[j];
+    }
+    tot[k] = wave_sum(a);
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     if (rc.result)
       for (int k = 0; k < rc.nvals; ++k) rc.result[(long long)rhs * rc.nvals + k] = tot[k];
     if (rc.epi) run_epilogue(rc.epi, rc.epi_state, rhs, tot);
@@ -181,7 +195,7 @@ inline unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1)
 
 void launch_reduce_finish(const RedCtx& rc, int batch, Gate gate, hipStream_t st) {
   if (rc.nblocks <= 1) return;
-  hipLaunchKernelGGL(k_reduce_finish, dim3(batch), dim3(NT), 0, st, rc, gate);
+  hipLaunchKernelGGL(k_reduce_finish, dim3(batch), dim3(kWave), 0, st, rc, gate);
   ETH_LAUNCH_CHECK();
 }
 
