@@ -200,6 +200,15 @@ void launch_cd_step(const Geo& g, const T* wind, const double* dF, double nu, co
                     long long ld64, double out_scale, Gate gate, hipStream_t st, int transpose = 0);
 // at = a^T for a dense ni x ni matrix
 void launch_transpose(const double* a, int ni, double* at, hipStream_t st);
+// the whole Chebyshev-Jacobi solve for Q_1 in one launch (steps <= 12): x_1 =
+// b[0] D^{-1} b, then x_{k+1} = x_k + a[k] (x_k - x_{k-1}) + b[k] D^{-1}(b - Q_1 x_k)
+struct Q1Cheb {
+  double a[12], b[12];
+  int steps;
+};
+template <typename T>
+void launch_q1mass_cheb_fused(const Geo& g, const T* b, T* out, const Q1Cheb& cc, int batch, Gate gate,
+                              hipStream_t st);
 template <typename T>
 void launch_q1mass_cheb(const Geo& g, const T* b, const T* x, T* xo, double alpha, double beta,
                         int has_prev, int batch, Gate gate, hipStream_t st);

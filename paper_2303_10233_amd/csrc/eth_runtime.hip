@@ -181,6 +181,7 @@ struct Problem {
   int s_coarse_ni = 0;
   double* ssums = nullptr;
   bool fused_mq = true;              // one launch per Chebyshev step (ETH_DEBUG_UNFUSED_MQ=1: per colour)
+  bool fused_q1 = true;              // the PCD's Q_1 solve in one launch (ETH_DEBUG_UNFUSED_Q1=1: per step)
   // tile side of the fused Chebyshev step, chosen at set-up for batch 1
   // (lo) and for max_batch (hi)
   // variant of the fused Chebyshev step: tile side and steps per launch
@@ -438,6 +439,7 @@ void Problem::setup(const eth_problem_desc& desc) {
     throw std::invalid_argument("invalid precision");
   mixed = d.precision == ETH_MIXED;
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) fused_mq = (e[0] != '1');
+  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_Q1")) fused_q1 = (e[0] != '1');
   max_batch = d.max_batch > 0 ? d.max_batch : 1;
   st = static_cast<hipStream_t>(d.stream);
   ETH_HIP(hipEventCreateWithFlags(&ev_poll, hipEventDisableTiming));
@@ -1665,6 +1667,16 @@ void Problem::pcd_schur(const double* r, double* z, long long ld, int batch, Gat
   };
   // Q_1^{-1} b: Chebyshev-Jacobi on [1/4, 9/4]; returns the buffer holding it
   auto q1_inv = [&](T* b, T* cur, T* oth) {
+    if (fused_q1 && d.pcd_q1_steps <= 12) {   // every step in one launch, bit for bit the same
+      Q1Cheb cc{};
+      cc.steps = d.pcd_q1_steps;
+      for (int k = 0; k < cc.steps; ++k) {
+        cc.a[k] = q1a[k];
+        cc.b[k] = q1b[k];
+      }
+      launch_q1mass_cheb_fused<T>(g, b, cur, cc, batch, gate, st);
+      return cur;
+    }
     launch_q1mass_cheb<T>(g, b, nullptr, cur, 0.0, q1b[0], 0, batch, gate, st);
     for (int k = 1; k < d.pcd_q1_steps; ++k) {
       launch_q1mass_cheb<T>(g, b, cur, oth, q1a[k], q1b[k], k == 1 ? 2 : 1, batch, gate, st);

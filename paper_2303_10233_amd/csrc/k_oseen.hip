@@ -17,6 +17,8 @@ namespace eth {
 namespace {
 
 constexpr int TX = 32, TY = 8, NT = TX * TY;
+// fused Q_1 Chebyshev-Jacobi solve: owned tile side, halo, region side, threads
+constexpr int Q1TQ = 16, Q1H = 12, Q1R = Q1TQ + 2 * Q1H, Q1NT = 512;
 constexpr int VX = 2 * TX + 4, VY = 2 * TY + 4;
 
 __host__ __device__ inline double diag90(int pi, int pj) {
@@ -286,6 +288,94 @@ __global__ void k_q1mass_cheb(Geo g, const T* __restrict__ b, const T* __restric
   const double r = (double)b[o] - q1_mass_row(xr, c, d, n, h2);
   const double prev = (has_prev == 2) ? 0.0 : (double)xo[o];   // 2: previous iterate is zero
   xo[o] = (T)(xc + alpha * (xc - prev) + beta * r / D);
+}
+
+// All steps of the Chebyshev-Jacobi solve Q_1 x = b in one launch.  A block
+// owns Q1TQ x Q1TQ nodes (the last block of a row or column also node n),
+// stages b on a region widened by Q1H nodes and iterates on the region in
+// LDS; the outermost ring of the region is never updated, and each stencil
+// step spreads its stale values inward by one node at most, so the owned
+// nodes are exact for steps <= Q1H.  Every step is the arithmetic of
+// k_q1mass_cheb (the same expressions, each iterate rounded to T), so the
+// result equals the one-launch-per-step solve bit for bit.
+template <typename T>
+__device__ inline double q1_mass_row_local(const T* x, int lx, int ly, int c, int d, int n, double h2) {
+  const int lxf = (c > 0), rx = (c < n), lyf = (d > 0), ry = (d < n);
+  const double wx[3] = {(double)lxf, 2.0 * (lxf + rx), (double)rx};
+  const double wy[3] = {(double)lyf, 2.0 * (lyf + ry), (double)ry};
+  double acc = 0.0;
+  for (int bb = -1; bb <= 1; ++bb) {
+    if (wy[bb + 1] == 0.0) continue;
+    double s = 0.0;
+    for (int aa = -1; aa <= 1; ++aa) {
+      if (wx[aa + 1] == 0.0) continue;
+      s += wx[aa + 1] * (double)x[(ly + bb) * Q1R + (lx + aa)];
+    }
+    acc += wy[bb + 1] * s;
+  }
+  return acc * h2 / 36.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(Q1NT) void k_q1mass_cheb_fused(Geo g, const T* __restrict__ b,
+                                                           T* __restrict__ out, Q1Cheb cc, Gate gate) {
+  __shared__ T sb[Q1R * Q1R];
+  __shared__ T sx[2][Q1R * Q1R];
+  const int rhs = blockIdx.z;
+  if (gate.off(rhs)) return;   // uniform per block
+  const int n = g.n, tid = threadIdx.x;
+  const int c0 = blockIdx.x * Q1TQ, d0 = blockIdx.y * Q1TQ;
+  const int gx = c0 - Q1H, gy = d0 - Q1H;
+  const bool last_x = blockIdx.x == gridDim.x - 1, last_y = blockIdx.y == gridDim.y - 1;
+  const T* br = b + (long long)rhs * g.nk;
+  const double h2 = g.h * g.h;
+  constexpr int IT = (Q1R * Q1R + Q1NT - 1) / Q1NT;
+  // staging of b and the first step x_1 = beta_0 D^{-1} b
+  T bv[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int k = tid + i * Q1NT, c = gx + k % Q1R, d = gy + k / Q1R;
+    bv[i] = T(0);
+    if (k < Q1R * Q1R && c >= 0 && c <= n && d >= 0 && d <= n) bv[i] = br[(long long)d * (n + 1) + c];
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int k = tid + i * Q1NT, c = gx + k % Q1R, d = gy + k / Q1R;
+    if (k >= Q1R * Q1R) break;
+    T x1 = T(0);
+    if (c >= 0 && c <= n && d >= 0 && d <= n) {
+      const double D = h2 * ((c > 0) + (c < n)) * ((d > 0) + (d < n)) / 9.0;
+      x1 = (T)(cc.b[0] * (double)bv[i] / D);
+    }
+    sb[k] = bv[i];
+    sx[0][k] = x1;
+    sx[1][k] = T(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int s = 1; s < cc.steps; ++s) {
+    const double alpha = cc.a[s], beta = cc.b[s];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int k = tid + i * Q1NT, lx = k % Q1R, ly = k / Q1R, c = gx + lx, d = gy + ly;
+      if (k >= Q1R * Q1R) break;
+      if (lx == 0 || ly == 0 || lx == Q1R - 1 || ly == Q1R - 1 || c < 0 || c > n || d < 0 || d > n) continue;
+      const double D = h2 * ((c > 0) + (c < n)) * ((d > 0) + (d < n)) / 9.0;
+      const double xc = (double)sx[cur][k];
+      const double r = (double)sb[k] - q1_mass_row_local(sx[cur], lx, ly, c, d, n, h2);
+      const double prev = (s == 1) ? 0.0 : (double)sx[cur ^ 1][k];   // step 1: the previous iterate is zero
+      sx[cur ^ 1][k] = (T)(xc + alpha * (xc - prev) + beta * r / D);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  T* outr = out + (long long)rhs * g.nk;
+  constexpr int OW = Q1TQ + 1;   // owned nodes per side, node n included for the last tiles
+  for (int k = tid; k < OW * OW; k += Q1NT) {
+    const int ox = k % OW, oy = k / OW, c = c0 + ox, d = d0 + oy;
+    if ((ox == Q1TQ && !last_x) || (oy == Q1TQ && !last_y) || c > n || d > n) continue;
+    outr[(long long)d * (n + 1) + c] = sx[cur][(oy + Q1H) * Q1R + (ox + Q1H)];
+  }
 }
 
 // y = F_1 x on Q1 vectors: F_1 = nu int grad psi_j . grad psi_i + int (w . grad psi_j) psi_i
@@ -598,6 +688,14 @@ void launch_cd_step(const Geo& g, const T* wind, const double* dF, double nu, co
   ETH_LAUNCH_CHECK();
 }
 template <typename T>
+void launch_q1mass_cheb_fused(const Geo& g, const T* b, T* out, const Q1Cheb& cc, int batch, Gate gate,
+                              hipStream_t st) {
+  if (cc.steps < 1 || cc.steps > Q1H) throw std::invalid_argument("fused Q_1 solve: 1 .. 12 steps");
+  const unsigned t = (unsigned)((g.n + Q1TQ - 1) / Q1TQ);
+  hipLaunchKernelGGL(k_q1mass_cheb_fused<T>, dim3(t, t, batch), dim3(Q1NT), 0, st, g, b, out, cc, gate);
+  ETH_LAUNCH_CHECK();
+}
+template <typename T>
 void launch_q1mass_cheb(const Geo& g, const T* b, const T* x, T* xo, double alpha, double beta,
                         int has_prev, int batch, Gate gate, hipStream_t st) {
   hipLaunchKernelGGL(k_q1mass_cheb<T>, dim3(nb(g.nk), batch), dim3(256), 0, st, g, b, x, xo, alpha, beta,
@@ -677,6 +775,8 @@ void launch_q1_dense_solve(const double* Ainv, int ni, const T* b, T* x, int bat
   template void launch_cd_step<T>(const Geo&, const T*, const double*, double, const T*, const T*, \
                                   T*, double, int, int, double*, long long, double, Gate, hipStream_t, \
                                   int);                                                               \
+  template void launch_q1mass_cheb_fused<T>(const Geo&, const T*, T*, const Q1Cheb&, int, Gate,       \
+                                           hipStream_t);                                             \
   template void launch_q1mass_cheb<T>(const Geo&, const T*, const T*, T*, double, double, int, int,    \
                                       Gate, hipStream_t);                                             \
   template void launch_f1_apply<T>(const Geo&, const double*, double, const T*, T*, int, Gate,          \

@@ -136,6 +136,23 @@ def test_pcd_matches_oracle(n, prec, tol):
     assert abs(z[o:o + m.nk].sum()) < 1e-9 * np.abs(z[o:o + m.nk]).sum()
 
 
+@pytest.mark.parametrize("n,prec", [(16, eth.FP64), (33, eth.FP64), (64, eth.MIXED), (96, eth.MIXED)])
+def test_fused_q1_solve_equals_per_step_launches(n, prec, monkeypatch):
+    """The PCD's Chebyshev-Jacobi solve with Q_1 in one launch (16 x 16
+    tiles, halo 12, the last tiles owning node n) gives the one-launch-per-step
+    result bit for bit, in the PCD and in its transpose."""
+    print(f"[fused Q1] n={n} prec={prec}", flush=True)
+    m, s, P = _setup(n, 0.01, prec)
+    r = uniform_vector(m.N, 7 + n)
+    r[: 2 * m.nv][s.vel_bnd] = 0.0
+    zf = [_np(P.apply_pcd(_t(r), transpose=t)) for t in (False, True)]
+    monkeypatch.setenv("ETH_DEBUG_UNFUSED_Q1", "1")
+    _, _, Q = _setup(n, 0.01, prec)
+    zs = [_np(Q.apply_pcd(_t(r), transpose=t)) for t in (False, True)]
+    for a, b in zip(zf, zs):
+        assert np.array_equal(a, b)
+
+
 def _true_rel_residual(s, x, b):
     xi, bi = s.to_interior(x), s.to_interior(b)
     return np.linalg.norm(bi - s.K @ xi) / np.linalg.norm(bi)
