@@ -200,6 +200,21 @@ void launch_cd_step(const Geo& g, const T* wind, const double* dF, double nu, co
                     long long ld64, double out_scale, Gate gate, hipStream_t st, int transpose = 0);
 // at = a^T for a dense ni x ni matrix
 void launch_transpose(const double* a, int ni, double* at, hipStream_t st);
+// the A_p multigrid from a level with n <= 32 down to the coarsest and back in
+// one launch per RHS (levels, element sizes, diag(A_p) per level, Chebyshev
+// coefficients per level and step, the coarsest bordered inverse)
+constexpr int APT_L = 8;
+struct ApTail {
+  int nlev, deg, ni;
+  int n[APT_L];
+  int off[APT_L + 1];   // offset of each level's values in the kernel's LDS arrays
+  double h[APT_L];
+  const double* dAp[APT_L];
+  double ca[APT_L][4], cb[APT_L][4];
+  const double* Ainv;
+};
+template <typename T>
+void launch_ap_tail(const ApTail& tl, const T* b0, T* x0, int batch, Gate gate, hipStream_t st);
 // the whole Chebyshev-Jacobi solve for Q_1 in one launch (steps <= 12): x_1 =
 // b[0] D^{-1} b, then x_{k+1} = x_k + a[k] (x_k - x_{k-1}) + b[k] D^{-1}(b - Q_1 x_k)
 struct Q1Cheb {

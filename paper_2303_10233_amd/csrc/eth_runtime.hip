@@ -182,6 +182,7 @@ struct Problem {
   double* ssums = nullptr;
   bool fused_mq = true;              // one launch per Chebyshev step (ETH_DEBUG_UNFUSED_MQ=1: per colour)
   bool fused_q1 = true;              // the PCD's Q_1 solve in one launch (ETH_DEBUG_UNFUSED_Q1=1: per step)
+  bool fused_aptail = true;          // A_p levels <= 32^2 in one launch (ETH_DEBUG_UNFUSED_APTAIL=1: per level)
   // tile side of the fused Chebyshev step, chosen at set-up for batch 1
   // (lo) and for max_batch (hi)
   // variant of the fused Chebyshev step: tile side and steps per launch
@@ -440,6 +441,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   mixed = d.precision == ETH_MIXED;
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) fused_mq = (e[0] != '1');
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_Q1")) fused_q1 = (e[0] != '1');
+  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_APTAIL")) fused_aptail = (e[0] != '1');
   max_batch = d.max_batch > 0 ? d.max_batch : 1;
   st = static_cast<hipStream_t>(d.stream);
   ETH_HIP(hipEventCreateWithFlags(&ev_poll, hipEventDisableTiming));
@@ -1620,7 +1622,17 @@ void Problem::ap_vcycle(int batch, Gate gate) {
     xo[l] = static_cast<T*>(qxo[l]);
   }
   const int deg = d.gmg_degree;
-  for (int l = 0; l + 1 < LQ; ++l) {
+  // levels from l0 (the first with n <= 32) down are one launch per RHS
+  int l0 = LQ;
+  if (fused_aptail && deg <= 4 && LQ - 1 <= APT_L)
+    for (int l = 0; l < LQ; ++l)
+      if (qlv[l].n <= 32) {
+        l0 = l;
+        break;
+      }
+  if (l0 < LQ && LQ - l0 > APT_L) l0 = LQ;
+  const int lstop = l0 < LQ ? l0 : LQ - 1;   // per-level launches above lstop
+  for (int l = 0; l < lstop; ++l) {
     for (int k = 0; k < deg; ++k) {
       launch_ap_op<T>(qlv[l], 1, b[l], x[l], xo[l], qca[l][k], qcb[l][k], k == 0 ? 0 : 1, qdAp[l],
                       batch, gate, st);
@@ -1629,8 +1641,29 @@ void Problem::ap_vcycle(int batch, Gate gate) {
     launch_ap_op<T>(qlv[l], 2, b[l], x[l], xo[l], 0.0, 0.0, 0, qdAp[l], batch, gate, st);
     launch_q1_restrict<T>(qlv[l], qlv[l + 1], xo[l], b[l + 1], x[l + 1], batch, gate, st);
   }
-  launch_q1_dense_solve<T>(qAinv, q_coarse_ni, b[LQ - 1], x[LQ - 1], batch, gate, st);
-  for (int l = LQ - 2; l >= 0; --l) {
+  if (l0 < LQ) {
+    ApTail tl{};
+    tl.nlev = LQ - l0;
+    tl.deg = deg;
+    tl.ni = q_coarse_ni;
+    tl.Ainv = qAinv;
+    tl.off[0] = 0;
+    for (int t = 0; t < tl.nlev; ++t) {
+      const Geo& gq = qlv[l0 + t];
+      tl.n[t] = gq.n;
+      tl.h[t] = gq.h;
+      tl.dAp[t] = qdAp[l0 + t];
+      tl.off[t + 1] = tl.off[t] + (gq.n + 1) * (gq.n + 1);
+      for (int k = 0; k < deg && t + 1 < tl.nlev; ++k) {
+        tl.ca[t][k] = qca[l0 + t][k];
+        tl.cb[t][k] = qcb[l0 + t][k];
+      }
+    }
+    launch_ap_tail<T>(tl, b[l0], x[l0], batch, gate, st);
+  } else {
+    launch_q1_dense_solve<T>(qAinv, q_coarse_ni, b[LQ - 1], x[LQ - 1], batch, gate, st);
+  }
+  for (int l = std::min(l0, LQ - 1) - 1; l >= 0; --l) {
     launch_q1_prolong_add<T>(qlv[l], qlv[l + 1], x[l + 1], x[l], batch, gate, st);
     for (int k = 0; k < deg; ++k) {
       launch_ap_op<T>(qlv[l], 1, b[l], x[l], xo[l], qca[l][k], qcb[l][k], k == 0 ? 0 : 1, qdAp[l],

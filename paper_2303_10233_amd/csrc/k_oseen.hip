@@ -19,6 +19,9 @@ namespace {
 constexpr int TX = 32, TY = 8, NT = TX * TY;
 // fused Q_1 Chebyshev-Jacobi solve: owned tile side, halo, region side, threads
 constexpr int Q1TQ = 16, Q1H = 12, Q1R = Q1TQ + 2 * Q1H, Q1NT = 512;
+// A_p multigrid tail: threads, Q1 values of all its levels (n <= 32 on the first),
+// velocity values of its first level
+constexpr int APT_NT = 1024, APT_Q = 1600, APT_V = 65 * 65;
 constexpr int VX = 2 * TX + 4, VY = 2 * TY + 4;
 
 __host__ __device__ inline double diag90(int pi, int pj) {
@@ -535,6 +538,164 @@ __global__ __launch_bounds__(QX * QY) void k_ap_op(Geo g, const T* __restrict__ 
   }
 }
 
+// The A_p multigrid from its first level with n <= 32 down to the coarsest
+// and back in one launch per right-hand side (one block): every level's
+// vectors stay in LDS, each operation is the arithmetic of the per-level
+// kernels (k_ap_op, k_q1_restrict, k_q1_prolong_add, k_q1_dense_solve: the
+// same expressions in the same order, every vector rounded to T where those
+// store it), so the result equals the per-level launches bit for bit.
+template <typename T>
+__global__ __launch_bounds__(APT_NT) void k_ap_tail(ApTail tl, const T* __restrict__ b0, T* __restrict__ x0,
+                                                    Gate gate) {
+  __shared__ T qb[APT_Q], qv[2][APT_Q];
+  __shared__ double stv[2][APT_V];
+  const int rhs = blockIdx.x;
+  if (gate.off(rhs)) return;   // uniform per block
+  const int tid = threadIdx.x;
+  // bit t: which of qv[0], qv[1] holds the iterate of level t (uniform)
+  unsigned curm = 0;
+  auto cur = [&](int t) { return (int)((curm >> t) & 1u); };
+  {
+    const int nk = (tl.n[0] + 1) * (tl.n[0] + 1);
+    for (int k = tid; k < nk; k += APT_NT) {
+      qb[k] = b0[(long long)rhs * nk + k];
+      qv[0][k] = T(0);
+    }
+  }
+  __syncthreads();
+  // y = A_p x on level t (MODE 1: Chebyshev step into the other array, MODE 2:
+  // residual into the other array), as k_ap_op
+  auto ap = [&](int t, int mode, double alpha, double beta, int has_prev) __attribute__((always_inline)) {
+    const int n = tl.n[t], nq = 2 * n + 1, top = 2 * n, n1 = n + 1;
+    const T* X = qv[cur(t)] + tl.off[t];
+    T* O = qv[cur(t) ^ 1] + tl.off[t];
+    const T* B = qb + tl.off[t];
+    const double h = tl.h[t], h2 = h * h, sB = -h / 36.0;
+    for (int k = tid; k < nq * nq; k += APT_NT) {
+      const int I = k % nq, J = k / nq;
+      double tvx = 0.0, tvy = 0.0;
+      if (I >= 1 && I < top && J >= 1 && J < top) {
+        const int ex = I >> 1, i = I & 1, ey = J >> 1, j = J & 1;
+        double ax = 0.0, ay = 0.0;
+#pragma unroll
+        for (int dd = -1; dd <= 1; ++dd)
+#pragma unroll
+          for (int dc = -1; dc <= 1; ++dc) {
+            const int c = ex + dc, d = ey + dd;
+            const double p = (c >= 0 && c <= n && d >= 0 && d <= n) ? (double)X[d * n1 + c] : 0.0;
+            ax += g6(i, dc) * mq6(j, dd) * p;
+            ay += mq6(i, dc) * g6(j, dd) * p;
+          }
+        const double inv = 1.0 / mv_diag(i, j, h2);
+        tvx = sB * ax * inv;
+        tvy = sB * ay * inv;
+      }
+      stv[0][k] = tvx;
+      stv[1][k] = tvy;
+    }
+    __syncthreads();
+    for (int k = tid; k < n1 * n1; k += APT_NT) {
+      const int c = k % n1, d = k / n1;
+      const int Lx = c > 0, Rx = c < n, Ly = d > 0, Ry = d < n;
+      const double Gx[5] = {-1.0 * Lx, -4.0 * Lx, 5.0 * Lx - 5.0 * Rx, 4.0 * Rx, 1.0 * Rx};
+      const double Mx[5] = {0.0, 2.0 * Lx, 1.0 * Lx + 1.0 * Rx, 2.0 * Rx, 0.0};
+      const double Gy[5] = {-1.0 * Ly, -4.0 * Ly, 5.0 * Ly - 5.0 * Ry, 4.0 * Ry, 1.0 * Ry};
+      const double My[5] = {0.0, 2.0 * Ly, 1.0 * Ly + 1.0 * Ry, 2.0 * Ry, 0.0};
+      double s = 0.0;
+#pragma unroll
+      for (int q = -2; q <= 2; ++q) {
+        const int J = 2 * d + q;
+        double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          const int I = 2 * c + o;
+          const bool in = I >= 0 && I <= top && J >= 0 && J <= top;
+          a1 += Gx[o + 2] * (in ? stv[0][J * nq + I] : 0.0);
+          a2 += Mx[o + 2] * (in ? stv[1][J * nq + I] : 0.0);
+        }
+        s += My[q + 2] * a1 + Gy[q + 2] * a2;
+      }
+      const double y = sB * s;
+      if (mode == 2) {
+        O[k] = (T)((double)B[k] - y);
+      } else {
+        const double xc = (double)X[k];
+        double xn = xc + beta * ((double)B[k] - y) / tl.dAp[t][k];
+        if (has_prev == 1) xn += alpha * (xc - (double)O[k]);
+        else if (has_prev == 2) xn += alpha * xc;
+        O[k] = (T)xn;
+      }
+    }
+    __syncthreads();
+    if (mode == 1) curm ^= 1u << t;
+  };
+  const int L = tl.nlev, deg = tl.deg;
+  for (int t = 0; t + 1 < L; ++t) {
+    for (int k = 0; k < deg; ++k) ap(t, 1, tl.ca[t][k], tl.cb[t][k], k == 0 ? 0 : 1);
+    ap(t, 2, 0.0, 0.0, 0);
+    // restriction of the residual (in the other array) as k_q1_restrict; x_c = 0
+    const int nf = tl.n[t], nc = tl.n[t + 1];
+    const T* rf = qv[cur(t) ^ 1] + tl.off[t];
+    const double w[3] = {0.5, 1.0, 0.5};
+    for (int k = tid; k < (nc + 1) * (nc + 1); k += APT_NT) {
+      const int C = k % (nc + 1), D = k / (nc + 1);
+      double s = 0.0;
+#pragma unroll
+      for (int q = -1; q <= 1; ++q) {
+        const int j = 2 * D + q;
+        if (j < 0 || j > nf) continue;
+#pragma unroll
+        for (int o = -1; o <= 1; ++o) {
+          const int i = 2 * C + o;
+          if (i < 0 || i > nf) continue;
+          s += w[o + 1] * w[q + 1] * (double)rf[j * (nf + 1) + i];
+        }
+      }
+      qb[tl.off[t + 1] + k] = (T)s;
+      qv[cur(t + 1)][tl.off[t + 1] + k] = T(0);
+    }
+    __syncthreads();
+  }
+  {
+    // coarsest level: x = Ainv b as k_q1_dense_solve (one wave per row)
+    const int t = L - 1, ni = tl.ni;
+    const int lane = tid & 63, wave = tid >> 6;
+    const T* B = qb + tl.off[t];
+    T* X = qv[cur(t)] + tl.off[t];
+    for (int i = wave; i < ni; i += APT_NT / 64) {
+      double s = 0.0;
+      for (int j = lane; j < ni; j += 64) s += tl.Ainv[(long long)i * ni + j] * (double)B[j];
+      s = wave_sum(s);
+      if (lane == 0) X[i] = (T)s;
+    }
+    __syncthreads();
+  }
+  for (int t = L - 2; t >= 0; --t) {
+    // x_f += P x_c as k_q1_prolong_add
+    const int nf = tl.n[t], nc = tl.n[t + 1] + 1;
+    const T* xr = qv[cur(t + 1)] + tl.off[t + 1];
+    T* xf = qv[cur(t)] + tl.off[t];
+    for (int k = tid; k < (nf + 1) * (nf + 1); k += APT_NT) {
+      const int i = k % (nf + 1), j = k / (nf + 1);
+      auto v = [&](int a, int b2) { return (double)xr[b2 * nc + a]; };
+      double s;
+      const int a0 = i >> 1, bb0 = j >> 1;
+      if ((i & 1) == 0 && (j & 1) == 0) s = v(a0, bb0);
+      else if ((j & 1) == 0) s = 0.5 * (v(a0, bb0) + v(a0 + 1, bb0));
+      else if ((i & 1) == 0) s = 0.5 * (v(a0, bb0) + v(a0, bb0 + 1));
+      else s = 0.25 * (v(a0, bb0) + v(a0 + 1, bb0) + v(a0, bb0 + 1) + v(a0 + 1, bb0 + 1));
+      xf[k] = (T)((double)xf[k] + s);
+    }
+    __syncthreads();
+    for (int k = 0; k < deg; ++k) ap(t, 1, tl.ca[t][k], tl.cb[t][k], k == 0 ? 0 : 1);
+  }
+  {
+    const int nk = (tl.n[0] + 1) * (tl.n[0] + 1);
+    const T* X = qv[cur(0)];
+    for (int k = tid; k < nk; k += APT_NT) x0[(long long)rhs * nk + k] = X[k];
+  }
+}
+
 // diag(A_p) at every Q1 node
 __global__ void k_ap_diag(Geo g, double* __restrict__ dAp) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -688,6 +849,19 @@ void launch_cd_step(const Geo& g, const T* wind, const double* dF, double nu, co
   ETH_LAUNCH_CHECK();
 }
 template <typename T>
+void launch_ap_tail(const ApTail& tl, const T* b0, T* x0, int batch, Gate gate, hipStream_t st) {
+  int q = 0;
+  for (int t = 0; t < tl.nlev; ++t) {
+    if (tl.off[t] != q) throw std::invalid_argument("A_p multigrid tail: level offsets");
+    q += (tl.n[t] + 1) * (tl.n[t] + 1);
+  }
+  if (tl.nlev < 1 || tl.nlev > APT_L || tl.n[0] > 32 || q > APT_Q || tl.deg < 1 || tl.deg > 4 ||
+      tl.ni != (tl.n[tl.nlev - 1] + 1) * (tl.n[tl.nlev - 1] + 1))
+    throw std::invalid_argument("A_p multigrid tail: unsupported levels");
+  hipLaunchKernelGGL(k_ap_tail<T>, dim3(batch), dim3(APT_NT), 0, st, tl, b0, x0, gate);
+  ETH_LAUNCH_CHECK();
+}
+template <typename T>
 void launch_q1mass_cheb_fused(const Geo& g, const T* b, T* out, const Q1Cheb& cc, int batch, Gate gate,
                               hipStream_t st) {
   if (cc.steps < 1 || cc.steps > Q1H) throw std::invalid_argument("fused Q_1 solve: 1 .. 12 steps");
@@ -775,6 +949,7 @@ void launch_q1_dense_solve(const double* Ainv, int ni, const T* b, T* x, int bat
   template void launch_cd_step<T>(const Geo&, const T*, const double*, double, const T*, const T*, \
                                   T*, double, int, int, double*, long long, double, Gate, hipStream_t, \
                                   int);                                                               \
+  template void launch_ap_tail<T>(const ApTail&, const T*, T*, int, Gate, hipStream_t);              \
   template void launch_q1mass_cheb_fused<T>(const Geo&, const T*, T*, const Q1Cheb&, int, Gate,       \
                                            hipStream_t);                                             \
   template void launch_q1mass_cheb<T>(const Geo&, const T*, const T*, T*, double, double, int, int,    \

@@ -153,6 +153,24 @@ def test_fused_q1_solve_equals_per_step_launches(n, prec, monkeypatch):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("n,prec", [(16, eth.FP64), (40, eth.FP64), (64, eth.MIXED), (96, eth.MIXED)])
+def test_ap_multigrid_tail_equals_per_level_launches(n, prec, monkeypatch):
+    """The A_p multigrid's levels from the first with n <= 32 down (one launch
+    per right-hand side, all levels in LDS) give the per-level launches'
+    result bit for bit, in the PCD and in its transpose (n = 16: the whole
+    cycle; 40: levels 20, 10, 5)."""
+    print(f"[A_p tail] n={n} prec={prec}", flush=True)
+    m, s, P = _setup(n, 0.01, prec)
+    r = uniform_vector(m.N, 11 + n)
+    r[: 2 * m.nv][s.vel_bnd] = 0.0
+    zf = [_np(P.apply_pcd(_t(r), transpose=t)) for t in (False, True)]
+    monkeypatch.setenv("ETH_DEBUG_UNFUSED_APTAIL", "1")
+    _, _, Q = _setup(n, 0.01, prec)
+    zs = [_np(Q.apply_pcd(_t(r), transpose=t)) for t in (False, True)]
+    for a, b in zip(zf, zs):
+        assert np.array_equal(a, b)
+
+
 def _true_rel_residual(s, x, b):
     xi, bi = s.to_interior(x), s.to_interior(b)
     return np.linalg.norm(bi - s.K @ xi) / np.linalg.norm(bi)
