@@ -458,6 +458,19 @@ def main():
                 note="pressure mass by P0 elimination + Q1 multigrid for S_k (mesh independent)")
             log(f"stokes n={n} schur-gmg M_Q {name}: {extra['stokes_schur_mq'][name]}")
             Ps.close()
+        # the larger configured cavity, same solver settings as the headline
+        extra["stokes512"] = {}
+        for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+            P5 = eth.Problem(512, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS)
+            b5 = P5.assemble_rhs()
+            dt, its, _ = time_solves(P5, b5, args.extra_steps, 1, args.rtol, use_graph)
+            _, ti = P5.solve(b5, rtol=args.rtol, maxit=2000, use_graph=use_graph, true_residual=True)
+            extra["stokes512"][name] = dict(
+                solves_per_s=round(args.extra_steps / dt, 4), ms_per_solve=round(1e3 * dt / args.extra_steps, 3),
+                iterations=its[-1], true_rel_residual=ti[0]["rel_residual_true"],
+                mq_variant=list(P5.mq_variant()[:2]))
+            log(f"stokes n=512 {name}: {extra['stokes512'][name]}")
+            P5.close()
         extra["adjoint"] = []
         for kind, an in (("stokes", 512), ("oseen", 256)):
             for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
