@@ -63,6 +63,23 @@ def test_apply_operator_matches_oracle(n):
     assert rel_err(y1, s.apply_full(xs[0])) < 1e-13
 
 
+@pytest.mark.parametrize("n", [16, 33, 64])
+def test_apply_with_xcd_band_order_matches_oracle(n, monkeypatch):
+    """Large grids of the apply renumber their tiles by XCD band; forced on
+    small grids here, the operator still equals the oracle's and its fused
+    dot is unchanged up to the summation order."""
+    monkeypatch.setenv("ETH_DEBUG_XCD_REMAP_MIN", "1")
+    m = Mesh(n)
+    s = System(m, nu=0.7)
+    P = eth.Problem(n, nu=0.7)
+    x = uniform_vector(m.N, 5 + n)
+    y = _np(P.apply_operator(_t(x)))
+    assert rel_err(y, s.apply_full(x)) < 1e-13
+    monkeypatch.setenv("ETH_DEBUG_XCD_REMAP_MIN", "1000000000")
+    y2 = _np(P.apply_operator(_t(x)))
+    assert np.array_equal(y, y2)
+
+
 def test_operator_symmetric_and_frame_null_vector():
     n = 24
     m = Mesh(n)
