@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 
 namespace eth {
@@ -40,6 +41,32 @@ inline Geo make_geo(int n, double h) {
 }
 
 constexpr int kWave = 64;
+
+// ----------------------------------------------------------------------------
+// XCD band order.  The eight XCDs take a grid's workgroups round-robin, each
+// with its own L2; a tiled stencil kernel whose vertically neighbouring tiles
+// share halo rows then fetches those rows once per XCD.  Grids of at least
+// `remap_min` tiles are renumbered so that XCD j (workgroups j, j+8, ...) takes
+// the j-th contiguous band of tiles in row-major order; smaller grids keep the
+// plain order.  The threshold comes from the host (xcd_remap_min), where
+// ETH_DEBUG_XCD_REMAP_MIN can force it down for tests.
+// ----------------------------------------------------------------------------
+constexpr int kXcdRemapMin = 2048;
+inline int xcd_remap_min() {
+  const char* e = std::getenv("ETH_DEBUG_XCD_REMAP_MIN");
+  return e ? std::atoi(e) : kXcdRemapMin;
+}
+__device__ __forceinline__ void xcd_band_tile(int remap_min, int& tile_x, int& tile_y) {
+  tile_x = blockIdx.x;
+  tile_y = blockIdx.y;
+  const int T = gridDim.x * gridDim.y;
+  if (T < remap_min) return;
+  const int old_id = blockIdx.x + gridDim.x * blockIdx.y;
+  const int q = T / 8, r = T % 8, j = old_id % 8, m = old_id / 8;
+  const int nid = j * q + (j < r ? j : r) + m;
+  tile_x = nid % gridDim.x;
+  tile_y = nid / gridDim.x;
+}
 
 // ----------------------------------------------------------------------------
 // Deterministic reductions

@@ -27,12 +27,6 @@ namespace {
 constexpr int AX = 64, AY = 4, RPT = 4;        // threads (x, y); rows per thread
 constexpr int TYN = AY * RPT;                  // 16 velocity rows per tile
 constexpr int NTA = AX * AY;
-constexpr int XCD_REMAP_MIN = 2048;         // tiles of a grid renumbered by XCD band (see k_apply)
-// ETH_DEBUG_XCD_REMAP_MIN overrides the threshold (tests force the renumbering on small grids)
-inline int xcd_remap_min() {
-  const char* e = std::getenv("ETH_DEBUG_XCD_REMAP_MIN");
-  return e ? std::atoi(e) : XCD_REMAP_MIN;
-}
 static_assert(RPT % 2 == 0, "rows 2m and 2m+1 of a thread share their pressure rows");
 constexpr int UX = AX + 4, UY = TYN + 4;       // velocity patch with halo 2
 constexpr int QX = AX / 2 + 2, QY = TYN / 2 + 2;   // Q1 nodes c0-1 .. c0+AX/2
@@ -67,22 +61,10 @@ __global__ __launch_bounds__(NTA) void k_apply(Geo g, double nu, const double* _
   clear.apply(rhs);
   const bool off = gate.off(rhs);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * AX + tx;
-  // Large grids (>= XCD_REMAP_MIN tiles) are renumbered so that each of the
-  // eight XCDs (which take workgroups round-robin) gets one contiguous band
-  // of tile rows: vertically neighbouring tiles share two halo rows, and
-  // within a band those are still in the XCD's own L2.  Small grids keep the
-  // plain order (a few blocks per CU: spreading them wins).
-  int tile_x = blockIdx.x, tile_y = blockIdx.y;
-  {
-    const int T = gridDim.x * gridDim.y;
-    if (T >= remap_min) {
-      const int old_id = blockIdx.x + gridDim.x * blockIdx.y;
-      const int q = T / 8, r = T % 8, j = old_id % 8, m = old_id / 8;
-      const int nid = j * q + (j < r ? j : r) + m;
-      tile_x = nid % gridDim.x;
-      tile_y = nid / gridDim.x;
-    }
-  }
+  // large grids in XCD band order (vertically neighbouring tiles share two
+  // halo rows; within a band those stay in the XCD's own L2)
+  int tile_x, tile_y;
+  xcd_band_tile(remap_min, tile_x, tile_y);
   const int I0 = tile_x * AX, J0 = tile_y * TYN;
   const int c0 = I0 / 2, d0 = J0 / 2;
   const int n = g.n, nq = g.nq, top = 2 * n;

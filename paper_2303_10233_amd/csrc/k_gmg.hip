@@ -12,6 +12,8 @@
 //    and (-1/8, 3/4, 3/8) of the coarse (left, mid, right) nodes; restriction
 //    is its transpose, P^T rows (1/8)[-1,0,3,8,3,0,-1] at a coarse vertex and
 //    (1/8)[6,8,6] at a coarse mid node.
+#include <climits>
+
 #include "eth_kernels.h"
 
 namespace eth {
@@ -63,13 +65,15 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Geo g, const T* __restrict__ b
                                                   const T* __restrict__ x, T* __restrict__ xo,
                                                   double alpha, double beta, int has_prev,
                                                   double* __restrict__ out64, long long ld64,
-                                                  double out_scale, Gate gate) {
+                                                  double out_scale, Gate gate, int remap_min) {
   __shared__ T s[HY * HX];
   const int plane = blockIdx.z;
   const bool off = gate.off(plane >> 1);   // tested after the staging (overlapped load)
   const int nq = g.nq, top = nq - 1;
   const long long po = (long long)plane * g.nv;
-  const int I0 = blockIdx.x * NX, J0 = blockIdx.y * NY;
+  int tile_x, tile_y;
+  xcd_band_tile(remap_min, tile_x, tile_y);   // large grids in XCD band order (shared halo rows in L2)
+  const int I0 = tile_x * NX, J0 = tile_y * NY;
   const int tid = threadIdx.x;
   // a thread takes four consecutive rows of one column: the x-direction sums
   // (K and M rows of its column parity) of each of the eight staged rows
@@ -192,7 +196,8 @@ constexpr int XF = RF + 4;              // fine iterate patch side
 template <typename T, bool RES_GIVEN>
 __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __restrict__ bf,
                                                  const T* __restrict__ xf, T* __restrict__ bc,
-                                                 T* __restrict__ xc, double beta_c, Gate gate) {
+                                                 T* __restrict__ xc, double beta_c, Gate gate,
+                                                 int remap_min) {
   using A = T;   // arithmetic in the storage type (FP32 in mixed precision)
   __shared__ T sx[XF * XF];
   __shared__ A sr[RF * RF];
@@ -200,7 +205,9 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
   const bool off = gate.off(plane >> 1);   // tested after the staging (overlapped load)
   const int nqf = gf.nq, topf = nqf - 1, nqc = gc.nq, topc = nqc - 1;
   const long long pf = (long long)plane * gf.nv, pc = (long long)plane * gc.nv;
-  const int C0x = blockIdx.x * CT, C0y = blockIdx.y * CT;
+  int tile_x, tile_y;
+  xcd_band_tile(remap_min, tile_x, tile_y);   // large grids in XCD band order (shared halo rows in L2)
+  const int C0x = tile_x * CT, C0y = tile_y * CT;
   const int F0x = 2 * C0x - 3, F0y = 2 * C0y - 3;     // residual patch origin
   const int tid = threadIdx.x;
   // The residual patch is computed by RG groups of RF threads: a thread takes
@@ -748,8 +755,11 @@ void launch_cheb_step(const Geo& g, const T* b, const T* x, T* xo, double alpha,
                       double out_scale, Gate gate, int batch, hipStream_t st) {
   (void)batch;
   dim3 grid((g.nq + NX - 1) / NX, (g.nq + NY - 1) / NY, nplanes);
+  // XCD band order for FP32 planes only: measured at 2048^2 it took the FP32
+  // step from 108 to 101 us and the FP64 step from 199 to 222 us
+  const int rm = sizeof(T) == 4 ? xcd_remap_min() : INT_MAX;
   hipLaunchKernelGGL(k_cheb_step<T>, grid, dim3(NT), 0, st, g, b, x, xo, alpha, beta, has_prev,
-                     out64, ld64, out_scale, gate);
+                     out64, ld64, out_scale, gate, rm);
   ETH_LAUNCH_CHECK();
 }
 
@@ -767,10 +777,11 @@ void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* 
                      double beta_c, int nplanes, int batch, Gate gate, hipStream_t st) {
   (void)batch;
   dim3 grid((gc.nq + CT - 1) / CT, (gc.nq + CT - 1) / CT, nplanes);
+  const int rm = xcd_remap_min();
   if (xf)
-    hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate);
+    hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate, rm);
   else
-    hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate);
+    hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(NT), 0, st, gf, gc, bf, xf, bc, xc, beta_c, gate, rm);
   ETH_LAUNCH_CHECK();
 }
 
