@@ -56,6 +56,14 @@ def test_binding_declares_every_symbol():
     assert not undeclared, undeclared
 
 
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """No CPU fallback: loading the product path without a built library is
+    an error, not a silent switch to another implementation."""
+    from paper_2303_10233_amd import eth
+    with pytest.raises(OSError):
+        eth.load_library(str(tmp_path / "libeth.so"))
+
+
 def test_status_strings_without_a_device(lib_path):
     lib = ctypes.CDLL(lib_path)
     lib.eth_status_string.argtypes = [ctypes.c_int]
@@ -88,3 +96,5 @@ def test_counter_grid_matches_the_launch_geometry():
     assert mq_grid(257, 64) == 5 * 5 * 1024
     assert mq_grid(256, 24) == 11 * 11 * 512
     assert mq_grid(256, 24, 2) == 11 * 11 * 1024
+    from paper_2303_10233_amd.traffic import apply_grid
+    assert apply_grid(2048) == 65 * 257 * 256   # 64 x 16 node tiles of 4097^2 nodes, 256 threads
