@@ -11,7 +11,7 @@ assembled, HBM-resident right-hand side to |eta|/gamma_1 <= 1e-6):
   `value` is the mixed-precision solver (FP32 preconditioner inside FP64
   MINRES); the FP64 solver is timed on the same input and reported beside it.
 
-Prints ONE JSON line.  --gpus N with N > 1 is refused: this build runs on one
+Prints ONE JSON line.  --gpus N with N > 1 is refused: the solver runs on one
 GPU (the method would shard by mesh blocks with halo exchanges).
 """
 import argparse
@@ -299,21 +299,28 @@ def microbench(reps):
     return out
 
 
-def counters_run(n, reps, tile):
+def counters_run(n, reps, tile, which="mq"):
     """The launches that the byte counters are read on (run under
-    `rocprofv3 --pmc FETCH_SIZE` and then `--pmc WRITE_SIZE`): the dominant
-    kernel of the headline workload (the fused Chebyshev-SGS step, mixed,
-    n x n) and plain copies of known size, at n and at n = 2048 (336 MB per
-    vector, beyond every cache), `reps` launches each.  The tile side of the
-    fused step is fixed (`tile`, the one set-up picks for this workload when
-    timed without a profiler: under the counters every launch is serialised
-    and timing-based choices would differ between runs).  Prints the launch
-    record the reduction script needs."""
+    `rocprofv3 --pmc FETCH_SIZE` and then `--pmc WRITE_SIZE`), `reps` each,
+    with plain copies of known size for the calibration (at n and at n = 2048:
+    336 MB per vector, beyond every cache).
+    which = "mq": the dominant kernel of the headline workload (the fused
+    Chebyshev-SGS step, mixed, n x n).  The tile side of the fused step is
+    fixed (`tile`, the one set-up picks for this workload when timed without
+    a profiler: under the counters every launch is serialised and
+    timing-based choices would differ between runs).
+    which = "apply": the FP64 saddle apply with its fused dot at n = 2048, the
+    stencil bandwidth figure (one 336 MB vector in, one out).
+    Prints the launch record the reduction script needs."""
     import torch
     from paper_2303_10233_amd import eth
-    rec = {"n": n, "reps": reps, "launches": []}
-    for nn, kernels in ((n, (eth.K_MQ_CHEB_STEP, eth.K_COPY)), (2048, (eth.K_COPY,))):
-        P = eth.Problem(nn, precision=eth.MIXED, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0",
+    rec = {"n": n, "reps": reps, "launches": [], "which": which}
+    if which == "apply":
+        plan = ((2048, eth.FP64, (eth.K_SADDLE_APPLY, eth.K_COPY)),)
+    else:
+        plan = ((n, eth.MIXED, (eth.K_MQ_CHEB_STEP, eth.K_COPY)), (2048, eth.MIXED, (eth.K_COPY,)))
+    for nn, prec, kernels in plan:
+        P = eth.Problem(nn, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0",
                         mq_tile=tile)
         torch.cuda.synchronize()
         for k in kernels:
@@ -347,6 +354,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="only the launches read by the rocprofv3 byte counters (see counters_run)")
     ap.add_argument("--mq-tile", type=int, default=16, help="tile side of the fused M_Q step in --counters")
+    ap.add_argument("--counters-kernel", choices=["mq", "apply"], default="mq",
+                    help="kernel of --counters: the fused M_Q step (headline) or the FP64 apply at n = 2048")
     ap.add_argument("--mq-variant", default="auto",
                     help="fused M_Q step of the headline solves as TILExSTEPS (e.g. 16x1), or auto (set-up "
                          "timing); a profiler serialises the two preconditioner branches, so a profiled run "
@@ -357,11 +366,11 @@ def main():
         t, st = args.mq_variant.lower().split("x")
         mq_kw = dict(mq_tile=int(t), mq_fuse_steps=int(st))
     if args.counters:
-        counters_run(args.n, args.profile_reps, args.mq_tile)
+        counters_run(args.n, args.profile_reps, args.mq_tile, args.counters_kernel)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described but not built)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
+                          "(sharding over several GPUs is described, not implemented)"}))
         sys.exit(2)
 
     import torch

@@ -5,7 +5,7 @@ oracle/ only.  Tolerances: FP64 operator and preconditioner applies agree to
 rounding (1e-12 relative); FP32 (mixed) preconditioner applies to 1e-5
 relative (single-precision rounding through the multigrid levels and 20
 Chebyshev steps); FP64 solves at rtol 1e-12 to 1e-8 relative in the
-canonicalised full vector (the spec FP64 bar).
+canonicalised full vector (the FP64 bar of 1e-8).
 """
 import numpy as np
 import pytest
