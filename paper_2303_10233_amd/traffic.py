@@ -6,6 +6,9 @@ copy of known size (n = 2048: 336 MB per vector, beyond every cache).
     python -m paper_2303_10233_amd.traffic --fetch F.csv --write W.csv \\
         --launches counters.json --kernel k_mq_cheb_fused --out profiles/...json
 
+(--kernel k_apply with the record of `bench.py --counters --counters-kernel
+apply`: the FP64 saddle apply at n = 2048.)
+
 The result records the sha256 of the kernel's source file, so a reader can
 tell when the counters no longer describe the code.
 """
@@ -57,6 +60,12 @@ def mq_grid(n, tile, steps=1):
     return (-(-n // tile)) ** 2 * threads
 
 
+def apply_grid(n):
+    """work-items of k_apply (64 x 4 threads per 64 x 16 velocity-node tile)"""
+    nq = 2 * n + 1
+    return (-(-nq // 64)) * (-(-nq // 16)) * 256
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--fetch", required=True)
@@ -68,17 +77,23 @@ def main():
     a = ap.parse_args()
     with open(a.launches) as f:
         rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
-    n = rec["n"]
+    n = 2048 if a.kernel == "k_apply" else rec["n"]
     target = [x for x in rec["launches"] if x["kernel"] == a.kernel and x["n"] == n][0]
     big_copy = [x for x in rec["launches"] if x["kernel"] == "k_copy" and x["n"] == 2048][0]
     small_copy = [x for x in rec["launches"] if x["kernel"] == "k_copy" and x["n"] == n][0]
     fetch = per_dispatch(a.fetch, "FETCH_SIZE")
     write = per_dispatch(a.write, "WRITE_SIZE")
-    if a.kernel != "k_mq_cheb_fused":
-        raise SystemExit("only the fused Chebyshev-SGS step is described here")
-    steps = target.get("mq_steps_per_launch", 1)
-    name = f"{a.kernel}<float, {target['mq_tile']}, {steps}>"
-    grid = mq_grid(n, target["mq_tile"], steps)
+    if a.kernel == "k_mq_cheb_fused":
+        steps = target.get("mq_steps_per_launch", 1)
+        name = f"{a.kernel}<float, {target['mq_tile']}, {steps}>"
+        grid = mq_grid(n, target["mq_tile"], steps)
+        workload = f"Stokes cavity {n}x{n}, mixed precision, one launch of the profile loop"
+    elif a.kernel == "k_apply":
+        name = "k_apply<true, false, false>"
+        grid = apply_grid(n)
+        workload = f"Stokes saddle apply with its fused dot, FP64, {n}x{n} (one 336 MB vector in, one out)"
+    else:
+        raise SystemExit("kernels described here: k_mq_cheb_fused, k_apply")
     f_kib, nf = pick(fetch, name, grid)
     w_kib, nw = pick(write, name, grid)
     cf_big, _ = pick(fetch, "k_copy", copy_grid(2048))
@@ -94,7 +109,7 @@ def main():
         sha = hashlib.sha256(f.read()).hexdigest()
     out = {
         "kernel": name, "source": src, "source_sha256": sha,
-        "workload": f"Stokes cavity {n}x{n}, mixed precision, one launch of the profile loop",
+        "workload": workload,
         "bytes_per_launch": round(traffic, 1),
         "algorithmic_bytes_per_launch": target["bytes_per_launch"],
         "fetch_kib_per_dispatch": round(f_kib, 3), "write_kib_per_dispatch": round(w_kib, 3),
