@@ -549,6 +549,7 @@ __global__ __launch_bounds__(APT_NT) void k_ap_tail(ApTail tl, const T* __restri
                                                     Gate gate) {
   __shared__ T qb[APT_Q], qv[2][APT_Q];
   __shared__ double stv[2][APT_V];
+  __shared__ double sdap[APT_Q];   // diag(A_p) of every level, at the level offsets of qb
   const int rhs = blockIdx.x;
   if (gate.off(rhs)) return;   // uniform per block
   const int tid = threadIdx.x;
@@ -561,6 +562,11 @@ __global__ __launch_bounds__(APT_NT) void k_ap_tail(ApTail tl, const T* __restri
       qb[k] = b0[(long long)rhs * nk + k];
       qv[0][k] = T(0);
     }
+    // the Jacobi diagonals are read in every smoothing step: staged once
+    for (int t = 0; t < tl.nlev; ++t) {
+      const int nt = (tl.n[t] + 1) * (tl.n[t] + 1);
+      for (int k = tid; k < nt; k += APT_NT) sdap[tl.off[t] + k] = tl.dAp[t][k];
+    }
   }
   __syncthreads();
   // y = A_p x on level t (MODE 1: Chebyshev step into the other array, MODE 2:
@@ -570,7 +576,11 @@ __global__ __launch_bounds__(APT_NT) void k_ap_tail(ApTail tl, const T* __restri
     const T* X = qv[cur(t)] + tl.off[t];
     T* O = qv[cur(t) ^ 1] + tl.off[t];
     const T* B = qb + tl.off[t];
+    const double* DA = sdap + tl.off[t];
     const double h = tl.h[t], h2 = h * h, sB = -h / 36.0;
+    // 1 / diag(M_v) takes four values per level (by the parities of I, J)
+    const double inv00 = 1.0 / mv_diag(0, 0, h2), inv10 = 1.0 / mv_diag(1, 0, h2),
+                 inv01 = 1.0 / mv_diag(0, 1, h2), inv11 = 1.0 / mv_diag(1, 1, h2);
     for (int k = tid; k < nq * nq; k += APT_NT) {
       const int I = k % nq, J = k / nq;
       double tvx = 0.0, tvy = 0.0;
@@ -586,7 +596,7 @@ __global__ __launch_bounds__(APT_NT) void k_ap_tail(ApTail tl, const T* __restri
             ax += g6(i, dc) * mq6(j, dd) * p;
             ay += mq6(i, dc) * g6(j, dd) * p;
           }
-        const double inv = 1.0 / mv_diag(i, j, h2);
+        const double inv = j ? (i ? inv11 : inv01) : (i ? inv10 : inv00);
         tvx = sB * ax * inv;
         tvy = sB * ay * inv;
       }
@@ -620,7 +630,7 @@ __global__ __launch_bounds__(APT_NT) void k_ap_tail(ApTail tl, const T* __restri
         O[k] = (T)((double)B[k] - y);
       } else {
         const double xc = (double)X[k];
-        double xn = xc + beta * ((double)B[k] - y) / tl.dAp[t][k];
+        double xn = xc + beta * ((double)B[k] - y) / DA[k];
         if (has_prev == 1) xn += alpha * (xc - (double)O[k]);
         else if (has_prev == 2) xn += alpha * xc;
         O[k] = (T)xn;
