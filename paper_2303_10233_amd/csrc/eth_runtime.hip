@@ -183,6 +183,7 @@ struct Problem {
   bool fused_mq = true;              // one launch per Chebyshev step (ETH_DEBUG_UNFUSED_MQ=1: per colour)
   bool fused_q1 = true;              // the PCD's Q_1 solve in one launch (ETH_DEBUG_UNFUSED_Q1=1: per step)
   bool fused_aptail = true;          // A_p levels <= 32^2 in one launch (ETH_DEBUG_UNFUSED_APTAIL=1: per level)
+  int aptail_max_n = 32;             // largest A_p level (elements per side) in that launch (ETH_APTAIL_MAX_N)
   // tile side of the fused Chebyshev step, chosen at set-up for batch 1
   // (lo) and for max_batch (hi)
   // variant of the fused Chebyshev step: tile side and steps per launch
@@ -442,6 +443,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) fused_mq = (e[0] != '1');
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_Q1")) fused_q1 = (e[0] != '1');
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_APTAIL")) fused_aptail = (e[0] != '1');
+  if (const char* e = std::getenv("ETH_APTAIL_MAX_N")) aptail_max_n = std::max(2, std::min(32, std::atoi(e)));
   max_batch = d.max_batch > 0 ? d.max_batch : 1;
   st = static_cast<hipStream_t>(d.stream);
   ETH_HIP(hipEventCreateWithFlags(&ev_poll, hipEventDisableTiming));
@@ -1622,11 +1624,11 @@ void Problem::ap_vcycle(int batch, Gate gate) {
     xo[l] = static_cast<T*>(qxo[l]);
   }
   const int deg = d.gmg_degree;
-  // levels from l0 (the first with n <= 32) down are one launch per RHS
+  // levels from l0 (the first with n <= aptail_max_n) down are one launch per RHS
   int l0 = LQ;
   if (fused_aptail && deg <= 4 && LQ - 1 <= APT_L)
     for (int l = 0; l < LQ; ++l)
-      if (qlv[l].n <= 32) {
+      if (qlv[l].n <= aptail_max_n) {
         l0 = l;
         break;
       }
