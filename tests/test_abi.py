@@ -98,3 +98,48 @@ def test_counter_grid_matches_the_launch_geometry():
     assert mq_grid(256, 24, 2) == 11 * 11 * 1024
     from paper_2303_10233_amd.traffic import apply_grid
     assert apply_grid(2048) == 65 * 257 * 256   # 64 x 16 node tiles of 4097^2 nodes, 256 threads
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w") as f:
+        f.write("Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+        for name, grid, kib in rows:
+            f.write(f'"{name}",{grid},{counter},{kib}\n')
+
+
+def test_traffic_reduction_scales_by_the_copy_calibration(tmp_path):
+    """The byte-counter reduction: each counter of the target kernel is
+    averaged over its dispatches and scaled by bytes / counter of the large
+    copy (FETCH_SIZE reading half the copied bytes gives the factor 2), and
+    the record names the sha256 of the kernel's source file."""
+    import hashlib
+    from paper_2303_10233_amd.traffic import copy_grid, mq_grid
+    half = 335708184.0                                   # bytes read = bytes written by the copy
+    name = "void eth::k_mq_cheb_fused<float, 16, 1>(eth::Geo, float*)"
+    g = mq_grid(256, 16)
+    fetch_rows = [("k_copy(long long)", copy_grid(2048), half / 1024 / 2),
+                  ("k_copy(long long)", copy_grid(256), 1000.0),
+                  (name, g, 2000.0), (name, g, 3000.0),     # mean 2500 KiB
+                  (name, g + 64, 9999.0)]                   # another grid: ignored
+    write_rows = [("k_copy(long long)", copy_grid(2048), half / 1024),
+                  ("k_copy(long long)", copy_grid(256), 2000.0),
+                  (name, g, 1500.0), (name, g, 1500.0)]
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", fetch_rows)
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", write_rows)
+    rec = {"n": 256, "launches": [
+        {"kernel": "k_mq_cheb_fused", "n": 256, "bytes_per_launch": 2631700.0, "mq_tile": 16},
+        {"kernel": "k_copy", "n": 2048, "bytes_per_launch": 2 * half},
+        {"kernel": "k_copy", "n": 256, "bytes_per_launch": 10526768.0}]}
+    (tmp_path / "l.json").write_text("log line\n" + json.dumps(rec) + "\n")
+    out = tmp_path / "t.json"
+    r = subprocess.run([sys.executable, "-m", "paper_2303_10233_amd.traffic", "--fetch", str(tmp_path / "f.csv"),
+                        "--write", str(tmp_path / "w.csv"), "--launches", str(tmp_path / "l.json"),
+                        "--out", str(out)], capture_output=True, text=True, timeout=60, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    d = json.loads(out.read_text())
+    assert d["dispatches"] == {"fetch": 2, "write": 2}
+    assert d["copy_calibration"]["fetch_scale"] == pytest.approx(2.0)
+    assert d["copy_calibration"]["write_scale"] == pytest.approx(1.0)
+    assert d["bytes_per_launch"] == pytest.approx(2500.0 * 1024 * 2 + 1500.0 * 1024, abs=0.1)
+    with open(os.path.join(ROOT, "paper_2303_10233_amd", "csrc", "k_mq.hip"), "rb") as f:
+        assert d["source_sha256"] == hashlib.sha256(f.read()).hexdigest()
