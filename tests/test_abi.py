@@ -143,3 +143,24 @@ def test_traffic_reduction_scales_by_the_copy_calibration(tmp_path):
     assert d["bytes_per_launch"] == pytest.approx(2500.0 * 1024 * 2 + 1500.0 * 1024, abs=0.1)
     with open(os.path.join(ROOT, "paper_2303_10233_amd", "csrc", "k_mq.hip"), "rb") as f:
         assert d["source_sha256"] == hashlib.sha256(f.read()).hexdigest()
+
+
+def test_bench_reports_counted_traffic_only_for_the_counted_kernel():
+    """bench.py's roofline.traffic comes from the committed counter record
+    only while it describes the timed kernel: same template variant and the
+    same source file (sha256); otherwise null."""
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(os.path.join(ROOT, "profiles", "k_mq_cheb_fused_stokes256_traffic.json")) as f:
+        rec = json.load(f)
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2303_10233_amd", "csrc", rec["source"]), "rb") as f:
+        current = hashlib.sha256(f.read()).hexdigest() == rec["source_sha256"]
+    v = bench.measured_traffic("k_mq_cheb_fused", 256, rec["kernel"])
+    if current:
+        assert v == rec["bytes_per_launch"] and v > rec["algorithmic_bytes_per_launch"]
+    else:   # the kernel changed after the counters were read
+        assert v is None
+    assert bench.measured_traffic("k_mq_cheb_fused", 256, "k_mq_cheb_fused<float, 32, 1>") is None
+    assert bench.measured_traffic("k_mq_cheb_fused", 512, rec["kernel"]) is None
+    assert bench.measured_traffic("k_dot", 256, None) is None
