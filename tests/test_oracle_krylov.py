@@ -83,8 +83,27 @@ def test_ideal_preconditioner_three_steps():
     Pd[:nI, :nI] = np.linalg.inv(A)
     Pd[nI:, nI:] = Sp
     ev = np.linalg.eigvals(Pd @ s.K.toarray()).real
-    targets = np.array([0.0, 1.0, (1 + 5 ** 0.5) / 2, (1 - 5 ** 0.5) / 2])
-    assert np.abs(ev[:, None] - targets[None, :]).min(axis=1).max() < 1e-8
+    targets = _golden_spectrum()
+    dist = np.abs(ev[:, None] - targets[None, :])
+    assert dist.min(axis=1).max() < 1e-8          # every eigenvalue is a printed one
+    assert (dist.min(axis=0) < 1e-8).all()         # and every printed one occurs
+
+
+def _golden_spectrum():
+    """The eigenvalues the paper prints for the ideal block preconditioner
+    (tests/golden/ideal_block_preconditioner_spectrum.txt, Sec. 2)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ideal_block_preconditioner_spectrum.txt")
+    vals = []
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                value, expr = line.split()
+                exact = {"0": 0.0, "1": 1.0, "(1-sqrt(5))/2": (1 - 5 ** 0.5) / 2,
+                         "(1+sqrt(5))/2": (1 + 5 ** 0.5) / 2}[expr]
+                assert abs(float(value) - exact) < 1e-15
+                vals.append(float(value))
+    return np.array(vals)
 
 
 def test_minres_p1_reaches_direct_solution():
