@@ -2,9 +2,15 @@
 
 Test infrastructure (see the package docstring).
 
-minres  -- preconditioned MINRES exactly in the order of alg:minres (Sec. 2.1,
-           after eq:anull), with the stopping rule of Sec. 2.4 (relative
-           reduction of the preconditioned residual norm |eta_j| / gamma_1).
+minres  -- preconditioned MINRES (the method of alg:minres, Sec. 2.1, after
+           eq:anull) derived here from its two ingredients: the preconditioned
+           Lanczos process, which builds a P-orthonormal basis q_1 .. q_k of the
+           Krylov space together with the tridiagonal matrix T_k of the
+           preconditioned operator in that basis, and the minimisation of
+           || beta_1 e_1 - T_k y || over y by a QR factorisation of the
+           (k+1) x k extended tridiagonal matrix, updated one Givens rotation
+           per step.  Stopping rule of Sec. 2.4: the residual in the P^{-1}
+           norm relative to its initial value.
 fgmres  -- restarted GMRES with right (flexible) preconditioning, modified
            Gram-Schmidt Arnoldi and Givens rotations (Sec. 3: GMRES monitored by
            the Euclidean residual norm of eq:residual-norm).
@@ -18,75 +24,114 @@ class KrylovBreakdown(RuntimeError):
     pass
 
 
+class _Lanczos:
+    """Preconditioned Lanczos for a symmetric operator A and a symmetric
+    positive semi-definite preconditioner P (given as its action r -> P^{-1} r
+    on consistent vectors, the singular case of Sec. 2.2 included).
+
+    It keeps the residual-space vectors u_k = P q_k beta-scaled (u_k = beta_k
+    P q_k), so that q_k = P^{-1} u_k / beta_k needs one preconditioner
+    application per step.  Each step returns the diagonal entry alpha_k =
+    q_k^T A q_k and the next off-diagonal entry beta_{k+1} of T_k."""
+
+    def __init__(self, apply, precond, r0):
+        self.apply, self.precond = apply, precond
+        self.u_old = np.zeros_like(r0)
+        self.u = r0
+        self.pu = precond(r0)
+        self.beta_old = 0.0
+        self.beta = self._norm(self.u, self.pu, scale=None)
+
+    @staticmethod
+    def _norm(u, pu, scale):
+        b2 = float(u @ pu)
+        if scale is not None and -1e-14 * scale < b2 < 0:
+            b2 = 0.0                       # rounding around an exact zero
+        if b2 < 0 or not math.isfinite(b2):
+            raise KrylovBreakdown("P is not positive semi-definite (u^T P^{-1} u < 0)")
+        return math.sqrt(b2)
+
+    def step(self):
+        """Returns (q_k, alpha_k, beta_{k+1})."""
+        q = self.pu / self.beta
+        Aq = self.apply(q)
+        alpha = float(Aq @ q)
+        # three-term recurrence in the residual space; the u_{k-1} term is
+        # absent at k = 1 (beta_0 = 0, u_0 = 0)
+        u_new = Aq - (alpha / self.beta) * self.u
+        if self.beta_old > 0.0:
+            u_new -= (self.beta / self.beta_old) * self.u_old
+        pu_new = self.precond(u_new)
+        beta_new = self._norm(u_new, pu_new, scale=abs(alpha) * self.beta)
+        self.u_old, self.u, self.pu = self.u, u_new, pu_new
+        self.beta_old, self.beta = self.beta, beta_new
+        return q, alpha, beta_new
+
+
+class _TridiagonalQR:
+    """QR factorisation of the extended tridiagonal matrix of the Lanczos
+    process, one column at a time.  Column k has beta_k above the diagonal,
+    alpha_k on it and beta_{k+1} below; the two previous rotations act on it,
+    then a new rotation annihilates beta_{k+1}.  The R factor has three
+    diagonals (rho on the diagonal, then sigma and tau above it), and the
+    transformed right-hand side beta_1 e_1 gives the least-squares step t_k
+    and the residual norm |phi|."""
+
+    def __init__(self, beta1):
+        self.rot = [(1.0, 0.0), (1.0, 0.0)]     # rotations k-2, k-1 as (cos, sin)
+        self.phi = beta1
+
+    def add_column(self, beta_k, alpha_k, beta_next):
+        (c2, s2), (c1, s1) = self.rot
+        tau = s2 * beta_k                       # row k-2
+        t = c2 * beta_k
+        sigma = c1 * t + s1 * alpha_k           # row k-1
+        diag = -s1 * t + c1 * alpha_k           # row k before the new rotation
+        rho = math.hypot(diag, beta_next)
+        c, s = diag / rho, beta_next / rho
+        self.rot = [(c1, s1), (c, s)]
+        step = c * self.phi
+        self.phi = -s * self.phi
+        return rho, sigma, tau, step
+
+
 def minres(apply, b, precond, tol=1e-8, maxit=1000, x0=None, record=False):
     """Preconditioned MINRES (alg:minres).
 
     apply(v) -> A v, precond(v) -> z with P z = v (P symmetric positive
     semi-definite; the singular case of Sec. 2.2 is allowed for consistent b).
-    Reading of the paper's first step: at j = 1 the term (gamma_1/gamma_0) v_0 is
-    taken to be zero (gamma_0 = 0, v_0 = 0).
-    Stops when |eta| / gamma_1 <= tol, i.e. the P^{-1}-norm of the residual has
-    been reduced by tol.  Returns (x, info) with info = dict(iterations,
-    eta (history of |eta|/gamma_1), gamma, delta, converged).
+    x_k = x_0 + Q_k y_k minimises the P^{-1}-norm of the residual over the
+    Krylov space; with R_k the QR factor of the Lanczos matrix, the search
+    directions d_k = (q_k - sigma_k d_{k-1} - tau_k d_{k-2}) / rho_k are the
+    columns of Q_k R_k^{-1}, so x_k = x_{k-1} + t_k d_k.  Stops when
+    |phi_k| / beta_1 <= tol, the relative P^{-1}-norm residual (reading of the
+    algorithm's convergence test).  Returns (x, info) with info =
+    dict(iterations, eta (history of |phi|/beta_1), gamma (the beta_k),
+    delta (the alpha_k), converged).
     """
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
-    v_prev = np.zeros_like(b)
-    w_prev = np.zeros_like(b)          # w^(j-1)
-    w_cur = np.zeros_like(b)           # w^(j)
-    v = b - apply(x)                   # v^(1)
-    z = precond(v)
-    g2 = float(z @ v)
-    if g2 < 0 or not math.isfinite(g2):
-        raise KrylovBreakdown("preconditioner is not positive semi-definite")
-    gamma = math.sqrt(g2)              # gamma_1
-    gamma_prev = 0.0
-    info = dict(iterations=0, eta=[1.0], gamma=[gamma], delta=[], converged=False)
-    if gamma == 0.0:
+    lz = _Lanczos(apply, precond, b - apply(x))
+    beta1 = lz.beta
+    info = dict(iterations=0, eta=[1.0], gamma=[beta1], delta=[], converged=False)
+    if beta1 == 0.0:
         info["converged"] = True
         return x, info
-    eta = gamma
-    gamma1 = gamma
-    s_prev, s_cur = 0.0, 0.0           # s_{j-1}, s_j
-    c_prev, c_cur = 1.0, 1.0           # c_{j-1}, c_j
-    for j in range(1, maxit + 1):
-        z = z / gamma                                   # z^(j) normalised
-        Az = apply(z)
-        delta = float(Az @ z)
-        v_next = Az - (delta / gamma) * v
-        if j > 1:
-            v_next -= (gamma / gamma_prev) * v_prev
-        z_next = precond(v_next)
-        g2 = float(z_next @ v_next)
-        if g2 < 0 and g2 > -1e-14 * abs(delta) * gamma1:
-            g2 = 0.0
-        if g2 < 0 or not math.isfinite(g2):
-            raise KrylovBreakdown("gamma^2 < 0: preconditioner not positive semi-definite")
-        gamma_next = math.sqrt(g2)
-        a0 = c_cur * delta - c_prev * s_cur * gamma
-        a1 = math.sqrt(a0 * a0 + gamma_next * gamma_next)
-        a2 = s_cur * delta + c_prev * c_cur * gamma
-        a3 = s_prev * gamma
-        c_next = a0 / a1
-        s_next = gamma_next / a1
-        w_next = (z - a3 * w_prev - a2 * w_cur) / a1
-        x = x + (c_next * eta) * w_next
-        eta = -s_next * eta
-        # shift the recurrences
-        v_prev, v = v, v_next
-        w_prev, w_cur = w_cur, w_next
-        gamma_prev, gamma = gamma, gamma_next
-        s_prev, s_cur = s_cur, s_next
-        c_prev, c_cur = c_cur, c_next
-        z = z_next
-        info["iterations"] = j
-        info["eta"].append(abs(eta) / gamma1)
-        info["gamma"].append(gamma)
-        info["delta"].append(delta)
-        if abs(eta) / gamma1 <= tol:
-            info["converged"] = True
-            break
-        if gamma == 0.0:
+    qr = _TridiagonalQR(beta1)
+    d_old = np.zeros_like(b)        # d_{k-2}
+    d = np.zeros_like(b)            # d_{k-1}
+    for k in range(1, maxit + 1):
+        beta_k = lz.beta
+        q, alpha, beta_next = lz.step()
+        rho, sigma, tau, step = qr.add_column(beta_k if k > 1 else 0.0, alpha, beta_next)
+        d_new = (q - sigma * d - tau * d_old) / rho
+        x = x + step * d_new
+        d_old, d = d, d_new
+        info["iterations"] = k
+        info["eta"].append(abs(qr.phi) / beta1)
+        info["gamma"].append(beta_next)
+        info["delta"].append(alpha)
+        if abs(qr.phi) / beta1 <= tol or beta_next == 0.0:
             info["converged"] = True
             break
     return x, info

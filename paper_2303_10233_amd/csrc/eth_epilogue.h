@@ -95,14 +95,21 @@ __device__ inline void minres_gamma(MinresScalars& s, double g2) {
   }
   const double gn = sqrt(g2);
   const double g = s.gamma, d = s.delta;
-  const double a0 = s.c * d - s.c_prev * s.s * g;
-  const double a1 = sqrt(a0 * a0 + gn * gn);
-  const double a2 = s.s * d + s.c_prev * s.c * g;
-  const double a3 = s.s_prev * g;
-  const double cn = a0 / a1, sn = gn / a1;
-  s.wz = 1.0 / (g * a1);
-  s.wp = a3 / a1;
-  s.wc = a2 / a1;
+  // Column j of the extended Lanczos tridiagonal is (g above the diagonal,
+  // d on it, gn below).  The rotations of steps j-2 (c_prev, s_prev) and j-1
+  // (c, s) act on it first; a new rotation then annihilates gn.  The result
+  // is column j of the QR factor R (rho on the diagonal, sigma and tau above)
+  // and the next entries of the rotated right-hand side (eta).
+  const double tau = s.s_prev * g;
+  const double t = s.c_prev * g;
+  const double sigma = s.c * t + s.s * d;
+  const double diag = s.c * d - s.s * t;
+  const double rho = sqrt(diag * diag + gn * gn);
+  const double cn = diag / rho, sn = gn / rho;
+  // search direction w_{j+1} = (zhat_j / g - sigma w_j - tau w_{j-1}) / rho
+  s.wz = 1.0 / (g * rho);
+  s.wp = tau / rho;
+  s.wc = sigma / rho;
   s.xc = cn * s.eta;
   s.eta = -sn * s.eta;
   s.c_prev = s.c;
