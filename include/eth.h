@@ -252,6 +252,21 @@ int eth_grad_viscosity(eth_problem* p, const double* lambda, const double* x, do
 int eth_misfit(eth_problem* p, const double* x, const double* x_target, double* J,
                double* grad, int64_t batch, int64_t ld);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): eth_misfit
+ * without a problem handle.  desc supplies n, the domain (square) and the
+ * stream; every other field is ignored.  x, x_target, J, grad as for
+ * eth_misfit (grad may be NULL).  Allocates nothing: the partial sums of the
+ * reduction go to a fixed 2 MiB device array of the library (one per GPU,
+ * held until the process ends), so batch * 2 * ceil((2n+1)^2 / 256) must not
+ * exceed 262144 (one right-hand side up to n = 2048, eight at n = 1024);
+ * larger calls return ETH_EINVAL with a message in eth_last_error(NULL).
+ * The current device must be the one holding the vectors and the stream.
+ * Calls that overlap in time on one GPU share that array and race: order
+ * them on one stream (the array keeps the last call's partial sums). */
+int eth_misfit_noalloc(const eth_problem_desc* desc, const double* x, const double* x_target,
+                       double* J, double* grad, int64_t batch, int64_t ld);
+
 /* Ragged batches: several Stokes problems of different sizes (e.g. cavities
  * of 32..256 elements per side) solved together.  Every problem gets its own
  * stream and workspaces; eth_batch_solve starts all MINRES solves, keeps each

@@ -42,6 +42,10 @@ inline Geo make_geo(int n, double h) {
 
 constexpr int kWave = 64;
 
+// message of the last failing call made without a handle (eth_setup and the
+// handle-free entry points); read by eth_last_error(NULL)
+extern thread_local std::string g_setup_error;
+
 // ----------------------------------------------------------------------------
 // XCD band order.  The eight XCDs take a grid's workgroups round-robin, each
 // with its own L2; a tiled stencil kernel whose vertically neighbouring tiles

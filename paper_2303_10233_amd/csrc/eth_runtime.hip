@@ -20,7 +20,7 @@
 
 namespace eth {
 
-static thread_local std::string g_setup_error;
+thread_local std::string g_setup_error;
 
 struct Buf {
   void* p = nullptr;

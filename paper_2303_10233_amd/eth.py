@@ -154,6 +154,8 @@ def load_library(path=LIB_PATH):
     lib.eth_grad_viscosity.restype = ctypes.c_int
     lib.eth_misfit.argtypes = [P, P, P, P, P, i64, i64]
     lib.eth_misfit.restype = ctypes.c_int
+    lib.eth_misfit_noalloc.argtypes = [ctypes.POINTER(ProblemDesc), P, P, P, P, i64, i64]
+    lib.eth_misfit_noalloc.restype = ctypes.c_int
     lib.eth_solve.restype = ctypes.c_int
     lib.eth_profile_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, i64,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -457,6 +459,29 @@ class Problem:
         g2 = _as_batch(gr, self.N)[0] if grad else None
         _check(lib().eth_misfit(self._h, _ptr(x2), _ptr(t2), _ptr(J), _ptr(g2), B, ld), self._h)
         return (J if x.dim() > 1 else J[0]), gr
+
+
+def misfit_noalloc(x, x_target, n, domain=(0.0, 1.0, 0.0, 1.0), grad=True, J=None, out_grad=None):
+    """eth_misfit_noalloc: (J, dJ/dx) as Problem.misfit computes them, without a
+    problem handle and without any device allocation in the library.  J and
+    out_grad may be given (preallocated) so that the call allocates nothing on
+    the torch side either; otherwise they are created here."""
+    N = 2 * (2 * n + 1) ** 2 + (n + 1) ** 2 + n * n
+    x2, B, ld = _as_batch(x, N)
+    t2, _, ldt = _as_batch(x_target, N)
+    if ldt != ld:
+        raise ValueError("x and x_target need the same stride")
+    if J is None:
+        J = torch.empty((B,), dtype=torch.float64, device=x.device)
+    gr = out_grad if out_grad is not None else (torch.empty_like(x) if grad else None)
+    g2 = _as_batch(gr, N)[0] if gr is not None else None
+    d = ProblemDesc()
+    d.n = n
+    d.x0, d.x1, d.y0, d.y1 = domain
+    with torch.cuda.device(x.device):
+        d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        _check(lib().eth_misfit_noalloc(ctypes.byref(d), _ptr(x2), _ptr(t2), _ptr(J), _ptr(g2), B, ld))
+    return (J if x.dim() > 1 else J[0]), gr
 
 
 class FlowSolve(torch.autograd.Function):
