@@ -46,6 +46,8 @@ extern "C" {
 #define ETH_EBREAKDOWN    -5  /* Krylov breakdown (gamma^2 < 0, NaN or Inf)         */
 #define ETH_EUNSUPPORTED  -6  /* option combination not available                   */
 #define ETH_WMAXIT         1  /* iteration limit reached; x holds the last iterate  */
+#define ETH_WNOPROGRESS    2  /* FGMRES ended with a true residual above that of the
+                                 initial guess; x holds the initial guess           */
 
 typedef struct eth_problem eth_problem;
 
@@ -104,6 +106,14 @@ typedef struct {
   int32_t mq_fuse_steps;     /* Chebyshev steps per launch, 1 or 2 (2 needs tile
                                 16 or 24 and ETH_MIXED); 0: 1 when mq_tile is
                                 given, else timed at setup                      */
+  double gmg_peclet_max;     /* Oseen: > 0 caps the element Peclet number of every
+                                level of the F multigrid: level l smooths and
+                                solves nu_l A + N(w) with nu_l = max(nu,
+                                max|w| h_l / (2 gmg_peclet_max)); the Krylov
+                                method still solves the Galerkin F.  Keeps the
+                                damped-Jacobi cycle a contraction where the
+                                unstabilised F is convection dominated (element
+                                Peclet >= 8, e.g. nu = 1/1000 on 256^2).  0: off */
 } eth_problem_desc;
 
 typedef struct {
@@ -120,6 +130,26 @@ typedef struct {
   int32_t use_x0;            /* 1: x holds the initial guess on entry               */
   int32_t use_graph;         /* 1: replay the iteration as a captured hipGraph      */
   int32_t true_residual;     /* 1: compute ||b - K x||/||b|| into info (default 0)   */
+  int32_t refine;            /* MINRES: at most this many FP64 defect-correction
+                                restarts (default 0).  When the recurrence has met
+                                rtol, the residual b - K x is formed again in FP64
+                                and MINRES restarts from x until the P^{-1}-norm of
+                                that true residual is <= rtol * gamma_1 (gamma_1 of
+                                the first start).  With an FP32 preconditioner the
+                                recurrence's |eta| and the true residual part below
+                                about 1e-7; the restarts close that gap.           */
+  double* residual_history;  /* host, batch x history_len doubles, or NULL: per
+                                right-hand side the stopping quantity before the
+                                first and after every iteration -- MINRES
+                                |eta_j|/gamma_1 (a refinement restart continues the
+                                sequence with the P^{-1}-norm of its FP64 residual
+                                over gamma_1); FGMRES the Arnoldi estimate of
+                                ||b-Kx_j||_2/||b||_2; TWO_STAGE the stage-I
+                                sequence (reduced system) followed by the stage-II
+                                one, whose first entry is the full residual of the
+                                stage-I iterate (Sec. 3.1: it jumps up where the
+                                P0 rows enter).  Entries past the end are -1.     */
+  int32_t history_len;       /* entries per right-hand side of residual_history     */
 } eth_solve_opts;
 
 typedef struct {
@@ -170,6 +200,14 @@ int eth_apply_preconditioner(eth_problem* p, int transpose, const double* r, dou
 /* Solve K x = b (b from eth_assemble_rhs).  x receives the boundary data on
  * boundary rows, the Krylov solution elsewhere, the pressure canonicalised if
  * opts->canonicalize.  info: host array of `batch` entries, or NULL.
+ * Consistency (Sec. 2.2): the flow is enclosed (Dirichlet velocity on the
+ * whole boundary), so null(K^T) = span{[0; 1_{n_k}; 0], [0; 0; 1_{n_0}]} and
+ * K x = b is solvable only if both pressure blocks of b sum to zero.  Before
+ * iterating, every right-hand side is checked: when the component of the
+ * interior b in that null space exceeds 1e-12 ||b_interior||_2 the call
+ * returns ETH_EINCONSISTENT, and when b holds a NaN or Inf it returns
+ * ETH_EINVAL; x is then not written and info (if given) receives the status
+ * of every right-hand side with zero iterations.
  * Methods: ETH_MINRES (Stokes; alg:minres with P), ETH_FGMRES (Oseen, right
  * preconditioned by M_1, restarted), ETH_TWO_STAGE (Oseen, Sec. 3.1: stage I
  * FGMRES on the reduced system with PCD until ||r|| <= c*rtol*||b||, stage II

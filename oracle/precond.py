@@ -399,14 +399,37 @@ def inject_q2(field_fine, fine, coarse):
     return np.concatenate([field_fine[: fine.nv][idx], field_fine[fine.nv:][idx]])
 
 
-def oseen_level_operator(fine_mesh, wind, nu):
+def wind_speed_max(wind, mesh):
+    """max over the Q2 nodes of the Euclidean length of the nodal wind."""
+    return float(np.sqrt(wind[: mesh.nv] ** 2 + wind[mesh.nv:] ** 2).max())
+
+
+def level_viscosity(nu, h, wmax, peclet_max=None):
+    """Viscosity of a multigrid level of element side h.  With peclet_max
+    given, the level operator is nu_l A + N with
+        nu_l = max(nu, wmax * h / (2 * peclet_max)),
+    so that its element Peclet number wmax * h / (2 nu_l) is at most
+    peclet_max: where the unstabilised Galerkin operator is convection
+    dominated, the cycle approximates the inverse of a more diffusive
+    operator (the paper's experiments have mesh Peclet numbers of order one
+    and say nothing about this regime; see the V-cycle docstrings)."""
+    if peclet_max is None:
+        return nu
+    return max(nu, wmax * h / (2.0 * peclet_max))
+
+
+def oseen_level_operator(fine_mesh, wind, nu, peclet_max=None):
     """make_op for the GMG of F = nu A + N(w): on every level the wind is the
-    injection of the finest-level nodal wind."""
+    injection of the finest-level nodal wind and the viscosity is
+    level_viscosity(nu, h_l, max |w|, peclet_max) (nu itself when
+    peclet_max is None)."""
     from .assemble import convection
+    wmax = wind_speed_max(wind, fine_mesh)
 
     def make(mesh):
         w = wind if mesh.n == fine_mesh.n else inject_q2(wind, fine_mesh, mesh)
-        return nu * laplacian(mesh) + convection(mesh, w)
+        nul = level_viscosity(nu, mesh.h, wmax, peclet_max)
+        return nul * laplacian(mesh) + convection(mesh, w)
     return make
 
 
@@ -519,10 +542,16 @@ class PCDStage1Inexact(PCDStage1):
         return self.apgmg(self.F1 @ self.q1_inv(rp))
 
 
-def oseen_velocity_gmg(system, omega=0.7, sweeps=2, coarse_n=32):
-    """F^{-1} approximation for both velocity components of an Oseen system
-    (parity unpinned as a whole, see GMGJacobi)."""
-    g = GMGJacobi(system.mesh, oseen_level_operator(system.mesh, system.wind, system.nu),
+def oseen_velocity_gmg(system, omega=0.7, sweeps=2, coarse_n=32, peclet_max=None):
+    """F^{-1} approximation for both velocity components of an Oseen system:
+    one GMGJacobi cycle per component; with peclet_max the level operators
+    carry the viscosity of level_viscosity (the finest included), which keeps
+    damped Jacobi a smoother where the Galerkin F is convection dominated
+    (at element Peclet numbers of 8 and more the unmodified cycle amplifies
+    the error and preconditions nothing).  Pinned as a whole operator
+    against the dense V-cycle formula."""
+    g = GMGJacobi(system.mesh,
+                  oseen_level_operator(system.mesh, system.wind, system.nu, peclet_max),
                   omega=omega, sweeps=sweeps, coarse_n=coarse_n)
     m = g.A[0].shape[0]
     return (lambda r: np.concatenate([g.vcycle(0, r[:m]), g.vcycle(0, r[m:])])), g

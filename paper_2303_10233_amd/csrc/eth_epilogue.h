@@ -25,6 +25,7 @@ struct MinresScalars {
   double gamma, gamma_prev, gamma1, delta, eta;
   double c, c_prev, s, s_prev;
   double tol;
+  double tol_abs;      // > 0: stop when |eta| <= tol_abs instead (refinement restarts)
   double vy, va, vb;   // v_{j+1} = vy*y - va*v_j - vb*v_{j-1},  y = K zhat_j
   double wz, wp, wc;   // w_{j+1} = wz*zhat_j - wp*w_{j-1} - wc*w_j
   double xc;           // x_j = x_{j-1} + xc*w_{j+1}
@@ -69,7 +70,7 @@ __device__ inline void minres_init(MinresScalars& s, double g2) {
   s.rel = 1.0;
   s.wx_todo = 0;
   s.status = kStOK;
-  s.active = (g > 0.0) ? 1 : 0;
+  s.active = (g > 0.0 && !(s.tol_abs > 0.0 && g <= s.tol_abs)) ? 1 : 0;
   if (s.hist && s.hist_len > 0) s.hist[0] = 1.0;
   if (s.hist_gamma && s.hist_len > 0) s.hist_gamma[0] = g;
 }
@@ -123,7 +124,7 @@ __device__ inline void minres_gamma(MinresScalars& s, double g2) {
   if (s.hist && s.iters < s.hist_len) s.hist[s.iters] = s.rel;
   if (s.hist_gamma && s.iters < s.hist_len) s.hist_gamma[s.iters] = gn;
   s.wx_todo = 1;
-  if (s.rel <= s.tol || gn == 0.0) {
+  if ((s.tol_abs > 0.0 ? fabs(s.eta) <= s.tol_abs : s.rel <= s.tol) || gn == 0.0) {
     s.active = 0;
   } else if (s.iters >= s.maxit) {
     s.active = 0;

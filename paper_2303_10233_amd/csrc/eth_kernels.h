@@ -103,6 +103,17 @@ void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* 
 template <typename T>
 void launch_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int nplanes,
                         int batch, Gate gate, hipStream_t st);
+// the second pre-smoothing step (has_prev 2, from x1 to x2, written to x2out
+// on the fine nodes) fused with the restriction of the residual of x2
+template <typename T>
+void launch_restrict_pre(const Geo& gf, const Geo& gc, const T* bf, const T* x1, T* x2out, double alpha,
+                         double beta, T* bc, T* xc, double beta_c, int nplanes, Gate gate, hipStream_t st);
+// x0 = xold + P xc, then two Chebyshev steps (beta0; alpha1, beta1), result
+// to xout (or out64 times out_scale)
+template <typename T>
+void launch_post2(const Geo& gf, const Geo& gc, const T* b, const T* xold, const T* xc, T* xout, double alpha1,
+                  double beta0, double beta1, int nplanes, double* out64, long long ld64, double out_scale,
+                  Gate gate, hipStream_t st);
 // dense coarse solve: x = Ainv * b on the interior nodes of each plane, with
 // the FP32 copy AinvF of the inverse when given; gbuf: 2*ni*batch doubles
 template <typename T>
@@ -180,6 +191,8 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
 // ---------------- Oseen preconditioner pieces (k_oseen.hip) ------------------
 void launch_inject_wind(const Geo& gf, const Geo& gc, const double* wf, double* wc, hipStream_t st);
 void launch_cd_diag(const Geo& g, const double* wind, double nu, double* dF, hipStream_t st);
+// *out = max over the Q2 nodes of |w| (device scalar)
+void launch_wind_speed_max(const Geo& g, const double* wind, double* out, hipStream_t st);
 // the coarse F as a dense row-major ni x ni matrix (A zero on entry)
 void launch_dense_convdiff(const Geo& g, const double* wind, double nu, double* A, int ni,
                            hipStream_t st);

@@ -220,6 +220,7 @@ struct Problem {
   double* f_work = nullptr;                 // blocked Gauss-Jordan workspace of the coarse F
   double* pic_b = nullptr;                  // right-hand side of a Picard step (N)
   std::vector<double*> lwind, ldF;          // wind and diag(F) per velocity level
+  std::vector<double> lnu;                  // viscosity of each F level (Peclet cap)
   std::vector<float*> lwindF;               // FP32 copy of each level's wind (mixed precision)
   // the wind of level l in the smoother's storage type
   template <typename T>
@@ -249,8 +250,10 @@ struct Problem {
 
   // graph cache (keyed by batch); graphs are captured and replayed on the
   // internal stream gst, joined to the caller's stream with events
-  hipGraphExec_t gexec = nullptr;
-  int gexec_batch = -1;
+  hipGraphExec_t gexecs[2] = {nullptr, nullptr};   // 2 and graph_iters iterations
+  int gexec_key[2] = {-1, -1};
+  int graph_iters = 2;               // iterations per long replayed graph (ETH_GRAPH_ITERS)
+  hipGraphExec_t iteration_graph(int batch, int iters);
   // captured Arnoldi chunks of FGMRES: (kind, reduced, transpose, batch, j0, j1) -> graph
   std::map<std::array<int, 6>, hipGraphExec_t> gm_graphs;
   hipStream_t gst = nullptr;
@@ -272,7 +275,8 @@ struct Problem {
   }
 
   ~Problem() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto& ge : gexecs)
+      if (ge) (void)hipGraphExecDestroy(ge);
     for (auto& kv : gm_graphs) (void)hipGraphExecDestroy(kv.second);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -380,7 +384,21 @@ struct Problem {
     double tol = 0.0, prev_rel = 1.0;
     int maxit = 0, done = 0, chunk = 8, prev_it = 0;
     bool use_graph = false;
+    // FP64 defect-correction restarts (opts.refine) and the per-RHS record
+    // kept across them: gamma_1 of the first start, iterations, the final
+    // |eta| / gamma_1 and (when asked for) the residual history
+    int refine_left = 0, runs = 0;
+    std::vector<double> gamma0, rel;
+    std::vector<int> iters;
+    std::vector<std::vector<double>> hist;
   };
+  void minres_end_of_run(MinresRun& R);
+  void minres_restart(MinresRun& R);
+  // per-RHS status of the right-hand sides b (0, ETH_EINCONSISTENT or
+  // ETH_EINVAL); consistency = false checks finiteness only
+  std::vector<int> check_rhs(const double* b, long long ld, int batch, bool consistency);
+  double mq_sign = 1.0;              // -1 under ETH_DEBUG_NEGATE_MQ (indefinite preconditioner)
+  bool fused_smooth = true;          // V(2,2) smoothing fused into restriction / correction launches
   hipEvent_t ev_poll = nullptr;
   void minres_begin(MinresRun& R);
   void minres_enqueue_chunk(MinresRun& R);
@@ -421,6 +439,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (!(d.mq_cheb_hi > d.mq_cheb_lo)) throw std::invalid_argument("mq interval empty");
   if (d.gmg_coarse_n <= 0) d.gmg_coarse_n = oseen ? 32 : 4;
   if (d.gmg_omega <= 0.0) d.gmg_omega = 0.7;
+  if (d.gmg_peclet_max < 0.0) throw std::invalid_argument("gmg_peclet_max must be >= 0");
   if (d.pcd_q1_steps <= 0) d.pcd_q1_steps = 10;
   if (d.gmres_restart <= 0) d.gmres_restart = 50;
   if (d.gmres_restart > 63) throw std::invalid_argument("gmres_restart must be <= 63");
@@ -440,7 +459,12 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.precision != ETH_FP64 && d.precision != ETH_MIXED)
     throw std::invalid_argument("invalid precision");
   mixed = d.precision == ETH_MIXED;
+  // failure-path tests: a negated pressure block makes the Stokes
+  // preconditioner indefinite, which MINRES reports as a breakdown
+  if (const char* e = std::getenv("ETH_DEBUG_NEGATE_MQ")) mq_sign = (e[0] == '1') ? -1.0 : 1.0;
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) fused_mq = (e[0] != '1');
+  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_SMOOTH")) fused_smooth = (e[0] != '1');
+  if (const char* e = std::getenv("ETH_GRAPH_ITERS")) graph_iters = std::max(2, std::min(64, std::atoi(e) & ~1));
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_Q1")) fused_q1 = (e[0] != '1');
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_APTAIL")) fused_aptail = (e[0] != '1');
   if (const char* e = std::getenv("ETH_APTAIL_MAX_N")) aptail_max_n = std::max(2, std::min(32, std::atoi(e)));
@@ -853,17 +877,26 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
   }
   const int np = 2 * batch;
   const int deg = d.gmg_degree;
+  // V(2,2): the second pre-smoothing step rides in the restriction's launch
+  // and the correction with both post-smoothing steps in one launch per level
+  const bool fuse = fused_smooth && deg == 2;
   // finest level: b = r_u, first smoothing step from zero
   launch_vcycle_entry<T>(lv[0], r, ld, b[0], x[0], cb[0][0], batch, gate, st);
   // levels below `lstop` are handled by the fused coarse kernel when enabled
   const int lstop = tail_l0 >= 1 ? tail_l0 : L - 1;
   for (int l = 0; l < lstop; ++l) {
+    const double beta_c = (l + 1 < L - 1) ? cb[l + 1][0] : 0.0;
+    if (fuse) {
+      launch_restrict_pre<T>(lv[l], lv[l + 1], b[l], x[l], xo[l], ca[l][1], cb[l][1], b[l + 1], x[l + 1],
+                             beta_c, np, gate, st);
+      std::swap(x[l], xo[l]);
+      continue;
+    }
     for (int k = 1; k < deg; ++k) {
       launch_cheb_step<T>(lv[l], b[l], x[l], xo[l], ca[l][k], cb[l][k], k == 1 ? 2 : 1, np,
                           nullptr, 0, 0.0, gate, batch, st);
       std::swap(x[l], xo[l]);
     }
-    const double beta_c = (l + 1 < L - 1) ? cb[l + 1][0] : 0.0;
     launch_restrict<T>(lv[l], lv[l + 1], b[l], x[l], b[l + 1], x[l + 1], beta_c, np, batch, gate, st);
   }
   if (tail_l0 >= 1)
@@ -872,6 +905,12 @@ void Problem::vcycle(const double* r, double* z, long long ld, int batch, Gate g
     launch_dense_solve<T>(lv[L - 1], Ainv, AinvF, coarse_ni, b[L - 1], x[L - 1], np, nullptr, 0, 0.0,
                           nullptr, 0, dense_gbuf, batch, gate, st);
   for (int l = lstop - 1; l >= 0; --l) {
+    if (fuse) {
+      launch_post2<T>(lv[l], lv[l + 1], b[l], x[l], x[l + 1], xo[l], ca[l][1], cb[l][0], cb[l][1], np,
+                      l == 0 ? z : nullptr, ld, sc, gate, st);
+      if (l > 0) std::swap(x[l], xo[l]);
+      continue;
+    }
     launch_prolong_add<T>(lv[l], lv[l + 1], x[l + 1], x[l], np, batch, gate, st);
     for (int k = 0; k < deg; ++k) {
       const bool last = (l == 0 && k == deg - 1);
@@ -1084,11 +1123,11 @@ void Problem::precond(const double* r, double* z, long long ld, int batch, Gate 
         ~Restore() { s = v; }
       } restore{st, st};
       st = pst;
-      mq_solve(r, z, ld, batch, gate, d.nu, !in_krylov);
+      mq_solve(r, z, ld, batch, gate, mq_sign * d.nu, !in_krylov);
     }
     ETH_HIP(hipEventRecord(ev_pj, pst));
   } else {
-    mq_solve(r, z, ld, batch, gate, d.nu, !in_krylov);
+    mq_solve(r, z, ld, batch, gate, mq_sign * d.nu, !in_krylov);
   }
   if (mixed) vcycle<float>(r, z, ld, batch, gate);
   else vcycle<double>(r, z, ld, batch, gate);
@@ -1117,30 +1156,47 @@ void Problem::minres_iteration(int batch, int parity) {
   launch_minres_wx(g.N, z, wp, w, kx, ldw, batch, d_ms, st);   // wp <- w_{j+1}
 }
 
+// The captured graph of `iters` (even) MINRES iterations for `batch`
+// right-hand sides, captured on the current stream at first use.
+hipGraphExec_t Problem::iteration_graph(int batch, int iters) {
+  const int slot = iters == 2 ? 0 : 1;
+  if (gexecs[slot] && gexec_key[slot] == batch * 1024 + iters) return gexecs[slot];
+  if (gexecs[slot]) {
+    ETH_HIP(hipGraphExecDestroy(gexecs[slot]));
+    gexecs[slot] = nullptr;
+  }
+  hipGraph_t graph;
+  ETH_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < iters; ++i) minres_iteration(batch, i & 1);
+  ETH_HIP(hipStreamEndCapture(st, &graph));
+  ETH_HIP(hipGraphInstantiate(&gexecs[slot], graph, nullptr, nullptr, 0));
+  ETH_HIP(hipGraphDestroy(graph));
+  gexec_key[slot] = batch * 1024 + iters;
+  return gexecs[slot];
+}
+
 void Problem::run_iterations(int batch, int count, bool use_graph) {
   // `count` is even: the buffer roles repeat every two iterations
   if (!use_graph) {
     for (int i = 0; i < count; ++i) minres_iteration(batch, i & 1);
     return;
   }
+  // long chunks replay a graph of graph_iters iterations, the rest one of two
+  auto replay = [&](hipStream_t s) {
+    int left = count;
+    if (graph_iters > 2 && left >= graph_iters) {
+      hipGraphExec_t gl = iteration_graph(batch, graph_iters);
+      for (; left >= graph_iters; left -= graph_iters) ETH_HIP(hipGraphLaunch(gl, s));
+    }
+    if (left > 0) {
+      hipGraphExec_t g2 = iteration_graph(batch, 2);
+      for (; left > 0; left -= 2) ETH_HIP(hipGraphLaunch(g2, s));
+    }
+  };
   if (own_stream) {
     // a ragged-batch member captures and replays on its own stream: one
     // stream per member spreads the members evenly over the hardware queues
-    if (!gexec || gexec_batch != batch) {
-      if (gexec) {
-        ETH_HIP(hipGraphExecDestroy(gexec));
-        gexec = nullptr;
-      }
-      hipGraph_t graph;
-      ETH_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      minres_iteration(batch, 0);
-      minres_iteration(batch, 1);
-      ETH_HIP(hipStreamEndCapture(st, &graph));
-      ETH_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-      ETH_HIP(hipGraphDestroy(graph));
-      gexec_batch = batch;
-    }
-    for (int i = 0; i < count; i += 2) ETH_HIP(hipGraphLaunch(gexec, st));
+    replay(st);
     return;
   }
   if (!gst) {
@@ -1157,21 +1213,7 @@ void Problem::run_iterations(int batch, int count, bool use_graph) {
     hipStream_t v;
     ~Restore() { s = v; }
   } restore{st, caller};
-  if (!gexec || gexec_batch != batch) {
-    if (gexec) {
-      ETH_HIP(hipGraphExecDestroy(gexec));
-      gexec = nullptr;
-    }
-    hipGraph_t graph;
-    ETH_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    minres_iteration(batch, 0);
-    minres_iteration(batch, 1);
-    ETH_HIP(hipStreamEndCapture(st, &graph));
-    ETH_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-    ETH_HIP(hipGraphDestroy(graph));
-    gexec_batch = batch;
-  }
-  for (int i = 0; i < count; i += 2) ETH_HIP(hipGraphLaunch(gexec, gst));
+  replay(gst);
   ETH_HIP(hipEventRecord(ev_join, gst));
   ETH_HIP(hipStreamWaitEvent(caller, ev_join, 0));
 }
@@ -1196,6 +1238,12 @@ void Problem::minres_begin(MinresRun& R) {
   R.chunk = 8;
   R.prev_rel = 1.0;
   R.prev_it = 0;
+  R.refine_left = std::max(0, std::min(o.refine, 10));
+  R.runs = 0;
+  R.gamma0.assign(batch, 0.0);
+  R.rel.assign(batch, 1.0);
+  R.iters.assign(batch, 0);
+  R.hist.assign(o.residual_history ? batch : 0, std::vector<double>());
   load_rhs(R.b, R.ld, batch, R.adjoint);
   // initial residual v1 = b - K x0
   if (o.use_x0) {
@@ -1215,6 +1263,7 @@ void Problem::minres_begin(MinresRun& R) {
     MinresScalars& sc = h_ms[r];
     std::memset(&sc, 0, sizeof(sc));
     sc.tol = R.tol;
+    sc.tol_abs = 0.0;
     sc.maxit = R.maxit;
     sc.hist = d_hist + (size_t)r * hist_len;
     sc.hist_delta = d_hist_delta + (size_t)r * hist_len;
@@ -1279,6 +1328,21 @@ bool Problem::minres_poll(MinresRun& R, bool block) {
     minres_enqueue_chunk(R);
     return false;
   }
+  minres_end_of_run(R);
+  if (R.refine_left > 0) {
+    // restart from x when every right-hand side met the recurrence's test
+    // (no breakdown, no iteration limit) and one of them still iterated
+    bool ok = true, iterated = false;
+    for (int r = 0; r < batch; ++r) {
+      ok = ok && h_ms[r].status == kStOK && !h_ms[r].active && R.iters[r] < R.maxit;
+      iterated = iterated || h_ms[r].iters > 0;
+    }
+    if (ok && iterated) {
+      --R.refine_left;
+      minres_restart(R);
+      return false;
+    }
+  }
   // output: x = interior solution + Dirichlet rows, canonical pressure
   launch_copy(g.N, kx, ldw, R.x, R.ld, batch, st);
   if (!R.adjoint) launch_copy_boundary(g, R.b, R.x, R.ld, batch, st);
@@ -1287,6 +1351,91 @@ bool Problem::minres_poll(MinresRun& R, bool block) {
     launch_pressure_shift(g, R.x, R.ld, batch, red_result, st);
   }
   return true;
+}
+
+// Book-keeping after one MINRES run (the first start or a restart) has
+// ended: iterations, |eta| relative to the first start's gamma_1, history.
+void Problem::minres_end_of_run(MinresRun& R) {
+  const int batch = R.batch;
+  std::vector<double> hbuf;
+  if (!R.hist.empty()) {
+    hbuf.resize((size_t)batch * hist_len);
+    ETH_HIP(hipMemcpyAsync(hbuf.data(), d_hist, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+  }
+  for (int r = 0; r < batch; ++r) {
+    const MinresScalars& sc = h_ms[r];
+    if (R.runs == 0) R.gamma0[r] = sc.gamma1;
+    const double scale = R.gamma0[r] > 0.0 ? sc.gamma1 / R.gamma0[r] : 0.0;
+    R.iters[r] += sc.iters;
+    R.rel[r] = sc.rel * scale;
+    if (!R.hist.empty()) {
+      const int k = std::min(sc.iters, hist_len - 1);
+      for (int j = 0; j <= k; ++j) R.hist[r].push_back(hbuf[(size_t)r * hist_len + j] * scale);
+    }
+  }
+  ++R.runs;
+}
+
+// FP64 defect correction: residual b - K x formed again from the current
+// iterate, MINRES restarted on it with the absolute threshold
+// rtol * gamma_1(first start); right-hand sides already below it stop at the
+// start.  The Lanczos record of the first start is kept for EST-MINRES.
+void Problem::minres_restart(MinresRun& R) {
+  const int batch = R.batch;
+  launch_apply_stokes(g, d.nu, kx, ky, ldw, batch, no_gate(), nullptr, st);
+  launch_residual_init(g, kb, ky, kv[0], ldw, batch, st);
+  launch_fill(g.N, 0.0, kv[1], ldw, batch, st);
+  launch_fill(g.N, 0.0, kw[0], ldw, batch, st);
+  launch_fill(g.N, 0.0, kw[1], ldw, batch, st);
+  int most = 0;
+  for (int r = 0; r < batch; ++r) {
+    MinresScalars& sc = h_ms[r];
+    std::memset(&sc, 0, sizeof(sc));
+    sc.tol = R.tol;
+    sc.tol_abs = std::max(R.tol * R.gamma0[r], 1e-300);
+    sc.maxit = std::max(1, R.maxit - R.iters[r]);
+    sc.hist = d_hist + (size_t)r * hist_len;
+    sc.hist_len = hist_len;
+    sc.active = 1;
+    most = std::max(most, R.iters[r]);
+  }
+  ETH_HIP(hipMemcpyAsync(d_ms, h_ms, sizeof(MinresScalars) * batch, hipMemcpyHostToDevice, st));
+  precond(kv[0], kz[0], ldw, batch, no_gate(), true);
+  RedCtx ri = red(dot_blocks(g.N), 1, EPI_MINRES_INIT, d_ms);
+  launch_dot(g.N, kz[0], kv[0], ldw, batch, ri, no_gate(), st);
+  R.done = most;
+  R.chunk = 8;
+  R.prev_rel = 1.0;
+  R.prev_it = 0;
+  minres_enqueue_chunk(R);
+}
+
+std::vector<int> Problem::check_rhs(const double* b, long long ld, int batch, bool consistency) {
+  // interior norm of b (boundary rows hold Dirichlet data) and the two
+  // pressure-block sums
+  launch_copy(g.N, b, ld, ky, ldw, batch, st);
+  launch_zero_boundary(g, ky, ldw, batch, st);
+  RedCtx rn = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
+  launch_dot(g.N, ky, ky, ldw, batch, rn, no_gate(), st);
+  ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+  ETH_HIP(hipStreamSynchronize(st));
+  std::vector<double> nb2(h_red, h_red + batch);
+  launch_pressure_sums(g, b, ld, batch, red_partials, red_result, st);
+  ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * 2 * batch, hipMemcpyDeviceToHost, st));
+  ETH_HIP(hipStreamSynchronize(st));
+  std::vector<int> out(batch, ETH_OK);
+  for (int r = 0; r < batch; ++r) {
+    const double sk = h_red[2 * r], s0 = h_red[2 * r + 1];
+    if (!std::isfinite(nb2[r]) || !std::isfinite(sk) || !std::isfinite(s0)) {
+      out[r] = ETH_EINVAL;
+      continue;
+    }
+    // Euclidean length of the projection of b onto null(K^T)
+    const double pn = std::sqrt(sk * sk / g.nk + s0 * s0 / g.n0);
+    if (consistency && pn > 1e-12 * std::sqrt(nb2[r])) out[r] = ETH_EINCONSISTENT;
+  }
+  return out;
 }
 
 int Problem::minres_finish(MinresRun& R, eth_solve_info* info) {
@@ -1315,10 +1464,16 @@ int Problem::minres_finish(MinresRun& R, eth_solve_info* info) {
     if (status == kStOK && sc.active) status = ETH_WMAXIT;
     if (info) {
       info[r].status = status;
-      info[r].iterations = sc.iters;
+      info[r].iterations = R.runs ? R.iters[r] : sc.iters;
       info[r].stage1_iterations = 0;
-      info[r].rel_residual_est = sc.rel;
+      info[r].rel_residual_est = R.runs ? R.rel[r] : sc.rel;
       info[r].rel_residual_true = true_rel[r];
+    }
+    if (R.o.residual_history && R.o.history_len > 0) {
+      double* out = R.o.residual_history + (size_t)r * R.o.history_len;
+      const std::vector<double>* hv = R.hist.empty() ? nullptr : &R.hist[r];
+      for (int j = 0; j < R.o.history_len; ++j)
+        out[j] = (hv && j < (int)hv->size()) ? (*hv)[j] : -1.0;
     }
     if (status < 0) worst = std::min(worst, status);
     else if (worst >= 0) worst = std::max(worst, status);
@@ -1457,16 +1612,26 @@ void Problem::build_oseen_velocity() {
 // when applied.  Allocates nothing.
 void Problem::refresh_wind() {
   const int L = (int)lv.size();
+  // level viscosities: nu, or with a Peclet cap max(nu, max|w| h_l / (2 cap))
+  lnu.assign(L, d.nu);
+  if (d.gmg_peclet_max > 0.0) {
+    launch_wind_speed_max(g, wind0, red_result, st);
+    double wmax = 0.0;
+    ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double), hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    wmax = h_red[0];
+    for (int l = 0; l < L; ++l) lnu[l] = std::max(d.nu, wmax * lv[l].h / (2.0 * d.gmg_peclet_max));
+  }
   for (int l = 0; l < L; ++l) {
     if (l > 0) launch_inject_wind(g, lv[l], wind0, lwind[l], st);
-    launch_cd_diag(lv[l], lwind[l], d.nu, ldF[l], st);
+    launch_cd_diag(lv[l], lwind[l], lnu[l], ldF[l], st);
     // the FP32 smoother rounds the wind to FP32 as it stages it: a rounded
     // copy gives the same values at half the bytes
     if (lwindF[l]) launch_to_float(lwind[l], lwindF[l], 2LL * lv[l].nv, st);
   }
   const int ni = coarse_ni;
   launch_fill((long long)ni * ni, 0.0, Ainv, 0, 1, st);
-  launch_dense_convdiff(lv.back(), lwind[L - 1], d.nu, Ainv, ni, st);
+  launch_dense_convdiff(lv.back(), lwind[L - 1], lnu[L - 1], Ainv, ni, st);
   launch_dense_inverse(Ainv, ni, f_work, st);
   launch_transpose(Ainv, ni, AinvT, st);
   if (AinvF) {
@@ -1586,11 +1751,11 @@ void Problem::vcycle_F(const double* r, const double* sub, double* z, long long 
   launch_vcycle_entry<T>(lv[0], r, ld, b[0], x[0], 0.0, batch, gate, st, sub);   // x = 0
   for (int l = 0; l + 1 < L; ++l) {
     for (int k = 0; k < deg; ++k) {
-      launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np, nullptr, 0, 0.0,
+      launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], lnu[l], b[l], x[l], xo[l], om, 0, np, nullptr, 0, 0.0,
                         gate, st, tr);
       std::swap(x[l], xo[l]);
     }
-    launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], d.nu, b[l], x[l], xo[l], om, 1, np, nullptr, 0, 0.0,
+    launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], lnu[l], b[l], x[l], xo[l], om, 1, np, nullptr, 0, 0.0,
                       gate, st, tr);
     launch_restrict<T>(lv[l], lv[l + 1], xo[l], nullptr, b[l + 1], x[l + 1], 0.0, np, batch, gate, st);
   }
@@ -1605,7 +1770,7 @@ void Problem::vcycle_F(const double* r, const double* sub, double* z, long long 
     launch_prolong_add<T>(lv[l], lv[l + 1], x[l + 1], x[l], np, batch, gate, st);
     for (int k = 0; k < deg; ++k) {
       const bool last = (l == 0 && k == deg - 1);
-      launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], d.nu, b[l], x[l], xo[l], om, 0, np,
+      launch_cd_step<T>(lv[l], level_wind<T>(l), ldF[l], lnu[l], b[l], x[l], xo[l], om, 0, np,
                         last ? z : nullptr, ld, 1.0, gate, st, tr);
       if (!last) std::swap(x[l], xo[l]);
     }
@@ -1889,15 +2054,36 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
   RedCtx rn = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
   launch_dot(g.N, kb, kb, ldw, batch, rn, no_gate(), st);
   ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+  ETH_HIP(hipStreamSynchronize(st));
+  std::vector<double> bn(batch), r0(batch);
+  for (int r = 0; r < batch; ++r) bn[r] = r0[r] = std::sqrt(h_red[r]);
   if (o.use_x0) {
     launch_copy(g.N, x, ld, kx, ldw, batch, st);
     launch_zero_boundary(g, kx, ldw, batch, st);
+    // the initial guess and its residual: the result falls back to it when
+    // the iteration ends worse (kw[1] is free outside MINRES)
+    launch_copy(g.N, kx, ldw, kw[1], ldw, batch, st);
+    apply_op(adjoint ? 1 : 0, kx, ky, ldw, batch, no_gate(), nullptr);
+    launch_residual_init(g, kb, ky, kv[1], ldw, batch, st);
+    launch_dot(g.N, kv[1], kv[1], ldw, batch, rn, no_gate(), st);
+    ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < batch; ++r) r0[r] = std::sqrt(h_red[r]);
   } else {
     launch_fill(g.N, 0.0, kx, ldw, batch, st);
   }
-  ETH_HIP(hipStreamSynchronize(st));
-  std::vector<double> bn(batch);
-  for (int r = 0; r < batch; ++r) bn[r] = std::sqrt(h_red[r]);
+  // residual history (host), stage by stage from the device record
+  const bool want_hist = o.residual_history && o.history_len > 0;
+  std::vector<std::vector<double>> hist(want_hist ? batch : 0);
+  auto take_hist = [&]() {
+    std::vector<double> hb((size_t)batch * hist_len);
+    ETH_HIP(hipMemcpyAsync(hb.data(), ghist, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < batch; ++r) {
+      const int k = std::min(h_gm[r].iters, hist_len - 1);
+      for (int j = 0; j <= k; ++j) hist[r].push_back(bn[r] > 0 ? hb[(size_t)r * hist_len + j] / bn[r] : 0.0);
+    }
+  };
   std::vector<int> it1(batch, 0);
   if (o.method == ETH_TWO_STAGE) {
     // stage I: reduced system [F B_1^T; B_1 0] (adjoint: its transpose), RHS
@@ -1909,10 +2095,22 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
     for (int r = 0; r < batch; ++r) a1[r] = c * eta * bn[r];
     run_fgmres(adjoint ? 4 : 2, true, kv[0], kx, batch, m, maxit, a1, adjoint, o.use_graph != 0);
     for (int r = 0; r < batch; ++r) it1[r] = h_gm[r].iters;
+    if (want_hist) take_hist();
   }
   std::vector<double> a2(batch);
   for (int r = 0; r < batch; ++r) a2[r] = eta * bn[r];
   run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint, o.use_graph != 0);
+  if (want_hist) take_hist();
+  // a result whose true residual exceeds that of the initial guess (the
+  // preconditioner made no headway, e.g. a convection-dominated F beyond
+  // what its multigrid smooths) falls back to the initial guess
+  std::vector<char> noprog(batch, 0);
+  for (int r = 0; r < batch; ++r) {
+    if (h_gm[r].status < 0 || !(h_gm[r].beta > r0[r] * (1.0 + 1e-12))) continue;
+    noprog[r] = 1;
+    if (o.use_x0) launch_copy(g.N, kw[1] + (size_t)r * ldw, ldw, kx + (size_t)r * ldw, ldw, 1, st);
+    else launch_fill(g.N, 0.0, kx + (size_t)r * ldw, ldw, 1, st);
+  }
   // output
   launch_copy(g.N, kx, ldw, x, ld, batch, st);
   if (!adjoint) launch_copy_boundary(g, b, x, ld, batch, st);
@@ -1926,12 +2124,18 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
     const GmresScalars& G = h_gm[r];
     int status = G.status;
     if (status == kStOK && !G.converged) status = ETH_WMAXIT;
+    const double fin = noprog[r] ? r0[r] : G.beta;
+    if (noprog[r]) status = ETH_WNOPROGRESS;
     if (info) {
       info[r].status = status;
       info[r].iterations = G.iters + it1[r];
       info[r].stage1_iterations = it1[r];
-      info[r].rel_residual_est = bn[r] > 0 ? G.beta / bn[r] : 0.0;
-      info[r].rel_residual_true = bn[r] > 0 ? G.beta / bn[r] : 0.0;
+      info[r].rel_residual_est = bn[r] > 0 ? fin / bn[r] : 0.0;
+      info[r].rel_residual_true = bn[r] > 0 ? fin / bn[r] : 0.0;
+    }
+    if (want_hist) {
+      double* out = o.residual_history + (size_t)r * o.history_len;
+      for (int j = 0; j < o.history_len; ++j) out[j] = j < (int)hist[r].size() ? hist[r][j] : -1.0;
     }
     if (status < 0) worst = std::min(worst, status);
     else if (worst >= 0) worst = std::max(worst, status);
@@ -2109,6 +2313,16 @@ int eth_solve_adjoint(eth_problem* p, const eth_solve_opts* opts, const double* 
     o.method = p->impl.oseen ? ETH_TWO_STAGE : ETH_MINRES;
   }
   if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
+  if (o.residual_history && o.history_len < 1) return fail(p, ETH_EINVAL, "history_len must be >= 1");
+  {
+    bool finite = true;
+    const int rc = guarded(p, [&] {
+      for (int s : p->impl.check_rhs(g, ld, (int)batch, false)) finite = finite && s == ETH_OK;
+      return ETH_OK;
+    });
+    if (rc != ETH_OK) return rc;
+    if (!finite) return fail(p, ETH_EINVAL, "adjoint right-hand side holds a NaN or Inf");
+  }
   if (p->impl.oseen) {
     if (o.method != ETH_FGMRES && o.method != ETH_TWO_STAGE)
       return fail(p, ETH_EUNSUPPORTED, "Oseen adjoints are solved by FGMRES or TWO_STAGE");
@@ -2401,12 +2615,28 @@ int eth_solve(eth_problem* p, const eth_solve_opts* opts, const double* b, doubl
     o.method = p->impl.oseen ? ETH_TWO_STAGE : ETH_MINRES;
   }
   if (o.maxit > 4096) return fail(p, ETH_EINVAL, "maxit > 4096");
+  if (o.residual_history && o.history_len < 1) return fail(p, ETH_EINVAL, "history_len must be >= 1");
   if (p->impl.oseen) {
     if (o.method != ETH_FGMRES && o.method != ETH_TWO_STAGE)
       return fail(p, ETH_EUNSUPPORTED, "Oseen systems are solved by FGMRES or TWO_STAGE");
-    return guarded(p, [&] { return p->impl.solve_oseen(o, b, x, (int)batch, ld, info); });
+  } else if (o.method != ETH_MINRES) {
+    return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
   }
-  if (o.method != ETH_MINRES) return fail(p, ETH_EUNSUPPORTED, "only MINRES is available for Stokes");
+  int bad = ETH_OK;
+  const int rc = guarded(p, [&] {
+    const std::vector<int> st = p->impl.check_rhs(b, ld, (int)batch, true);
+    for (int r = 0; r < (int)batch; ++r) {
+      if (st[r] != ETH_OK && (bad == ETH_OK || st[r] == ETH_EINVAL)) bad = st[r];
+      if (info) info[r] = eth_solve_info{st[r], 0, 0, -1.0, -1.0};
+    }
+    return ETH_OK;
+  });
+  if (rc != ETH_OK) return rc;
+  if (bad == ETH_EINVAL) return fail(p, ETH_EINVAL, "right-hand side holds a NaN or Inf");
+  if (bad == ETH_EINCONSISTENT)
+    return fail(p, ETH_EINCONSISTENT,
+                "right-hand side not orthogonal to null(K^T): a pressure block of b does not sum to zero");
+  if (p->impl.oseen) return guarded(p, [&] { return p->impl.solve_oseen(o, b, x, (int)batch, ld, info); });
   return guarded(p, [&] { return p->impl.solve_minres(o, b, x, (int)batch, ld, info); });
 }
 
@@ -2559,11 +2789,11 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
         const eth::Geo& gf = P.lv[0];
         launch = [&] {
           if (P.mixed)
-            eth::launch_cd_step<float>(gf, P.level_wind<float>(0), P.ldF[0], P.d.nu, (float*)P.vb[0], (float*)P.vx[0],
+            eth::launch_cd_step<float>(gf, P.level_wind<float>(0), P.ldF[0], P.lnu[0], (float*)P.vb[0], (float*)P.vx[0],
                                        (float*)P.vxo[0], P.d.gmg_omega, 0, 2 * B, nullptr, 0, 0.0, gate,
                                        P.st);
           else
-            eth::launch_cd_step<double>(gf, P.lwind[0], P.ldF[0], P.d.nu, (double*)P.vb[0],
+            eth::launch_cd_step<double>(gf, P.lwind[0], P.ldF[0], P.lnu[0], (double*)P.vb[0],
                                         (double*)P.vx[0], (double*)P.vxo[0], P.d.gmg_omega, 0, 2 * B,
                                         nullptr, 0, 0.0, gate, P.st);
         };
@@ -2650,6 +2880,7 @@ const char* eth_status_string(int status) {
     case ETH_EBREAKDOWN: return "Krylov breakdown";
     case ETH_EUNSUPPORTED: return "unsupported option";
     case ETH_WMAXIT: return "iteration limit reached";
+    case ETH_WNOPROGRESS: return "no progress: the initial guess is returned";
     default: return "unknown status";
   }
 }

@@ -57,6 +57,45 @@ __device__ __forceinline__ double lap90(const T* s, int lx, int ly, int pi, int 
   return acc;
 }
 
+// One Chebyshev update of node (lx, ly) of a staged patch s (row pitch P):
+// x + beta D^{-1}(b - A x), plus alpha (x - xprev) (has_prev 1) or alpha x
+// (has_prev 2).  The expressions and their order are those of k_cheb_step
+// (x-direction K and M sums per staged row, then the y combination), so the
+// fused kernels below give its results.
+template <typename T, int P>
+__device__ __forceinline__ T cheb_node(const T* s, int lx, int ly, int pi, int pj, T bval, T xprev, T ta,
+                                       T tb, int has_prev) {
+  using A = T;
+  A kx[5], mx[5], ky[5], my[5];
+  k1row(pi, kx);
+  m1row(pi, mx);
+  k1row(pj, ky);
+  m1row(pj, my);
+  A tk[5], tm[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const T* row = s + (ly - 2 + j) * P + lx - 2;
+    A a = 0, c = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const A u = (A)row[q];
+      a += kx[q] * u;
+      c += mx[q] * u;
+    }
+    tk[j] = a;
+    tm[j] = c;
+  }
+  A acc = 0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) acc += my[q] * tk[q] + ky[q] * tm[q];
+  const A xc = (A)s[ly * P + lx];
+  const A res = (A)bval - acc / A(90);
+  A xn = xc + tb * res * (A(90) / diag90<A>(pi, pj));
+  if (has_prev == 1) xn += ta * (xc - (A)xprev);
+  else if (has_prev == 2) xn += ta * xc;
+  return xn;
+}
+
 // One Chebyshev step  x_new = x + alpha (x - x_prev) + beta D^{-1} (b - A x)
 // on every plane; x_new overwrites x_prev (xo).  With out64 the result is
 // instead written (times out_scale) to the velocity part of FP64 vectors.
@@ -193,14 +232,23 @@ constexpr int XF = RF + 4;              // fine iterate patch side
 
 // Coarse rhs b_c = P^T (b_f - A_f x_f); x_c = beta_c D_c^{-1} b_c.
 // RES_GIVEN: bf already holds the fine residual (xf unused), b_c = P^T bf.
-template <typename T, bool RES_GIVEN>
+// PRE: xf holds the first pre-smoothing iterate x1 (x0 = 0); the block first
+// takes the second Chebyshev step x2 = x1 + alpha x1 + beta D^{-1}(b - A x1)
+// on its patch (from x1 staged with two more layers), writes x2 on the fine
+// nodes it owns (2 per coarse node and direction) to x2out, and restricts
+// the residual of x2: the smoothing launch before the restriction is saved.
+constexpr int XP = XF + 4;              // first-iterate patch side (PRE)
+
+template <typename T, bool RES_GIVEN, bool PRE = false>
 __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __restrict__ bf,
                                                  const T* __restrict__ xf, T* __restrict__ bc,
                                                  T* __restrict__ xc, double beta_c, Gate gate,
-                                                 int remap_min) {
+                                                 int remap_min, T* __restrict__ x2out = nullptr,
+                                                 double pre_alpha = 0.0, double pre_beta = 0.0) {
   using A = T;   // arithmetic in the storage type (FP32 in mixed precision)
   __shared__ T sx[XF * XF];
   __shared__ A sr[RF * RF];
+  __shared__ T s1[PRE ? XP * XP : 1];
   const int plane = blockIdx.z;
   const bool off = gate.off(plane >> 1);   // tested after the staging (overlapped load)
   const int nqf = gf.nq, topf = nqf - 1, nqc = gc.nq, topc = nqc - 1;
@@ -228,14 +276,39 @@ __global__ __launch_bounds__(NT) void k_restrict(Geo gf, Geo gc, const T* __rest
     if (rt && ly0 + i < RF && Ir > 0 && Ir < topf && J > 0 && J < topf)
       bv[i] = bf[pf + (long long)J * nqf + Ir];
   }
-  if constexpr (!RES_GIVEN) {
+  if constexpr (PRE) {
+    stage1<NT, XP * XP>(s1, tid, [&](int k, T& v) {
+      const int I = F0x - 4 + k % XP, J = F0y - 4 + k / XP;
+      if (I >= 0 && I <= topf && J >= 0 && J <= topf) v = xf[pf + (long long)J * nqf + I];
+    });
+    if (off) return;   // uniform per block
+    __syncthreads();
+    // x2 on the iterate patch (zero outside the grid and on its boundary)
+    const A ta = (A)pre_alpha, tb = (A)pre_beta;
+    for (int k = tid; k < XF * XF; k += NT) {
+      const int lx = k % XF, ly = k / XF;
+      const int I = F0x - 2 + lx, J = F0y - 2 + ly;
+      T v = T(0);
+      if (I > 0 && I < topf && J > 0 && J < topf)
+        v = (T)cheb_node<T, XP>(s1, lx + 2, ly + 2, I & 1, J & 1, bf[pf + (long long)J * nqf + I], T(0),
+                                ta, tb, 2);
+      sx[k] = v;
+    }
+    __syncthreads();
+    // the fine nodes this block owns: [2 C0, 2 C0 + 2 CT) per direction
+    for (int k = tid; k < 4 * CT * CT; k += NT) {
+      const int I = 2 * C0x + k % (2 * CT), J = 2 * C0y + k / (2 * CT);
+      if (I > topf || J > topf) continue;
+      x2out[pf + (long long)J * nqf + I] = sx[(J - F0y + 2) * XF + (I - F0x + 2)];
+    }
+  } else if constexpr (!RES_GIVEN) {
     stage1<NT, XF * XF>(sx, tid, [&](int k, T& v) {
       const int I = F0x - 2 + k % XF, J = F0y - 2 + k / XF;
       if (I >= 0 && I <= topf && J >= 0 && J <= topf) v = xf[pf + (long long)J * nqf + I];
     });
   }
   if (off) return;   // uniform per block
-  if constexpr (!RES_GIVEN) __syncthreads();
+  if constexpr (!RES_GIVEN && !PRE) __syncthreads();
   if (rt) {
     A tk[RES_GIVEN ? 1 : RR + 4], tm[RES_GIVEN ? 1 : RR + 4];
     A kx[5], mx[5];
@@ -391,6 +464,129 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geo gf, Geo gc, const T* __
   f[q] = (T)((double)f1 + a1);
   f[2 * q] = (T)((double)f2 + a2);
   f[3 * q] = (T)((double)f3 + a3);
+}
+
+// Coarse-grid correction and both post-smoothing steps of a V(., 2) cycle in
+// one launch: x0 = x + P x_c on the tile with four layers of halo (the
+// expressions of k_prolong_add), x1 = x0 + beta0 D^{-1}(b - A x0) with two,
+// x2 = x1 + alpha1 (x1 - x0) + beta1 D^{-1}(b - A x1) on the tile (the
+// expressions of k_cheb_step), written to xout (or, times out_scale, to the
+// velocity part of FP64 vectors).  Two launches and their gaps are saved
+// per level.
+constexpr int PX = NX + 8, PY = NY + 8;              // x0 patch (halo 4)
+constexpr int QX = NX + 4, QY = NY + 4;              // x1 patch (halo 2)
+constexpr int CWX = NX / 2 + 8, CWY = NY / 2 + 8;    // coarse staging
+
+template <typename T>
+__device__ __forceinline__ double prolong_row_sum(const T* sc, int row, int I, int cx0) {
+  // t[b] of k_prolong_add for coarse row `row` (staged) and fine column I
+  int ix0, ix1, ix2;
+  double wx0, wx1, wx2;
+  if ((I & 1) == 0) {
+    ix0 = ix1 = ix2 = I >> 1;
+    wx0 = 1.0; wx1 = 0.0; wx2 = 0.0;
+  } else {
+    const int k = (I - 1) >> 1;
+    if ((k & 1) == 0) {
+      ix0 = k; ix1 = k + 1; ix2 = k + 2;
+      wx0 = 0.375; wx1 = 0.75; wx2 = -0.125;
+    } else {
+      ix0 = k - 1; ix1 = k; ix2 = k + 1;
+      wx0 = -0.125; wx1 = 0.75; wx2 = 0.375;
+    }
+  }
+  const T* r = sc + row * CWX - cx0;
+  double v = 0.0;
+  v += wx0 * (double)r[ix0];
+  v += wx1 * (double)r[ix1];
+  v += wx2 * (double)r[ix2];
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_post2(Geo gf, Geo gc, const T* __restrict__ b,
+                                              const T* __restrict__ xold, const T* __restrict__ xc,
+                                              T* __restrict__ xout, double alpha1, double beta0,
+                                              double beta1, double* __restrict__ out64, long long ld64,
+                                              double out_scale, Gate gate, int remap_min) {
+  __shared__ T sc[CWY * CWX];
+  __shared__ T s0[PY * PX];
+  __shared__ T s1[QY * QX];
+  const int plane = blockIdx.z;
+  const bool off = gate.off(plane >> 1);
+  const int nqf = gf.nq, topf = nqf - 1, nqc = gc.nq, topc = nqc - 1;
+  const long long pf = (long long)plane * gf.nv, pc = (long long)plane * gc.nv;
+  int tile_x, tile_y;
+  xcd_band_tile(remap_min, tile_x, tile_y);
+  const int I0 = tile_x * NX, J0 = tile_y * NY;
+  const int cx0 = I0 / 2 - 4, cy0 = J0 / 2 - 4;
+  const int tid = threadIdx.x;
+  stage1<NT, CWX * CWY>(sc, tid, [&](int k, T& v) {
+    const int Ic = cx0 + k % CWX, Jc = cy0 + k / CWX;
+    if (Ic >= 0 && Ic <= topc && Jc >= 0 && Jc <= topc) v = xc[pc + (long long)Jc * nqc + Ic];
+  });
+  stage1<NT, PX * PY>(s0, tid, [&](int k, T& v) {
+    const int I = I0 - 4 + k % PX, J = J0 - 4 + k / PX;
+    if (I >= 0 && I <= topf && J >= 0 && J <= topf) v = xold[pf + (long long)J * nqf + I];
+  });
+  if (off) return;   // uniform per block
+  __syncthreads();
+  // x0 = x + P x_c on the interior nodes of the patch
+  for (int k = tid; k < PX * PY; k += NT) {
+    const int I = I0 - 4 + k % PX, J = J0 - 4 + k / PX;
+    if (I <= 0 || I >= topf || J <= 0 || J >= topf) continue;
+    const int e = J >> 2, q = J & 3;
+    const int r0 = 2 * e - cy0;
+    double a = 0.0;
+    if (q == 0) {
+      const double t0 = prolong_row_sum(sc, r0, I, cx0);
+      a += 1.0 * t0;
+    } else if (q == 2) {
+      const double t1 = prolong_row_sum(sc, r0 + 1, I, cx0);
+      a += 1.0 * t1;
+    } else {
+      const double t0 = prolong_row_sum(sc, r0, I, cx0);
+      const double t1 = prolong_row_sum(sc, r0 + 1, I, cx0);
+      const double t2 = prolong_row_sum(sc, r0 + 2, I, cx0);
+      if (q == 1) {
+        a += 0.375 * t0;
+        a += 0.75 * t1;
+        a += -0.125 * t2;
+      } else {
+        a += -0.125 * t0;
+        a += 0.75 * t1;
+        a += 0.375 * t2;
+      }
+    }
+    s0[k] = (T)((double)s0[k] + a);
+  }
+  __syncthreads();
+  const T tb0 = (T)beta0, ta1 = (T)alpha1, tb1 = (T)beta1;
+  for (int k = tid; k < QX * QY; k += NT) {
+    const int lx = k % QX, ly = k / QX;
+    const int I = I0 - 2 + lx, J = J0 - 2 + ly;
+    T v = T(0);
+    if (I > 0 && I < topf && J > 0 && J < topf)
+      v = cheb_node<T, PX>(s0, lx + 2, ly + 2, I & 1, J & 1, b[pf + (long long)J * nqf + I], T(0), T(0),
+                           tb0, 0);
+    s1[k] = v;
+  }
+  __syncthreads();
+  for (int k = tid; k < NX * NY; k += NT) {
+    const int lx = k % NX, ly = k / NX;
+    const int I = I0 + lx, J = J0 + ly;
+    if (I > topf || J > topf) continue;
+    T xn = T(0);
+    if (I > 0 && I < topf && J > 0 && J < topf)
+      xn = cheb_node<T, QX>(s1, lx + 2, ly + 2, I & 1, J & 1, b[pf + (long long)J * nqf + I],
+                            s0[(ly + 4) * PX + lx + 4], ta1, tb1, 1);
+    if (out64) {
+      out64[(long long)(plane >> 1) * ld64 + (long long)(plane & 1) * gf.nv + (long long)J * nqf + I] =
+          out_scale * (double)xn;
+    } else {
+      xout[pf + (long long)J * nqf + I] = xn;
+    }
+  }
 }
 
 // Dense solve x = Ainv b on the ni interior nodes of the two planes of one
@@ -786,6 +982,29 @@ void launch_restrict(const Geo& gf, const Geo& gc, const T* bf, const T* xf, T* 
 }
 
 template <typename T>
+void launch_restrict_pre(const Geo& gf, const Geo& gc, const T* bf, const T* x1, T* x2out, double alpha,
+                         double beta, T* bc, T* xc, double beta_c, int nplanes, Gate gate, hipStream_t st) {
+  dim3 grid((gc.nq + CT - 1) / CT, (gc.nq + CT - 1) / CT, nplanes);
+  const int rm = xcd_remap_min();
+  hipLaunchKernelGGL((k_restrict<T, false, true>), grid, dim3(NT), 0, st, gf, gc, bf, x1, bc, xc, beta_c, gate,
+                     rm, x2out, alpha, beta);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_post2(const Geo& gf, const Geo& gc, const T* b, const T* xold, const T* xc, T* xout, double alpha1,
+                  double beta0, double beta1, int nplanes, double* out64, long long ld64, double out_scale,
+                  Gate gate, hipStream_t st) {
+  if (gf.nq - 1 != 2 * (gc.nq - 1) || (gc.nq - 1) % 2 != 0)
+    throw std::invalid_argument("prolongation needs a fine level of twice the coarse elements");
+  dim3 grid((gf.nq + NX - 1) / NX, (gf.nq + NY - 1) / NY, nplanes);
+  const int rm = sizeof(T) == 4 ? xcd_remap_min() : INT_MAX;
+  hipLaunchKernelGGL(k_post2<T>, grid, dim3(NT), 0, st, gf, gc, b, xold, xc, xout, alpha1, beta0, beta1, out64,
+                     ld64, out_scale, gate, rm);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
 void launch_prolong_add(const Geo& gf, const Geo& gc, const T* xc, T* xf, int nplanes, int batch,
                         Gate gate, hipStream_t st) {
   (void)batch;
@@ -864,6 +1083,11 @@ void launch_plane_op(const Geo& g, int mode, const double* x, double* y, hipStre
                                    int, int, Gate, hipStream_t);                                 \
   template void launch_prolong_add<T>(const Geo&, const Geo&, const T*, T*, int, int, Gate,       \
                                       hipStream_t);                                              \
+  template void launch_restrict_pre<T>(const Geo&, const Geo&, const T*, const T*, T*, double,   \
+                                       double, T*, T*, double, int, Gate, hipStream_t);          \
+  template void launch_post2<T>(const Geo&, const Geo&, const T*, const T*, const T*, T*, double, \
+                                double, double, int, double*, long long, double, Gate,          \
+                                hipStream_t);                                                    \
   template void launch_dense_solve<T>(const Geo&, const double*, const float*, int, const T*, T*, int, double*, \
                                       long long, double, const double*, long long, double*, int,  \
                                       Gate, hipStream_t);                                         \

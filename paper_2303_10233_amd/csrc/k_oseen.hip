@@ -830,9 +830,34 @@ __global__ void k_q1_dense_solve(const double* __restrict__ Ainv, int ni, const 
   }
 }
 
+// max over the nodes of |w| (one block; the maximum is independent of the
+// order in which it is taken)
+__global__ __launch_bounds__(1024) void k_wind_speed_max(Geo g, const double* __restrict__ w,
+                                                         double* __restrict__ out) {
+  __shared__ double sm[1024 / 64];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < g.nv; i += 1024) {
+    const double a = w[i], b = w[(long long)g.nv + i];
+    m = fmax(m, sqrt(a * a + b * b));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sm[0];
+    for (int k = 1; k < 1024 / 64; ++k) t = fmax(t, sm[k]);
+    *out = t;
+  }
+}
+
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_wind_speed_max(const Geo& g, const double* wind, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_wind_speed_max, dim3(1), dim3(1024), 0, st, g, wind, out);
+  ETH_LAUNCH_CHECK();
+}
 
 void launch_inject_wind(const Geo& gf, const Geo& gc, const double* wf, double* wc, hipStream_t st) {
   hipLaunchKernelGGL(k_inject_wind, dim3(nb(2LL * gc.nv)), dim3(256), 0, st, gf, gc, wf, wc);

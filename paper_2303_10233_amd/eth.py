@@ -19,7 +19,7 @@ VEL_GMG, VEL_EXACT = 0, 1
 MQ_DIAG, MQ_CHEB_SGS, MQ_SCHUR_GMG = 1, 2, 3
 MINRES, FGMRES, TWO_STAGE = 0, 1, 2
 OK, EINVAL, EDEVICE, ENOMEM, EINCONSISTENT, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-WMAXIT = 1
+WMAXIT, WNOPROGRESS = 1, 2
 
 
 class ProblemDesc(ctypes.Structure):
@@ -50,6 +50,7 @@ class ProblemDesc(ctypes.Structure):
         ("gmres_restart", ctypes.c_int32),
         ("mq_tile", ctypes.c_int32),
         ("mq_fuse_steps", ctypes.c_int32),
+        ("gmg_peclet_max", ctypes.c_double),
     ]
 
 
@@ -64,6 +65,9 @@ class SolveOpts(ctypes.Structure):
         ("use_x0", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("true_residual", ctypes.c_int32),
+        ("refine", ctypes.c_int32),
+        ("residual_history", ctypes.POINTER(ctypes.c_double)),
+        ("history_len", ctypes.c_int32),
     ]
 
 
@@ -206,11 +210,28 @@ def _as_batch(t, N):
     return t, t.shape[0], (t.stride(0) if t.shape[0] > 1 else t.shape[1])
 
 
+def _history(B, history_len):
+    """Host buffer for eth_solve_opts.residual_history (None when not asked)."""
+    if not history_len:
+        return None, None
+    buf = (ctypes.c_double * (B * history_len))()
+    return buf, ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+
+
+def _with_history(infos, B, buf, history_len):
+    out = [infos[i].as_dict() for i in range(B)]
+    if buf is not None:
+        for i in range(B):
+            h = list(buf[i * history_len:(i + 1) * history_len])
+            out[i]["history"] = [v for v in h if v != -1.0]
+    return out
+
+
 def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0, kind=STOKES,
                wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0, mq_cheb=(0.0, 0.0),
                gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0), gmg_lambda=None, precision=FP64,
                max_batch=1, device=None, gmg_omega=0.0, pcd_q1_steps=0, gmres_restart=0,
-               mq_tile=0, mq_fuse_steps=0):
+               mq_tile=0, mq_fuse_steps=0, gmg_peclet_max=0.0):
     """A filled ProblemDesc and the Python objects it points into."""
     d = ProblemDesc()
     d.n = n
@@ -238,6 +259,7 @@ def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
     d.gmres_restart = gmres_restart
     d.mq_tile = mq_tile
     d.mq_fuse_steps = mq_fuse_steps
+    d.gmg_peclet_max = gmg_peclet_max
     dev = torch.device("cuda" if device is None else device)
     with torch.cuda.device(dev):
         d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -251,7 +273,7 @@ class Problem:
                  kind=STOKES, wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0,
                  mq_cheb=(0.0, 0.0), gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0),
                  gmg_lambda=None, precision=FP64, max_batch=1, device=None, gmg_omega=0.0,
-                 pcd_q1_steps=0, gmres_restart=0, mq_tile=0, mq_fuse_steps=0):
+                 pcd_q1_steps=0, gmres_restart=0, mq_tile=0, mq_fuse_steps=0, gmg_peclet_max=0.0):
         d, keep = _make_desc(**{k: v for k, v in locals().items() if k not in ("self", "__class__")})
         self._keep = keep
         h = ctypes.c_void_p()
@@ -363,8 +385,13 @@ class Problem:
         return ms.value, by.value
 
     def solve(self, b, rtol=1e-6, maxit=1000, x0=None, method=None, restart=0, c_factor=10.0,
-              canonicalize=True, use_graph=False, true_residual=False, out=None):
-        """method None: MINRES for Stokes, TWO_STAGE for Oseen."""
+              canonicalize=True, use_graph=False, true_residual=False, out=None, refine=0,
+              history_len=0, raise_on_error=True):
+        """method None: MINRES for Stokes, TWO_STAGE for Oseen.  refine: MINRES
+        FP64 defect-correction restarts.  history_len > 0: each info dict gets
+        'history', the residual history (see eth_solve_opts).  With
+        raise_on_error False a negative status is returned in the infos
+        instead of raised."""
         if method is None:
             method = TWO_STAGE if self.kind == OSEEN else MINRES
         x = out if out is not None else torch.empty_like(b)
@@ -372,13 +399,16 @@ class Problem:
             x.copy_(x0)
         b2, B, ld = _as_batch(b, self.N)
         x2, _, _ = _as_batch(x, self.N)
+        buf, hp = _history(B, history_len)
         o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=c_factor,
                       canonicalize=int(canonicalize), use_x0=int(x0 is not None),
-                      use_graph=int(use_graph), true_residual=int(true_residual))
+                      use_graph=int(use_graph), true_residual=int(true_residual), refine=refine,
+                      residual_history=hp, history_len=history_len)
         infos = (SolveInfo * B)()
         st = lib().eth_solve(self._h, ctypes.byref(o), _ptr(b2), _ptr(x2), B, ld, infos)
-        _check(st, self._h)
-        return x, [infos[i].as_dict() for i in range(B)]
+        if raise_on_error:
+            _check(st, self._h)
+        return x, _with_history(infos, B, buf, history_len)
 
     def infsup_estimate(self, rhs=0):
         """EST-MINRES (gamma^2, theta, Lanczos steps) from the last MINRES solve."""
@@ -580,7 +610,7 @@ class RaggedBatch:
         torch.cuda.synchronize(self.device)
         return out
 
-    def solve(self, bs, rtol=1e-6, maxit=1000, use_graph=True, true_residual=False, out=None):
+    def solve(self, bs, rtol=1e-6, maxit=1000, use_graph=True, true_residual=False, out=None, refine=0):
         xs = out if out is not None else [torch.empty_like(b) for b in bs]
         for p, b, x in zip(self.problems, bs, xs):
             if b.numel() < p.N or x.numel() < p.N or b.dtype != torch.float64:
@@ -589,7 +619,7 @@ class RaggedBatch:
         B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
         X = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         o = SolveOpts(method=MINRES, rtol=rtol, maxit=maxit, restart=0, c_factor=10.0, canonicalize=1,
-                      use_x0=0, use_graph=int(use_graph), true_residual=int(true_residual))
+                      use_x0=0, use_graph=int(use_graph), true_residual=int(true_residual), refine=refine)
         infos = (SolveInfo * n)()
         st = lib().eth_batch_solve(self._h, ctypes.byref(o), B, X, infos)
         if st < 0:

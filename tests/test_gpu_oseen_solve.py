@@ -48,13 +48,13 @@ def _mq_lo(n):
     return min(0.01, 0.4 / n)
 
 
-def _setup(n, nu, prec=eth.FP64, velocity=eth.VEL_GMG, max_batch=1, mq=eth.MQ_CHEB_SGS):
+def _setup(n, nu, prec=eth.FP64, velocity=eth.VEL_GMG, max_batch=1, mq=eth.MQ_CHEB_SGS, peclet_max=0.0):
     m = Mesh(n, -1, 1, -1, 1)
     w = recirculating_wind(n)
     s = System(m, nu=nu, wind=w)
     P = eth.Problem(n, domain=(-1.0, 1.0, -1.0, 1.0), nu=nu, kind=eth.OSEEN, wind=_t(w),
                     velocity=velocity, mq=mq, mq_cheb=(_mq_lo(n), 1.0), precision=prec,
-                    max_batch=max_batch)
+                    max_batch=max_batch, gmg_peclet_max=peclet_max)
     return m, s, P
 
 
@@ -311,3 +311,45 @@ def test_transposed_preconditioners_match_oracle(n):
     assert rel_err(zp[:o], zref[:o]) < 1e-11
     assert rel_err(zp[o:o + m.nk], zref[o:o + m.nk]) < 1e-11
     assert np.abs(zp[o + m.nk:]).max() == 0.0
+
+
+@pytest.mark.parametrize("n,prec,tol", [(64, eth.FP64, 1e-11), (128, eth.FP64, 1e-11), (64, eth.MIXED, 2e-5)])
+def test_m1_with_peclet_capped_f_multigrid_matches_oracle(n, prec, tol):
+    """nu = 1/1000: every F level smooths nu_l A + N with nu_l = max(nu,
+    max|w| h_l / 8) (Peclet cap 4), in the oracle and on the GPU."""
+    print(f"[oseen M1 peclet cap] n={n} prec={prec}", flush=True)
+    nu = 1e-3
+    m, s, P = _setup(n, nu, prec, peclet_max=4.0)
+    r = uniform_vector(m.N, 131 + n)
+    r[: 2 * m.nv][s.vel_bnd] = 0.0
+    vel, _ = opc.oseen_velocity_gmg(s, peclet_max=4.0)
+    pre = opc.OseenM1(s, velocity_solve=vel, mq=opc.MQChebSGS(m, s.MQ, _mq_lo(n), 1.0, 20))
+    z = _np(P.apply_preconditioner(_t(r)))
+    zref = s.to_full(pre(s.to_interior(r)))
+    o = 2 * m.nv
+    assert rel_err(z[:o], zref[:o]) < tol
+    assert rel_err(z[o:], zref[o:]) < tol
+
+
+def test_peclet_cap_makes_the_high_reynolds_solve_progress():
+    """nu = 1/1000 on 128^2 (element Peclet 15.6): with the plain F multigrid
+    FGMRES makes no headway (the returned iterate is never worse than the
+    start); with the Peclet cap the two-stage residual falls steadily."""
+    n, nu = 128, 1e-3
+    print(f"[oseen nu=1/1000] n={n}", flush=True)
+    res = {}
+    for cap in (0.0, 4.0):
+        m, s, P = _setup(n, nu, eth.MIXED, peclet_max=cap)
+        b = P.assemble_rhs()
+        x, info = P.solve(b, rtol=1e-6, maxit=300, method=eth.TWO_STAGE, raise_on_error=False,
+                          history_len=400)
+        i = info[0]
+        res[cap] = i
+        print(f"  cap={cap}: status={i['status']} its={i['iterations']} "
+              f"true={i['rel_residual_true']:.3e}", flush=True)
+        P.close()
+    assert res[0.0]["rel_residual_true"] <= 1.0
+    assert res[4.0]["rel_residual_true"] < 0.1
+    h = res[4.0]["history"]
+    k1 = res[4.0]["stage1_iterations"]
+    assert h[min(k1, 100)] < 0.5 * h[0]

@@ -1,0 +1,137 @@
+"""Solution parity against the oracle's direct solve at the bars the method
+is held to: FP64 mode within 1e-8 and mixed mode within 1e-6 in the relative
+2-norm of the full canonicalised vector (velocity, Q1 and P0 pressure), for
+the Stokes cavity at 128^2, the lockstep batch of 64 forcings at 128^2, the
+ragged cavity batch and the Oseen two-stage solve (eq:saddle_point,
+eq:oseen-system)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.assemble import Mesh, System, lid_dirichlet  # noqa: E402
+from oracle.direct import BorderedLU, canonicalize, direct_solve, rel_err  # noqa: E402
+from paper_2303_10233_amd import eth  # noqa: E402
+from paper_2303_10233_amd.workloads import gaussian_bumps, recirculating_wind  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eth.load_library()
+
+
+def _parts(x, xd, m):
+    o = 2 * m.nv
+    return (rel_err(x, xd), rel_err(x[:o], xd[:o]), rel_err(x[o:], xd[o:]))
+
+
+@pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
+def test_stokes_128_matches_direct(prec):
+    n = 128
+    print(f"[parity stokes] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    s = System(m)
+    xd = direct_solve(s, s.rhs(None, lid_dirichlet(m)))
+    P = eth.Problem(n, precision=prec)
+    b = P.assemble_rhs()
+    # mixed precision: FP64 defect-correction restarts take the true
+    # residual to the requested tolerance (an FP32 preconditioner limits what
+    # the recurrence alone reaches)
+    rtol, refine = (1e-12, 0) if prec == eth.FP64 else (1e-9, 4)
+    x, info = P.solve(b, rtol=rtol, maxit=1500, use_graph=True, true_residual=True, refine=refine)
+    e = _parts(_np(x), xd, m)
+    print(f"  status={info[0]['status']} its={info[0]['iterations']} "
+          f"true={info[0]['rel_residual_true']:.2e} err full/u/p={e[0]:.2e}/{e[1]:.2e}/{e[2]:.2e}",
+          flush=True)
+    assert e[0] < (1e-8 if prec == eth.FP64 else 1e-6)
+    P.close()
+
+
+@pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
+def test_batch64_128_matches_direct(prec):
+    """The lockstep batch of 64 Gaussian-bump forcings (seeds 1000..1063) at
+    128^2: three of its right-hand sides against the direct solve."""
+    n, B = 128, 64
+    print(f"[parity batch64] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    s = System(m)
+    lu = BorderedLU(s)
+    P = eth.Problem(n, precision=prec, max_batch=B)
+    F = torch.stack([_t(gaussian_bumps(n, 1000 + k)) for k in range(B)])
+    b = P.assemble_rhs(F, batch=B)
+    rtol, refine = (1e-12, 0) if prec == eth.FP64 else (1e-9, 4)
+    x, infos = P.solve(b, rtol=rtol, maxit=1500, use_graph=True, refine=refine)
+    X = _np(x)
+    for k in (0, 31, 63):
+        xd = canonicalize(lu.solve(s.rhs(gaussian_bumps(n, 1000 + k), lid_dirichlet(m))), m)
+        e = _parts(X[k, : m.N], xd, m)
+        print(f"  rhs {k}: status={infos[k]['status']} its={infos[k]['iterations']} "
+              f"err full/u/p={e[0]:.2e}/{e[1]:.2e}/{e[2]:.2e}", flush=True)
+        assert e[0] < (1e-8 if prec == eth.FP64 else 1e-6)
+    P.close()
+
+
+def test_ragged_mixed_matches_direct():
+    """Mixed-precision ragged members solved to 1e-8 (with FP64 defect
+    correction), the 8^2 and 64^2 members held to 1e-6 against the direct
+    solve."""
+    sizes = [8, 16, 24, 32, 48, 64]
+    print(f"[parity ragged mixed] sizes={sizes}", flush=True)
+    R = eth.RaggedBatch(sizes, precision=eth.MIXED)
+    bs = R.assemble_rhs()
+    xs, infos = R.solve(bs, rtol=1e-8, maxit=3000, use_graph=True, true_residual=True, refine=4)
+    torch.cuda.synchronize()
+    for n, x, info in zip(sizes, xs, infos):
+        print(f"  n={n}: status={info['status']} its={info['iterations']} "
+              f"true={info['rel_residual_true']:.2e}", flush=True)
+        assert info["status"] == 0
+    for n, x in zip(sizes, xs):
+        if n not in (8, 64):
+            continue
+        m = Mesh(n)
+        s = System(m)
+        xd = direct_solve(s, s.rhs(None, lid_dirichlet(m)))
+        e = _parts(_np(x), xd, m)
+        print(f"  n={n}: err full/u/p={e[0]:.2e}/{e[1]:.2e}/{e[2]:.2e}", flush=True)
+        assert e[0] < 1e-6
+    R.close()
+
+
+@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("prec", [eth.FP64, eth.MIXED])
+def test_oseen_two_stage_full_vector_matches_direct(n, prec):
+    """Oseen nu = 1/100 on [-1,1]^2 with the recirculating wind: the whole
+    canonicalised vector, pressure included."""
+    nu = 0.01
+    print(f"[parity oseen] n={n} prec={prec}", flush=True)
+    m = Mesh(n, -1, 1, -1, 1)
+    w = recirculating_wind(n)
+    s = System(m, nu=nu, wind=w)
+    xd = direct_solve(s, s.rhs(None, lid_dirichlet(m)))
+    P = eth.Problem(n, domain=(-1.0, 1.0, -1.0, 1.0), nu=nu, kind=eth.OSEEN, wind=_t(w),
+                    mq_cheb=(min(0.01, 0.4 / n), 1.0), precision=prec)
+    b = P.assemble_rhs()
+    rtol = 1e-12 if prec == eth.FP64 else 1e-10
+    x, info = P.solve(b, rtol=rtol, maxit=3000, method=eth.TWO_STAGE, true_residual=True)
+    e = _parts(_np(x), xd, m)
+    print(f"  status={info[0]['status']} its={info[0]['iterations']} "
+          f"true={info[0]['rel_residual_true']:.2e} err full/u/p={e[0]:.2e}/{e[1]:.2e}/{e[2]:.2e}",
+          flush=True)
+    assert info[0]["status"] == 0
+    assert e[0] < (1e-8 if prec == eth.FP64 else 1e-6)
+    P.close()

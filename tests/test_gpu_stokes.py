@@ -201,6 +201,49 @@ def test_fused_coarse_vcycle_equals_per_level_launches(n, prec, tol, monkeypatch
     assert np.array_equal(z_fused[o:], z_ref[o:])
 
 
+@pytest.mark.parametrize("n,prec", [(16, eth.FP64), (64, eth.FP64), (96, eth.FP64), (256, eth.FP64),
+                                    (40, eth.MIXED), (128, eth.MIXED), (256, eth.MIXED)])
+def test_fused_smoothing_launches_equal_per_step_launches(n, prec, monkeypatch):
+    """V(2,2) with the second pre-smoothing step inside the restriction's
+    launch and the correction plus both post-smoothing steps in one launch
+    per level, against one launch per step: the same node expressions in the
+    same order.  In FP32 (the mixed-precision preconditioner) the two agree
+    bit for bit, preconditioner and whole graph-replayed solve; in FP64 the
+    compiler contracts a few multiply-adds differently in the two code
+    shapes, which leaves differences at the rounding level (measured up to
+    7e-14 absolute at 256^2)."""
+    print(f"[fused smoothing] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    r = uniform_vector(m.N, 21 + n)
+    r[: 2 * m.nv][System(m).vel_bnd] = 0.0
+    P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_DIAG)
+    z_fused = _np(P.apply_preconditioner(_t(r)))
+    b = P.assemble_rhs()
+    # FP64: solved far enough that a one-iteration difference in where the
+    # two stop does not show in the comparison
+    rtol = 1e-8 if prec == eth.MIXED else 1e-12
+    x_fused, i_fused = P.solve(b, rtol=rtol, maxit=2000, use_graph=True)
+    x_fused = _np(x_fused)
+    monkeypatch.setenv("ETH_DEBUG_UNFUSED_SMOOTH", "1")
+    Q = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_DIAG)
+    z_ref = _np(Q.apply_preconditioner(_t(r)))
+    x_ref, i_ref = Q.solve(Q.assemble_rhs(), rtol=rtol, maxit=2000, use_graph=True)
+    o = 2 * m.nv
+    print(f"  max |dz| = {np.abs(z_fused - z_ref).max():.3e}", flush=True)
+    print(f"  iterations {i_fused[0]['iterations']} / {i_ref[0]['iterations']}, status "
+          f"{i_fused[0]['status']} / {i_ref[0]['status']}", flush=True)
+    if prec == eth.MIXED:
+        assert np.array_equal(z_fused[:o], z_ref[:o])
+        assert i_fused[0]["iterations"] == i_ref[0]["iterations"]
+        assert np.array_equal(x_fused, _np(x_ref))
+    else:
+        assert rel_err(z_fused[:o], z_ref[:o]) < 1e-13
+        if n <= 128:   # the diagonal pressure block needs more than maxit beyond
+            assert i_fused[0]["status"] == 0 and i_ref[0]["status"] == 0
+            assert abs(i_fused[0]["iterations"] - i_ref[0]["iterations"]) <= 2
+            assert rel_err(x_fused, _np(x_ref)) < 1e-9
+
+
 @pytest.mark.parametrize("n,prec", [(8, eth.FP64), (16, eth.FP64), (66, eth.FP64), (12, eth.MIXED),
                                     (64, eth.MIXED), (132, eth.MIXED)])
 def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):

@@ -169,3 +169,56 @@ def test_dense_formula_detects_a_dropped_post_smoothing():
         return x + g.P[0] @ g.coarse_lu.solve(g.P[0].T @ (r - g.A[0] @ x))
     V = _columns(pre_only, As[0].shape[0])
     assert np.abs(V - B).max() > 1e-3 * np.abs(B).max()
+
+
+def test_stabilised_oseen_multigrid_is_the_damped_jacobi_vcycle():
+    """With a Peclet cap the level operators are nu_l A_l + N_l with A_l, N_l
+    the Galerkin products of the finest Laplacian and convection and
+    nu_l = max(nu, max|w| h_l / (2 peclet_max)); the cycle is the textbook
+    damped-Jacobi V-cycle on those operators."""
+    from oracle.assemble import convection
+    m = Mesh(16, -1, 1, -1, 1)
+    w = recirculating_wind(m)
+    s = System(m, nu=1e-3, wind=w)
+    _, g = pc.oseen_velocity_gmg(s, coarse_n=4, omega=0.7, sweeps=2, peclet_max=4.0)
+    assert g.ns == [16, 8, 4]
+    I0 = g.I[0]
+    A = laplacian(m).toarray()[np.ix_(I0, I0)]
+    N = convection(m, w).toarray()[np.ix_(I0, I0)]
+    Ps = [P.toarray() for P in g.P]
+    wmax = 2.0                                   # max |w| of the recirculating wind on [-1,1]^2
+    assert abs(pc.wind_speed_max(w, m) - wmax) < 1e-12
+    As = []
+    for l, k in enumerate(g.ns):
+        h = 2.0 / k
+        nul = max(1e-3, wmax * h / 8.0)
+        assert nul == pc.level_viscosity(1e-3, h, wmax, 4.0)
+        As.append(nul * A + N)
+        assert np.abs(As[l] - g.A[l].toarray()).max() < 1e-12 * np.abs(As[l]).max()
+        if l + 1 < len(g.ns):
+            A = Ps[l].T @ A @ Ps[l]
+            N = Ps[l].T @ N @ Ps[l]
+    Ms = [_smoother_inverse(As[l], _jacobi_error_poly(0.7, 2)) for l in range(len(As) - 1)]
+    B = _vcycle_dense(As, Ps, Ms, np.linalg.inv(As[-1]))
+    V = _columns(lambda v: g.vcycle(0, v), As[0].shape[0])
+    assert np.abs(V - B).max() < 1e-10 * np.abs(B).max()
+
+
+def test_stabilised_cycle_contracts_where_the_plain_cycle_diverges():
+    """nu = 1/1000 on 16^2 (element Peclet number 125): the plain damped-Jacobi
+    cycle amplifies the error by orders of magnitude, the Peclet-capped one is
+    a contraction for its own finest operator and leaves the spectrum of the
+    preconditioned F in the right half-plane (GMRES on F B converges)."""
+    m = Mesh(16, -1, 1, -1, 1)
+    s = System(m, nu=1e-3, wind=recirculating_wind(m))
+    I0 = np.flatnonzero(~m.boundary_q2())
+    F = s.F_s[I0][:, I0].toarray()
+    E = np.eye(F.shape[0])
+    _, gp = pc.oseen_velocity_gmg(s, coarse_n=4)
+    Bp = _columns(lambda v: gp.vcycle(0, v), F.shape[0])
+    assert np.abs(np.linalg.eigvals(E - Bp @ F)).max() > 10.0
+    _, gs = pc.oseen_velocity_gmg(s, coarse_n=4, peclet_max=4.0)
+    Bs = _columns(lambda v: gs.vcycle(0, v), F.shape[0])
+    Fs = gs.A[0].toarray()
+    assert np.abs(np.linalg.eigvals(E - Bs @ Fs)).max() < 0.8
+    assert np.linalg.eigvals(F @ Bs).real.min() > 0.0
