@@ -114,6 +114,24 @@ typedef struct {
                                 damped-Jacobi cycle a contraction where the
                                 unstabilised F is convection dominated (element
                                 Peclet >= 8, e.g. nu = 1/1000 on 256^2).  0: off */
+  int32_t oseen_schur;       /* Oseen: Schur block of the full-system preconditioner
+                                [F~ B^T; 0 -M_S] used by ETH_FGMRES and stage II:
+                                0: M_1, M_S = M_Q / nu (eq:nse-precon-ref);
+                                1: M_2, the two-field PCD approximation M_S =
+                                   diag(Q_1,Q_0) diag(F_1,F_0)^{-1} B M^{-1} B^T
+                                   (eq:twofield-pcd) with F_0 the jump-based P0
+                                   convection-diffusion operator;
+                                2: M_3, the least-squares commutator M_S =
+                                   (B M^{-1} B^T)(B M^{-1} F M^{-1} B^T)^{-1}
+                                   (B M^{-1} B^T) (eq:lsc-definition, boundary
+                                   scaling D = I).  M = diag of the velocity mass.
+                                1 and 2 (comparison preconditioners of Sec. 3.1
+                                and 3.2) need max_batch 1, invert B M^{-1} B^T by
+                                conjugate gradients on its range, synchronise
+                                with the host inside and so run without graph
+                                replay, and have no transposed form              */
+  double schur_cg_tol;       /* relative tolerance of that CG (default 1e-10)       */
+  int32_t schur_cg_maxit;    /* its iteration limit (default 2000)                  */
 } eth_problem_desc;
 
 typedef struct {

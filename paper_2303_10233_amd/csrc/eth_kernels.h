@@ -191,6 +191,12 @@ void launch_mq_project_out(const Geo& g, const T* z, double* out, long long ld, 
 // ---------------- Oseen preconditioner pieces (k_oseen.hip) ------------------
 void launch_inject_wind(const Geo& gf, const Geo& gc, const double* wf, double* wc, hipStream_t st);
 void launch_cd_diag(const Geo& g, const double* wind, double nu, double* dF, hipStream_t st);
+// y = F_0 (scale x) on the n^2 elements (jump-based P0 convection-diffusion)
+void launch_p0_cd_apply(const Geo& g, const double* wind, double nu, const double* x, double scale, double* y,
+                        hipStream_t st);
+// velocity part of a full vector times diag(M_v)^{-1} (interior nodes, else
+// 0), pressure part zeroed
+void launch_vel_minv(const Geo& g, double* x, hipStream_t st);
 // *out = max over the Q2 nodes of |w| (device scalar)
 void launch_wind_speed_max(const Geo& g, const double* wind, double* out, hipStream_t st);
 // the coarse F as a dense row-major ni x ni matrix (A zero on entry)

@@ -355,6 +355,20 @@ struct Problem {
   void ap_vcycle(int batch, Gate gate);
   template <typename T>
   void pcd_schur(const double* r, double* z, long long ld, int batch, Gate gate, bool trans);
+  // Q_1^{-1} b by pcd_q1_steps Chebyshev-Jacobi steps; returns the buffer holding it
+  template <typename T>
+  T* q1_inverse(T* b, T* cur, T* oth, int batch, Gate gate);
+  // comparison Schur blocks (Sec. 3.1 two-field PCD, Sec. 3.2 LSC), one
+  // right-hand side: z_p = -M_S^{-1} r_p with the pressure Laplacian
+  // B M^{-1} B^T inverted by conjugate gradients on its range
+  template <typename T>
+  void schur2(const double* r, double* z, Gate gate);
+  std::vector<double*> s2v;          // FP64 full-layout work vectors of schur2
+  double dot1(const double* a, const double* b);
+  void project_pressure(double* x);
+  void lp_apply(const double* p, double* q);
+  int lp_pinv(double* b, double* x);
+  int lp_last_iters = 0;
   // kind 1: M_1, kind 2: stage-I PCD; kinds 3 and 4: the same for the
   // transposed system [F^T B^T; B 0] (velocity block F^T, Schur complement
   // S^T); r, z internal vectors (stride ldw)
@@ -440,6 +454,11 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.gmg_coarse_n <= 0) d.gmg_coarse_n = oseen ? 32 : 4;
   if (d.gmg_omega <= 0.0) d.gmg_omega = 0.7;
   if (d.gmg_peclet_max < 0.0) throw std::invalid_argument("gmg_peclet_max must be >= 0");
+  if (d.oseen_schur < 0 || d.oseen_schur > 2) throw std::invalid_argument("oseen_schur must be 0, 1 or 2");
+  if (d.oseen_schur != 0 && (d.kind != ETH_OSEEN || d.max_batch > 1))
+    throw std::invalid_argument("oseen_schur needs an Oseen problem with max_batch 1");
+  if (d.schur_cg_tol <= 0.0) d.schur_cg_tol = 1e-10;
+  if (d.schur_cg_maxit <= 0) d.schur_cg_maxit = 2000;
   if (d.pcd_q1_steps <= 0) d.pcd_q1_steps = 10;
   if (d.gmres_restart <= 0) d.gmres_restart = 50;
   if (d.gmres_restart > 63) throw std::invalid_argument("gmres_restart must be <= 63");
@@ -507,6 +526,11 @@ void Problem::setup(const eth_problem_desc& desc) {
     build_oseen_velocity();
     build_pcd();
     build_gmres();
+    if (d.oseen_schur != 0)
+      for (int i = 0; i < 7; ++i) {
+        s2v.push_back(alloc<double>(ldw));
+        ETH_HIP(hipMemsetAsync(s2v.back(), 0, sizeof(double) * ldw, st));
+      }
   } else {
     build_velocity();
     // members of a ragged batch run concurrently with each other instead: a
@@ -1865,25 +1889,7 @@ void Problem::pcd_schur(const double* r, double* z, long long ld, int batch, Gat
     launch_q1_shift<T, std::remove_pointer_t<decltype(dst)>>(g, qx0, nk, 0, dst, ldd, offd, q1sums, scale,
                                                             batch, gate, st);
   };
-  // Q_1^{-1} b: Chebyshev-Jacobi on [1/4, 9/4]; returns the buffer holding it
-  auto q1_inv = [&](T* b, T* cur, T* oth) {
-    if (fused_q1 && d.pcd_q1_steps <= 12) {   // every step in one launch, bit for bit the same
-      Q1Cheb cc{};
-      cc.steps = d.pcd_q1_steps;
-      for (int k = 0; k < cc.steps; ++k) {
-        cc.a[k] = q1a[k];
-        cc.b[k] = q1b[k];
-      }
-      launch_q1mass_cheb_fused<T>(g, b, cur, cc, batch, gate, st);
-      return cur;
-    }
-    launch_q1mass_cheb<T>(g, b, nullptr, cur, 0.0, q1b[0], 0, batch, gate, st);
-    for (int k = 1; k < d.pcd_q1_steps; ++k) {
-      launch_q1mass_cheb<T>(g, b, cur, oth, q1a[k], q1b[k], k == 1 ? 2 : 1, batch, gate, st);
-      std::swap(cur, oth);
-    }
-    return cur;
-  };
+  auto q1_inv = [&](T* b, T* cur, T* oth) { return q1_inverse<T>(b, cur, oth, batch, gate); };
   launch_q1_shift<double, T>(g, r, ld, g.off_pk(), A, nk, 0, nullptr, 1.0, batch, gate, st);
   if (!trans) {
     T* q = q1_inv(A, B, C);
@@ -1897,6 +1903,110 @@ void Problem::pcd_schur(const double* r, double* z, long long ld, int batch, Gat
   }
 }
 
+// Q_1^{-1} b: Chebyshev-Jacobi on [1/4, 9/4]
+template <typename T>
+T* Problem::q1_inverse(T* b, T* cur, T* oth, int batch, Gate gate) {
+  if (fused_q1 && d.pcd_q1_steps <= 12) {   // every step in one launch, bit for bit the same
+    Q1Cheb cc{};
+    cc.steps = d.pcd_q1_steps;
+    for (int k = 0; k < cc.steps; ++k) {
+      cc.a[k] = q1a[k];
+      cc.b[k] = q1b[k];
+    }
+    launch_q1mass_cheb_fused<T>(g, b, cur, cc, batch, gate, st);
+    return cur;
+  }
+  launch_q1mass_cheb<T>(g, b, nullptr, cur, 0.0, q1b[0], 0, batch, gate, st);
+  for (int k = 1; k < d.pcd_q1_steps; ++k) {
+    launch_q1mass_cheb<T>(g, b, cur, oth, q1a[k], q1b[k], k == 1 ? 2 : 1, batch, gate, st);
+    std::swap(cur, oth);
+  }
+  return cur;
+}
+
+double Problem::dot1(const double* a, const double* b) {
+  RedCtx rc = red(dot_blocks(g.N), 1, EPI_NONE, nullptr, red_result);
+  launch_dot(g.N, a, b, ldw, 1, rc, no_gate(), st);
+  ETH_HIP(hipMemcpyAsync(h_red, red_result, sizeof(double), hipMemcpyDeviceToHost, st));
+  ETH_HIP(hipStreamSynchronize(st));
+  return h_red[0];
+}
+
+// remove the means of the Q1 and P0 blocks (the null space of B^T)
+void Problem::project_pressure(double* x) {
+  launch_pressure_sums(g, x, ldw, 1, red_partials, red_result, st);
+  launch_pressure_shift(g, x, ldw, 1, red_result, st);
+}
+
+// q = [0; B M^{-1} B^T p_p] for p = [0; p_p] (M = diag of the velocity mass
+// on the interior nodes): B^T and B from the saddle apply with nu = 0
+void Problem::lp_apply(const double* p, double* q) {
+  double* t = s2v[5];
+  launch_apply_stokes(g, 0.0, p, t, ldw, 1, no_gate(), nullptr, st);
+  launch_vel_minv(g, t, st);
+  launch_apply_stokes(g, 0.0, t, q, ldw, 1, no_gate(), nullptr, st);
+}
+
+// x = (B M^{-1} B^T)^+ b by conjugate gradients on the range (b and x with
+// zero velocity parts; b is projected first, x at the end): from x = 0 until
+// ||r|| <= schur_cg_tol ||b||, at most schur_cg_maxit steps
+int Problem::lp_pinv(double* b, double* x) {
+  double *r = s2v[2], *p = s2v[3], *q = s2v[4];
+  project_pressure(b);
+  launch_fill(g.N, 0.0, x, ldw, 1, st);
+  launch_copy(g.N, b, ldw, r, ldw, 1, st);
+  launch_copy(g.N, b, ldw, p, ldw, 1, st);
+  double rho = dot1(r, r);
+  const double stop = d.schur_cg_tol * d.schur_cg_tol * rho;
+  int it = 0;
+  while (rho > stop && it < d.schur_cg_maxit) {
+    lp_apply(p, q);
+    const double pq = dot1(p, q);
+    if (!(pq > 0.0)) break;
+    const double alpha = rho / pq;
+    launch_axpby(g.N, alpha, p, 1.0, x, ldw, 1, st);
+    launch_axpby(g.N, -alpha, q, 1.0, r, ldw, 1, st);
+    const double rn = dot1(r, r);
+    launch_axpby(g.N, 1.0, r, rn / rho, p, ldw, 1, st);
+    rho = rn;
+    ++it;
+  }
+  project_pressure(x);
+  return it;
+}
+
+template <typename T>
+void Problem::schur2(const double* r, double* z, Gate gate) {
+  double *b = s2v[0], *x = s2v[1], *t = s2v[5], *t2 = s2v[6];
+  const long long np = (long long)g.nk + g.n0;
+  launch_fill(g.N, 0.0, b, ldw, 1, st);
+  if (d.oseen_schur == 1) {
+    // [F_1 Q_1^{-1} r_k ; F_0 Q_0^{-1} r_0]  (Q_0 = h^2 I)
+    T* A = static_cast<T*>(pa);
+    T* B = static_cast<T*>(pb);
+    T* C = static_cast<T*>(pc);
+    launch_q1_shift<double, T>(g, r, ldw, g.off_pk(), A, g.nk, 0, nullptr, 1.0, 1, gate, st);
+    T* q = q1_inverse<T>(A, B, C, 1, gate);
+    launch_f1_apply<T>(g, wind0, d.nu, q, A, 1, gate, st, 0);
+    launch_q1_shift<T, double>(g, A, g.nk, 0, b, ldw, g.off_pk(), nullptr, 1.0, 1, gate, st);
+    launch_p0_cd_apply(g, wind0, d.nu, r + g.off_p0(), 1.0 / (g.h * g.h), b + g.off_p0(), st);
+  } else {
+    launch_copy(np, r + g.off_pk(), ldw, b + g.off_pk(), ldw, 1, st);
+  }
+  lp_last_iters = lp_pinv(b, x);
+  if (d.oseen_schur == 2) {
+    // LSC: the middle factor B M^{-1} F M^{-1} B^T, then the pressure Laplacian again
+    launch_apply_stokes(g, 0.0, x, t, ldw, 1, no_gate(), nullptr, st);
+    launch_vel_minv(g, t, st);
+    launch_apply_oseen(g, d.nu, d.wind, 0, t, t2, ldw, 1, no_gate(), nullptr, st);
+    launch_vel_minv(g, t2, st);
+    launch_apply_stokes(g, 0.0, t2, b, ldw, 1, no_gate(), nullptr, st);
+    lp_last_iters += lp_pinv(b, x);
+  }
+  launch_fill(np, 0.0, z + g.off_pk(), ldw, 1, st);
+  launch_axpby(np, -1.0, x + g.off_pk(), 0.0, z + g.off_pk(), ldw, 1, st);
+}
+
 void Problem::precond_oseen(int kind, const double* r, double* z, int batch, Gate gate) {
   const GmresScalars* gs = (gate.p == gm_gate().p) ? d_gm : nullptr;
   const bool tr = (kind == 3 || kind == 4);
@@ -1904,6 +2014,11 @@ void Problem::precond_oseen(int kind, const double* r, double* z, int batch, Gat
     if (mixed) pcd_schur<float>(r, z, ldw, batch, gate, tr);
     else pcd_schur<double>(r, z, ldw, batch, gate, tr);
     launch_gm_zero_range(z, ldw, g.off_p0(), g.n0, batch, gs, st);
+  } else if (d.oseen_schur != 0) {
+    if (kind == 3) throw std::runtime_error("unsupported:the transposed M_2 / M_3 preconditioner");
+    if (batch != 1) throw std::runtime_error("unsupported:M_2 / M_3 take one right-hand side");
+    if (mixed) schur2<float>(r, z, gate);
+    else schur2<double>(r, z, gate);
   } else {
     mq_solve(r, z, ldw, batch, gate, -d.nu);
   }
@@ -2099,7 +2214,10 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
   }
   std::vector<double> a2(batch);
   for (int r = 0; r < batch; ++r) a2[r] = eta * bn[r];
-  run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint, o.use_graph != 0);
+  // the M_2 / M_3 Schur blocks synchronise with the host inside (inner CG):
+  // their Arnoldi steps run eagerly
+  run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint,
+             o.use_graph != 0 && d.oseen_schur == 0);
   if (want_hist) take_hist();
   // a result whose true residual exceeds that of the initial guess (the
   // preconditioner made no headway, e.g. a convection-dominated F beyond

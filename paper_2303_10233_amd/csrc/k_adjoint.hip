@@ -103,9 +103,37 @@ __global__ __launch_bounds__(NT) void k_grad_viscosity(Geo g, const double* __re
   reduce_and_finish<NT>(rc, rhs, blockIdx.y * gridDim.x + blockIdx.x, vals, sred);
 }
 
+// x_u <- diag(M_v)^{-1} x_u on the interior velocity nodes (zero on the
+// boundary) and x_p <- 0: the M^{-1} between B^T and B in B M^{-1} B^T
+// (two-field PCD and LSC).  The assembled diagonal of the Q2 mass matrix is
+// (h/30)^2 m(I) m(J) with m = 8 at a vertex and 16 at a mid node.
+__global__ __launch_bounds__(NT) void k_vel_minv(Geo g, double* __restrict__ x) {
+  const long long k = (long long)blockIdx.x * NT + threadIdx.x;
+  const long long np = (long long)g.nk + g.n0;
+  if (k >= 2LL * g.nv + np) return;
+  if (k >= 2LL * g.nv) {
+    x[k] = 0.0;
+    return;
+  }
+  const int node = (int)(k % g.nv), nq = g.nq, top = nq - 1;
+  const int I = node % nq, J = node / nq;
+  if (on_boundary(I, J, top)) {
+    x[k] = 0.0;
+    return;
+  }
+  const double mi = (I & 1) ? 16.0 : 8.0, mj = (J & 1) ? 16.0 : 8.0;
+  const double d = (g.h / 30.0) * (g.h / 30.0) * mi * mj;
+  x[k] = x[k] / d;
+}
+
 inline unsigned nblk(long long n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
+
+void launch_vel_minv(const Geo& g, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_vel_minv, dim3(nblk(g.N)), dim3(NT), 0, st, g, x);
+  ETH_LAUNCH_CHECK();
+}
 
 int adjoint_blocks(const Geo& g) { return 2 * (int)nblk(g.nv); }
 

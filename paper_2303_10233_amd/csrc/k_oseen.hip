@@ -850,9 +850,55 @@ __global__ __launch_bounds__(1024) void k_wind_speed_max(Geo g, const double* __
   }
 }
 
+// y = F_0 (scale * x) on the elements (two-field PCD, Sec. 3.1): the
+// cell-centred operator of -nu Lap + w . grad from the jumps across interior
+// edges -- diffusion nu (x_T - x_U) per edge (|e| / d = 1 on squares),
+// convection by the upwind value times the edge flux F_e = int_e w . n,
+// integrated exactly from the edge's three nodal wind values (Simpson).
+// x, y: element vectors (n^2, index ey*n + ex).
+__global__ void k_p0_cd_apply(Geo g, const double* __restrict__ wind, double nu, const double* __restrict__ x,
+                              double scale, double* __restrict__ y) {
+  const int T = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = g.n;
+  if (T >= n * n) return;
+  const int ex = T % n, ey = T / n, nq = g.nq;
+  const double h = g.h;
+  const double* wx = wind;
+  const double* wy = wind + g.nv;
+  auto vflux = [&](int I) {   // int over the vertical edge x = x0 + (I/2) h of element row ey of w_x
+    const int J0 = 2 * ey;
+    return (wx[(long long)J0 * nq + I] + 4 * wx[(long long)(J0 + 1) * nq + I] + wx[(long long)(J0 + 2) * nq + I]) *
+           h / 6.0;
+  };
+  auto hflux = [&](int J) {   // int over the horizontal edge y = y0 + (J/2) h of element column ex of w_y
+    const int I0 = 2 * ex;
+    return (wy[(long long)J * nq + I0] + 4 * wy[(long long)J * nq + I0 + 1] + wy[(long long)J * nq + I0 + 2]) *
+           h / 6.0;
+  };
+  const double xt = scale * x[T];
+  double acc = 0.0;
+  auto edge = [&](int U, double out) {
+    const double xu = scale * x[U];
+    acc += nu * xt;
+    acc += -nu * xu;
+    acc += out > 0 ? out * xt : out * xu;
+  };
+  if (ex > 0) edge(T - 1, -vflux(2 * ex));
+  if (ex < n - 1) edge(T + 1, vflux(2 * ex + 2));
+  if (ey > 0) edge(T - n, -hflux(2 * ey));
+  if (ey < n - 1) edge(T + n, hflux(2 * ey + 2));
+  y[T] = acc;
+}
+
 inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_p0_cd_apply(const Geo& g, const double* wind, double nu, const double* x, double scale, double* y,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_p0_cd_apply, dim3(nb((long long)g.n * g.n)), dim3(256), 0, st, g, wind, nu, x, scale, y);
+  ETH_LAUNCH_CHECK();
+}
 
 void launch_wind_speed_max(const Geo& g, const double* wind, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_wind_speed_max, dim3(1), dim3(1024), 0, st, g, wind, out);

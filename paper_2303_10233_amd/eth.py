@@ -18,6 +18,7 @@ FP64, MIXED = 0, 1
 VEL_GMG, VEL_EXACT = 0, 1
 MQ_DIAG, MQ_CHEB_SGS, MQ_SCHUR_GMG = 1, 2, 3
 MINRES, FGMRES, TWO_STAGE = 0, 1, 2
+SCHUR_M1, SCHUR_M2_PCD, SCHUR_M3_LSC = 0, 1, 2
 OK, EINVAL, EDEVICE, ENOMEM, EINCONSISTENT, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 WMAXIT, WNOPROGRESS = 1, 2
 
@@ -51,6 +52,9 @@ class ProblemDesc(ctypes.Structure):
         ("mq_tile", ctypes.c_int32),
         ("mq_fuse_steps", ctypes.c_int32),
         ("gmg_peclet_max", ctypes.c_double),
+        ("oseen_schur", ctypes.c_int32),
+        ("schur_cg_tol", ctypes.c_double),
+        ("schur_cg_maxit", ctypes.c_int32),
     ]
 
 
@@ -231,7 +235,8 @@ def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
                wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0, mq_cheb=(0.0, 0.0),
                gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0), gmg_lambda=None, precision=FP64,
                max_batch=1, device=None, gmg_omega=0.0, pcd_q1_steps=0, gmres_restart=0,
-               mq_tile=0, mq_fuse_steps=0, gmg_peclet_max=0.0):
+               mq_tile=0, mq_fuse_steps=0, gmg_peclet_max=0.0, oseen_schur=0, schur_cg_tol=0.0,
+               schur_cg_maxit=0):
     """A filled ProblemDesc and the Python objects it points into."""
     d = ProblemDesc()
     d.n = n
@@ -260,6 +265,9 @@ def _make_desc(n, domain=(0.0, 1.0, 0.0, 1.0), nu=1.0, lid_u=1.0, corner_mode=0,
     d.mq_tile = mq_tile
     d.mq_fuse_steps = mq_fuse_steps
     d.gmg_peclet_max = gmg_peclet_max
+    d.oseen_schur = oseen_schur
+    d.schur_cg_tol = schur_cg_tol
+    d.schur_cg_maxit = schur_cg_maxit
     dev = torch.device("cuda" if device is None else device)
     with torch.cuda.device(dev):
         d.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -273,7 +281,8 @@ class Problem:
                  kind=STOKES, wind=None, velocity=VEL_GMG, mq=MQ_CHEB_SGS, mq_steps=0,
                  mq_cheb=(0.0, 0.0), gmg_coarse_n=0, gmg_degree=0, gmg_frac=(0.0, 0.0),
                  gmg_lambda=None, precision=FP64, max_batch=1, device=None, gmg_omega=0.0,
-                 pcd_q1_steps=0, gmres_restart=0, mq_tile=0, mq_fuse_steps=0, gmg_peclet_max=0.0):
+                 pcd_q1_steps=0, gmres_restart=0, mq_tile=0, mq_fuse_steps=0, gmg_peclet_max=0.0,
+                 oseen_schur=0, schur_cg_tol=0.0, schur_cg_maxit=0):
         d, keep = _make_desc(**{k: v for k, v in locals().items() if k not in ("self", "__class__")})
         self._keep = keep
         h = ctypes.c_void_p()
