@@ -72,6 +72,27 @@ def time_solves(P, b, steps, warmup, rtol, use_graph):
     return dt, its, info
 
 
+def cpu_identity():
+    """What the host baseline ran on: core counts, affinity, CPU model and the
+    BLAS / OpenMP thread settings."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    return {"os_cpu_count": os.cpu_count(), "affinity": affinity, "cpu_model": model,
+            "thread_env": {k: v for k, v in env.items() if v is not None}}
+
+
 def cpu_baseline(n, iterations_per_solve, cpu_iters):
     """The oracle (NumPy/SciPy, FP64, as it stands) on the same workload: a
     bounded sample of `cpu_iters` MINRES iterations with the same
@@ -98,6 +119,7 @@ def cpu_baseline(n, iterations_per_solve, cpu_iters):
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
+        "host": cpu_identity(),
         "sample": (f"{cpu_iters} MINRES iterations of the NumPy/SciPy oracle at n={n} "
                    f"(GMG V(2,2) + 20 Chebyshev-SGS steps, FP64; {dt:.1f} s, setup "
                    f"{t_setup:.1f} s excluded), scaled by the GPU iteration count "
@@ -106,22 +128,117 @@ def cpu_baseline(n, iterations_per_solve, cpu_iters):
     }
 
 
-def bench_oseen(n, nu, prec, steps, rtol, maxit=1000):
+def _pool_minres_sample(args):
+    """Worker of the k-core oracle pool: MINRES iterations of the oracle at
+    n x n with one Gaussian-bump forcing (GMG + Chebyshev-SGS, FP64)."""
+    n, seed, iters = args
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)          # one core per worker: k workers on k cores
+    from oracle.assemble import Mesh, System, lid_dirichlet
+    from oracle.krylov import minres
+    from oracle.precond import StokesBlockDiag
+    from paper_2303_10233_amd.workloads import gaussian_bumps
+    m = Mesh(n)
+    s = System(m)
+    b = s.to_interior(s.rhs(gaussian_bumps(n, seed), lid_dirichlet(m)))
+    P = StokesBlockDiag(s, "gmg", "cheb_sgs", mq_lo=min(0.01, 0.4 / n), mq_steps=20)
+    t0 = time.perf_counter()
+    minres(lambda v: s.K @ v, b, P, tol=1e-30, maxit=iters)
+    return time.perf_counter() - t0
+
+
+def cpu_other(gpu):
+    """Oracle baselines of the other configurations, timed on this host beside
+    the GPU figures (`gpu`: the GPU results they are compared with):
+    config 1 (16^2, exact velocity block, diagonal M_Q): direct solve with the
+    factorisation and the solve timed apart, and the oracle's own MINRES;
+    the 64-RHS batch at 128^2: a pool of k worker processes, each running a
+    bounded MINRES sample, scaled to solves/s on k cores; Oseen 128^2
+    (nu = 1/100): a bounded sample of the oracle's two-stage FGMRES with the
+    GPU's inexact pieces, scaled by the GPU's iteration count.  The direct
+    factorisation at 128^2 (SuperLU, about 250 s and 10-14 GB on the build
+    host) does not fit the bench's time budget and is not run here."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle.assemble import Mesh, System, lid_dirichlet, recirculating_wind
+    from oracle.direct import BorderedLU, canonicalize, rel_err
+    from oracle.krylov import minres
+    from oracle import precond as opc
+    out = {"host": cpu_identity()}
+    # config 1
+    m = Mesh(16)
+    s = System(m)
+    b = s.rhs(None, lid_dirichlet(m))
+    t0 = time.perf_counter()
+    lu = BorderedLU(s)
+    t_fact = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        xd = canonicalize(lu.solve(b), m)
+    t_solve = (time.perf_counter() - t0) / reps
+    P = opc.StokesBlockDiag(s, "exact", "diag")
+    t0 = time.perf_counter()
+    _, info = minres(lambda v: s.K @ v, s.to_interior(b), P, tol=1e-6, maxit=3000)
+    t_minres = time.perf_counter() - t0
+    c1 = {"cores": 1, "direct_factor_s": round(t_fact, 4), "direct_solve_s": round(t_solve, 5),
+          "direct_solves_per_s": round(1.0 / t_solve, 2), "minres_iterations": info["iterations"],
+          "minres_s": round(t_minres, 3), "minres_solves_per_s": round(1.0 / t_minres, 2)}
+    if gpu.get("c1_x") is not None:
+        c1["gpu_rel_err_vs_direct"] = float(rel_err(gpu["c1_x"], xd))
+    out["config1_stokes16"] = c1
+    # 64-RHS batch at 128^2 on a pool of k cores
+    k = max(1, min(8, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1))
+    iters = 10
+    with mp.get_context("fork").Pool(k) as pool:
+        t0 = time.perf_counter()
+        times = pool.map(_pool_minres_sample, [(128, 1000 + i, iters) for i in range(k)])
+        wall = time.perf_counter() - t0
+    per_iter = float(np.mean(times)) / iters
+    its = gpu.get("batch64_iterations") or 62
+    out["batch64_stokes128"] = {
+        "cores": k, "solves_per_s": round(k / (per_iter * its), 4),
+        "sample": (f"{k} processes (one BLAS thread each) x {iters} MINRES iterations of the oracle at "
+                   f"128^2 (one bump forcing each, {wall:.1f} s wall with set-up), scaled by the GPU "
+                   f"iteration count {its}"),
+        "seconds_per_iteration": round(per_iter, 4)}
+    # Oseen 128^2, nu = 1/100, two-stage with the GPU's inexact pieces
+    n = 128
+    m = Mesh(n, -1, 1, -1, 1)
+    s = System(m, nu=0.01, wind=recirculating_wind(m))
+    b = s.rhs(None, lid_dirichlet(m))
+    vel, _ = opc.oseen_velocity_gmg(s)
+    P1 = opc.PCDStage1Inexact(s, vel)
+    P2 = opc.OseenM1(s, velocity_solve=vel, mq=opc.MQChebSGS(m, s.MQ, min(0.01, 0.4 / n), 1.0, 20))
+    sample = 20
+    t0 = time.perf_counter()
+    opc.two_stage(s, b, eta=1e-30, maxit=sample // 2, stage1_prec=P1, stage2_prec=P2)
+    dt = time.perf_counter() - t0
+    its = gpu.get("oseen128_iterations") or 60
+    out["oseen128_nu100"] = {"cores": 1, "solves_per_s": round(1.0 / (dt / sample * its), 5),
+                             "sample": (f"{sample} two-stage FGMRES iterations of the oracle ({dt:.1f} s), "
+                                        f"scaled by the GPU iteration count {its}"),
+                             "seconds_per_iteration": round(dt / sample, 4)}
+    return out
+
+
+def bench_oseen(n, nu, prec, steps, rtol, maxit=1000, peclet_max=0.0):
     """Two-stage PCD FGMRES(50) on the recirculating-wind Oseen problem."""
     import torch
     from paper_2303_10233_amd import eth
     from paper_2303_10233_amd.workloads import recirculating_wind
     w = torch.as_tensor(recirculating_wind(n), dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
-    P = eth.Problem(n, domain=(-1.0, 1.0, -1.0, 1.0), nu=nu, kind=eth.OSEEN, wind=w, precision=prec)
+    P = eth.Problem(n, domain=(-1.0, 1.0, -1.0, 1.0), nu=nu, kind=eth.OSEEN, wind=w, precision=prec,
+                    gmg_peclet_max=peclet_max)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     b = P.assemble_rhs()
-    x, info = P.solve(b, rtol=rtol, maxit=maxit, method=eth.TWO_STAGE)   # warm-up
+    x, info = P.solve(b, rtol=rtol, maxit=maxit, method=eth.TWO_STAGE, raise_on_error=False)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        x, info = P.solve(b, rtol=rtol, maxit=maxit, method=eth.TWO_STAGE, out=x)
+        x, info = P.solve(b, rtol=rtol, maxit=maxit, method=eth.TWO_STAGE, out=x, raise_on_error=False)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     i = info[0]
@@ -311,23 +428,36 @@ def counters_run(n, reps, tile, which="mq"):
     timing-based choices would differ between runs).
     which = "apply": the FP64 saddle apply with its fused dot at n = 2048, the
     stencil bandwidth figure (one 336 MB vector in, one out).
+    which = "oseen": the Oseen saddle apply (FP64) and the damped-Jacobi F
+    smoothing step (FP64 and FP32) at n = 2048.
     Prints the launch record the reduction script needs."""
     import torch
     from paper_2303_10233_amd import eth
     rec = {"n": n, "reps": reps, "launches": [], "which": which}
     if which == "apply":
         plan = ((2048, eth.FP64, (eth.K_SADDLE_APPLY, eth.K_COPY)),)
+    elif which == "oseen":
+        plan = ((2048, eth.FP64, (eth.K_OSEEN_APPLY, eth.K_CD_STEP, eth.K_COPY)),
+                (2048, eth.MIXED, (eth.K_CD_STEP,)))
     else:
         plan = ((n, eth.MIXED, (eth.K_MQ_CHEB_STEP, eth.K_COPY)), (2048, eth.MIXED, (eth.K_COPY,)))
     for nn, prec, kernels in plan:
-        P = eth.Problem(nn, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0",
-                        mq_tile=tile)
+        if which == "oseen":
+            from paper_2303_10233_amd.workloads import recirculating_wind
+            w = torch.as_tensor(recirculating_wind(nn), dtype=torch.float64, device="cuda:0")
+            P = eth.Problem(nn, domain=(-1.0, 1.0, -1.0, 1.0), nu=0.01, kind=eth.OSEEN, wind=w, precision=prec,
+                            device="cuda:0", gmres_restart=8)
+        else:
+            P = eth.Problem(nn, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_CHEB_SGS, device="cuda:0",
+                            mq_tile=tile)
         torch.cuda.synchronize()
         for k in kernels:
             ms, by = P.profile_kernel(k, reps=reps)
+            var = P.mq_variant() if which != "oseen" else (0, 0)
             rec["launches"].append(dict(n=nn, kernel=eth.KERNEL_NAMES[k], bytes_per_launch=by,
-                                        avg_us=round(1e3 * ms, 3), mq_tile=P.mq_variant()[0],
-                                        mq_steps_per_launch=P.mq_variant()[1]))
+                                        avg_us=round(1e3 * ms, 3), mq_tile=var[0],
+                                        mq_steps_per_launch=var[1],
+                                        precision="mixed" if prec == eth.MIXED else "fp64"))
             log(f"counters n={nn} {eth.KERNEL_NAMES[k]}: {by:.0f} B, {1e3 * ms:.2f} us")
         P.close()
         del P
@@ -354,8 +484,9 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="only the launches read by the rocprofv3 byte counters (see counters_run)")
     ap.add_argument("--mq-tile", type=int, default=16, help="tile side of the fused M_Q step in --counters")
-    ap.add_argument("--counters-kernel", choices=["mq", "apply"], default="mq",
-                    help="kernel of --counters: the fused M_Q step (headline) or the FP64 apply at n = 2048")
+    ap.add_argument("--counters-kernel", choices=["mq", "apply", "oseen"], default="mq",
+                    help="kernel of --counters: the fused M_Q step (headline), the FP64 apply at n = 2048, "
+                         "or the Oseen apply and F smoothing step at n = 2048")
     ap.add_argument("--mq-variant", default="auto",
                     help="fused M_Q step of the headline solves as TILExSTEPS (e.g. 16x1), or auto (set-up "
                          "timing); a profiler serialises the two preconditioner branches, so a profiled run "
@@ -421,12 +552,41 @@ def main():
                                             us_per_iteration=1e3 * ms * cnt)
     dom = max(kernels, key=lambda k: kernels[k]["us_per_iteration"])
     dk = kernels[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(dk["gbs"], 2),
+    s_mixed = 4.0
+    n_p = (n + 1) ** 2 + n * n
+    N_u = 2 * (2 * n + 1) ** 2
+    N_all = N_u + n_p
+    # the bytes the roofline counts: the cost model's per-unit figure for the
+    # dominant kernel (a Chebyshev-SGS step moves 10 s n_p: r, z, d and the
+    # symmetric sweep's reads and writes), the kernel's own fused minimum
+    # (read r, z, d; write z, d: 5 s n_p) reported beside it
+    if dom == "k_mq_cheb_fused":
+        steps_per_launch = Pm.mq_variant()[1]
+        model_bytes = 10.0 * s_mixed * n_p * steps_per_launch
+    else:
+        model_bytes = dk["bytes"]
+    achieved = model_bytes / (dk["avg_us"] * 1e-6) / 1e9
+    working_set = 8.0 * N_all * 8    # eight FP64 Krylov vectors
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
                 "peak": MI355X_HBM_GBS, "unit": "GB/s",
-                "frac": round(dk["gbs"] / MI355X_HBM_GBS, 5),
+                "frac": round(achieved / MI355X_HBM_GBS, 5),
                 "traffic": measured_traffic(dom, n, "k_mq_cheb_fused<float, %d, %d>" % Pm.mq_variant()[:2]
                                             if dom == "k_mq_cheb_fused" else None),
-                "bytes_per_launch": dk["bytes"], "avg_launch_us": round(dk["avg_us"], 3)}
+                "bytes_per_launch": model_bytes, "bytes_fused_min": dk["bytes"],
+                "avg_launch_us": round(dk["avg_us"], 3),
+                "mall_resident": working_set < 256e6,
+                "note": ("working set below the 256 MB Infinity Cache: the figure is a cache/latency "
+                         "rate, not an HBM one; HBM-scale kernel rates are in microbench")}
+
+    def iteration_roofline(s_bytes, seconds, iterations):
+        # cost model per MINRES iteration: Krylov vectors (FP64) + one V-cycle
+        # + 20 Chebyshev-SGS steps
+        by = 104.0 * N_all + s_bytes * N_u * 21 + 16.0 * N_u + 10.0 * s_bytes * n_p * 20
+        t = seconds / args.steps / iterations
+        return {"bytes": by, "us": round(t * 1e6, 2), "achieved": round(by / t / 1e9, 1),
+                "frac": round(by / t / 1e9 / MI355X_HBM_GBS, 4), "unit": "GB/s"}
+    iter_roof = {"mixed": iteration_roofline(4.0, mixed["seconds"], its_m),
+                 "fp64": iteration_roofline(8.0, fp64["seconds"], fp64["iterations"][-1])}
     log("kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us {v['gbs']:.0f}GB/s"
                                 for k, v in kernels.items()))
 
@@ -440,12 +600,23 @@ def main():
                 extra["oseen"].append(r)
                 log(f"oseen n={on} nu=1/100 {name}: {r['solves_per_s']} solves/s, "
                     f"{r['iterations']} its ({r['stage1_iterations']} stage I)")
+        # nu = 1/1000: the plain F multigrid makes no headway (status no-progress);
+        # with the Peclet cap the solve progresses but, as with exact pieces in
+        # the oracle, does not reach 1e-6 within 4096 iterations
         r = bench_oseen(128, 0.001, eth.MIXED, 1, args.rtol, maxit=300)
         r["precision"] = "mixed"
-        r["note"] = ("nu = 1/1000 (cell Peclet 15.6): the unstabilised damped-Jacobi F multigrid "
-                     "diverges; reported with maxit 300")
+        r["note"] = "nu = 1/1000 (element Peclet 15.6), plain damped-Jacobi F multigrid, maxit 300"
         extra["oseen"].append(r)
-        log(f"oseen n=128 nu=1/1000: status {r['status']}, residual {r['rel_residual']:.2e}")
+        log(f"oseen n=128 nu=1/1000 plain: status {r['status']}, residual {r['rel_residual']:.2e}")
+        for on in (128, 256):
+            for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+                r = bench_oseen(on, 0.001, prec, 1, args.rtol, maxit=4096, peclet_max=4.0)
+                r["precision"] = name
+                r["note"] = ("nu = 1/1000, F multigrid with element Peclet cap 4, maxit 4096 (exact pieces "
+                             "in the oracle need more than 4096 per stage at 64^2 and 128^2)")
+                extra["oseen"].append(r)
+                log(f"oseen n={on} nu=1/1000 cap 4 {name}: status {r['status']}, {r['iterations']} its, "
+                    f"residual {r['rel_residual']:.2e}, {r['ms_per_solve']} ms")
         extra["oseen_picard"] = []
         for on in (128, 256):
             for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
@@ -496,11 +667,29 @@ def main():
 
     micro = None if args.no_micro else microbench(20)
 
+    # configuration 1 on the GPU (16^2, exact velocity block, diagonal M_Q,
+    # FP64 MINRES to 1e-6): rate, and the solution for the error against the
+    # oracle's direct solve
+    P1 = eth.Problem(16, precision=eth.FP64, velocity=eth.VEL_EXACT, mq=eth.MQ_DIAG)
+    b1 = P1.assemble_rhs()
+    dt1, its1, _ = time_solves(P1, b1, args.steps, args.warmup, args.rtol, use_graph)
+    x1, _ = P1.solve(b1, rtol=args.rtol, maxit=3000, use_graph=use_graph)
+    c1_gpu = {"solves_per_s": round(args.steps / dt1, 2), "iterations": its1[-1]}
+    c1_x = x1.cpu().numpy()
+    P1.close()
+
     cpu = None
+    cpu_more = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")
         cpu = cpu_baseline(n, its_m, args.cpu_iters)
         log(f"oracle: {cpu['value']:.4g} solves/s ({cpu['seconds_per_iteration']:.2f} s/iteration)")
+        g = {"c1_x": c1_x}
+        if extra:
+            g["batch64_iterations"] = extra["batch64"]["mixed"]["iterations_max"]
+            g["oseen128_iterations"] = extra["oseen"][0]["iterations"]
+        cpu_more = cpu_other(g)
+        log(f"oracle, other configurations: {json.dumps(cpu_more)}")
 
     value = args.steps / mixed["seconds"]
     out = {
@@ -535,9 +724,12 @@ def main():
         "mixed_over_fp64": round(fp64["seconds"] / mixed["seconds"], 4),
         "equal_residual_ok": bool(equal_residual_ok),
         "roofline": roofline,
+        "iteration_roofline": iter_roof,
+        "config1_stokes16": c1_gpu,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        "cpu_other": cpu_more,
         "other_workloads": extra,
         "microbench": micro,
     }

@@ -7,7 +7,9 @@ copy of known size (n = 2048: 336 MB per vector, beyond every cache).
         --launches counters.json --kernel k_mq_cheb_fused --out profiles/...json
 
 (--kernel k_apply with the record of `bench.py --counters --counters-kernel
-apply`: the FP64 saddle apply at n = 2048.)
+apply`: the FP64 saddle apply at n = 2048; --kernel k_apply_oseen or
+k_cd_step --precision fp64|mixed with the record of `--counters-kernel
+oseen`: the Oseen apply and the damped-Jacobi F smoothing step at n = 2048.)
 
 The result records the sha256 of the kernel's source file, so a reader can
 tell when the counters no longer describe the code.
@@ -20,7 +22,8 @@ import os
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = {"k_mq_cheb_fused": "k_mq.hip", "k_apply": "k_apply.hip", "k_cheb_step": "k_gmg.hip"}
+SOURCES = {"k_mq_cheb_fused": "k_mq.hip", "k_apply": "k_apply.hip", "k_cheb_step": "k_gmg.hip",
+           "k_apply_oseen": "k_apply.hip", "k_cd_step": "k_oseen.hip"}
 
 
 def per_dispatch(path, counter):
@@ -40,6 +43,17 @@ def pick(groups, name_part, grid_size):
     if not v:
         raise SystemExit(f"no dispatch of {name_part!r} with {grid_size} work-items")
     return sum(v) / len(v), len(v)
+
+
+def modal_grid(groups, name_part):
+    """The grid size most dispatches of a kernel share (the profile loop's)."""
+    count = {}
+    for (name, gs), vals in groups.items():
+        if name_part in name:
+            count[gs] = count.get(gs, 0) + len(vals)
+    if not count:
+        raise SystemExit(f"no dispatch of {name_part!r}")
+    return max(count, key=count.get)
 
 
 def vector_length(n):
@@ -72,13 +86,15 @@ def main():
     ap.add_argument("--write", required=True)
     ap.add_argument("--launches", required=True, help="the JSON line printed by bench.py --counters")
     ap.add_argument("--kernel", default="k_mq_cheb_fused")
+    ap.add_argument("--precision", default=None, help="fp64 or mixed (records with several)")
     ap.add_argument("--commands", nargs=2, metavar=("FETCH_CMD", "WRITE_CMD"), default=None)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     with open(a.launches) as f:
         rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
-    n = 2048 if a.kernel == "k_apply" else rec["n"]
-    target = [x for x in rec["launches"] if x["kernel"] == a.kernel and x["n"] == n][0]
+    n = 2048 if a.kernel in ("k_apply", "k_apply_oseen", "k_cd_step") else rec["n"]
+    target = [x for x in rec["launches"] if x["kernel"] == a.kernel and x["n"] == n and
+              (a.precision is None or x.get("precision") == a.precision)][0]
     big_copy = [x for x in rec["launches"] if x["kernel"] == "k_copy" and x["n"] == 2048][0]
     small_copy = [x for x in rec["launches"] if x["kernel"] == "k_copy" and x["n"] == n][0]
     fetch = per_dispatch(a.fetch, "FETCH_SIZE")
@@ -92,8 +108,17 @@ def main():
         name = "k_apply<true, false, false>"
         grid = apply_grid(n)
         workload = f"Stokes saddle apply with its fused dot, FP64, {n}x{n} (one 336 MB vector in, one out)"
+    elif a.kernel == "k_apply_oseen":
+        name = "k_apply<true, true, false>"
+        grid = modal_grid(fetch, name)
+        workload = f"Oseen saddle apply with its fused dot, FP64, {n}x{n} (336 MB vector in, one out, wind)"
+    elif a.kernel == "k_cd_step":
+        t = "float" if target.get("precision") == "mixed" else "double"
+        name = f"k_cd_step<{t}, 0, false>"
+        grid = modal_grid(fetch, name)
+        workload = f"damped-Jacobi F smoothing step, finest level, {t}, {n}x{n}, both velocity planes"
     else:
-        raise SystemExit("kernels described here: k_mq_cheb_fused, k_apply")
+        raise SystemExit("kernels described here: k_mq_cheb_fused, k_apply, k_apply_oseen, k_cd_step")
     f_kib, nf = pick(fetch, name, grid)
     w_kib, nw = pick(write, name, grid)
     cf_big, _ = pick(fetch, "k_copy", copy_grid(2048))
