@@ -256,6 +256,15 @@ int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas);
 int eth_get_mq_tile(const eth_problem* p, int32_t* tile_1, int32_t* tile_max, int32_t* steps_1,
                     int32_t* steps_max);
 
+/* Set-up choices made by timing (the fused Chebyshev step's variant for one
+ * and for max_batch right-hand sides, the V(2,2) smoothing launch pattern):
+ * how many were timed during this set-up and how many were read from the
+ * set-up cache instead.  The cache is a text file of "key value" lines keyed
+ * by device (architecture, compute units), kernel or launch pattern, storage
+ * type, mesh size and batch: $ETH_TUNE_CACHE (empty: no cache), default
+ * $HOME/.cache/eth_tune.txt.  Either pointer may be NULL. */
+int eth_tuning_source(const eth_problem* p, int32_t* timed, int32_t* cached);
+
 /* Replace the nodal Q2 wind of an Oseen problem (device, 2(2n+1)^2
  * [w_x|w_y], the w_h of eq:generic-conv-diff) and rebuild what depends on it:
  * the wind and the F diagonal of every multigrid level and the dense inverse

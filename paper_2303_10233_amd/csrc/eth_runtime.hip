@@ -14,11 +14,71 @@
 #include <vector>
 #include <map>
 #include <array>
+#include <filesystem>
+#include <fstream>
+#include <mutex>
+#include <sstream>
 
 #include "../../include/eth.h"
 #include "eth_kernels.h"
 
 namespace eth {
+
+// On-disk record of the choices set-up makes by timing, one "key value" line
+// per choice.  The key names the device (architecture and compute units),
+// the tuned kernel or launch pattern, the storage type, the mesh and the
+// batch, so a later set-up of the same problem on the same kind of GPU reads
+// the choice instead of timing it again.  ETH_TUNE_CACHE gives the file (an
+// empty value disables the cache); default $HOME/.cache/eth_tune.txt.
+struct TuneCache {
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
+  }
+  static std::string path() {
+    if (const char* e = std::getenv("ETH_TUNE_CACHE")) return std::string(e);
+    const char* h = std::getenv("HOME");
+    return h ? std::string(h) + "/.cache/eth_tune.txt" : std::string();
+  }
+  static std::string device() {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::ostringstream o;
+    o << prop.gcnArchName << "/" << prop.multiProcessorCount << "cu";
+    std::string s = o.str();
+    for (char& c : s)
+      if (c == ' ') c = '_';
+    return s;
+  }
+  static bool get(const std::string& key, std::string& val) {
+    const std::string p = path();
+    if (p.empty()) return false;
+    std::lock_guard<std::mutex> lk(mu());
+    std::ifstream f(p);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+      const size_t sp = line.rfind(' ');
+      if (sp != std::string::npos && line.compare(0, sp, key) == 0 && sp == key.size()) {
+        val = line.substr(sp + 1);   // the last record of a key wins
+        found = true;
+      }
+    }
+    return found;
+  }
+  static void put(const std::string& key, const std::string& val) {
+    const std::string p = path();
+    if (p.empty()) return;
+    std::lock_guard<std::mutex> lk(mu());
+    std::error_code ec;
+    const std::filesystem::path fp(p);
+    if (fp.has_parent_path()) std::filesystem::create_directories(fp.parent_path(), ec);
+    std::ofstream f(p, std::ios::app);
+    if (f) f << key << " " << val << "\n";
+  }
+};
 
 thread_local std::string g_setup_error;
 
@@ -195,6 +255,9 @@ struct Problem {
     return (long long)batch * batch > max_batch ? mq_var_hi : mq_var_lo;
   }
   MqVariant tune_mq_variant(int batch);
+  MqVariant cached_mq_variant(int batch);
+  void tune_vcycle_fusion();
+  int tuned_timed = 0, tuned_cached = 0;   // set-up choices timed / read from the cache
   template <typename T>
   void mq_chain(const MqVariant& v, T* rr, T* zz, T* tt, const double* r, long long ld, double* z,
                 double scale, bool sink_out, bool project_in, int batch, Gate gate);
@@ -482,7 +545,6 @@ void Problem::setup(const eth_problem_desc& desc) {
   // preconditioner indefinite, which MINRES reports as a breakdown
   if (const char* e = std::getenv("ETH_DEBUG_NEGATE_MQ")) mq_sign = (e[0] == '1') ? -1.0 : 1.0;
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) fused_mq = (e[0] != '1');
-  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_SMOOTH")) fused_smooth = (e[0] != '1');
   if (const char* e = std::getenv("ETH_GRAPH_ITERS")) graph_iters = std::max(2, std::min(64, std::atoi(e) & ~1));
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_Q1")) fused_q1 = (e[0] != '1');
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_APTAIL")) fused_aptail = (e[0] != '1');
@@ -541,6 +603,7 @@ void Problem::setup(const eth_problem_desc& desc) {
       ETH_HIP(hipEventCreateWithFlags(&ev_pf, hipEventDisableTiming));
       ETH_HIP(hipEventCreateWithFlags(&ev_pj, hipEventDisableTiming));
     }
+    if (d.velocity_mode == ETH_VEL_GMG) tune_vcycle_fusion();
   }
   build_pressure();
   ETH_HIP(hipStreamSynchronize(st));
@@ -750,10 +813,87 @@ void Problem::build_pressure() {
       mq_var_lo.tile = mq_var_hi.tile = d.mq_tile;
       mq_var_lo.steps = mq_var_hi.steps = d.mq_fuse_steps > 0 ? d.mq_fuse_steps : 1;
     } else {
-      mq_var_lo = tune_mq_variant(1);
-      mq_var_hi = max_batch > 1 ? tune_mq_variant(max_batch) : mq_var_lo;
+      mq_var_lo = cached_mq_variant(1);
+      mq_var_hi = max_batch > 1 ? cached_mq_variant(max_batch) : mq_var_lo;
     }
   }
+}
+
+// tune_mq_variant through the set-up cache
+Problem::MqVariant Problem::cached_mq_variant(int batch) {
+  std::ostringstream k;
+  k << TuneCache::device() << " mq_cheb_fused " << (mixed ? "f32" : "f64") << " n=" << g.n << " batch=" << batch
+    << " steps=" << d.mq_steps << " fuse=" << d.mq_fuse_steps << " ctx=" << (pst != nullptr ? 1 : 0);
+  std::string v;
+  MqVariant r;
+  if (TuneCache::get(k.str(), v) && std::sscanf(v.c_str(), "%dx%d", &r.tile, &r.steps) == 2 &&
+      (r.tile == 16 || r.tile == 24 || r.tile == 32 || (r.tile == 64 && mixed)) && (r.steps == 1 || r.steps == 2)) {
+    ++tuned_cached;
+    return r;
+  }
+  r = tune_mq_variant(batch);
+  ++tuned_timed;
+  TuneCache::put(k.str(), std::to_string(r.tile) + "x" + std::to_string(r.steps));
+  return r;
+}
+
+// Launch pattern of the V(2,2) smoothing on the levels above the fused coarse
+// end: the second pre-smoothing step inside the restriction's launch and the
+// correction with both post-smoothing steps in one launch (fewer launches,
+// wider halos), or one launch per step (narrower halos).  Timed on whole
+// V-cycles at set-up, the choice kept in the set-up cache.
+// ETH_DEBUG_UNFUSED_SMOOTH = 1 / 0 forces one launch per step / the fused form.
+void Problem::tune_vcycle_fusion() {
+  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_SMOOTH")) {
+    fused_smooth = (e[0] != '1');
+    return;
+  }
+  if (d.gmg_degree != 2 || lv.size() < 2 || (tail_l0 >= 0 && tail_l0 < 1)) return;
+  std::ostringstream k;
+  k << TuneCache::device() << " vcycle_smoothing " << (mixed ? "f32" : "f64") << " n=" << g.n
+    << " batch=" << max_batch << " coarse=" << d.gmg_coarse_n;
+  std::string v;
+  if (TuneCache::get(k.str(), v) && (v == "fused" || v == "split")) {
+    fused_smooth = v == "fused";
+    ++tuned_cached;
+    return;
+  }
+  ETH_HIP(hipMemsetAsync(kv[0], 0, (size_t)ldw * max_batch * sizeof(double), st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ETH_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    throw std::runtime_error("hipEventCreate failed");
+  }
+  float best[2] = {0.0f, 0.0f};
+  try {
+    auto cycle = [&](bool f) {
+      fused_smooth = f;
+      if (mixed) vcycle<float>(kv[0], kz[0], ldw, max_batch, no_gate());
+      else vcycle<double>(kv[0], kz[0], ldw, max_batch, no_gate());
+    };
+    for (int f = 0; f < 2; ++f)
+      for (int i = 0; i < 3; ++i) cycle(f == 1);
+    for (int round = 0; round < 3; ++round)
+      for (int f = 0; f < 2; ++f) {
+        ETH_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < 10; ++i) cycle(f == 1);
+        ETH_HIP(hipEventRecord(e1, st));
+        ETH_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (round == 0 || ms < best[f]) best[f] = ms;
+      }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  fused_smooth = best[1] <= best[0];
+  ++tuned_timed;
+  TuneCache::put(k.str(), fused_smooth ? "fused" : "split");
 }
 
 // The fastest variant of the fused Chebyshev step (tile side, one or two
@@ -2705,6 +2845,13 @@ int eth_get_q1_levels(const eth_problem* p, int32_t* levels, double* lambdas) {
   if (levels) *levels = (int32_t)lv->size();
   if (lambdas)
     for (size_t i = 0; i < lam->size(); ++i) lambdas[i] = (*lam)[i];
+  return ETH_OK;
+}
+
+int eth_tuning_source(const eth_problem* p, int32_t* timed, int32_t* cached) {
+  if (!p) return ETH_EINVAL;
+  if (timed) *timed = p->impl.tuned_timed;
+  if (cached) *cached = p->impl.tuned_cached;
   return ETH_OK;
 }
 

@@ -130,6 +130,8 @@ def load_library(path=LIB_PATH):
     lib.eth_apply_pcd.restype = ctypes.c_int
     lib.eth_get_q1_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.eth_get_q1_levels.restype = ctypes.c_int
+    lib.eth_tuning_source.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.eth_tuning_source.restype = ctypes.c_int
     lib.eth_get_mq_tile.argtypes = [P] + [ctypes.POINTER(ctypes.c_int32)] * 4
     lib.eth_get_mq_tile.restype = ctypes.c_int
     lib.eth_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, i64, i64, ctypes.POINTER(SolveInfo)]
@@ -337,6 +339,12 @@ class Problem:
         """(tile side for one RHS, for max_batch RHS) of the fused Chebyshev
         step of MQ_CHEB_SGS, chosen at set-up unless mq_tile was given."""
         return self.mq_variant()[0::2]
+
+    def tuning_source(self):
+        """(choices timed at set-up, choices read from the set-up cache)"""
+        t, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().eth_tuning_source(self._h, ctypes.byref(t), ctypes.byref(c)), self._h)
+        return t.value, c.value
 
     def mq_variant(self):
         """(tile_1, steps_1, tile_max, steps_max): tile side and Chebyshev

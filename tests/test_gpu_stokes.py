@@ -216,6 +216,7 @@ def test_fused_smoothing_launches_equal_per_step_launches(n, prec, monkeypatch):
     m = Mesh(n)
     r = uniform_vector(m.N, 21 + n)
     r[: 2 * m.nv][System(m).vel_bnd] = 0.0
+    monkeypatch.setenv("ETH_DEBUG_UNFUSED_SMOOTH", "0")
     P = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_DIAG)
     z_fused = _np(P.apply_preconditioner(_t(r)))
     b = P.assemble_rhs()
