@@ -599,6 +599,12 @@ def main():
                  "fp64": iteration_roofline(8.0, fp64["seconds"], fp64["iterations"][-1])}
     log("kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us {v['gbs']:.0f}GB/s"
                                 for k, v in kernels.items()))
+    # persistent kernel or kernel boundaries: one step of a ring dependency
+    # over one block per CU, as dependent launches replayed from a graph and
+    # as rounds of one cooperative launch separated by grid-wide barriers
+    sync_probe = {"graph_launch_us": round(1e3 * Pm.profile_kernel(eth.K_SYNC_GRAPH, reps=1000)[0], 3),
+                  "grid_barrier_us": round(1e3 * Pm.profile_kernel(eth.K_SYNC_GRID, reps=1000)[0], 3)}
+    log(f"sync probe: {sync_probe}")
 
     extra = None
     if not args.no_extra:
@@ -736,6 +742,7 @@ def main():
         "equal_residual_ok": bool(equal_residual_ok),
         "roofline": roofline,
         "iteration_roofline": iter_roof,
+        "sync_probe": sync_probe,
         "config1_stokes16": c1_gpu,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},

@@ -389,6 +389,10 @@ int eth_infsup_estimate(eth_problem* p, int64_t rhs, double* gamma2, double* the
 #define ETH_K_GM_MDOT       10   /* a7: CGS multi-dot against m/2 Arnoldi vectors      */
 #define ETH_K_GM_MAXPY      11   /* a7: CGS update with m/2 Arnoldi vectors            */
 #define ETH_K_COPY          12   /* plain copy of N doubles (calibrates byte counters)  */
+#define ETH_K_SYNC_GRAPH    13   /* one step of a ring dependency over one block per CU
+                                    per launch, reps launches replayed as one graph     */
+#define ETH_K_SYNC_GRID     14   /* the same steps inside one cooperative launch,
+                                    separated by grid-wide barriers (persistent form)   */
 int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, double* avg_ms,
                        double* bytes);
 

@@ -197,6 +197,12 @@ void launch_p0_cd_apply(const Geo& g, const double* wind, double nu, const doubl
 // velocity part of a full vector times diag(M_v)^{-1} (interior nodes, else
 // 0), pressure part zeroed
 void launch_vel_minv(const Geo& g, double* x, hipStream_t st);
+// synchronisation probes (one block of 256 threads per CU; buf >= 512 * CUs
+// doubles): one step of a ring dependency per launch, or `rounds` steps in
+// one cooperative launch separated by grid-wide barriers (one per step)
+int sync_probe_blocks();
+void launch_sync_step(double* buf, int round, hipStream_t st);
+void launch_grid_sync_rounds(double* buf, int rounds, hipStream_t st);
 // *out = max over the Q2 nodes of |w| (device scalar)
 void launch_wind_speed_max(const Geo& g, const double* wind, double* out, hipStream_t st);
 // the coarse F as a dense row-major ni x ni matrix (A zero on entry)

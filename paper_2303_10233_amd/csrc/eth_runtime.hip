@@ -3106,6 +3106,49 @@ int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, doub
         by = 16.0 * N * B;   // read + write of N doubles per RHS: the calibration of byte counters
         break;
       }
+      case ETH_K_SYNC_GRAPH:
+      case ETH_K_SYNC_GRID: {
+        // persistent kernel vs kernel boundaries: per step of a ring
+        // dependency across one block per CU
+        const int nb = eth::sync_probe_blocks();
+        if ((long long)nb * 512 > P.ldw) throw std::invalid_argument("problem too small for the sync probe");
+        double* buf = P.kz[1];
+        ETH_HIP(hipMemsetAsync(buf, 0, sizeof(double) * 512 * nb, P.st));
+        hipEvent_t e0, e1;
+        ETH_HIP(hipEventCreate(&e0));
+        ETH_HIP(hipEventCreate(&e1));
+        float ms = 0.0f;
+        if (kernel == ETH_K_SYNC_GRID) {
+          eth::launch_grid_sync_rounds(buf, 4, P.st);   // warm-up
+          ETH_HIP(hipEventRecord(e0, P.st));
+          eth::launch_grid_sync_rounds(buf, reps, P.st);
+          ETH_HIP(hipEventRecord(e1, P.st));
+        } else {
+          hipGraph_t graph;
+          hipGraphExec_t exec;
+          hipStream_t cs;
+          ETH_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+          ETH_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+          for (int i = 0; i < reps; ++i) eth::launch_sync_step(buf, i, cs);
+          ETH_HIP(hipStreamEndCapture(cs, &graph));
+          ETH_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+          ETH_HIP(hipGraphLaunch(exec, P.st));   // warm-up
+          ETH_HIP(hipEventRecord(e0, P.st));
+          ETH_HIP(hipGraphLaunch(exec, P.st));
+          ETH_HIP(hipEventRecord(e1, P.st));
+          ETH_HIP(hipEventSynchronize(e1));
+          ETH_HIP(hipGraphExecDestroy(exec));
+          ETH_HIP(hipGraphDestroy(graph));
+          ETH_HIP(hipStreamDestroy(cs));
+        }
+        ETH_HIP(hipEventSynchronize(e1));
+        ETH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *avg_ms = (double)ms / reps;
+        *bytes = 16.0 * 256 * nb;
+        return ETH_OK;
+      }
       default:
         throw std::invalid_argument("unknown kernel id");
     }

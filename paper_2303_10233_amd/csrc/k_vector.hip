@@ -1,5 +1,7 @@
 // Krylov vector kernels: fused MINRES updates (alg:minres), deterministic dot
 // products and the pressure canonicalisation.  FP64 throughout.
+#include <hip/hip_cooperative_groups.h>
+
 #include "eth_kernels.h"
 #include "eth_reduce.h"
 
@@ -294,6 +296,53 @@ void launch_pressure_shift(const Geo& g, double* x, long long ld, int batch,
   hipLaunchKernelGGL(k_pressure_shift, dim3(blocks_for(np, 256), batch), dim3(256), 0, st, g, x,
                      ld, sums);
   ETH_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Synchronisation probes for the choice between kernel boundaries and a
+// persistent kernel: every round each thread of a one-block-per-CU grid
+// writes one value that the next round of another block reads (a halo-like
+// dependency), separated either by a grid-wide barrier inside one cooperative
+// launch or by the boundary between dependent launches.
+namespace {
+// step r reads slice (b + 1) mod nb of buffer r mod 2 and writes slice b of
+// the other buffer, so one barrier per step orders everything
+__device__ __forceinline__ void ring_step(double* buf, int nb, int b, int t, int r) {
+  const double* src = buf + (long long)(r & 1) * 256 * nb;
+  double* dst = buf + (long long)((r + 1) & 1) * 256 * nb;
+  dst[(long long)b * 256 + t] = src[(long long)((b + 1) % nb) * 256 + t] + (double)r;
+}
+
+__global__ __launch_bounds__(256) void k_sync_step(double* __restrict__ buf, int round) {
+  ring_step(buf, gridDim.x, blockIdx.x, threadIdx.x, round);
+}
+
+__global__ __launch_bounds__(256) void k_grid_sync_rounds(double* __restrict__ buf, int rounds) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  for (int r = 0; r < rounds; ++r) {
+    ring_step(buf, gridDim.x, blockIdx.x, threadIdx.x, r);
+    grid.sync();
+  }
+}
+}  // namespace
+
+int sync_probe_blocks() {
+  int dev = 0, cus = 0;
+  ETH_HIP(hipGetDevice(&dev));
+  ETH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return cus;
+}
+
+void launch_sync_step(double* buf, int round, hipStream_t st) {
+  hipLaunchKernelGGL(k_sync_step, dim3(sync_probe_blocks()), dim3(256), 0, st, buf, round);
+  ETH_LAUNCH_CHECK();
+}
+
+void launch_grid_sync_rounds(double* buf, int rounds, hipStream_t st) {
+  void* args[] = {(void*)&buf, (void*)&rounds};
+  ETH_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_grid_sync_rounds),
+                                     dim3(sync_probe_blocks()), dim3(256), args, 0, st));
 }
 
 }  // namespace eth

@@ -96,11 +96,13 @@ EXPORTED = [
 
 K_SADDLE_APPLY, K_CHEB_STEP, K_RESTRICT, K_PROLONG, K_MQ_CHEB_STEP, K_DOT, K_MINRES_V, K_MINRES_WX = range(8)
 K_OSEEN_APPLY, K_CD_STEP, K_GM_MDOT, K_GM_MAXPY, K_COPY = 8, 9, 10, 11, 12
+K_SYNC_GRAPH, K_SYNC_GRID = 13, 14
 KERNEL_NAMES = {
     K_SADDLE_APPLY: "k_apply", K_CHEB_STEP: "k_cheb_step", K_RESTRICT: "k_restrict",
     K_PROLONG: "k_prolong_add", K_MQ_CHEB_STEP: "k_mq_cheb_fused", K_DOT: "k_dot",
     K_MINRES_V: "k_minres_v", K_MINRES_WX: "k_minres_wx", K_OSEEN_APPLY: "k_apply_oseen",
     K_CD_STEP: "k_cd_step", K_GM_MDOT: "k_gm_mdot", K_GM_MAXPY: "k_gm_maxpy", K_COPY: "k_copy",
+    K_SYNC_GRAPH: "k_sync_step (graph)", K_SYNC_GRID: "k_grid_sync_rounds",
 }
 
 

@@ -514,3 +514,15 @@ def test_schur_gmg_solve_is_mesh_independent(prec):
             assert abs(info[0]["iterations"] - oinfo["iterations"]) <= 1
     print(f"  iterations {its}", flush=True)
     assert max(its) - min(its) <= 3
+
+
+def test_sync_probes_run():
+    """The persistent-kernel probe (grid-wide barriers in one cooperative
+    launch) and the launch-boundary probe (graph-replayed dependent launches)
+    both complete and report a per-step time."""
+    P = eth.Problem(128)      # the probe borrows a workspace of 512 doubles per CU
+    g, _ = P.profile_kernel(eth.K_SYNC_GRAPH, reps=200)
+    c, _ = P.profile_kernel(eth.K_SYNC_GRID, reps=200)
+    print(f"[sync probe] graph launch {1e3 * g:.2f} us, grid barrier {1e3 * c:.2f} us", flush=True)
+    assert 0 < g < 1.0 and 0 < c < 1.0
+    P.close()
