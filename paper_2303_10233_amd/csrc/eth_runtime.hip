@@ -19,10 +19,19 @@
 #include <mutex>
 #include <sstream>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/eth.h"
 #include "eth_kernels.h"
 
 namespace eth {
+
+// Phase ranges for timeline tools (rocprofv3 --marker-trace): set-up, each
+// solve and each stage of one.  Without a tool attached a range costs a call.
+struct PhaseRange {
+  explicit PhaseRange(const char* name) { roctxRangePushA(name); }
+  ~PhaseRange() { roctxRangePop(); }
+};
 
 // On-disk record of the choices set-up makes by timing, one "key value" line
 // per choice.  The key names the device (architecture and compute units),
@@ -334,8 +343,12 @@ struct Problem {
     if (count == 0) count = 1;
     if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
     allocs.push_back(p);
+    // debug mode: every workspace starts as NaN (all bits set), so a read of
+    // memory the code never wrote shows up in the results
+    if (nan_fill && hipMemset(p, 0xFF, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
     return static_cast<T*>(p);
   }
+  bool nan_fill = false;             // ETH_DEBUG_NAN_FILL=1
 
   ~Problem() {
     for (auto& ge : gexecs)
@@ -494,7 +507,9 @@ struct Problem {
 
 // ------------------------------------------------------------------------------
 void Problem::setup(const eth_problem_desc& desc) {
+  PhaseRange range("eth_setup");
   d = desc;
+  if (const char* e = std::getenv("ETH_DEBUG_NAN_FILL")) nan_fill = (e[0] == '1');
   if (d.n < 2) throw std::invalid_argument("n must be >= 2");
   if (!(d.x1 > d.x0) || !(d.y1 > d.y0)) throw std::invalid_argument("empty domain");
   if (std::fabs((d.x1 - d.x0) - (d.y1 - d.y0)) > 1e-12 * (d.x1 - d.x0))
@@ -1647,6 +1662,7 @@ int Problem::minres_finish(MinresRun& R, eth_solve_info* info) {
 
 int Problem::solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch,
                           long long ld, eth_solve_info* info, bool adjoint) {
+  PhaseRange range(adjoint ? "eth_minres_adjoint" : "eth_minres");
   MinresRun R;
   R.o = o;
   R.b = b;
@@ -2340,7 +2356,9 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
     }
   };
   std::vector<int> it1(batch, 0);
+  PhaseRange range(adjoint ? "eth_fgmres_adjoint" : "eth_fgmres");
   if (o.method == ETH_TWO_STAGE) {
+    PhaseRange stage("stage I (reduced system, PCD)");
     // stage I: reduced system [F B_1^T; B_1 0] (adjoint: its transpose), RHS
     // without the P0 rows
     launch_copy(g.N, kb, ldw, kv[0], ldw, batch, st);
@@ -2356,8 +2374,11 @@ int Problem::solve_oseen(const eth_solve_opts& o, const double* b, double* x, in
   for (int r = 0; r < batch; ++r) a2[r] = eta * bn[r];
   // the M_2 / M_3 Schur blocks synchronise with the host inside (inner CG):
   // their Arnoldi steps run eagerly
-  run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint,
-             o.use_graph != 0 && d.oseen_schur == 0);
+  {
+    PhaseRange stage("stage II (full system)");
+    run_fgmres(adjoint ? 3 : 1, false, kb, kx, batch, m, std::max(1, maxit), a2, adjoint,
+               o.use_graph != 0 && d.oseen_schur == 0);
+  }
   if (want_hist) take_hist();
   // a result whose true residual exceeds that of the initial guess (the
   // preconditioner made no headway, e.g. a convection-dominated F beyond
@@ -2723,6 +2744,7 @@ int eth_batch_solve(eth_batch* bt, const eth_solve_opts* opts, const double* con
     return ETH_EINVAL;
   }
   try {
+    eth::PhaseRange range("eth_batch_solve");
     std::vector<Problem::MinresRun> runs(count);
     std::vector<char> done(count, 0);
     ETH_HIP(hipEventRecord(bt->ev_in, bt->caller));

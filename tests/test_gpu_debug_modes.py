@@ -1,0 +1,53 @@
+"""Debug mode ETH_DEBUG_NAN_FILL=1: every workspace starts as NaN instead of
+whatever the allocator returned.  A solve that reads only what it wrote gives
+bit for bit the result of the default mode."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_2303_10233_amd import eth  # noqa: E402
+from paper_2303_10233_amd.workloads import recirculating_wind  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eth.load_library()
+
+
+def _stokes(prec):
+    P = eth.Problem(64, precision=prec, max_batch=2)
+    b = P.assemble_rhs(batch=2)
+    x, info = P.solve(b, rtol=1e-8, maxit=500, use_graph=True)
+    out = (x.clone(), [i["iterations"] for i in info])
+    P.close()
+    return out
+
+
+def _oseen(schur):
+    n = 32
+    w = torch.as_tensor(recirculating_wind(n), dtype=torch.float64, device="cuda:0")
+    P = eth.Problem(n, domain=(-1.0, 1.0, -1.0, 1.0), nu=0.01, kind=eth.OSEEN, wind=w, oseen_schur=schur)
+    b = P.assemble_rhs()
+    method = eth.TWO_STAGE if schur == 0 else eth.FGMRES
+    x, info = P.solve(b, rtol=1e-8, maxit=400, method=method, raise_on_error=False)
+    out = (x.clone(), [info[0]["iterations"]])
+    P.close()
+    return out
+
+
+@pytest.mark.parametrize("case", ["stokes_mixed", "stokes_fp64", "oseen_two_stage", "oseen_lsc"])
+def test_nan_filled_workspaces_change_nothing(case, monkeypatch):
+    print(f"[nan fill] {case}", flush=True)
+    run = {"stokes_mixed": lambda: _stokes(eth.MIXED), "stokes_fp64": lambda: _stokes(eth.FP64),
+           "oseen_two_stage": lambda: _oseen(0), "oseen_lsc": lambda: _oseen(2)}[case]
+    x0, it0 = run()
+    monkeypatch.setenv("ETH_DEBUG_NAN_FILL", "1")
+    x1, it1 = run()
+    assert it0 == it1
+    assert bool(torch.isfinite(x1).all())
+    assert torch.equal(x0, x1)
