@@ -84,6 +84,8 @@ typedef struct {
   double mq_cheb_lo;         /* eigen-interval of M_SGS^{-1} M_Q (default min(0.01, 0.4/n)) */
   double mq_cheb_hi;         /*   (default 1, the SGS bound)                        */
   int32_t gmg_coarse_n;      /* halve while n even and n > gmg_coarse_n (default 4;
+                                the coarsest level is solved with a dense inverse,
+                                so n = m 2^k needs an odd factor m <= 49;
                                 Oseen 32: coarse levels of the unstabilised F must
                                 keep a moderate cell Peclet number)                 */
   int32_t gmg_degree;        /* smoothing steps pre and post (default 2): Chebyshev

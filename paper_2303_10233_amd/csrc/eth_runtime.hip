@@ -26,6 +26,8 @@
 
 namespace eth {
 
+constexpr int kDenseCoarseMax = 97 * 97;   // interior nodes of the densely solved coarsest level
+
 // Phase ranges for timeline tools (rocprofv3 --marker-trace): set-up, each
 // solve and each stage of one.  Without a tool attached a range costs a call.
 struct PhaseRange {
@@ -691,7 +693,11 @@ void Problem::build_velocity() {
   }
   const Geo& gc = lv.back();
   coarse_ni = (gc.nq - 2) * (gc.nq - 2);
-  if (coarse_ni > 4225) throw std::runtime_error("unsupported:coarsest mesh too large for the dense solve (odd n > 33 needs n = m * 2^k with m <= 33)");
+  // the coarsest level is solved with a dense inverse (FP64, and an FP32
+  // copy in mixed precision): up to 97^2 interior nodes per component
+  // (odd factor m <= 49 of n = m * 2^k), 0.7 GB for the FP64 matrix
+  if (coarse_ni > kDenseCoarseMax)
+    throw std::runtime_error("unsupported:coarsest mesh too large for the dense solve (n = m * 2^k needs odd m <= 49)");
   dense_gbuf = alloc<double>((size_t)2 * coarse_ni * max_batch);
   // dense inverse of the coarsest-level Laplacian (Gauss-Jordan, SPD, no pivoting)
   {
@@ -1759,7 +1765,7 @@ void Problem::build_oseen_velocity() {
   }
   const Geo& gc = lv.back();
   coarse_ni = (gc.nq - 2) * (gc.nq - 2);
-  if (coarse_ni > 4225)
+  if (coarse_ni > kDenseCoarseMax)
     throw std::runtime_error("unsupported:coarsest mesh too large for the dense solve");
   dense_gbuf = alloc<double>((size_t)2 * coarse_ni * max_batch);
   f_work = alloc<double>(dense_inverse_work(coarse_ni));

@@ -135,3 +135,25 @@ def test_oseen_two_stage_full_vector_matches_direct(n, prec):
     assert info[0]["status"] == 0
     assert e[0] < (1e-8 if prec == eth.FP64 else 1e-6)
     P.close()
+
+
+@pytest.mark.parametrize("n,prec", [(70, eth.FP64), (74, eth.MIXED)])
+def test_meshes_with_a_large_odd_factor(n, prec):
+    """n = 2 * 35 and 2 * 37: the velocity multigrid ends on a 35^2 / 37^2
+    level (69^2 / 73^2 interior nodes per component) solved with its dense
+    inverse."""
+    print(f"[parity odd factor] n={n} prec={prec}", flush=True)
+    m = Mesh(n)
+    s = System(m)
+    xd = direct_solve(s, s.rhs(None, lid_dirichlet(m)))
+    P = eth.Problem(n, precision=prec)
+    levels, _ = P.levels()
+    assert levels == 2
+    b = P.assemble_rhs()
+    rtol, refine = (1e-12, 0) if prec == eth.FP64 else (1e-9, 4)
+    x, info = P.solve(b, rtol=rtol, maxit=3000, use_graph=True, refine=refine)
+    e = _parts(_np(x), xd, m)
+    print(f"  status={info[0]['status']} its={info[0]['iterations']} err={e[0]:.2e}", flush=True)
+    assert info[0]["status"] == 0
+    assert e[0] < (1e-8 if prec == eth.FP64 else 1e-6)
+    P.close()
