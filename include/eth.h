@@ -398,6 +398,102 @@ int eth_infsup_estimate(eth_problem* p, int64_t rhs, double* gamma2, double* the
 int eth_profile_kernel(eth_problem* p, int kernel, int reps, int64_t batch, double* avg_ms,
                        double* bytes);
 
+/* ---------------------------------------------------------------------------
+ * Flow over a step (Sec. 3, the inflow-outflow example): the domain
+ * [-1, 0) x [0, 1] union [0, L] x [-1, 1] (L = 5 in the paper), fixed walls,
+ * the parabolic inflow u_x = 4 y (1 - y) on x = -1 and the natural outflow
+ * condition on x = L, squares of side h = 1/m.  With an outflow the pressure
+ * function is unique: null(K) is spanned by [0; k] alone (Sec. 2, the frame
+ * null vector k = [1_{n_k}; -1_{n_0}]).
+ *
+ * Layout of a state vector (length N, device, FP64): [u_x (n_v) | u_y (n_v) |
+ * p_1 (n_k) | p_0 (n_0)] over the Q2 nodes, Q1 nodes and elements of the
+ * bounding box [-1, L] x [-1, 1] that belong to the domain, each counted row
+ * by row (y outer, x inner); eth_step_host_layout gives their grid indices.
+ * Velocity rows of Dirichlet nodes (walls, inflow) carry the boundary values
+ * in a right-hand side and in a solution; the operator ignores them.
+ *
+ * The geometry is not one square, so the operators are assembled on the host
+ * at set-up (and again for every new wind) and applied on the GPU as
+ * sliced-ELL sparse matrices; every Krylov iteration runs in kernels.
+ * Solves: ETH_TWO_STAGE (Sec. 3.1: stage I FGMRES on the reduced system with
+ * PCD, stage II FGMRES with M_1 of eq:nse-precon-ref) or ETH_FGMRES (M_1
+ * only).  The PCD matrix F_1 carries the inflow term -int (w.n) psi_j psi_i
+ * ds (without it F_1 annihilates constants while A_p does not, and stage I
+ * stalls); pcd_inflow_bc = 1 leaves it out.  Pressure mass solves: Chebyshev
+ * semi-iteration based on multicolour symmetric Gauss-Seidel (Sec. 2.3).
+ * One right-hand side per call. */
+typedef struct eth_step eth_step;
+
+typedef struct {
+  int32_t m;                 /* elements per unit length, h = 1/m                  */
+  int32_t length;            /* L: the channel ends at x = L (0: 5)                 */
+  int32_t channel;           /* 1: the strip [-1, L] x [0, 1] without the step      */
+  double nu;                 /* viscosity (the paper: 1/50)                        */
+  int32_t precision;         /* eth_precision of the preconditioner                 */
+  int32_t coarse_m;          /* multigrid levels m, m/2, ... while even and above
+                                coarse_m (0: 4); the last is solved densely        */
+  double gmg_omega;          /* damped-Jacobi weight of the F multigrid (0: 0.7)     */
+  double gmg_peclet_max;     /* >0: level viscosity max(nu, |w|_max h/(2 Pe_max))    */
+  int32_t pcd_q1_steps;      /* Chebyshev-Jacobi steps for Q_1^{-1} (0: 10)          */
+  int32_t pcd_inflow_bc;     /* 0: inflow term in F_1 (default); 1: none             */
+  int32_t mq_steps;          /* Chebyshev-SGS steps for M_Q (0: 20)                  */
+  double mq_cheb_lo;         /* lower end of the SGS interval (0: min(0.01,
+                                0.4 / (m (1 + L))))                                 */
+  int32_t gmres_restart;     /* FGMRES restart length, <= 63 (0: 50)                 */
+  void* stream;              /* hipStream_t for every call, or NULL (own stream)   */
+} eth_step_desc;
+
+/* Host-only inspection (no GPU needed): sizes[4] = {n_v, n_k, n_0, N}; the
+ * grid indices (I, J) of every Q2 node (half grid, x = -1 + I h/2), Q1 node
+ * and element (lower-left corner), and the Dirichlet flag of every Q2 node.
+ * Any output may be NULL. */
+int eth_step_host_layout(int32_t m, int32_t length, int32_t channel, int64_t* sizes, int32_t* q2_ij,
+                         int32_t* q1_ij, int32_t* el_ij, uint8_t* dirichlet);
+/* Host-only assembly of one matrix in CSR form (no GPU needed): call with
+ * ptr/col/val NULL for rows, cols, nnz, then again with arrays of rows+1,
+ * nnz, nnz entries.  wind: host, 2 n_v nodal values, or NULL.  which: */
+#define ETH_STEP_K    0   /* the saddle operator K (N x N; Dirichlet rows and columns empty) */
+#define ETH_STEP_MQ   1   /* pressure mass [Q_k R^T; R Q_0] (Sec. 2.3)                       */
+#define ETH_STEP_Q1   2   /* Q_1 (Sec. 3.1)                                                  */
+#define ETH_STEP_F1   3   /* F_1 with the inflow term (Sec. 3.1)                             */
+#define ETH_STEP_AP   4   /* A_p = B_1 diag(M_v)^{-1} B_1^T over the free velocity nodes     */
+#define ETH_STEP_P    5   /* Q2 prolongation from mesh m/2 (free rows and columns)           */
+#define ETH_STEP_PQ   6   /* Q1 prolongation from mesh m/2                                   */
+#define ETH_STEP_RHS  7   /* the lifted right-hand side (one column of N rows)              */
+int eth_step_host_matrix(int32_t m, int32_t length, int32_t channel, double nu, const double* wind,
+                         int32_t which, int64_t* rows, int64_t* cols, int64_t* nnz, int64_t* ptr,
+                         int32_t* col, double* val);
+
+/* Set up: host assembly, multigrid hierarchies, smoother bounds, coarse
+ * inverses and every workspace; the operator starts without a wind (Stokes). */
+int eth_step_setup(const eth_step_desc* desc, eth_step** out);
+int eth_step_destroy(eth_step* p);
+int eth_step_sizes(const eth_step* p, int64_t* nv, int64_t* nk, int64_t* n0, int64_t* N);
+/* levels of the hierarchies, m of each, and lambda_max(D^{-1} A_p) of every
+ * level but the coarsest (host arrays; any may be NULL) */
+int eth_step_levels(const eth_step* p, int32_t* levels, int32_t* m_per_level, double* ap_lambdas);
+/* wind: device, 2 n_v nodal values (the Picard iterate's velocity, Sec. 3.1
+ * text after eq:generic-conv-diff), or NULL for none; re-assembles F on every
+ * level, K and F_1 on the host */
+int eth_step_set_wind(eth_step* p, const double* wind);
+/* b (device, N): the lifted right-hand side with the inflow data, f = 0 */
+int eth_step_rhs(eth_step* p, double* b);
+/* y = K x (device, N) */
+int eth_step_apply(eth_step* p, const double* x, double* y);
+/* z = P^{-1} r (device, N): which 1 = M_1 (stage II), 2 = stage-I PCD
+ * (the p_0 part of z is zero) */
+int eth_step_apply_preconditioner(eth_step* p, int32_t which, const double* r, double* z);
+/* opts as for eth_solve (method ETH_TWO_STAGE or ETH_FGMRES); canonicalize
+ * shifts the pressure along k so that the element pressures have mean zero */
+int eth_step_solve(eth_step* p, const eth_solve_opts* opts, const double* b, double* x, eth_solve_info* info);
+/* The Stokes solution (FGMRES with M_1) followed by `steps` Picard steps, each
+ * an Oseen solve by opts->method whose wind is the velocity of the previous
+ * iterate, started from it.  x (device, N): the last iterate; info: host
+ * array of steps + 1 entries or NULL.  The problem keeps the last wind. */
+int eth_step_picard(eth_step* p, const eth_solve_opts* opts, int32_t steps, double* x, eth_solve_info* info);
+const char* eth_step_last_error(const eth_step* p);
+
 const char* eth_status_string(int status);
 /* message of the last failing call on this handle (or of the last failing
  * eth_setup when p is NULL); valid until the next call */

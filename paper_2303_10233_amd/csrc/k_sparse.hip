@@ -1,0 +1,228 @@
+// Sliced-ELL sparse kernels for the step domain: one thread per row, 64 rows
+// (one wavefront) per slice, the entries of a slice stored column-major so
+// that a wavefront reads 64 consecutive values and column indices per step.
+// Sums are formed in FP64 whatever the storage type of the matrix (V) and
+// of the vectors (T).
+#include "eth_step.h"
+
+namespace eth {
+
+namespace {
+constexpr int NT = 256;
+
+__device__ __forceinline__ bool gated(const int* gate) { return gate && *gate == 0; }
+
+template <typename T, typename V>
+__device__ __forceinline__ double row_dot(const SellView<V>& A, int row, const T* __restrict__ x) {
+  const int slice = row >> 6, lane = row & 63;
+  const int beg = A.ptr[slice];
+  const int width = (A.ptr[slice + 1] - beg) >> 6;
+  const int* c = A.col + beg + lane;
+  const V* v = A.val + beg + lane;
+  double s = 0.0;
+  for (int k = 0; k < width; ++k) s += (double)v[64 * k] * (double)x[c[64 * k]];
+  return s;
+}
+
+template <typename T, typename V, int MODE>
+__global__ __launch_bounds__(NT) void k_sell(SellView<V> A, const T* __restrict__ x, long long sx,
+                                              const T* __restrict__ b, long long sb, T* __restrict__ y,
+                                              long long sy, double w, double alpha, int has_prev,
+                                              const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= A.rows) return;
+  const int vec = blockIdx.y;
+  const T* xv = x ? x + vec * sx : nullptr;
+  T* yv = y + vec * sy;
+  if constexpr (MODE == 0 || MODE == 1) {
+    const double s = row_dot(A, row, xv);
+    if constexpr (MODE == 0) yv[row] = (T)s;
+    else yv[row] = (T)((double)yv[row] + s);
+  } else {
+    const T* bv = b + vec * sb;
+    const double s = xv ? row_dot(A, row, xv) : 0.0;
+    const double res = (double)bv[row] - s;
+    if constexpr (MODE == 2) {
+      yv[row] = (T)res;
+    } else {
+      const double xc = xv ? (double)xv[row] : 0.0;
+      double xn = xc + w * (double)A.dinv[row] * res;
+      if constexpr (MODE == 4) {
+        if (has_prev == 1) xn += alpha * (xc - (double)yv[row]);
+        else if (has_prev == 2) xn += alpha * xc;
+      }
+      yv[row] = (T)xn;
+    }
+  }
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(NT) void k_sell_colour(SellView<V> A, const int* __restrict__ rows, int count,
+                                                     const T* __restrict__ b, T* __restrict__ x,
+                                                     const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= count) return;
+  const int r = rows[i];
+  // rows of one colour do not couple, so every x read here except x[r]
+  // (read by this thread only) is final for the pass
+  const double s = row_dot(A, r, x);
+  x[r] = (T)((double)x[r] + ((double)b[r] - s) * (double)A.dinv[r]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dense_apply(const double* __restrict__ Ainv, int n,
+                                                     const T* __restrict__ b, long long sb, T* __restrict__ x,
+                                                     long long sx, const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int vec = blockIdx.y;
+  if (row >= n) return;
+  const T* bv = b + vec * sb;
+  const double* a = Ainv + (size_t)row * n;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += a[j] * (double)bv[j];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) x[vec * sx + row] = (T)s;
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(NT) void k_vcombine(long long n, double a, const Ti* __restrict__ x, double c,
+                                                  const Ti* __restrict__ z, To* __restrict__ y,
+                                                  const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  double v = a * (double)x[i];
+  if (z) v += c * (double)z[i];
+  y[i] = (To)v;
+}
+
+// frame projection: partials of sum(p_1) - sum(p_0), then the shift
+constexpr int FP_PER = 4 * NT;
+template <typename T>
+__global__ __launch_bounds__(NT) void k_frame_partial(int nk, int np, const T* __restrict__ p,
+                                                       double* __restrict__ part, const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  __shared__ double red[NT / 64];
+  double s = 0.0;
+  const int base = blockIdx.x * FP_PER;
+  for (int k = threadIdx.x; k < FP_PER; k += NT) {
+    const int i = base + k;
+    if (i < np) s += (i < nk ? 1.0 : -1.0) * (double)p[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_frame_shift(int nk, int np, int nparts, const double* __restrict__ part,
+                                                     T* __restrict__ p, const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  __shared__ double tot;
+  if (threadIdx.x == 0) {   // every block sums the partials in the same order
+    double t = 0.0;
+    for (int k = 0; k < nparts; ++k) t += part[k];
+    tot = t / (double)np;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= np) return;
+  p[i] = (T)((double)p[i] - (i < nk ? tot : -tot));
+}
+
+unsigned nblk(long long n) { return (unsigned)((n + NT - 1) / NT); }
+}  // namespace
+
+template <typename T, typename V>
+void launch_sell(const Sell& A, int mode, const T* x, long long sx, const T* b, long long sb, T* y, long long sy,
+                 int nvec, double w, double alpha, int has_prev, const int* gate, hipStream_t st) {
+  const SellView<V> v = view<V>(A);
+  const dim3 grid(nblk(A.rows), nvec);
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL((k_sell<T, V, 0>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_sell<T, V, 1>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_sell<T, V, 2>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_sell<T, V, 3>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
+      break;
+    default:
+      hipLaunchKernelGGL((k_sell<T, V, 4>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
+      break;
+  }
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T, typename V>
+void launch_sell_colour(const Sell& A, const int* rows, int count, const T* b, T* x, const int* gate,
+                        hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL((k_sell_colour<T, V>), dim3(nblk(count)), dim3(NT), 0, st, view<V>(A), rows, count, b, x, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_dense_apply(const double* Ainv, int n, const T* b, long long sb, T* x, long long sx, int nvec,
+                        const int* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_apply<T>, dim3((n + NT / 64 - 1) / (NT / 64), nvec), dim3(NT), 0, st, Ainv, n, b, sb,
+                     x, sx, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename Ti, typename To>
+void launch_vcombine(long long n, double a, const Ti* x, double c, const Ti* z, To* y, const int* gate,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((k_vcombine<Ti, To>), dim3(nblk(n)), dim3(NT), 0, st, n, a, x, c, z, y, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+int frame_project_blocks(int np) { return (np + FP_PER - 1) / FP_PER; }
+
+void launch_frame_project(double* part, int nk, int n0, void* p, bool fp32, const int* gate, hipStream_t st) {
+  const int np = nk + n0, nb = frame_project_blocks(np);
+  if (fp32) {
+    hipLaunchKernelGGL(k_frame_partial<float>, dim3(nb), dim3(NT), 0, st, nk, np, (const float*)p, part, gate);
+    ETH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_frame_shift<float>, dim3(nblk(np)), dim3(NT), 0, st, nk, np, nb, part, (float*)p, gate);
+  } else {
+    hipLaunchKernelGGL(k_frame_partial<double>, dim3(nb), dim3(NT), 0, st, nk, np, (const double*)p, part, gate);
+    ETH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_frame_shift<double>, dim3(nblk(np)), dim3(NT), 0, st, nk, np, nb, part, (double*)p, gate);
+  }
+  ETH_LAUNCH_CHECK();
+}
+
+#define ETH_SELL_INST(T, V)                                                                                  \
+  template void launch_sell<T, V>(const Sell&, int, const T*, long long, const T*, long long, T*, long long, \
+                                  int, double, double, int, const int*, hipStream_t);                      \
+  template void launch_sell_colour<T, V>(const Sell&, const int*, int, const T*, T*, const int*, hipStream_t);
+ETH_SELL_INST(double, double)
+ETH_SELL_INST(float, float)
+template void launch_dense_apply<double>(const double*, int, const double*, long long, double*, long long, int,
+                                         const int*, hipStream_t);
+template void launch_dense_apply<float>(const double*, int, const float*, long long, float*, long long, int,
+                                        const int*, hipStream_t);
+template void launch_vcombine<double, double>(long long, double, const double*, double, const double*, double*,
+                                              const int*, hipStream_t);
+template void launch_vcombine<double, float>(long long, double, const double*, double, const double*, float*,
+                                             const int*, hipStream_t);
+template void launch_vcombine<float, double>(long long, double, const float*, double, const float*, double*,
+                                             const int*, hipStream_t);
+template void launch_vcombine<float, float>(long long, double, const float*, double, const float*, float*,
+                                            const int*, hipStream_t);
+
+}  // namespace eth

@@ -106,6 +106,20 @@ KERNEL_NAMES = {
 }
 
 
+class StepDesc(ctypes.Structure):
+    """eth_step_desc: flow over a step (see eth.h)."""
+    _fields_ = [
+        ("m", ctypes.c_int32), ("length", ctypes.c_int32), ("channel", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("precision", ctypes.c_int32), ("coarse_m", ctypes.c_int32),
+        ("gmg_omega", ctypes.c_double), ("gmg_peclet_max", ctypes.c_double),
+        ("pcd_q1_steps", ctypes.c_int32), ("pcd_inflow_bc", ctypes.c_int32), ("mq_steps", ctypes.c_int32),
+        ("mq_cheb_lo", ctypes.c_double), ("gmres_restart", ctypes.c_int32), ("stream", ctypes.c_void_p),
+    ]
+
+
+STEP_K, STEP_MQ, STEP_Q1, STEP_F1, STEP_AP, STEP_P, STEP_PQ, STEP_RHS = range(8)
+
+
 def load_library(path=LIB_PATH):
     """Load libeth.so and declare the C signatures.  Raises OSError when the
     library has not been built."""
@@ -176,6 +190,37 @@ def load_library(path=LIB_PATH):
     lib.eth_status_string.restype = ctypes.c_char_p
     lib.eth_last_error.argtypes = [P]
     lib.eth_last_error.restype = ctypes.c_char_p
+    SP = ctypes.POINTER
+    lib.eth_step_host_layout.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, SP(i64),
+                                         SP(ctypes.c_int32), SP(ctypes.c_int32), SP(ctypes.c_int32),
+                                         SP(ctypes.c_uint8)]
+    lib.eth_step_host_layout.restype = ctypes.c_int
+    lib.eth_step_host_matrix.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                         SP(ctypes.c_double), ctypes.c_int32, SP(i64), SP(i64), SP(i64),
+                                         SP(i64), SP(ctypes.c_int32), SP(ctypes.c_double)]
+    lib.eth_step_host_matrix.restype = ctypes.c_int
+    lib.eth_step_setup.argtypes = [SP(StepDesc), SP(P)]
+    lib.eth_step_setup.restype = ctypes.c_int
+    lib.eth_step_destroy.argtypes = [P]
+    lib.eth_step_destroy.restype = ctypes.c_int
+    lib.eth_step_sizes.argtypes = [P, SP(i64), SP(i64), SP(i64), SP(i64)]
+    lib.eth_step_sizes.restype = ctypes.c_int
+    lib.eth_step_levels.argtypes = [P, SP(ctypes.c_int32), SP(ctypes.c_int32), SP(ctypes.c_double)]
+    lib.eth_step_levels.restype = ctypes.c_int
+    lib.eth_step_set_wind.argtypes = [P, P]
+    lib.eth_step_set_wind.restype = ctypes.c_int
+    lib.eth_step_rhs.argtypes = [P, P]
+    lib.eth_step_rhs.restype = ctypes.c_int
+    lib.eth_step_apply.argtypes = [P, P, P]
+    lib.eth_step_apply.restype = ctypes.c_int
+    lib.eth_step_apply_preconditioner.argtypes = [P, ctypes.c_int32, P, P]
+    lib.eth_step_apply_preconditioner.restype = ctypes.c_int
+    lib.eth_step_solve.argtypes = [P, SP(SolveOpts), P, P, SP(SolveInfo)]
+    lib.eth_step_solve.restype = ctypes.c_int
+    lib.eth_step_picard.argtypes = [P, SP(SolveOpts), ctypes.c_int32, P, SP(SolveInfo)]
+    lib.eth_step_picard.restype = ctypes.c_int
+    lib.eth_step_last_error.argtypes = [P]
+    lib.eth_step_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -657,3 +702,154 @@ class RaggedBatch:
             self.close()
         except Exception:
             pass
+
+
+# -- flow over a step ----------------------------------------------------------
+
+def _step_check(status, handle=None):
+    if status < 0:
+        L = lib()
+        msg = L.eth_step_last_error(handle).decode() or L.eth_status_string(status).decode()
+        raise EthError(status, msg)
+    return status
+
+
+def step_host_layout(m, length=5, channel=False):
+    """Sizes (n_v, n_k, n_0, N) and the grid indices of the step numbering
+    (host only, no GPU): dict of numpy arrays q2_ij (n_v x 2), q1_ij, el_ij,
+    dirichlet (n_v,)."""
+    import numpy as np
+    L = lib()
+    sizes = (ctypes.c_int64 * 4)()
+    _step_check(L.eth_step_host_layout(m, length, int(channel), sizes, None, None, None, None))
+    nv, nk, n0, N = (int(v) for v in sizes)
+    q2 = np.zeros((nv, 2), np.int32)
+    q1 = np.zeros((nk, 2), np.int32)
+    el = np.zeros((n0, 2), np.int32)
+    dr = np.zeros(nv, np.uint8)
+    c32 = ctypes.POINTER(ctypes.c_int32)
+    _step_check(L.eth_step_host_layout(m, length, int(channel), sizes, q2.ctypes.data_as(c32),
+                                       q1.ctypes.data_as(c32), el.ctypes.data_as(c32),
+                                       dr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return dict(nv=nv, nk=nk, n0=n0, N=N, q2_ij=q2, q1_ij=q1, el_ij=el, dirichlet=dr.astype(bool))
+
+
+def step_host_matrix(m, which, length=5, channel=False, nu=1.0, wind=None):
+    """One assembled step matrix in CSR form (host only, no GPU): returns
+    (indptr, indices, data, (rows, cols)) as numpy arrays."""
+    import numpy as np
+    L = lib()
+    w = None
+    if wind is not None:
+        wind = np.ascontiguousarray(wind, dtype=np.float64)
+        w = wind.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rows, cols, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _step_check(L.eth_step_host_matrix(m, length, int(channel), nu, w, which, ctypes.byref(rows),
+                                       ctypes.byref(cols), ctypes.byref(nnz), None, None, None))
+    ptr = np.zeros(rows.value + 1, np.int64)
+    col = np.zeros(nnz.value, np.int32)
+    val = np.zeros(nnz.value, np.float64)
+    _step_check(L.eth_step_host_matrix(m, length, int(channel), nu, w, which, ctypes.byref(rows),
+                                       ctypes.byref(cols), ctypes.byref(nnz),
+                                       ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       val.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return ptr, col, val, (rows.value, cols.value)
+
+
+class StepProblem:
+    """Flow over a step on the GPU (see eth.h, "flow over a step")."""
+
+    def __init__(self, m, length=5, channel=False, nu=1.0 / 50, precision=FP64, coarse_m=0, gmg_omega=0.0,
+                 gmg_peclet_max=0.0, pcd_q1_steps=0, pcd_inflow_bc=0, mq_steps=0, mq_cheb_lo=0.0,
+                 gmres_restart=0, device=None):
+        self.device = torch.device("cuda" if device is None else device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        d = StepDesc(m=m, length=length, channel=int(channel), nu=nu, precision=precision, coarse_m=coarse_m,
+                     gmg_omega=gmg_omega, gmg_peclet_max=gmg_peclet_max, pcd_q1_steps=pcd_q1_steps,
+                     pcd_inflow_bc=pcd_inflow_bc, mq_steps=mq_steps, mq_cheb_lo=mq_cheb_lo,
+                     gmres_restart=gmres_restart, stream=ctypes.c_void_p(stream))
+        h = ctypes.c_void_p()
+        _step_check(lib().eth_step_setup(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.m, self.length, self.channel, self.nu = m, length, bool(channel), nu
+        sz = [ctypes.c_int64() for _ in range(4)]
+        _step_check(lib().eth_step_sizes(h, *[ctypes.byref(v) for v in sz]), h)
+        self.nv, self.nk, self.n0, self.N = (int(v.value) for v in sz)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().eth_step_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t):
+        if t.dtype != torch.float64 or not t.is_cuda or t.numel() != self.N or not t.is_contiguous():
+            raise ValueError("vectors must be contiguous float64 CUDA tensors of length N")
+        return _ptr(t)
+
+    def empty(self):
+        return torch.empty(self.N, dtype=torch.float64, device=self.device)
+
+    def levels(self):
+        L = lib()
+        lv = ctypes.c_int32()
+        _step_check(L.eth_step_levels(self._h, ctypes.byref(lv), None, None), self._h)
+        ms = (ctypes.c_int32 * lv.value)()
+        lam = (ctypes.c_double * max(lv.value, 1))()
+        _step_check(L.eth_step_levels(self._h, None, ms, lam), self._h)
+        return [ms[i] for i in range(lv.value)], [lam[i] for i in range(lv.value - 1)]
+
+    def set_wind(self, wind):
+        """wind: 2 n_v nodal values on the device, or None for none."""
+        if wind is not None and (wind.dtype != torch.float64 or wind.numel() < 2 * self.nv
+                                 or not wind.is_contiguous()):
+            raise ValueError("wind must be a contiguous float64 tensor of 2 n_v values")
+        _step_check(lib().eth_step_set_wind(self._h, None if wind is None else _ptr(wind)), self._h)
+
+    def rhs(self, out=None):
+        b = out if out is not None else self.empty()
+        _step_check(lib().eth_step_rhs(self._h, self._vec(b)), self._h)
+        return b
+
+    def apply(self, x, out=None):
+        y = out if out is not None else self.empty()
+        _step_check(lib().eth_step_apply(self._h, self._vec(x), self._vec(y)), self._h)
+        return y
+
+    def apply_preconditioner(self, r, which=1, out=None):
+        """which 1: M_1, 2: the stage-I PCD preconditioner."""
+        z = out if out is not None else self.empty()
+        _step_check(lib().eth_step_apply_preconditioner(self._h, which, self._vec(r), self._vec(z)), self._h)
+        return z
+
+    def solve(self, b, rtol=1e-6, maxit=1000, x0=None, method=TWO_STAGE, restart=0, c_factor=10.0,
+              canonicalize=True, use_graph=False, out=None, history_len=0, raise_on_error=True):
+        x = out if out is not None else self.empty()
+        if x0 is not None:
+            x.copy_(x0)
+        buf, hp = _history(1, history_len)
+        o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=c_factor,
+                      canonicalize=int(canonicalize), use_x0=int(x0 is not None), use_graph=int(use_graph),
+                      true_residual=0, residual_history=hp, history_len=history_len)
+        info = (SolveInfo * 1)()
+        st = lib().eth_step_solve(self._h, ctypes.byref(o), self._vec(b), self._vec(x), info)
+        if raise_on_error:
+            _step_check(st, self._h)
+        return x, _with_history(info, 1, buf, history_len)[0]
+
+    def picard(self, steps, rtol=1e-6, maxit=1000, method=TWO_STAGE, restart=0, c_factor=10.0,
+               canonicalize=True, use_graph=False, out=None):
+        """The Stokes solution and `steps` Picard steps; returns the last
+        iterate and one info dict per solve (steps + 1)."""
+        x = out if out is not None else self.empty()
+        o = SolveOpts(method=method, rtol=rtol, maxit=maxit, restart=restart, c_factor=c_factor,
+                      canonicalize=int(canonicalize), use_x0=0, use_graph=int(use_graph), true_residual=0)
+        infos = (SolveInfo * (steps + 1))()
+        _step_check(lib().eth_step_picard(self._h, ctypes.byref(o), steps, self._vec(x), infos), self._h)
+        return x, [infos[i].as_dict() for i in range(steps + 1)]

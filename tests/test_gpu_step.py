@@ -1,0 +1,182 @@
+"""Flow over a step on the GPU (Sec. 3, the inflow-outflow example) against
+the oracle: the sparse saddle apply, both preconditioners (M_1 and the
+stage-I PCD, with the GPU's smoother bounds handed to the oracle), the
+two-stage and M_1 solves against the direct solution, Picard steps, the
+exact Poiseuille flow of the channel, and mass conservation (a property at
+any size) at the benchmark's mesh.
+
+Winds come from the oracle (its Stokes solution or Picard iterates), never
+from the GPU path."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.assemble import System  # noqa: E402
+from oracle.precond import OseenM1  # noqa: E402
+from oracle.step import (StepMesh, inflow_dirichlet, poiseuille, direct_solve, stokes_start, picard,  # noqa: E402
+                         line_fluxes, velocity_gmg, PCDStage1, MQChebSGS, two_stage, ap_gmg,
+                         lambda_max_dinv, pressure_laplacian)
+from oracle.direct import rel_err  # noqa: E402
+from paper_2303_10233_amd import eth  # noqa: E402
+from paper_2303_10233_amd.workloads import uniform_vector  # noqa: E402
+
+DEV = "cuda:0"
+NU = 1.0 / 50
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eth.load_library()
+
+
+def _interior(S, x):
+    return S.to_interior(x)
+
+
+def _problem(m, wind, prec=eth.FP64, channel=False):
+    P = eth.StepProblem(m, channel=channel, nu=NU, precision=prec)
+    if wind is not None:
+        P.set_wind(_t(wind))
+    return P
+
+
+@pytest.mark.parametrize("m,channel", [(2, False), (4, False), (6, True), (8, False)])
+def test_apply_matches_oracle(m, channel):
+    print(f"[step apply] m={m} channel={channel}", flush=True)
+    M = StepMesh(m, channel=channel)
+    w = uniform_vector(2 * M.nv, 40 + m)
+    S = System(M, nu=NU, wind=w)
+    P = _problem(m, w, channel=channel)
+    x = uniform_vector(M.N, 7 + m)
+    y = _np(P.apply(_t(x)))
+    ref = S.apply_full(x)
+    assert np.abs(y - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("m,prec,tol", [(8, eth.FP64, 1e-11), (16, eth.FP64, 1e-11), (16, eth.MIXED, 5e-5)])
+def test_preconditioners_match_oracle(m, prec, tol):
+    print(f"[step precond] m={m} prec={prec}", flush=True)
+    M = StepMesh(m)
+    x0 = stokes_start(M, NU)
+    w = x0[: 2 * M.nv]
+    S = System(M, nu=NU, wind=w)
+    P = _problem(m, w, prec)
+    ms, lam = P.levels()
+    assert ms[0] == m and ms[-1] <= 4
+    # the GPU's Lanczos bounds are close to the exact ones
+    exact = [lambda_max_dinv(pressure_laplacian(StepMesh(k))) for k in ms[:-1]]
+    assert np.allclose(lam, exact, rtol=2e-3)
+    r = uniform_vector(M.N, 300 + m)
+    r[: 2 * M.nv][S.vel_bnd] = 0.0
+    vel, _ = velocity_gmg(S)
+    # M_1 (stage II)
+    z = _np(P.apply_preconditioner(_t(r), which=1))
+    ref = S.to_full(OseenM1(S, velocity_solve=vel, mq=MQChebSGS(S))(S.to_interior(r)))
+    assert rel_err(z, ref) < tol
+    # stage-I PCD on the reduced system (zero p_0 part)
+    rr = r.copy()
+    rr[2 * M.nv + M.nk:] = 0.0
+    z = _np(P.apply_preconditioner(_t(rr), which=2))
+    pcd = PCDStage1(S, velocity_solve=vel, inexact=True, ap_kw=dict(lambdas=lam))
+    zi = pcd(S.to_interior(rr)[: S.nI + M.nk])
+    ref = S.to_full(np.concatenate([zi, np.zeros(M.n0)]))
+    assert np.abs(z[2 * M.nv + M.nk:]).max() == 0.0
+    assert rel_err(z, ref) < tol
+
+
+@pytest.mark.parametrize("m,prec,rtol,bar", [(8, eth.FP64, 1e-10, 1e-8), (16, eth.FP64, 1e-10, 1e-8),
+                                             (16, eth.MIXED, 1e-8, 1e-6)])
+def test_two_stage_solve_matches_direct(m, prec, rtol, bar):
+    print(f"[step solve] m={m} prec={prec}", flush=True)
+    M = StepMesh(m)
+    x0 = stokes_start(M, NU)
+    w = x0[: 2 * M.nv]
+    S = System(M, nu=NU, wind=w)
+    b = S.rhs(None, inflow_dirichlet(M))
+    xd = direct_solve(S, b)
+    P = _problem(m, w, prec)
+    bg = P.rhs()
+    assert np.abs(_np(bg) - b).max() < 1e-13
+    x, info = P.solve(bg, rtol=rtol, maxit=2000, history_len=2000)
+    assert info["status"] == eth.OK, info
+    assert 0 < info["stage1_iterations"] < 80
+    xh = _np(x)
+    assert rel_err(xh, xd) < bar
+    assert np.abs(line_fluxes(M, xh) - 2.0 / 3.0).max() < 10 * bar
+    # iteration counts follow the oracle's two-stage run with the same pieces (FP64)
+    if prec == eth.FP64 and m == 8:
+        vel, _ = velocity_gmg(S)
+        _, lam = P.levels()
+        P1 = PCDStage1(S, velocity_solve=vel, inexact=True, ap_kw=dict(lambdas=lam))
+        P2 = OseenM1(S, velocity_solve=vel, mq=MQChebSGS(S))
+        _, oinfo = two_stage(S, b, eta=rtol, stage1_prec=P1, stage2_prec=P2, maxit=2000)
+        assert abs(info["stage1_iterations"] - oinfo["stage1"]["iterations"]) <= 2
+        assert abs(info["iterations"] - oinfo["iterations"]) <= 4
+
+
+def test_m1_solve_and_stokes_operator():
+    M = StepMesh(8)
+    S = System(M, nu=NU)
+    b = S.rhs(None, inflow_dirichlet(M))
+    xd = direct_solve(S, b)
+    P = _problem(8, None)
+    x, info = P.solve(_t(b), rtol=1e-10, maxit=3000, method=eth.FGMRES)
+    assert info["status"] == eth.OK
+    assert rel_err(_np(x), xd) < 1e-8
+    with pytest.raises(eth.EthError):     # the PCD needs a wind
+        P.solve(_t(b), method=eth.TWO_STAGE)
+
+
+def test_channel_is_poiseuille_on_the_gpu():
+    M = StepMesh(8, channel=True)
+    ex = poiseuille(M, NU)
+    P = _problem(8, ex[: 2 * M.nv], channel=True)
+    x, info = P.solve(P.rhs(), rtol=1e-12, maxit=2000)
+    assert info["status"] == eth.OK
+    assert np.abs(_np(x) - ex).max() < 1e-9
+
+
+def test_picard_matches_oracle():
+    M = StepMesh(4)
+    ref = picard(M, NU, 5)[-1]
+    P = _problem(4, None)
+    x, infos = P.picard(5, rtol=1e-11, maxit=2000)
+    assert len(infos) == 6 and all(i["status"] == eth.OK for i in infos)
+    assert rel_err(_np(x), ref) < 1e-8
+
+
+@pytest.mark.parametrize("prec", [eth.MIXED, eth.FP64])
+def test_benchmark_mesh_conserves_mass(prec):
+    """m = 64 (the bench mesh): five Picard steps, then the two-stage solve
+    of the last Oseen system; properties that hold at any size (every
+    vertical line carries the inflow flux, the true residual)."""
+    print(f"[step m=64] prec={prec}", flush=True)
+    M = StepMesh(64)
+    P = _problem(64, None, prec)
+    x, infos = P.picard(5, rtol=1e-8, maxit=2000)
+    assert all(i["status"] == eth.OK for i in infos), infos
+    b = P.rhs()
+    y, info = P.solve(b, rtol=1e-8, x0=None, maxit=2000)
+    assert info["status"] == eth.OK
+    yh = _np(y)
+    assert np.abs(line_fluxes(M, yh) - 2.0 / 3.0).max() < 1e-6
+    dirichlet = np.concatenate([M.boundary_q2()] * 2)
+    r = _np(b) - _np(P.apply(y))
+    r[: 2 * M.nv][dirichlet] = 0.0
+    bb = _np(b)
+    bb[: 2 * M.nv][dirichlet] = 0.0
+    assert np.linalg.norm(r) <= 2e-8 * np.linalg.norm(bb)
