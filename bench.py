@@ -219,6 +219,31 @@ def cpu_other(gpu):
                              "sample": (f"{sample} two-stage FGMRES iterations of the oracle ({dt:.1f} s), "
                                         f"scaled by the GPU iteration count {its}"),
                              "seconds_per_iteration": round(dt / sample, 4)}
+    # flow over a step, m = 32 (the paper's intermediate grid, 11264 squares):
+    # a bounded sample of the oracle's two-stage FGMRES with the GPU's inexact
+    # pieces; the wind is the channel profile (1 - y^2)/2 (the oracle's direct
+    # Stokes solve at this size takes about 100 s, and the cost of an
+    # iteration does not depend on the wind)
+    from oracle import step as ostep
+    sm = 32
+    M = ostep.StepMesh(sm)
+    X, Y = M.q2_coords()
+    wind = np.concatenate([0.5 * (1.0 - Y ** 2), np.zeros(M.nv)])
+    s = System(M, nu=0.02, wind=wind)
+    b = s.rhs(None, ostep.inflow_dirichlet(M))
+    vel, _ = ostep.velocity_gmg(s)
+    P1 = ostep.PCDStage1(s, velocity_solve=vel, inexact=True)
+    P2 = opc.OseenM1(s, velocity_solve=vel, mq=ostep.MQChebSGS(s))
+    sample = 40
+    t0 = time.perf_counter()
+    ostep.two_stage(s, b, eta=1e-30, maxit=sample // 2, stage1_prec=P1, stage2_prec=P2)
+    dt = time.perf_counter() - t0
+    its = gpu.get("step32_iterations") or 150
+    out["step32_nu50"] = {"cores": 1, "solves_per_s": round(1.0 / (dt / sample * its), 5),
+                          "sample": (f"{sample} two-stage FGMRES iterations of the oracle at m = {sm} "
+                                     f"({dt:.1f} s, channel-profile wind), scaled by the GPU iteration "
+                                     f"count {its}"),
+                          "seconds_per_iteration": round(dt / sample, 4)}
     return out
 
 
@@ -281,6 +306,48 @@ def bench_picard(n, nu, prec, steps, rtol, picard_steps=5, maxit=1000):
                 stage1_iterations=i["stage1_iterations"], rel_residual=i["rel_residual_true"],
                 status=i["status"], picard_seconds=round(t_picard, 4),
                 picard_iterations=[p["iterations"] for p in pinfo])
+
+
+def bench_step(m, prec, steps, rtol, picard_steps=5, maxit=2000):
+    """Flow over a step (Sec. 3, the inflow-outflow example, nu = 1/50): the
+    Stokes solution and `picard_steps` Picard steps on the GPU, then the
+    Oseen system they produce solved from zero `steps` times by the
+    two-stage PCD method; the volume flux through every vertical grid line
+    of the solution against the inflow flux 2/3 (mass conservation)."""
+    import numpy as np
+    import torch
+    from paper_2303_10233_amd import eth
+    t0 = time.perf_counter()
+    P = eth.StepProblem(m, nu=1.0 / 50, precision=prec)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, pinfo = P.picard(picard_steps, rtol=rtol, maxit=maxit)
+    torch.cuda.synchronize()
+    t_picard = time.perf_counter() - t0
+    b = P.rhs()
+    y, info = P.solve(b, rtol=rtol, maxit=maxit, raise_on_error=False)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        y, info = P.solve(b, rtol=rtol, maxit=maxit, out=y, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    lay = eth.step_host_layout(m)
+    yh = y.cpu().numpy()
+    # flux through the vertical element lines by Simpson's rule on every edge
+    nqx, nqy = 2 * 6 * m + 1, 4 * m + 1
+    ux = np.zeros((nqy, nqx))
+    ux[lay["q2_ij"][:, 1], lay["q2_ij"][:, 0]] = yh[: lay["nv"]]
+    h = 1.0 / m
+    fl = h / 6.0 * (ux[0:-1:2, 0::2] + 4.0 * ux[1::2, 0::2] + ux[2::2, 0::2]).sum(axis=0)
+    P.close()
+    return dict(m=m, nu=0.02, unknowns=lay["N"], elements=lay["n0"], solves_per_s=round(1.0 / dt, 4),
+                ms_per_solve=round(1e3 * dt, 3), iterations=info["iterations"],
+                stage1_iterations=info["stage1_iterations"], rel_residual=info["rel_residual_true"],
+                status=info["status"], setup_s=round(setup, 3), picard_seconds=round(t_picard, 3),
+                picard_iterations=[p["iterations"] for p in pinfo],
+                max_flux_error=float(np.abs(fl - 2.0 / 3.0).max()))
 
 
 def bench_batch(n, nrhs, prec, steps, rtol):
@@ -642,6 +709,15 @@ def main():
                 log(f"cavity Re=200 n={on} {name}: {r['solves_per_s']} solves/s, {r['iterations']} its "
                     f"({r['stage1_iterations']} stage I); 5 Picard steps {r['picard_seconds']} s "
                     f"{r['picard_iterations']}")
+        extra["step"] = []
+        for sm in (32, 64, 128):
+            for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+                r = bench_step(sm, prec, args.extra_steps, args.rtol)
+                r["precision"] = name
+                extra["step"].append(r)
+                log(f"step m={sm} {name}: {r['solves_per_s']} solves/s, {r['iterations']} its "
+                    f"({r['stage1_iterations']} stage I), flux error {r['max_flux_error']:.1e}, "
+                    f"Picard {r['picard_seconds']} s {r['picard_iterations']}")
         extra["stokes_schur_mq"] = {}
         for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
             Ps = eth.Problem(n, precision=prec, velocity=eth.VEL_GMG, mq=eth.MQ_SCHUR_GMG)
@@ -704,6 +780,7 @@ def main():
         if extra:
             g["batch64_iterations"] = extra["batch64"]["mixed"]["iterations_max"]
             g["oseen128_iterations"] = extra["oseen"][0]["iterations"]
+            g["step32_iterations"] = extra["step"][0]["iterations"]
         cpu_more = cpu_other(g)
         log(f"oracle, other configurations: {json.dumps(cpu_more)}")
 

@@ -115,6 +115,7 @@ struct StepProblem {
   std::vector<double> q1a, q1b, mqa, mqb;
   double mq_theta = 1.0;
   std::array<int*, 5> mq_rows{};
+  unsigned char* mq_colour = nullptr;   // colour of every pressure row
   std::array<int, 5> mq_count{};
   int* dir_idx = nullptr;
   int ndir = 0;
@@ -347,6 +348,11 @@ void StepProblem::setup(const eth_step_desc& desc) {
     std::array<std::vector<int>, 5> rows;
     for (int k = 0; k < g.nk; ++k) rows[(g.q1_I[k] & 1) + 2 * (g.q1_J[k] & 1)].push_back(k);
     for (int e = 0; e < g.n0; ++e) rows[4].push_back(g.nk + e);
+    std::vector<unsigned char> col((size_t)g.nk + g.n0);
+    for (int c = 0; c < 5; ++c)
+      for (int r : rows[c]) col[r] = (unsigned char)c;
+    mq_colour = alloc<unsigned char>(col.size());
+    ETH_HIP(hipMemcpy(mq_colour, col.data(), col.size(), hipMemcpyHostToDevice));
     for (int c = 0; c < 5; ++c) {
       mq_count[c] = (int)rows[c].size();
       mq_rows[c] = alloc<int>(rows[c].size());
@@ -554,21 +560,15 @@ void StepProblem::mq_solve(const int* gate) {
   T* s = static_cast<T*>(msg);
   T* res = static_cast<T*>(mres);
   launch_frame_project(fpart, nk_, n0_, r, mixed, gate, st);
-  static const int order[9] = {0, 1, 2, 3, 4, 3, 2, 1, 0};
-  auto sgs = [&](const T* b) {
-    launch_vcombine<T, T>(np, 0.0, b, 0.0, nullptr, s, gate, st);
-    for (int c : order) launch_sell_colour<T, T>(MQ, mq_rows[c], mq_count[c], b, s, gate, st);
-  };
-  // x_1 = d_0 = SGS(r) / theta;  x_{k+1} = x_k + d_k,  d_k = alpha_k d_{k-1} + beta_k SGS(r - M x_k)
-  sgs(r);
-  launch_vcombine<T, T>(np, mqb[0], s, 0.0, nullptr, dd, gate, st);
-  launch_vcombine<T, T>(np, 1.0, dd, 0.0, nullptr, x, gate, st);
-  for (int k = 1; k < d.mq_steps; ++k) {
-    launch_sell<T, T>(MQ, 2, x, 0, r, 0, res, 0, 1, 0.0, 0.0, 0, gate, st);
-    sgs(res);
-    launch_vcombine<T, T>(np, mqa[k], dd, mqb[k], s, dd, gate, st);
-    launch_vcombine<T, T>(np, 1.0, x, 1.0, dd, x, gate, st);
+  // x_1 = d_0 = SGS(r) / theta;  x_{k+1} = x_k + d_k,  d_k = alpha_k d_{k-1} + beta_k SGS(r - M x_k);
+  // the sweep from zero visits the colours 0, 1, 2, 3, 4, 3, 2, 1, 0
+  static const int inner[7] = {1, 2, 3, 4, 3, 2, 1};
+  for (int k = 0; k < d.mq_steps; ++k) {
+    launch_sgs_enter<T, T>(MQ, mq_colour, k == 0 ? nullptr : x, r, res, s, gate, st);
+    for (int c : inner) launch_sell_colour<T, T>(MQ, mq_rows[c], mq_count[c], res, s, gate, st);
+    launch_sgs_leave<T, T>(MQ, mq_colour, res, s, dd, x, mqa[k], mqb[k], k == 0 ? 1 : 0, gate, st);
   }
+  (void)np;
   launch_frame_project(fpart, nk_, n0_, x, mixed, gate, st);
 }
 

@@ -12,6 +12,9 @@ constexpr int NT = 256;
 
 __device__ __forceinline__ bool gated(const int* gate) { return gate && *gate == 0; }
 
+// four entries per round: the column indices and values of a round are
+// loaded together, then the four vector entries they address, so a thread
+// has several independent loads in flight instead of one dependent chain
 template <typename T, typename V>
 __device__ __forceinline__ double row_dot(const SellView<V>& A, int row, const T* __restrict__ x) {
   const int slice = row >> 6, lane = row & 63;
@@ -20,7 +23,18 @@ __device__ __forceinline__ double row_dot(const SellView<V>& A, int row, const T
   const int* c = A.col + beg + lane;
   const V* v = A.val + beg + lane;
   double s = 0.0;
-  for (int k = 0; k < width; ++k) s += (double)v[64 * k] * (double)x[c[64 * k]];
+  int k = 0;
+  for (; k + 4 <= width; k += 4) {
+    const int c0 = c[64 * k], c1 = c[64 * (k + 1)], c2 = c[64 * (k + 2)], c3 = c[64 * (k + 3)];
+    const double v0 = (double)v[64 * k], v1 = (double)v[64 * (k + 1)], v2 = (double)v[64 * (k + 2)],
+                 v3 = (double)v[64 * (k + 3)];
+    const double x0 = (double)x[c0], x1 = (double)x[c1], x2 = (double)x[c2], x3 = (double)x[c3];
+    s += v0 * x0;
+    s += v1 * x1;
+    s += v2 * x2;
+    s += v3 * x3;
+  }
+  for (; k < width; ++k) s += (double)v[64 * k] * (double)x[c[64 * k]];
   return s;
 }
 
@@ -69,6 +83,42 @@ __global__ __launch_bounds__(NT) void k_sell_colour(SellView<V> A, const int* __
   // (read by this thread only) is final for the pass
   const double s = row_dot(A, r, x);
   x[r] = (T)((double)x[r] + ((double)b[r] - s) * (double)A.dinv[r]);
+}
+
+// First kernel of a Chebyshev-SGS step on M_Q: res = r - M x (x == null:
+// res = r) over all rows, and the first colour pass of a symmetric sweep
+// from zero, s = D^{-1} res on colour 0 and s = 0 elsewhere.
+template <typename T, typename V>
+__global__ __launch_bounds__(NT) void k_sgs_enter(SellView<V> A, const unsigned char* __restrict__ colour,
+                                                   const T* __restrict__ x, const T* __restrict__ r,
+                                                   T* __restrict__ res, T* __restrict__ s,
+                                                   const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= A.rows) return;
+  const double q = (double)r[row] - (x ? row_dot(A, row, x) : 0.0);
+  res[row] = (T)q;
+  s[row] = colour[row] == 0 ? (T)(q * (double)A.dinv[row]) : T(0);
+}
+
+// Last kernel of the step: the closing colour-0 pass of the sweep, then the
+// Chebyshev update d = alpha d + beta s, x = x + d (x_zero: x = d).
+template <typename T, typename V>
+__global__ __launch_bounds__(NT) void k_sgs_leave(SellView<V> A, const unsigned char* __restrict__ colour,
+                                                   const T* __restrict__ res, T* __restrict__ s,
+                                                   T* __restrict__ d, T* __restrict__ x, double alpha,
+                                                   double beta, int x_zero, const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= A.rows) return;
+  double sv = (double)s[row];
+  if (colour[row] == 0) {
+    // the neighbours read here are of other colours: final for this pass
+    sv = (double)(T)(sv + ((double)res[row] - row_dot(A, row, s)) * (double)A.dinv[row]);
+  }
+  const double dn = (double)(T)(alpha * (double)d[row] + beta * sv);
+  d[row] = (T)dn;
+  x[row] = x_zero ? (T)dn : (T)((double)x[row] + dn);
 }
 
 template <typename T>
@@ -175,6 +225,22 @@ void launch_sell_colour(const Sell& A, const int* rows, int count, const T* b, T
   ETH_LAUNCH_CHECK();
 }
 
+template <typename T, typename V>
+void launch_sgs_enter(const Sell& A, const unsigned char* colour, const T* x, const T* r, T* res, T* s,
+                      const int* gate, hipStream_t st) {
+  hipLaunchKernelGGL((k_sgs_enter<T, V>), dim3(nblk(A.rows)), dim3(NT), 0, st, view<V>(A), colour, x, r, res, s,
+                     gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T, typename V>
+void launch_sgs_leave(const Sell& A, const unsigned char* colour, const T* res, T* s, T* d, T* x, double alpha,
+                      double beta, int x_zero, const int* gate, hipStream_t st) {
+  hipLaunchKernelGGL((k_sgs_leave<T, V>), dim3(nblk(A.rows)), dim3(NT), 0, st, view<V>(A), colour, res, s, d, x,
+                     alpha, beta, x_zero, gate);
+  ETH_LAUNCH_CHECK();
+}
+
 template <typename T>
 void launch_dense_apply(const double* Ainv, int n, const T* b, long long sb, T* x, long long sx, int nvec,
                         const int* gate, hipStream_t st) {
@@ -209,7 +275,11 @@ void launch_frame_project(double* part, int nk, int n0, void* p, bool fp32, cons
 #define ETH_SELL_INST(T, V)                                                                                  \
   template void launch_sell<T, V>(const Sell&, int, const T*, long long, const T*, long long, T*, long long, \
                                   int, double, double, int, const int*, hipStream_t);                      \
-  template void launch_sell_colour<T, V>(const Sell&, const int*, int, const T*, T*, const int*, hipStream_t);
+  template void launch_sell_colour<T, V>(const Sell&, const int*, int, const T*, T*, const int*, hipStream_t); \
+  template void launch_sgs_enter<T, V>(const Sell&, const unsigned char*, const T*, const T*, T*, T*, const int*, \
+                                       hipStream_t);                                                       \
+  template void launch_sgs_leave<T, V>(const Sell&, const unsigned char*, const T*, T*, T*, T*, double, double, \
+                                       int, const int*, hipStream_t);
 ETH_SELL_INST(double, double)
 ETH_SELL_INST(float, float)
 template void launch_dense_apply<double>(const double*, int, const double*, long long, double*, long long, int,
