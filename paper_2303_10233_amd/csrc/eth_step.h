@@ -140,11 +140,17 @@ void launch_sell_colour(const Sell& A, const int* rows, int count, const T* b, T
                         hipStream_t st);
 // a Chebyshev step on M_Q based on multicolour SGS, in three parts:
 // enter: res = r - M x (x null: r), s = D^{-1} res on colour 0, 0 elsewhere;
-// the colour passes 1, 2, 3, 4, 3, 2, 1 (launch_sell_colour with b = res);
+// the colour passes 1, 2, 3, 4, 3, 2, 1 (launch_sell_colour with b = res,
+// or launch_sgs_middle for 3, 4, 3);
 // leave: the closing colour-0 pass, d = alpha d + beta s, x = x + d (x_zero: d)
 template <typename T, typename V>
 void launch_sgs_enter(const Sell& A, const unsigned char* colour, const T* x, const T* r, T* res, T* s,
                       const int* gate, hipStream_t st);
+// the colour-3 forward pass, the element (colour-4) pass and the colour-3
+// backward pass in one launch over the colour-3 rows (rows >= nk: elements)
+template <typename T, typename V>
+void launch_sgs_middle(const Sell& A, const int* rows, int count, int nk, const T* b, T* x, const int* gate,
+                       hipStream_t st);
 template <typename T, typename V>
 void launch_sgs_leave(const Sell& A, const unsigned char* colour, const T* res, T* s, T* d, T* x, double alpha,
                       double beta, int x_zero, const int* gate, hipStream_t st);

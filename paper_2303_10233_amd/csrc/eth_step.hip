@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -140,12 +141,15 @@ struct StepProblem {
   std::map<std::array<int, 4>, hipGraphExec_t> graphs;
 
   ~StepProblem();
+  bool nan_fill = false;   // ETH_DEBUG_NAN_FILL=1: workspaces start as NaN
+  bool sgs_split = false;  // ETH_DEBUG_UNFUSED_MQ=1: colours 3, 4, 3 as three launches
   template <typename X>
   X* alloc(size_t n) {
     void* p = nullptr;
     if (n == 0) n = 1;
     if (hipMalloc(&p, n * sizeof(X)) != hipSuccess) throw std::bad_alloc();
     owned.push_back(p);
+    if (nan_fill) ETH_HIP(hipMemset(p, 0xff, n * sizeof(X)));   // all-ones bytes: a NaN in FP32 and FP64
     return static_cast<X*>(p);
   }
   void* allocT(size_t n) { return mixed ? (void*)alloc<float>(n) : (void*)alloc<double>(n); }
@@ -266,6 +270,8 @@ void StepProblem::upload(Sell& s, const Csr& A, bool f32, bool dinv) {
 void StepProblem::setup(const eth_step_desc& desc) {
   Range range("eth_step_setup");
   d = desc;
+  if (const char* e = std::getenv("ETH_DEBUG_NAN_FILL")) nan_fill = (e[0] == '1');
+  if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) sgs_split = (e[0] == '1');
   if (d.m < 1) throw std::invalid_argument("m must be >= 1");
   if (d.length == 0) d.length = 5;
   if (d.length < 1) throw std::invalid_argument("length must be >= 1");
@@ -562,10 +568,19 @@ void StepProblem::mq_solve(const int* gate) {
   launch_frame_project(fpart, nk_, n0_, r, mixed, gate, st);
   // x_1 = d_0 = SGS(r) / theta;  x_{k+1} = x_k + d_k,  d_k = alpha_k d_{k-1} + beta_k SGS(r - M x_k);
   // the sweep from zero visits the colours 0, 1, 2, 3, 4, 3, 2, 1, 0
-  static const int inner[7] = {1, 2, 3, 4, 3, 2, 1};
   for (int k = 0; k < d.mq_steps; ++k) {
     launch_sgs_enter<T, T>(MQ, mq_colour, k == 0 ? nullptr : x, r, res, s, gate, st);
-    for (int c : inner) launch_sell_colour<T, T>(MQ, mq_rows[c], mq_count[c], res, s, gate, st);
+    launch_sell_colour<T, T>(MQ, mq_rows[1], mq_count[1], res, s, gate, st);
+    launch_sell_colour<T, T>(MQ, mq_rows[2], mq_count[2], res, s, gate, st);
+    if (sgs_split) {
+      launch_sell_colour<T, T>(MQ, mq_rows[3], mq_count[3], res, s, gate, st);
+      launch_sell_colour<T, T>(MQ, mq_rows[4], mq_count[4], res, s, gate, st);
+      launch_sell_colour<T, T>(MQ, mq_rows[3], mq_count[3], res, s, gate, st);
+    } else {
+      launch_sgs_middle<T, T>(MQ, mq_rows[3], mq_count[3], nk_, res, s, gate, st);
+    }
+    launch_sell_colour<T, T>(MQ, mq_rows[2], mq_count[2], res, s, gate, st);
+    launch_sell_colour<T, T>(MQ, mq_rows[1], mq_count[1], res, s, gate, st);
     launch_sgs_leave<T, T>(MQ, mq_colour, res, s, dd, x, mqa[k], mqb[k], k == 0 ? 1 : 0, gate, st);
   }
   (void)np;

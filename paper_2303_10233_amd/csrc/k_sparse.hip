@@ -15,6 +15,8 @@ __device__ __forceinline__ bool gated(const int* gate) { return gate && *gate ==
 // four entries per round: the column indices and values of a round are
 // loaded together, then the four vector entries they address, so a thread
 // has several independent loads in flight instead of one dependent chain
+// (eight per round with predicated tails measured slower: 142 -> 201 ms per
+// solve at m = 64)
 template <typename T, typename V>
 __device__ __forceinline__ double row_dot(const SellView<V>& A, int row, const T* __restrict__ x) {
   const int slice = row >> 6, lane = row & 63;
@@ -101,6 +103,34 @@ __global__ __launch_bounds__(NT) void k_sgs_enter(SellView<V> A, const unsigned 
   s[row] = colour[row] == 0 ? (T)(q * (double)A.dinv[row]) : T(0);
 }
 
+// The middle of the sweep in one launch, over the colour-3 Q1 rows: every
+// element has exactly one corner of each Q1 colour, so the thread of a
+// colour-3 node alone can take its forward update, then the colour-4
+// (element) updates of the elements around it (whose other corners are final
+// from the earlier passes), then its backward update; no other thread reads
+// or writes those entries in this launch.  Rows at or past nk are elements.
+template <typename T, typename V>
+__global__ __launch_bounds__(NT) void k_sgs_middle(SellView<V> A, const int* __restrict__ rows, int count, int nk,
+                                                    const T* __restrict__ b, T* __restrict__ x,
+                                                    const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= count) return;
+  const int r = rows[i];
+  x[r] = (T)((double)x[r] + ((double)b[r] - row_dot(A, r, x)) * (double)A.dinv[r]);
+  const int slice = r >> 6, lane = r & 63;
+  const int beg = A.ptr[slice];
+  const int width = (A.ptr[slice + 1] - beg) >> 6;
+  int prev = -1;
+  for (int k = 0; k < width; ++k) {
+    const int e = A.col[beg + 64 * k + lane];
+    if (e < nk || e == prev) continue;   // Q1 columns, and the padding that repeats the last column
+    prev = e;
+    x[e] = (T)((double)x[e] + ((double)b[e] - row_dot(A, e, x)) * (double)A.dinv[e]);
+  }
+  x[r] = (T)((double)x[r] + ((double)b[r] - row_dot(A, r, x)) * (double)A.dinv[r]);
+}
+
 // Last kernel of the step: the closing colour-0 pass of the sweep, then the
 // Chebyshev update d = alpha d + beta s, x = x + d (x_zero: x = d).
 template <typename T, typename V>
@@ -116,7 +146,9 @@ __global__ __launch_bounds__(NT) void k_sgs_leave(SellView<V> A, const unsigned 
     // the neighbours read here are of other colours: final for this pass
     sv = (double)(T)(sv + ((double)res[row] - row_dot(A, row, s)) * (double)A.dinv[row]);
   }
-  const double dn = (double)(T)(alpha * (double)d[row] + beta * sv);
+  // the first step starts the direction afresh: d is not read (its memory
+  // may hold anything, NaN included, before the first step writes it)
+  const double dn = x_zero ? (double)(T)(beta * sv) : (double)(T)(alpha * (double)d[row] + beta * sv);
   d[row] = (T)dn;
   x[row] = x_zero ? (T)dn : (T)((double)x[row] + dn);
 }
@@ -234,6 +266,15 @@ void launch_sgs_enter(const Sell& A, const unsigned char* colour, const T* x, co
 }
 
 template <typename T, typename V>
+void launch_sgs_middle(const Sell& A, const int* rows, int count, int nk, const T* b, T* x, const int* gate,
+                       hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL((k_sgs_middle<T, V>), dim3(nblk(count)), dim3(NT), 0, st, view<V>(A), rows, count, nk, b, x,
+                     gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T, typename V>
 void launch_sgs_leave(const Sell& A, const unsigned char* colour, const T* res, T* s, T* d, T* x, double alpha,
                       double beta, int x_zero, const int* gate, hipStream_t st) {
   hipLaunchKernelGGL((k_sgs_leave<T, V>), dim3(nblk(A.rows)), dim3(NT), 0, st, view<V>(A), colour, res, s, d, x,
@@ -279,7 +320,8 @@ void launch_frame_project(double* part, int nk, int n0, void* p, bool fp32, cons
   template void launch_sgs_enter<T, V>(const Sell&, const unsigned char*, const T*, const T*, T*, T*, const int*, \
                                        hipStream_t);                                                       \
   template void launch_sgs_leave<T, V>(const Sell&, const unsigned char*, const T*, T*, T*, T*, double, double, \
-                                       int, const int*, hipStream_t);
+                                       int, const int*, hipStream_t);                                        \
+  template void launch_sgs_middle<T, V>(const Sell&, const int*, int, int, const T*, T*, const int*, hipStream_t);
 ETH_SELL_INST(double, double)
 ETH_SELL_INST(float, float)
 template void launch_dense_apply<double>(const double*, int, const double*, long long, double*, long long, int,

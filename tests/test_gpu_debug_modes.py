@@ -40,11 +40,23 @@ def _oseen(schur):
     return out
 
 
-@pytest.mark.parametrize("case", ["stokes_mixed", "stokes_fp64", "oseen_two_stage", "oseen_lsc"])
+def _step(prec):
+    """Flow over a step, m = 8: Stokes start and two Picard steps (M_1 and
+    two-stage solves, every workspace of the sparse path)."""
+    P = eth.StepProblem(8, precision=prec)
+    x, infos = P.picard(2, rtol=1e-8, maxit=800)
+    out = (x.clone(), [i["iterations"] for i in infos])
+    P.close()
+    return out
+
+
+@pytest.mark.parametrize("case", ["stokes_mixed", "stokes_fp64", "oseen_two_stage", "oseen_lsc", "step_mixed",
+                                  "step_fp64"])
 def test_nan_filled_workspaces_change_nothing(case, monkeypatch):
     print(f"[nan fill] {case}", flush=True)
     run = {"stokes_mixed": lambda: _stokes(eth.MIXED), "stokes_fp64": lambda: _stokes(eth.FP64),
-           "oseen_two_stage": lambda: _oseen(0), "oseen_lsc": lambda: _oseen(2)}[case]
+           "oseen_two_stage": lambda: _oseen(0), "oseen_lsc": lambda: _oseen(2),
+           "step_mixed": lambda: _step(eth.MIXED), "step_fp64": lambda: _step(eth.FP64)}[case]
     x0, it0 = run()
     monkeypatch.setenv("ETH_DEBUG_NAN_FILL", "1")
     x1, it1 = run()

@@ -180,3 +180,20 @@ def test_benchmark_mesh_conserves_mass(prec):
     bb = _np(b)
     bb[: 2 * M.nv][dirichlet] = 0.0
     assert np.linalg.norm(r) <= 2e-8 * np.linalg.norm(bb)
+
+
+@pytest.mark.parametrize("prec", [eth.MIXED, eth.FP64])
+def test_fused_sweep_middle_equals_one_launch_per_colour(prec, monkeypatch):
+    """The colour-3 / element / colour-3 passes of the M_Q sweep in one
+    launch give bit for bit the three separate passes."""
+    M = StepMesh(16)
+    r = uniform_vector(M.N, 77)
+    r[: 2 * M.nv][np.concatenate([M.boundary_q2()] * 2)] = 0.0
+    w = stokes_start(StepMesh(16), NU)[: 2 * M.nv]
+    out = []
+    for split in ("0", "1"):
+        monkeypatch.setenv("ETH_DEBUG_UNFUSED_MQ", split)
+        P = _problem(16, w, prec)
+        out.append(_np(P.apply_preconditioner(_t(r), which=1)))
+        P.close()
+    assert np.array_equal(out[0], out[1])
