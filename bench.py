@@ -390,6 +390,14 @@ def bench_ragged(prec, steps, rtol):
         xs, infos = R.solve(bs, rtol=rtol, maxit=2000, out=xs)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    # every member's iterations in one captured graph per chunk (use_graph = 2)
+    xs, _ = R.solve(bs, rtol=rtol, maxit=2000, out=xs, use_graph=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xs, _ = R.solve(bs, rtol=rtol, maxit=2000, out=xs, use_graph=2)
+    torch.cuda.synchronize()
+    dt_joint = (time.perf_counter() - t0) / steps
     # the same problems one after another on one stream, for comparison
     t0 = time.perf_counter()
     for p, b, x in zip(R.problems, bs, xs):
@@ -399,7 +407,8 @@ def bench_ragged(prec, steps, rtol):
     dofs = sum(p.N for p in R.problems)
     R.close()
     return dict(cavities=len(sizes), total_dofs=dofs, solves_per_s=round(len(sizes) / dt, 3),
-                ms_per_batch=round(1e3 * dt, 3), ms_sequential=round(1e3 * seq, 3),
+                ms_per_batch=round(1e3 * dt, 3), ms_joint_graph=round(1e3 * dt_joint, 3),
+                ms_sequential=round(1e3 * seq, 3),
                 iterations_max=max(i["iterations"] for i in infos),
                 all_converged=all(i["status"] == 0 for i in infos), setup_s=round(setup, 2))
 

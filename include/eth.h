@@ -148,7 +148,11 @@ typedef struct {
                                 modulo null(K) (MINRES may leave a multiple of
                                 the frame null vector k in it)                    */
   int32_t use_x0;            /* 1: x holds the initial guess on entry               */
-  int32_t use_graph;         /* 1: replay the iteration as a captured hipGraph      */
+  int32_t use_graph;         /* 1: replay the iteration as a captured hipGraph;
+                                2 (eth_batch_solve only): one graph holds eight
+                                MINRES iterations of every member of the ragged
+                                batch, replayed until no member is active (no
+                                refinement restarts)                               */
   int32_t true_residual;     /* 1: compute ||b - K x||/||b|| into info (default 0)   */
   int32_t refine;            /* MINRES: at most this many FP64 defect-correction
                                 restarts (default 0).  When the recurrence has met

@@ -492,8 +492,13 @@ struct Problem {
   double mq_sign = 1.0;              // -1 under ETH_DEBUG_NEGATE_MQ (indefinite preconditioner)
   bool fused_smooth = true;          // V(2,2) smoothing fused into restriction / correction launches
   hipEvent_t ev_poll = nullptr;
-  void minres_begin(MinresRun& R);
+  // enqueue: also the first chunk of iterations (a joint batch graph runs
+  // the iterations of every member itself)
+  void minres_begin(MinresRun& R, bool enqueue = true);
   void minres_enqueue_chunk(MinresRun& R);
+  // after the iterations have ended (scalars on the host): the book-keeping
+  // and the output copies; false when an FP64 refinement restart was enqueued
+  bool minres_conclude(MinresRun& R);
   // true once the iteration has ended and the output copies are enqueued;
   // block = false returns false at once while the last chunk still runs
   bool minres_poll(MinresRun& R, bool block);
@@ -1413,7 +1418,7 @@ void Problem::load_rhs(const double* b, long long ld, int batch, bool adjoint) {
   }
 }
 
-void Problem::minres_begin(MinresRun& R) {
+void Problem::minres_begin(MinresRun& R, bool enqueue) {
   const eth_solve_opts& o = R.o;
   const int batch = R.batch;
   R.tol = o.rtol > 0 ? o.rtol : 1e-8;
@@ -1462,7 +1467,7 @@ void Problem::minres_begin(MinresRun& R) {
   precond(kv[0], kz[0], ldw, batch, no_gate(), true);
   RedCtx ri = red(dot_blocks(g.N), 1, EPI_MINRES_INIT, d_ms);
   launch_dot(g.N, kz[0], kv[0], ldw, batch, ri, no_gate(), st);
-  minres_enqueue_chunk(R);
+  if (enqueue) minres_enqueue_chunk(R);
 }
 
 // enqueue R.chunk iterations, then the copy of the scalars to the host and
@@ -1513,6 +1518,11 @@ bool Problem::minres_poll(MinresRun& R, bool block) {
     minres_enqueue_chunk(R);
     return false;
   }
+  return minres_conclude(R);
+}
+
+bool Problem::minres_conclude(MinresRun& R) {
+  const int batch = R.batch;
   minres_end_of_run(R);
   if (R.refine_left > 0) {
     // restart from x when every right-hand side met the recurrence's test
@@ -2666,7 +2676,13 @@ struct eth_batch {
   hipEvent_t ev_in = nullptr;
   std::vector<hipEvent_t> ev_out;
   std::string err;
+  // use_graph = 2: every member's iterations of one chunk in one captured
+  // graph, replayed on jst (created at first use)
+  hipStream_t jst = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_done = nullptr;
+  hipGraphExec_t joint = nullptr;
   ~eth_batch() {
+    if (jst) (void)hipStreamSynchronize(jst);
     for (auto* p : probs) {
       if (!p) continue;
       (void)hipStreamSynchronize(p->impl.st);
@@ -2674,8 +2690,48 @@ struct eth_batch {
     }
     for (auto e : ev_out) (void)hipEventDestroy(e);
     if (ev_in) (void)hipEventDestroy(ev_in);
+    if (joint) (void)hipGraphExecDestroy(joint);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_done) (void)hipEventDestroy(ev_done);
+    if (jst) (void)hipStreamDestroy(jst);
   }
 };
+
+namespace {
+constexpr int kJointChunk = 8;   // MINRES iterations per replay of the joint graph
+
+// One graph holding kJointChunk MINRES iterations of every member, each on
+// its own stream (captured by joining the member streams to a capture on
+// jst with events), so one launch drives the whole ragged batch; members
+// that have converged skip their kernels through their device flags.
+void joint_graph(eth_batch* bt) {
+  if (bt->joint) return;
+  ETH_HIP(hipStreamCreateWithFlags(&bt->jst, hipStreamNonBlocking));
+  ETH_HIP(hipEventCreateWithFlags(&bt->ev_fork, hipEventDisableTiming));
+  ETH_HIP(hipEventCreateWithFlags(&bt->ev_done, hipEventDisableTiming));
+  hipGraph_t graph;
+  ETH_HIP(hipStreamBeginCapture(bt->jst, hipStreamCaptureModeThreadLocal));
+  try {
+    ETH_HIP(hipEventRecord(bt->ev_fork, bt->jst));
+    for (size_t i = 0; i < bt->probs.size(); ++i) {
+      Problem& P = bt->probs[i]->impl;
+      ETH_HIP(hipStreamWaitEvent(P.st, bt->ev_fork, 0));
+      P.run_iterations(1, kJointChunk, false);
+      ETH_HIP(hipEventRecord(bt->ev_out[i], P.st));
+      ETH_HIP(hipStreamWaitEvent(bt->jst, bt->ev_out[i], 0));
+    }
+  } catch (...) {
+    hipGraph_t discard = nullptr;
+    (void)hipStreamEndCapture(bt->jst, &discard);
+    if (discard) (void)hipGraphDestroy(discard);
+    throw;
+  }
+  ETH_HIP(hipStreamEndCapture(bt->jst, &graph));
+  const hipError_t e = hipGraphInstantiate(&bt->joint, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  ETH_HIP(e);
+}
+}  // namespace
 
 extern "C" {
 
@@ -2749,11 +2805,59 @@ int eth_batch_solve(eth_batch* bt, const eth_solve_opts* opts, const double* con
     bt->err = "ragged batches run MINRES with maxit <= 4096";
     return ETH_EINVAL;
   }
+  if (o.use_graph == 2 && o.refine > 0) {
+    bt->err = "the joint batch graph (use_graph = 2) takes no refinement restarts";
+    return ETH_EUNSUPPORTED;
+  }
   try {
     eth::PhaseRange range("eth_batch_solve");
     std::vector<Problem::MinresRun> runs(count);
     std::vector<char> done(count, 0);
     ETH_HIP(hipEventRecord(bt->ev_in, bt->caller));
+    if (o.use_graph == 2) {
+      // every member's set-up work on its stream, then one joint replay per
+      // chunk on jst until no member is active
+      joint_graph(bt);
+      int maxit = 0;
+      for (int i = 0; i < count; ++i) {
+        Problem& P = bt->probs[i]->impl;
+        ETH_HIP(hipStreamWaitEvent(P.st, bt->ev_in, 0));
+        Problem::MinresRun& R = runs[i];
+        R.o = o;
+        R.b = b[i];
+        R.x = x[i];
+        R.batch = 1;
+        R.ld = P.g.N;
+        P.minres_begin(R, false);
+        maxit = std::max(maxit, R.maxit);
+        ETH_HIP(hipEventRecord(bt->ev_out[i], P.st));
+        ETH_HIP(hipStreamWaitEvent(bt->jst, bt->ev_out[i], 0));
+      }
+      for (int it = 0; it < maxit + 2; it += kJointChunk) {
+        ETH_HIP(hipGraphLaunch(bt->joint, bt->jst));
+        for (int i = 0; i < count; ++i) {
+          Problem& P = bt->probs[i]->impl;
+          ETH_HIP(hipMemcpyAsync(P.h_ms, P.d_ms, sizeof(eth::MinresScalars), hipMemcpyDeviceToHost, bt->jst));
+        }
+        ETH_HIP(hipStreamSynchronize(bt->jst));
+        bool any = false;
+        for (int i = 0; i < count; ++i) any = any || bt->probs[i]->impl.h_ms[0].active;
+        if (!any) break;
+      }
+      ETH_HIP(hipEventRecord(bt->ev_done, bt->jst));
+      int worst = ETH_OK;
+      for (int i = 0; i < count; ++i) {
+        Problem& P = bt->probs[i]->impl;
+        ETH_HIP(hipStreamWaitEvent(P.st, bt->ev_done, 0));
+        (void)P.minres_conclude(runs[i]);
+        const int st = P.minres_finish(runs[i], infos ? &infos[i] : nullptr);
+        ETH_HIP(hipEventRecord(bt->ev_out[i], P.st));
+        ETH_HIP(hipStreamWaitEvent(bt->caller, bt->ev_out[i], 0));
+        if (st < 0) worst = std::min(worst, st);
+        else if (worst >= 0) worst = std::max(worst, st);
+      }
+      return worst;
+    }
     for (int i = 0; i < count; ++i) {
       Problem& P = bt->probs[i]->impl;
       ETH_HIP(hipStreamWaitEvent(P.st, bt->ev_in, 0));

@@ -23,7 +23,8 @@ def _gpu():
     eth.load_library()
 
 
-@pytest.mark.parametrize("prec,graph", [(eth.FP64, True), (eth.MIXED, True), (eth.FP64, False)])
+@pytest.mark.parametrize("prec,graph", [(eth.FP64, True), (eth.MIXED, True), (eth.FP64, False), (eth.FP64, 2),
+                                        (eth.MIXED, 2)])
 def test_ragged_equals_standalone(prec, graph):
     sizes = [8, 12, 16, 24, 32, 48, 64]
     print(f"[ragged] sizes={sizes} prec={prec} graph={graph}", flush=True)
@@ -34,6 +35,9 @@ def test_ragged_equals_standalone(prec, graph):
     rtol = 1e-10 if prec == eth.FP64 else 1e-6
     xs, infos = R.solve(bs, rtol=rtol, maxit=2000, use_graph=graph, true_residual=True)
     torch.cuda.synchronize()
+    if graph == 2:   # a second solve replays the joint graph captured by the first
+        xs, infos = R.solve(bs, rtol=rtol, maxit=2000, use_graph=graph, true_residual=True, out=xs)
+        torch.cuda.synchronize()
     for n, b, x, info in zip(sizes, bs, xs, infos):
         assert info["status"] == 0
         P = eth.Problem(n, precision=prec)
