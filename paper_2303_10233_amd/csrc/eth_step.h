@@ -111,6 +111,30 @@ struct Sell {                 // sliced ELL: 64 rows per slice, column-major in 
   long long stored = 0;       // entries incl. padding
 };
 
+// ELL block of one colour class of a colour-ordered matrix: rows
+// [off, off + count), entry k of row i at k * count + i
+struct Ell {
+  int off = 0, count = 0, width = 0;
+  int* col = nullptr;
+  double* val = nullptr;
+  float* valf = nullptr;
+  double* dinv = nullptr;
+  float* dinvf = nullptr;
+};
+template <typename V>
+struct EllView {
+  int off, count, width;
+  const int* col;
+  const V* val;
+  const V* dinv;
+};
+template <typename V>
+inline EllView<V> eview(const Ell& e);
+template <>
+inline EllView<double> eview<double>(const Ell& e) { return {e.off, e.count, e.width, e.col, e.val, e.dinv}; }
+template <>
+inline EllView<float> eview<float>(const Ell& e) { return {e.off, e.count, e.width, e.col, e.valf, e.dinvf}; }
+
 template <typename V>
 struct SellView {
   int rows;
@@ -134,26 +158,27 @@ inline SellView<float> view<float>(const Sell& s) { return {s.rows, s.ptr, s.col
 template <typename T, typename V>
 void launch_sell(const Sell& A, int mode, const T* x, long long sx, const T* b, long long sb, T* y, long long sy,
                  int nvec, double w, double alpha, int has_prev, const int* gate, hipStream_t st);
-// x[r] += (b[r] - (A x)[r]) / A[r][r] for the rows r of one colour class
-template <typename T, typename V>
-void launch_sell_colour(const Sell& A, const int* rows, int count, const T* b, T* x, const int* gate,
-                        hipStream_t st);
 // a Chebyshev step on M_Q based on multicolour SGS, in three parts:
 // enter: res = r - M x (x null: r), s = D^{-1} res on colour 0, 0 elsewhere;
-// the colour passes 1, 2, 3, 4, 3, 2, 1 (launch_sell_colour with b = res,
-// or launch_sgs_middle for 3, 4, 3);
+// the colour passes 1, 2, 3, 4, 3, 2, 1 (launch_ell_colour with b = res,
+// or launch_ell_middle for 3, 4, 3);
 // leave: the closing colour-0 pass, d = alpha d + beta s, x = x + d (x_zero: d)
 template <typename T, typename V>
 void launch_sgs_enter(const Sell& A, const unsigned char* colour, const T* x, const T* r, T* res, T* s,
                       const int* gate, hipStream_t st);
-// the colour-3 forward pass, the element (colour-4) pass and the colour-3
-// backward pass in one launch over the colour-3 rows (rows >= nk: elements)
-template <typename T, typename V>
-void launch_sgs_middle(const Sell& A, const int* rows, int count, int nk, const T* b, T* x, const int* gate,
-                       hipStream_t st);
 template <typename T, typename V>
 void launch_sgs_leave(const Sell& A, const unsigned char* colour, const T* res, T* s, T* d, T* x, double alpha,
                       double beta, int x_zero, const int* gate, hipStream_t st);
+// colour pass / the colour-3, element, colour-3 middle on ELL blocks of a
+// colour-ordered matrix (b, x in the colour order)
+template <typename T, typename V>
+void launch_ell_colour(const Ell& E, const T* b, T* x, const int* gate, hipStream_t st);
+template <typename T, typename V>
+void launch_ell_middle(const Ell& E3, const Ell& E4, const T* b, T* x, const int* gate, hipStream_t st);
+// gather y[i] = a x[idx[i]] or scatter y[idx[i]] = a x[i], with type conversion
+template <typename Ti, typename To>
+void launch_permute(int n, const int* idx, bool scatter, double a, const Ti* x, To* y, const int* gate,
+                    hipStream_t st);
 // x = Ainv b (dense, FP64 matrix), nvec vectors of length n with strides
 template <typename T>
 void launch_dense_apply(const double* Ainv, int n, const T* b, long long sb, T* x, long long sx, int nvec,

@@ -115,8 +115,12 @@ struct StepProblem {
   std::vector<std::array<double, 2>> ap_a, ap_b;   // degree-2 Chebyshev per A_p level
   std::vector<double> q1a, q1b, mqa, mqb;
   double mq_theta = 1.0;
-  std::array<int*, 5> mq_rows{};
-  unsigned char* mq_colour = nullptr;   // colour of every pressure row
+  unsigned char* mq_colour = nullptr;   // colour of every pressure row (colour order)
+  // M_Q is held in colour order (the Q1 classes 0..3, then the elements):
+  // MQ is the permuted matrix, mq_ell[c] the ELL block of class c, mq_perm
+  // the pressure index of each row of the colour order
+  std::array<Ell, 5> mq_ell{};
+  int* mq_perm = nullptr;
   std::array<int, 5> mq_count{};
   int* dir_idx = nullptr;
   int ndir = 0;
@@ -154,6 +158,7 @@ struct StepProblem {
   }
   void* allocT(size_t n) { return mixed ? (void*)alloc<float>(n) : (void*)alloc<double>(n); }
   void upload(Sell& s, const Csr& A, bool f32, bool dinv);
+  void upload_ell(Ell& e, const Csr& A, int off, int count);
   void setup(const eth_step_desc& desc);
   void assemble_wind();   // F levels, K, F1 and the coarse inverse from `wind`
   long long N() const { return ms[0].N(); }
@@ -267,6 +272,44 @@ void StepProblem::upload(Sell& s, const Csr& A, bool f32, bool dinv) {
   }
 }
 
+// rows [off, off + count) of A as an ELL block (entry k of row i at
+// k * count + i; padding repeats the row's last column with value 0)
+void StepProblem::upload_ell(Ell& e, const Csr& A, int off, int count) {
+  int w = 0;
+  for (int i = 0; i < count; ++i) w = std::max(w, A.ptr[off + i + 1] - A.ptr[off + i]);
+  std::vector<int> col((size_t)w * count, 0);
+  std::vector<double> val((size_t)w * count, 0.0), di(count, 0.0);
+  for (int i = 0; i < count; ++i) {
+    const int r = off + i, b = A.ptr[r], len = A.ptr[r + 1] - b;
+    int last = r;
+    for (int k = 0; k < w; ++k) {
+      if (k < len) {
+        last = A.col[b + k];
+        val[(size_t)k * count + i] = A.val[b + k];
+      }
+      col[(size_t)k * count + i] = last;
+    }
+    const double dd = A.diag(r);
+    di[i] = dd != 0.0 ? 1.0 / dd : 0.0;
+  }
+  e.off = off;
+  e.count = count;
+  e.width = w;
+  e.col = alloc<int>(col.size());
+  e.val = alloc<double>(val.size());
+  e.dinv = alloc<double>(count);
+  ETH_HIP(hipMemcpy(e.col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice));
+  ETH_HIP(hipMemcpy(e.val, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice));
+  ETH_HIP(hipMemcpy(e.dinv, di.data(), sizeof(double) * di.size(), hipMemcpyHostToDevice));
+  if (mixed) {
+    std::vector<float> vf(val.begin(), val.end()), df(di.begin(), di.end());
+    e.valf = alloc<float>(vf.size());
+    e.dinvf = alloc<float>(df.size());
+    ETH_HIP(hipMemcpy(e.valf, vf.data(), sizeof(float) * vf.size(), hipMemcpyHostToDevice));
+    ETH_HIP(hipMemcpy(e.dinvf, df.data(), sizeof(float) * df.size(), hipMemcpyHostToDevice));
+  }
+}
+
 void StepProblem::setup(const eth_step_desc& desc) {
   Range range("eth_step_setup");
   d = desc;
@@ -309,7 +352,6 @@ void StepProblem::setup(const eth_step_desc& desc) {
   const StepMesh& g = ms[0];
   // fixed operators
   B = step_assemble_B(g, el[0]);
-  upload(MQ, step_assemble_MQ(g, el[0]), mixed, true);
   upload(Q1, step_assemble_Q1(g, el[0]), mixed, true);
   F.resize(L);
   P.resize(L > 1 ? L - 1 : 0);
@@ -349,21 +391,49 @@ void StepProblem::setup(const eth_step_desc& desc) {
   }
   cheb_ab(0.25, 2.25, d.pcd_q1_steps, q1a, q1b);
   cheb_ab(d.mq_cheb_lo, 1.0, d.mq_steps, mqa, mqb);
-  // multicolour classes of M_Q: Q1 node parities (I mod 2) + 2 (J mod 2), then the elements
+  // multicolour classes of M_Q: Q1 node parities (I mod 2) + 2 (J mod 2),
+  // then the elements; M_Q is stored with its rows and columns in this order
   {
     std::array<std::vector<int>, 5> rows;
     for (int k = 0; k < g.nk; ++k) rows[(g.q1_I[k] & 1) + 2 * (g.q1_J[k] & 1)].push_back(k);
     for (int e = 0; e < g.n0; ++e) rows[4].push_back(g.nk + e);
-    std::vector<unsigned char> col((size_t)g.nk + g.n0);
+    const int np = g.nk + g.n0;
+    std::vector<int> perm, inv(np);
+    std::array<int, 6> off{};
+    for (int c = 0; c < 5; ++c) {
+      off[c] = (int)perm.size();
+      perm.insert(perm.end(), rows[c].begin(), rows[c].end());
+    }
+    off[5] = np;
+    for (int i = 0; i < np; ++i) inv[perm[i]] = i;
+    const Csr M = step_assemble_MQ(g, el[0]);
+    Csr Mp;
+    Mp.rows = Mp.cols = np;
+    Mp.ptr.assign(np + 1, 0);
+    std::vector<std::pair<int, double>> row;
+    for (int i = 0; i < np; ++i) {
+      const int r = perm[i];
+      row.clear();
+      for (int k = M.ptr[r]; k < M.ptr[r + 1]; ++k) row.emplace_back(inv[M.col[k]], M.val[k]);
+      std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      for (const auto& e : row) {
+        Mp.col.push_back(e.first);
+        Mp.val.push_back(e.second);
+      }
+      Mp.ptr[i + 1] = (int)Mp.col.size();
+    }
+    upload(MQ, Mp, mixed, true);
+    for (int c = 0; c < 5; ++c) {
+      upload_ell(mq_ell[c], Mp, off[c], off[c + 1] - off[c]);
+      mq_count[c] = off[c + 1] - off[c];
+    }
+    std::vector<unsigned char> col(np);
     for (int c = 0; c < 5; ++c)
-      for (int r : rows[c]) col[r] = (unsigned char)c;
+      for (int i = off[c]; i < off[c + 1]; ++i) col[i] = (unsigned char)c;
     mq_colour = alloc<unsigned char>(col.size());
     ETH_HIP(hipMemcpy(mq_colour, col.data(), col.size(), hipMemcpyHostToDevice));
-    for (int c = 0; c < 5; ++c) {
-      mq_count[c] = (int)rows[c].size();
-      mq_rows[c] = alloc<int>(rows[c].size());
-      ETH_HIP(hipMemcpy(mq_rows[c], rows[c].data(), sizeof(int) * rows[c].size(), hipMemcpyHostToDevice));
-    }
+    mq_perm = alloc<int>(perm.size());
+    ETH_HIP(hipMemcpy(mq_perm, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice));
   }
   {
     std::vector<int> di;
@@ -570,17 +640,17 @@ void StepProblem::mq_solve(const int* gate) {
   // the sweep from zero visits the colours 0, 1, 2, 3, 4, 3, 2, 1, 0
   for (int k = 0; k < d.mq_steps; ++k) {
     launch_sgs_enter<T, T>(MQ, mq_colour, k == 0 ? nullptr : x, r, res, s, gate, st);
-    launch_sell_colour<T, T>(MQ, mq_rows[1], mq_count[1], res, s, gate, st);
-    launch_sell_colour<T, T>(MQ, mq_rows[2], mq_count[2], res, s, gate, st);
+    launch_ell_colour<T, T>(mq_ell[1], res, s, gate, st);
+    launch_ell_colour<T, T>(mq_ell[2], res, s, gate, st);
     if (sgs_split) {
-      launch_sell_colour<T, T>(MQ, mq_rows[3], mq_count[3], res, s, gate, st);
-      launch_sell_colour<T, T>(MQ, mq_rows[4], mq_count[4], res, s, gate, st);
-      launch_sell_colour<T, T>(MQ, mq_rows[3], mq_count[3], res, s, gate, st);
+      launch_ell_colour<T, T>(mq_ell[3], res, s, gate, st);
+      launch_ell_colour<T, T>(mq_ell[4], res, s, gate, st);
+      launch_ell_colour<T, T>(mq_ell[3], res, s, gate, st);
     } else {
-      launch_sgs_middle<T, T>(MQ, mq_rows[3], mq_count[3], nk_, res, s, gate, st);
+      launch_ell_middle<T, T>(mq_ell[3], mq_ell[4], res, s, gate, st);
     }
-    launch_sell_colour<T, T>(MQ, mq_rows[2], mq_count[2], res, s, gate, st);
-    launch_sell_colour<T, T>(MQ, mq_rows[1], mq_count[1], res, s, gate, st);
+    launch_ell_colour<T, T>(mq_ell[2], res, s, gate, st);
+    launch_ell_colour<T, T>(mq_ell[1], res, s, gate, st);
     launch_sgs_leave<T, T>(MQ, mq_colour, res, s, dd, x, mqa[k], mqb[k], k == 0 ? 1 : 0, gate, st);
   }
   (void)np;
@@ -592,10 +662,10 @@ template <typename T>
 void StepProblem::m1(const double* r, double* z, const int* gate) {
   const int nv2 = 2 * nv(), np = nk() + n0();
   const GmresScalars* gs = gate ? d_gm : nullptr;
-  launch_vcombine<double, T>(np, 1.0, r + nv2, 0.0, nullptr, static_cast<T*>(mr), gate, st);
+  launch_permute<double, T>(np, mq_perm, false, 1.0, r + nv2, static_cast<T*>(mr), gate, st);
   mq_solve<T>(gate);
   launch_gm_zero_range(z, 0, 0, nv2, 1, gs, st);
-  launch_vcombine<T, double>(np, -d.nu, static_cast<const T*>(mxx), 0.0, nullptr, z + nv2, gate, st);
+  launch_permute<T, double>(np, mq_perm, true, -d.nu, static_cast<const T*>(mxx), z + nv2, gate, st);
   apply(z, kw, gate);
   vcycle_F<T>(r, kw, z, gate);
 }

@@ -73,20 +73,6 @@ __global__ __launch_bounds__(NT) void k_sell(SellView<V> A, const T* __restrict_
   }
 }
 
-template <typename T, typename V>
-__global__ __launch_bounds__(NT) void k_sell_colour(SellView<V> A, const int* __restrict__ rows, int count,
-                                                     const T* __restrict__ b, T* __restrict__ x,
-                                                     const int* __restrict__ gate) {
-  if (gated(gate)) return;
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= count) return;
-  const int r = rows[i];
-  // rows of one colour do not couple, so every x read here except x[r]
-  // (read by this thread only) is final for the pass
-  const double s = row_dot(A, r, x);
-  x[r] = (T)((double)x[r] + ((double)b[r] - s) * (double)A.dinv[r]);
-}
-
 // First kernel of a Chebyshev-SGS step on M_Q: res = r - M x (x == null:
 // res = r) over all rows, and the first colour pass of a symmetric sweep
 // from zero, s = D^{-1} res on colour 0 and s = 0 elsewhere.
@@ -101,34 +87,6 @@ __global__ __launch_bounds__(NT) void k_sgs_enter(SellView<V> A, const unsigned 
   const double q = (double)r[row] - (x ? row_dot(A, row, x) : 0.0);
   res[row] = (T)q;
   s[row] = colour[row] == 0 ? (T)(q * (double)A.dinv[row]) : T(0);
-}
-
-// The middle of the sweep in one launch, over the colour-3 Q1 rows: every
-// element has exactly one corner of each Q1 colour, so the thread of a
-// colour-3 node alone can take its forward update, then the colour-4
-// (element) updates of the elements around it (whose other corners are final
-// from the earlier passes), then its backward update; no other thread reads
-// or writes those entries in this launch.  Rows at or past nk are elements.
-template <typename T, typename V>
-__global__ __launch_bounds__(NT) void k_sgs_middle(SellView<V> A, const int* __restrict__ rows, int count, int nk,
-                                                    const T* __restrict__ b, T* __restrict__ x,
-                                                    const int* __restrict__ gate) {
-  if (gated(gate)) return;
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= count) return;
-  const int r = rows[i];
-  x[r] = (T)((double)x[r] + ((double)b[r] - row_dot(A, r, x)) * (double)A.dinv[r]);
-  const int slice = r >> 6, lane = r & 63;
-  const int beg = A.ptr[slice];
-  const int width = (A.ptr[slice + 1] - beg) >> 6;
-  int prev = -1;
-  for (int k = 0; k < width; ++k) {
-    const int e = A.col[beg + 64 * k + lane];
-    if (e < nk || e == prev) continue;   // Q1 columns, and the padding that repeats the last column
-    prev = e;
-    x[e] = (T)((double)x[e] + ((double)b[e] - row_dot(A, e, x)) * (double)A.dinv[e]);
-  }
-  x[r] = (T)((double)x[r] + ((double)b[r] - row_dot(A, r, x)) * (double)A.dinv[r]);
 }
 
 // Last kernel of the step: the closing colour-0 pass of the sweep, then the
@@ -151,6 +109,79 @@ __global__ __launch_bounds__(NT) void k_sgs_leave(SellView<V> A, const unsigned 
   const double dn = x_zero ? (double)(T)(beta * sv) : (double)(T)(alpha * (double)d[row] + beta * sv);
   d[row] = (T)dn;
   x[row] = x_zero ? (T)dn : (T)((double)x[row] + dn);
+}
+
+// One colour pass on a colour-ordered matrix: the rows of the class are the
+// contiguous range [off, off + count) and their entries an ELL block
+// (entry k of row i at k * count + i), so a thread loads its entries
+// directly, without a row list or slice offsets in the dependent chain.
+template <typename T, typename V>
+__device__ __forceinline__ double ell_dot(const EllView<V>& E, int i, const T* __restrict__ x) {
+  const int* c = E.col + i;
+  const V* v = E.val + i;
+  const int n = E.count;
+  double s = 0.0;
+  int k = 0;
+  for (; k + 4 <= E.width; k += 4) {
+    const int c0 = c[k * n], c1 = c[(k + 1) * n], c2 = c[(k + 2) * n], c3 = c[(k + 3) * n];
+    const double v0 = (double)v[k * n], v1 = (double)v[(k + 1) * n], v2 = (double)v[(k + 2) * n],
+                 v3 = (double)v[(k + 3) * n];
+    const double x0 = (double)x[c0], x1 = (double)x[c1], x2 = (double)x[c2], x3 = (double)x[c3];
+    s += v0 * x0;
+    s += v1 * x1;
+    s += v2 * x2;
+    s += v3 * x3;
+  }
+  for (; k < E.width; ++k) s += (double)v[k * n] * (double)x[c[k * n]];
+  return s;
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(NT) void k_ell_colour(EllView<V> E, const T* __restrict__ b, T* __restrict__ x,
+                                                    const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= E.count) return;
+  const int r = E.off + i;
+  const double s = ell_dot(E, i, x);
+  x[r] = (T)((double)x[r] + ((double)b[r] - s) * (double)E.dinv[i]);
+}
+
+// The middle of the sweep in one launch over the colour-3 rows: every
+// element has exactly one corner of each Q1 colour, so the thread of a
+// colour-3 node alone takes its forward update, then the colour-4 (element)
+// updates of the elements around it (rows from E4.off on; their other
+// corners are final from the earlier passes), then its backward update; no
+// other thread reads or writes those entries in this launch.
+template <typename T, typename V>
+__global__ __launch_bounds__(NT) void k_ell_middle(EllView<V> E3, EllView<V> E4, const T* __restrict__ b,
+                                                    T* __restrict__ x, const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= E3.count) return;
+  const int r = E3.off + i;
+  x[r] = (T)((double)x[r] + ((double)b[r] - ell_dot(E3, i, x)) * (double)E3.dinv[i]);
+  int prev = -1;
+  for (int k = 0; k < E3.width; ++k) {
+    const int e = E3.col[k * E3.count + i];
+    if (e < E4.off || e == prev) continue;   // Q1 columns, and padding repeating the last column
+    prev = e;
+    const int j = e - E4.off;
+    x[e] = (T)((double)x[e] + ((double)b[e] - ell_dot(E4, j, x)) * (double)E4.dinv[j]);
+  }
+  x[r] = (T)((double)x[r] + ((double)b[r] - ell_dot(E3, i, x)) * (double)E3.dinv[i]);
+}
+
+// y[i] = (To)(a * x[idx[i]])  (gather) or y[idx[i]] = (To)(a * x[i])  (scatter)
+template <typename Ti, typename To, bool SCATTER>
+__global__ __launch_bounds__(NT) void k_permute(int n, const int* __restrict__ idx, double a,
+                                                 const Ti* __restrict__ x, To* __restrict__ y,
+                                                 const int* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  if constexpr (SCATTER) y[idx[i]] = (To)(a * (double)x[i]);
+  else y[i] = (To)(a * (double)x[idx[i]]);
 }
 
 template <typename T>
@@ -250,14 +281,6 @@ void launch_sell(const Sell& A, int mode, const T* x, long long sx, const T* b, 
 }
 
 template <typename T, typename V>
-void launch_sell_colour(const Sell& A, const int* rows, int count, const T* b, T* x, const int* gate,
-                        hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL((k_sell_colour<T, V>), dim3(nblk(count)), dim3(NT), 0, st, view<V>(A), rows, count, b, x, gate);
-  ETH_LAUNCH_CHECK();
-}
-
-template <typename T, typename V>
 void launch_sgs_enter(const Sell& A, const unsigned char* colour, const T* x, const T* r, T* res, T* s,
                       const int* gate, hipStream_t st) {
   hipLaunchKernelGGL((k_sgs_enter<T, V>), dim3(nblk(A.rows)), dim3(NT), 0, st, view<V>(A), colour, x, r, res, s,
@@ -266,11 +289,27 @@ void launch_sgs_enter(const Sell& A, const unsigned char* colour, const T* x, co
 }
 
 template <typename T, typename V>
-void launch_sgs_middle(const Sell& A, const int* rows, int count, int nk, const T* b, T* x, const int* gate,
-                       hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL((k_sgs_middle<T, V>), dim3(nblk(count)), dim3(NT), 0, st, view<V>(A), rows, count, nk, b, x,
-                     gate);
+void launch_ell_colour(const Ell& E, const T* b, T* x, const int* gate, hipStream_t st) {
+  if (E.count <= 0) return;
+  hipLaunchKernelGGL((k_ell_colour<T, V>), dim3(nblk(E.count)), dim3(NT), 0, st, eview<V>(E), b, x, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename T, typename V>
+void launch_ell_middle(const Ell& E3, const Ell& E4, const T* b, T* x, const int* gate, hipStream_t st) {
+  if (E3.count <= 0) return;
+  hipLaunchKernelGGL((k_ell_middle<T, V>), dim3(nblk(E3.count)), dim3(NT), 0, st, eview<V>(E3), eview<V>(E4), b,
+                     x, gate);
+  ETH_LAUNCH_CHECK();
+}
+
+template <typename Ti, typename To>
+void launch_permute(int n, const int* idx, bool scatter, double a, const Ti* x, To* y, const int* gate,
+                    hipStream_t st) {
+  if (scatter)
+    hipLaunchKernelGGL((k_permute<Ti, To, true>), dim3(nblk(n)), dim3(NT), 0, st, n, idx, a, x, y, gate);
+  else
+    hipLaunchKernelGGL((k_permute<Ti, To, false>), dim3(nblk(n)), dim3(NT), 0, st, n, idx, a, x, y, gate);
   ETH_LAUNCH_CHECK();
 }
 
@@ -316,18 +355,24 @@ void launch_frame_project(double* part, int nk, int n0, void* p, bool fp32, cons
 #define ETH_SELL_INST(T, V)                                                                                  \
   template void launch_sell<T, V>(const Sell&, int, const T*, long long, const T*, long long, T*, long long, \
                                   int, double, double, int, const int*, hipStream_t);                      \
-  template void launch_sell_colour<T, V>(const Sell&, const int*, int, const T*, T*, const int*, hipStream_t); \
   template void launch_sgs_enter<T, V>(const Sell&, const unsigned char*, const T*, const T*, T*, T*, const int*, \
                                        hipStream_t);                                                       \
   template void launch_sgs_leave<T, V>(const Sell&, const unsigned char*, const T*, T*, T*, T*, double, double, \
                                        int, const int*, hipStream_t);                                        \
-  template void launch_sgs_middle<T, V>(const Sell&, const int*, int, int, const T*, T*, const int*, hipStream_t);
+  template void launch_ell_colour<T, V>(const Ell&, const T*, T*, const int*, hipStream_t);                 \
+  template void launch_ell_middle<T, V>(const Ell&, const Ell&, const T*, T*, const int*, hipStream_t);
 ETH_SELL_INST(double, double)
 ETH_SELL_INST(float, float)
 template void launch_dense_apply<double>(const double*, int, const double*, long long, double*, long long, int,
                                          const int*, hipStream_t);
 template void launch_dense_apply<float>(const double*, int, const float*, long long, float*, long long, int,
                                         const int*, hipStream_t);
+template void launch_permute<double, double>(int, const int*, bool, double, const double*, double*, const int*,
+                                             hipStream_t);
+template void launch_permute<double, float>(int, const int*, bool, double, const double*, float*, const int*,
+                                            hipStream_t);
+template void launch_permute<float, double>(int, const int*, bool, double, const float*, double*, const int*,
+                                            hipStream_t);
 template void launch_vcombine<double, double>(long long, double, const double*, double, const double*, double*,
                                               const int*, hipStream_t);
 template void launch_vcombine<double, float>(long long, double, const double*, double, const double*, float*,
