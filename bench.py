@@ -563,6 +563,9 @@ def main():
     ap.add_argument("--counters-kernel", choices=["mq", "apply", "oseen"], default="mq",
                     help="kernel of --counters: the fused M_Q step (headline), the FP64 apply at n = 2048, "
                          "or the Oseen apply and F smoothing step at n = 2048")
+    ap.add_argument("--step-only", type=int, default=0, metavar="M",
+                    help="only the flow-over-a-step workload at m elements per unit length (mixed and FP64; "
+                         "the command of the step's kernel statistics)")
     ap.add_argument("--mq-variant", default="auto",
                     help="fused M_Q step of the headline solves as TILExSTEPS (e.g. 16x1), or auto (set-up "
                          "timing); a profiler serialises the two preconditioner branches, so a profiled run "
@@ -574,6 +577,16 @@ def main():
         mq_kw = dict(mq_tile=int(t), mq_fuse_steps=int(st))
     if args.counters:
         counters_run(args.n, args.profile_reps, args.mq_tile, args.counters_kernel)
+        return
+    if args.step_only:
+        from paper_2303_10233_amd import eth
+        res = []
+        for name, prec in (("mixed", eth.MIXED), ("fp64", eth.FP64)):
+            r = bench_step(args.step_only, prec, args.extra_steps, args.rtol)
+            r["precision"] = name
+            res.append(r)
+            log(f"step m={args.step_only} {name}: {r['solves_per_s']} solves/s, {r['iterations']} its")
+        print(json.dumps({"step": res}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
