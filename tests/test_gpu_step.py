@@ -197,3 +197,37 @@ def test_fused_sweep_middle_equals_one_launch_per_colour(prec, monkeypatch):
         out.append(_np(P.apply_preconditioner(_t(r), which=1)))
         P.close()
     assert np.array_equal(out[0], out[1])
+
+
+def test_odd_factor_hierarchy_matches_direct():
+    """m = 12: levels 12, 6, 3 (the coarsest with an odd number of elements
+    per unit length, solved densely)."""
+    print("[step m=12]", flush=True)
+    M = StepMesh(12)
+    w = stokes_start(M, NU)[: 2 * M.nv]
+    S = System(M, nu=NU, wind=w)
+    b = S.rhs(None, inflow_dirichlet(M))
+    xd = direct_solve(S, b)
+    P = _problem(12, w)
+    ms, _ = P.levels()
+    assert ms == [12, 6, 3]
+    x, info = P.solve(P.rhs(), rtol=1e-10, maxit=2000)
+    assert info["status"] == eth.OK
+    assert rel_err(_np(x), xd) < 1e-8
+
+
+def test_setup_rejects_bad_descriptions():
+    with pytest.raises(eth.EthError) as e:
+        eth.StepProblem(0)
+    assert e.value.status == eth.EINVAL
+    with pytest.raises(eth.EthError) as e:      # a prime m leaves a coarsest level too large to invert
+        eth.StepProblem(67)
+    assert e.value.status == eth.EINVAL
+    with pytest.raises(eth.EthError):
+        eth.StepProblem(8, nu=0.0)
+    P = _problem(4, None)
+    with pytest.raises(eth.EthError) as e:      # the PCD needs a wind
+        P.solve(P.rhs(), method=eth.TWO_STAGE)
+    assert e.value.status == eth.EUNSUPPORTED
+    with pytest.raises(ValueError):
+        P.apply(torch.zeros(P.N + 1, dtype=torch.float64, device=DEV))
