@@ -68,15 +68,6 @@ struct RowBuilder {
   Csr finish(bool drop_zeros = false) const;
 };
 
-// Everything the solver needs on one mesh, assembled on the host.
-struct StepHostLevel {
-  StepMesh mesh;
-  Csr F;          // scalar Q2 operator nu_l A + N(w), Dirichlet rows = identity, Dirichlet columns dropped
-  Csr P;          // Q2 prolongation from the next coarser level (fine x coarse), free rows / columns only
-  Csr Ap;         // B_1 diag(M_v)^{-1} B_1^T (Q1 x Q1)
-  Csr Pq;         // Q1 prolongation from the next coarser level
-};
-
 // Host assembly entry points (eth_step_asm.hip)
 Csr step_assemble_F(const StepMesh& mesh, const StepElem& E, double nu, const double* wind, bool embed);
 Csr step_assemble_B(const StepMesh& mesh, const StepElem& E);          // n_p x 2 n_v (all velocity columns)

@@ -114,14 +114,12 @@ struct StepProblem {
   std::vector<double> ap_lam;
   std::vector<std::array<double, 2>> ap_a, ap_b;   // degree-2 Chebyshev per A_p level
   std::vector<double> q1a, q1b, mqa, mqb;
-  double mq_theta = 1.0;
   unsigned char* mq_colour = nullptr;   // colour of every pressure row (colour order)
   // M_Q is held in colour order (the Q1 classes 0..3, then the elements):
   // MQ is the permuted matrix, mq_ell[c] the ELL block of class c, mq_perm
   // the pressure index of each row of the colour order
   std::array<Ell, 5> mq_ell{};
   int* mq_perm = nullptr;
-  std::array<int, 5> mq_count{};
   int* dir_idx = nullptr;
   int ndir = 0;
   // workspaces
@@ -425,7 +423,6 @@ void StepProblem::setup(const eth_step_desc& desc) {
     upload(MQ, Mp, mixed, true);
     for (int c = 0; c < 5; ++c) {
       upload_ell(mq_ell[c], Mp, off[c], off[c + 1] - off[c]);
-      mq_count[c] = off[c + 1] - off[c];
     }
     std::vector<unsigned char> col(np);
     for (int c = 0; c < 5; ++c)

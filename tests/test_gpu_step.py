@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 from oracle.assemble import System  # noqa: E402
 from oracle.precond import OseenM1  # noqa: E402
 from oracle.step import (StepMesh, inflow_dirichlet, poiseuille, direct_solve, stokes_start, picard,  # noqa: E402
-                         line_fluxes, velocity_gmg, PCDStage1, MQChebSGS, two_stage, ap_gmg,
+                         line_fluxes, velocity_gmg, PCDStage1, MQChebSGS, two_stage,
                          lambda_max_dinv, pressure_laplacian)
 from oracle.direct import rel_err  # noqa: E402
 from paper_2303_10233_amd import eth  # noqa: E402
@@ -41,10 +41,6 @@ def _gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     eth.load_library()
-
-
-def _interior(S, x):
-    return S.to_interior(x)
 
 
 def _problem(m, wind, prec=eth.FP64, channel=False):
