@@ -489,7 +489,10 @@ int eth_step_apply(eth_step* p, const double* x, double* y);
  * (the p_0 part of z is zero) */
 int eth_step_apply_preconditioner(eth_step* p, int32_t which, const double* r, double* z);
 /* opts as for eth_solve (method ETH_TWO_STAGE or ETH_FGMRES); canonicalize
- * shifts the pressure along k so that the element pressures have mean zero */
+ * shifts the pressure along k so that the element pressures have mean zero.
+ * b must be consistent with null(K^T) = span{[0; k]}: ETH_EINCONSISTENT when
+ * |k . b_p| > 1e-10 sqrt(n_k + n_0) ||b|| (the lifted right-hand side of
+ * eth_step_rhs satisfies it to rounding), ETH_EINVAL for a NaN or Inf in b. */
 int eth_step_solve(eth_step* p, const eth_solve_opts* opts, const double* b, double* x, eth_solve_info* info);
 /* The Stokes solution (FGMRES with M_1) followed by `steps` Picard steps, each
  * an Oseen solve by opts->method whose wind is the velocity of the previous

@@ -183,5 +183,7 @@ void launch_vcombine(long long n, double a, const Ti* x, double c, const Ti* z, 
 void launch_frame_project(double* p_part_scratch, int nk, int n0, void* p, bool fp32, const int* gate,
                           hipStream_t st);
 int frame_project_blocks(int np);
+// block partial sums of k . p = sum(p_1) - sum(p_0) (FP64, frame_project_blocks(nk + n0) of them)
+void launch_frame_partials(double* part, int nk, int n0, const double* p, hipStream_t st);
 
 }  // namespace eth

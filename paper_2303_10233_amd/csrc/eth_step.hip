@@ -795,6 +795,22 @@ int StepProblem::solve(const eth_solve_opts& o, const double* b, double* x, eth_
   hipLaunchKernelGGL(k_scatter_zero, dim3(nblk(ndir)), dim3(NT), 0, st, dir_idx, ndir, kb);
   ETH_LAUNCH_CHECK();
   const double bn = norm(kb);
+  if (!std::isfinite(bn)) throw std::invalid_argument("right-hand side holds a NaN or Inf");
+  {
+    // consistency with null(K^T) = span{[0; k]}: k . b_p = 0 (for the lifted
+    // right-hand side k . b_p = -(B^T k) . u_B = 0 exactly)
+    const int nb = frame_project_blocks(nk() + n0());
+    launch_frame_partials(fpart, nk(), n0(), kb + nv2, st);
+    std::vector<double> part(nb);
+    ETH_HIP(hipMemcpyAsync(part.data(), fpart, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    ETH_HIP(hipStreamSynchronize(st));
+    double kb_dot = 0.0;
+    for (double v : part) kb_dot += v;
+    const double kn = std::sqrt((double)(nk() + n0()));
+    if (std::fabs(kb_dot) > 1e-10 * kn * std::max(bn, 1e-300))
+      throw std::runtime_error("inconsistent:right-hand side not orthogonal to null(K^T): k . b_p = " +
+                               std::to_string(kb_dot));
+  }
   double r0 = bn;
   if (o.use_x0) {
     launch_copy(n, x, n, kx, n, 1, st);
@@ -894,6 +910,7 @@ int sguard(eth_step* p, F&& f) {
   } catch (const std::runtime_error& e) {
     const std::string m = e.what();
     if (m.rfind("unsupported:", 0) == 0) return sfail(p, ETH_EUNSUPPORTED, m.substr(12));
+    if (m.rfind("inconsistent:", 0) == 0) return sfail(p, ETH_EINCONSISTENT, m.substr(13));
     return sfail(p, ETH_EDEVICE, m);
   }
 }

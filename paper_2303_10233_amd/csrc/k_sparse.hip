@@ -352,6 +352,12 @@ void launch_frame_project(double* part, int nk, int n0, void* p, bool fp32, cons
   ETH_LAUNCH_CHECK();
 }
 
+void launch_frame_partials(double* part, int nk, int n0, const double* p, hipStream_t st) {
+  const int np = nk + n0, nb = frame_project_blocks(np);
+  hipLaunchKernelGGL(k_frame_partial<double>, dim3(nb), dim3(NT), 0, st, nk, np, p, part, nullptr);
+  ETH_LAUNCH_CHECK();
+}
+
 #define ETH_SELL_INST(T, V)                                                                                  \
   template void launch_sell<T, V>(const Sell&, int, const T*, long long, const T*, long long, T*, long long, \
                                   int, double, double, int, const int*, hipStream_t);                      \

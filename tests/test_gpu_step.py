@@ -227,3 +227,23 @@ def test_setup_rejects_bad_descriptions():
     assert e.value.status == eth.EUNSUPPORTED
     with pytest.raises(ValueError):
         P.apply(torch.zeros(P.N + 1, dtype=torch.float64, device=DEV))
+
+
+def test_solve_rejects_inconsistent_and_non_finite_rhs():
+    P = _problem(4, stokes_start(StepMesh(4), NU)[: 2 * StepMesh(4).nv])
+    b = P.rhs()
+    bad = b.clone()
+    bad[2 * P.nv] += 1.0                 # one Q1 row: k . b_p = 1
+    with pytest.raises(eth.EthError) as e:
+        P.solve(bad)
+    assert e.value.status == eth.EINCONSISTENT
+    bad = b.clone()
+    bad[2 * P.nv] += 1.0
+    bad[2 * P.nv + P.nk] += 1.0          # and one element row: k . b_p = 0 again
+    x, info = P.solve(bad, rtol=1e-8, maxit=2000)
+    assert info["status"] == eth.OK
+    bad = b.clone()
+    bad[int(np.flatnonzero(~StepMesh(4).boundary_q2())[0])] = float("nan")   # a free velocity row
+    with pytest.raises(eth.EthError) as e:
+        P.solve(bad)
+    assert e.value.status == eth.EINVAL
