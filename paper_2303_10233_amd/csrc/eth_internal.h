@@ -152,6 +152,7 @@ struct RedCtx {
   int nvals;           // values reduced per block (<= kMaxRedVals)
   int epi;             // epilogue id (eth_epilogue.h), 0 = none
   void* epi_state;     // epilogue state array
+  int defer;           // 1: no finishing launch; the consuming kernel sums the partials
 };
 
 // ----------------------------------------------------------------------------

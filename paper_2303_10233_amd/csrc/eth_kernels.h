@@ -71,8 +71,12 @@ void launch_zero_boundary(const Geo& g, double* y, long long ld, int batch, hipS
 void launch_copy_boundary(const Geo& g, const double* b, double* x, long long ld, int batch,
                           hipStream_t st);
 // MINRES vector updates
+// partials (may be null): nb > 1 block partials of <K zhat_j, zhat_j> whose
+// finishing launch was deferred (RedCtx.defer); summed here with the delta
+// epilogue
 void launch_minres_v(long long n, const double* y, const double* v, double* vprev_io,
-                     long long ld, int batch, const MinresScalars* s, hipStream_t st);
+                     long long ld, int batch, MinresScalars* s, hipStream_t st,
+                     const double* partials = nullptr, int nb = 0);
 void launch_minres_wx(long long n, const double* z, double* wprev_io, const double* w,
                       double* x, long long ld, int batch, const MinresScalars* s, hipStream_t st);
 // v = b - y with boundary rows zeroed (initial residual)

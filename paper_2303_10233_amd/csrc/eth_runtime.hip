@@ -1336,10 +1336,13 @@ void Problem::minres_iteration(int batch, int parity) {
   double* w = kw[a];
   double* wp = kw[b];
   const Gate gate = active_gate();
+  // the delta reduction of the apply is finished inside the v update (one
+  // launch fewer on the iteration's critical path)
   RedCtx rd = red(saddle_blocks(g), 1, EPI_MINRES_DELTA, d_ms);
+  rd.defer = 1;
   const ClearFlag clear_wx{&d_ms[0].wx_todo, (int)(sizeof(MinresScalars) / sizeof(int))};
   launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st, clear_wx);
-  launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st);   // vp <- v_{j+1}
+  launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st, rd.partials, apply_blocks(g));   // vp <- v_{j+1}
   precond(vp, zn, ldw, batch, gate, true);
   RedCtx rg = red(dot_blocks(g.N), 1, EPI_MINRES_GAMMA, d_ms);
   launch_dot(g.N, zn, vp, ldw, batch, rg, gate, st);

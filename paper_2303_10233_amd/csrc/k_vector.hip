@@ -102,13 +102,64 @@ __global__ void k_residual_init(Geo g, const double* __restrict__ b, const doubl
   v[o] = bnd ? 0.0 : b[o] - y[o];
 }
 
-// v_{j+1} = vy*y - va*v_j - vb*v_{j-1}   (written over v_{j-1})
+constexpr int FIN_LOADS = 8;
+// total of nb block partials by one wavefront (every lane gets it)
+__device__ inline double finish_total(const double* __restrict__ p, int nb, int lane) {
+  double a = 0.0;
+  for (int base = 0; base < nb; base += kWave * FIN_LOADS) {
+    double v[FIN_LOADS];
+#pragma unroll
+    for (int j = 0; j < FIN_LOADS; ++j) {
+      const int i = base + j * kWave + lane;
+      v[j] = i < nb ? p[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < FIN_LOADS; ++j) a += v[j];
+  }
+  return wave_sum(a);
+}
+
+// v_{j+1} = vy*y - va*v_j - vb*v_{j-1}   (written over v_{j-1}).  With
+// nb > 1 the reduction of <K zhat_j, zhat_j> left its nb block partials
+// unfinished: every block sums them (the finishing kernel's order) and forms
+// the coefficients itself (the delta epilogue reads only fields no block
+// writes here), and block 0 stores delta, the coefficients and the history
+// entry, as the finishing launch would have.
 __global__ void k_minres_v(long long n, const double* __restrict__ y, const double* __restrict__ v,
-                           double* __restrict__ vp, long long ld, const MinresScalars* __restrict__ s) {
+                           double* __restrict__ vp, long long ld, MinresScalars* __restrict__ s,
+                           const double* __restrict__ partials, int nb) {
+  __shared__ double cf[3];
   const int rhs = blockIdx.y;
   const MinresScalars& S = s[rhs];
   if (!S.active) return;
-  const double vy = S.vy, va = S.va, vb = S.vb;
+  double vy, va, vb;
+  if (nb > 1) {
+    if (threadIdx.x < kWave) {
+      const double tot = finish_total(partials + (long long)rhs * nb, nb, threadIdx.x);
+      if (threadIdx.x == 0) {
+        MinresScalars loc = S;
+        if (blockIdx.x != 0) loc.hist_delta = nullptr;
+        minres_delta(loc, tot);
+        cf[0] = loc.vy;
+        cf[1] = loc.va;
+        cf[2] = loc.vb;
+        if (blockIdx.x == 0) {
+          s[rhs].delta = loc.delta;
+          s[rhs].vy = loc.vy;
+          s[rhs].va = loc.va;
+          s[rhs].vb = loc.vb;
+        }
+      }
+    }
+    __syncthreads();
+    vy = cf[0];
+    va = cf[1];
+    vb = cf[2];
+  } else {
+    vy = S.vy;
+    va = S.va;
+    vb = S.vb;
+  }
   const long long o = (long long)rhs * ld;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -163,27 +214,13 @@ __global__ void k_pressure_shift(Geo g, double* __restrict__ x, long long ld,
 // flight per lane and round, a fixed order), then a shuffle reduction; no LDS
 // and no barrier, since this launch sits between two dependent kernels of
 // the Krylov iteration.
-constexpr int FIN_LOADS = 8;
 __global__ __launch_bounds__(kWave) void k_reduce_finish(RedCtx rc, Gate gate) {
   const int rhs = blockIdx.x;
   if (gate.off(rhs)) return;
   const int lane = threadIdx.x;
   double tot[kMaxRedVals];
-  for (int k = 0; k < rc.nvals; ++k) {
-    const double* p = rc.partials + ((long long)rhs * rc.nvals + k) * rc.nblocks;
-    double a = 0.0;
-    for (int base = 0; base < rc.nblocks; base += kWave * FIN_LOADS) {
-      double v[FIN_LOADS];
-#pragma unroll
-      for (int j = 0; j < FIN_LOADS; ++j) {
-        const int i = base + j * kWave + lane;
-        v[j] = i < rc.nblocks ? p[i] : 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < FIN_LOADS; ++j) a += v[j];
-    }
-    tot[k] = wave_sum(a);
-  }
+  for (int k = 0; k < rc.nvals; ++k)
+    tot[k] = finish_total(rc.partials + ((long long)rhs * rc.nvals + k) * rc.nblocks, rc.nblocks, lane);
   if (lane == 0) {
     if (rc.result)
       for (int k = 0; k < rc.nvals; ++k) rc.result[(long long)rhs * rc.nvals + k] = tot[k];
@@ -196,7 +233,7 @@ inline unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1)
 }  // namespace
 
 void launch_reduce_finish(const RedCtx& rc, int batch, Gate gate, hipStream_t st) {
-  if (rc.nblocks <= 1) return;
+  if (rc.nblocks <= 1 || rc.defer) return;
   hipLaunchKernelGGL(k_reduce_finish, dim3(batch), dim3(kWave), 0, st, rc, gate);
   ETH_LAUNCH_CHECK();
 }
@@ -265,9 +302,10 @@ static unsigned update_blocks(long long n) {
 }
 
 void launch_minres_v(long long n, const double* y, const double* v, double* vprev_io,
-                     long long ld, int batch, const MinresScalars* s, hipStream_t st) {
+                     long long ld, int batch, MinresScalars* s, hipStream_t st, const double* partials,
+                     int nb) {
   hipLaunchKernelGGL(k_minres_v, dim3(update_blocks(n), batch), dim3(256), 0, st, n, y, v,
-                     vprev_io, ld, s);
+                     vprev_io, ld, s, partials, partials ? nb : 0);
   ETH_LAUNCH_CHECK();
 }
 
