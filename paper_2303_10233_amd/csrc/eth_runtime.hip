@@ -491,6 +491,7 @@ struct Problem {
   std::vector<int> check_rhs(const double* b, long long ld, int batch, bool consistency);
   double mq_sign = 1.0;              // -1 under ETH_DEBUG_NEGATE_MQ (indefinite preconditioner)
   bool fused_smooth = true;          // V(2,2) smoothing fused into restriction / correction launches
+  bool fold_delta = true;            // the delta reduction finished inside the v update (ETH_DEBUG_FOLD_DELTA=0: separate launch)
   hipEvent_t ev_poll = nullptr;
   // enqueue: also the first chunk of iterations (a joint batch graph runs
   // the iterations of every member itself)
@@ -517,6 +518,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   PhaseRange range("eth_setup");
   d = desc;
   if (const char* e = std::getenv("ETH_DEBUG_NAN_FILL")) nan_fill = (e[0] == '1');
+  if (const char* e = std::getenv("ETH_DEBUG_FOLD_DELTA")) fold_delta = (e[0] != '0');
   if (d.n < 2) throw std::invalid_argument("n must be >= 2");
   if (!(d.x1 > d.x0) || !(d.y1 > d.y0)) throw std::invalid_argument("empty domain");
   if (std::fabs((d.x1 - d.x0) - (d.y1 - d.y0)) > 1e-12 * (d.x1 - d.x0))
@@ -1339,10 +1341,11 @@ void Problem::minres_iteration(int batch, int parity) {
   // the delta reduction of the apply is finished inside the v update (one
   // launch fewer on the iteration's critical path)
   RedCtx rd = red(saddle_blocks(g), 1, EPI_MINRES_DELTA, d_ms);
-  rd.defer = 1;
+  rd.defer = fold_delta ? 1 : 0;
   const ClearFlag clear_wx{&d_ms[0].wx_todo, (int)(sizeof(MinresScalars) / sizeof(int))};
   launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st, clear_wx);
-  launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st, rd.partials, apply_blocks(g));   // vp <- v_{j+1}
+  launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st, fold_delta ? rd.partials : nullptr,
+                  apply_blocks(g));   // vp <- v_{j+1}
   precond(vp, zn, ldw, batch, gate, true);
   RedCtx rg = red(dot_blocks(g.N), 1, EPI_MINRES_GAMMA, d_ms);
   launch_dot(g.N, zn, vp, ldw, batch, rg, gate, st);

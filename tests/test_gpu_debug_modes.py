@@ -63,3 +63,15 @@ def test_nan_filled_workspaces_change_nothing(case, monkeypatch):
     assert it0 == it1
     assert bool(torch.isfinite(x1).all())
     assert torch.equal(x0, x1)
+
+
+@pytest.mark.parametrize("prec", [eth.MIXED, eth.FP64])
+def test_delta_finished_in_the_v_update_changes_nothing(prec, monkeypatch):
+    """The MINRES delta reduction finished inside the v update gives the
+    iterates of the separate finishing launch bit for bit."""
+    out = []
+    for fold in ("1", "0"):
+        monkeypatch.setenv("ETH_DEBUG_FOLD_DELTA", fold)
+        out.append(_stokes(prec))
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
