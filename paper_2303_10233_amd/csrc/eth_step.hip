@@ -107,6 +107,7 @@ struct StepProblem {
   std::vector<void*> owned;
   // device operators
   Sell K, Q1, F1, MQ;
+  Sell Bt;                           // B^T on the free velocity rows (2 n_v x n_p): the preconditioners' B^T z_p
   std::vector<Sell> F, P, R, Ap, Pq, Rq;
   double* Finv = nullptr;
   double* Apinv = nullptr;
@@ -350,6 +351,24 @@ void StepProblem::setup(const eth_step_desc& desc) {
   const StepMesh& g = ms[0];
   // fixed operators
   B = step_assemble_B(g, el[0]);
+  {
+    // the velocity rows of K restricted to its pressure columns, entries in
+    // K's order (so B^T z_p here has the bits of K [0; z_p])
+    const Csr T = csr_transpose(B);   // 2 n_v x n_p
+    Csr Bv;
+    Bv.rows = T.rows;
+    Bv.cols = T.cols;
+    Bv.ptr.assign(T.rows + 1, 0);
+    for (int r = 0; r < T.rows; ++r) {
+      if (!g.dirichlet[r % g.nv])
+        for (int k = T.ptr[r]; k < T.ptr[r + 1]; ++k) {
+          Bv.col.push_back(T.col[k]);
+          Bv.val.push_back(T.val[k]);
+        }
+      Bv.ptr[r + 1] = (int)Bv.col.size();
+    }
+    upload(Bt, Bv, false, false);
+  }
   upload(Q1, step_assemble_Q1(g, el[0]), mixed, true);
   F.resize(L);
   P.resize(L > 1 ? L - 1 : 0);
@@ -615,12 +634,11 @@ void StepProblem::pcd(const double* r, double* z, const int* gate) {
   // F_1 q, then A_p^{-1}
   launch_sell<T, T>(F1, 0, q[cur], 0, (const T*)nullptr, 0, static_cast<T*>(qb[0]), 0, 1, 0.0, 0.0, 0, gate, st);
   const int c = cycle_Ap<T>(0, gate);
-  // z = [0_u; -x; 0]
-  launch_gm_zero_range(z, 0, 0, nv2, 1, gs, st);
+  // z_p = [-x; 0] (z_u is written by the V-cycle below)
   launch_vcombine<T, double>(nk_, -1.0, static_cast<const T*>(qx[0][c]), 0.0, nullptr, z + nv2, gate, st);
   launch_gm_zero_range(z, 0, (long long)nv2 + nk_, n0(), 1, gs, st);
   // z_u = F^{-1}(r_u - B_1^T z_p)
-  apply(z, kw, gate);
+  launch_sell<double, double>(Bt, 0, z + nv2, 0, nullptr, 0, kw, 0, 1, 0.0, 0.0, 0, gate, st);
   vcycle_F<T>(r, kw, z, gate);
 }
 
@@ -661,9 +679,8 @@ void StepProblem::m1(const double* r, double* z, const int* gate) {
   const GmresScalars* gs = gate ? d_gm : nullptr;
   launch_permute<double, T>(np, mq_perm, false, 1.0, r + nv2, static_cast<T*>(mr), gate, st);
   mq_solve<T>(gate);
-  launch_gm_zero_range(z, 0, 0, nv2, 1, gs, st);
   launch_permute<T, double>(np, mq_perm, true, -d.nu, static_cast<const T*>(mxx), z + nv2, gate, st);
-  apply(z, kw, gate);
+  launch_sell<double, double>(Bt, 0, z + nv2, 0, nullptr, 0, kw, 0, 1, 0.0, 0.0, 0, gate, st);
   vcycle_F<T>(r, kw, z, gate);
 }
 
