@@ -102,7 +102,7 @@ typedef struct {
   int32_t pcd_q1_steps;      /* Chebyshev-Jacobi steps for Q_1^{-1} in PCD (10)     */
   int32_t gmres_restart;     /* largest FGMRES restart length, <= 63 (50)          */
   int32_t mq_tile;           /* ETH_MQ_CHEB_SGS: Q1 nodes per side of the blocks of
-                                the fused Chebyshev step, 16, 24, 32 or 64 (64
+                                the fused Chebyshev step, 8, 16, 24, 32 or 64 (64
                                 with ETH_MIXED only); 0: the fastest, timed at
                                 setup                                           */
   int32_t mq_fuse_steps;     /* Chebyshev steps per launch, 1 or 2 (2 needs tile

@@ -549,8 +549,9 @@ void Problem::setup(const eth_problem_desc& desc) {
   if (d.pcd_q1_steps <= 0) d.pcd_q1_steps = 10;
   if (d.gmres_restart <= 0) d.gmres_restart = 50;
   if (d.gmres_restart > 63) throw std::invalid_argument("gmres_restart must be <= 63");
-  if (d.mq_tile != 0 && d.mq_tile != 16 && d.mq_tile != 24 && d.mq_tile != 32 && d.mq_tile != 64)
-    throw std::invalid_argument("mq_tile must be 0, 16, 24, 32 or 64");
+  if (d.mq_tile != 0 && d.mq_tile != 8 && d.mq_tile != 16 && d.mq_tile != 24 && d.mq_tile != 32 &&
+      d.mq_tile != 64)
+    throw std::invalid_argument("mq_tile must be 0, 8, 16, 24, 32 or 64");
   if (d.mq_tile == 64 && d.precision != ETH_MIXED)
     throw std::invalid_argument("mq_tile 64 needs the FP32 preconditioner");
   if (d.mq_fuse_steps < 0 || d.mq_fuse_steps > 2) throw std::invalid_argument("mq_fuse_steps must be 0, 1 or 2");
@@ -855,7 +856,7 @@ Problem::MqVariant Problem::cached_mq_variant(int batch) {
   std::string v;
   MqVariant r;
   if (TuneCache::get(k.str(), v) && std::sscanf(v.c_str(), "%dx%d", &r.tile, &r.steps) == 2 &&
-      (r.tile == 16 || r.tile == 24 || r.tile == 32 || (r.tile == 64 && mixed)) && (r.steps == 1 || r.steps == 2)) {
+      (r.tile == 8 || r.tile == 16 || r.tile == 24 || r.tile == 32 || (r.tile == 64 && mixed)) && (r.steps == 1 || r.steps == 2)) {
     ++tuned_cached;
     return r;
   }
@@ -951,7 +952,7 @@ Problem::MqVariant Problem::tune_mq_variant(int batch) {
   // favour the later ones
   std::vector<MqVariant> cands;
   const int fs = d.mq_fuse_steps;
-  for (int t : {16, 24, 32, 64}) {
+  for (int t : {8, 16, 24, 32, 64}) {
     if (t == 64 && !mixed) continue;
     if (fs != 2) cands.push_back(MqVariant{t, 1});
     if ((t == 16 || t == 24) && fs != 1 && d.mq_steps >= 2 && mixed) cands.push_back(MqVariant{t, 2});

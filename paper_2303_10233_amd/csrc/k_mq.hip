@@ -254,7 +254,7 @@ __global__ void k_mq_project_out(Geo g, const T* __restrict__ z, double* __restr
 // first combination is formed on the whole region (z_k and d held in
 // registers per staged node), the second sweep starts from it, and the
 // owned part is exact after eighteen passes.
-// The tile side TQ (16, 24, 32 or 64) and ST are chosen per problem by timing the
+// The tile side TQ (8, 16, 24, 32 or 64) and ST are chosen per problem by timing the
 // candidates at set-up: small meshes want many blocks, large meshes less
 // halo (the redundancy is ((TQ + 2 HALO) / TQ)^2 per launch).
 // Node updates share q1_gs_update / p0_gs_update with the per-colour kernel,
@@ -759,7 +759,7 @@ void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, const T* di
   if (tile == 64 && sizeof(T) != 4) throw std::invalid_argument("M_Q tile 64 needs the FP32 preconditioner");
   if (steps == 2 && ((tile != 16 && tile != 24) || din == dout))
     throw std::invalid_argument("two M_Q steps per launch need 16 x 16 or 24 x 24 tiles and separate d arrays");
-  const int tq = (tile == 16 || tile == 24 || tile == 64) ? tile : 32;
+  const int tq = (tile == 8 || tile == 16 || tile == 24 || tile == 64) ? tile : 32;
   const MqSource s = src ? *src : MqSource{};
   const MqSink k = sink ? *sink : MqSink{};
 #define ETH_MQF(TQ, ST)                                                                                \
@@ -775,6 +775,8 @@ void launch_mq_cheb_fused(const Geo& g, T* r, const T* zin, T* zout, const T* di
     } else {
       throw std::invalid_argument("two M_Q steps per launch need the FP32 preconditioner");
     }
+  } else if (tq == 8) {
+    ETH_MQF(8, 1);
   } else if (tq == 16) {
     ETH_MQF(16, 1);
   } else if (tq == 24) {

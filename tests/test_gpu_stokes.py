@@ -257,7 +257,7 @@ def test_fused_cheb_sgs_step_equals_per_colour_passes(n, prec, monkeypatch):
     r = uniform_vector(m.N, 3 + n)
     r[: 2 * m.nv][System(m).vel_bnd] = 0.0
     o = 2 * m.nv
-    tiles = [16, 24, 32] + ([64] if prec == eth.MIXED else [])
+    tiles = [8, 16, 24, 32] + ([64] if prec == eth.MIXED else [])
     z_fused = {}
     for tile in tiles:
         print(f"[fused mq] n={n} prec={prec} tile={tile}", flush=True)
@@ -336,7 +336,7 @@ def test_timed_variant_solve_equals_forced_variant(prec):
     n = 64
     A = eth.Problem(n, precision=prec)
     tile, steps, tile_hi, steps_hi = A.mq_variant()
-    assert (tile, steps) in [(16, 1), (24, 1), (32, 1), (16, 2), (24, 2), (64, 1)]
+    assert (tile, steps) in [(8, 1), (16, 1), (24, 1), (32, 1), (16, 2), (24, 2), (64, 1)]
     assert steps == 1 or (prec == eth.MIXED and tile in (16, 24))
     F = eth.Problem(n, precision=prec, mq_tile=tile, mq_fuse_steps=steps)
     b = A.assemble_rhs()
