@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["k_saddle.hip", "k_vector.hip", "k_gmg.hip", "k_mq.hip", "k_oseen.hip", "k_gmres.hip", "k_adjoint.hip", "k_apply.hip", "k_schur.hip", "k_dense.hip",
            "eth_runtime.hip", "eth_noalloc.hip",
-           "k_sparse.hip", "eth_step_asm.hip", "eth_step.hip"]
+           "k_sparse.hip", "k_step_mq.hip", "eth_step_asm.hip", "eth_step.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

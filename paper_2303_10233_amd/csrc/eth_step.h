@@ -166,6 +166,22 @@ template <typename T, typename V>
 void launch_ell_colour(const Ell& E, const T* b, T* x, const int* gate, hipStream_t st);
 template <typename T, typename V>
 void launch_ell_middle(const Ell& E3, const Ell& E4, const T* b, T* x, const int* gate, hipStream_t st);
+// The pressure-mass solve on the bounding box of the step (k_step_mq.hip):
+// Q1 node (c, d) at d (ex + 1) + c, then element (e, f) at
+// (ex + 1)(ey + 1) + f ex + e; the elements e < hx, f < hy are absent.
+struct StepBox {
+  int ex = 0, ey = 0, hx = 0, hy = 0;
+  double h = 0.0;
+  long long size() const { return (long long)(ex + 1) * (ey + 1) + (long long)ex * ey; }
+};
+// blocks of one launch with tile side `tile`
+int step_mq_tiles(const StepBox& b, int tile);
+// one Chebyshev step of the multicolour SGS semi-iteration on M_Q in one
+// launch (tile 8 or 16 Q1 nodes per side of a block): from z_k = zin (not
+// read when first) to z_{k+1} = zout, direction d updated in place
+template <typename T>
+void launch_step_mq_fused(const StepBox& b, int tile, const T* r, const T* zin, T* zout, T* d, double a, double bc,
+                          int first, const int* gate, hipStream_t st);
 // gather y[i] = a x[idx[i]] or scatter y[idx[i]] = a x[i], with type conversion
 template <typename Ti, typename To>
 void launch_permute(int n, const int* idx, bool scatter, double a, const Ti* x, To* y, const int* gate,

@@ -146,6 +146,16 @@ struct StepProblem {
   ~StepProblem();
   bool nan_fill = false;   // ETH_DEBUG_NAN_FILL=1: workspaces start as NaN
   bool sgs_split = false;  // ETH_DEBUG_UNFUSED_MQ=1: colours 3, 4, 3 as three launches
+  // M_Q solved on the bounding box of the step, one launch per Chebyshev
+  // step (ETH_DEBUG_STEP_MQ_ELL=1: the colour-ordered sparse sweep, seven
+  // launches per step); tile side 8 or 16 (ETH_STEP_MQ_TILE), by default 16
+  // from 128 blocks on (measured: 8 faster at m = 32, 16 at m = 64 and 128)
+  bool mq_box = true;
+  int mq_box_tile = 16;
+  StepBox box;
+  int* box_idx = nullptr;            // pressure index -> box entry
+  void *bx_r = nullptr, *bx_d = nullptr;
+  void* bx_z[2] = {nullptr, nullptr};
   template <typename X>
   X* alloc(size_t n) {
     void* p = nullptr;
@@ -180,6 +190,8 @@ struct StepProblem {
   void m1(const double* r, double* z, const int* gate);
   template <typename T>
   void mq_solve(const int* gate);   // mr (projected) -> mxx (projected)
+  template <typename T>
+  void mq_solve_box(const int* gate);   // the same on the bounding box
   void precond(int kind, const double* r, double* z, const int* gate) {
     if (mixed) kind == 2 ? pcd<float>(r, z, gate) : m1<float>(r, z, gate);
     else kind == 2 ? pcd<double>(r, z, gate) : m1<double>(r, z, gate);
@@ -314,6 +326,7 @@ void StepProblem::setup(const eth_step_desc& desc) {
   d = desc;
   if (const char* e = std::getenv("ETH_DEBUG_NAN_FILL")) nan_fill = (e[0] == '1');
   if (const char* e = std::getenv("ETH_DEBUG_UNFUSED_MQ")) sgs_split = (e[0] == '1');
+  if (const char* e = std::getenv("ETH_DEBUG_STEP_MQ_ELL")) mq_box = (e[0] != '1');
   if (d.m < 1) throw std::invalid_argument("m must be >= 1");
   if (d.length == 0) d.length = 5;
   if (d.length < 1) throw std::invalid_argument("length must be >= 1");
@@ -450,6 +463,42 @@ void StepProblem::setup(const eth_step_desc& desc) {
     ETH_HIP(hipMemcpy(mq_colour, col.data(), col.size(), hipMemcpyHostToDevice));
     mq_perm = alloc<int>(perm.size());
     ETH_HIP(hipMemcpy(mq_perm, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice));
+  }
+  // the bounding box of the pressure-mass solve: the absent elements must
+  // be the corner e < hx, f < hy
+  {
+    box.ex = g.ex;
+    box.ey = g.ey;
+    box.h = g.h;
+    int hx = 0, hy = 0;
+    while (hx < g.ex && !g.elem_act[hx]) ++hx;
+    while (hy < g.ey && !g.elem_act[(size_t)hy * g.ex]) ++hy;
+    box.hx = hx;
+    box.hy = hy;
+    for (int f = 0; f < g.ey; ++f)
+      for (int e = 0; e < g.ex; ++e)
+        if ((g.elem_act[(size_t)f * g.ex + e] != 0) == (e < hx && f < hy))
+          throw std::logic_error("step mesh: the absent elements are not a corner of the box");
+    if (mq_box) {
+      std::vector<int> bi((size_t)g.nk + g.n0);
+      const long long nq = (long long)(g.ex + 1) * (g.ey + 1);
+      for (int k = 0; k < g.nk; ++k) bi[k] = g.q1_J[k] * (g.ex + 1) + g.q1_I[k];
+      for (int e = 0; e < g.n0; ++e) bi[(size_t)g.nk + e] = (int)(nq + (long long)g.el_y[e] * g.ex + g.el_x[e]);
+      box_idx = alloc<int>(bi.size());
+      ETH_HIP(hipMemcpy(box_idx, bi.data(), sizeof(int) * bi.size(), hipMemcpyHostToDevice));
+      // absent entries are never written: zero them once
+      const size_t bytes = (size_t)box.size() * (mixed ? sizeof(float) : sizeof(double));
+      for (void** p : {&bx_r, &bx_d, &bx_z[0], &bx_z[1]}) {
+        *p = allocT((size_t)box.size());
+        ETH_HIP(hipMemset(*p, 0, bytes));
+      }
+      mq_box_tile = step_mq_tiles(box, 16) >= 128 ? 16 : 8;
+      if (const char* e = std::getenv("ETH_STEP_MQ_TILE")) {
+        const int t = std::atoi(e);
+        if (t != 8 && t != 16) throw std::invalid_argument("ETH_STEP_MQ_TILE must be 8 or 16");
+        mq_box_tile = t;
+      }
+    }
   }
   {
     std::vector<int> di;
@@ -672,14 +721,36 @@ void StepProblem::mq_solve(const int* gate) {
   launch_frame_project(fpart, nk_, n0_, x, mixed, gate, st);
 }
 
+// The same solve on the bounding box: the projected input scattered to the
+// box, one fused launch per Chebyshev step, the result gathered back and
+// projected.
+template <typename T>
+void StepProblem::mq_solve_box(const int* gate) {
+  const int nk_ = nk(), n0_ = n0(), np = nk_ + n0_;
+  launch_frame_project(fpart, nk_, n0_, mr, mixed, gate, st);
+  launch_permute<T, T>(np, box_idx, true, 1.0, static_cast<const T*>(mr), static_cast<T*>(bx_r), gate, st);
+  for (int k = 0; k < d.mq_steps; ++k)
+    launch_step_mq_fused<T>(box, mq_box_tile, static_cast<const T*>(bx_r), static_cast<const T*>(bx_z[k & 1]),
+                            static_cast<T*>(bx_z[(k + 1) & 1]), static_cast<T*>(bx_d), mqa[k], mqb[k],
+                            k == 0 ? 1 : 0, gate, st);
+  launch_permute<T, T>(np, box_idx, false, 1.0, static_cast<const T*>(bx_z[d.mq_steps & 1]),
+                       static_cast<T*>(mxx), gate, st);
+  launch_frame_project(fpart, nk_, n0_, mxx, mixed, gate, st);
+}
+
 // stage-II preconditioner M_1
 template <typename T>
 void StepProblem::m1(const double* r, double* z, const int* gate) {
   const int nv2 = 2 * nv(), np = nk() + n0();
-  const GmresScalars* gs = gate ? d_gm : nullptr;
-  launch_permute<double, T>(np, mq_perm, false, 1.0, r + nv2, static_cast<T*>(mr), gate, st);
-  mq_solve<T>(gate);
-  launch_permute<T, double>(np, mq_perm, true, -d.nu, static_cast<const T*>(mxx), z + nv2, gate, st);
+  if (mq_box) {
+    launch_vcombine<double, T>(np, 1.0, r + nv2, 0.0, nullptr, static_cast<T*>(mr), gate, st);
+    mq_solve_box<T>(gate);
+    launch_vcombine<T, double>(np, -d.nu, static_cast<const T*>(mxx), 0.0, nullptr, z + nv2, gate, st);
+  } else {
+    launch_permute<double, T>(np, mq_perm, false, 1.0, r + nv2, static_cast<T*>(mr), gate, st);
+    mq_solve<T>(gate);
+    launch_permute<T, double>(np, mq_perm, true, -d.nu, static_cast<const T*>(mxx), z + nv2, gate, st);
+  }
   launch_sell<double, double>(Bt, 0, z + nv2, 0, nullptr, 0, kw, 0, 1, 0.0, 0.0, 0, gate, st);
   vcycle_F<T>(r, kw, z, gate);
 }

@@ -379,6 +379,8 @@ template void launch_permute<double, float>(int, const int*, bool, double, const
                                             hipStream_t);
 template void launch_permute<float, double>(int, const int*, bool, double, const float*, double*, const int*,
                                             hipStream_t);
+template void launch_permute<float, float>(int, const int*, bool, double, const float*, float*, const int*,
+                                           hipStream_t);
 template void launch_vcombine<double, double>(long long, double, const double*, double, const double*, double*,
                                               const int*, hipStream_t);
 template void launch_vcombine<double, float>(long long, double, const double*, double, const double*, float*,

@@ -181,11 +181,13 @@ def test_benchmark_mesh_conserves_mass(prec):
 @pytest.mark.parametrize("prec", [eth.MIXED, eth.FP64])
 def test_fused_sweep_middle_equals_one_launch_per_colour(prec, monkeypatch):
     """The colour-3 / element / colour-3 passes of the M_Q sweep in one
-    launch give bit for bit the three separate passes."""
+    launch give bit for bit the three separate passes (the sparse,
+    colour-ordered form of the pressure-mass solve)."""
     M = StepMesh(16)
     r = uniform_vector(M.N, 77)
     r[: 2 * M.nv][np.concatenate([M.boundary_q2()] * 2)] = 0.0
     w = stokes_start(StepMesh(16), NU)[: 2 * M.nv]
+    monkeypatch.setenv("ETH_DEBUG_STEP_MQ_ELL", "1")
     out = []
     for split in ("0", "1"):
         monkeypatch.setenv("ETH_DEBUG_UNFUSED_MQ", split)
@@ -247,3 +249,30 @@ def test_solve_rejects_inconsistent_and_non_finite_rhs():
     with pytest.raises(eth.EthError) as e:
         P.solve(bad)
     assert e.value.status == eth.EINVAL
+
+
+@pytest.mark.parametrize("m,channel,tile", [(4, False, 8), (8, False, 8), (8, False, 16), (12, False, 16),
+                                            (16, False, 8), (6, True, 8), (10, True, 16)])
+@pytest.mark.parametrize("prec,tol", [(eth.FP64, 1e-12), (eth.MIXED, 5e-5)])
+def test_box_pressure_solve_matches_sparse_sweep(m, channel, tile, prec, tol, monkeypatch):
+    """M_1 with the pressure-mass solve on the bounding box (one fused launch
+    per Chebyshev step, absent corner elements and nodes masked) agrees with
+    the colour-ordered sparse sweep (the same Chebyshev-SGS in another
+    rounding order): tiles of 8 and 16, meshes of one tile, several tiles
+    and ragged last tiles, the step and the channel."""
+    print(f"[step box M_Q] m={m} channel={channel} tile={tile} prec={prec}", flush=True)
+    M = StepMesh(m, channel=channel)
+    w = uniform_vector(2 * M.nv, 90 + m)
+    r = uniform_vector(M.N, 91 + m)
+    r[: 2 * M.nv][np.concatenate([M.boundary_q2()] * 2)] = 0.0
+    out = []
+    for ell in ("0", "1"):
+        monkeypatch.setenv("ETH_DEBUG_STEP_MQ_ELL", ell)
+        monkeypatch.setenv("ETH_STEP_MQ_TILE", str(tile))
+        P = _problem(m, w, prec, channel=channel)
+        out.append(_np(P.apply_preconditioner(_t(r), which=1)))
+        P.close()
+    o = 2 * M.nv
+    assert np.all(np.isfinite(out[0]))
+    assert rel_err(out[0][o:], out[1][o:]) < tol
+    assert rel_err(out[0], out[1]) < tol
