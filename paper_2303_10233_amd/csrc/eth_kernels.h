@@ -18,6 +18,7 @@ inline Gate no_gate() { return Gate{nullptr, 0}; }
 struct ClearFlag {
   int* p;
   int stride;  // in ints
+  // for grids whose right-hand side r is blockIdx.z
   __device__ void apply(int r) const {
     if (p && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0)
       p[(long long)r * stride] = 0;
@@ -54,8 +55,11 @@ void launch_dirichlet_lid(const Geo& g, double lid_u, int corner_mode, double* u
 // block order, result and epilogue; nothing to do for a single block.  Every
 // launcher of a reducing kernel calls it right after the kernel.
 void launch_reduce_finish(const RedCtx& rc, int batch, Gate gate, hipStream_t st);
+// (clear: a flag reset by the first block before the gate is read)
 void launch_dot(long long n, const double* x, const double* y, long long ld, int batch,
-                const RedCtx& rc, Gate gate, hipStream_t st);
+                const RedCtx& rc, Gate gate, hipStream_t st, ClearFlag clear = no_clear());
+// flag of every right-hand side = 0 (one small launch)
+void launch_clear_flag(const ClearFlag& f, int batch, hipStream_t st);
 int dot_blocks(long long n);
 // y = a*x + b*y on [0,n)
 void launch_axpby(long long n, double a, const double* x, double b, double* y, long long ld,
@@ -74,9 +78,17 @@ void launch_copy_boundary(const Geo& g, const double* b, double* x, long long ld
 // partials (may be null): nb > 1 block partials of <K zhat_j, zhat_j> whose
 // finishing launch was deferred (RedCtx.defer); summed here with the delta
 // epilogue
+// wx (z null: none): the previous iteration's w/x update made in the same
+// pass while its wx_todo flag is set (see launch_minres_wx)
+struct MinresWx {
+  const double* z = nullptr;
+  double* wprev_io = nullptr;
+  const double* w = nullptr;
+  double* x = nullptr;
+};
 void launch_minres_v(long long n, const double* y, const double* v, double* vprev_io,
                      long long ld, int batch, MinresScalars* s, hipStream_t st,
-                     const double* partials = nullptr, int nb = 0);
+                     const double* partials = nullptr, int nb = 0, MinresWx wx = MinresWx{});
 void launch_minres_wx(long long n, const double* z, double* wprev_io, const double* w,
                       double* x, long long ld, int batch, const MinresScalars* s, hipStream_t st);
 // v = b - y with boundary rows zeroed (initial residual)

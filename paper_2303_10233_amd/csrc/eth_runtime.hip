@@ -492,6 +492,7 @@ struct Problem {
   double mq_sign = 1.0;              // -1 under ETH_DEBUG_NEGATE_MQ (indefinite preconditioner)
   bool fused_smooth = true;          // V(2,2) smoothing fused into restriction / correction launches
   bool fold_delta = true;            // the delta reduction finished inside the v update (ETH_DEBUG_FOLD_DELTA=0: separate launch)
+  bool fold_wx = true;               // the w/x update made inside the next v update (ETH_DEBUG_FOLD_WX=0: own launch)
   hipEvent_t ev_poll = nullptr;
   // enqueue: also the first chunk of iterations (a joint batch graph runs
   // the iterations of every member itself)
@@ -505,6 +506,7 @@ struct Problem {
   bool minres_poll(MinresRun& R, bool block);
   int minres_finish(MinresRun& R, eth_solve_info* info);
   void minres_iteration(int batch, int parity);
+  void minres_flush_wx(int batch);
   int solve_minres(const eth_solve_opts& o, const double* b, double* x, int batch, long long ld,
                    eth_solve_info* info, bool adjoint = false);
   // Krylov RHS kb from b: boundary rows zeroed; for the adjoint also the
@@ -519,6 +521,7 @@ void Problem::setup(const eth_problem_desc& desc) {
   d = desc;
   if (const char* e = std::getenv("ETH_DEBUG_NAN_FILL")) nan_fill = (e[0] == '1');
   if (const char* e = std::getenv("ETH_DEBUG_FOLD_DELTA")) fold_delta = (e[0] != '0');
+  if (const char* e = std::getenv("ETH_DEBUG_FOLD_WX")) fold_wx = (e[0] != '0');
   if (d.n < 2) throw std::invalid_argument("n must be >= 2");
   if (!(d.x1 > d.x0) || !(d.y1 > d.y0)) throw std::invalid_argument("empty domain");
   if (std::fabs((d.x1 - d.x0) - (d.y1 - d.y0)) > 1e-12 * (d.x1 - d.x0))
@@ -1330,6 +1333,13 @@ void Problem::precond(const double* r, double* z, long long ld, int batch, Gate 
 // ---------------------------------------------------------------- MINRES
 // One iteration of alg:minres.  parity selects which buffers hold
 // (v_j, v_{j-1}), (zhat_j, zhat_{j+1}) and (w_j, w_{j-1}).
+//
+// The w/x update that closes iteration j is made by the v update of
+// iteration j + 1 (one launch fewer per iteration; the update reads only
+// zhat_j, w_j, w_{j-1}, x and the Givens coefficients, which nothing in
+// between touches).  Its pending flag (wx_todo, set by the Givens step) is
+// then cleared by the gamma dot instead of the apply, and the update of the
+// last iteration of a run is made by minres_flush_wx.
 void Problem::minres_iteration(int batch, int parity) {
   const int a = parity, b = 1 - parity;
   double* v = kv[a];
@@ -1344,13 +1354,25 @@ void Problem::minres_iteration(int batch, int parity) {
   RedCtx rd = red(saddle_blocks(g), 1, EPI_MINRES_DELTA, d_ms);
   rd.defer = fold_delta ? 1 : 0;
   const ClearFlag clear_wx{&d_ms[0].wx_todo, (int)(sizeof(MinresScalars) / sizeof(int))};
-  launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st, clear_wx);
+  launch_apply_stokes(g, d.nu, z, ky, ldw, batch, gate, &rd, st, fold_wx ? no_clear() : clear_wx);
+  // the previous iteration's buffers: its zhat is kz[b], its w kw[b], its
+  // w_{j-1} (overwritten by w_{j+1}) kw[a]
+  const MinresWx prev = fold_wx ? MinresWx{kz[b], kw[a], kw[b], kx} : MinresWx{};
   launch_minres_v(g.N, ky, v, vp, ldw, batch, d_ms, st, fold_delta ? rd.partials : nullptr,
-                  apply_blocks(g));   // vp <- v_{j+1}
+                  apply_blocks(g), prev);   // vp <- v_{j+1}
   precond(vp, zn, ldw, batch, gate, true);
   RedCtx rg = red(dot_blocks(g.N), 1, EPI_MINRES_GAMMA, d_ms);
-  launch_dot(g.N, zn, vp, ldw, batch, rg, gate, st);
-  launch_minres_wx(g.N, z, wp, w, kx, ldw, batch, d_ms, st);   // wp <- w_{j+1}
+  launch_dot(g.N, zn, vp, ldw, batch, rg, gate, st, fold_wx ? clear_wx : no_clear());
+  if (!fold_wx) launch_minres_wx(g.N, z, wp, w, kx, ldw, batch, d_ms, st);   // wp <- w_{j+1}
+}
+
+// The w/x update of the last iteration of a run of minres_iteration calls
+// (an even count, so its parity is 1), and its flag cleared, so that the
+// next run starts with nothing pending.
+void Problem::minres_flush_wx(int batch) {
+  if (!fold_wx) return;
+  launch_minres_wx(g.N, kz[1], kw[0], kw[1], kx, ldw, batch, d_ms, st);
+  launch_clear_flag(ClearFlag{&d_ms[0].wx_todo, (int)(sizeof(MinresScalars) / sizeof(int))}, batch, st);
 }
 
 // The captured graph of `iters` (even) MINRES iterations for `batch`
@@ -1376,6 +1398,7 @@ void Problem::run_iterations(int batch, int count, bool use_graph) {
   // `count` is even: the buffer roles repeat every two iterations
   if (!use_graph) {
     for (int i = 0; i < count; ++i) minres_iteration(batch, i & 1);
+    minres_flush_wx(batch);
     return;
   }
   // long chunks replay a graph of graph_iters iterations, the rest one of two
@@ -1389,6 +1412,7 @@ void Problem::run_iterations(int batch, int count, bool use_graph) {
       hipGraphExec_t g2 = iteration_graph(batch, 2);
       for (; left > 0; left -= 2) ETH_HIP(hipGraphLaunch(g2, s));
     }
+    minres_flush_wx(batch);   // on st == s
   };
   if (own_stream) {
     // a ragged-batch member captures and replays on its own stream: one

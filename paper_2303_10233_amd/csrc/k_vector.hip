@@ -13,9 +13,11 @@ constexpr int kVecBlocksMax = 512;    // grid-stride cap per RHS for reductions
 
 __global__ __launch_bounds__(NT) void k_dot(long long n, const double* __restrict__ x,
                                             const double* __restrict__ y, long long ld,
-                                            RedCtx rc, Gate gate) {
+                                            RedCtx rc, Gate gate, ClearFlag clear) {
   __shared__ double sred[NT / 64];
   const int rhs = blockIdx.y;
+  // (the first block of each right-hand side: here the RHS is blockIdx.y)
+  if (clear.p && blockIdx.x == 0 && threadIdx.x == 0) clear.p[(long long)rhs * clear.stride] = 0;
   if (gate.off(rhs)) return;
   const double* xr = x + (long long)rhs * ld;
   const double* yr = y + (long long)rhs * ld;
@@ -125,13 +127,29 @@ __device__ inline double finish_total(const double* __restrict__ p, int nb, int 
 // the coefficients itself (the delta epilogue reads only fields no block
 // writes here), and block 0 stores delta, the coefficients and the history
 // entry, as the finishing launch would have.
+// With wx.z set, the same pass also makes the pending w/x update of the
+// previous iteration (k_minres_wx's arithmetic on the previous iteration's
+// buffers, while wx_todo is set, also once the solve has stopped).
 __global__ void k_minres_v(long long n, const double* __restrict__ y, const double* __restrict__ v,
                            double* __restrict__ vp, long long ld, MinresScalars* __restrict__ s,
-                           const double* __restrict__ partials, int nb) {
+                           const double* __restrict__ partials, int nb, MinresWx wx) {
   __shared__ double cf[3];
   const int rhs = blockIdx.y;
   const MinresScalars& S = s[rhs];
-  if (!S.active) return;
+  const bool do_v = S.active != 0;
+  const bool do_wx = wx.z != nullptr && S.wx_todo != 0;
+  if (!do_v && !do_wx) return;
+  const long long o = (long long)rhs * ld;
+  if (!do_v) {
+    const double cz = S.wz, cp = S.wp, cw = S.wc, cx = S.xc;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+      const double wn = cz * wx.z[o + i] - cp * wx.wprev_io[o + i] - cw * wx.w[o + i];
+      wx.wprev_io[o + i] = wn;
+      wx.x[o + i] += cx * wn;
+    }
+    return;
+  }
   double vy, va, vb;
   if (nb > 1) {
     if (threadIdx.x < kWave) {
@@ -160,10 +178,20 @@ __global__ void k_minres_v(long long n, const double* __restrict__ y, const doub
     va = S.va;
     vb = S.vb;
   }
-  const long long o = (long long)rhs * ld;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    vp[o + i] = vy * y[o + i] - va * v[o + i] - vb * vp[o + i];
+  if (do_wx) {
+    const double cz = S.wz, cp = S.wp, cw = S.wc, cx = S.xc;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+      vp[o + i] = vy * y[o + i] - va * v[o + i] - vb * vp[o + i];
+      const double wn = cz * wx.z[o + i] - cp * wx.wprev_io[o + i] - cw * wx.w[o + i];
+      wx.wprev_io[o + i] = wn;
+      wx.x[o + i] += cx * wn;
+    }
+  } else {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+      vp[o + i] = vy * y[o + i] - va * v[o + i] - vb * vp[o + i];
+  }
 }
 
 // w_{j+1} = wz*zhat_j - wp*w_{j-1} - wc*w_j (written over w_{j-1}); x += xc*w_{j+1}
@@ -183,6 +211,12 @@ __global__ void k_minres_wx(long long n, const double* __restrict__ z, double* _
     wp[o + i] = wn;
     x[o + i] += cx * wn;
   }
+}
+
+// flag of every right-hand side = 0
+__global__ void k_clear_flag(ClearFlag f, int batch) {
+  const int r = threadIdx.x;
+  if (r < batch) f.p[(long long)r * f.stride] = 0;
 }
 
 __global__ __launch_bounds__(NT) void k_pressure_sums(Geo g, const double* __restrict__ x,
@@ -246,8 +280,8 @@ int dot_blocks(long long n) {
 }
 
 void launch_dot(long long n, const double* x, const double* y, long long ld, int batch,
-                const RedCtx& rc, Gate gate, hipStream_t st) {
-  hipLaunchKernelGGL(k_dot, dim3(rc.nblocks, batch), dim3(NT), 0, st, n, x, y, ld, rc, gate);
+                const RedCtx& rc, Gate gate, hipStream_t st, ClearFlag clear) {
+  hipLaunchKernelGGL(k_dot, dim3(rc.nblocks, batch), dim3(NT), 0, st, n, x, y, ld, rc, gate, clear);
   ETH_LAUNCH_CHECK();
   launch_reduce_finish(rc, batch, gate, st);
 }
@@ -303,10 +337,20 @@ static unsigned update_blocks(long long n) {
 
 void launch_minres_v(long long n, const double* y, const double* v, double* vprev_io,
                      long long ld, int batch, MinresScalars* s, hipStream_t st, const double* partials,
-                     int nb) {
+                     int nb, MinresWx wx) {
   hipLaunchKernelGGL(k_minres_v, dim3(update_blocks(n), batch), dim3(256), 0, st, n, y, v,
-                     vprev_io, ld, s, partials, partials ? nb : 0);
+                     vprev_io, ld, s, partials, partials ? nb : 0, wx);
   ETH_LAUNCH_CHECK();
+}
+
+void launch_clear_flag(const ClearFlag& f, int batch, hipStream_t st) {
+  if (!f.p || batch < 1) return;
+  for (int r0 = 0; r0 < batch; r0 += 256) {
+    const int nb = batch - r0 < 256 ? batch - r0 : 256;
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(256), 0, st, ClearFlag{f.p + (long long)r0 * f.stride, f.stride},
+                       nb);
+    ETH_LAUNCH_CHECK();
+  }
 }
 
 void launch_minres_wx(long long n, const double* z, double* wprev_io, const double* w,

@@ -75,3 +75,30 @@ def test_delta_finished_in_the_v_update_changes_nothing(prec, monkeypatch):
         out.append(_stokes(prec))
     assert out[0][1] == out[1][1]
     assert torch.equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("prec", [eth.MIXED, eth.FP64])
+@pytest.mark.parametrize("graph", [True, False])
+def test_wx_update_folded_into_the_next_v_update_changes_nothing(prec, graph, monkeypatch):
+    """The MINRES w/x update made by the next iteration's v update (and by a
+    closing launch at the end of each run of iterations) gives the iterates
+    of its own launch bit for bit, eagerly and graph-replayed, with two
+    right-hand sides that stop at different iterations (the gated iterations
+    after the first one stops must make its last update exactly once)."""
+    from paper_2303_10233_amd.workloads import uniform_vector
+    print(f"[fold wx] prec={prec} graph={graph}", flush=True)
+    out = []
+    for fold in ("1", "0"):
+        monkeypatch.setenv("ETH_DEBUG_FOLD_WX", fold)
+        P = eth.Problem(64, precision=prec, max_batch=2)
+        b = P.empty(2)
+        b[0] = P.assemble_rhs()
+        y = torch.as_tensor(uniform_vector(P.N, 11), dtype=torch.float64, device="cuda:0")
+        b[1] = P.apply_operator(y)
+        x, info = P.solve(b, rtol=1e-8, maxit=500, use_graph=graph)
+        out.append((x.clone(), [i["iterations"] for i in info], [i["status"] for i in info]))
+        P.close()
+    assert out[0][2] == [eth.OK, eth.OK]
+    assert out[0][1][0] != out[0][1][1]
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
