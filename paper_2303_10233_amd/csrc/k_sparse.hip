@@ -5,6 +5,8 @@
 // of the vectors (T).
 #include "eth_step.h"
 
+#include <cstdlib>
+
 namespace eth {
 
 namespace {
@@ -40,7 +42,46 @@ __device__ __forceinline__ double row_dot(const SellView<V>& A, int row, const T
   return s;
 }
 
-template <typename T, typename V, int MODE>
+// the same row sums for two vectors x0, x1 from one read of the row's
+// entries (each sum in row_dot's order, so bit for bit row_dot's)
+template <typename T, typename V>
+__device__ __forceinline__ void row_dot2(const SellView<V>& A, int row, const T* __restrict__ x0,
+                                         const T* __restrict__ x1, double& s0, double& s1) {
+  const int slice = row >> 6, lane = row & 63;
+  const int beg = A.ptr[slice];
+  const int width = (A.ptr[slice + 1] - beg) >> 6;
+  const int* c = A.col + beg + lane;
+  const V* v = A.val + beg + lane;
+  double a = 0.0, e = 0.0;
+  int k = 0;
+  for (; k + 4 <= width; k += 4) {
+    const int c0 = c[64 * k], c1 = c[64 * (k + 1)], c2 = c[64 * (k + 2)], c3 = c[64 * (k + 3)];
+    const double v0 = (double)v[64 * k], v1 = (double)v[64 * (k + 1)], v2 = (double)v[64 * (k + 2)],
+                 v3 = (double)v[64 * (k + 3)];
+    const double p0 = (double)x0[c0], p1 = (double)x0[c1], p2 = (double)x0[c2], p3 = (double)x0[c3];
+    const double q0 = (double)x1[c0], q1 = (double)x1[c1], q2 = (double)x1[c2], q3 = (double)x1[c3];
+    a += v0 * p0;
+    a += v1 * p1;
+    a += v2 * p2;
+    a += v3 * p3;
+    e += v0 * q0;
+    e += v1 * q1;
+    e += v2 * q2;
+    e += v3 * q3;
+  }
+  for (; k < width; ++k) {
+    const double vk = (double)v[64 * k];
+    const int ck = c[64 * k];
+    a += vk * (double)x0[ck];
+    e += vk * (double)x1[ck];
+  }
+  s0 = a;
+  s1 = e;
+}
+
+// NV vectors per thread (1, or 2: the row's entries read once for a pair of
+// vectors, the pairs on blockIdx.y)
+template <typename T, typename V, int MODE, int NV>
 __global__ __launch_bounds__(NT) void k_sell(SellView<V> A, const T* __restrict__ x, long long sx,
                                               const T* __restrict__ b, long long sb, T* __restrict__ y,
                                               long long sy, double w, double alpha, int has_prev,
@@ -48,27 +89,36 @@ __global__ __launch_bounds__(NT) void k_sell(SellView<V> A, const T* __restrict_
   if (gated(gate)) return;
   const int row = blockIdx.x * NT + threadIdx.x;
   if (row >= A.rows) return;
-  const int vec = blockIdx.y;
-  const T* xv = x ? x + vec * sx : nullptr;
-  T* yv = y + vec * sy;
-  if constexpr (MODE == 0 || MODE == 1) {
-    const double s = row_dot(A, row, xv);
-    if constexpr (MODE == 0) yv[row] = (T)s;
-    else yv[row] = (T)((double)yv[row] + s);
+  const int vec0 = blockIdx.y * NV;
+  double s[NV];
+  if constexpr (NV == 2) {
+    if (x) row_dot2(A, row, x + vec0 * sx, x + (vec0 + 1) * sx, s[0], s[1]);
+    else s[0] = s[1] = 0.0;
   } else {
-    const T* bv = b + vec * sb;
-    const double s = xv ? row_dot(A, row, xv) : 0.0;
-    const double res = (double)bv[row] - s;
-    if constexpr (MODE == 2) {
-      yv[row] = (T)res;
+    s[0] = x ? row_dot(A, row, x + vec0 * sx) : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const int vec = vec0 + q;
+    const T* xv = x ? x + vec * sx : nullptr;
+    T* yv = y + vec * sy;
+    if constexpr (MODE == 0 || MODE == 1) {
+      if constexpr (MODE == 0) yv[row] = (T)s[q];
+      else yv[row] = (T)((double)yv[row] + s[q]);
     } else {
-      const double xc = xv ? (double)xv[row] : 0.0;
-      double xn = xc + w * (double)A.dinv[row] * res;
-      if constexpr (MODE == 4) {
-        if (has_prev == 1) xn += alpha * (xc - (double)yv[row]);
-        else if (has_prev == 2) xn += alpha * xc;
+      const T* bv = b + vec * sb;
+      const double res = (double)bv[row] - s[q];
+      if constexpr (MODE == 2) {
+        yv[row] = (T)res;
+      } else {
+        const double xc = xv ? (double)xv[row] : 0.0;
+        double xn = xc + w * (double)A.dinv[row] * res;
+        if constexpr (MODE == 4) {
+          if (has_prev == 1) xn += alpha * (xc - (double)yv[row]);
+          else if (has_prev == 2) xn += alpha * xc;
+        }
+        yv[row] = (T)xn;
       }
-      yv[row] = (T)xn;
     }
   }
 }
@@ -253,30 +303,38 @@ __global__ __launch_bounds__(NT) void k_frame_shift(int nk, int np, int nparts, 
 }
 
 unsigned nblk(long long n) { return (unsigned)((n + NT - 1) / NT); }
+// ETH_DEBUG_SELL_UNPAIRED=1: one vector per thread also for pairs
+bool sell_unpaired() {
+  const char* e = std::getenv("ETH_DEBUG_SELL_UNPAIRED");
+  return e && e[0] == '1';
+}
 }  // namespace
 
 template <typename T, typename V>
 void launch_sell(const Sell& A, int mode, const T* x, long long sx, const T* b, long long sb, T* y, long long sy,
                  int nvec, double w, double alpha, int has_prev, const int* gate, hipStream_t st) {
   const SellView<V> v = view<V>(A);
-  const dim3 grid(nblk(A.rows), nvec);
+  // pairs of vectors share one read of the matrix (the two velocity
+  // components of the F levels and transfers) where the matrix is large:
+  // measured 3-5 % faster step solves at m = 128, within 1 % at m = 64 and
+  // 2 % slower at m = 32 (half the blocks)
+  const bool pair = nvec % 2 == 0 && A.rows >= (1 << 17) && !sell_unpaired();
+  const dim3 grid(nblk(A.rows), pair ? nvec / 2 : nvec);
+#define ETH_SELL(M)                                                                                        \
+  if (pair)                                                                                                \
+    hipLaunchKernelGGL((k_sell<T, V, M, 2>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha,     \
+                       has_prev, gate);                                                                    \
+  else                                                                                                     \
+    hipLaunchKernelGGL((k_sell<T, V, M, 1>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha,     \
+                       has_prev, gate)
   switch (mode) {
-    case 0:
-      hipLaunchKernelGGL((k_sell<T, V, 0>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_sell<T, V, 1>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_sell<T, V, 2>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_sell<T, V, 3>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
-      break;
-    default:
-      hipLaunchKernelGGL((k_sell<T, V, 4>), grid, dim3(NT), 0, st, v, x, sx, b, sb, y, sy, w, alpha, has_prev, gate);
-      break;
+    case 0: ETH_SELL(0); break;
+    case 1: ETH_SELL(1); break;
+    case 2: ETH_SELL(2); break;
+    case 3: ETH_SELL(3); break;
+    default: ETH_SELL(4); break;
   }
+#undef ETH_SELL
   ETH_LAUNCH_CHECK();
 }
 
