@@ -281,10 +281,14 @@ def test_box_pressure_solve_matches_sparse_sweep(m, channel, tile, prec, tol, mo
 @pytest.mark.parametrize("prec", [eth.MIXED, eth.FP64])
 def test_paired_sparse_rows_change_nothing(prec, monkeypatch):
     """The sparse kernels read a matrix row once for both velocity
-    components (F smoothing, residual, transfers): both preconditioners and
-    a two-stage solve give the one-vector-per-thread results bit for bit."""
-    M = StepMesh(16)
-    w = stokes_start(M, NU)[: 2 * M.nv]
+    components on large matrices (F smoothing, residual and transfers of
+    the finest level at m = 64, 181 k rows): both preconditioners and 40
+    two-stage iterations give the one-vector-per-thread results bit for
+    bit."""
+    m = 64
+    print(f"[step paired rows] m={m} prec={prec}", flush=True)
+    M = StepMesh(m)
+    w = 0.5 * uniform_vector(2 * M.nv, 4)
     r = uniform_vector(M.N, 5)
     r[: 2 * M.nv][np.concatenate([M.boundary_q2()] * 2)] = 0.0
     rr = r.copy()
@@ -292,12 +296,13 @@ def test_paired_sparse_rows_change_nothing(prec, monkeypatch):
     out = []
     for unpaired in ("0", "1"):
         monkeypatch.setenv("ETH_DEBUG_SELL_UNPAIRED", unpaired)
-        P = _problem(16, w, prec)
+        P = _problem(m, w, prec)
         z1 = _np(P.apply_preconditioner(_t(r), which=1))
         z2 = _np(P.apply_preconditioner(_t(rr), which=2))
-        x, info = P.solve(P.rhs(), rtol=1e-8, maxit=2000)
+        x, info = P.solve(P.rhs(), rtol=1e-12, maxit=40, raise_on_error=False)
         out.append((z1, z2, _np(x), info["iterations"]))
         P.close()
+    assert np.all(np.isfinite(out[0][0])) and np.all(np.isfinite(out[0][2]))
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
     assert out[0][3] == out[1][3]
