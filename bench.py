@@ -638,7 +638,9 @@ def main():
     # launches of each kernel per MINRES iteration (mixed solver, finest level
     # for the multigrid kernels): V(2,2) with degree-2 Chebyshev = 1 pre-step
     # kernel + 2 post-step kernels on the finest level; 20 fused Chebyshev-SGS
-    # steps; 1 saddle apply, 1 dot, 1 v update, 1 w/x update.
+    # steps; 1 saddle apply, 1 dot, 1 v update, 1 w/x update (the last two
+    # run as one launch inside MINRES, the v update making the previous
+    # iteration's w/x update; timed here as two, with the same bytes).
     per_iter = {eth.K_SADDLE_APPLY: 1, eth.K_CHEB_STEP: 3, eth.K_RESTRICT: 1, eth.K_PROLONG: 1,
                 eth.K_MQ_CHEB_STEP: 20 // Pm.mq_variant()[1], eth.K_DOT: 1, eth.K_MINRES_V: 1,
                 eth.K_MINRES_WX: 1,
