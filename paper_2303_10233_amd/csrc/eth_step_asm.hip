@@ -307,6 +307,14 @@ Csr step_assemble_K(const StepMesh& g, const Csr& F, const Csr& B) {
   Csr K;
   K.rows = K.cols = (int)N;
   K.ptr.assign(N + 1, 0);
+  {
+    size_t nnz = 0;   // an upper bound: F and B^T rows of free nodes, B rows
+    for (int i = 0; i < nv; ++i)
+      if (!g.dirichlet[i]) nnz += 2 * (size_t)(F.ptr[i + 1] - F.ptr[i]);
+    nnz += 2 * B.col.size();
+    K.col.reserve(nnz);
+    K.val.reserve(nnz);
+  }
   for (int c = 0; c < 2; ++c)
     for (int i = 0; i < nv; ++i) {
       const int row = c * nv + i;
