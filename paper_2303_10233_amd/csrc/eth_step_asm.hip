@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <stdexcept>
+#include <thread>
 
 #include "eth_step.h"
 
@@ -255,32 +256,120 @@ void elem_nodes(const StepMesh& g, int e, int f, int vel[9], int q1[4], int& p0)
 }
 }  // namespace
 
-Csr step_assemble_F(const StepMesh& g, const StepElem& E, double nu, const double* wind, bool embed) {
-  RowBuilder rb(g.nv, g.nv);
+namespace {
+// the elements of every Q2 node in ascending order (CSR over the nodes)
+struct NodeElems {
+  std::vector<int> ptr, el;
+};
+NodeElems node_elements(const StepMesh& g) {
+  NodeElems ne;
+  ne.ptr.assign((size_t)g.nv + 1, 0);
+  int vel[9], q1[4], p0;
   for (int k = 0; k < g.n0; ++k) {
-    int vel[9], q1[4], p0;
     elem_nodes(g, g.el_x[k], g.el_y[k], vel, q1, p0);
-    double wx[9] = {0}, wy[9] = {0};
-    if (wind)
-      for (int m = 0; m < 9; ++m) {
-        wx[m] = wind[vel[m]];
-        wy[m] = wind[g.nv + vel[m]];
-      }
-    for (int i = 0; i < 9; ++i) {
-      if (embed && g.dirichlet[vel[i]]) continue;
+    for (int m = 0; m < 9; ++m) ne.ptr[(size_t)vel[m] + 1]++;
+  }
+  for (int i = 0; i < g.nv; ++i) ne.ptr[(size_t)i + 1] += ne.ptr[i];
+  ne.el.resize(ne.ptr[g.nv]);
+  std::vector<int> next(ne.ptr.begin(), ne.ptr.end() - 1);
+  for (int k = 0; k < g.n0; ++k) {
+    elem_nodes(g, g.el_x[k], g.el_y[k], vel, q1, p0);
+    for (int m = 0; m < 9; ++m) ne.el[next[vel[m]]++] = k;
+  }
+  return ne;
+}
+
+// body(r0, r1) over contiguous blocks of rows on up to 16 host threads
+// (one for small matrices); blocks are independent
+template <typename Body>
+void parallel_rows(int rows, Body&& body) {
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 16u));
+  if (rows < 8192) nt = 1;
+  if (nt == 1) {
+    body(0, rows);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int per = (rows + (int)nt - 1) / (int)nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int r0 = (int)t * per, r1 = std::min(rows, r0 + per);
+    if (r0 >= r1) break;
+    th.emplace_back([&body, r0, r1] { body(r0, r1); });
+  }
+  for (auto& x : th) x.join();
+}
+}  // namespace
+
+// F row by row: row i visits its elements in ascending order, so every entry
+// sums its element contributions in the order of an element-by-element
+// assembly; rows are filled on several host threads.
+Csr step_assemble_F(const StepMesh& g, const StepElem& E, double nu, const double* wind, bool embed) {
+  const NodeElems ne = node_elements(g);
+  Csr A;
+  A.rows = A.cols = g.nv;
+  A.ptr.assign((size_t)g.nv + 1, 0);
+  // row sizes first (a row's columns: the nodes of its elements, Dirichlet
+  // ones left out in the embedded form), then the values into place
+  std::vector<int> len(g.nv, 0);
+  auto row_entries = [&](int i, std::vector<std::pair<int, double>>& row) {
+    row.clear();
+    if (embed && g.dirichlet[i]) {
+      row.emplace_back(i, 1.0);
+      return;
+    }
+    int vel[9], q1[4], p0;
+    for (int q = ne.ptr[i]; q < ne.ptr[(size_t)i + 1]; ++q) {
+      const int k = ne.el[q];
+      elem_nodes(g, g.el_x[k], g.el_y[k], vel, q1, p0);
+      double wx[9] = {0}, wy[9] = {0};
+      if (wind)
+        for (int m = 0; m < 9; ++m) {
+          wx[m] = wind[vel[m]];
+          wy[m] = wind[g.nv + vel[m]];
+        }
+      int li = 0;
+      while (vel[li] != i) ++li;
       for (int j = 0; j < 9; ++j) {
         if (embed && g.dirichlet[vel[j]]) continue;
-        double v = nu * E.A[i][j];
+        double v = nu * E.A[li][j];
         if (wind)
-          for (int m = 0; m < 9; ++m) v += E.Cx[i][j][m] * wx[m] + E.Cy[i][j][m] * wy[m];
-        rb.add(vel[i], vel[j], v);
+          for (int m = 0; m < 9; ++m) v += E.Cx[li][j][m] * wx[m] + E.Cy[li][j][m] * wy[m];
+        bool found = false;
+        for (auto& e : row)
+          if (e.first == vel[j]) {
+            e.second += v;
+            found = true;
+            break;
+          }
+        if (!found) row.emplace_back(vel[j], v);
       }
     }
-  }
-  if (embed)
-    for (int i = 0; i < g.nv; ++i)
-      if (g.dirichlet[i]) rb.add(i, i, 1.0);
-  return rb.finish();
+    std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  };
+  parallel_rows(g.nv, [&](int r0, int r1) {
+    std::vector<std::pair<int, double>> row;
+    for (int i = r0; i < r1; ++i) {
+      row_entries(i, row);
+      len[i] = (int)row.size();
+    }
+  });
+  for (int i = 0; i < g.nv; ++i) A.ptr[(size_t)i + 1] = A.ptr[i] + len[i];
+  A.col.resize(A.ptr[g.nv]);
+  A.val.resize(A.ptr[g.nv]);
+  parallel_rows(g.nv, [&](int r0, int r1) {
+    std::vector<std::pair<int, double>> row;
+    for (int i = r0; i < r1; ++i) {
+      row_entries(i, row);
+      int o = A.ptr[i];
+      for (const auto& e : row) {
+        A.col[o] = e.first;
+        A.val[o] = e.second;
+        ++o;
+      }
+    }
+  });
+  return A;
 }
 
 Csr step_assemble_B(const StepMesh& g, const StepElem& E) {
@@ -307,39 +396,45 @@ Csr step_assemble_K(const StepMesh& g, const Csr& F, const Csr& B) {
   Csr K;
   K.rows = K.cols = (int)N;
   K.ptr.assign(N + 1, 0);
-  {
-    size_t nnz = 0;   // an upper bound: F and B^T rows of free nodes, B rows
-    for (int i = 0; i < nv; ++i)
-      if (!g.dirichlet[i]) nnz += 2 * (size_t)(F.ptr[i + 1] - F.ptr[i]);
-    nnz += 2 * B.col.size();
-    K.col.reserve(nnz);
-    K.val.reserve(nnz);
-  }
-  for (int c = 0; c < 2; ++c)
-    for (int i = 0; i < nv; ++i) {
-      const int row = c * nv + i;
-      if (!g.dirichlet[i]) {
-        for (int k = F.ptr[i]; k < F.ptr[i + 1]; ++k)
-          if (!g.dirichlet[F.col[k]]) {
-            K.col.push_back(c * nv + F.col[k]);
-            K.val.push_back(F.val[k]);
-          }
-        for (int k = Bt.ptr[row]; k < Bt.ptr[row + 1]; ++k) {
-          K.col.push_back(2 * nv + Bt.col[k]);
-          K.val.push_back(Bt.val[k]);
-        }
-      }
-      K.ptr[row + 1] = (int)K.col.size();
+  // row r of K: velocity rows (component c, node i) hold F's row i without
+  // the Dirichlet columns, then B^T's row (none for a Dirichlet node);
+  // pressure rows hold B's row without the Dirichlet velocity columns.
+  // visit(r, emit) lists a row's entries in that order.
+  auto visit = [&](int r, auto&& emit) {
+    if (r < 2 * nv) {
+      const int c = r / nv, i = r % nv;
+      if (g.dirichlet[i]) return;
+      for (int k = F.ptr[i]; k < F.ptr[i + 1]; ++k)
+        if (!g.dirichlet[F.col[k]]) emit(c * nv + F.col[k], F.val[k]);
+      for (int k = Bt.ptr[r]; k < Bt.ptr[r + 1]; ++k) emit(2 * nv + Bt.col[k], Bt.val[k]);
+    } else {
+      const int p = r - 2 * nv;
+      for (int k = B.ptr[p]; k < B.ptr[p + 1]; ++k)
+        if (!g.dirichlet[B.col[k] % nv]) emit(B.col[k], B.val[k]);
     }
-  for (int p = 0; p < np; ++p) {
-    for (int k = B.ptr[p]; k < B.ptr[p + 1]; ++k) {
-      const int j = B.col[k] % nv;
-      if (g.dirichlet[j]) continue;
-      K.col.push_back(B.col[k]);
-      K.val.push_back(B.val[k]);
+  };
+  std::vector<int> len((size_t)N, 0);
+  parallel_rows((int)N, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      int n = 0;
+      visit(r, [&](int, double) { ++n; });
+      len[r] = n;
     }
-    K.ptr[2 * nv + p + 1] = (int)K.col.size();
-  }
+  });
+  for (long long r = 0; r < N; ++r) K.ptr[r + 1] = K.ptr[r] + len[r];
+  K.col.resize(K.ptr[N]);
+  K.val.resize(K.ptr[N]);
+  parallel_rows((int)N, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      int o = K.ptr[r];
+      visit(r, [&](int col, double v) {
+        K.col[o] = col;
+        K.val[o] = v;
+        ++o;
+      });
+    }
+  });
+  (void)np;
   return K;
 }
 

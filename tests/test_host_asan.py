@@ -1,10 +1,12 @@
 """The host side of the runtime under AddressSanitizer and UBSan (no GPU
-needed): eth_runtime.hip and eth_noalloc.hip are rebuilt with the sanitizers
-on their host code only (-Xarch_host), linked with the other objects, and a
-child Python process with the ASan runtime preloaded drives every call that
-answers without a device (status strings, argument checks, failing set-ups
-with their clean-up).  Opt-in (ETH_ASAN=1): the instrumented build takes about
-a minute."""
+needed): eth_runtime.hip, eth_noalloc.hip, eth_step.hip and eth_step_asm.hip
+are rebuilt with the sanitizers on their host code only (-Xarch_host), linked
+with the other objects, and a child Python process with the ASan runtime
+preloaded drives every call that answers without a device (status strings,
+argument checks, failing set-ups with their clean-up, and the step's host
+assembly of every matrix kind, on meshes large enough for its multi-threaded
+row fill).  Opt-in (ETH_ASAN=1): the instrumented build takes about a
+minute."""
 import os
 import subprocess
 import sys
@@ -25,7 +27,7 @@ def test_host_code_under_asan_and_ubsan(tmp_path):
     objs = []
     for src in build.SOURCES:
         obj = os.path.join(build.BUILD, os.path.splitext(src)[0] + ".o")
-        if src in ("eth_runtime.hip", "eth_noalloc.hip"):
+        if src in ("eth_runtime.hip", "eth_noalloc.hip", "eth_step.hip", "eth_step_asm.hip"):
             obj = str(tmp_path / (os.path.splitext(src)[0] + ".asan.o"))
             cmd = [hipcc, *build.FLAGS, *san, "-c", os.path.join(build.CSRC, src), "-o", obj]
             r = subprocess.run(cmd, capture_output=True, text=True)
@@ -63,6 +65,12 @@ rc = L.eth_setup(ctypes.byref(d), ctypes.byref(h))   # no GPU here: fails in the
 assert rc < 0 and not h.value, rc
 assert L.eth_destroy(None) == eth.EINVAL
 assert L.eth_misfit_noalloc(None, None, None, None, None, 1, 1) == eth.EINVAL
+import numpy as np
+for m, ch in ((4, False), (32, False), (6, True)):
+    nv = eth.step_host_layout(m, channel=ch)["q2_ij"].shape[0]
+    w = np.linspace(-1.0, 1.0, 2 * nv)
+    for k in (eth.STEP_K, eth.STEP_F1, eth.STEP_MQ, eth.STEP_Q1, eth.STEP_AP, eth.STEP_P, eth.STEP_PQ, eth.STEP_RHS):
+        eth.step_host_matrix(m, k, channel=ch, nu=0.02, wind=w)
 print("ASAN_DRIVER_OK")
 """ % (ROOT, lib)
     env = dict(os.environ, LD_PRELOAD=rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
