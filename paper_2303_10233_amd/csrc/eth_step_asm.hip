@@ -4,6 +4,7 @@
 // to the GPU as sliced-ELL matrices (eth_step.hip).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <stdexcept>
 #include <thread>
 
@@ -280,10 +281,12 @@ NodeElems node_elements(const StepMesh& g) {
 }
 
 // body(r0, r1) over contiguous blocks of rows on up to 16 host threads
-// (one for small matrices); blocks are independent
+// (one for small matrices; ETH_HOST_THREADS caps the count); blocks are
+// independent
 template <typename Body>
 void parallel_rows(int rows, Body&& body) {
   unsigned nt = std::thread::hardware_concurrency();
+  if (const char* e = std::getenv("ETH_HOST_THREADS")) nt = (unsigned)std::max(1, std::atoi(e));
   nt = std::max(1u, std::min(nt, 16u));
   if (rows < 8192) nt = 1;
   if (nt == 1) {

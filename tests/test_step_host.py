@@ -10,6 +10,7 @@ import scipy.sparse as sp
 from oracle.assemble import System, q1_mass
 from oracle.step import (StepMesh, inflow_dirichlet, step_f1, pressure_laplacian, q2_prolongation,
                          q1_prolongation)
+from paper_2303_10233_amd.workloads import uniform_vector
 
 eth = pytest.importorskip("paper_2303_10233_amd.eth")
 
@@ -58,3 +59,19 @@ def test_host_calls_reject_bad_sizes():
         eth.step_host_layout(0)
     with pytest.raises(eth.EthError):
         eth.step_host_matrix(3, eth.STEP_P)      # odd m has no coarser level
+
+
+def test_threaded_host_assembly_does_not_depend_on_the_thread_count(monkeypatch):
+    """F and K are filled row by row on several host threads, each row
+    summing its elements in ascending order: one thread and eight give the
+    same matrices bit for bit (m = 32, 45 569 velocity nodes, enough rows for
+    the threaded fill)."""
+    M = StepMesh(32)
+    w = uniform_vector(2 * M.nv, 3)
+    out = []
+    for nt in ("1", "8"):
+        monkeypatch.setenv("ETH_HOST_THREADS", nt)
+        out.append([eth.step_host_matrix(32, k, nu=1.0 / 50, wind=w) for k in (eth.STEP_K, eth.STEP_RHS)])
+    for a, b in zip(out[0], out[1]):
+        for x, y in zip(a[:3], b[:3]):
+            assert np.array_equal(x, y)
