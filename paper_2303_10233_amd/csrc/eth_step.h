@@ -85,6 +85,9 @@ std::vector<double> step_inflow(const StepMesh& mesh);   // 2 n_v Dirichlet vect
 // lifted right-hand side: free rows -F u_B (both components), pressure rows
 // -B u_B, Dirichlet rows u_B
 std::vector<double> step_lift(const StepMesh& mesh, const Csr& Ffull, const Csr& B, const std::vector<double>& uB);
+// sliced-ELL arrays of A (64 rows per slice, column-major in a slice, padding
+// repeats a row's last column with value 0): slice offsets, columns, values
+void sell_layout(const Csr& A, std::vector<int>& ptr, std::vector<int>& col, std::vector<double>& val);
 // inverse of a small dense matrix (row-major), Gauss-Jordan with partial pivoting
 std::vector<double> dense_inverse(const Csr& A);
 // largest eigenvalue of D^{-1} A for symmetric positive definite A (Lanczos)

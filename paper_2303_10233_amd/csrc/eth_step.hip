@@ -222,32 +222,10 @@ StepProblem::~StepProblem() {
 // entries repeat the row's last column with value 0
 void StepProblem::upload(Sell& s, const Csr& A, bool f32, bool dinv) {
   const int slices = (A.rows + 63) / 64;
-  std::vector<int> ptr(slices + 1, 0);
-  for (int sl = 0; sl < slices; ++sl) {
-    int w = 0;
-    for (int r = sl * 64; r < std::min(A.rows, sl * 64 + 64); ++r) w = std::max(w, A.ptr[r + 1] - A.ptr[r]);
-    ptr[sl + 1] = ptr[sl] + 64 * w;
-  }
+  std::vector<int> ptr, col;
+  std::vector<double> val;
+  sell_layout(A, ptr, col, val);
   const size_t tot = (size_t)ptr[slices];
-  std::vector<int> col(tot, 0);
-  std::vector<double> val(tot, 0.0);
-  for (int sl = 0; sl < slices; ++sl) {
-    const int w = (ptr[sl + 1] - ptr[sl]) / 64;
-    for (int lane = 0; lane < 64; ++lane) {
-      const int r = sl * 64 + lane;
-      int last = 0;
-      for (int k = 0; k < w; ++k) {
-        const size_t o = (size_t)ptr[sl] + (size_t)k * 64 + lane;
-        if (r < A.rows && k < A.ptr[r + 1] - A.ptr[r]) {
-          last = A.col[A.ptr[r] + k];
-          col[o] = last;
-          val[o] = A.val[A.ptr[r] + k];
-        } else {
-          col[o] = last;
-        }
-      }
-    }
-  }
   const bool same = s.ptr && s.rows == A.rows && s.stored == (long long)tot;
   if (!same) {
     s.rows = A.rows;

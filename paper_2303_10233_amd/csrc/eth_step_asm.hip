@@ -441,6 +441,45 @@ Csr step_assemble_K(const StepMesh& g, const Csr& F, const Csr& B) {
   return K;
 }
 
+// Sliced-ELL layout of A: 64 rows per slice, a slice as wide as its longest
+// row, entries column-major inside the slice (entry k of lane l at
+// ptr[slice] + 64 k + l); a row's padding repeats its last column (0 for an
+// empty row) with value 0.  Slices are filled on several host threads.
+void sell_layout(const Csr& A, std::vector<int>& ptr, std::vector<int>& col, std::vector<double>& val) {
+  const int slices = (A.rows + 63) / 64;
+  ptr.assign((size_t)slices + 1, 0);
+  std::vector<int> width(slices, 0);
+  parallel_rows(slices, [&](int s0, int s1) {
+    for (int sl = s0; sl < s1; ++sl) {
+      int w = 0;
+      for (int r = sl * 64; r < std::min(A.rows, sl * 64 + 64); ++r) w = std::max(w, A.ptr[r + 1] - A.ptr[r]);
+      width[sl] = w;
+    }
+  });
+  for (int sl = 0; sl < slices; ++sl) ptr[(size_t)sl + 1] = ptr[sl] + 64 * width[sl];
+  const size_t tot = (size_t)ptr[slices];
+  col.assign(tot, 0);
+  val.assign(tot, 0.0);
+  parallel_rows(slices, [&](int s0, int s1) {
+    for (int sl = s0; sl < s1; ++sl) {
+      const int w = width[sl];
+      for (int lane = 0; lane < 64; ++lane) {
+        const int r = sl * 64 + lane;
+        const int len = r < A.rows ? A.ptr[r + 1] - A.ptr[r] : 0;
+        int last = 0;
+        for (int k = 0; k < w; ++k) {
+          const size_t o = (size_t)ptr[sl] + (size_t)k * 64 + lane;
+          if (k < len) {
+            last = A.col[A.ptr[r] + k];
+            val[o] = A.val[A.ptr[r] + k];
+          }
+          col[o] = last;
+        }
+      }
+    }
+  });
+}
+
 Csr step_assemble_MQ(const StepMesh& g, const StepElem& E) {
   RowBuilder rb(g.nk + g.n0, g.nk + g.n0);
   for (int k = 0; k < g.n0; ++k) {
